@@ -1,0 +1,229 @@
+"""Drivers on top of the single-pair oracle solver.
+
+  rbicg_sequence -- a sequence of dual pairs (eq. initialSys): the final U_j,
+                    U~_j of system j become U, U~ of system j+1, whose C, C~ are
+                    recomputed with the new matrix and biorthogonalized
+                    (Sec. 4.3, last paragraph).
+  shifted_pairs  -- pairs (sigma I - A) x = b, (sigma I - A)^H x~ = c of IRKA
+                    (Algorithm 3, steps 2-3) for several shifts sharing one
+                    recycle space U, U~; each shift gets its own C_sigma =
+                    (sigma I - A) U biorthogonalized on its own.  For E = I the
+                    shifted matrices share A's eigenvectors, which is why one U
+                    can serve all shifts (reading; the paper recycles per shift).
+  mixed_refine   -- FP64 iterative refinement around an RBiCG inner solve that
+                    stores vectors and matrix values in FP32 (not in the paper).
+  bilinear       -- u^H A^{-1} w from one dual solve with the correction term
+                    x~^H r (error r~^H A^{-1} r, quadratic in the residuals).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .krylov import rbicg, as_csr, SolveResult, _dot
+from . import recycle as rc
+
+
+def rbicg_sequence(mats, bs, bts, k, s, tol, maxit=5000, x0s=None, xt0s=None,
+                   update=True, svd_tol=1e-2, seed=0, max_restarts=2,
+                   U0=None, Ut0=None):
+    """Solve the dual pairs in order, recycling between them.  With k=0 (or
+    update=False and no U0) this is plain BiCG on every pair.
+    Returns (results, (U, U~)) with the recycle space left after the last pair."""
+    U, Ut = U0, Ut0
+    out = []
+    for j, A in enumerate(mats):
+        A = as_csr(A)
+        AH = A.conj().T.tocsr()
+        C = Ct = None
+        if U is not None and U.shape[1] > 0 and k > 0:
+            U, Ut, C, Ct = rc.biorthogonalize(A, AH, U, Ut, svd_tol)
+            if C is None:
+                U = Ut = None
+        x0 = None if x0s is None else x0s[j]
+        xt0 = None if xt0s is None else xt0s[j]
+        res = rbicg(A, bs[j], bts[j], x0, xt0, U, Ut, C, Ct, tol=tol, maxit=maxit,
+                    s=s, k=k, update=(update and k > 0), seed=seed,
+                    max_restarts=max_restarts, svd_tol=svd_tol)
+        out.append(res)
+        U, Ut = res.U_next, res.Ut_next
+    return out, (U, Ut)
+
+
+def shifted_matrix(A, sigma):
+    A = as_csr(A)
+    n = A.shape[0]
+    return (sigma * sp.identity(n, dtype=np.complex128, format="csr") - A).tocsr()
+
+
+def shifted_pairs(A, b, c, sigmas, U=None, Ut=None, k=20, s=40, tol=1e-8,
+                  maxit=5000, x0s=None, xt0s=None, update_from=None,
+                  svd_tol=1e-2, seed=0):
+    """One IRKA-style sweep: for each shift sigma_i solve
+    (sigma_i I - A) x_i = b and (sigma_i I - A)^H x~_i = c with RBiCG, all
+    shifts sharing the recycle space (U, U~).  The recycle space for the next
+    sweep comes from the cycle data of shift index ``update_from`` (default: the
+    shift of smallest modulus; reading, since the paper recycles only for the
+    small shifts).  Returns (results, (U_next, U~_next))."""
+    A = as_csr(A)
+    if update_from is None:
+        update_from = int(np.argmin(np.abs(np.asarray(sigmas))))
+    out = []
+    Unext = Utnext = None
+    for i, sg in enumerate(sigmas):
+        M = shifted_matrix(A, sg)
+        MH = M.conj().T.tocsr()
+        Ui = Uti = C = Ct = None
+        if U is not None and U.shape[1] > 0:
+            Ui, Uti, C, Ct = rc.biorthogonalize(M, MH, U.astype(np.complex128),
+                                                Ut.astype(np.complex128), svd_tol)
+            if C is None:
+                Ui = Uti = None
+        x0 = None if x0s is None else x0s[i]
+        xt0 = None if xt0s is None else xt0s[i]
+        res = rbicg(M, b.astype(np.complex128), c.astype(np.complex128), x0, xt0,
+                    Ui, Uti, C, Ct, tol=tol, maxit=maxit, s=s, k=k,
+                    update=(i == update_from), seed=seed, svd_tol=svd_tol)
+        out.append(res)
+        if i == update_from:
+            Unext, Utnext = res.U_next, res.Ut_next
+    if Unext is None:
+        Unext, Utnext = U, Ut
+    return out, (Unext, Utnext)
+
+
+def _f32(v):
+    return np.asarray(v).astype(np.float32)
+
+
+def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
+                     svd_tol=1e-2, A64=None, AH64=None):
+    """RBiCG with FP32 storage: matrix values and every n-vector are float32;
+    each element operation is evaluated in float64 and rounded once when stored;
+    all inner products and norms accumulate in float64.  Starts from x = x~ = 0.
+    The recycle space (U, C, ...) is given in FP64 and used through FP32
+    copies; the cycle update works in FP64 on the FP64 matrix (A64) from the
+    FP32-stored Lanczos vectors.  Returns (d, d~, iters, cycle state)."""
+    from .krylov import _CycleState
+    n = A32.shape[0]
+    f64 = np.float64
+    kc = 0 if U is None else U.shape[1]
+    U32, Ut32 = (_f32(U), _f32(Ut)) if kc else (None, None)
+    C32, Ct32 = (_f32(C), _f32(Ct)) if kc else (None, None)
+    A64e = A32.astype(f64)
+    AH64e = AH32.astype(f64)
+    r = _f32(b); rt = _f32(bt)        # r_{-1} with x_{-1} = 0
+    x = np.zeros(n, np.float32); xt = np.zeros(n, np.float32)
+    if kc:
+        g = Ct32.astype(f64).T @ r.astype(f64)
+        x = _f32(x.astype(f64) + U32.astype(f64) @ g)
+        r = _f32(r.astype(f64) - C32.astype(f64) @ g)
+        gt = C32.astype(f64).T @ rt.astype(f64)
+        xt = _f32(xt.astype(f64) + Ut32.astype(f64) @ gt)
+        rt = _f32(rt.astype(f64) - Ct32.astype(f64) @ gt)
+    bn = np.linalg.norm(b); btn = np.linalg.norm(bt)
+    cyc = _CycleState(U if kc else None, Ut if kc else None, k, s, True, svd_tol)
+    p = np.zeros(n, np.float32); pt = np.zeros(n, np.float32)
+    beta = 0.0
+    zeta_c = np.zeros(kc); zetat_c = np.zeros(kc)
+    rho = float(rt.astype(f64) @ r.astype(f64))
+    rn = np.linalg.norm(r.astype(f64)); rtn = np.linalg.norm(rt.astype(f64))
+    V, Vt, ca, cb, cr = [], [], [], [], []
+    it = 0
+    while it < maxit and not (rn <= tol * bn and rtn <= tol * btn):
+        it += 1
+        p = _f32(r.astype(f64) + beta * p.astype(f64))
+        pt = _f32(rt.astype(f64) + beta * pt.astype(f64))
+        z = _f32(A64e @ p.astype(f64))
+        zt = _f32(AH64e @ pt.astype(f64))
+        if kc:
+            zeta = Ct32.astype(f64).T @ z.astype(f64)
+            zetat = C32.astype(f64).T @ zt.astype(f64)
+            q = _f32(z.astype(f64) - C32.astype(f64) @ zeta)
+            qt = _f32(zt.astype(f64) - Ct32.astype(f64) @ zetat)
+        else:
+            q, qt = z, zt
+        sigma = float(pt.astype(f64) @ q.astype(f64))
+        alpha = rho / sigma
+        if kc:
+            zeta_c += alpha * zeta
+            zetat_c += alpha * zetat
+        if update:
+            v = r.astype(f64) / rn
+            V.append(v); Vt.append(rt.astype(f64) / float(v @ rt.astype(f64)))
+            ca.append(alpha); cb.append(beta); cr.append(rn)
+        x = _f32(x.astype(f64) + alpha * p.astype(f64))
+        xt = _f32(xt.astype(f64) + alpha * pt.astype(f64))
+        r = _f32(r.astype(f64) - alpha * q.astype(f64))
+        rt = _f32(rt.astype(f64) - alpha * qt.astype(f64))
+        rho_new = float(rt.astype(f64) @ r.astype(f64))
+        rn = np.linalg.norm(r.astype(f64)); rtn = np.linalg.norm(rt.astype(f64))
+        if update and len(V) == s:
+            cyc.update(A64, AH64, V, Vt, np.asarray(ca), np.asarray(cb), np.asarray(cr))
+            V, Vt, ca, cb, cr = [], [], [], [], []
+        if rn <= tol * bn and rtn <= tol * btn:
+            break
+        beta = rho_new / rho
+        rho = rho_new
+    d = x.astype(f64)
+    dt_ = xt.astype(f64)
+    if kc:
+        d = d - U @ zeta_c
+        dt_ = dt_ - Ut @ zetat_c
+    return d, dt_, it, cyc
+
+
+def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
+                 inner_tol=1e-5, max_outer=30, maxit_inner=5000, svd_tol=1e-2,
+                 update=True):
+    """FP64 iterative refinement with an FP32-storage RBiCG inner solver.
+    Outer: r = b - A x, r~ = b~ - A^H x~ in FP64; stop when both relative true
+    residuals are <= tol; otherwise solve A d = r, A^H d~ = r~ to inner_tol
+    relative with the FP32 inner RBiCG and update x += d, x~ += d~ in FP64.
+    The recycle space carries over between outer steps (the latest cycle's
+    space when one completed).  Returns (x, x~, info, (U, U~))."""
+    A = as_csr(A).astype(np.float64)
+    AH = A.T.tocsr()
+    A32 = A.astype(np.float32)
+    AH32 = AH.astype(np.float32)
+    n = A.shape[0]
+    x = np.zeros(n); xt = np.zeros(n)
+    bn = np.linalg.norm(b); btn = np.linalg.norm(bt)
+    inner_total = 0
+    outer = 0
+    while True:
+        r = b - A @ x
+        rt = bt - AH @ xt
+        rel, relt = np.linalg.norm(r) / bn, np.linalg.norm(rt) / btn
+        if (rel <= tol and relt <= tol) or outer >= max_outer:
+            break
+        C = Ct = None
+        if U is not None and U.shape[1] > 0:
+            U, Ut, C, Ct = rc.biorthogonalize(A, AH, U, Ut, svd_tol)
+            if C is None:
+                U = Ut = None
+        d, dt_, it, cyc = rbicg_fp32_inner(A32, AH32, r, rt, U, Ut, C, Ct, inner_tol,
+                                           maxit_inner, s, k, update, svd_tol, A, AH)
+        inner_total += it
+        outer += 1
+        x = x + d
+        xt = xt + dt_
+        if cyc.Uj is not None and cyc.Uj.shape[1] > 0:
+            U, Ut = cyc.Uj, cyc.Utj
+    info = {"outer": outer, "inner_iters": inner_total, "relres": rel, "relres_dual": relt}
+    return x, xt, info, (U, Ut)
+
+
+def bilinear(A, u, w, tol=1e-8, maxit=5000, U=None, Ut=None, C=None, Ct=None, s=40,
+             k=None, update=False):
+    """u^H A^{-1} w (Sec. 1): solve A x = w and A^H x~ = u with RBiCG and return
+    u^H x + x~^H r with the true residual r = w - A x.  Since
+    u^H A^{-1} w = u^H x + x~^H r + r~^H A^{-1} r, the error is r~^H A^{-1} r,
+    bounded by ||r~|| ||A^{-1}|| ||r||.  Returns (value, ||r|| * ||r~||, result)."""
+    A = as_csr(A)
+    res = rbicg(A, w, u, None, None, U, Ut, C, Ct, tol=tol, maxit=maxit, s=s, k=k,
+                update=update)
+    r = w - A @ res.x
+    rt = u - A.conj().T @ res.xt
+    val = _dot(u, res.x) + _dot(res.xt, r)
+    return val, float(np.linalg.norm(r) * np.linalg.norm(rt)), res
