@@ -1,0 +1,195 @@
+/*
+ * rbicg.h -- C ABI of the MI355X recycling-BiCG library (librbicg.so).
+ *
+ * Method: Ahuja, de Sturler, Gugercin, Chang, "Recycling BiCG with an
+ * Application to Model Reduction".  The library solves sequences of dual
+ * systems (Sec. 1, eq. initialSys)
+ *        A_j x_j = b_j,     A_j^H x~_j = b~_j,
+ * with RBiCG (Algorithm 2), updating the recycle spaces U, U~ cycle by cycle
+ * while a system is solved (Sec. 4) and carrying them to the next system.
+ *
+ * Conventions
+ *   - Inner product (a, b) = a^H b.  The paper's A^* is written A^H.
+ *   - Sparse matrices enter as CSR with int32 row pointers / column indices.
+ *     Inside the library they are repacked into a wave-sliced ELL layout for
+ *     the gfx950 kernels; the caller never sees it.
+ *   - n-vectors are contiguous, of the handle's vector type:
+ *       RBICG_F64            double
+ *       RBICG_C128           complex double, interleaved (re, im)
+ *       RBICG_F32_IN_F64_OUT double at the boundary (FP64 outer refinement);
+ *                            the inner RBiCG stores float vectors internally
+ *   - Every vector argument is a DEVICE pointer on the current HIP device,
+ *     used in stream order on opts.stream; the call returns after the result
+ *     is complete (it synchronizes that stream).  The library never frees
+ *     caller memory.
+ *   - Recycle bases are column-major n x k device arrays (leading dimension n).
+ *
+ * Ownership: a handle owns device copies of A and of the explicit A^H, the
+ * recycle bases U, U~, C = A U, C~ = A^H U~, the cycle buffers and the
+ * workspace.  They persist across systems until rbicg_destroy.  One handle
+ * must not be used by two host threads at once.
+ *
+ * Return codes (every int function):
+ *    0 RBICG_OK
+ *    1 RBICG_NOT_CONVERGED  maxit or max_restarts reached; x, x~ hold the
+ *                           last iterates and the stats are filled in
+ *   -1 RBICG_EINVAL         bad argument (null pointer, size, k > 64, ...)
+ *   -2 RBICG_ENOMEM         device allocation failed
+ *   -3 RBICG_BREAKDOWN      (p~, q) or (r~, r) vanished or became NaN (Sec. 2:
+ *                           serious breakdown / breakdown of the second kind;
+ *                           no look-ahead is attempted)
+ *   -4 RBICG_EHIP           a HIP runtime call failed
+ * rbicg_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef RBICG_H
+#define RBICG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBICG_OK 0
+#define RBICG_NOT_CONVERGED 1
+#define RBICG_EINVAL (-1)
+#define RBICG_ENOMEM (-2)
+#define RBICG_BREAKDOWN (-3)
+#define RBICG_EHIP (-4)
+
+#define RBICG_KMAX 64
+
+typedef struct rbicg_s *rbicg_handle;
+
+typedef enum {
+  RBICG_F64 = 0,
+  RBICG_C128 = 1,
+  RBICG_F32_IN_F64_OUT = 2
+} rbicg_precision;
+
+/* A sparse n x n matrix in CSR form.  values is double[nnz], or double[2*nnz]
+ * (interleaved complex) when values_complex = 1.  on_device = 1: the three
+ * arrays are device pointers, else host pointers.  Column indices inside a
+ * row need not be sorted; duplicate entries are not allowed. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const void *values;
+  int32_t values_complex;
+  int32_t on_device;
+} rbicg_csr;
+
+/* Options (rbicg_default_opts fills them).
+ *   k            recycle-space dimension (0 = plain BiCG, Algorithm 1), <= 64
+ *   s            cycle length: iterations between recycle updates (Sec. 4.1)
+ *   maxit        iteration cap per solve (restarts included)
+ *   max_restarts restarts after a failed true-residual check
+ *   update       1: update the recycle space at every completed cycle
+ *   svd_tol      truncation tolerance on the cosines of the principal angles
+ *                between range(C) and range(C~) (Sec. 4.3)
+ *   seed         SplitMix64 seed of the x~ re-seed vector (Algorithm 2 step 3)
+ *   prec         vector type / precision mode
+ *   inner_tol    FP32 inner tolerance of RBICG_F32_IN_F64_OUT
+ *   max_outer    outer refinement steps of RBICG_F32_IN_F64_OUT
+ *   stream       hipStream_t to run on (NULL: the null stream)
+ *   chunk        iterations launched between convergence polls (0: auto) */
+typedef struct {
+  int32_t k, s, maxit, max_restarts, update;
+  double svd_tol;
+  uint64_t seed;
+  rbicg_precision prec;
+  double inner_tol;
+  int32_t max_outer;
+  void *stream;
+  int32_t chunk;
+} rbicg_opts;
+
+/* Per-solve statistics.  relres / relres_dual are TRUE relative residuals
+ * ||b - A x|| / ||b|| computed after the solve; alg_bytes counts the
+ * algorithmic HBM bytes of the iterations (per-iteration model times iters). */
+typedef struct {
+  int32_t status, iters, restarts, outer_steps, cycles, k_used, reseeds;
+  double relres, relres_dual, time_ms, alg_bytes;
+} rbicg_stats;
+
+/* Fill *opts with defaults: k=20, s=40, maxit=10000, max_restarts=2,
+ * update=1, svd_tol=1e-2, seed=0, prec=RBICG_F64, inner_tol=1e-5,
+ * max_outer=30, stream=NULL, chunk=0. */
+void rbicg_default_opts(rbicg_opts *opts);
+
+/* Create a handle for matrix A (problem statement, Sec. 1).  AH may be NULL,
+ * in which case the explicit conjugate transpose A^H is built on the host by
+ * a counting sort; the iteration never uses atomics for A^H products.
+ * Returns RBICG_OK and *out, or an error code. */
+int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
+                 rbicg_handle *out);
+
+/* Solve the dual pair A x = b, A^H x~ = b~ with RBiCG (Algorithm 2) to
+ * ||b - A x|| <= tol ||b|| and ||b~ - A^H x~|| <= tol ||b~|| (relative; if b~ = 0
+ * the initial dual residual replaces ||b~||).  x, xt hold x_{-1}, x~_{-1} on
+ * entry and the solutions on exit.  The recycle space U, U~ of the handle is
+ * used as fixed (Sec. 3); when opts.update is set, the cycle-wise update of
+ * Sec. 4 builds the recycle space for the next system, installed by
+ * rbicg_update_recycle.  st may be NULL. */
+int rbicg_solve_dual(rbicg_handle h, const void *b, const void *bt, void *x, void *xt,
+                     double tol, rbicg_stats *st);
+
+/* Move to the next system of the sequence (end of Sec. 4.3): take the recycle
+ * space built during the last solve (or keep the current one if no cycle
+ * completed, Sec. 6.2), optionally replace the matrix by A_next (AH_next may be
+ * NULL; A_next NULL keeps the matrix), recompute C = A U, C~ = A^H U~ and
+ * biorthogonalize them (C~^H C = I).  A_next must have the same n. */
+int rbicg_update_recycle(rbicg_handle h, const rbicg_csr *A_next, const rbicg_csr *AH_next);
+
+/* Bilinear form u^H A^{-1} w (Sec. 1): solves A x = w and A^H x~ = u with
+ * RBiCG and returns u^H x + x~^H r, r = w - A x, whose error r~^H A^{-1} r is
+ * quadratic in the residuals.  *value is one double (real) or two (complex,
+ * re/im) on the HOST; *err_est (host, may be NULL) receives ||r|| ||r~||, the
+ * error bound without the factor ||A^{-1}||.  u, w are device vectors. */
+int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, double tol, void *value,
+                   double *err_est, rbicg_stats *st);
+
+/* Release every device buffer of the handle. */
+int rbicg_destroy(rbicg_handle h);
+
+/* Thread-local message of the last failure ("" if none). */
+const char *rbicg_last_error(void);
+
+/* Install U, U~ (device, column-major n x k, vector type of the handle) as the
+ * recycle space and biorthogonalize C = A U, C~ = A^H U~ as in
+ * rbicg_update_recycle (Algorithm 2 step 1).  k = 0 clears the space. */
+int rbicg_set_recycle(rbicg_handle h, const void *U, const void *Ut, int32_t k);
+
+/* Copy the current recycle space out: U, Ut, C, Ct (device, n x kcap each,
+ * column-major; any may be NULL); *k receives the dimension.  next = 1 copies
+ * the space built by the last solve's cycles instead of the installed one. */
+int rbicg_get_recycle(rbicg_handle h, void *U, void *Ut, void *C, void *Ct, int32_t kcap,
+                      int32_t next, int32_t *k);
+
+/* Copy the per-iteration log of the last solve to host memory: for each
+ * iteration i = 1..*count (at most cap), 10 doubles
+ *   alpha_i (re, im), beta_{i-1} (re, im), rho_i (re, im), ||r_i||, ||r~_i||,
+ *   restart index, reserved. */
+int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *count);
+
+/* Shifted dual pairs of IRKA (Algorithm 3 steps 2-3 with E = I):
+ *   (sigma_i I - A) X_i = b,   (sigma_i I - A)^H Xt_i = c,   i < S (S <= 16)
+ * for a complex (RBICG_C128) handle.  All shifts share the handle's recycle
+ * space U, U~; each shift's C_sigma = sigma U - A U and C~_sigma = conj(sigma)
+ * U~ - A^H U~ are biorthogonalized by a per-shift k x k rotation, so one
+ * contraction against [U~, A^H U~] and [U, A U] serves all shifts in each
+ * iteration.  sigma: host array of S complex values (re, im).  b, c: device
+ * n-vectors; X, Xt: device n x S column-major, initial guesses on entry.
+ * When opts.update is set the recycle space for the next sweep is built from
+ * the cycles of shift index update_from (< 0: the shift of smallest |sigma|).
+ * st: host array of S stats (may be NULL). */
+int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const void *b,
+                        const void *c, void *X, void *Xt, double tol, int32_t update_from,
+                        rbicg_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBICG_H */

@@ -1,0 +1,61 @@
+/*
+ * rbicg_hostla.h -- host FP64 dense linear algebra used at the cycle ends of
+ * recycling BiCG (librbicg.so).  Exported so that it can be checked on a CPU.
+ *
+ * Matrices are complex, column-major, interleaved (re, im) doubles: element
+ * (i, j) of an m x n matrix sits at 2*(i + j*m).  All arrays are host memory
+ * owned by the caller.  Return value: 0 on success, -1 on bad arguments or a
+ * failed factorization (message in rbicg_last_error()).
+ */
+#ifndef RBICG_HOSTLA_H
+#define RBICG_HOSTLA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Generalized eigenproblem P w = lambda Q w (Q = NULL: standard problem), the
+ * form of eq. finalGenEigValue (Sec. 4.1) and of the first-cycle problem
+ * T w = lambda w (Sec. 4.2).  Q must be nonsingular: the pencil is reduced to
+ * Q^{-1} P by an LU solve, then Hessenberg reduction and shifted complex QR
+ * give the Schur form.  Outputs (any may be NULL):
+ *   lam[2m]    eigenvalues
+ *   W[2m*m]    right eigenvectors (unit 2-norm columns)
+ *   Wl[2m*m]   left eigenvectors y: y^H P = lambda y^H Q (unit 2-norm),
+ *              i.e. the eigenvectors of the conjugate-transposed pencil. */
+int rbicg_host_eig(int32_t m, const double *P, const double *Q, double *lam, double *W,
+                   double *Wl);
+
+/* Select eigenvectors for the k eigenvalues closest to the origin (Sec. 4.1),
+ * ordered by (|lambda|, Re, Im); infinite/NaN values are skipped.  For a real
+ * problem (real_problem = 1) a conjugate pair contributes the two real vectors
+ * [Re w, Im w] and a real eigenvalue the real vector w (phase removed); a pair
+ * that does not fit in k is dropped.  Wsel, Wlsel: m x k outputs; returns the
+ * number of selected columns (>= 0), or -1. */
+int rbicg_host_select(int32_t m, const double *lam, const double *W, const double *Wl,
+                      int32_t k, int32_t real_problem, double *Wsel, double *Wlsel);
+
+/* Thin SVD A = U diag(s) V^H of an m x n matrix (m >= n) by one-sided Jacobi;
+ * singular values descending.  U: m x n, s: n reals, V: n x n. */
+int rbicg_host_svd(int32_t m, int32_t n, const double *A, double *U, double *s, double *V);
+
+/* Hermitian eigendecomposition A = V diag(w) V^H (cyclic Jacobi), ascending. */
+int rbicg_host_heig(int32_t m, const double *A, double *w, double *V);
+
+/* Biorthogonalization step of Sec. 4.3 from Gram matrices of C = A U and
+ * C~ = A^H U~ (k columns each): Gcc = C^H C, Gtt = C~^H C~, Gtc = C~^H C.
+ * Orthonormal bases Q = C L, Q~ = C~ L~ come from the Hermitian eigen-
+ * decompositions of Gcc and Gtt (directions with eigenvalue below
+ * 1e-13 * max are dropped); Q~^H Q = M Sigma N^H; the p cosines sigma_i >= tol
+ * are kept and TU = L N_p Sigma_p^{-1/2}, TUt = L~ M_p Sigma_p^{-1/2} (k x p,
+ * column-major, leading dimension k) make U TU, U~ TUt a biorthogonal pair
+ * (C~^H C = I_p).  Returns p (>= 0) or -1. */
+int rbicg_host_biorth(int32_t k, const double *Gcc, const double *Gtt, const double *Gtc,
+                      double tol, double *TU, double *TUt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBICG_HOSTLA_H */

@@ -1,0 +1,165 @@
+"""Python front end of the RBiCG library: torch tensors on the GPU in, torch
+tensors out.  Only marshalling happens here (pointers, sizes, the current HIP
+stream); the solver runs in librbicg.so."""
+from __future__ import annotations
+
+import ctypes as ct
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_PREC = {"f64": _lib.RBICG_F64, "c128": _lib.RBICG_C128, "mixed": _lib.RBICG_F32_IN_F64_OUT}
+
+
+def _csr_struct(A, keep):
+    """rbicg_csr for a host CSR (workloads.CSR or scipy.sparse)."""
+    if hasattr(A, "rowptr"):
+        n, rowptr, colind, vals = A.n, A.rowptr, A.colind, A.vals
+    else:
+        A = A.tocsr()
+        n, rowptr, colind, vals = A.shape[0], A.indptr, A.indices, A.data
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    cplx = np.iscomplexobj(vals)
+    vals = np.ascontiguousarray(vals, dtype=np.complex128 if cplx else np.float64)
+    keep.extend([rowptr, colind, vals])
+    s = _lib.rbicg_csr()
+    s.n = int(n)
+    s.nnz = int(rowptr[-1])
+    s.rowptr = rowptr.ctypes.data
+    s.colind = colind.ctypes.data
+    s.values = vals.ctypes.data
+    s.values_complex = 1 if cplx else 0
+    s.on_device = 0
+    return s
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Solver:
+    """One handle: a matrix (and its explicit conjugate transpose), a recycle
+    space and the device workspace, kept across the systems of a sequence."""
+
+    def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
+                 svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
+                 stream=None):
+        self.lib = _lib.load()
+        o = _lib.rbicg_opts()
+        self.lib.rbicg_default_opts(ct.byref(o))
+        o.k, o.s, o.maxit, o.max_restarts = k, s, maxit, max_restarts
+        o.update = 1 if update else 0
+        o.svd_tol, o.seed, o.prec = svd_tol, seed, _PREC[prec]
+        o.inner_tol, o.max_outer, o.chunk = inner_tol, max_outer, chunk
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        o.stream = _stream_ptr(self.stream)
+        self.opts = o
+        self.prec = prec
+        self.dtype = torch.complex128 if prec == "c128" else torch.float64
+        keep = []
+        a = _csr_struct(A, keep)
+        ah = _csr_struct(AH, keep) if AH is not None else None
+        self.n = a.n
+        h = ct.c_void_p()
+        rc = self.lib.rbicg_create(ct.byref(a), ct.byref(ah) if ah is not None else None,
+                                   ct.byref(o), ct.byref(h))
+        _lib.check(rc, "rbicg_create")
+        self.h = h
+
+    # --------------------------------------------------------------- helpers
+    def _vec(self, v, name):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda):
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if v.dtype != self.dtype or not v.is_contiguous() or v.numel() != self.n:
+            raise TypeError(f"{name} must be a contiguous {self.dtype} tensor of length {self.n}")
+        return ct.c_void_p(v.data_ptr())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbicg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ API
+    def solve(self, b, bt, x=None, xt=None, tol=1e-8, allow_not_converged=True):
+        """rbicg_solve_dual: returns (x, x~, stats dict)."""
+        x = torch.zeros_like(b) if x is None else x
+        xt = torch.zeros_like(bt) if xt is None else xt
+        st = _lib.rbicg_stats()
+        rc = self.lib.rbicg_solve_dual(self.h, self._vec(b, "b"), self._vec(bt, "bt"),
+                                       self._vec(x, "x"), self._vec(xt, "xt"), float(tol),
+                                       ct.byref(st))
+        ok = (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED) if allow_not_converged else (_lib.RBICG_OK,)
+        _lib.check(rc, "rbicg_solve_dual", ok)
+        return x, xt, st.as_dict()
+
+    def update_recycle(self, A_next=None, AH_next=None):
+        keep = []
+        a = _csr_struct(A_next, keep) if A_next is not None else None
+        ah = _csr_struct(AH_next, keep) if AH_next is not None else None
+        rc = self.lib.rbicg_update_recycle(self.h, ct.byref(a) if a is not None else None,
+                                           ct.byref(ah) if ah is not None else None)
+        _lib.check(rc, "rbicg_update_recycle")
+
+    def set_recycle(self, U, Ut):
+        k = 0 if U is None else U.shape[1]
+        if k:
+            Ucm = U.t().contiguous()   # column-major: each column contiguous
+            Utcm = Ut.t().contiguous()
+            rc = self.lib.rbicg_set_recycle(self.h, ct.c_void_p(Ucm.data_ptr()),
+                                            ct.c_void_p(Utcm.data_ptr()), k)
+        else:
+            rc = self.lib.rbicg_set_recycle(self.h, None, None, 0)
+        _lib.check(rc, "rbicg_set_recycle")
+
+    def get_recycle(self, next=False, kcap=64):
+        """Returns (U, U~, C, C~) as n x k tensors."""
+        bufs = [torch.zeros((kcap, self.n), dtype=self.dtype, device="cuda") for _ in range(4)]
+        k = ct.c_int32()
+        rc = self.lib.rbicg_get_recycle(self.h, *[ct.c_void_p(b.data_ptr()) for b in bufs],
+                                        kcap, 1 if next else 0, ct.byref(k))
+        _lib.check(rc, "rbicg_get_recycle")
+        kk = min(k.value, kcap)
+        return tuple(b[:kk].t() for b in bufs)
+
+    def log(self):
+        """Per-iteration log of the last solve as an (iters, 10) float64 array."""
+        cnt = ct.c_int32()
+        self.lib.rbicg_get_log(self.h, None, 0, ct.byref(cnt))
+        out = np.zeros((max(cnt.value, 1), 10))
+        self.lib.rbicg_get_log(self.h, _lib.dptr(out), cnt.value, ct.byref(cnt))
+        return out[:cnt.value]
+
+    def bilinear(self, u, w, tol=1e-8):
+        val = np.zeros(2)
+        err = ct.c_double()
+        st = _lib.rbicg_stats()
+        rc = self.lib.rbicg_bilinear(self.h, self._vec(u, "u"), self._vec(w, "w"), float(tol),
+                                     ct.c_void_p(val.ctypes.data), ct.byref(err), ct.byref(st))
+        _lib.check(rc, "rbicg_bilinear", (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED))
+        v = complex(val[0], val[1]) if self.prec == "c128" else float(val[0])
+        return v, err.value, st.as_dict()
+
+    def solve_shifted(self, sigmas, b, c, X=None, Xt=None, tol=1e-8, update_from=-1):
+        S = len(sigmas)
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.complex128))
+        Xcm = torch.zeros((S, self.n), dtype=self.dtype, device="cuda") if X is None else X
+        Xtcm = torch.zeros((S, self.n), dtype=self.dtype, device="cuda") if Xt is None else Xt
+        sts = (_lib.rbicg_stats * S)()
+        rc = self.lib.rbicg_solve_shifted(self.h, S, sig.view(np.float64).ctypes.data_as(_lib._DP),
+                                          self._vec(b, "b"), self._vec(c, "c"),
+                                          ct.c_void_p(Xcm.data_ptr()), ct.c_void_p(Xtcm.data_ptr()),
+                                          float(tol), update_from, sts)
+        _lib.check(rc, "rbicg_solve_shifted", (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED))
+        return Xcm, Xtcm, [s.as_dict() for s in sts]

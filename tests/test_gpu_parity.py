@@ -1,0 +1,182 @@
+"""GPU parity of the HIP path against the CPU oracle, element by element on the
+same seeded inputs, through the C ABI (python binding -> librbicg.so).
+
+Bars (from the method's use): true relative residual <= tol on both sides,
+iteration counts within 5% of the oracle's, solutions within 1e-6 relative of
+the oracle's, and early per-iteration scalars (alpha, beta, ||r||) to 1e-9
+relative where both sides start from the same recycle space."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import recycle as rc
+from oracle.krylov import as_csr
+from paper_1010_0762_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _solver(*a, **kw):
+    from paper_1010_0762_amd.solver import Solver
+    return Solver(*a, **kw)
+
+
+def _t(v, dtype=None):
+    dt = dtype or (torch.complex128 if np.iscomplexobj(v) else torch.float64)
+    return torch.as_tensor(np.ascontiguousarray(v)).to(device="cuda", dtype=dt)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _iters_close(a, b, frac=0.05):
+    return abs(a - b) <= max(1, int(np.ceil(frac * b)))
+
+
+def test_bicg_k0_matches_oracle_iterates():
+    seq = wl.cfg1_sequence(1)
+    A, b, bt = seq.mats[0], seq.b[0], seq.bt[0]
+    ref = oracle.bicg(A, b, bt, tol=1e-8, maxit=2000)
+    S = _solver(A, k=0, s=40, update=False)
+    x, xt, st = S.solve(_t(b), _t(bt), tol=1e-8)
+    assert st["status"] == 0
+    assert _iters_close(st["iters"], ref.iters, 0.0)
+    lg = S.log()
+    m = min(30, len(lg))
+    alpha = ref.log["alpha"][:m]
+    assert np.allclose(lg[:m, 0], alpha, rtol=1e-9, atol=0)
+    assert np.allclose(lg[:m, 6], ref.log["rnorm"][1:m + 1], rtol=1e-9, atol=0)
+    assert st["relres"] <= 1e-8 and st["relres_dual"] <= 1e-8
+    assert _rel(_np(x), ref.x) <= 1e-6 and _rel(_np(xt), ref.xt) <= 1e-6
+
+
+def test_injected_recycle_space_matches_oracle():
+    """The oracle's recycle space from system 0, installed on the GPU
+    (Algorithm 2 step 1), then system 1 solved without updating: the oblique
+    projector is basis independent, so the iterations agree to rounding."""
+    seq = wl.cfg1_sequence(2)
+    A0, A1 = as_csr(seq.mats[0]), as_csr(seq.mats[1])
+    r0 = oracle.rbicg(A0, seq.b[0], seq.bt[0], tol=1e-8, maxit=2000, s=40, k=10)
+    U, Ut, C, Ct = rc.biorthogonalize(A1, A1.T.tocsr(), r0.U_next, r0.Ut_next)
+    ref = oracle.rbicg(A1, seq.b[1], seq.bt[1], None, None, U, Ut, C, Ct, tol=1e-8, maxit=2000,
+                       update=False)
+    S = _solver(seq.mats[1], k=10, s=40, update=False)
+    S.set_recycle(_t(r0.U_next), _t(r0.Ut_next))
+    Ug, Utg, Cg, Ctg = (_np(t) for t in S.get_recycle())
+    assert Ug.shape[1] == U.shape[1]
+    assert np.abs(Ctg.T @ Cg - np.eye(Ug.shape[1])).max() <= 1e-12
+    x, xt, st = S.solve(_t(seq.b[1]), _t(seq.bt[1]), tol=1e-8)
+    assert st["status"] == 0 and st["k_used"] == U.shape[1]
+    assert _iters_close(st["iters"], ref.iters)
+    lg = S.log()
+    m = 15
+    assert np.allclose(lg[:m, 0], ref.log["alpha"][:m], rtol=1e-9, atol=0)
+    assert np.allclose(lg[:m, 6], ref.log["rnorm"][:m], rtol=1e-9, atol=0)
+    assert st["relres"] <= 1e-8 and st["relres_dual"] <= 1e-8
+    assert _rel(_np(x), ref.x) <= 1e-6 and _rel(_np(xt), ref.xt) <= 1e-6
+
+
+@pytest.mark.parametrize("nsys", [5])
+def test_sequence_cfg1_matches_oracle(nsys):
+    """2D convection-diffusion 32x32 sequence (k=10, s=40, tol 1e-8) with the
+    GPU's own cycle-wise recycle updates."""
+    seq = wl.cfg1_sequence(nsys)
+    ref, _ = oracle.rbicg_sequence(seq.mats, seq.b, seq.bt, seq.k, seq.s, seq.tol)
+    S = _solver(seq.mats[0], k=seq.k, s=seq.s)
+    its = []
+    for j in range(nsys):
+        if j:
+            S.update_recycle(seq.mats[j])
+        x, xt, st = S.solve(_t(seq.b[j]), _t(seq.bt[j]), tol=seq.tol)
+        its.append(st["iters"])
+        assert st["status"] == 0, (j, st)
+        assert st["relres"] <= seq.tol and st["relres_dual"] <= seq.tol, (j, st)
+        assert _iters_close(st["iters"], ref[j].iters), (j, st["iters"], ref[j].iters)
+        assert _rel(_np(x), ref[j].x) <= 1e-6 and _rel(_np(xt), ref[j].xt) <= 1e-6
+        assert st["cycles"] == ref[j].cycles
+    assert sum(its[1:]) < sum(r.iters for r in ref[:1]) * (nsys - 1)
+
+
+def test_ragged_size_and_determinism():
+    """n = 37^2 = 1369 (not a multiple of the 64-row slice or 256-row block)."""
+    A = wl.convdiff(37, 2, [6.0, 3.0])
+    rng = np.random.default_rng(77)
+    b, bt = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    ref, _ = oracle.rbicg_sequence([A, A], [b, b], [bt, bt], 10, 40, 1e-9)
+    S = _solver(A, k=10, s=40)
+    x0, xt0, st0 = S.solve(_t(b), _t(bt), tol=1e-9)
+    assert _iters_close(st0["iters"], ref[0].iters)
+    S.update_recycle()
+    x1, xt1, st1 = S.solve(_t(b), _t(bt), tol=1e-9)
+    assert _iters_close(st1["iters"], ref[1].iters)
+    assert st1["relres"] <= 1e-9 and _rel(_np(x1), ref[1].x) <= 1e-6
+    # bitwise determinism: the same handle state gives the same result
+    S2 = _solver(A, k=10, s=40)
+    y0, yt0, _ = S2.solve(_t(b), _t(bt), tol=1e-9)
+    assert torch.equal(x0, y0) and torch.equal(xt0, yt0)
+
+
+def test_complex_sequence_matches_oracle():
+    A = wl.random_sparse(700, 6, 31, 6.0, complex_vals=True)
+    rng = np.random.default_rng(32)
+    b = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+    bt = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+    A2 = wl.CSR(A.n, A.rowptr, A.colind, A.vals * (1 + 0.01j))
+    ref, _ = oracle.rbicg_sequence([A, A2], [b, b], [bt, bt], 8, 20, 1e-9)
+    S = _solver(A, k=8, s=20, prec="c128")
+    for j, M in enumerate([A, A2]):
+        if j:
+            S.update_recycle(M)
+        x, xt, st = S.solve(_t(b), _t(bt), tol=1e-9)
+        assert st["status"] == 0
+        assert _iters_close(st["iters"], ref[j].iters), (st["iters"], ref[j].iters)
+        assert st["relres"] <= 1e-9 and st["relres_dual"] <= 1e-9
+        assert _rel(_np(x), ref[j].x) <= 1e-6 and _rel(_np(xt), ref[j].xt) <= 1e-6
+
+
+def test_reseed_matches_oracle():
+    A = wl.convdiff(8, 2, [4.0, 2.0])
+    rng = np.random.default_rng(51)
+    b = rng.standard_normal(A.n)
+    bt = rng.standard_normal(A.n)
+    bt -= b * (b @ bt) / (b @ b)
+    ref = oracle.rbicg(A, b, bt, tol=1e-9, maxit=300, update=False)
+    S = _solver(A, k=0, s=40, update=False)
+    x, xt, st = S.solve(_t(b), _t(bt), tol=1e-9)
+    assert st["reseeds"] == ref.reseeds == 1
+    assert st["iters"] == ref.iters
+    assert _rel(_np(xt), ref.xt) <= 1e-8
+
+
+def test_bilinear_form():
+    A = wl.convdiff(20, 2, [5.0, 2.0])
+    D = A.to_dense()
+    rng = np.random.default_rng(61)
+    u, w = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    exact = u @ np.linalg.solve(D, w)
+    S = _solver(A, k=0, s=40, update=False)
+    val, err, st = S.bilinear(_t(u), _t(w), tol=1e-6)
+    ainv = np.linalg.norm(np.linalg.inv(D), 2)
+    assert abs(val - exact) <= err * ainv * 1.001 + 1e-12 * abs(exact)
+    ov, orr, _ = oracle.bilinear(A, u, w, tol=1e-6)
+    assert abs(val - ov) <= 1e-6 * abs(exact)
+
+
+def test_maxit_and_bad_args():
+    from paper_1010_0762_amd import _lib
+    A = wl.convdiff(16, 2, [4.0, 2.0])
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.n)
+    S = _solver(A, k=0, s=40, update=False, maxit=5)
+    x, xt, st = S.solve(_t(b), _t(b), tol=1e-12)
+    assert st["status"] == _lib.RBICG_NOT_CONVERGED and st["iters"] == 5
+    with pytest.raises(TypeError):
+        S.solve(_t(b[:10]), _t(b), tol=1e-8)
+    with pytest.raises(_lib.RBiCGError):
+        _solver(A, k=65)

@@ -1,0 +1,138 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the public
+headers declare, and its host FP64 dense linear algebra (used at cycle ends)
+agrees with numpy/scipy.  No GPU call is made."""
+import ctypes as ct
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_1010_0762_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names.update(re.findall(r"\b(rbicg_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 15
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+        assert nm in _lib.SIGNATURES, nm
+
+
+def _c(a):
+    a = np.asfortranarray(a.astype(np.complex128))
+    return np.ascontiguousarray(a.T.reshape(-1)).view(np.float64).copy()  # column-major interleaved
+
+
+def _uc(buf, m, n):
+    return buf.view(np.complex128).reshape(n, m).T
+
+
+@pytest.mark.parametrize("m,cplx,gen", [(12, False, False), (30, True, False), (25, True, True),
+                                        (41, False, True)])
+def test_host_eig_matches_scipy(m, cplx, gen):
+    lib = _lib.load()
+    rng = np.random.default_rng(m)
+    P = rng.standard_normal((m, m)) + (1j * rng.standard_normal((m, m)) if cplx else 0)
+    Q = (np.eye(m) + 0.2 * rng.standard_normal((m, m))) if gen else None
+    lam = np.zeros(2 * m); W = np.zeros(2 * m * m); Wl = np.zeros(2 * m * m)
+    Pb = _c(P); Qb = _c(Q) if gen else None
+    rc = lib.rbicg_host_eig(m, _lib.dptr(Pb), _lib.dptr(Qb) if gen else None, _lib.dptr(lam),
+                            _lib.dptr(W), _lib.dptr(Wl))
+    assert rc == 0
+    lam = lam.view(np.complex128)
+    W = _uc(W, m, m); Wl = _uc(Wl, m, m)
+    ref = sla.eigvals(P, Q)
+    for l in ref:
+        assert np.min(np.abs(lam - l)) <= 1e-9 * max(1, abs(l))
+    Qm = Q if gen else np.eye(m)
+    scale = np.linalg.norm(P, 2) + np.abs(lam).max() * np.linalg.norm(Qm, 2)
+    for j in range(m):
+        assert np.linalg.norm(P @ W[:, j] - lam[j] * Qm @ W[:, j]) <= 1e-10 * scale
+        y = Wl[:, j]
+        assert np.linalg.norm(y.conj() @ P - lam[j] * (y.conj() @ Qm)) <= 1e-10 * scale
+        assert abs(np.linalg.norm(W[:, j]) - 1) < 1e-12
+
+
+def test_host_svd_and_heig():
+    lib = _lib.load()
+    rng = np.random.default_rng(5)
+    for m, n in [(9, 9), (20, 13)]:
+        A = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+        U = np.zeros(2 * m * n); s = np.zeros(n); V = np.zeros(2 * n * n)
+        assert lib.rbicg_host_svd(m, n, _lib.dptr(_c(A)), _lib.dptr(U), _lib.dptr(s), _lib.dptr(V)) == 0
+        U = _uc(U, m, n); V = _uc(V, n, n)
+        assert np.allclose(s, np.linalg.svd(A, compute_uv=False), rtol=1e-12)
+        assert np.allclose(U @ np.diag(s) @ V.conj().T, A, atol=1e-12)
+    H = rng.standard_normal((15, 15)) + 1j * rng.standard_normal((15, 15))
+    H = H + H.conj().T
+    w = np.zeros(15); V = np.zeros(2 * 225)
+    assert lib.rbicg_host_heig(15, _lib.dptr(_c(H)), _lib.dptr(w), _lib.dptr(V)) == 0
+    V = _uc(V, 15, 15)
+    assert np.allclose(w, np.linalg.eigvalsh(H), atol=1e-12)
+    assert np.allclose(V @ np.diag(w) @ V.conj().T, H, atol=1e-11)
+
+
+def test_host_select_real_pairs_and_order():
+    lib = _lib.load()
+    # real matrix with known spectrum: 1, 2, 3+-1i, 10, 20
+    rng = np.random.default_rng(7)
+    Lam = np.zeros((6, 6))
+    Lam[0, 0], Lam[1, 1] = 1.0, 2.0
+    Lam[2:4, 2:4] = [[3.0, 1.0], [-1.0, 3.0]]
+    Lam[4, 4], Lam[5, 5] = 10.0, 20.0
+    S = np.eye(6) + 0.3 * rng.standard_normal((6, 6))
+    M = S @ Lam @ np.linalg.inv(S)
+    m = 6
+    lam = np.zeros(2 * m); W = np.zeros(2 * m * m); Wl = np.zeros(2 * m * m)
+    lib.rbicg_host_eig(m, _lib.dptr(_c(M)), None, _lib.dptr(lam), _lib.dptr(W), _lib.dptr(Wl))
+    for k, expect in [(4, 4), (3, 2), (5, 5)]:
+        Ws = np.zeros(2 * m * m); Wls = np.zeros(2 * m * m)
+        got = lib.rbicg_host_select(m, _lib.dptr(lam), _lib.dptr(W), _lib.dptr(Wl), k, 1,
+                                    _lib.dptr(Ws), _lib.dptr(Wls))
+        assert got == expect
+        Wsel = _uc(Ws, m, m)[:, :got]
+        assert np.abs(Wsel.imag).max() == 0.0
+        # the selected real columns span the invariant subspace of the smallest eigenvalues
+        ref = S[:, :got]
+        ang = sla.subspace_angles(Wsel.real, ref)
+        assert ang.max() < 1e-8
+
+
+def test_host_biorth_gives_identity():
+    lib = _lib.load()
+    rng = np.random.default_rng(9)
+    n, k = 200, 7
+    C = rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))
+    Ct = C + 0.3 * (rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    Gcc, Gtt, Gtc = C.conj().T @ C, Ct.conj().T @ Ct, Ct.conj().T @ C
+    TU = np.zeros(2 * k * k); TUt = np.zeros(2 * k * k)
+    p = lib.rbicg_host_biorth(k, _lib.dptr(_c(Gcc)), _lib.dptr(_c(Gtt)), _lib.dptr(_c(Gtc)), 1e-2,
+                              _lib.dptr(TU), _lib.dptr(TUt))
+    assert p == k
+    TU = _uc(TU, k, k)[:, :p]; TUt = _uc(TUt, k, k)[:, :p]
+    G = (Ct @ TUt).conj().T @ (C @ TU)
+    assert np.abs(G - np.eye(p)).max() < 1e-12
+    # cosines of principal angles decide the truncation
+    cos = np.cos(sla.subspace_angles(C, Ct))
+    Ct2 = Ct.copy(); Ct2[:, 0] = rng.standard_normal(n)  # nearly orthogonal direction
+    q1, _ = np.linalg.qr(C); q2, _ = np.linalg.qr(Ct2)
+    sv = np.linalg.svd(q2.conj().T @ q1, compute_uv=False)
+    p2 = lib.rbicg_host_biorth(k, _lib.dptr(_c(Gcc)), _lib.dptr(_c(Ct2.conj().T @ Ct2)),
+                               _lib.dptr(_c(Ct2.conj().T @ C)), 0.5, _lib.dptr(TU.copy()),
+                               _lib.dptr(TUt.copy()))
+    assert p2 == int(np.sum(sv >= 0.5))
