@@ -1,0 +1,166 @@
+"""Benchmark: dual-system solves/sec of recycling BiCG on one MI355X.
+
+Workload (default): 3D convection-diffusion, 7-point upwind, 64^3 grid
+(n = 262144), a sequence of 10 dual systems with beta_j = (20,10,5)(1+0.02j),
+b, b~ ~ N(0,1) drawn once, k = 20 recycle vectors, cycle length s = 40,
+relative tolerance 1e-8, FP64.  All matrices and right-hand sides are resident
+in device memory before the timed region.  One step = solving the whole
+sequence from an empty recycle space (recycle-space updates included).
+
+Prints one JSON line.  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dual-system solves/sec + HBM GB/s per RBiCG iter; p50/p99 latency served"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=64, help="grid edge")
+    ap.add_argument("--nsys", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-timed", type=int, default=1,
+                    help="1: time the iteration kernels with HIP events inside the timed region")
+    ap.add_argument("--chunk", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(seq):
+    """The oracle as it stands, on a bounded sample: the first dual system of
+    the sequence (from an empty recycle space, with its cycle updates)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    t0 = time.perf_counter()
+    res = oracle.rbicg(seq.mats[0], seq.b[0], seq.bt[0], tol=seq.tol, maxit=20000, s=seq.s,
+                       k=seq.k)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "dual-system solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"system 0 of the sequence ({res.iters} iterations, {res.cycles} recycle "
+                       f"updates) in {dt:.1f} s; sparse products single-threaded, dense "
+                       f"vector/basis work on {threads} BLAS threads")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1010_0762_amd import workloads as wl
+    from paper_1010_0762_amd.solver import Solver, DeviceMatrix
+
+    seq = wl.cfg2_sequence(nsys=args.nsys, N=args.N)
+    n = seq.mats[0].n
+    torch.cuda.set_device(0)
+    mats = [DeviceMatrix(A) for A in seq.mats]
+    b = torch.as_tensor(seq.b[0], device="cuda")
+    bt = torch.as_tensor(seq.bt[0], device="cuda")
+    xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
+    xts = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
+    S = Solver(mats[0], k=seq.k, s=seq.s, prec="f64", chunk=args.chunk,
+               profile=bool(args.profile_timed))
+
+    def step():
+        S.set_recycle(None, None)
+        stats = []
+        for j in range(args.nsys):
+            S.update_recycle(mats[j])
+            xs[j].zero_()
+            xts[j].zero_()
+            _, _, st = S.solve(b, bt, xs[j], xts[j], tol=seq.tol)
+            stats.append(st)
+        return stats
+
+    for _ in range(args.warmup):
+        step()
+    S.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for _ in range(args.steps):
+        all_stats.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = S.profile(reset=True)
+
+    iters = [st["iters"] for st in all_stats[-1]]
+    deterministic = all([st["iters"] for st in stp] == iters for stp in all_stats)
+    tot_iters = sum(sum(st["iters"] for st in stp) for stp in all_stats)
+    relres = max(max(st["relres"], st["relres_dual"]) for stp in all_stats for st in stp)
+    ok = all(st["status"] == 0 for stp in all_stats for st in stp)
+    solves = args.steps * args.nsys
+    value = solves / elapsed
+    iter_bytes = prof["iter_bytes"]
+    eff_gbs = iter_bytes * tot_iters / elapsed / 1e9
+    kernels = {
+        "spmv_restrict": (prof["spmv_ms"], prof["spmv_n"]),
+        "expand_sigma": (prof["expand_ms"], prof["expand_n"]),
+        "update_norms": (prof["update_ms"], prof["update_n"]),
+    }
+    roof = None
+    if prof["spmv_n"] > 0:
+        avg_ms = prof["spmv_ms"] / prof["spmv_n"]
+        achieved = prof["spmv_bytes"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_iter_spmv (direction update + A p, A^H p~ + restriction)",
+                "avg_us": round(avg_ms * 1e3, 2),
+                "alg_bytes_per_launch": prof["spmv_bytes"]}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "dual-system solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"convdiff3d_{args.N}^3_seq{args.nsys}_k{seq.k}_s{seq.s}_tol1e-8",
+                   "n": n, "nnz": seq.mats[0].nnz, "systems_per_step": args.nsys, "k": seq.k,
+                   "s": seq.s, "tol": seq.tol, "precision": "FP64"},
+        "iters_per_system": iters,
+        "total_iters": tot_iters,
+        "us_per_iter": round(elapsed / tot_iters * 1e6, 2),
+        "effective_gbs_per_iter": round(eff_gbs, 1),
+        "alg_bytes_per_iter": iter_bytes,
+        "max_true_relres": relres,
+        "iters_identical_across_steps": deterministic,
+        "all_converged": ok,
+        "kernel_avg_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in kernels.items()},
+        "kernel_share": {k: round(v[0] / max(1e-9, sum(u[0] for u in kernels.values())), 3)
+                         for k, v in kernels.items()},
+        "profiled_timed_region": bool(args.profile_timed),
+        "roofline": roof,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline(seq),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

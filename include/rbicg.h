@@ -94,7 +94,9 @@ typedef struct {
  *   inner_tol    FP32 inner tolerance of RBICG_F32_IN_F64_OUT
  *   max_outer    outer refinement steps of RBICG_F32_IN_F64_OUT
  *   stream       hipStream_t to run on (NULL: the null stream)
- *   chunk        iterations launched between convergence polls (0: auto) */
+ *   chunk        iterations launched between convergence polls (0: auto)
+ *   profile      1: time every iteration kernel with HIP events (read with
+ *                rbicg_profile); adds event records between the launches */
 typedef struct {
   int32_t k, s, maxit, max_restarts, update;
   double svd_tol;
@@ -104,7 +106,13 @@ typedef struct {
   int32_t max_outer;
   void *stream;
   int32_t chunk;
+  int32_t profile;
 } rbicg_opts;
+
+/* A matrix repacked and resident in device memory (A and its explicit A^H),
+ * so that a sequence's matrices can be uploaded once and switched without
+ * host work.  It must outlive every handle that uses it. */
+typedef struct rbicg_mat_s *rbicg_matrix;
 
 /* Per-solve statistics.  relres / relres_dual are TRUE relative residuals
  * ||b - A x|| / ||b|| computed after the solve; alg_bytes counts the
@@ -116,8 +124,32 @@ typedef struct {
 
 /* Fill *opts with defaults: k=20, s=40, maxit=10000, max_restarts=2,
  * update=1, svd_tol=1e-2, seed=0, prec=RBICG_F64, inner_tol=1e-5,
- * max_outer=30, stream=NULL, chunk=0. */
+ * max_outer=30, stream=NULL, chunk=0, profile=0. */
 void rbicg_default_opts(rbicg_opts *opts);
+
+/* Repack A (and A^H, built on the host by a counting sort when AH is NULL)
+ * into device memory once (a matrix of the sequence of eq. initialSys).
+ * Blocks until the upload is complete. */
+int rbicg_matrix_create(const rbicg_csr *A, const rbicg_csr *AH, rbicg_matrix *out);
+
+/* Free a matrix made by rbicg_matrix_create (no handle may still use it). */
+int rbicg_matrix_destroy(rbicg_matrix m);
+
+/* As rbicg_create, on a preloaded matrix (not owned by the handle). */
+int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);
+
+/* As rbicg_update_recycle with A_next given as a preloaded matrix (NULL: keep
+ * the current one): no host-side repacking or upload. */
+int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next);
+
+/* Kernel timing of the iteration kernels accumulated while opts.profile is
+ * set: out[0..5] = total ms and launch count of (1) the fused direction
+ * update + paired SpMV + restriction kernel, (2) the expansion + (p~, q)
+ * kernel, (3) the recurrence update + norms kernel; out[6] = algorithmic bytes
+ * of one launch of kernel (1) with the current recycle dimension, out[7] =
+ * algorithmic bytes of one iteration.  reset = 1 clears the counters after
+ * reading.  out: host array of 8 doubles. */
+int rbicg_profile(rbicg_handle h, int32_t reset, double *out);
 
 /* Create a handle for matrix A (problem statement, Sec. 1).  AH may be NULL,
  * in which case the explicit conjugate transpose A^H is built on the host by
@@ -170,8 +202,8 @@ int rbicg_get_recycle(rbicg_handle h, void *U, void *Ut, void *C, void *Ct, int3
 
 /* Copy the per-iteration log of the last solve to host memory: for each
  * iteration i = 1..*count (at most cap), 10 doubles
- *   alpha_i (re, im), beta_{i-1} (re, im), rho_i (re, im), ||r_i||, ||r~_i||,
- *   restart index, reserved. */
+ *   alpha_i (re, im), beta_{i-1} (re, im), rho_i = (r~_i, r_i) (re, im),
+ *   ||r_i||, ||r~_i||, Re (p~_i, q_i), restart index. */
 int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *count);
 
 /* Shifted dual pairs of IRKA (Algorithm 3 steps 2-3 with E = I):

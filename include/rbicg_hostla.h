@@ -37,6 +37,12 @@ int rbicg_host_eig(int32_t m, const double *P, const double *Q, double *lam, dou
 int rbicg_host_select(int32_t m, const double *lam, const double *W, const double *Wl,
                       int32_t k, int32_t real_problem, double *Wsel, double *Wlsel);
 
+/* rbicg_host_eig followed by rbicg_host_select, computing eigenvectors only
+ * for the selected eigenvalues (the cycle-end path).  Wsel, Wlsel: m x k
+ * outputs.  Returns the number of selected columns (>= 0), or -1. */
+int rbicg_host_eig_select(int32_t m, const double *P, const double *Q, int32_t k,
+                          int32_t real_problem, double *Wsel, double *Wlsel);
+
 /* Thin SVD A = U diag(s) V^H of an m x n matrix (m >= n) by one-sided Jacobi;
  * singular values descending.  U: m x n, s: n reals, V: n x n. */
 int rbicg_host_svd(int32_t m, int32_t n, const double *A, double *U, double *s, double *V);

@@ -33,7 +33,7 @@ class rbicg_opts(ct.Structure):
                 ("max_restarts", ct.c_int32), ("update", ct.c_int32),
                 ("svd_tol", ct.c_double), ("seed", ct.c_uint64), ("prec", ct.c_int),
                 ("inner_tol", ct.c_double), ("max_outer", ct.c_int32),
-                ("stream", ct.c_void_p), ("chunk", ct.c_int32)]
+                ("stream", ct.c_void_p), ("chunk", ct.c_int32), ("profile", ct.c_int32)]
 
 
 class rbicg_stats(ct.Structure):
@@ -66,8 +66,15 @@ SIGNATURES = {
     "rbicg_get_log": (ct.c_int, [_P, _DP, _I, ct.POINTER(_I)]),
     "rbicg_solve_shifted": (ct.c_int, [_P, _I, _DP, _P, _P, _P, _P, _D, _I,
                                        ct.POINTER(rbicg_stats)]),
+    "rbicg_matrix_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(rbicg_csr),
+                                       ct.POINTER(_P)]),
+    "rbicg_matrix_destroy": (ct.c_int, [_P]),
+    "rbicg_create_on": (ct.c_int, [_P, ct.POINTER(rbicg_opts), ct.POINTER(_P)]),
+    "rbicg_update_recycle_on": (ct.c_int, [_P, _P]),
+    "rbicg_profile": (ct.c_int, [_P, _I, _DP]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),
     "rbicg_host_select": (ct.c_int, [_I, _DP, _DP, _DP, _I, _I, _DP, _DP]),
+    "rbicg_host_eig_select": (ct.c_int, [_I, _DP, _DP, _I, _I, _DP, _DP]),
     "rbicg_host_svd": (ct.c_int, [_I, _I, _DP, _DP, _DP, _DP]),
     "rbicg_host_heig": (ct.c_int, [_I, _DP, _DP, _DP]),
     "rbicg_host_biorth": (ct.c_int, [_I, _DP, _DP, _DP, _D, _DP, _DP]),

@@ -21,10 +21,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librbicg.so")
 
 ARCH = os.environ.get("RBICG_ARCH", "gfx950")
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fcx-limited-range",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-parameter"]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-fcx-limited-range", "-march=x86-64-v3"]
 
 
 def hipcc() -> str:

@@ -12,15 +12,17 @@ struct cd {
   double x, y;
 };
 
-// Per-handle scalar block in device memory.  Complex slots hold real values
-// in .x with .y = 0 for real problems.
+// Per-handle scalar block in device memory.  Vectors of k complex or real
+// values are stored as doubles (ND = 1 or 2 per value): zbuf holds
+// [zeta_i | zeta~_i] of the current iteration, zc holds [zeta_c | zeta~_c],
+// gbuf holds host-requested restrictions, red the results of host-requested
+// dot products.
 struct Scalars {
-  cd rho, beta, alpha, sigma;
-  double rn, rtn, bn, btn, tol;
+  double tol, bn, btn;
   int iter, done, status, maxit;
-  int log_base, pad0, pad1, pad2;
-  unsigned tickets[16];
-  cd zeta[KMAXD], zetat[KMAXD], zeta_c[KMAXD], zetat_c[KMAXD], g[KMAXD], gt[KMAXD];
+  double zbuf[4 * KMAXD];
+  double zc[4 * KMAXD];
+  double gbuf[4 * KMAXD];
   double red[32];
 };
 

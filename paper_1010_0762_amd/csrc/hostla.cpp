@@ -40,6 +40,8 @@ void store(const CMat &A, double *p) {
   }
 }
 double abs1(cplx z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
+// modulus without hypot's overflow guard (entries here are far from the limits)
+inline double cabs(cplx z) { return std::sqrt(z.real() * z.real() + z.imag() * z.imag()); }
 
 // LU with partial pivoting; solves A X = B in place (B overwritten by X).
 bool lu_solve(CMat A, CMat &B) {
@@ -356,6 +358,211 @@ void svd_jacobi(const CMat &A, CMat &U, std::vector<double> &s, CMat &V) {
   s = s2;
 }
 
+
+// Complex Givens rotation G = [[c, s], [-conj(s), c]] (c real) with
+// G [x; y] = [r; 0].
+struct Giv {
+  double c;
+  cplx s;
+};
+Giv givens(cplx x, cplx y) {
+  const double ax = cabs(x), ay = cabs(y);
+  if (ay == 0.0) return {1.0, 0.0};
+  if (ax == 0.0) return {0.0, std::conj(y) / ay};
+  const double r = std::sqrt(ax * ax + ay * ay);
+  const cplx ph = x / ax;
+  return {ax / r, ph * std::conj(y) / r};
+}
+// rows (i, j) of M <- G [row i; row j], columns c0..c1-1
+void rot_rows(CMat &M, int i, int j, const Giv &g, int c0, int c1) {
+  for (int c = c0; c < c1; ++c) {
+    const cplx a = M(i, c), b = M(j, c);
+    M(i, c) = g.c * a + g.s * b;
+    M(j, c) = -std::conj(g.s) * a + g.c * b;
+  }
+}
+// columns (i, j) of M <- [col i, col j] G^H, rows r0..r1-1
+void rot_cols(CMat &M, int i, int j, const Giv &g, int r0, int r1) {
+  for (int r = r0; r < r1; ++r) {
+    const cplx a = M(r, i), b = M(r, j);
+    M(r, i) = g.c * a + std::conj(g.s) * b;
+    M(r, j) = -g.s * a + g.c * b;
+  }
+}
+// column rotation that zeroes M(r, i) against M(r, j): [M(r,i), M(r,j)] G^H = [0, *]
+Giv givens_col_zero_left(cplx mi, cplx mj) {
+  // want a c + b conj(s) = 0 with a = mi, b = mj: take G from (conj(mj), -conj(mi)) style
+  const double ai = cabs(mi), aj = cabs(mj);
+  if (ai == 0.0) return {1.0, 0.0};
+  if (aj == 0.0) return {0.0, 1.0};
+  const double r = std::sqrt(ai * ai + aj * aj);
+  // c = |mj| / r, s such that mi c + mj conj(s) = 0  ->  conj(s) = -mi c / mj
+  const double c = aj / r;
+  const cplx sc = -mi * c / mj;
+  return {c, std::conj(sc)};
+}
+
+// Generalized complex Schur form of the pencil (A, B): Q^H A Z = S, Q^H B Z = T
+// with S, T upper triangular (QZ algorithm of Moler and Stewart: Hessenberg-
+// triangular reduction, then implicit single-shift QZ sweeps).
+bool qz(CMat &A, CMat &B, CMat &Q, CMat &Z) {
+  const int m = A.m;
+  Q = CMat(m, m);
+  Z = CMat(m, m);
+  for (int i = 0; i < m; ++i) { Q(i, i) = 1.0; Z(i, i) = 1.0; }
+  // B = QR by Givens, applied to A as well
+  for (int j = 0; j < m; ++j)
+    for (int i = m - 1; i > j; --i) {
+      const Giv g = givens(B(i - 1, j), B(i, j));
+      rot_rows(B, i - 1, i, g, 0, m);
+      rot_rows(A, i - 1, i, g, 0, m);
+      // Q <- Q G^H
+      rot_cols(Q, i - 1, i, g, 0, m);
+      B(i, j) = 0.0;
+    }
+  // A to Hessenberg keeping B triangular
+  for (int j = 0; j + 2 < m; ++j)
+    for (int i = m - 1; i > j + 1; --i) {
+      const Giv g = givens(A(i - 1, j), A(i, j));
+      rot_rows(A, i - 1, i, g, 0, m);
+      rot_rows(B, i - 1, i, g, 0, m);
+      rot_cols(Q, i - 1, i, g, 0, m);
+      A(i, j) = 0.0;
+      // fill-in B(i, i-1): zero it with a column rotation on (i-1, i)
+      const Giv h = givens_col_zero_left(B(i, i - 1), B(i, i));
+      rot_cols(B, i - 1, i, h, 0, m);
+      rot_cols(A, i - 1, i, h, 0, m);
+      rot_cols(Z, i - 1, i, h, 0, m);
+      B(i, i - 1) = 0.0;
+    }
+  double anorm = 0, bnorm = 0;
+  for (auto &z : A.a) anorm = std::max(anorm, abs1(z));
+  for (auto &z : B.a) bnorm = std::max(bnorm, abs1(z));
+  if (anorm == 0.0) anorm = 1.0;
+  if (bnorm == 0.0) bnorm = 1.0;
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    while (l > 0) {
+      if (abs1(A(l, l - 1)) <= kEps * (abs1(A(l - 1, l - 1)) + abs1(A(l, l)) + 1e-300 * anorm) ||
+          abs1(A(l, l - 1)) <= kEps * anorm * 1e-3) {
+        A(l, l - 1) = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    ++iter;
+    if (++total > 80 * m) return false;
+    // tiny diagonal entries of B: set to a floor (infinite eigenvalues become huge)
+    for (int i = l; i <= hi; ++i)
+      if (cabs(B(i, i)) < kEps * bnorm) B(i, i) = kEps * bnorm;
+    // shift: eigenvalue of the trailing 2x2 of A B^{-1} closest to A(hi,hi)/B(hi,hi)
+    cplx mu;
+    {
+      const cplx b11 = B(hi - 1, hi - 1), b12 = B(hi - 1, hi), b22 = B(hi, hi);
+      const cplx a11 = A(hi - 1, hi - 1), a12 = A(hi - 1, hi), a21 = A(hi, hi - 1), a22 = A(hi, hi);
+      // M = [a] [b]^{-1}, b upper triangular 2x2
+      const cplx i11 = 1.0 / b11, i22 = 1.0 / b22, i12 = -b12 / (b11 * b22);
+      const cplx m11 = a11 * i11, m12 = a11 * i12 + a12 * i22;
+      const cplx m21 = a21 * i11, m22 = a21 * i12 + a22 * i22;
+      const cplx half = 0.5 * (m11 - m22);
+      const cplx disc = std::sqrt(half * half + m12 * m21);
+      const cplx e1 = 0.5 * (m11 + m22) + disc, e2 = 0.5 * (m11 + m22) - disc;
+      const cplx tgt = a22 / b22;
+      mu = (cabs(e1 - tgt) < cabs(e2 - tgt)) ? e1 : e2;
+      if (iter % 10 == 0) mu = tgt + cplx(0.75 * cabs(a21 / b11), 0.0);
+    }
+    // first rotation from the first column of A - mu B
+    Giv g = givens(A(l, l) - mu * B(l, l), A(l + 1, l));
+    for (int k = l; k < hi; ++k) {
+      if (k > l) g = givens(A(k, k - 1), A(k + 1, k - 1));
+      rot_rows(A, k, k + 1, g, std::max(l, k - 1), m);
+      rot_rows(B, k, k + 1, g, k, m);
+      rot_cols(Q, k, k + 1, g, 0, m);
+      if (k > l) A(k + 1, k - 1) = 0.0;
+      // B(k+1, k) fill-in: column rotation on (k, k+1)
+      const Giv h = givens_col_zero_left(B(k + 1, k), B(k + 1, k + 1));
+      rot_cols(B, k, k + 1, h, 0, k + 2);
+      rot_cols(A, k, k + 1, h, 0, std::min(k + 3, hi + 1));
+      rot_cols(Z, k, k + 1, h, 0, m);
+      B(k + 1, k) = 0.0;
+    }
+  }
+  for (int j = 0; j < m; ++j)
+    for (int i = j + 1; i < m; ++i) {
+      A(i, j) = 0.0;
+      B(i, j) = 0.0;
+    }
+  return true;
+}
+
+// Eigenvalues of a complex pencil via QZ, and right eigenvectors W
+// (A w = lambda B w) and left eigenvectors Y (y^H A = lambda y^H B) for the
+// eigenvalue indices in `want` (all when empty); W and Y hold one column per
+// wanted index, in the order given.
+struct PencilSchur {
+  CMat S, T, Q, Z;
+  std::vector<cplx> lam;
+};
+bool pencil_schur(CMat A, CMat B, PencilSchur &ps) {
+  const int m = A.m;
+  if (!qz(A, B, ps.Q, ps.Z)) return false;
+  ps.S = A;
+  ps.T = B;
+  ps.lam.resize(m);
+  for (int i = 0; i < m; ++i) ps.lam[i] = A(i, i) / B(i, i);
+  return true;
+}
+void pencil_vectors(const PencilSchur &ps, const std::vector<int> &want, CMat &W, CMat &Y) {
+  const CMat &A = ps.S, &B = ps.T;
+  const int m = A.m, nw = (int)want.size();
+  double snorm = 0;
+  for (auto &z : A.a) snorm = std::max(snorm, cabs(z));
+  for (auto &z : B.a) snorm = std::max(snorm, cabs(z));
+  const double small = std::max(snorm * kEps, 1e-300);
+  W = CMat(m, nw);
+  Y = CMat(m, nw);
+  std::vector<cplx> yr(m), yl(m);
+  for (int c = 0; c < nw; ++c) {
+    const int j = want[c];
+    const cplx lj = ps.lam[j];
+    std::fill(yr.begin(), yr.end(), cplx(0.0));
+    std::fill(yl.begin(), yl.end(), cplx(0.0));
+    // right: (S - lam T) y = 0 with y supported on rows 0..j
+    yr[j] = 1.0;
+    for (int i = j - 1; i >= 0; --i) {
+      cplx sacc = 0;
+      for (int l = i + 1; l <= j; ++l) sacc += (A(i, l) - lj * B(i, l)) * yr[l];
+      cplx d = A(i, i) - lj * B(i, i);
+      if (cabs(d) < small) d = small;
+      yr[i] = -sacc / d;
+    }
+    // left: u^H (S - lam T) = 0 with u supported on rows j..m-1
+    yl[j] = 1.0;
+    for (int i = j + 1; i < m; ++i) {
+      cplx sacc = 0;
+      for (int l = j; l < i; ++l) sacc += std::conj(yl[l]) * (A(l, i) - lj * B(l, i));
+      cplx d = A(i, i) - lj * B(i, i);
+      if (cabs(d) < small) d = small;
+      yl[i] = std::conj(-sacc / d);
+    }
+    for (int i = 0; i < m; ++i) {
+      cplx a = 0, b = 0;
+      for (int l = 0; l <= j; ++l) a += ps.Z(i, l) * yr[l];
+      for (int l = j; l < m; ++l) b += ps.Q(i, l) * yl[l];
+      W(i, c) = a;
+      Y(i, c) = b;
+    }
+  }
+  normalize_cols(W);
+  normalize_cols(Y);
+}
+
 bool finite(cplx z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
 
 }  // namespace
@@ -364,36 +571,133 @@ extern "C" int rbicg_host_eig(int32_t m, const double *P, const double *Q, doubl
                               double *W, double *Wl) {
   if (m <= 0 || !P) return rbicg_fail(-1, "host_eig: bad arguments");
   CMat Pm = load(m, m, P);
-  CMat M = Pm;
-  CMat Qm;
+  CMat Qm(m, m);
   if (Q) {
     Qm = load(m, m, Q);
-    if (!lu_solve(Qm, M)) return rbicg_fail(-1, "host_eig: Q is singular");
+  } else {
+    for (int i = 0; i < m; ++i) Qm(i, i) = 1.0;
   }
-  std::vector<cplx> ev;
-  CMat X;
-  if (!eig_general(M, ev, X)) return rbicg_fail(-1, "host_eig: QR iteration did not converge");
+  PencilSchur ps;
+  if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig: QZ iteration did not converge");
+  std::vector<cplx> &ev = ps.lam;
+  CMat X, Y;
+  std::vector<int> all(m);
+  std::iota(all.begin(), all.end(), 0);
+  if (W || Wl) pencil_vectors(ps, all, X, Y);
   if (lam)
     for (int i = 0; i < m; ++i) { lam[2 * i] = ev[i].real(); lam[2 * i + 1] = ev[i].imag(); }
   if (W) store(X, W);
-  if (Wl) {
-    // y^H P = lambda y^H Q  <=>  y = Q^{-H} g with g the columns of X^{-H}.
-    CMat Xi;
-    if (!inverse(X, Xi)) return rbicg_fail(-1, "host_eig: eigenvector matrix is singular");
-    CMat G(m, m);  // X^{-H}
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) G(i, j) = std::conj(Xi(j, i));
-    if (Q) {
-      CMat QH(m, m);
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) QH(i, j) = std::conj(Qm(j, i));
-      if (!lu_solve(QH, G)) return rbicg_fail(-1, "host_eig: Q is singular");
-    }
-    normalize_cols(G);
-    store(G, Wl);
-  }
+  if (Wl) store(Y, Wl);
   return 0;
 }
+
+namespace {
+// One selected eigenvalue and how its vector enters the recycle space:
+// 0 as is (complex problem), 1 real eigenvalue of a real problem (phase
+// removed, real part), 2 conjugate pair of a real problem ([Re w, Im w]),
+// 3 complex value without a partner in a real problem (real part only).
+struct SelItem {
+  int idx, kind;
+};
+
+std::vector<SelItem> select_indices(const std::vector<cplx> &lam, int k, bool real_problem,
+                                    int &ncols) {
+  const int m = (int)lam.size();
+  std::vector<int> order;
+  for (int i = 0; i < m; ++i)
+    if (finite(lam[i])) order.push_back(i);
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    const double ma = cabs(lam[a]), mb = cabs(lam[b]);
+    if (ma != mb) return ma < mb;
+    if (lam[a].real() != lam[b].real()) return lam[a].real() < lam[b].real();
+    if (lam[a].imag() != lam[b].imag()) return lam[a].imag() < lam[b].imag();
+    return a < b;
+  });
+  std::vector<SelItem> out;
+  ncols = 0;
+  if (!real_problem) {
+    for (size_t t = 0; t < order.size() && ncols < k; ++t) {
+      out.push_back({order[t], 0});
+      ++ncols;
+    }
+    return out;
+  }
+  double scale = 1.0;
+  for (int i : order) scale = std::max(scale, cabs(lam[i]));
+  std::vector<char> used(m, 0);
+  for (size_t t = 0; t < order.size() && ncols < k; ++t) {
+    const int i = order[t];
+    if (used[i]) continue;
+    if (std::fabs(lam[i].imag()) <= 1e-9 * std::max(cabs(lam[i]), 1e-300)) {
+      used[i] = 1;
+      out.push_back({i, 1});
+      ++ncols;
+      continue;
+    }
+    int jbest = -1;
+    double dbest = 0;
+    for (int j : order) {
+      if (used[j] || j == i) continue;
+      const double d = cabs(lam[j] - std::conj(lam[i]));
+      if (jbest < 0 || d < dbest) { jbest = j; dbest = d; }
+    }
+    if (jbest < 0) break;
+    if (dbest > 1e-8 * scale) {
+      used[i] = 1;
+      out.push_back({i, 3});
+      ++ncols;
+      continue;
+    }
+    if (ncols + 2 > k) break;
+    used[i] = used[jbest] = 1;
+    out.push_back({lam[i].imag() > 0 ? i : jbest, 2});
+    ncols += 2;
+  }
+  return out;
+}
+
+std::vector<cplx> dephase(std::vector<cplx> c) {
+  int im = 0;
+  for (size_t i = 1; i < c.size(); ++i)
+    if (cabs(c[i]) > cabs(c[im])) im = (int)i;
+  const cplx ph = (cabs(c[im]) > 0) ? std::conj(c[im]) / cabs(c[im]) : cplx(1.0);
+  for (auto &z : c) z = cplx((z * ph).real(), 0.0);
+  return c;
+}
+
+// Expand the selection into output columns (m x ncols, column-major,
+// interleaved); col(c) gives the vector of selection entry c.
+template <class F>
+void emit(const std::vector<SelItem> &sel, int m, F col, double *out) {
+  int c = 0;
+  auto put = [&](const std::vector<cplx> &v) {
+    for (int i = 0; i < m; ++i) {
+      out[2 * ((size_t)i + (size_t)c * m)] = v[i].real();
+      out[2 * ((size_t)i + (size_t)c * m) + 1] = v[i].imag();
+    }
+    ++c;
+  };
+  for (size_t t = 0; t < sel.size(); ++t) {
+    std::vector<cplx> v = col((int)t);
+    switch (sel[t].kind) {
+      case 0: put(v); break;
+      case 1: put(dephase(v)); break;
+      case 2: {
+        std::vector<cplx> re(m), im(m);
+        for (int i = 0; i < m; ++i) { re[i] = v[i].real(); im[i] = v[i].imag(); }
+        put(re);
+        put(im);
+        break;
+      }
+      default: {
+        std::vector<cplx> re(m);
+        for (int i = 0; i < m; ++i) re[i] = v[i].real();
+        put(re);
+      }
+    }
+  }
+}
+}  // namespace
 
 extern "C" int rbicg_host_select(int32_t m, const double *lamp, const double *Wp,
                                  const double *Wlp, int32_t k, int32_t real_problem,
@@ -401,94 +705,59 @@ extern "C" int rbicg_host_select(int32_t m, const double *lamp, const double *Wp
   if (m <= 0 || k < 0 || !lamp || !Wp || !Wsel) return rbicg_fail(-1, "host_select: bad arguments");
   std::vector<cplx> lam(m);
   for (int i = 0; i < m; ++i) lam[i] = cplx(lamp[2 * i], lamp[2 * i + 1]);
-  CMat W = load(m, m, Wp);
+  const CMat W = load(m, m, Wp);
   CMat Wl;
   if (Wlp) Wl = load(m, m, Wlp);
-  std::vector<int> order;
-  for (int i = 0; i < m; ++i)
-    if (finite(lam[i])) order.push_back(i);
-  std::sort(order.begin(), order.end(), [&](int a, int b) {
-    double ma = std::abs(lam[a]), mb = std::abs(lam[b]);
-    if (ma != mb) return ma < mb;
-    if (lam[a].real() != lam[b].real()) return lam[a].real() < lam[b].real();
-    if (lam[a].imag() != lam[b].imag()) return lam[a].imag() < lam[b].imag();
-    return a < b;
-  });
-  std::vector<std::vector<cplx>> cols, lcols;
-  auto column = [&](const CMat &A, int j) {
-    std::vector<cplx> c(m);
-    for (int i = 0; i < m; ++i) c[i] = A(i, j);
-    return c;
+  int ncols = 0;
+  const std::vector<SelItem> sel = select_indices(lam, k, real_problem != 0, ncols);
+  auto colW = [&](int t) {
+    std::vector<cplx> v(m);
+    for (int i = 0; i < m; ++i) v[i] = W(i, sel[t].idx);
+    return v;
   };
-  // phase that makes the largest entry real positive
-  auto dephase = [&](std::vector<cplx> c) {
-    int im = 0;
-    for (int i = 1; i < m; ++i)
-      if (std::abs(c[i]) > std::abs(c[im])) im = i;
-    cplx ph = (std::abs(c[im]) > 0) ? std::conj(c[im]) / std::abs(c[im]) : cplx(1.0);
-    for (auto &z : c) z = cplx((z * ph).real(), 0.0);
-    return c;
-  };
-  auto repart = [&](const std::vector<cplx> &c, bool imagpart) {
-    std::vector<cplx> o(m);
-    for (int i = 0; i < m; ++i) o[i] = imagpart ? cplx(c[i].imag(), 0.0) : cplx(c[i].real(), 0.0);
-    return o;
-  };
-  if (!real_problem) {
-    for (size_t t = 0; t < order.size() && (int)cols.size() < k; ++t) {
-      cols.push_back(column(W, order[t]));
-      if (Wlp) lcols.push_back(column(Wl, order[t]));
-    }
-  } else {
-    double scale = 1.0;
-    for (int i : order) scale = std::max(scale, std::abs(lam[i]));
-    std::vector<char> used(m, 0);
-    for (size_t t = 0; t < order.size() && (int)cols.size() < k; ++t) {
-      int i = order[t];
-      if (used[i]) continue;
-      if (std::fabs(lam[i].imag()) <= 1e-9 * std::max(std::abs(lam[i]), 1e-300)) {
-        used[i] = 1;
-        cols.push_back(dephase(column(W, i)));
-        if (Wlp) lcols.push_back(dephase(column(Wl, i)));
-        continue;
-      }
-      int jbest = -1;
-      double dbest = 0;
-      for (int j : order) {
-        if (used[j] || j == i) continue;
-        double d = std::abs(lam[j] - std::conj(lam[i]));
-        if (jbest < 0 || d < dbest) { jbest = j; dbest = d; }
-      }
-      if (jbest < 0) break;
-      if (dbest > 1e-8 * scale) {
-        used[i] = 1;
-        cols.push_back(repart(column(W, i), false));
-        if (Wlp) lcols.push_back(repart(column(Wl, i), false));
-        continue;
-      }
-      if ((int)cols.size() + 2 > k) break;
-      used[i] = used[jbest] = 1;
-      int ip = lam[i].imag() > 0 ? i : jbest;
-      auto w = column(W, ip);
-      cols.push_back(repart(w, false));
-      cols.push_back(repart(w, true));
-      if (Wlp) {
-        auto wl = column(Wl, ip);
-        lcols.push_back(repart(wl, false));
-        lcols.push_back(repart(wl, true));
-      }
-    }
+  emit(sel, m, colW, Wsel);
+  if (Wlp && Wlsel) {
+    auto colL = [&](int t) {
+      std::vector<cplx> v(m);
+      for (int i = 0; i < m; ++i) v[i] = Wl(i, sel[t].idx);
+      return v;
+    };
+    emit(sel, m, colL, Wlsel);
   }
-  for (size_t j = 0; j < cols.size(); ++j)
-    for (int i = 0; i < m; ++i) {
-      Wsel[2 * (i + j * m)] = cols[j][i].real();
-      Wsel[2 * (i + j * m) + 1] = cols[j][i].imag();
-      if (Wlp && Wlsel) {
-        Wlsel[2 * (i + j * m)] = lcols[j][i].real();
-        Wlsel[2 * (i + j * m) + 1] = lcols[j][i].imag();
-      }
-    }
-  return (int)cols.size();
+  return ncols;
+}
+
+extern "C" int rbicg_host_eig_select(int32_t m, const double *P, const double *Q, int32_t k,
+                                     int32_t real_problem, double *Wsel, double *Wlsel) {
+  if (m <= 0 || k < 0 || !P || !Wsel || !Wlsel) return rbicg_fail(-1, "host_eig_select: bad arguments");
+  CMat Pm = load(m, m, P);
+  CMat Qm(m, m);
+  if (Q) {
+    Qm = load(m, m, Q);
+  } else {
+    for (int i = 0; i < m; ++i) Qm(i, i) = 1.0;
+  }
+  PencilSchur ps;
+  if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig_select: QZ iteration did not converge");
+  int ncols = 0;
+  const std::vector<SelItem> sel = select_indices(ps.lam, k, real_problem != 0, ncols);
+  std::vector<int> want;
+  for (const auto &it : sel) want.push_back(it.idx);
+  CMat W, Y;
+  pencil_vectors(ps, want, W, Y);
+  auto colW = [&](int t) {
+    std::vector<cplx> v(m);
+    for (int i = 0; i < m; ++i) v[i] = W(i, t);
+    return v;
+  };
+  auto colY = [&](int t) {
+    std::vector<cplx> v(m);
+    for (int i = 0; i < m; ++i) v[i] = Y(i, t);
+    return v;
+  };
+  emit(sel, m, colW, Wsel);
+  emit(sel, m, colY, Wlsel);
+  return ncols;
 }
 
 extern "C" int rbicg_host_svd(int32_t m, int32_t n, const double *A, double *U, double *s,

@@ -11,37 +11,57 @@ struct ColList {
   const void *p[RBICG_MAXCOLS];
 };
 
+// Blocks of the iteration kernels for n rows (at most 8 rows per thread).
+int iter_grid(int n);
+
 template <class V, class M>
-void launch_iter_spmv(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, const V *r,
-                      const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt,
-                      const V *C, const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ,
-                      V *capZt, double *partial, Scalars *S);
+void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, const V *r,
+                const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt, const V *C,
+                const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
+                const double *P3, double *P1, Scalars *S, double *rec, int it, int first);
+template <class V>
+void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
+                const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
+                double *P2, Scalars *S);
+template <class V>
+void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
+                const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
+                Scalars *S, double *rec, int it);
+template <class V>
+void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
+                  int first);
+template <class V>
+void launch_init_p3(hipStream_t st, int nb, int n, const V *r, const V *rt, double *P3);
+// dots (a_i, b_i), i < 3, reduced into out[0 .. 3*ND)
+template <class V>
+void launch_dots(hipStream_t st, int nb, int n, const V *a0, const V *b0, const V *a1,
+                 const V *b1, const V *a2, const V *b2, double *P, double *out);
+// [B^H u, B2^H u2] reduced into out[0 .. 2*k*ND)
+template <class V>
+void launch_restrict(hipStream_t st, int nb, int n, const V *u, const V *B, const V *u2,
+                     const V *B2, int k, int ld, double *P, double *out);
+void launch_fin_red(hipStream_t st, const double *P, int nb, int nv, double *out);
 template <class V, class M>
 void launch_residual(hipStream_t st, const Sell<M> &A, const V *b, const V *x, V *out);
 template <class V, class M>
 void launch_spmm(hipStream_t st, const Sell<M> &A, const V *X, V *Y, int ld, int m);
 template <class V>
-void launch_iter_expand(hipStream_t st, int n, const V *z, const V *zt, const V *C,
-                        const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, double *partial,
-                        Scalars *S);
-template <class V>
-void launch_iter_update(hipStream_t st, int n, V *x, V *xt, V *r, V *rt, const V *pn,
-                        const V *ptn, const V *q, const V *qt, double *partial, Scalars *S,
-                        double *log);
-template <class V>
-void launch_restrict(hipStream_t st, int n, const V *u, const V *B, const V *u2, const V *B2,
-                     int k, int ld, double *partial, Scalars *S);
-template <class V>
 void launch_expand2(hipStream_t st, int n, V *x, const V *U, double sx, V *r, const V *C,
                     double sr, V *xt, const V *Ut, double sxt, V *rt, const V *Ct, double srt,
-                    int k, int ld, int mode, const Scalars *S);
-template <class V>
-void launch_dots(hipStream_t st, int n, const V *a0, const V *b0, const V *a1, const V *b1,
-                 const V *a2, const V *b2, double *partial, Scalars *S);
+                    int k, int ld, const double *coef);
 template <class V>
 void launch_fill_zero(hipStream_t st, V *p, size_t n);
 template <class V>
 void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed);
+// row chunks (blocks) of the Gram kernel for n rows
+int gram_chunks(int n);
+// Gram kernel: rows per LDS slab, LDS budget per block
+#define GRAM_SR_R 32
+#define GRAM_SR_C 16
+#define GRAM_LDS_BYTES 65536
+// widest column group of Y per Gram launch for mx columns of X
+int gram_group(int mx, int complex_vals);
+// G = X^H Y for mx, my <= 192 columns (complex (re, im) row-major by (i, j))
 template <class V>
 void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
                  double *partial, double *G, int nchunks);

@@ -1,26 +1,34 @@
 // gfx950 kernels of the RBiCG hot path (Algorithm 2) and of the cycle-end
 // recycle-space computations (Sec. 4).
 //
-// One iteration of Algorithm 2 is three launches, each ending in a grid-wide
-// reduction finished by the last block to arrive (ticket counter, fixed
-// summation order, so results are deterministic):
-//   k_iter_spmv    p = r + beta p, p~ = r~ + conj(beta) p~ (own rows written,
-//                  gathered rows recomputed on the fly), z = A p and
-//                  z~ = A^H p~ from the two sliced-ELL matrices (no atomics),
-//                  and the restriction zeta = C~^H z, zeta~ = C^H z~;
-//   k_iter_expand  q = z - C zeta, q~ = z~ - C~ zeta~, sigma = (p~, q),
-//                  alpha = rho / sigma, zeta_c += alpha zeta, ...;
-//   k_iter_update  x += alpha p, x~ += conj(alpha) p~, r -= alpha q,
-//                  r~ -= conj(alpha) q~, ||r||, ||r~||, rho' = (r~, r), the
-//                  stopping test and beta = rho' / rho.
-// Every launch first reads the device 'done' flag and returns at once after
-// convergence, so the host may enqueue iterations ahead of the test.
+// One iteration i of Algorithm 2 is three launches.  No kernel synchronizes
+// its grid: each writes one partial sum per block, and every block of the
+// NEXT kernel reduces those partials itself, in a fixed order (so every block
+// obtains bit-identical scalars and runs are deterministic; no atomics, no
+// fences, no extra launches):
+//   k_it1  reduce ||r_{i-1}||^2, ||r~_{i-1}||^2, rho_{i-1} = (r~, r); stopping
+//          test; beta_{i-1} = rho_{i-1} / rho_{i-2};
+//          p = r + beta p, p~ = r~ + conj(beta) p~ (own rows written, gathered
+//          rows recomputed on the fly), z = A p, z~ = A^H p~ from the two
+//          sliced-ELL matrices (no atomics), partials of zeta = C~^H z and
+//          zeta~ = C^H z~;
+//   k_it2  reduce zeta, zeta~; q = z - C zeta, q~ = z~ - C~ zeta~; partials of
+//          sigma = (p~, q);
+//   k_it3  reduce sigma; alpha = rho_{i-1} / sigma, zeta_c += alpha zeta,
+//          zeta~_c += conj(alpha) zeta~; x += alpha p, x~ += conj(alpha) p~,
+//          r -= alpha q, r~ -= conj(alpha) q~; partials of ||r||^2, ||r~||^2,
+//          (r~, r).
+// Block 0 records the scalars of every iteration for the host.  Every launch
+// first reads the device 'done' flag and returns at once after the stopping
+// test has fired, so the host may enqueue iterations ahead of the test.
 //
 // Vector storage type V is double, float (FP32-inner mode; every element
 // operation is done in double and rounded once when stored) or cd (complex).
 // Matrix value type M is double, float or cd.  Reductions accumulate in
 // double.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device.h"
 #include "kernels.h"
@@ -79,99 +87,71 @@ __device__ __forceinline__ cd cdiv(cd a, cd b) {
   return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
 }
 
+
 // ------------------------------------------------------------ reductions
+#define IB 1024               // threads per block of the iteration kernels
+#define NW (IB / 64)          // waves per block
+#define RMAX 8                // rows per thread at most
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__device__ __forceinline__ double ld_coherent(const double *p) {
-  unsigned long long v = __hip_atomic_load((unsigned long long *)p, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)v);
-}
-
-// Block partial of one value: every wave reduces its lanes, wave sums go to
-// lds[wave * stride + idx].
-__device__ __forceinline__ void wave_put(double *lds, int stride, int idx, double v) {
+// wave sum of v into lds[wave * stride + idx]
+__device__ __forceinline__ void wput(double *lds, int stride, int idx, double v) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) lds[(threadIdx.x >> 6) * stride + idx] = v;
 }
-
-// Sum the 4 wave slots of nv values in a fixed order and store the block
-// partial (caller synchronizes before).
-__device__ __forceinline__ void block_store(const double *lds, int stride, int nv,
-                                            double *partial) {
-  for (int t = threadIdx.x; t < nv; t += RBICG_BLOCK) {
-    double s = lds[t] + lds[stride + t] + lds[2 * stride + t] + lds[3 * stride + t];
-    partial[(size_t)blockIdx.x * nv + t] = s;
-  }
-}
-
-// Grid arrival: true in the last block to finish.  Partials written before
-// the call are visible to that block afterwards.
-__device__ __forceinline__ bool arrive_last(unsigned *ticket, unsigned nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(ticket, 1u);
-    s_last = (prev == nblocks - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
-// Last block: out[t] = sum over blocks of partial[b*nv + t], summed in a fixed
-// order (groups of blocks, then the groups in order).  nv <= 256.
-__device__ void grid_finish(const double *partial, int nv, int nblocks, double *tmp,
-                            double *out, unsigned *ticket) {
-  const int G = (nv >= RBICG_BLOCK) ? 1 : RBICG_BLOCK / nv;
-  const int t = threadIdx.x;
-  const int j = t % nv, g = t / nv;
-  if (g < G && t < G * nv) {
-    double s = 0.0;
-    for (int b = g; b < nblocks; b += G) s += ld_coherent(&partial[(size_t)b * nv + j]);
-    tmp[g * nv + j] = s;
-  }
-  __syncthreads();
-  for (int u = t; u < nv; u += RBICG_BLOCK) {
-    double s = 0.0;
-    for (int gg = 0; gg < G; ++gg) s += tmp[gg * nv + u];
-    out[u] = s;
-  }
-  __syncthreads();
-  if (t == 0) atomicExch(ticket, 0u);
-}
-
 template <class T> __device__ __forceinline__ void put(double *lds, int stride, int idx, T v) {
 #pragma unroll
-  for (int c = 0; c < ND<T>::v; ++c) wave_put(lds, stride, idx * ND<T>::v + c, comp(v, c));
+  for (int c = 0; c < ND<T>::v; ++c) wput(lds, stride, idx * ND<T>::v + c, comp(v, c));
 }
 template <class T> __device__ __forceinline__ T get(const double *v, int idx);
 template <> __device__ __forceinline__ double get<double>(const double *v, int idx) { return v[idx]; }
 template <> __device__ __forceinline__ cd get<cd>(const double *v, int idx) {
   return {v[2 * idx], v[2 * idx + 1]};
 }
+template <class T> __device__ __forceinline__ void set(double *v, int idx, T x) {
+#pragma unroll
+  for (int c = 0; c < ND<T>::v; ++c) v[idx * ND<T>::v + c] = comp(x, c);
+}
 
-// Restriction partials: out_j = sum_rows conj(B[j]) u, out2_j = sum conj(B2[j]) u2
-// (j < k); values go to LDS slots [0, k) and [k, 2k) (times ND).
-template <class V, class T>
-__device__ __forceinline__ void restrict_pair(int row, int n, T u, T u2, const V *B,
-                                              const V *B2, int k, int ld, double *lds,
-                                              int stride) {
-  for (int j = 0; j < k; ++j) {
-    T a = zero<T>(), b = zero<T>();
-    if (row < n) {
-      a = cj(up(B[(size_t)j * ld + row])) * u;
-      b = cj(up(B2[(size_t)j * ld + row])) * u2;
-    }
-    put<T>(lds, stride, j, a);
-    put<T>(lds, stride, k + j, b);
+// Block partial: P[block * nv + t] = sum over the waves (fixed order) of the
+// wave sums in lds (caller synchronizes before).
+__device__ __forceinline__ void bstore(const double *lds, int stride, int nwaves, int nv,
+                                       double *P) {
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += lds[w * stride + t];
+    P[(size_t)blockIdx.x * nv + t] = s;
   }
 }
+
+// Whole block: out[t] = sum over nb blocks of P[b * nv + t] (t < nv <= 256) in
+// a fixed order; every block that calls it gets the same bits.  tmp holds
+// blockDim.x doubles.  Synchronizes before returning.
+__device__ __forceinline__ void breduce(const double *P, int nb, int nv, double *tmp,
+                                        double *out) {
+  const int G = min((int)blockDim.x / nv, 32);
+  const int t = threadIdx.x, j = t % nv, g = t / nv;
+  if (g < G) {
+    double s = 0.0;
+    for (int b = g; b < nb; b += G) s += P[(size_t)b * nv + j];
+    tmp[g * nv + j] = s;
+  }
+  __syncthreads();
+  for (int u = t; u < nv; u += blockDim.x) {
+    double s = 0.0;
+    for (int gg = 0; gg < G; ++gg) s += tmp[gg * nv + u];
+    out[u] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double divide(double a, double b) { return a / b; }
+__device__ __forceinline__ cd divide(cd a, cd b) { return cdiv(a, b); }
 
 // ------------------------------------------------------------ SpMV helpers
 template <class V, class M, class T>
@@ -196,174 +176,294 @@ __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   return acc;
 }
 
+// Stopping test of iteration it-1 and beta_{it-1} (start of iteration it).
+// Every block computes the same values; block 0 records them.  Returns false
+// (uniformly) when the solve must stop.
+template <class T>
+__device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, int it, int first,
+                            double *tmp, double *red, T &beta) {
+  constexpr int nv = 2 + ND<T>::v;
+  breduce(P3, nb, nv, tmp, red);
+  const double rn = sqrt(red[0]), rtn = sqrt(red[1]);
+  const T rho = get<T>(red + 2, 0);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  double *Rm1 = rec + (size_t)(it - 1) * LOG_STRIDE;
+  if (lead) {
+    set<T>(Rm1 + 4, 0, rho);
+    if (ND<T>::v == 1) Rm1[5] = 0.0;
+    Rm1[6] = rn;
+    Rm1[7] = rtn;
+  }
+  int st = ST_RUNNING;
+  if (rn <= S->tol * S->bn && rtn <= S->tol * S->btn) st = ST_CONVERGED;
+  else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
+  else if (it > S->maxit) st = ST_MAXIT;
+  if (st != ST_RUNNING) {
+    if (lead) {
+      S->status = st;
+      S->iter = it - 1;
+      S->done = 1;
+    }
+    return false;
+  }
+  if (first) {
+    beta = zero<T>();
+  } else {
+    beta = divide(rho, get<T>(rec + (size_t)(it - 2) * LOG_STRIDE + 4, 0));
+  }
+  if (lead) {
+    double *R0 = rec + (size_t)it * LOG_STRIDE;
+    set<T>(R0 + 2, 0, beta);
+    if (ND<T>::v == 1) R0[3] = 0.0;
+  }
+  return true;
+}
+
 }  // namespace
 
 // ===================================================================== kernels
 template <class V, class M>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_iter_spmv(
+__global__ __launch_bounds__(IB) void k_it1(
     Sell<M> A, Sell<M> AH, const V *__restrict__ r, const V *__restrict__ p,
     const V *__restrict__ rt, const V *__restrict__ pt, V *__restrict__ pn, V *__restrict__ ptn,
     V *__restrict__ z, V *__restrict__ zt, const V *__restrict__ C, const V *__restrict__ Ct,
-    int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, double *partial, Scalars *S) {
+    int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, const double *__restrict__ P3,
+    double *__restrict__ P1, Scalars *S, double *rec, int it, int first) {
   using T = typename Ar<V>::T;
   if (S->done) return;
-  __shared__ double lds[4 * 4 * KMAXD];
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double res[4 * KMAXD];
-  const int n = A.n;
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  const T beta = sc<T>(S->beta);
+  __shared__ double lds[NW * 4 * KMAXD];
+  __shared__ double tmp[IB];
+  __shared__ double red[8];
+  T beta;
+  if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
   const T betac = cj(beta);
-  T zz = zero<T>(), zzt = zero<T>();
-  if (row < n) {
-    const V rv = r[row], rtv = rt[row];
-    pn[row] = down<V>(up(rv) + beta * up(p[row]));
-    ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
-    zz = up(down<V>(spmv_dir<V, M, T>(A, row, r, p, beta)));
-    zzt = up(down<V>(spmv_dir<V, M, T>(AH, row, rt, pt, betac)));
-    z[row] = down<V>(zz);
-    zt[row] = down<V>(zzt);
-    if (capR) {
-      capR[row] = rv;
-      capRt[row] = rtv;
-      capZ[row] = down<V>(zz);
-      capZt[row] = down<V>(zzt);
+  const int n = A.n;
+  const int stride = gridDim.x * IB;
+  const int row0 = blockIdx.x * IB + threadIdx.x;
+  T zr[RMAX], ztr[RMAX];
+#pragma unroll
+  for (int q = 0; q < RMAX; ++q) {
+    zr[q] = zero<T>();
+    ztr[q] = zero<T>();
+    const int row = row0 + q * stride;
+    if (row < n) {
+      const V rv = r[row], rtv = rt[row];
+      pn[row] = down<V>(up(rv) + beta * up(p[row]));
+      ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
+      const T zz = up(down<V>(spmv_dir<V, M, T>(A, row, r, p, beta)));
+      const T zzt = up(down<V>(spmv_dir<V, M, T>(AH, row, rt, pt, betac)));
+      zr[q] = zz;
+      ztr[q] = zzt;
+      z[row] = down<V>(zz);
+      zt[row] = down<V>(zzt);
+      if (capR) {
+        capR[row] = rv;
+        capRt[row] = rtv;
+        capZ[row] = down<V>(zz);
+        capZt[row] = down<V>(zzt);
+      }
     }
   }
   if (k == 0) return;
-  const int nv = 2 * k * ND<T>::v;
-  const int stride = 4 * KMAXD;
-  restrict_pair<V, T>(row, n, zz, zzt, Ct, C, k, ld, lds, stride);
-  __syncthreads();
-  block_store(lds, stride, nv, partial);
-  if (arrive_last(&S->tickets[0], gridDim.x)) {
-    grid_finish(partial, nv, gridDim.x, tmp, res, &S->tickets[0]);
-    for (int j = threadIdx.x; j < k; j += RBICG_BLOCK) {
-      S->zeta[j] = tocd(get<T>(res, j));
-      S->zetat[j] = tocd(get<T>(res, k + j));
+  const int ls = 4 * KMAXD;
+  for (int j = 0; j < k; ++j) {
+    T a = zero<T>(), b = zero<T>();
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const int row = row0 + q * stride;
+      if (row < n) {
+        a += cj(up(Ct[(size_t)j * ld + row])) * zr[q];
+        b += cj(up(C[(size_t)j * ld + row])) * ztr[q];
+      }
     }
+    put<T>(lds, ls, j, a);
+    put<T>(lds, ls, k + j, b);
   }
+  __syncthreads();
+  bstore(lds, ls, NW, 2 * k * ND<T>::v, P1);
 }
 
 template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_iter_expand(
-    int n, const V *__restrict__ z, const V *__restrict__ zt, const V *__restrict__ C,
-    const V *__restrict__ Ct, int k, int ld, const V *__restrict__ ptn, V *__restrict__ q,
-    V *__restrict__ qt, double *partial, Scalars *S) {
+__global__ __launch_bounds__(IB) void k_it2(int n, const V *__restrict__ z,
+                                            const V *__restrict__ zt, const V *__restrict__ C,
+                                            const V *__restrict__ Ct, int k, int ld,
+                                            const V *__restrict__ ptn, V *__restrict__ q,
+                                            V *__restrict__ qt, const double *__restrict__ P1,
+                                            double *__restrict__ P2, Scalars *S) {
   using T = typename Ar<V>::T;
   if (S->done) return;
-  __shared__ double lds[4 * 2];
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double res[2];
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  __shared__ double lds[NW * 2];
+  __shared__ double tmp[IB];
+  __shared__ double zl[4 * KMAXD];
+  const int nv1 = 2 * k * ND<T>::v;
+  if (k > 0) {
+    breduce(P1, gridDim.x, nv1, tmp, zl);
+    if (blockIdx.x == 0)
+      for (int t = threadIdx.x; t < nv1; t += IB) S->zbuf[t] = zl[t];
+  }
+  const int stride = gridDim.x * IB;
   T part = zero<T>();
-  if (row < n) {
-    T s = zero<T>(), st = zero<T>();
-    for (int j = 0; j < k; ++j) {
-      s += up(C[(size_t)j * ld + row]) * sc<T>(S->zeta[j]);
-      st += up(Ct[(size_t)j * ld + row]) * sc<T>(S->zetat[j]);
-    }
+  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
     T qq = up(z[row]);
     T qqt = up(zt[row]);
     if (k > 0) {
+      T s = zero<T>(), st = zero<T>();
+      for (int j = 0; j < k; ++j) {
+        s += up(C[(size_t)j * ld + row]) * get<T>(zl, j);
+        st += up(Ct[(size_t)j * ld + row]) * get<T>(zl, k + j);
+      }
       qq = up(down<V>(qq - s));
       qqt = up(down<V>(qqt - st));
       q[row] = down<V>(qq);
       qt[row] = down<V>(qqt);
     }
-    part = cj(up(ptn[row])) * qq;
+    part += cj(up(ptn[row])) * qq;
   }
   put<T>(lds, 2, 0, part);
   __syncthreads();
-  block_store(lds, 2, ND<T>::v, partial);
-  if (arrive_last(&S->tickets[1], gridDim.x)) {
-    grid_finish(partial, ND<T>::v, gridDim.x, tmp, res, &S->tickets[1]);
-    if (threadIdx.x == 0) {
-      const T sigma = get<T>(res, 0);
-      S->sigma = tocd(sigma);
-      if (abs2(sigma) == 0.0 || !isfin(sigma)) {
-        S->done = 1;
-        S->status = ST_BREAKDOWN;
-        S->alpha = tocd(zero<T>());
-      } else {
-        const cd a = cdiv(S->rho, tocd(sigma));
-        S->alpha = a;
-        const T al = sc<T>(a);
-        for (int j = 0; j < k; ++j) {
-          S->zeta_c[j] = tocd(sc<T>(S->zeta_c[j]) + al * sc<T>(S->zeta[j]));
-          S->zetat_c[j] = tocd(sc<T>(S->zetat_c[j]) + cj(al) * sc<T>(S->zetat[j]));
-        }
-      }
-    }
-  }
+  bstore(lds, 2, NW, ND<T>::v, P2);
 }
 
 template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_iter_update(
-    int n, V *__restrict__ x, V *__restrict__ xt, V *__restrict__ r, V *__restrict__ rt,
-    const V *__restrict__ pn, const V *__restrict__ ptn, const V *__restrict__ q,
-    const V *__restrict__ qt, double *partial, Scalars *S, double *log) {
+__global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restrict__ xt,
+                                            V *__restrict__ r, V *__restrict__ rt,
+                                            const V *__restrict__ pn, const V *__restrict__ ptn,
+                                            const V *__restrict__ q, const V *__restrict__ qt,
+                                            int k, const double *__restrict__ P2,
+                                            double *__restrict__ P3, Scalars *S, double *rec,
+                                            int it) {
   using T = typename Ar<V>::T;
   if (S->done) return;
-  __shared__ double lds[4 * 4];
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double res[4];
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  const T al = sc<T>(S->alpha);
+  __shared__ double lds[NW * 4];
+  __shared__ double tmp[IB];
+  __shared__ double red[4];
+  breduce(P2, gridDim.x, ND<T>::v, tmp, red);
+  const T sigma = get<T>(red, 0);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  double *Ri = rec + (size_t)it * LOG_STRIDE;
+  if (abs2(sigma) == 0.0 || !isfin(sigma)) {
+    if (lead) {
+      S->status = ST_BREAKDOWN;
+      S->iter = it - 1;
+      S->done = 1;
+    }
+    return;
+  }
+  const T al = divide(get<T>(rec + (size_t)(it - 1) * LOG_STRIDE + 4, 0), sigma);
   const T alc = cj(al);
+  if (lead) {
+    set<T>(Ri, 0, al);
+    if (ND<T>::v == 1) Ri[1] = 0.0;
+    Ri[8] = comp(sigma, 0);
+    for (int j = 0; j < k; ++j) {
+      set<T>(S->zc, j, get<T>(S->zc, j) + al * get<T>(S->zbuf, j));
+      set<T>(S->zc, k + j, get<T>(S->zc, k + j) + alc * get<T>(S->zbuf, k + j));
+    }
+  }
+  const int stride = gridDim.x * IB;
   double rr = 0.0, rtrt = 0.0;
   T rho = zero<T>();
-  if (row < n) {
+  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
     x[row] = down<V>(up(x[row]) + al * up(pn[row]));
     xt[row] = down<V>(up(xt[row]) + alc * up(ptn[row]));
     const T rv = up(down<V>(up(r[row]) - al * up(q[row])));
     const T rtv = up(down<V>(up(rt[row]) - alc * up(qt[row])));
     r[row] = down<V>(rv);
     rt[row] = down<V>(rtv);
-    rr = abs2(rv);
-    rtrt = abs2(rtv);
-    rho = cj(rtv) * rv;
+    rr += abs2(rv);
+    rtrt += abs2(rtv);
+    rho += cj(rtv) * rv;
   }
-  wave_put(lds, 4, 0, rr);
-  wave_put(lds, 4, 1, rtrt);
+  wput(lds, 4, 0, rr);
+  wput(lds, 4, 1, rtrt);
 #pragma unroll
-  for (int c = 0; c < ND<T>::v; ++c) wave_put(lds, 4, 2 + c, comp(rho, c));
+  for (int c = 0; c < ND<T>::v; ++c) wput(lds, 4, 2 + c, comp(rho, c));
   __syncthreads();
-  const int nv = 2 + ND<T>::v;
-  block_store(lds, 4, nv, partial);
-  if (arrive_last(&S->tickets[2], gridDim.x)) {
-    grid_finish(partial, nv, gridDim.x, tmp, res, &S->tickets[2]);
-    if (threadIdx.x == 0) {
-      const double rn = sqrt(res[0]), rtn = sqrt(res[1]);
-      const T rho_new = get<T>(res + 2, 0);
-      const int it = S->iter + 1;
-      S->iter = it;
-      S->rn = rn;
-      S->rtn = rtn;
-      double *L = log + (size_t)(S->log_base + it) * LOG_STRIDE;
-      L[0] = S->alpha.x; L[1] = S->alpha.y;
-      L[2] = S->beta.x; L[3] = S->beta.y;
-      const cd rn_c = tocd(rho_new);
-      L[4] = rn_c.x; L[5] = rn_c.y;
-      L[6] = rn; L[7] = rtn;
-      const bool conv = rn <= S->tol * S->bn && rtn <= S->tol * S->btn;
-      if (conv) {
-        S->done = 1;
-        S->status = ST_CONVERGED;
-      } else if (abs2(rho_new) == 0.0 || !isfin(rho_new) || !isfinite(rn) || !isfinite(rtn)) {
-        S->done = 1;
-        S->status = ST_BREAKDOWN;
-      } else {
-        if (it >= S->maxit) {
-          S->done = 1;
-          S->status = ST_MAXIT;
-        }
-        S->beta = cdiv(rn_c, S->rho);
-        S->rho = rn_c;
-      }
-      if (conv) S->rho = rn_c;
-    }
+  bstore(lds, 4, NW, 2 + ND<T>::v, P3);
+}
+
+// Stopping test after the last launched iteration (one block).
+template <class V>
+__global__ __launch_bounds__(IB) void k_itfin(const double *__restrict__ P3, int nb,
+                                              Scalars *S, double *rec, int it, int first) {
+  using T = typename Ar<V>::T;
+  if (S->done) return;
+  __shared__ double tmp[IB];
+  __shared__ double red[8];
+  T beta;
+  (void)it_prologue<T>(P3, nb, S, rec, it, first, tmp, red, beta);
+}
+
+// P3-layout partials (||r||^2, ||r~||^2, (r~, r)) of the initial residuals.
+template <class V>
+__global__ __launch_bounds__(IB) void k_init_p3(int n, const V *__restrict__ r,
+                                                const V *__restrict__ rt, double *P3) {
+  using T = typename Ar<V>::T;
+  __shared__ double lds[NW * 4];
+  const int stride = gridDim.x * IB;
+  double rr = 0.0, rtrt = 0.0;
+  T rho = zero<T>();
+  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
+    const T rv = up(r[row]), rtv = up(rt[row]);
+    rr += abs2(rv);
+    rtrt += abs2(rtv);
+    rho += cj(rtv) * rv;
   }
+  wput(lds, 4, 0, rr);
+  wput(lds, 4, 1, rtrt);
+#pragma unroll
+  for (int c = 0; c < ND<T>::v; ++c) wput(lds, 4, 2 + c, comp(rho, c));
+  __syncthreads();
+  bstore(lds, 4, NW, 2 + ND<T>::v, P3);
+}
+
+// Up to three dot products (a_i, b_i) as block partials (3 * ND values).
+template <class V>
+__global__ __launch_bounds__(IB) void k_dots(int n, const V *a0, const V *b0, const V *a1,
+                                             const V *b1, const V *a2, const V *b2, double *P) {
+  using T = typename Ar<V>::T;
+  __shared__ double lds[NW * 8];
+  const int stride = gridDim.x * IB;
+  T d0 = zero<T>(), d1 = zero<T>(), d2 = zero<T>();
+  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
+    if (a0) d0 += cj(up(a0[row])) * up(b0[row]);
+    if (a1) d1 += cj(up(a1[row])) * up(b1[row]);
+    if (a2) d2 += cj(up(a2[row])) * up(b2[row]);
+  }
+  put<T>(lds, 8, 0, d0);
+  put<T>(lds, 8, 1, d1);
+  put<T>(lds, 8, 2, d2);
+  __syncthreads();
+  bstore(lds, 8, NW, 3 * ND<T>::v, P);
+}
+
+// Restriction partials: [B^H u (k values), B2^H u2 (k values)].
+template <class V>
+__global__ __launch_bounds__(IB) void k_restrict(int n, const V *u, const V *B, const V *u2,
+                                                 const V *B2, int k, int ld, double *P) {
+  using T = typename Ar<V>::T;
+  __shared__ double lds[NW * 4 * KMAXD];
+  const int stride = gridDim.x * IB;
+  const int ls = 4 * KMAXD;
+  for (int j = 0; j < k; ++j) {
+    T a = zero<T>(), b = zero<T>();
+    for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
+      a += cj(up(B[(size_t)j * ld + row])) * up(u[row]);
+      b += cj(up(B2[(size_t)j * ld + row])) * up(u2[row]);
+    }
+    put<T>(lds, ls, j, a);
+    put<T>(lds, ls, k + j, b);
+  }
+  __syncthreads();
+  bstore(lds, ls, NW, 2 * k * ND<T>::v, P);
+}
+
+// One block: out[t] = fixed-order sum of the nb block partials.
+__global__ __launch_bounds__(IB) void k_fin_red(const double *P, int nb, int nv, double *out) {
+  __shared__ double tmp[IB];
+  __shared__ double res[4 * KMAXD];
+  breduce(P, nb, nv, tmp, res);
+  for (int t = threadIdx.x; t < nv; t += IB) out[t] = res[t];
 }
 
 // r_out = b - A x (x may be null -> r_out = b)
@@ -388,48 +488,20 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm(Sell<M> A, const V *X, V *
   Y[off + row] = down<V>(spmv_plain<V, M, T>(A, row, X + off));
 }
 
-// out_j = sum conj(B[j]) u, out2_j = sum conj(B2[j]) u2 into S->g, S->gt
-template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_restrict(int n, const V *u, const V *B,
-                                                          const V *u2, const V *B2, int k,
-                                                          int ld, double *partial, Scalars *S) {
-  using T = typename Ar<V>::T;
-  __shared__ double lds[4 * 4 * KMAXD];
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double res[4 * KMAXD];
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  const T a = row < n ? up(u[row]) : zero<T>();
-  const T b = row < n ? up(u2[row]) : zero<T>();
-  const int stride = 4 * KMAXD;
-  restrict_pair<V, T>(row, n, a, b, B, B2, k, ld, lds, stride);
-  __syncthreads();
-  const int nv = 2 * k * ND<T>::v;
-  block_store(lds, stride, nv, partial);
-  if (arrive_last(&S->tickets[3], gridDim.x)) {
-    grid_finish(partial, nv, gridDim.x, tmp, res, &S->tickets[3]);
-    for (int j = threadIdx.x; j < k; j += RBICG_BLOCK) {
-      S->g[j] = tocd(get<T>(res, j));
-      S->gt[j] = tocd(get<T>(res, k + j));
-    }
-  }
-}
-
-// x += sign * sum_j U[j] coef[j]; x2 += sign2 * sum_j U2[j] coef2[j]  (two pairs)
-// mode 0: coefficients g/gt ; mode 1: zeta_c / zetat_c
+// x += sx * U c1; r += sr * C c1; xt += sxt * Ut c2; rt += srt * Ct c2 with
+// coefficients coef = [c1 (k values), c2 (k values)] (doubles, ND per value).
 template <class V>
 __global__ __launch_bounds__(RBICG_BLOCK) void k_expand2(int n, V *x, const V *U, double sx,
                                                          V *r, const V *C, double sr, V *xt,
                                                          const V *Ut, double sxt, V *rt,
                                                          const V *Ct, double srt, int k, int ld,
-                                                         int mode, const Scalars *S) {
+                                                         const double *coef) {
   using T = typename Ar<V>::T;
   const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
   if (row >= n) return;
-  const cd *c1 = mode ? S->zeta_c : S->g;
-  const cd *c2 = mode ? S->zetat_c : S->gt;
   T a = zero<T>(), b = zero<T>(), c = zero<T>(), d = zero<T>();
   for (int j = 0; j < k; ++j) {
-    const T g1 = sc<T>(c1[j]), g2 = sc<T>(c2[j]);
+    const T g1 = get<T>(coef, j), g2 = get<T>(coef, k + j);
     const size_t o = (size_t)j * ld + row;
     if (x) a += up(U[o]) * g1;
     if (r) b += up(C[o]) * g1;
@@ -440,41 +512,6 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_expand2(int n, V *x, const V *U
   if (r) r[row] = down<V>(up(r[row]) + sr * b);
   if (xt) xt[row] = down<V>(up(xt[row]) + sxt * c);
   if (rt) rt[row] = down<V>(up(rt[row]) + srt * d);
-}
-
-// Up to three dot products (a_i, b_i) = sum conj(a_i) b_i written (as cd) to
-// S->red[2i], S->red[2i+1].
-template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_dots(int n, const V *a0, const V *b0,
-                                                      const V *a1, const V *b1, const V *a2,
-                                                      const V *b2, double *partial,
-                                                      Scalars *S) {
-  using T = typename Ar<V>::T;
-  __shared__ double lds[4 * 8];
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double res[8];
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  T d0 = zero<T>(), d1 = zero<T>(), d2 = zero<T>();
-  if (row < n) {
-    if (a0) d0 = cj(up(a0[row])) * up(b0[row]);
-    if (a1) d1 = cj(up(a1[row])) * up(b1[row]);
-    if (a2) d2 = cj(up(a2[row])) * up(b2[row]);
-  }
-  put<T>(lds, 8, 0, d0);
-  put<T>(lds, 8, 1, d1);
-  put<T>(lds, 8, 2, d2);
-  __syncthreads();
-  const int nv = 3 * ND<T>::v;
-  block_store(lds, 8, nv, partial);
-  if (arrive_last(&S->tickets[4], gridDim.x)) {
-    grid_finish(partial, nv, gridDim.x, tmp, res, &S->tickets[4]);
-    if (threadIdx.x == 0)
-      for (int i = 0; i < 3; ++i) {
-        const cd v = tocd(get<T>(res, i));
-        S->red[2 * i] = v.x;
-        S->red[2 * i + 1] = v.y;
-      }
-  }
 }
 
 template <class V>
@@ -509,41 +546,107 @@ __global__ void k_reseed(V *x, size_t n, unsigned long long seed) {
 }
 
 // ----------------------------------------------------- cycle-end kernels
-// Gram partials G[i][j] = sum_rows conj(X_i) Y_j over a chunk of rows; tiles of
-// 16 x 16 outputs per block, 64-row slabs staged in LDS.
-template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_gram(int n, ColList X, int mx, ColList Y,
-                                                      int my, int rows_per_chunk,
-                                                      double *partial) {
-  using T = typename Ar<V>::T;
-  constexpr int TL = 16, SL = 64;
-  __shared__ T xs[TL][SL + 1];
-  __shared__ T ys[TL][SL + 1];
-  const int tilesy = (my + TL - 1) / TL;
-  const int ti = blockIdx.y / tilesy, tj = blockIdx.y % tilesy;
-  const int i = threadIdx.x / TL, j = threadIdx.x % TL;
-  const int gi = ti * TL + i, gj = tj * TL + j;
+// FP64 MFMA 16x16x4 (one wave): A operand A[i][kk] in lane i + 16 kk, B operand
+// B[kk][j] in lane j + 16 kk, accumulator D[i][j] in lane j + 16 (i % 4),
+// register i / 4.
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+#define GRAM_MAXT 9        // output tiles per wave (at most 36 tiles of 16 x 16)
+#define GRAM_BLOCK 256
+
+// Gram partials over a chunk of rows: G[i][j] = sum conj(X_i) Y_j for every
+// (i < mx, j < my) (mx, my <= 192, (mx16 + my16) * (SR + 2) * ND * 8 bytes of
+// LDS), one output of complex (re, im) per entry.  Each block reads its rows
+// of every column once (slabs of SR rows staged in LDS with a column stride of
+// SR + 2 doubles, which keeps the MFMA operand reads free of bank conflicts)
+// and accumulates all 16 x 16 output tiles on MFMA.
+template <class V, int SR>
+__global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int mx, ColList Y,
+                                                          int my, int rows_per_chunk,
+                                                          double *partial) {
+  constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
+  constexpr int PC = SR + 2;
+  extern __shared__ double sm[];
+  const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
+  double *xs = sm;                              // [ndv][mxp][PC]
+  double *ys = sm + (size_t)ndv * mxp * PC;     // [ndv][myp][PC]
+  const int TX = mxp / 16, TY = myp / 16, T = TX * TY;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[GRAM_MAXT][ndv];
+#pragma unroll
+  for (int t = 0; t < GRAM_MAXT; ++t)
+#pragma unroll
+    for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
   const int r0 = blockIdx.x * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  T acc = zero<T>();
-  for (int base = r0; base < r1; base += SL) {
-    // load slab: 16 columns x 64 rows for X and Y (256 threads, 4 loads each)
-    for (int t = threadIdx.x; t < TL * SL; t += RBICG_BLOCK) {
-      const int c = t / SL, rr = t % SL, row = base + rr;
-      const int cx = ti * TL + c, cy = tj * TL + c;
-      xs[c][rr] = (row < r1 && cx < mx) ? up(((const V *)X.p[cx])[row]) : zero<T>();
-      ys[c][rr] = (row < r1 && cy < my) ? up(((const V *)Y.p[cy])[row]) : zero<T>();
+  for (int base = r0; base < r1; base += SR) {
+    for (int idx = threadIdx.x; idx < (mxp + myp) * SR; idx += GRAM_BLOCK) {
+      const int c = idx / SR, rr = idx % SR, row = base + rr;
+      const bool isx = c < mxp;
+      const int cc = isx ? c : c - mxp;
+      const int lim = isx ? mx : my;
+      double vr = 0.0, vi = 0.0;
+      if (row < r1 && cc < lim) {
+        const V *col = (const V *)(isx ? X.p[cc] : Y.p[cc]);
+        const V v = col[row];
+        if constexpr (ndv == 2) {
+          vr = ((const cd &)v).x;
+          vi = ((const cd &)v).y;
+        } else {
+          vr = (double)v;
+        }
+      }
+      double *dst = isx ? xs : ys;
+      const int mp = isx ? mxp : myp;
+      dst[(size_t)cc * PC + rr] = vr;
+      if constexpr (ndv == 2) dst[(size_t)mp * PC + (size_t)cc * PC + rr] = vi;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < SL; ++rr) acc += cj(xs[i][rr]) * ys[j][rr];
+#pragma unroll
+    for (int t = 0; t < GRAM_MAXT; ++t) {
+      const int tile = w + 4 * t;
+      if (tile < T) {
+        const int ti = tile / TY, tj = tile % TY;
+        const double *xa = xs + (size_t)(ti * 16 + li) * PC + lk;
+        const double *yb = ys + (size_t)(tj * 16 + li) * PC + lk;
+        for (int kk = 0; kk < SR; kk += 4) {
+          const double ar = xa[kk], br = yb[kk];
+          if constexpr (ndv == 1) {
+            acc[t][0] = mfma(ar, br, acc[t][0]);
+          } else {
+            const double ai = xa[(size_t)mxp * PC + kk], bi = yb[(size_t)myp * PC + kk];
+            // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
+            acc[t][0] = mfma(ar, br, acc[t][0]);
+            acc[t][0] = mfma(ai, bi, acc[t][0]);
+            acc[t][1] = mfma(ar, bi, acc[t][1]);
+            acc[t][1] = mfma(-ai, br, acc[t][1]);
+          }
+        }
+      }
+    }
     __syncthreads();
   }
-  if (gi < mx && gj < my) {
-    const cd v = tocd(acc);
-    double *o = partial + ((size_t)blockIdx.x * mx * my + (size_t)gi * my + gj) * 2;
-    o[0] = v.x;
-    o[1] = v.y;
+#pragma unroll
+  for (int t = 0; t < GRAM_MAXT; ++t) {
+    const int tile = w + 4 * t;
+    if (tile < T) {
+      const int ti = tile / TY, tj = tile % TY;
+      const int gj = tj * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = ti * 16 + lk + 4 * v;
+        if (gi < mx && gj < my) {
+          double *o = partial + ((size_t)blockIdx.x * mx * my + (size_t)gi * my + gj) * 2;
+          o[0] = acc[t][0][v];
+          if constexpr (ndv == 2) o[1] = acc[t][ndv - 1][v];
+          else o[1] = 0.0;
+        }
+      }
+    }
   }
 }
 
@@ -552,33 +655,119 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_gram(int n, ColList X, int mx, 
 __global__ void k_gram_reduce(const double *partial, int nchunks, int count, double *G) {
   const int t = blockIdx.x * RBICG_BLOCK + threadIdx.x;
   if (t >= count) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += partial[(size_t)c * count + t];
-  G[t] = s;
+  // four independent chains keep several loads in flight; fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= nchunks; c += 4) {
+    s0 += partial[(size_t)c * count + t];
+    s1 += partial[(size_t)(c + 1) * count + t];
+    s2 += partial[(size_t)(c + 2) * count + t];
+    s3 += partial[(size_t)(c + 3) * count + t];
+  }
+  for (; c < nchunks; ++c) s0 += partial[(size_t)c * count + t];
+  G[t] = (s0 + s1) + (s2 + s3);
 }
 
-// Y[:, c] = sum_l X_l W[l, c] (W: m x p complex, column-major), c < p.
+// Tall-skinny product Y[:, c] = sum_l X_l W[l, c] (W: m x p complex,
+// column-major; p <= 64) computed as Y^T = W^T X^T on MFMA so that both the X
+// loads and the Y stores are contiguous 16-row segments.  Each wave owns 16
+// rows.
 template <class V>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_tsgemm(int n, ColList X, int m, const cd *W,
-                                                        int p, V *Y, int ld) {
-  using T = typename Ar<V>::T;
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  if (row >= n) return;
-  constexpr int CB = 8;
-  for (int c0 = 0; c0 < p; c0 += CB) {
-    T acc[CB];
+__global__ __launch_bounds__(256) void k_tsgemm_mfma(int n, ColList X, int m, const cd *W, int p,
+                                                     V *Y, int ld) {
+  constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = (blockIdx.x * 4 + w) * 16;
+  if (row0 >= n) return;
+  const int row = row0 + li;
+  const int JT = (p + 15) / 16;
+  d4 acc[4][ndv];
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc[u] = zero<T>();
-    for (int l = 0; l < m; ++l) {
-      const T xv = up(((const V *)X.p[l])[row]);
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int u = 0; u < CB; ++u)
-        if (c0 + u < p) acc[u] += xv * sc<T>(W[(size_t)(c0 + u) * m + l]);
+    for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int kcol = k0 + lk;
+    double xr = 0.0, xi = 0.0;
+    if (kcol < m && row < n) {
+      const V v = ((const V *)X.p[kcol])[row];
+      if constexpr (ndv == 2) {
+        xr = ((const cd &)v).x;
+        xi = ((const cd &)v).y;
+      } else {
+        xr = (double)v;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u)
-      if (c0 + u < p) Y[(size_t)(c0 + u) * ld + row] = down<V>(acc[u]);
+    for (int t = 0; t < 4; ++t) {
+      if (t < JT) {
+        const int c = t * 16 + li;
+        double wr = 0.0, wi = 0.0;
+        if (kcol < m && c < p) {
+          const cd wv = W[(size_t)c * m + kcol];
+          wr = wv.x;
+          wi = wv.y;
+        }
+        if constexpr (ndv == 1) {
+          acc[t][0] = mfma(wr, xr, acc[t][0]);
+        } else {
+          // (W^T X^T): re = wr xr - wi xi, im = wr xi + wi xr
+          acc[t][0] = mfma(wr, xr, acc[t][0]);
+          acc[t][0] = mfma(-wi, xi, acc[t][0]);
+          acc[t][1] = mfma(wr, xi, acc[t][1]);
+          acc[t][1] = mfma(wi, xr, acc[t][1]);
+        }
+      }
+    }
   }
+  if (row >= n) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t < JT) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = t * 16 + lk + 4 * v;
+        if (c < p) {
+          if constexpr (ndv == 2) {
+            cd o;
+            o.x = acc[t][0][v];
+            o.y = acc[t][1][v];
+            ((cd *)Y)[(size_t)c * ld + row] = o;
+          } else {
+            Y[(size_t)c * ld + row] = (V)acc[t][0][v];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Y[:, c] = A X[:, c] for the 8 columns c = 8 blockIdx.y + (0..7) (< m):
+// the matrix is read once per 8 columns.
+template <class V, class M>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V *Y, int ld,
+                                                       int m) {
+  using T = typename Ar<V>::T;
+  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (row >= A.n) return;
+  const int c0 = blockIdx.y * 8;
+  const int nc = min(8, m - c0);
+  T acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = zero<T>();
+  const int slice = row >> 6, lane = row & 63;
+  const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
+  for (int e = beg + lane; e < end; e += RBICG_WAVE) {
+    const int c = A.col[e];
+    const auto a = up(A.val[e]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < nc) acc[j] += a * up(X[(size_t)(c0 + j) * ld + c]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < nc) Y[(size_t)(c0 + j) * ld + row] = down<V>(acc[j]);
 }
 
 // =============================================================== launchers
@@ -586,14 +775,58 @@ namespace {
 inline unsigned nblk(size_t n) { return (unsigned)((n + RBICG_BLOCK - 1) / RBICG_BLOCK); }
 }
 
+int iter_grid(int n) {
+  const int a = (n + IB - 1) / IB;
+  const int b = (n + IB * RMAX - 1) / (IB * RMAX);
+  return std::max(1, std::max(std::min(a, 256), b));
+}
+
 template <class V, class M>
-void launch_iter_spmv(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, const V *r,
-                      const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt,
-                      const V *C, const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ,
-                      V *capZt, double *partial, Scalars *S) {
-  hipLaunchKernelGGL((k_iter_spmv<V, M>), dim3(nblk(A.n)), dim3(RBICG_BLOCK), 0, st, A, AH, r,
-                     p, rt, pt, pn, ptn, z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, partial,
-                     S);
+void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, const V *r,
+                const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt, const V *C,
+                const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
+                const double *P3, double *P1, Scalars *S, double *rec, int it, int first) {
+  hipLaunchKernelGGL((k_it1<V, M>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn, z,
+                     zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first);
+}
+template <class V>
+void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
+                const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
+                double *P2, Scalars *S) {
+  hipLaunchKernelGGL((k_it2<V>), dim3(nb), dim3(IB), 0, st, n, z, zt, C, Ct, k, ld, ptn, q, qt,
+                     P1, P2, S);
+}
+template <class V>
+void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
+                const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
+                Scalars *S, double *rec, int it) {
+  hipLaunchKernelGGL((k_it3<V>), dim3(nb), dim3(IB), 0, st, n, x, xt, r, rt, pn, ptn, q, qt, k,
+                     P2, P3, S, rec, it);
+}
+template <class V>
+void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
+                  int first) {
+  hipLaunchKernelGGL((k_itfin<V>), dim3(1), dim3(IB), 0, st, P3, nb, S, rec, it, first);
+}
+template <class V>
+void launch_init_p3(hipStream_t st, int nb, int n, const V *r, const V *rt, double *P3) {
+  hipLaunchKernelGGL((k_init_p3<V>), dim3(nb), dim3(IB), 0, st, n, r, rt, P3);
+}
+template <class V>
+void launch_dots(hipStream_t st, int nb, int n, const V *a0, const V *b0, const V *a1,
+                 const V *b1, const V *a2, const V *b2, double *P, double *out) {
+  hipLaunchKernelGGL((k_dots<V>), dim3(nb), dim3(IB), 0, st, n, a0, b0, a1, b1, a2, b2, P);
+  hipLaunchKernelGGL(k_fin_red, dim3(1), dim3(IB), 0, st, P, nb, sizeof(V) == 16 ? 6 : 3, out);
+}
+template <class V>
+void launch_restrict(hipStream_t st, int nb, int n, const V *u, const V *B, const V *u2,
+                     const V *B2, int k, int ld, double *P, double *out) {
+  hipLaunchKernelGGL((k_restrict<V>), dim3(nb), dim3(IB), 0, st, n, u, B, u2, B2, k, ld, P);
+  const int nv = 2 * k * (sizeof(V) == 16 ? 2 : 1);
+  hipLaunchKernelGGL(k_fin_red, dim3(1), dim3(IB), 0, st, P, nb, nv, out);
+}
+void launch_fin_red(hipStream_t st, const double *P, int nb, int nv, double *out) {
+  hipLaunchKernelGGL(k_fin_red, dim3(1), dim3(IB), 0, st, P, nb, nv, out);
 }
 template <class V, class M>
 void launch_residual(hipStream_t st, const Sell<M> &A, const V *b, const V *x, V *out) {
@@ -603,40 +836,15 @@ void launch_residual(hipStream_t st, const Sell<M> &A, const V *b, const V *x, V
 template <class V, class M>
 void launch_spmm(hipStream_t st, const Sell<M> &A, const V *X, V *Y, int ld, int m) {
   if (m <= 0) return;
-  hipLaunchKernelGGL((k_spmm<V, M>), dim3(nblk(A.n), m), dim3(RBICG_BLOCK), 0, st, A, X, Y, ld);
-}
-template <class V>
-void launch_iter_expand(hipStream_t st, int n, const V *z, const V *zt, const V *C,
-                        const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, double *partial,
-                        Scalars *S) {
-  hipLaunchKernelGGL((k_iter_expand<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, z, zt, C,
-                     Ct, k, ld, ptn, q, qt, partial, S);
-}
-template <class V>
-void launch_iter_update(hipStream_t st, int n, V *x, V *xt, V *r, V *rt, const V *pn,
-                        const V *ptn, const V *q, const V *qt, double *partial, Scalars *S,
-                        double *log) {
-  hipLaunchKernelGGL((k_iter_update<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, x, xt, r,
-                     rt, pn, ptn, q, qt, partial, S, log);
-}
-template <class V>
-void launch_restrict(hipStream_t st, int n, const V *u, const V *B, const V *u2, const V *B2,
-                     int k, int ld, double *partial, Scalars *S) {
-  hipLaunchKernelGGL((k_restrict<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, u, B, u2, B2,
-                     k, ld, partial, S);
+  hipLaunchKernelGGL((k_spmm8<V, M>), dim3(nblk(A.n), (m + 7) / 8), dim3(RBICG_BLOCK), 0, st, A,
+                     X, Y, ld, m);
 }
 template <class V>
 void launch_expand2(hipStream_t st, int n, V *x, const V *U, double sx, V *r, const V *C,
                     double sr, V *xt, const V *Ut, double sxt, V *rt, const V *Ct, double srt,
-                    int k, int ld, int mode, const Scalars *S) {
+                    int k, int ld, const double *coef) {
   hipLaunchKernelGGL((k_expand2<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, x, U, sx, r,
-                     C, sr, xt, Ut, sxt, rt, Ct, srt, k, ld, mode, S);
-}
-template <class V>
-void launch_dots(hipStream_t st, int n, const V *a0, const V *b0, const V *a1, const V *b1,
-                 const V *a2, const V *b2, double *partial, Scalars *S) {
-  hipLaunchKernelGGL((k_dots<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, a0, b0, a1, b1,
-                     a2, b2, partial, S);
+                     C, sr, xt, Ut, sxt, rt, Ct, srt, k, ld, coef);
 }
 template <class V>
 void launch_fill_zero(hipStream_t st, V *p, size_t n) {
@@ -647,12 +855,28 @@ template <class V>
 void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed) {
   hipLaunchKernelGGL((k_reseed<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, n, seed);
 }
+int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
+
+int gram_group(int mx, int complex_vals) {
+  const int TX = (mx + 15) / 16;
+  const int pc = (complex_vals ? GRAM_SR_C : GRAM_SR_R) + 2;
+  const int nd = complex_vals ? 2 : 1;
+  const int mxp = TX * 16;
+  const int lds_cols = (int)(GRAM_LDS_BYTES / ((size_t)pc * nd * sizeof(double)));
+  int g = std::min(96, (4 * GRAM_MAXT / TX) * 16);
+  g = std::min(g, (lds_cols - mxp) / 16 * 16);
+  return std::max(16, g);
+}
+
 template <class V>
 void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
                  double *partial, double *G, int nchunks) {
+  constexpr int SR = sizeof(V) == 16 ? GRAM_SR_C : GRAM_SR_R;
+  constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
   const int rpc = (int)(((size_t)n + nchunks - 1) / nchunks);
-  const int tiles = ((mx + 15) / 16) * ((my + 15) / 16);
-  hipLaunchKernelGGL((k_gram<V>), dim3(nchunks, tiles), dim3(RBICG_BLOCK), 0, st, n, X, mx, Y,
+  const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
+  const size_t lds = (size_t)(mxp + myp) * (SR + 2) * ndv * sizeof(double);
+  hipLaunchKernelGGL((k_gram_mfma<V, SR>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X, mx, Y,
                      my, rpc, partial);
   const int count = 2 * mx * my;
   hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count)), dim3(RBICG_BLOCK), 0, st, partial,
@@ -662,33 +886,36 @@ template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
                    int ld) {
   if (p <= 0) return;
-  hipLaunchKernelGGL((k_tsgemm<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, X, m, W, p, Y,
-                     ld);
+  const unsigned nb = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL((k_tsgemm_mfma<V>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
 }
 
 #define INST_VM(V, M)                                                                        \
-  template void launch_iter_spmv<V, M>(hipStream_t, const Sell<M> &, const Sell<M> &,        \
-                                       const V *, const V *, const V *, const V *, V *, V *, \
-                                       V *, V *, const V *, const V *, int, int, V *, V *,   \
-                                       V *, V *, double *, Scalars *);                       \
+  template void launch_it1<V, M>(hipStream_t, int, const Sell<M> &, const Sell<M> &,         \
+                                 const V *, const V *, const V *, const V *, V *, V *, V *,  \
+                                 V *, const V *, const V *, int, int, V *, V *, V *, V *,    \
+                                 const double *, double *, Scalars *, double *, int, int);   \
   template void launch_residual<V, M>(hipStream_t, const Sell<M> &, const V *, const V *,    \
                                       V *);                                                  \
   template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);
 
 #define INST_V(V)                                                                            \
-  template void launch_iter_expand<V>(hipStream_t, int, const V *, const V *, const V *,     \
-                                      const V *, int, int, const V *, V *, V *, double *,    \
-                                      Scalars *);                                            \
-  template void launch_iter_update<V>(hipStream_t, int, V *, V *, V *, V *, const V *,       \
-                                      const V *, const V *, const V *, double *, Scalars *,  \
-                                      double *);                                             \
-  template void launch_restrict<V>(hipStream_t, int, const V *, const V *, const V *,        \
-                                   const V *, int, int, double *, Scalars *);                \
+  template void launch_it2<V>(hipStream_t, int, int, const V *, const V *, const V *,        \
+                              const V *, int, int, const V *, V *, V *, const double *,      \
+                              double *, Scalars *);                                          \
+  template void launch_it3<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
+                              const V *, const V *, const V *, int, const double *, double *, \
+                              Scalars *, double *, int);                                     \
+  template void launch_itfin<V>(hipStream_t, int, const double *, Scalars *, double *, int,  \
+                                int);                                                        \
+  template void launch_init_p3<V>(hipStream_t, int, int, const V *, const V *, double *);    \
+  template void launch_dots<V>(hipStream_t, int, int, const V *, const V *, const V *,       \
+                               const V *, const V *, const V *, double *, double *);         \
+  template void launch_restrict<V>(hipStream_t, int, int, const V *, const V *, const V *,   \
+                                   const V *, int, int, double *, double *);                 \
   template void launch_expand2<V>(hipStream_t, int, V *, const V *, double, V *, const V *,  \
                                   double, V *, const V *, double, V *, const V *, double,    \
-                                  int, int, int, const Scalars *);                           \
-  template void launch_dots<V>(hipStream_t, int, const V *, const V *, const V *, const V *, \
-                               const V *, const V *, double *, Scalars *);                   \
+                                  int, int, const double *);                                 \
   template void launch_fill_zero<V>(hipStream_t, V *, size_t);                               \
   template void launch_reseed<V>(hipStream_t, V *, size_t, unsigned long long);              \
   template void launch_gram<V>(hipStream_t, int, const ColList &, int, const ColList &, int, \

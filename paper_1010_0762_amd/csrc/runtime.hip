@@ -9,6 +9,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <future>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -209,6 +212,13 @@ int upload_sell(const HostCsr &A, int vkind, DevSell &D) {
 
 }  // namespace
 
+// A device-resident matrix: A and its explicit conjugate transpose, repacked.
+struct rbicg_mat_s {
+  int n = 0;
+  bool complex_vals = false;
+  DevSell A, AH;
+};
+
 // ====================================================================== handle
 struct rbicg_s {
   rbicg_opts opt{};
@@ -219,7 +229,13 @@ struct rbicg_s {
   bool mat_complex = false;
   size_t vb = 8;
   int kcap = 0, scap = 0;
-  DevSell A, AH;
+  rbicg_mat_s *mat = nullptr;
+  bool own_mat = false;
+  // optional per-kernel timing of the iteration kernels (opts.profile)
+  std::vector<hipEvent_t> pev;
+  hipEvent_t sev[2] = {nullptr, nullptr};
+  double prof_ms[3] = {0, 0, 0};
+  long prof_n[3] = {0, 0, 0};
   // iteration vectors (x, x~ are the caller's)
   void *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr}, *pt[2] = {nullptr, nullptr};
   void *z = nullptr, *zt = nullptr, *q = nullptr, *qt = nullptr, *t1 = nullptr, *t2 = nullptr;
@@ -237,7 +253,9 @@ struct rbicg_s {
   Scalars *S = nullptr;
   double *log = nullptr;
   int logcap = 0;
-  double *partial = nullptr;
+  double *partial = nullptr;  // host-requested reductions
+  double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;  // iteration partials
+  int nb = 1;                 // blocks of the iteration kernels
   double *gpart = nullptr;
   size_t gpart_bytes = 0;
   double *Gd = nullptr;
@@ -282,8 +300,8 @@ int push_scalars(rbicg_s *h) {
 
 // bytes per algorithmic iteration (matrix streams + 29 vector streams + C, C~ twice)
 double alg_bytes_iter(const rbicg_s *h, int k) {
-  const double ba = (double)h->A.vbytes;
-  const double nnz = (double)h->A.nnz;
+  const double ba = (double)h->mat->A.vbytes;
+  const double nnz = (double)h->mat->A.nnz;
   const double n = h->n;
   return 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (29.0 + 4.0 * k) * n * (double)h->vb;
 }
@@ -293,113 +311,158 @@ template <class V> struct VK;
 template <> struct VK<double> { static constexpr int kind = 0; };
 template <> struct VK<cd> { static constexpr int kind = 1; };
 
-// Gram G = X^H Y (mx x my, complex, row-major by (i, j)) into h->hG.
+// Gram G = X^H Y (mx x my, complex): enqueue the kernels and the download
+// into h->hG (no synchronization).  Y is processed in column groups so that
+// every launch fits the kernel's tile and LDS budget (mx <= 128); the download
+// keeps the group layout, gram_parse restores row-major (i, j) order.
 template <class V>
-int gram(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y) {
+int gram_enqueue(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y) {
   const int mx = (int)X.size(), my = (int)Y.size();
-  if (mx > RBICG_MAXCOLS || my > RBICG_MAXCOLS) return rbicg_fail(RBICG_EINVAL, "gram too wide");
-  ColList xl{}, yl{};
+  if (mx > 128 || mx < 1 || my < 1) return rbicg_fail(RBICG_EINVAL, "gram shape %d x %d unsupported", mx, my);
+  const int gy = gram_group(mx, sizeof(V) == 16 ? 1 : 0);
+  const int nchunks = gram_chunks(h->n);
+  ColList xl{};
   for (int i = 0; i < mx; ++i) xl.p[i] = X[i];
-  for (int i = 0; i < my; ++i) yl.p[i] = Y[i];
-  int nchunks = std::max(1, std::min(64, (h->n + 4095) / 4096));
-  const size_t need = (size_t)nchunks * mx * my * 2 * sizeof(double);
-  if (need > h->gpart_bytes) return rbicg_fail(RBICG_EINVAL, "gram workspace too small");
-  launch_gram<V>(h->st, h->n, xl, mx, yl, my, h->gpart, h->Gd, nchunks);
-  HIPCHECK(hipGetLastError());
+  for (int j0 = 0; j0 < my; j0 += gy) {
+    const int g = std::min(gy, my - j0);
+    const size_t need = (size_t)nchunks * mx * g * 2 * sizeof(double);
+    if (need > h->gpart_bytes) return rbicg_fail(RBICG_EINVAL, "gram workspace too small");
+    ColList yl{};
+    for (int j = 0; j < g; ++j) yl.p[j] = Y[j0 + j];
+    launch_gram<V>(h->st, h->n, xl, mx, yl, g, h->gpart, h->Gd + (size_t)2 * mx * j0, nchunks);
+    HIPCHECK(hipGetLastError());
+  }
   HIPCHECK(hipMemcpyAsync(h->hG, h->Gd, (size_t)mx * my * 2 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-  return sync(h);
-}
-inline cplx G_at(const rbicg_s *h, int my, int i, int j) {
-  const double *g = h->hG + ((size_t)i * my + j) * 2;
-  return cplx(g[0], g[1]);
+  return 0;
 }
 
-// Y (ld columns) = X W with W given on the host (m x p, column-major, complex).
+// Row-major (i, j) complex Gram from the downloaded group layout (host only).
+std::vector<cplx> gram_parse(const double *hG, int mx, int my, int gy) {
+  std::vector<cplx> G((size_t)mx * my);
+  for (int j0 = 0; j0 < my; j0 += gy) {
+    const int g = std::min(gy, my - j0);
+    const double *blk = hG + (size_t)2 * mx * j0;
+    for (int i = 0; i < mx; ++i)
+      for (int j = 0; j < g; ++j)
+        G[(size_t)i * my + j0 + j] = cplx(blk[2 * ((size_t)i * g + j)], blk[2 * ((size_t)i * g + j) + 1]);
+  }
+  return G;
+}
+
+
+// Stage W (m x p, column-major, complex) into coefficient slot `slot` and
+// enqueue Y = X W.  A slot is reused only after the stream has been
+// synchronized at least once since its last use (every cycle update and every
+// biorthogonalization synchronize to read a Gram).
+#define RBICG_WSLOT ((size_t)RBICG_MAXCOLS * KMAXD)
 template <class V>
 int tsgemm(rbicg_s *h, const std::vector<const void *> &X, const std::vector<cplx> &W, int p,
-           void *Y) {
+           void *Y, int slot) {
   const int m = (int)X.size();
-  if (m > RBICG_MAXCOLS) return rbicg_fail(RBICG_EINVAL, "tsgemm too wide");
+  if (m > RBICG_MAXCOLS || p > KMAXD) return rbicg_fail(RBICG_EINVAL, "tsgemm too wide");
   if (p == 0 || m == 0) return 0;
-  // the staging buffer may still be read by a previous GEMM on the stream
-  TRY(sync(h));
-  for (int t = 0; t < m * p; ++t) h->hW[t] = cd{W[t].real(), W[t].imag()};
-  HIPCHECK(hipMemcpyAsync(h->Wd, h->hW, (size_t)m * p * sizeof(cd), hipMemcpyHostToDevice, h->st));
+  cd *hw = h->hW + (size_t)slot * RBICG_WSLOT;
+  cd *dw = h->Wd + (size_t)slot * RBICG_WSLOT;
+  for (int t = 0; t < m * p; ++t) hw[t] = cd{W[t].real(), W[t].imag()};
+  HIPCHECK(hipMemcpyAsync(dw, hw, (size_t)m * p * sizeof(cd), hipMemcpyHostToDevice, h->st));
   ColList xl{};
   for (int i = 0; i < m; ++i) xl.p[i] = X[i];
-  launch_tsgemm<V>(h->st, h->n, xl, m, h->Wd, p, (V *)Y, h->ld);
+  launch_tsgemm<V>(h->st, h->n, xl, m, dw, p, (V *)Y, h->ld);
   HIPCHECK(hipGetLastError());
   return 0;
 }
 
-template <class V, class M> struct MatOf;
+// ------------------------------------------------- recycle-space updates
+// The update at the end of a cycle (Sec. 4) runs as a job in stages, so that
+// its host work (the small eigenproblem and SVD) overlaps the iterations of
+// the next cycle on the GPU:
+//   begin   enqueue the download of the cycle's scalars and the Gram
+//           X1^H [Y1 | Y2] of the harmonic Ritz pencil, record an event;
+//   host1   (worker thread) build T or the pencil (P, Q) and pick the
+//           eigenvectors of the k eigenvalues closest to the origin;
+//   stage2  enqueue U_j = Phi W, U~_j = Phi~ W~ (MFMA tall-skinny products),
+//           C = A U_j, C~ = A^H U~_j, their Grams, record an event;
+//   host3   (worker thread) biorthogonalization (Sec. 4.3) from the Grams;
+//   stage4  enqueue the rotations into the cycle buffers and install them.
+// Jobs run one after another.  The cycle's captured vectors live in one of two
+// ring sets; the iterations of cycle c+2 (which overwrite that set) are
+// enqueued only after the job of cycle c has enqueued its last ring read.
+struct CycleJob {
+  int cycle = 0, e = 0, set = 0, run_start = 0;
+  int stage = 0;          // 0 pending, 1 begun, 2 host1, 3 stage2 done, 4 host3, 5 finished
+  bool tpath = false;     // first cycle of the first system: eigenvectors of T
+  double rn0 = 0;
+  cplx rho0;
+  int kp = 0, mm = 0, mz = 0, gy = 0;
+  std::vector<const void *> XU, XUt;
+  hipEvent_t ev = nullptr;
+  std::future<int> fut;
+  int m = 0, p = 0;
+  std::vector<cplx> Wc, Wtc, TU, TUt;
+  int g2y = 0;
+  std::string err;
+};
 
-// Apply the biorthogonalization of Sec. 4.3 to U_j = Ua, U~_j = Uta (m columns):
-// C = A U, C~ = A^H U~, Grams, host SVD, and write the biorthogonal pair
-// (p columns) to (Uo, Uto, Co, Cto).  Returns p (>= 0) or an error.
-template <class V, class M>
-int biorth(rbicg_s *h, int m, void *Uo, void *Uto, void *Co, void *Cto) {
-  if (m == 0) return 0;
-  Sell<M> A = h->A.view<M>(), AH = h->AH.view<M>();
-  launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
-  launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
-  HIPCHECK(hipGetLastError());
-  std::vector<const void *> X;
-  for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Ca, j, h));
-  for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Cta, j, h));
-  TRY(gram<V>(h, X, X));
-  const int w = 2 * m;
-  std::vector<double> Gcc(2 * m * m), Gtt(2 * m * m), Gtc(2 * m * m);
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      // column-major (i, j) for the host routines
-      cplx a = G_at(h, w, i, j), b = G_at(h, w, m + i, m + j), c = G_at(h, w, m + i, j);
-      Gcc[2 * (i + j * m)] = a.real(); Gcc[2 * (i + j * m) + 1] = a.imag();
-      Gtt[2 * (i + j * m)] = b.real(); Gtt[2 * (i + j * m) + 1] = b.imag();
-      Gtc[2 * (i + j * m)] = c.real(); Gtc[2 * (i + j * m) + 1] = c.imag();
-    }
-  std::vector<double> TU(2 * m * m), TUt(2 * m * m);
-  const int p = rbicg_host_biorth(m, Gcc.data(), Gtt.data(), Gtc.data(), h->opt.svd_tol,
-                                  TU.data(), TUt.data());
-  if (p < 0) return rbicg_fail(RBICG_EINVAL, "biorthogonalization failed: %s", rbicg_last_error());
-  if (p == 0) return 0;
-  std::vector<cplx> W(m * p), Wt(m * p);
-  for (int t = 0; t < m * p; ++t) {
-    W[t] = cplx(TU[2 * t], TU[2 * t + 1]);
-    Wt[t] = cplx(TUt[2 * t], TUt[2 * t + 1]);
-  }
-  std::vector<const void *> XU, XC, XUt, XCt;
-  for (int j = 0; j < m; ++j) {
-    XU.push_back(col_ptr(h->Ua, j, h));
-    XC.push_back(col_ptr(h->Ca, j, h));
-    XUt.push_back(col_ptr(h->Uta, j, h));
-    XCt.push_back(col_ptr(h->Cta, j, h));
-  }
-  TRY(tsgemm<V>(h, XU, W, p, Uo));
-  TRY(tsgemm<V>(h, XC, W, p, Co));
-  TRY(tsgemm<V>(h, XUt, Wt, p, Uto));
-  TRY(tsgemm<V>(h, XCt, Wt, p, Cto));
-  TRY(sync(h));
-  return p;
-}
-
-// One log entry of iteration i (1-based, global index within the solve).
 struct LogEntry {
   cplx alpha, beta_prev, rho;
   double rn, rtn;
 };
 
-// End of a cycle (Sec. 4): build U_j, U~_j from the ring and the logged
-// scalars, then biorthogonalize into the cycle buffers.
-template <class V, class M>
-int cycle_update(rbicg_s *h, int e, int run_start, double rn0, cplx rho0) {
+inline char *ring_col(void *base, int set, int slots, int c, const rbicg_s *h) {
+  return (char *)base + ((size_t)set * slots + c) * h->ld * h->vb;
+}
+
+template <class V>
+int job_begin(rbicg_s *h, CycleJob &J) {
   const int s = h->opt.s;
-  const bool real_problem = (VK<V>::kind == 0);
-  // pull log entries e-s .. e (entry run_start is the run's initial state)
-  const int lo = e - s;
+  const int lo = J.e - s;
   HIPCHECK(hipMemcpyAsync(h->hlog, h->log + (size_t)lo * LOG_STRIDE,
                           (size_t)(s + 1) * LOG_STRIDE * sizeof(double), hipMemcpyDeviceToHost, h->st));
-  TRY(sync(h));
+  J.XU.clear();
+  J.XUt.clear();
+  J.tpath = !h->have_cyc && h->ksys == 0;
+  if (J.tpath) {
+    for (int c = 0; c < s; ++c) {
+      J.XU.push_back(ring_col(h->R, J.set, s, c, h));
+      J.XUt.push_back(ring_col(h->Rt, J.set, s, c, h));
+    }
+  } else {
+    void *Up = h->have_cyc ? h->Uc[h->cur] : h->U;
+    void *Utp = h->have_cyc ? h->Utc[h->cur] : h->Ut;
+    void *Cp = h->have_cyc ? h->Cc[h->cur] : h->C;
+    void *Ctp = h->have_cyc ? h->Ctc[h->cur] : h->Ct;
+    const int kp = h->have_cyc ? h->kcyc : h->ksys;
+    J.kp = kp;
+    J.mm = kp + s;
+    J.mz = kp + s + 1;
+    std::vector<const void *> X1, Yall;
+    for (int j = 0; j < kp; ++j) {
+      X1.push_back(col_ptr(Ctp, j, h));
+      Yall.push_back(col_ptr(Cp, j, h));
+      J.XU.push_back(col_ptr(Up, j, h));
+      J.XUt.push_back(col_ptr(Utp, j, h));
+    }
+    for (int c = 0; c <= s; ++c) {
+      X1.push_back(ring_col(h->Zt, J.set, s + 1, c, h));
+      Yall.push_back(ring_col(h->Z, J.set, s + 1, c, h));
+    }
+    for (int j = 0; j < kp; ++j) Yall.push_back(col_ptr(Up, j, h));
+    for (int c = 0; c < s; ++c) {
+      Yall.push_back(ring_col(h->R, J.set, s, c, h));
+      J.XU.push_back(ring_col(h->R, J.set, s, c, h));
+      J.XUt.push_back(ring_col(h->Rt, J.set, s, c, h));
+    }
+    J.gy = gram_group((int)X1.size(), sizeof(V) == 16 ? 1 : 0);
+    TRY(gram_enqueue<V>(h, X1, Yall));
+  }
+  HIPCHECK(hipEventRecord(J.ev, h->st));
+  J.stage = 1;
+  return 0;
+}
+
+// Host part 1 (no HIP calls): coefficient matrices of U_j and U~_j.
+int job_host1(const rbicg_s *h, CycleJob &J, bool real_problem) {
+  const int s = h->opt.s, k = h->opt.k;
   std::vector<LogEntry> L(s + 1);
   for (int t = 0; t <= s; ++t) {
     const double *q = h->hlog + (size_t)t * LOG_STRIDE;
@@ -409,11 +472,13 @@ int cycle_update(rbicg_s *h, int e, int run_start, double rn0, cplx rho0) {
     L[t].rn = q[6];
     L[t].rtn = q[7];
   }
-  if (lo == run_start) {
-    L[0].rn = rn0;
-    L[0].rho = rho0;
+  if (J.e - s == J.run_start) {
+    L[0].rn = J.rn0;
+    L[0].rho = J.rho0;
   }
-  // cycle iteration c (0..s-1) is i = lo + 1 + c; ||r_{i-1}|| = L[c].rn, rho_{i-1} = L[c].rho
+  // cycle iteration c (0..s-1) is i = e - s + 1 + c: ||r_{i-1}|| = L[c].rn,
+  // rho_{i-1} = L[c].rho, alpha_i = L[c+1].alpha, beta_{i-1} = L[c+1].beta_prev;
+  // v_i = r_{i-1} a_i and v~_i = r~_{i-1} at_i (Sec. 4.1 scaling)
   std::vector<double> a(s);
   std::vector<cplx> at(s), alpha(s), beta(s);
   for (int c = 0; c < s; ++c) {
@@ -422,12 +487,8 @@ int cycle_update(rbicg_s *h, int e, int run_start, double rn0, cplx rho0) {
     alpha[c] = L[c + 1].alpha;
     beta[c] = L[c + 1].beta_prev;
   }
-  const int k = h->opt.k;
   int m = 0;
-  std::vector<cplx> Wc, Wtc;
-  std::vector<const void *> XU, XUt;
-  if (!h->have_cyc && h->ksys == 0) {
-    // first cycle of the first system: eigenvectors of T_s (Sec. 4.2)
+  if (J.tpath) {
     std::vector<double> T(2 * s * s, 0.0);
     auto setT = [&](int i, int j, cplx v) {
       T[2 * (i + j * s)] = v.real();
@@ -442,139 +503,235 @@ int cycle_update(rbicg_s *h, int e, int run_start, double rn0, cplx rho0) {
       setT(i - 1, i - 1, d);
       if (i <= s - 1) setT(i, i - 1, -(L[i].rn / L[i - 1].rn) / alpha[i - 1]);
     }
-    std::vector<double> lam(2 * s), W(2 * s * s), Wl(2 * s * s), Ws(2 * s * s), Wls(2 * s * s);
-    if (rbicg_host_eig(s, T.data(), nullptr, lam.data(), W.data(), Wl.data()) != 0)
-      return rbicg_fail(RBICG_EINVAL, "cycle eigenproblem failed: %s", rbicg_last_error());
-    m = rbicg_host_select(s, lam.data(), W.data(), Wl.data(), k, real_problem ? 1 : 0, Ws.data(), Wls.data());
-    if (m < 0) return m;
-    Wc.resize(s * m);
-    Wtc.resize(s * m);
+    std::vector<double> Ws(2 * s * s), Wls(2 * s * s);
+    m = rbicg_host_eig_select(s, T.data(), nullptr, k, real_problem ? 1 : 0, Ws.data(), Wls.data());
+    if (m < 0) {
+      J.err = std::string("cycle eigenproblem failed: ") + rbicg_last_error();
+      return -1;
+    }
+    J.Wc.assign((size_t)s * m, 0.0);
+    J.Wtc.assign((size_t)s * m, 0.0);
     for (int c = 0; c < m; ++c)
       for (int l = 0; l < s; ++l) {
-        Wc[l + c * s] = a[l] * cplx(Ws[2 * (l + c * s)], Ws[2 * (l + c * s) + 1]);
-        Wtc[l + c * s] = at[l] * cplx(Wls[2 * (l + c * s)], Wls[2 * (l + c * s) + 1]);
+        J.Wc[l + c * s] = a[l] * cplx(Ws[2 * (l + c * s)], Ws[2 * (l + c * s) + 1]);
+        J.Wtc[l + c * s] = at[l] * cplx(Wls[2 * (l + c * s)], Wls[2 * (l + c * s) + 1]);
       }
-    for (int c = 0; c < s; ++c) {
-      XU.push_back(col_ptr(h->R, c, h));
-      XUt.push_back(col_ptr(h->Rt, c, h));
-    }
   } else {
-    // Phi = [U_prev, V_j]; harmonic Ritz pencil of eq. finalGenEigValue
-    void *Up = h->have_cyc ? h->Uc[h->cur] : h->U;
-    void *Utp = h->have_cyc ? h->Utc[h->cur] : h->Ut;
-    void *Cp = h->have_cyc ? h->Cc[h->cur] : h->C;
-    void *Ctp = h->have_cyc ? h->Ctc[h->cur] : h->Ct;
-    const int kp = h->have_cyc ? h->kcyc : h->ksys;
-    const int mm = kp + s;       // columns of Phi
-    const int mz = kp + s + 1;   // columns of [C_prev, Z ring]
-    std::vector<const void *> X1, Y1, Y2;
-    for (int j = 0; j < kp; ++j) {
-      X1.push_back(col_ptr(Ctp, j, h));
-      Y1.push_back(col_ptr(Cp, j, h));
-      Y2.push_back(col_ptr(Up, j, h));
-      XU.push_back(col_ptr(Up, j, h));
-      XUt.push_back(col_ptr(Utp, j, h));
-    }
-    for (int c = 0; c <= s; ++c) {
-      X1.push_back(col_ptr(h->Zt, c, h));
-      Y1.push_back(col_ptr(h->Z, c, h));
-    }
-    for (int c = 0; c < s; ++c) {
-      Y2.push_back(col_ptr(h->R, c, h));
-      XU.push_back(col_ptr(h->R, c, h));
-      XUt.push_back(col_ptr(h->Rt, c, h));
-    }
-    // transforms: A Phi = [C_p, Z] B, A^H Phi~ = [C~_p, Z~] Bt, Phi = [U_p, R] D
-    std::vector<cplx> B((size_t)mz * mm, 0.0), Bt((size_t)mz * mm, 0.0), D((size_t)mm * mm, 0.0);
-    for (int j = 0; j < kp; ++j) {
-      B[j + (size_t)j * mz] = 1.0;
-      Bt[j + (size_t)j * mz] = 1.0;
-      D[j + (size_t)j * mm] = 1.0;
-    }
-    for (int c = 0; c < s; ++c) {
-      const int col = kp + c;
-      B[(kp + c + 1) + (size_t)col * mz] = a[c];
-      B[(kp + c) + (size_t)col * mz] = -beta[c] * a[c];
-      Bt[(kp + c + 1) + (size_t)col * mz] = at[c];
-      Bt[(kp + c) + (size_t)col * mz] = -std::conj(beta[c]) * at[c];
-      D[col + (size_t)col * mm] = a[c];
-    }
-    TRY(gram<V>(h, X1, Y1));
-    std::vector<cplx> G1((size_t)mz * mz);
-    for (int i = 0; i < mz; ++i)
-      for (int j = 0; j < mz; ++j) G1[i + (size_t)j * mz] = G_at(h, mz, i, j);
-    TRY(gram<V>(h, X1, Y2));
-    std::vector<cplx> G2((size_t)mz * mm);
-    for (int i = 0; i < mz; ++i)
-      for (int j = 0; j < mm; ++j) G2[i + (size_t)j * mz] = G_at(h, mm, i, j);
-    // P = Bt^H G1 B, Q = Bt^H G2 D
-    auto mulH = [&](const std::vector<cplx> &Lm, int lr, int lc, const std::vector<cplx> &Mm,
-                    int mc) {  // Lm^H (lr x lc)^H * Mm (lr x mc) -> lc x mc
-      std::vector<cplx> O((size_t)lc * mc, 0.0);
-      for (int j = 0; j < mc; ++j)
-        for (int i = 0; i < lc; ++i) {
-          cplx sacc = 0;
-          for (int l = 0; l < lr; ++l) sacc += std::conj(Lm[l + (size_t)i * lr]) * Mm[l + (size_t)j * lr];
-          O[i + (size_t)j * lc] = sacc;
-        }
-      return O;
+    const int kp = J.kp, mm = J.mm, mz = J.mz;
+    const std::vector<cplx> G = gram_parse(h->hG, mz, mz + mm, J.gy);
+    const int wy = mz + mm;
+    // A Phi = [C_p, Z] B, A^H Phi~ = [C~_p, Z~] Bt, Phi = [U_p, R] D with
+    // A v_i = (z_i - beta_{i-1} z_{i-1}) a_i and A^H v~_i likewise; then
+    // P = Bt^H G1 B, Q = Bt^H G2 D (eq. finalGenEigValue).  B, Bt, D are
+    // identity blocks plus (bi)diagonals, applied entrywise here.
+    auto G1 = [&](int i, int j) { return G[(size_t)i * wy + j]; };
+    auto G2 = [&](int i, int j) { return G[(size_t)i * wy + mz + j]; };
+    auto Bcol = [&](int col, int row) -> cplx {  // B(row, col)
+      if (col < kp) return row == col ? cplx(1.0) : cplx(0.0);
+      const int c = col - kp;
+      if (row == kp + c + 1) return a[c];
+      if (row == kp + c) return -beta[c] * a[c];
+      return 0.0;
     };
-    auto mul = [&](const std::vector<cplx> &Lm, int lr, int lc, const std::vector<cplx> &Mm,
-                   int mc) {  // (lr x lc) * (lc x mc)
-      std::vector<cplx> O((size_t)lr * mc, 0.0);
-      for (int j = 0; j < mc; ++j)
-        for (int l = 0; l < lc; ++l) {
-          const cplx f = Mm[l + (size_t)j * lc];
-          if (f == 0.0) continue;
-          for (int i = 0; i < lr; ++i) O[i + (size_t)j * lr] += Lm[i + (size_t)l * lr] * f;
-        }
-      return O;
+    auto Btcol = [&](int col, int row) -> cplx {
+      if (col < kp) return row == col ? cplx(1.0) : cplx(0.0);
+      const int c = col - kp;
+      if (row == kp + c + 1) return at[c];
+      if (row == kp + c) return -std::conj(beta[c]) * at[c];
+      return 0.0;
     };
-    std::vector<cplx> P = mulH(Bt, mz, mm, mul(G1, mz, mz, B, mm), mm);
-    std::vector<cplx> Q = mulH(Bt, mz, mm, mul(G2, mz, mm, D, mm), mm);
+    auto rows_of = [&](int col, int *r) {  // nonzero rows of column col of B / Bt
+      if (col < kp) { r[0] = col; return 1; }
+      r[0] = col;       // kp + c
+      r[1] = col + 1;   // kp + c + 1
+      return 2;
+    };
+    // X1 = G1 B (mz x mm), X2 = G2 D (mz x mm)
+    std::vector<cplx> X1((size_t)mz * mm), X2((size_t)mz * mm);
+    for (int j = 0; j < mm; ++j) {
+      int rr[2];
+      const int nr = rows_of(j, rr);
+      const cplx dj = j < kp ? cplx(1.0) : cplx(a[j - kp]);
+      for (int i = 0; i < mz; ++i) {
+        cplx acc = 0;
+        for (int t = 0; t < nr; ++t) acc += G1(i, rr[t]) * Bcol(j, rr[t]);
+        X1[i + (size_t)j * mz] = acc;
+        X2[i + (size_t)j * mz] = G2(i, j) * dj;
+      }
+    }
     std::vector<double> Pd(2 * (size_t)mm * mm), Qd(2 * (size_t)mm * mm);
-    for (size_t t = 0; t < (size_t)mm * mm; ++t) {
-      Pd[2 * t] = P[t].real(); Pd[2 * t + 1] = P[t].imag();
-      Qd[2 * t] = Q[t].real(); Qd[2 * t + 1] = Q[t].imag();
-    }
-    std::vector<double> lam(2 * mm), W(2 * (size_t)mm * mm), Wl(2 * (size_t)mm * mm),
-        Ws(2 * (size_t)mm * mm), Wls(2 * (size_t)mm * mm);
-    if (rbicg_host_eig(mm, Pd.data(), Qd.data(), lam.data(), W.data(), Wl.data()) != 0)
-      return rbicg_fail(RBICG_EINVAL, "harmonic Ritz problem failed: %s", rbicg_last_error());
-    m = rbicg_host_select(mm, lam.data(), W.data(), Wl.data(), k, real_problem ? 1 : 0, Ws.data(), Wls.data());
-    if (m < 0) return m;
-    std::vector<cplx> Wsel((size_t)mm * m), Wlsel((size_t)mm * m);
-    for (size_t t = 0; t < (size_t)mm * m; ++t) {
-      Wsel[t] = cplx(Ws[2 * t], Ws[2 * t + 1]);
-      Wlsel[t] = cplx(Wls[2 * t], Wls[2 * t + 1]);
+    for (int j = 0; j < mm; ++j)
+      for (int i = 0; i < mm; ++i) {
+        int rr[2];
+        const int nr = rows_of(i, rr);
+        cplx p = 0, q = 0;
+        for (int t = 0; t < nr; ++t) {
+          const cplx f = std::conj(Btcol(i, rr[t]));
+          p += f * X1[rr[t] + (size_t)j * mz];
+          q += f * X2[rr[t] + (size_t)j * mz];
+        }
+        Pd[2 * (i + (size_t)j * mm)] = p.real();
+        Pd[2 * (i + (size_t)j * mm) + 1] = p.imag();
+        Qd[2 * (i + (size_t)j * mm)] = q.real();
+        Qd[2 * (i + (size_t)j * mm) + 1] = q.imag();
+      }
+    std::vector<double> Ws(2 * (size_t)mm * mm), Wls(2 * (size_t)mm * mm);
+    m = rbicg_host_eig_select(mm, Pd.data(), Qd.data(), k, real_problem ? 1 : 0, Ws.data(), Wls.data());
+    if (m < 0) {
+      J.err = std::string("harmonic Ritz problem failed: ") + rbicg_last_error();
+      return -1;
     }
     // U_j = [U_p, R] (D W), U~_j = [U~_p, R~] (Dt W~), Dt = blockdiag(I, diag(at))
-    Wc = mul(D, mm, mm, Wsel, m);
-    std::vector<cplx> Dt((size_t)mm * mm, 0.0);
-    for (int j = 0; j < kp; ++j) Dt[j + (size_t)j * mm] = 1.0;
-    for (int c = 0; c < s; ++c) Dt[(kp + c) + (size_t)(kp + c) * mm] = at[c];
-    Wtc = mul(Dt, mm, mm, Wlsel, m);
+    J.Wc.assign((size_t)mm * m, 0.0);
+    J.Wtc.assign((size_t)mm * m, 0.0);
+    for (int c = 0; c < m; ++c)
+      for (int l = 0; l < mm; ++l) {
+        const cplx w = cplx(Ws[2 * (l + (size_t)c * mm)], Ws[2 * (l + (size_t)c * mm) + 1]);
+        const cplx wl = cplx(Wls[2 * (l + (size_t)c * mm)], Wls[2 * (l + (size_t)c * mm) + 1]);
+        J.Wc[l + (size_t)c * mm] = (l < kp ? cplx(1.0) : cplx(a[l - kp])) * w;
+        J.Wtc[l + (size_t)c * mm] = (l < kp ? cplx(1.0) : at[l - kp]) * wl;
+      }
   }
-  if (m == 0) return 0;
-  TRY(tsgemm<V>(h, XU, Wc, m, h->Ua));
-  TRY(tsgemm<V>(h, XUt, Wtc, m, h->Uta));
-  const int nxt = h->have_cyc ? 1 - h->cur : h->cur;
-  const int p = biorth<V, M>(h, m, h->Uc[nxt], h->Utc[nxt], h->Cc[nxt], h->Ctc[nxt]);
-  if (p < 0) return p;
-  if (p > 0) {
-    h->cur = nxt;
-    h->kcyc = p;
-    h->have_cyc = true;
+  J.m = m;
+  return 0;
+}
+
+// Enqueue U_j, U~_j into (Ua, Uta), C = A U_j, C~ = A^H U~_j and the Grams of
+// [C, C~] (biorthogonalization input); record the job's event.
+template <class V, class M>
+int job_stage2(rbicg_s *h, CycleJob &J) {
+  const int m = J.m;
+  if (m > 0) {
+    TRY(tsgemm<V>(h, J.XU, J.Wc, m, h->Ua, 4));
+    TRY(tsgemm<V>(h, J.XUt, J.Wtc, m, h->Uta, 5));
+    Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
+    launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
+    launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
+    HIPCHECK(hipGetLastError());
+    std::vector<const void *> X;
+    for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Ca, j, h));
+    for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Cta, j, h));
+    J.g2y = gram_group(2 * m, sizeof(V) == 16 ? 1 : 0);
+    TRY(gram_enqueue<V>(h, X, X));
+  }
+  HIPCHECK(hipEventRecord(J.ev, h->st));
+  J.stage = 3;
+  return 0;
+}
+
+// Host part 2 (no HIP calls): biorthogonalizing transforms from the Grams.
+int job_host3(const rbicg_s *h, CycleJob &J) {
+  const int m = J.m;
+  if (m == 0) {
+    J.p = 0;
+    return 0;
+  }
+  const int w = 2 * m;
+  const std::vector<cplx> G = gram_parse(h->hG, w, w, J.g2y);
+  std::vector<double> Gcc(2 * m * m), Gtt(2 * m * m), Gtc(2 * m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const cplx a = G[(size_t)i * w + j], b = G[(size_t)(m + i) * w + m + j], c = G[(size_t)(m + i) * w + j];
+      Gcc[2 * (i + j * m)] = a.real(); Gcc[2 * (i + j * m) + 1] = a.imag();
+      Gtt[2 * (i + j * m)] = b.real(); Gtt[2 * (i + j * m) + 1] = b.imag();
+      Gtc[2 * (i + j * m)] = c.real(); Gtc[2 * (i + j * m) + 1] = c.imag();
+    }
+  std::vector<double> TU(2 * m * m), TUt(2 * m * m);
+  const int p = rbicg_host_biorth(m, Gcc.data(), Gtt.data(), Gtc.data(), h->opt.svd_tol, TU.data(), TUt.data());
+  if (p < 0) {
+    J.err = std::string("biorthogonalization failed: ") + rbicg_last_error();
+    return -1;
+  }
+  J.p = p;
+  J.TU.resize((size_t)m * p);
+  J.TUt.resize((size_t)m * p);
+  for (size_t t = 0; t < (size_t)m * p; ++t) {
+    J.TU[t] = cplx(TU[2 * t], TU[2 * t + 1]);
+    J.TUt[t] = cplx(TUt[2 * t], TUt[2 * t + 1]);
   }
   return 0;
 }
 
+// Enqueue the rotations of (Ua, Ca, Uta, Cta) into the given outputs.
+template <class V>
+int apply_biorth(rbicg_s *h, int m, int p, const std::vector<cplx> &TU, const std::vector<cplx> &TUt,
+                 void *Uo, void *Uto, void *Co, void *Cto) {
+  if (p == 0) return 0;
+  std::vector<const void *> XU, XC, XUt, XCt;
+  for (int j = 0; j < m; ++j) {
+    XU.push_back(col_ptr(h->Ua, j, h));
+    XC.push_back(col_ptr(h->Ca, j, h));
+    XUt.push_back(col_ptr(h->Uta, j, h));
+    XCt.push_back(col_ptr(h->Cta, j, h));
+  }
+  TRY(tsgemm<V>(h, XU, TU, p, Uo, 0));
+  TRY(tsgemm<V>(h, XC, TU, p, Co, 1));
+  TRY(tsgemm<V>(h, XUt, TUt, p, Uto, 2));
+  TRY(tsgemm<V>(h, XCt, TUt, p, Cto, 3));
+  return 0;
+}
+
+template <class V>
+int job_stage4(rbicg_s *h, CycleJob &J) {
+  if (J.p > 0) {
+    const int nxt = h->have_cyc ? 1 - h->cur : h->cur;
+    TRY(apply_biorth<V>(h, J.m, J.p, J.TU, J.TUt, h->Uc[nxt], h->Utc[nxt], h->Cc[nxt], h->Ctc[nxt]));
+    h->cur = nxt;
+    h->kcyc = J.p;
+    h->have_cyc = true;
+  }
+  J.stage = 5;
+  return 0;
+}
+
+// Synchronous biorthogonalization of (Ua, Uta) with m columns into the
+// system's recycle space (rbicg_set_recycle, rbicg_update_recycle).
+template <class V, class M>
+int biorth_sync(rbicg_s *h, int m) {
+  CycleJob J;
+  J.m = m;
+  HIPCHECK(hipEventCreateWithFlags(&J.ev, hipEventDisableTiming));
+  int rc = 0;
+  if (m > 0) {
+    Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
+    launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
+    launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
+    std::vector<const void *> X;
+    for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Ca, j, h));
+    for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Cta, j, h));
+    J.g2y = gram_group(2 * m, sizeof(V) == 16 ? 1 : 0);
+    rc = gram_enqueue<V>(h, X, X);
+    if (rc >= 0) rc = sync(h);
+    if (rc >= 0 && job_host3(h, J) < 0) rc = rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
+    if (rc >= 0) rc = apply_biorth<V>(h, m, J.p, J.TU, J.TUt, h->U, h->Ut, h->C, h->Ct);
+    if (rc >= 0) rc = sync(h);
+  }
+  (void)hipEventDestroy(J.ev);
+  if (rc < 0) return rc;
+  return J.p;
+}
+
 // ------------------------------------------------------------------ solve
+template <class V> constexpr int ndv() { return sizeof(V) == 16 ? 2 : 1; }
+
+// dots (a_i, b_i) -> host values (complex)
+template <class V>
+int host_dots(rbicg_s *h, const V *a0, const V *b0, const V *a1, const V *b1, const V *a2,
+              const V *b2, cplx out[3]) {
+  launch_dots<V>(h->st, h->nb, h->n, a0, b0, a1, b1, a2, b2, h->partial, h->S->red);
+  HIPCHECK(hipGetLastError());
+  TRY(pull_scalars(h));
+  const int nd = ndv<V>();
+  for (int i = 0; i < 3; ++i)
+    out[i] = cplx(h->hS->red[i * nd], nd == 2 ? h->hS->red[i * nd + 1] : 0.0);
+  return 0;
+}
+
 template <class V, class M>
 int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbicg_stats *stp) {
   rbicg_stats st{};
-  const int n = h->n, ld = h->ld, s = h->opt.s;
-  Sell<M> A = h->A.view<M>(), AH = h->AH.view<M>();
+  const int n = h->n, ld = h->ld, s = h->opt.s, nb = h->nb;
+  Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
   hipEvent_t ev0, ev1;
   HIPCHECK(hipEventCreate(&ev0));
   HIPCHECK(hipEventCreate(&ev1));
@@ -584,49 +741,49 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   V *r = (V *)h->r, *rt = (V *)h->rt;
   const int ks = h->ksys;
   const V *U = (const V *)h->U, *Ut = (const V *)h->Ut, *C = (const V *)h->C, *Ct = (const V *)h->Ct;
-  // reference norms
-  launch_dots<V>(h->st, n, b, b, bt, bt, nullptr, nullptr, h->partial, h->S);
-  HIPCHECK(hipGetLastError());
-  TRY(pull_scalars(h));
-  double bn = std::sqrt(std::fabs(h->hS->red[0])), btn = std::sqrt(std::fabs(h->hS->red[2]));
+  cplx d[3];
+  TRY(host_dots<V>(h, b, b, bt, bt, nullptr, nullptr, d));
+  double bn = std::sqrt(std::fabs(d[0].real())), btn = std::sqrt(std::fabs(d[1].real()));
   int total = 0, restarts = 0, reseeds = 0, status = ST_MAXIT;
   double relres = NAN, relres_dual = NAN;
   bool first = true;
   std::vector<double> fulllog;
+  std::deque<std::unique_ptr<CycleJob>> jobs;
   while (true) {
     // eq. minusXR: r_{-1} = b - A x, projection with C, C~
     launch_residual<V, M>(h->st, A, b, x, r);
     launch_residual<V, M>(h->st, AH, bt, xt, rt);
     if (first && (bn == 0.0 || btn == 0.0)) {
-      launch_dots<V>(h->st, n, r, r, rt, rt, nullptr, nullptr, h->partial, h->S);
-      TRY(pull_scalars(h));
-      if (bn == 0.0) bn = std::sqrt(std::fabs(h->hS->red[0]));
-      if (btn == 0.0) btn = std::sqrt(std::fabs(h->hS->red[2]));
+      TRY(host_dots<V>(h, r, r, rt, rt, nullptr, nullptr, d));
+      if (bn == 0.0) bn = std::sqrt(std::fabs(d[0].real()));
+      if (btn == 0.0) btn = std::sqrt(std::fabs(d[1].real()));
       if (bn == 0.0) bn = 1.0;
       if (btn == 0.0) btn = 1.0;
     }
     if (ks > 0) {
-      launch_restrict<V>(h->st, n, r, Ct, rt, C, ks, ld, h->partial, h->S);
-      launch_expand2<V>(h->st, n, x, U, 1.0, r, C, -1.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, 0, h->S);
+      launch_restrict<V>(h->st, nb, n, r, Ct, rt, C, ks, ld, h->partial, h->S->gbuf);
+      launch_expand2<V>(h->st, n, x, U, 1.0, r, C, -1.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, h->S->gbuf);
     }
-    launch_dots<V>(h->st, n, rt, r, r, r, rt, rt, h->partial, h->S);
+    launch_init_p3<V>(h->st, nb, n, r, rt, h->P3);
+    launch_fin_red(h->st, h->P3, nb, 2 + ndv<V>(), h->S->red);
     HIPCHECK(hipGetLastError());
     TRY(pull_scalars(h));
-    cplx rho(h->hS->red[0], h->hS->red[1]);
-    double rn = std::sqrt(std::fabs(h->hS->red[2])), rtn = std::sqrt(std::fabs(h->hS->red[4]));
+    double rn = std::sqrt(std::fabs(h->hS->red[0])), rtn = std::sqrt(std::fabs(h->hS->red[1]));
+    cplx rho(h->hS->red[2], ndv<V>() == 2 ? h->hS->red[3] : 0.0);
     // Algorithm 2 step 3: re-seed x~ if (r_0, r~_0) vanishes
     while (std::abs(rho) <= 1e-14 * rn * rtn && rn > 0 && reseeds < 3) {
       launch_reseed<V>(h->st, xt, (size_t)n, (unsigned long long)(h->opt.seed + reseeds));
       launch_residual<V, M>(h->st, AH, bt, xt, rt);
       if (ks > 0) {
-        launch_restrict<V>(h->st, n, r, Ct, rt, C, ks, ld, h->partial, h->S);
-        launch_expand2<V>(h->st, n, nullptr, U, 0.0, nullptr, C, 0.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, 0, h->S);
+        launch_restrict<V>(h->st, nb, n, r, Ct, rt, C, ks, ld, h->partial, h->S->gbuf);
+        launch_expand2<V>(h->st, n, nullptr, U, 0.0, nullptr, C, 0.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, h->S->gbuf);
       }
-      launch_dots<V>(h->st, n, rt, r, r, r, rt, rt, h->partial, h->S);
+      launch_init_p3<V>(h->st, nb, n, r, rt, h->P3);
+      launch_fin_red(h->st, h->P3, nb, 2 + ndv<V>(), h->S->red);
       TRY(pull_scalars(h));
-      rho = cplx(h->hS->red[0], h->hS->red[1]);
-      rn = std::sqrt(std::fabs(h->hS->red[2]));
-      rtn = std::sqrt(std::fabs(h->hS->red[4]));
+      rn = std::sqrt(std::fabs(h->hS->red[0]));
+      rtn = std::sqrt(std::fabs(h->hS->red[1]));
+      rho = cplx(h->hS->red[2], ndv<V>() == 2 ? h->hS->red[3] : 0.0);
       ++reseeds;
     }
     first = false;
@@ -634,16 +791,12 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     // scalar block for the run
     Scalars *hs = h->hS;
     std::memset(hs, 0, sizeof(Scalars));
-    hs->rho = cd{rho.real(), rho.imag()};
     hs->tol = tol;
     hs->bn = bn;
     hs->btn = btn;
-    hs->rn = rn;
-    hs->rtn = rtn;
     hs->iter = total;
     hs->maxit = h->opt.maxit;
-    hs->log_base = 0;
-    bool conv0 = rn <= tol * bn && rtn <= tol * btn;
+    const bool conv0 = rn <= tol * bn && rtn <= tol * btn;
     hs->done = conv0 ? 1 : 0;
     hs->status = conv0 ? ST_CONVERGED : ST_RUNNING;
     if (total >= h->opt.maxit && !conv0) {
@@ -654,79 +807,231 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     launch_fill_zero<V>(h->st, (V *)h->p[0], (size_t)n);
     launch_fill_zero<V>(h->st, (V *)h->pt[0], (size_t)n);
     if (update) {
-      launch_fill_zero<V>(h->st, (V *)h->Z, (size_t)ld);
-      launch_fill_zero<V>(h->st, (V *)h->Zt, (size_t)ld);
+      launch_fill_zero<V>(h->st, (V *)ring_col(h->Z, 0, s + 1, 0, h), (size_t)ld);
+      launch_fill_zero<V>(h->st, (V *)ring_col(h->Zt, 0, s + 1, 0, h), (size_t)ld);
     }
     int pc = 0;
-    int launched = total;  // iterations enqueued
+    int launched = total;          // iterations enqueued
+    int known = total;             // iterations known to be complete
     int done = hs->done, dev_status = hs->status;
+    int completed = total;
     const int chunk_def = h->opt.chunk > 0 ? h->opt.chunk : 8;
-    while (!done) {
-      int in_run = launched - run_start;
-      int chunk = chunk_def;
-      if (update) chunk = std::min(chunk, s - (in_run % s));
-      chunk = std::min(chunk, h->opt.maxit - launched);
-      if (chunk <= 0) break;
-      for (int c = 0; c < chunk; ++c) {
-        const int pos = (launched - run_start) % s;
-        V *capR = nullptr, *capRt = nullptr, *capZ = nullptr, *capZt = nullptr;
-        if (update) {
-          capR = (V *)col_ptr(h->R, pos, h);
-          capRt = (V *)col_ptr(h->Rt, pos, h);
-          capZ = (V *)col_ptr(h->Z, pos + 1, h);
-          capZt = (V *)col_ptr(h->Zt, pos + 1, h);
+    struct Flight {
+      int upto, slot, chunk_start, chunk;
+      bool prof;
+    };
+    std::deque<Flight> flight;
+    int slot_next = 0;
+    const bool real_problem = (VK<V>::kind == 0);
+
+    // advance the job queue; blocking: wait for what the front job needs
+    auto advance = [&](bool blocking) -> int {
+      bool progress = true;
+      while (progress && !jobs.empty()) {
+        progress = false;
+        CycleJob &J = *jobs.front();
+        if (J.stage == 0) {
+          TRY(job_begin<V>(h, J));
+          progress = true;
+        } else if (J.stage == 1) {
+          const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
+          if (q == hipSuccess) {
+            J.fut = std::async(std::launch::async, [h, &J, real_problem]() { return job_host1(h, J, real_problem); });
+            J.stage = 2;
+            progress = true;
+          } else if (q != hipErrorNotReady) {
+            return rbicg_fail(RBICG_EHIP, "cycle event: %s", hipGetErrorString(q));
+          }
+        } else if (J.stage == 2) {
+          if (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready) {
+            if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
+            TRY((job_stage2<V, M>(h, J)));
+            progress = true;
+          }
+        } else if (J.stage == 3) {
+          const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
+          if (q == hipSuccess) {
+            J.fut = std::async(std::launch::async, [h, &J]() { return job_host3(h, J); });
+            J.stage = 4;
+            progress = true;
+          } else if (q != hipErrorNotReady) {
+            return rbicg_fail(RBICG_EHIP, "cycle event: %s", hipGetErrorString(q));
+          }
+        } else if (J.stage == 4) {
+          // install only once the cycle is known to have been completed
+          if (J.e <= known &&
+              (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready)) {
+            if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
+            TRY(job_stage4<V>(h, J));
+            st.cycles++;
+            (void)hipEventDestroy(J.ev);
+            jobs.pop_front();
+            progress = true;
+          }
         }
-        V *pn = (V *)h->p[1 - pc], *ptn = (V *)h->pt[1 - pc];
-        launch_iter_spmv<V, M>(h->st, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn, ptn,
-                               (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt,
-                               h->partial, h->S);
-        launch_iter_expand<V>(h->st, n, (const V *)h->z, (const V *)h->zt, C, Ct, ks, ld, ptn,
-                              (V *)h->q, (V *)h->qt, h->partial, h->S);
-        const V *qq = ks > 0 ? (const V *)h->q : (const V *)h->z;
-        const V *qqt = ks > 0 ? (const V *)h->qt : (const V *)h->zt;
-        launch_iter_update<V>(h->st, n, x, xt, r, rt, pn, ptn, qq, qqt, h->partial, h->S, h->log);
-        pc = 1 - pc;
-        ++launched;
+        if (blocking) break;
       }
-      HIPCHECK(hipGetLastError());
-      TRY(pull_scalars(h));
-      done = h->hS->done;
-      dev_status = h->hS->status;
-      const int it = h->hS->iter;
-      // no-op launches after convergence do not advance the count or the parity
-      if (it != launched) {
-        if ((launched - it) % 2) pc = 1 - pc;
-        launched = it;
+      return 0;
+    };
+
+    // read the scalars of the oldest chunk in flight
+    auto read_one = [&]() -> int {
+      if (flight.empty()) return 0;
+      const Flight f = flight.front();
+      flight.pop_front();
+      HIPCHECK(hipEventSynchronize(h->sev[f.slot]));
+      const Scalars &sc = h->hS[f.slot];
+      if (sc.done) {
+        done = 1;
+        dev_status = sc.status;
+        completed = sc.iter;
+      } else {
+        completed = f.upto;
       }
-      if (update && it > run_start && (it - run_start) % s == 0 &&
-          (dev_status == ST_RUNNING || dev_status == ST_CONVERGED || dev_status == ST_MAXIT)) {
-        TRY((cycle_update<V, M>(h, it, run_start, rn, rho)));
-        st.cycles++;
-        // z_{js} becomes slot 0 of the next cycle
-        HIPCHECK(hipMemcpyAsync(h->Z, col_ptr(h->Z, s, h), (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
-        HIPCHECK(hipMemcpyAsync(h->Zt, col_ptr(h->Zt, s, h), (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+      known = std::max(known, completed);
+      if (f.prof) {
+        const int eb = f.slot * 4 * f.chunk;
+        for (int c = 0; c < completed - f.chunk_start && c < f.chunk; ++c)
+          for (int kk = 0; kk < 3; ++kk) {
+            float ms = 0;
+            HIPCHECK(hipEventElapsedTime(&ms, h->pev[eb + 4 * c + kk], h->pev[eb + 4 * c + kk + 1]));
+            h->prof_ms[kk] += ms;
+            h->prof_n[kk] += 1;
+          }
+      }
+      return 0;
+    };
+
+    while (true) {
+      // keep up to two chunks in flight
+      while (!done && (int)flight.size() < 2 && launched < h->opt.maxit) {
+        const int in_run = launched - run_start;
+        const int cyc = in_run / s;
+        // the ring set of cycle cyc was last used by cycle cyc-2: its job must
+        // have enqueued all reads of that set first
+        if (update) {
+          auto must_wait = [&]() {
+            for (const auto &j : jobs)
+              if (j->cycle <= cyc - 2 && j->stage < 3) return true;
+            return false;
+          };
+          while (!done && must_wait()) {
+            const int before = jobs.front()->stage;
+            const size_t nj = jobs.size();
+            TRY(advance(true));
+            if (jobs.size() == nj && jobs.front()->stage == before) TRY(read_one());
+          }
+          if (done) break;
+          // first chunk of cycle cyc >= 1: the z of cycle cyc-1's last iteration
+          // seeds slot 0 of this cycle's set (whose previous reader, the job of
+          // cycle cyc-2, has enqueued its reads: checked just above)
+          if (cyc >= 1 && in_run % s == 0) {
+            HIPCHECK(hipMemcpyAsync(ring_col(h->Z, cyc % 2, s + 1, 0, h), ring_col(h->Z, (cyc - 1) % 2, s + 1, s, h),
+                                    (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+            HIPCHECK(hipMemcpyAsync(ring_col(h->Zt, cyc % 2, s + 1, 0, h), ring_col(h->Zt, (cyc - 1) % 2, s + 1, s, h),
+                                    (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+          }
+        }
+        int chunk = chunk_def;
+        if (update) chunk = std::min(chunk, s - (in_run % s));
+        chunk = std::min(chunk, h->opt.maxit - launched);
+        const int chunk_start = launched;
+        const bool prof = h->opt.profile && (int)h->pev.size() >= 8 * chunk;
+        const int eb = (slot_next % 2) * 4 * chunk;
+        for (int c = 0; c < chunk; ++c) {
+          const int it = launched + 1;
+          const int pos = (it - 1 - run_start) % s;
+          const int set = ((it - 1 - run_start) / s) % 2;
+          V *capR = nullptr, *capRt = nullptr, *capZ = nullptr, *capZt = nullptr;
+          if (update) {
+            capR = (V *)ring_col(h->R, set, s, pos, h);
+            capRt = (V *)ring_col(h->Rt, set, s, pos, h);
+            capZ = (V *)ring_col(h->Z, set, s + 1, pos + 1, h);
+            capZt = (V *)ring_col(h->Zt, set, s + 1, pos + 1, h);
+          }
+          V *pn = (V *)h->p[1 - pc], *ptn = (V *)h->pt[1 - pc];
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c], h->st));
+          launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
+                           ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
+                           h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0);
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 1], h->st));
+          launch_it2<V>(h->st, nb, n, (const V *)h->z, (const V *)h->zt, C, Ct, ks, ld, ptn,
+                        (V *)h->q, (V *)h->qt, h->P1, h->P2, h->S);
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 2], h->st));
+          const V *qq = ks > 0 ? (const V *)h->q : (const V *)h->z;
+          const V *qqt = ks > 0 ? (const V *)h->qt : (const V *)h->zt;
+          launch_it3<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, qq, qqt, ks, h->P2, h->P3, h->S, h->log, it);
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 3], h->st));
+          pc = 1 - pc;
+          ++launched;
+        }
+        // stopping test of the chunk's last iteration, then its scalars to the host
+        const int slot = slot_next % 2;
+        launch_itfin<V>(h->st, nb, h->P3, h->S, h->log, launched + 1, launched == run_start ? 1 : 0);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(&h->hS[slot], h->S, sizeof(Scalars), hipMemcpyDeviceToHost, h->st));
+        HIPCHECK(hipEventRecord(h->sev[slot], h->st));
+        flight.push_back({launched, slot, chunk_start, chunk, prof});
+        ++slot_next;
+        if (update && (launched - run_start) % s == 0) {
+          const int c = (launched - run_start) / s - 1;  // cycle c just ended
+          auto J = std::make_unique<CycleJob>();
+          J->cycle = c;
+          J->e = launched;
+          J->set = c % 2;
+          J->run_start = run_start;
+          J->rn0 = rn;
+          J->rho0 = rho;
+          HIPCHECK(hipEventCreateWithFlags(&J->ev, hipEventDisableTiming));
+          jobs.push_back(std::move(J));
+        }
+      }
+      if (update) TRY(advance(false));
+      if (flight.empty()) break;
+      TRY(read_one());
+      if (done) {
+        // drain the chunk still in flight (its launches returned at once)
+        while (!flight.empty()) {
+          HIPCHECK(hipEventSynchronize(h->sev[flight.front().slot]));
+          flight.pop_front();
+        }
+        break;
       }
     }
-    total = h->hS->iter;
-    status = h->hS->status;
+    if (!done) {
+      // maxit reached without the stopping test firing
+      completed = launched;
+      dev_status = ST_MAXIT;
+      known = completed;
+    }
+    // cycles that ended after the last completed iteration never happened
+    while (!jobs.empty() && jobs.back()->e > completed) {
+      CycleJob &J = *jobs.back();
+      if (J.stage == 2 || J.stage == 4) J.fut.wait();
+      if (J.stage >= 1) (void)hipEventSynchronize(J.ev);
+      (void)hipEventDestroy(J.ev);
+      jobs.pop_back();
+    }
+    // finish the remaining updates of this run
+    while (!jobs.empty()) TRY(advance(true));
+    total = completed;
+    status = dev_status;
     // keep this run's log
     if (total > run_start) {
       std::vector<double> tmp((size_t)(total - run_start) * LOG_STRIDE);
       HIPCHECK(hipMemcpy(tmp.data(), h->log + (size_t)(run_start + 1) * LOG_STRIDE,
                          tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
-      for (size_t t = 0; t < tmp.size(); t += LOG_STRIDE) tmp[t + 8] = restarts;
+      for (size_t t = 0; t < tmp.size(); t += LOG_STRIDE) tmp[t + 9] = restarts;
       fulllog.insert(fulllog.end(), tmp.begin(), tmp.end());
     }
     // Algorithm 2 step 7: x -= U zeta_c, x~ -= U~ zeta~_c
     if (ks > 0)
-      launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, 1, h->S);
+      launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
     // true residuals
     launch_residual<V, M>(h->st, A, b, x, (V *)h->t1);
     launch_residual<V, M>(h->st, AH, bt, xt, (V *)h->t2);
-    launch_dots<V>(h->st, n, (V *)h->t1, (V *)h->t1, (V *)h->t2, (V *)h->t2, nullptr, nullptr, h->partial, h->S);
-    HIPCHECK(hipGetLastError());
-    TRY(pull_scalars(h));
-    const double tr = std::sqrt(std::fabs(h->hS->red[0])), trt = std::sqrt(std::fabs(h->hS->red[2]));
+    TRY(host_dots<V>(h, (V *)h->t1, (V *)h->t1, (V *)h->t2, (V *)h->t2, nullptr, nullptr, d));
+    const double tr = std::sqrt(std::fabs(d[0].real())), trt = std::sqrt(std::fabs(d[1].real()));
     relres = tr / bn;
     relres_dual = trt / btn;
     const bool true_ok = tr <= tol * bn && trt <= tol * btn;
@@ -766,7 +1071,7 @@ int install_recycle(rbicg_s *h, const void *Usrc, const void *Utsrc, int k) {
   }
   if (Usrc != h->Ua) HIPCHECK(hipMemcpy2DAsync(h->Ua, h->ld * h->vb, Usrc, h->ld * h->vb, h->n * h->vb, k, hipMemcpyDeviceToDevice, h->st));
   if (Utsrc != h->Uta) HIPCHECK(hipMemcpy2DAsync(h->Uta, h->ld * h->vb, Utsrc, h->ld * h->vb, h->n * h->vb, k, hipMemcpyDeviceToDevice, h->st));
-  const int p = biorth<V, M>(h, k, h->U, h->Ut, h->C, h->Ct);
+  const int p = biorth_sync<V, M>(h, k);
   if (p < 0) return p;
   h->ksys = p;
   return 0;
@@ -790,51 +1095,89 @@ int alloc_workspace(rbicg_s *h) {
                     &h->Uc[1], &h->Utc[1], &h->Cc[1], &h->Ctc[1]};
   for (void **v : bases) TRY(dalloc(h, v, kb));
   if (h->kcap > 0 && h->opt.update) {
-    TRY(dalloc(h, &h->R, vbytes * h->scap));
-    TRY(dalloc(h, &h->Rt, vbytes * h->scap));
-    TRY(dalloc(h, &h->Z, vbytes * (h->scap + 1)));
-    TRY(dalloc(h, &h->Zt, vbytes * (h->scap + 1)));
+    TRY(dalloc(h, &h->R, 2 * vbytes * h->scap));
+    TRY(dalloc(h, &h->Rt, 2 * vbytes * h->scap));
+    TRY(dalloc(h, &h->Z, 2 * vbytes * (h->scap + 1)));
+    TRY(dalloc(h, &h->Zt, 2 * vbytes * (h->scap + 1)));
   }
   TRY(dalloc(h, (void **)&h->S, sizeof(Scalars)));
   HIPCHECK(hipMemset(h->S, 0, sizeof(Scalars)));
   h->logcap = h->opt.maxit + 2;
   TRY(dalloc(h, (void **)&h->log, (size_t)h->logcap * LOG_STRIDE * sizeof(double)));
-  const size_t nblocks = (h->n + RBICG_BLOCK - 1) / RBICG_BLOCK;
-  TRY(dalloc(h, (void **)&h->partial, nblocks * 4 * KMAXD * sizeof(double)));
-  const int w = std::max(2 * h->kcap, h->kcap + h->scap + 1);
-  h->gpart_bytes = (size_t)64 * w * w * 2 * sizeof(double);
+  h->nb = iter_grid(h->n);
+  TRY(dalloc(h, (void **)&h->partial, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
+  TRY(dalloc(h, (void **)&h->P1, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
+  TRY(dalloc(h, (void **)&h->P2, (size_t)h->nb * 4 * sizeof(double)));
+  TRY(dalloc(h, (void **)&h->P3, (size_t)h->nb * 8 * sizeof(double)));
+  const int wx = std::max(2 * h->kcap, h->kcap + h->scap + 1);
+  const int wy = std::max(2 * h->kcap, 2 * (h->kcap + h->scap) + 1);
+  const int w = std::max(wx, wy);
+  h->gpart_bytes = (size_t)gram_chunks(h->n) * wx * 96 * 2 * sizeof(double);
   TRY(dalloc(h, (void **)&h->gpart, h->gpart_bytes));
-  TRY(dalloc(h, (void **)&h->Gd, (size_t)w * w * 2 * sizeof(double)));
-  TRY(dalloc(h, (void **)&h->Wd, (size_t)RBICG_MAXCOLS * KMAXD * sizeof(cd)));
-  HIPCHECK(hipHostMalloc((void **)&h->hS, sizeof(Scalars), hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void **)&h->hG, (size_t)w * w * 2 * sizeof(double), hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void **)&h->hW, (size_t)RBICG_MAXCOLS * KMAXD * sizeof(cd), hipHostMallocDefault));
+  TRY(dalloc(h, (void **)&h->Gd, (size_t)wx * wy * 2 * sizeof(double)));
+  TRY(dalloc(h, (void **)&h->Wd, 6 * RBICG_WSLOT * sizeof(cd)));
+  if (h->opt.profile) {
+    const int nev = 8 * std::max(8, h->opt.chunk);
+    h->pev.resize(nev);
+    for (auto &e : h->pev) HIPCHECK(hipEventCreate(&e));
+  }
+  HIPCHECK(hipHostMalloc((void **)&h->hS, 2 * sizeof(Scalars), hipHostMallocDefault));
+  for (auto &e : h->sev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPCHECK(hipHostMalloc((void **)&h->hG, (size_t)wx * wy * 2 * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&h->hW, 6 * RBICG_WSLOT * sizeof(cd), hipHostMallocDefault));
+  (void)w;
   HIPCHECK(hipHostMalloc((void **)&h->hlog, (size_t)(h->scap + 2) * LOG_STRIDE * sizeof(double), hipHostMallocDefault));
   return 0;
 }
 
-int set_matrix(rbicg_s *h, const rbicg_csr *A, const rbicg_csr *AH) {
+int build_matrix(const rbicg_csr *A, const rbicg_csr *AH, rbicg_mat_s *m) {
   HostCsr hA, hAH;
   TRY(read_csr(A, hA));
-  if (hA.n != h->n) return rbicg_fail(RBICG_EINVAL, "matrix size %d does not match handle n=%d", hA.n, h->n);
   if (AH) {
     TRY(read_csr(AH, hAH));
-    if (hAH.n != h->n) return rbicg_fail(RBICG_EINVAL, "A^H size mismatch");
+    if (hAH.n != hA.n) return rbicg_fail(RBICG_EINVAL, "A^H size mismatch");
   } else {
     hAH = conj_transpose(hA);
   }
-  const bool cm = hA.complex_vals || hAH.complex_vals;
-  if (cm && h->vkind == 0) return rbicg_fail(RBICG_EINVAL, "complex matrix needs a RBICG_C128 handle");
-  h->mat_complex = cm;
-  const int kind = cm ? 1 : 0;
-  TRY(upload_sell(hA, kind, h->A));
-  TRY(upload_sell(hAH, kind, h->AH));
+  m->n = hA.n;
+  m->complex_vals = hA.complex_vals || hAH.complex_vals;
+  const int kind = m->complex_vals ? 1 : 0;
+  TRY(upload_sell(hA, kind, m->A));
+  TRY(upload_sell(hAH, kind, m->AH));
   return 0;
+}
+
+int attach_matrix(rbicg_s *h, rbicg_mat_s *m, bool own) {
+  if (!m) return rbicg_fail(RBICG_EINVAL, "null matrix");
+  if (m->n != h->n) return rbicg_fail(RBICG_EINVAL, "matrix size %d does not match handle n=%d", m->n, h->n);
+  if (m->complex_vals && h->vkind == 0) return rbicg_fail(RBICG_EINVAL, "complex matrix needs a RBICG_C128 handle");
+  if (h->own_mat && h->mat && h->mat != m) {
+    h->mat->A.release();
+    h->mat->AH.release();
+    delete h->mat;
+  }
+  h->mat = m;
+  h->own_mat = own;
+  h->mat_complex = m->complex_vals;
+  return 0;
+}
+
+int set_matrix(rbicg_s *h, const rbicg_csr *A, const rbicg_csr *AH) {
+  rbicg_mat_s *m = new rbicg_mat_s();
+  int rc = build_matrix(A, AH, m);
+  if (rc >= 0) rc = attach_matrix(h, m, true);
+  if (rc < 0) {
+    m->A.release();
+    m->AH.release();
+    delete m;
+  }
+  return rc;
 }
 
 }  // namespace
 
 // ====================================================================== C ABI
+static int check_opts(const rbicg_opts *opt);
 extern "C" void rbicg_default_opts(rbicg_opts *o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -855,12 +1198,7 @@ extern "C" void rbicg_default_opts(rbicg_opts *o) {
 extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
                             rbicg_handle *out) {
   if (!A || !opt || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
-  if (opt->k < 0 || opt->k > RBICG_KMAX) return rbicg_fail(RBICG_EINVAL, "k must be in [0, %d]", RBICG_KMAX);
-  if (opt->s < 2 || opt->s + opt->k + 1 > RBICG_MAXCOLS || opt->s > 120)
-    return rbicg_fail(RBICG_EINVAL, "cycle length s=%d out of range", opt->s);
-  if (opt->maxit < 1) return rbicg_fail(RBICG_EINVAL, "maxit must be positive");
-  if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128)
-    return rbicg_fail(RBICG_EINVAL, "precision mode %d is not available", (int)opt->prec);
+  TRY(check_opts(opt));
   if (A->n <= 0) return rbicg_fail(RBICG_EINVAL, "n must be positive");
   rbicg_s *h = new rbicg_s();
   h->opt = *opt;
@@ -881,12 +1219,99 @@ extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg
   return RBICG_OK;
 }
 
+extern "C" int rbicg_matrix_create(const rbicg_csr *A, const rbicg_csr *AH, rbicg_matrix *out) {
+  if (!A || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  rbicg_mat_s *m = new rbicg_mat_s();
+  const int rc = build_matrix(A, AH, m);
+  if (rc < 0) {
+    m->A.release();
+    m->AH.release();
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_matrix_destroy(rbicg_matrix m) {
+  if (!m) return RBICG_OK;
+  (void)hipDeviceSynchronize();
+  m->A.release();
+  m->AH.release();
+  delete m;
+  return RBICG_OK;
+}
+
+static int check_opts(const rbicg_opts *opt) {
+  if (opt->k < 0 || opt->k > RBICG_KMAX) return rbicg_fail(RBICG_EINVAL, "k must be in [0, %d]", RBICG_KMAX);
+  if (opt->s < 2 || opt->s + opt->k + 1 > 128)
+    return rbicg_fail(RBICG_EINVAL, "cycle length s=%d out of range", opt->s);
+  if (opt->maxit < 1) return rbicg_fail(RBICG_EINVAL, "maxit must be positive");
+  if (opt->chunk < 0 || opt->chunk > 256) return rbicg_fail(RBICG_EINVAL, "chunk out of range");
+  if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128)
+    return rbicg_fail(RBICG_EINVAL, "precision mode %d is not available", (int)opt->prec);
+  return 0;
+}
+
+extern "C" int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out) {
+  if (!A || !opt || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  TRY(check_opts(opt));
+  rbicg_s *h = new rbicg_s();
+  h->opt = *opt;
+  h->n = A->n;
+  h->ld = (A->n + 255) / 256 * 256;
+  h->st = (hipStream_t)opt->stream;
+  h->vkind = opt->prec == RBICG_C128 ? 1 : 0;
+  h->vb = h->vkind ? 16 : 8;
+  h->kcap = opt->k;
+  h->scap = opt->s;
+  int rc = attach_matrix(h, A, false);
+  if (rc >= 0) rc = alloc_workspace(h);
+  if (rc < 0) {
+    rbicg_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next) {
+  if (!h) return rbicg_fail(RBICG_EINVAL, "null handle");
+  if (A_next) TRY(attach_matrix(h, A_next, false));
+  return rbicg_update_recycle(h, nullptr, nullptr);
+}
+
+extern "C" int rbicg_profile(rbicg_handle h, int32_t reset, double *out) {
+  if (!h || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  for (int k = 0; k < 3; ++k) {
+    out[2 * k] = h->prof_ms[k];
+    out[2 * k + 1] = (double)h->prof_n[k];
+  }
+  const double n = h->n, b = (double)h->vb, ba = h->mat->A.vbytes, nnz = (double)h->mat->A.nnz;
+  const int k = h->ksys;
+  const double cap = (h->opt.update && h->opt.k > 0) ? 4.0 : 0.0;
+  out[6] = 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (8.0 + 2.0 * k + cap) * n * b;
+  out[7] = alg_bytes_iter(h, k);
+  if (reset)
+    for (int kk = 0; kk < 3; ++kk) {
+      h->prof_ms[kk] = 0;
+      h->prof_n[kk] = 0;
+    }
+  return RBICG_OK;
+}
+
 extern "C" int rbicg_destroy(rbicg_handle h) {
   if (!h) return RBICG_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
-  h->A.release();
-  h->AH.release();
+  if (h->own_mat && h->mat) {
+    h->mat->A.release();
+    h->mat->AH.release();
+    delete h->mat;
+  }
+  for (hipEvent_t e : h->pev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->sev)
+    if (e) (void)hipEventDestroy(e);
   for (void *p : h->allocs) (void)hipFree(p);
   if (h->hS) (void)hipHostFree(h->hS);
   if (h->hG) (void)hipHostFree(h->hG);
@@ -981,18 +1406,15 @@ extern "C" int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, doub
     int r1 = solve_impl<V, M>(h, (const V *)w, (const V *)u, (V *)x, (V *)xt, tol, st);
     if (r1 < 0 && r1 != RBICG_BREAKDOWN) return r1;
     // value = u^H x + x~^H r with r = w - A x;  ||r||, ||r~||
-    launch_residual<V, M>(h->st, h->A.view<M>(), (const V *)w, (const V *)x, (V *)h->t1);
-    launch_residual<V, M>(h->st, h->AH.view<M>(), (const V *)u, (const V *)xt, (V *)h->t2);
-    launch_dots<V>(h->st, h->n, (const V *)u, (const V *)x, (const V *)xt, (const V *)h->t1,
-                   (const V *)h->t1, (const V *)h->t1, h->partial, h->S);
-    TRY(pull_scalars(h));
-    const double *red = h->hS->red;
-    const double vr = red[0] + red[2], vi = red[1] + red[3];
-    const double rnorm = std::sqrt(std::fabs(red[4]));
-    launch_dots<V>(h->st, h->n, (const V *)h->t2, (const V *)h->t2, nullptr, nullptr, nullptr,
-                   nullptr, h->partial, h->S);
-    TRY(pull_scalars(h));
-    const double rtnorm = std::sqrt(std::fabs(h->hS->red[0]));
+    launch_residual<V, M>(h->st, h->mat->A.view<M>(), (const V *)w, (const V *)x, (V *)h->t1);
+    launch_residual<V, M>(h->st, h->mat->AH.view<M>(), (const V *)u, (const V *)xt, (V *)h->t2);
+    cplx dd[3];
+    TRY(host_dots<V>(h, (const V *)u, (const V *)x, (const V *)xt, (const V *)h->t1,
+                     (const V *)h->t1, (const V *)h->t1, dd));
+    const double vr = dd[0].real() + dd[1].real(), vi = dd[0].imag() + dd[1].imag();
+    const double rnorm = std::sqrt(std::fabs(dd[2].real()));
+    TRY(host_dots<V>(h, (const V *)h->t2, (const V *)h->t2, nullptr, nullptr, nullptr, nullptr, dd));
+    const double rtnorm = std::sqrt(std::fabs(dd[0].real()));
     double *out = (double *)value;
     out[0] = vr;
     if (h->vkind == 1) out[1] = vi;

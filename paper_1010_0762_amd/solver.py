@@ -43,13 +43,44 @@ def _stream_ptr(stream) -> Optional[int]:
     return int(stream.cuda_stream)
 
 
+class DeviceMatrix:
+    """A matrix (and its explicit conjugate transpose) repacked and resident in
+    device memory (rbicg_matrix_create)."""
+
+    def __init__(self, A, AH=None):
+        self.lib = _lib.load()
+        keep = []
+        a = _csr_struct(A, keep)
+        ah = _csr_struct(AH, keep) if AH is not None else None
+        self.n = a.n
+        self.complex = bool(a.values_complex)
+        h = ct.c_void_p()
+        rc = self.lib.rbicg_matrix_create(ct.byref(a), ct.byref(ah) if ah is not None else None,
+                                          ct.byref(h))
+        _lib.check(rc, "rbicg_matrix_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbicg_matrix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One handle: a matrix (and its explicit conjugate transpose), a recycle
-    space and the device workspace, kept across the systems of a sequence."""
+    space and the device workspace, kept across the systems of a sequence.
+    ``A`` is a host CSR (copied into a matrix the handle owns) or a
+    DeviceMatrix (shared; it must outlive the handle)."""
 
     def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
                  svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
-                 stream=None):
+                 stream=None, profile=False):
         self.lib = _lib.load()
         o = _lib.rbicg_opts()
         self.lib.rbicg_default_opts(ct.byref(o))
@@ -57,19 +88,26 @@ class Solver:
         o.update = 1 if update else 0
         o.svd_tol, o.seed, o.prec = svd_tol, seed, _PREC[prec]
         o.inner_tol, o.max_outer, o.chunk = inner_tol, max_outer, chunk
+        o.profile = 1 if profile else 0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         o.stream = _stream_ptr(self.stream)
         self.opts = o
         self.prec = prec
         self.dtype = torch.complex128 if prec == "c128" else torch.float64
-        keep = []
-        a = _csr_struct(A, keep)
-        ah = _csr_struct(AH, keep) if AH is not None else None
-        self.n = a.n
         h = ct.c_void_p()
-        rc = self.lib.rbicg_create(ct.byref(a), ct.byref(ah) if ah is not None else None,
-                                   ct.byref(o), ct.byref(h))
-        _lib.check(rc, "rbicg_create")
+        if isinstance(A, DeviceMatrix):
+            self.matrix = A
+            self.n = A.n
+            rc = self.lib.rbicg_create_on(A.h, ct.byref(o), ct.byref(h))
+            _lib.check(rc, "rbicg_create_on")
+        else:
+            keep = []
+            a = _csr_struct(A, keep)
+            ah = _csr_struct(AH, keep) if AH is not None else None
+            self.n = a.n
+            rc = self.lib.rbicg_create(ct.byref(a), ct.byref(ah) if ah is not None else None,
+                                       ct.byref(o), ct.byref(h))
+            _lib.check(rc, "rbicg_create")
         self.h = h
 
     # --------------------------------------------------------------- helpers
@@ -105,6 +143,10 @@ class Solver:
         return x, xt, st.as_dict()
 
     def update_recycle(self, A_next=None, AH_next=None):
+        if isinstance(A_next, DeviceMatrix):
+            self.matrix = A_next
+            _lib.check(self.lib.rbicg_update_recycle_on(self.h, A_next.h), "rbicg_update_recycle_on")
+            return
         keep = []
         a = _csr_struct(A_next, keep) if A_next is not None else None
         ah = _csr_struct(AH_next, keep) if AH_next is not None else None
@@ -132,6 +174,15 @@ class Solver:
         _lib.check(rc, "rbicg_get_recycle")
         kk = min(k.value, kcap)
         return tuple(b[:kk].t() for b in bufs)
+
+    def profile(self, reset=False):
+        """Per-kernel timing (rbicg_profile): dict with ms/launch counts and
+        the algorithmic bytes of one SpMV-kernel launch and of one iteration."""
+        out = np.zeros(8)
+        _lib.check(self.lib.rbicg_profile(self.h, 1 if reset else 0, _lib.dptr(out)), "rbicg_profile")
+        return {"spmv_ms": out[0], "spmv_n": int(out[1]), "expand_ms": out[2],
+                "expand_n": int(out[3]), "update_ms": out[4], "update_n": int(out[5]),
+                "spmv_bytes": out[6], "iter_bytes": out[7]}
 
     def log(self):
         """Per-iteration log of the last solve as an (iters, 10) float64 array."""

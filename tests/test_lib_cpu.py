@@ -136,3 +136,27 @@ def test_host_biorth_gives_identity():
                                _lib.dptr(_c(Ct2.conj().T @ C)), 0.5, _lib.dptr(TU.copy()),
                                _lib.dptr(TUt.copy()))
     assert p2 == int(np.sum(sv >= 0.5))
+
+
+def test_host_eig_ill_conditioned_pencil_matches_qz():
+    """cond(Q) ~ 1e9 (as in the harmonic Ritz pencils): the pencil is solved
+    without forming Q^{-1} P, so the small eigenvalues agree with LAPACK's QZ."""
+    lib = _lib.load()
+    rng = np.random.default_rng(11)
+    m = 40
+    U1, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    U2, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Q = U1 @ np.diag(np.logspace(0, -9, m)) @ U2
+    P = rng.standard_normal((m, m))
+    lam = np.zeros(2 * m); W = np.zeros(2 * m * m); Wl = np.zeros(2 * m * m)
+    assert lib.rbicg_host_eig(m, _lib.dptr(_c(P)), _lib.dptr(_c(Q)), _lib.dptr(lam), _lib.dptr(W),
+                              _lib.dptr(Wl)) == 0
+    lam = lam.view(np.complex128)
+    ref = sla.eigvals(P, Q)
+    small = ref[np.argsort(np.abs(ref))[:8]]
+    for l in small:
+        assert np.min(np.abs(lam - l)) <= 1e-7 * abs(l), l
+    W = _uc(W, m, m)
+    for j in np.argsort(np.abs(lam))[:8]:
+        res = np.linalg.norm(P @ W[:, j] - lam[j] * (Q @ W[:, j]))
+        assert res <= 1e-12 * (np.linalg.norm(P, 2) + abs(lam[j]) * np.linalg.norm(Q, 2))
