@@ -55,10 +55,8 @@ template <class V>
 void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed);
 // row chunks (blocks) of the Gram kernel for n rows
 int gram_chunks(int n);
-// Gram kernel: rows per LDS slab, LDS budget per block
-#define GRAM_SR_R 32
-#define GRAM_SR_C 16
-#define GRAM_LDS_BYTES 65536
+// Gram kernel: LDS budget per block (gfx950 has 160 KB per CU)
+#define GRAM_LDS_BYTES 153600
 // widest column group of Y per Gram launch for mx columns of X
 int gram_group(int mx, int complex_vals);
 // G = X^H Y for mx, my <= 192 columns (complex (re, im) row-major by (i, j))

@@ -558,12 +558,12 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 #define GRAM_BLOCK 256
 
 // Gram partials over a chunk of rows: G[i][j] = sum conj(X_i) Y_j for every
-// (i < mx, j < my) (mx, my <= 192, (mx16 + my16) * (SR + 2) * ND * 8 bytes of
-// LDS), one output of complex (re, im) per entry.  Each block reads its rows
-// of every column once (slabs of SR rows staged in LDS with a column stride of
-// SR + 2 doubles, which keeps the MFMA operand reads free of bank conflicts)
-// and accumulates all 16 x 16 output tiles on MFMA.
-template <class V, int SR>
+// (i < mx <= 128, j < my), one complex (re, im) per entry.  Each block reads its
+// rows of every column once, in slabs of SR rows staged in LDS (column stride
+// SR + 2 doubles keeps the MFMA operand reads free of bank conflicts), double
+// buffered: the next slab's loads are in flight while the MFMAs consume the
+// current one.  All 16 x 16 output tiles of the block accumulate on MFMA.
+template <class V, int SR, int GRAM_NLD>
 __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int mx, ColList Y,
                                                           int my, int rows_per_chunk,
                                                           double *partial) {
@@ -571,11 +571,12 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
   constexpr int PC = SR + 2;
   extern __shared__ double sm[];
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
-  double *xs = sm;                              // [ndv][mxp][PC]
-  double *ys = sm + (size_t)ndv * mxp * PC;     // [ndv][myp][PC]
-  const int TX = mxp / 16, TY = myp / 16, T = TX * TY;
+  const size_t bufsz = (size_t)ndv * (mxp + myp) * PC;
+  const int TY = myp / 16, T = (mxp / 16) * TY;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int ncol = mxp + myp;
+  const int nval = ncol * SR;
   d4 acc[GRAM_MAXT][ndv];
 #pragma unroll
   for (int t = 0; t < GRAM_MAXT; ++t)
@@ -583,16 +584,31 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
     for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
   const int r0 = blockIdx.x * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
-  for (int base = r0; base < r1; base += SR) {
-    for (int idx = threadIdx.x; idx < (mxp + myp) * SR; idx += GRAM_BLOCK) {
-      const int c = idx / SR, rr = idx % SR, row = base + rr;
-      const bool isx = c < mxp;
-      const int cc = isx ? c : c - mxp;
-      const int lim = isx ? mx : my;
+  const int nslabs = (r1 - r0 + SR - 1) / SR;
+  double pre[GRAM_NLD][ndv];
+  // Each thread's (column, row-in-slab) pairs are the same for every slab:
+  // resolve the column pointers once (a per-lane index into the pointer list
+  // would otherwise make every data load wait for a pointer load first).
+  const V *colp[GRAM_NLD];
+  int rrs[GRAM_NLD];
+#pragma unroll
+  for (int t = 0; t < GRAM_NLD; ++t) {
+    const int idx = threadIdx.x + t * GRAM_BLOCK;
+    const int c = idx / SR;
+    rrs[t] = idx % SR;
+    const bool isx = c < mxp;
+    const int cc = isx ? c : c - mxp;
+    colp[t] = (idx < nval && cc < (isx ? mx : my)) ? (const V *)(isx ? X.p[cc] : Y.p[cc]) : nullptr;
+  }
+  // global -> registers for slab `sl`
+  auto load = [&](int sl) {
+    const int base = r0 + sl * SR;
+#pragma unroll
+    for (int t = 0; t < GRAM_NLD; ++t) {
+      const int row = base + rrs[t];
       double vr = 0.0, vi = 0.0;
-      if (row < r1 && cc < lim) {
-        const V *col = (const V *)(isx ? X.p[cc] : Y.p[cc]);
-        const V v = col[row];
+      if (colp[t] && row < r1) {
+        const V v = colp[t][row];
         if constexpr (ndv == 2) {
           vr = ((const cd &)v).x;
           vi = ((const cd &)v).y;
@@ -600,34 +616,58 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
           vr = (double)v;
         }
       }
-      double *dst = isx ? xs : ys;
-      const int mp = isx ? mxp : myp;
-      dst[(size_t)cc * PC + rr] = vr;
-      if constexpr (ndv == 2) dst[(size_t)mp * PC + (size_t)cc * PC + rr] = vi;
+      pre[t][0] = vr;
+      if constexpr (ndv == 2) pre[t][ndv - 1] = vi;
     }
-    __syncthreads();
+  };
+  // registers -> LDS buffer b: layout [part][column][PC] with X columns first
+  auto store = [&](int b) {
+    double *buf = sm + (size_t)b * bufsz;
 #pragma unroll
-    for (int t = 0; t < GRAM_MAXT; ++t) {
-      const int tile = w + 4 * t;
-      if (tile < T) {
-        const int ti = tile / TY, tj = tile % TY;
-        const double *xa = xs + (size_t)(ti * 16 + li) * PC + lk;
-        const double *yb = ys + (size_t)(tj * 16 + li) * PC + lk;
-        for (int kk = 0; kk < SR; kk += 4) {
+    for (int t = 0; t < GRAM_NLD; ++t) {
+      const int idx = threadIdx.x + t * GRAM_BLOCK;
+      if (idx < nval) {
+        const int c = idx / SR, rr = idx % SR;
+        buf[(size_t)c * PC + rr] = pre[t][0];
+        if constexpr (ndv == 2) buf[(size_t)ncol * PC + (size_t)c * PC + rr] = pre[t][ndv - 1];
+      }
+    }
+  };
+  if (nslabs > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int sl = 0; sl < nslabs; ++sl) {
+    if (sl + 1 < nslabs) load(sl + 1);
+    const double *buf = sm + (size_t)(sl & 1) * bufsz;
+    // k-steps outside, tiles inside: consecutive MFMAs feed different
+    // accumulators, so they issue back to back instead of waiting out the
+    // latency of a dependent chain
+#pragma unroll
+    for (int kk = 0; kk < SR; kk += 4) {
+#pragma unroll
+      for (int t = 0; t < GRAM_MAXT; ++t) {
+        const int tile = w + 4 * t;
+        if (tile < T) {
+          const int ti = tile / TY, tj = tile % TY;
+          const double *xa = buf + (size_t)(ti * 16 + li) * PC + lk;
+          const double *yb = buf + (size_t)(mxp + tj * 16 + li) * PC + lk;
           const double ar = xa[kk], br = yb[kk];
           if constexpr (ndv == 1) {
             acc[t][0] = mfma(ar, br, acc[t][0]);
           } else {
-            const double ai = xa[(size_t)mxp * PC + kk], bi = yb[(size_t)myp * PC + kk];
+            const double ai = xa[(size_t)ncol * PC + kk], bi = yb[(size_t)ncol * PC + kk];
             // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
             acc[t][0] = mfma(ar, br, acc[t][0]);
             acc[t][0] = mfma(ai, bi, acc[t][0]);
-            acc[t][1] = mfma(ar, bi, acc[t][1]);
-            acc[t][1] = mfma(-ai, br, acc[t][1]);
+            acc[t][ndv - 1] = mfma(ar, bi, acc[t][ndv - 1]);
+            acc[t][ndv - 1] = mfma(-ai, br, acc[t][ndv - 1]);
           }
         }
       }
     }
+    if (sl + 1 < nslabs) store((sl + 1) & 1);
     __syncthreads();
   }
 #pragma unroll
@@ -859,25 +899,41 @@ int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
 
 int gram_group(int mx, int complex_vals) {
   const int TX = (mx + 15) / 16;
-  const int pc = (complex_vals ? GRAM_SR_C : GRAM_SR_R) + 2;
-  const int nd = complex_vals ? 2 : 1;
-  const int mxp = TX * 16;
-  const int lds_cols = (int)(GRAM_LDS_BYTES / ((size_t)pc * nd * sizeof(double)));
   int g = std::min(96, (4 * GRAM_MAXT / TX) * 16);
-  g = std::min(g, (lds_cols - mxp) / 16 * 16);
+  // the short-slab variant holds up to 282 (real) / 266 (complex) columns
+  const int mxp = TX * 16;
+  const int lim = (complex_vals ? 266 : 282) / 16 * 16;
+  g = std::min(g, lim - mxp);
   return std::max(16, g);
 }
 
 template <class V>
 void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
                  double *partial, double *G, int nchunks) {
-  constexpr int SR = sizeof(V) == 16 ? GRAM_SR_C : GRAM_SR_R;
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
   const int rpc = (int)(((size_t)n + nchunks - 1) / nchunks);
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
-  const size_t lds = (size_t)(mxp + myp) * (SR + 2) * ndv * sizeof(double);
-  hipLaunchKernelGGL((k_gram_mfma<V, SR>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X, mx, Y,
-                     my, rpc, partial);
+  const int ncol = mxp + myp;
+  // longest slab (contiguous run per column) whose two LDS buffers fit
+  const int sr_big = ndv == 2 ? 32 : 64;
+  const bool big = 2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES;
+  const int sr = big ? sr_big : sr_big / 2;
+  const size_t lds = 2 * (size_t)ncol * (sr + 2) * ndv * sizeof(double);
+  if (ndv == 1) {
+    if (big)
+      hipLaunchKernelGGL((k_gram_mfma<V, 64, 36>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+                         mx, Y, my, rpc, partial);
+    else
+      hipLaunchKernelGGL((k_gram_mfma<V, 32, 36>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+                         mx, Y, my, rpc, partial);
+  } else {
+    if (big)
+      hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+                         mx, Y, my, rpc, partial);
+    else
+      hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+                         mx, Y, my, rpc, partial);
+  }
   const int count = 2 * mx * my;
   hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count)), dim3(RBICG_BLOCK), 0, st, partial,
                      nchunks, count, G);
