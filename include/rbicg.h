@@ -22,7 +22,9 @@
  *     used in stream order on opts.stream; the call returns after the result
  *     is complete (it synchronizes that stream).  The library never frees
  *     caller memory.
- *   - Recycle bases are column-major n x k device arrays (leading dimension n).
+ *   - Recycle bases are column-major n x k device arrays (leading dimension n)
+ *     of the handle's storage type: double, complex double, or float for
+ *     RBICG_F32_IN_F64_OUT (whose inner solver works on float copies).
  *
  * Ownership: a handle owns device copies of A and of the explicit A^H, the
  * recycle bases U, U~, C = A U, C~ = A^H U~, the cycle buffers and the
@@ -164,7 +166,15 @@ int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
  * entry and the solutions on exit.  The recycle space U, U~ of the handle is
  * used as fixed (Sec. 3); when opts.update is set, the cycle-wise update of
  * Sec. 4 builds the recycle space for the next system, installed by
- * rbicg_update_recycle.  st may be NULL. */
+ * rbicg_update_recycle.  st may be NULL.
+ * RBICG_F32_IN_F64_OUT handles (not in the paper): FP64 iterative refinement
+ * around the float RBiCG.  Each outer step forms r = b - A x, r~ = b~ - A^H x~
+ * with the FP64 matrix, stops when both are <= tol relative, else solves
+ * A d = r, A^H d~ = r~ with float matrix values and vectors (every reduction
+ * in FP64) to opts.inner_tol relative and adds d, d~ to x, x~ in FP64; the
+ * latest cycle's recycle space carries to the next outer step.  st->iters
+ * counts inner iterations, st->outer_steps the refinement steps; st->relres
+ * is the FP64 true residual.  At most opts.max_outer steps. */
 int rbicg_solve_dual(rbicg_handle h, const void *b, const void *bt, void *x, void *xt,
                      double tol, rbicg_stats *st);
 

@@ -101,6 +101,8 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
     """RBiCG with FP32 storage: matrix values and every n-vector are float32;
     each element operation is evaluated in float64 and rounded once when stored;
     all inner products and norms accumulate in float64.  Starts from x = x~ = 0.
+    With a recycle space, r and r~ are re-projected in every iteration (see
+    the loop).
     The recycle space (U, C, ...) is given in FP64 and used through FP32
     copies; the cycle update works in FP64 on the FP64 matrix (A64) from the
     FP32-stored Lanczos vectors.  Returns (d, d~, iters, cycle state)."""
@@ -129,6 +131,10 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
     rho = float(rt.astype(f64) @ r.astype(f64))
     rn = np.linalg.norm(r.astype(f64)); rtn = np.linalg.norm(rt.astype(f64))
     V, Vt, ca, cb, cr = [], [], [], [], []
+    # relative residual max(||r||/||b||, ||r~||/||b~||) by iteration, for the
+    # stagnation stop below
+    hist = [max(rn / bn, rtn / btn)]
+    diverged = False
     it = 0
     while it < maxit and not (rn <= tol * bn and rtn <= tol * btn):
         it += 1
@@ -152,6 +158,19 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
             v = r.astype(f64) / rn
             V.append(v); Vt.append(rt.astype(f64) / float(v @ rt.astype(f64)))
             ca.append(alpha); cb.append(beta); cr.append(rn)
+        if kc:
+            # Re-projection (reading for FP32 storage, not in the paper): in
+            # exact arithmetic C~^H r = 0 and C^H r~ = 0 (Sec. 3.1), so
+            # r <- r - C (C~^H r) together with zeta_c <- zeta_c - C~^H r
+            # changes nothing; in float storage the rounding of every update
+            # feeds C~^H r, which the oblique projector amplifies until the
+            # iteration stagnates.  Done on r_{i-1} once per iteration.
+            g = Ct32.astype(f64).T @ r.astype(f64)
+            gt = C32.astype(f64).T @ rt.astype(f64)
+            r = _f32(r.astype(f64) - C32.astype(f64) @ g)
+            rt = _f32(rt.astype(f64) - Ct32.astype(f64) @ gt)
+            zeta_c -= g
+            zetat_c -= gt
         x = _f32(x.astype(f64) + alpha * p.astype(f64))
         xt = _f32(xt.astype(f64) + alpha * pt.astype(f64))
         r = _f32(r.astype(f64) - alpha * q.astype(f64))
@@ -163,6 +182,23 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
             V, Vt, ca, cb, cr = [], [], [], [], []
         if rn <= tol * bn and rtn <= tol * btn:
             break
+        hist.append(max(rn / bn, rtn / btn))
+        # Cycle-end guards (reading for FP32 storage, not in the paper); both
+        # need a whole cycle without progress (hist[it] >= hist[it - s]):
+        #  stagnation -- float storage behind the oblique projector limits the
+        #    attainable residual to about the inner tolerance; once below
+        #    sqrt(tol), return the iterate and let the FP64 outer loop go on;
+        #  divergence -- for some recycle spaces the deflated iteration is so
+        #    ill conditioned that float rounding keeps it from converging (FP64
+        #    is fine); with a recycle space in use, from the second cycle on,
+        #    a residual not below the initial one gives up on this inner solve
+        #    (the outer loop discards it and drops the recycle space).
+        if it % s == 0 and it >= s and hist[it] >= hist[it - s]:
+            if hist[it] <= np.sqrt(tol):
+                break
+            if kc and it >= 2 * s and hist[it] >= hist[0]:
+                diverged = True
+                break
         beta = rho_new / rho
         rho = rho_new
     d = x.astype(f64)
@@ -170,7 +206,20 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
     if kc:
         d = d - U @ zeta_c
         dt_ = dt_ - Ut @ zetat_c
-    return d, dt_, it, cyc
+    return d, dt_, it, cyc, diverged
+
+
+# unit roundoff of IEEE binary32
+EPS32 = 2.0 ** -24
+
+
+def mixed_svd_tol(svd_tol, inner_tol):
+    """Cosine cut of the biorthogonalization in FP32-inner mode (reading, not
+    in the paper): float rounding inside the projected iteration is amplified
+    by ||I - C C~^H|| <= 1 + 1/tau, so the attainable inner residual is about
+    eps32 / tau; keeping it ten times below the inner tolerance needs
+    tau >= 10 eps32 / inner_tol."""
+    return max(svd_tol, 10.0 * EPS32 / inner_tol)
 
 
 def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
@@ -181,31 +230,53 @@ def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
     residuals are <= tol; otherwise solve A d = r, A^H d~ = r~ to inner_tol
     relative with the FP32 inner RBiCG and update x += d, x~ += d~ in FP64.
     The recycle space carries over between outer steps (the latest cycle's
-    space when one completed).  Returns (x, x~, info, (U, U~))."""
+    space when one completed), biorthogonalized with the cut of
+    mixed_svd_tol.  Safeguards (readings): an inner solve stopped as diverging
+    is discarded; a correction that raises max(||r||/||b||, ||r~||/||b~||) is
+    taken back (x -= d, x~ -= d~); either way the recycle space is dropped.
+    Returns (x, x~, info, (U, U~))."""
     A = as_csr(A).astype(np.float64)
     AH = A.T.tocsr()
     A32 = A.astype(np.float32)
     AH32 = AH.astype(np.float32)
+    tau = mixed_svd_tol(svd_tol, inner_tol)
     n = A.shape[0]
     x = np.zeros(n); xt = np.zeros(n)
     bn = np.linalg.norm(b); btn = np.linalg.norm(bt)
+    bn = bn if bn > 0 else 1.0
+    btn = btn if btn > 0 else 1.0
     inner_total = 0
     outer = 0
+    prev = None          # residual measure before the last applied correction
+    last = None          # the last applied correction (d, d~)
     while True:
         r = b - A @ x
         rt = bt - AH @ xt
         rel, relt = np.linalg.norm(r) / bn, np.linalg.norm(rt) / btn
+        if last is not None and max(rel, relt) > prev:
+            x = x - last[0]
+            xt = xt - last[1]
+            U = Ut = None
+            r = b - A @ x
+            rt = bt - AH @ xt
+            rel, relt = np.linalg.norm(r) / bn, np.linalg.norm(rt) / btn
+        last = None
         if (rel <= tol and relt <= tol) or outer >= max_outer:
             break
         C = Ct = None
         if U is not None and U.shape[1] > 0:
-            U, Ut, C, Ct = rc.biorthogonalize(A, AH, U, Ut, svd_tol)
+            U, Ut, C, Ct = rc.biorthogonalize(A, AH, U, Ut, tau)
             if C is None:
                 U = Ut = None
-        d, dt_, it, cyc = rbicg_fp32_inner(A32, AH32, r, rt, U, Ut, C, Ct, inner_tol,
-                                           maxit_inner, s, k, update, svd_tol, A, AH)
+        d, dt_, it, cyc, diverged = rbicg_fp32_inner(A32, AH32, r, rt, U, Ut, C, Ct, inner_tol,
+                                                     maxit_inner, s, k, update, tau, A, AH)
         inner_total += it
         outer += 1
+        if diverged:
+            U = Ut = None
+            continue
+        prev = max(rel, relt)
+        last = (d, dt_)
         x = x + d
         xt = xt + dt_
         if cyc.Uj is not None and cyc.Uj.shape[1] > 0:

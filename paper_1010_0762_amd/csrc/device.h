@@ -20,6 +20,13 @@ struct cd {
 struct Scalars {
   double tol, bn, btn;
   int iter, done, status, maxit;
+  // FP32-inner solves: at every stag_s-th iteration, when the relative
+  // residual max(||r||/||b||, ||r~||/||b~||) is not below the one stag_s
+  // iterations earlier, stop as stagnated if it is <= stag_lim, or (with
+  // stag_div set: a recycle space is in use) as diverged if, from the second
+  // cycle on, it is not below the initial one (stag_s = 0: off)
+  int stag_s, stag_div;
+  double stag_lim;
   double zbuf[4 * KMAXD];
   double zc[4 * KMAXD];
   double gbuf[4 * KMAXD];
@@ -31,6 +38,8 @@ struct Scalars {
 #define ST_CONVERGED 1
 #define ST_MAXIT 2
 #define ST_BREAKDOWN 3
+#define ST_STAGNATED 4
+#define ST_DIVERGED 5
 
 // Wave-sliced ELL: rows grouped in slices of 64 (one wavefront, one row per
 // lane); entry j of row r sits at sliceptr[r/64] + j*64 + r%64.  Padding

@@ -18,15 +18,16 @@ template <class V, class M>
 void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, const V *r,
                 const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt, const V *C,
                 const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
-                const double *P3, double *P1, Scalars *S, double *rec, int it, int first);
+                const double *P3, double *P1, Scalars *S, double *rec, int it, int first,
+                int rp);
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
                 const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
-                double *P2, Scalars *S);
+                double *P2, Scalars *S, V *r, V *rt, int rp);
 template <class V>
 void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
                 const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
-                Scalars *S, double *rec, int it);
+                Scalars *S, double *rec, int it, int rp);
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
                   int first);
@@ -53,6 +54,9 @@ template <class V>
 void launch_fill_zero(hipStream_t st, V *p, size_t n);
 template <class V>
 void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed);
+// out = (float)in; x += sgn (double)d (FP32-inner mode)
+void launch_d2f(hipStream_t st, const double *in, float *out, size_t n);
+void launch_add_f2d(hipStream_t st, double *x, const float *d, double sgn, size_t n);
 // row chunks (blocks) of the Gram kernel for n rows
 int gram_chunks(int n);
 // Gram kernel: LDS budget per block (gfx950 has 160 KB per CU)

@@ -18,6 +18,13 @@
 //          zeta~_c += conj(alpha) zeta~; x += alpha p, x~ += conj(alpha) p~,
 //          r -= alpha q, r~ -= conj(alpha) q~; partials of ||r||^2, ||r~||^2,
 //          (r~, r).
+// In FP32-storage inner solves (flag rp) k_it1 also forms partials of
+// g = C~^H r_{i-1}, g~ = C^H r~_{i-1}; k_it2 re-projects r_{i-1} -= C g,
+// r~_{i-1} -= C~ g~ and k_it3 subtracts g, g~ from zeta_c, zeta~_c, which
+// keeps x - U zeta_c consistent.  In exact arithmetic g = 0 (the recurrences
+// keep r orthogonal to range(C~), Sec. 3.1); in float storage the rounding of
+// every update feeds C~^H r, the oblique projector amplifies it and the
+// iteration stagnates without this step.
 // Block 0 records the scalars of every iteration for the host.  Every launch
 // first reads the device 'done' flag and returns at once after the stopping
 // test has fired, so the host may enqueue iterations ahead of the test.
@@ -198,6 +205,16 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
   if (rn <= S->tol * S->bn && rtn <= S->tol * S->btn) st = ST_CONVERGED;
   else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
   else if (it > S->maxit) st = ST_MAXIT;
+  else if (S->stag_s > 0 && (it - 1) % S->stag_s == 0 && it - 1 >= S->stag_s) {
+    const double *Rp = rec + (size_t)(it - 1 - S->stag_s) * LOG_STRIDE;
+    const double cur = fmax(rn / S->bn, rtn / S->btn);
+    const double prev = fmax(Rp[6] / S->bn, Rp[7] / S->btn);
+    if (cur >= prev) {
+      if (cur <= S->stag_lim) st = ST_STAGNATED;
+      else if (S->stag_div && it - 1 >= 2 * S->stag_s && cur >= fmax(rec[6] / S->bn, rec[7] / S->btn))
+        st = ST_DIVERGED;
+    }
+  }
   if (st != ST_RUNNING) {
     if (lead) {
       S->status = st;
@@ -228,7 +245,7 @@ __global__ __launch_bounds__(IB) void k_it1(
     const V *__restrict__ rt, const V *__restrict__ pt, V *__restrict__ pn, V *__restrict__ ptn,
     V *__restrict__ z, V *__restrict__ zt, const V *__restrict__ C, const V *__restrict__ Ct,
     int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, const double *__restrict__ P3,
-    double *__restrict__ P1, Scalars *S, double *rec, int it, int first) {
+    double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp) {
   using T = typename Ar<V>::T;
   if (S->done) return;
   __shared__ double lds[NW * 4 * KMAXD];
@@ -240,14 +257,18 @@ __global__ __launch_bounds__(IB) void k_it1(
   const int n = A.n;
   const int stride = gridDim.x * IB;
   const int row0 = blockIdx.x * IB + threadIdx.x;
-  T zr[RMAX], ztr[RMAX];
+  T zr[RMAX], ztr[RMAX], rr_[RMAX], rtr_[RMAX];
 #pragma unroll
   for (int q = 0; q < RMAX; ++q) {
     zr[q] = zero<T>();
     ztr[q] = zero<T>();
+    rr_[q] = zero<T>();
+    rtr_[q] = zero<T>();
     const int row = row0 + q * stride;
     if (row < n) {
       const V rv = r[row], rtv = rt[row];
+      rr_[q] = up(rv);
+      rtr_[q] = up(rtv);
       pn[row] = down<V>(up(rv) + beta * up(p[row]));
       ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
       const T zz = up(down<V>(spmv_dir<V, M, T>(A, row, r, p, beta)));
@@ -267,39 +288,54 @@ __global__ __launch_bounds__(IB) void k_it1(
   if (k == 0) return;
   const int ls = 4 * KMAXD;
   for (int j = 0; j < k; ++j) {
-    T a = zero<T>(), b = zero<T>();
+    T a = zero<T>(), b = zero<T>(), c = zero<T>(), d = zero<T>();
 #pragma unroll
     for (int q = 0; q < RMAX; ++q) {
       const int row = row0 + q * stride;
       if (row < n) {
-        a += cj(up(Ct[(size_t)j * ld + row])) * zr[q];
-        b += cj(up(C[(size_t)j * ld + row])) * ztr[q];
+        const T ctv = cj(up(Ct[(size_t)j * ld + row])), cv = cj(up(C[(size_t)j * ld + row]));
+        a += ctv * zr[q];
+        b += cv * ztr[q];
+        c += ctv * rr_[q];
+        d += cv * rtr_[q];
       }
     }
     put<T>(lds, ls, j, a);
     put<T>(lds, ls, k + j, b);
+    if (rp) {
+      put<T>(lds, ls, 2 * k + j, c);
+      put<T>(lds, ls, 3 * k + j, d);
+    }
   }
   __syncthreads();
-  bstore(lds, ls, NW, 2 * k * ND<T>::v, P1);
+  bstore(lds, ls, NW, (rp ? 4 : 2) * k * ND<T>::v, P1);
 }
 
+//          with rp set (FP32 storage), also r_{i-1} -= C g, r~_{i-1} -= C~ g~
+//          for the g = C~^H r_{i-1}, g~ = C^H r~_{i-1} whose partials k_it1
+//          wrote (re-projection; block 0 keeps g, g~ in S->gbuf for k_it3).
 template <class V>
 __global__ __launch_bounds__(IB) void k_it2(int n, const V *__restrict__ z,
                                             const V *__restrict__ zt, const V *__restrict__ C,
                                             const V *__restrict__ Ct, int k, int ld,
                                             const V *__restrict__ ptn, V *__restrict__ q,
                                             V *__restrict__ qt, const double *__restrict__ P1,
-                                            double *__restrict__ P2, Scalars *S) {
+                                            double *__restrict__ P2, Scalars *S,
+                                            V *__restrict__ r, V *__restrict__ rt, int rp) {
   using T = typename Ar<V>::T;
   if (S->done) return;
   __shared__ double lds[NW * 2];
   __shared__ double tmp[IB];
   __shared__ double zl[4 * KMAXD];
-  const int nv1 = 2 * k * ND<T>::v;
+  const int nz = 2 * k * ND<T>::v;
+  const int nv1 = (rp ? 2 : 1) * nz;
   if (k > 0) {
     breduce(P1, gridDim.x, nv1, tmp, zl);
-    if (blockIdx.x == 0)
-      for (int t = threadIdx.x; t < nv1; t += IB) S->zbuf[t] = zl[t];
+    if (blockIdx.x == 0) {
+      for (int t = threadIdx.x; t < nz; t += IB) S->zbuf[t] = zl[t];
+      if (rp)
+        for (int t = threadIdx.x; t < nz; t += IB) S->gbuf[t] = zl[nz + t];
+    }
   }
   const int stride = gridDim.x * IB;
   T part = zero<T>();
@@ -307,15 +343,24 @@ __global__ __launch_bounds__(IB) void k_it2(int n, const V *__restrict__ z,
     T qq = up(z[row]);
     T qqt = up(zt[row]);
     if (k > 0) {
-      T s = zero<T>(), st = zero<T>();
+      T s = zero<T>(), st = zero<T>(), g = zero<T>(), gt = zero<T>();
       for (int j = 0; j < k; ++j) {
-        s += up(C[(size_t)j * ld + row]) * get<T>(zl, j);
-        st += up(Ct[(size_t)j * ld + row]) * get<T>(zl, k + j);
+        const T cv = up(C[(size_t)j * ld + row]), ctv = up(Ct[(size_t)j * ld + row]);
+        s += cv * get<T>(zl, j);
+        st += ctv * get<T>(zl, k + j);
+        if (rp) {
+          g += cv * get<T>(zl, 2 * k + j);
+          gt += ctv * get<T>(zl, 3 * k + j);
+        }
       }
       qq = up(down<V>(qq - s));
       qqt = up(down<V>(qqt - st));
       q[row] = down<V>(qq);
       qt[row] = down<V>(qqt);
+      if (rp) {
+        r[row] = down<V>(up(r[row]) - g);
+        rt[row] = down<V>(up(rt[row]) - gt);
+      }
     }
     part += cj(up(ptn[row])) * qq;
   }
@@ -331,7 +376,7 @@ __global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restr
                                             const V *__restrict__ q, const V *__restrict__ qt,
                                             int k, const double *__restrict__ P2,
                                             double *__restrict__ P3, Scalars *S, double *rec,
-                                            int it) {
+                                            int it, int rp) {
   using T = typename Ar<V>::T;
   if (S->done) return;
   __shared__ double lds[NW * 4];
@@ -356,8 +401,14 @@ __global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restr
     if (ND<T>::v == 1) Ri[1] = 0.0;
     Ri[8] = comp(sigma, 0);
     for (int j = 0; j < k; ++j) {
-      set<T>(S->zc, j, get<T>(S->zc, j) + al * get<T>(S->zbuf, j));
-      set<T>(S->zc, k + j, get<T>(S->zc, k + j) + alc * get<T>(S->zbuf, k + j));
+      T u = get<T>(S->zc, j) + al * get<T>(S->zbuf, j);
+      T ut = get<T>(S->zc, k + j) + alc * get<T>(S->zbuf, k + j);
+      if (rp) {
+        u = u - get<T>(S->gbuf, j);
+        ut = ut - get<T>(S->gbuf, k + j);
+      }
+      set<T>(S->zc, j, u);
+      set<T>(S->zc, k + j, ut);
     }
   }
   const int stride = gridDim.x * IB;
@@ -529,6 +580,17 @@ __device__ __forceinline__ double smix_uniform(unsigned long long seed, unsigned
   z = z ^ (z >> 31);
   return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
 }
+// FP32-inner mode: round FP64 data to float storage, and accumulate a float
+// correction into an FP64 vector (x += sgn d, sgn = +-1, computed in double).
+__global__ void k_d2f(const double *__restrict__ in, float *__restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+__global__ void k_add_f2d(double *__restrict__ x, const float *__restrict__ d, double sgn, size_t n) {
+  const size_t i = (size_t)blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i < n) x[i] += sgn * (double)d[i];
+}
+
 template <class V> __device__ V reseed_val(unsigned long long seed, size_t i);
 template <> __device__ double reseed_val<double>(unsigned long long seed, size_t i) {
   return smix_uniform(seed, i);
@@ -825,23 +887,23 @@ template <class V, class M>
 void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, const V *r,
                 const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt, const V *C,
                 const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
-                const double *P3, double *P1, Scalars *S, double *rec, int it, int first) {
+                const double *P3, double *P1, Scalars *S, double *rec, int it, int first, int rp) {
   hipLaunchKernelGGL((k_it1<V, M>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn, z,
-                     zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first);
+                     zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
 }
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
                 const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
-                double *P2, Scalars *S) {
+                double *P2, Scalars *S, V *r, V *rt, int rp) {
   hipLaunchKernelGGL((k_it2<V>), dim3(nb), dim3(IB), 0, st, n, z, zt, C, Ct, k, ld, ptn, q, qt,
-                     P1, P2, S);
+                     P1, P2, S, r, rt, rp);
 }
 template <class V>
 void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
                 const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
-                Scalars *S, double *rec, int it) {
+                Scalars *S, double *rec, int it, int rp) {
   hipLaunchKernelGGL((k_it3<V>), dim3(nb), dim3(IB), 0, st, n, x, xt, r, rt, pn, ptn, q, qt, k,
-                     P2, P3, S, rec, it);
+                     P2, P3, S, rec, it, rp);
 }
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
@@ -894,6 +956,14 @@ void launch_fill_zero(hipStream_t st, V *p, size_t n) {
 template <class V>
 void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed) {
   hipLaunchKernelGGL((k_reseed<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, n, seed);
+}
+void launch_d2f(hipStream_t st, const double *in, float *out, size_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_d2f, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, in, out, n);
+}
+void launch_add_f2d(hipStream_t st, double *x, const float *d, double sgn, size_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_add_f2d, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
 }
 int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
 
@@ -950,7 +1020,8 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
   template void launch_it1<V, M>(hipStream_t, int, const Sell<M> &, const Sell<M> &,         \
                                  const V *, const V *, const V *, const V *, V *, V *, V *,  \
                                  V *, const V *, const V *, int, int, V *, V *, V *, V *,    \
-                                 const double *, double *, Scalars *, double *, int, int);   \
+                                 const double *, double *, Scalars *, double *, int, int,    \
+                                 int);                                                       \
   template void launch_residual<V, M>(hipStream_t, const Sell<M> &, const V *, const V *,    \
                                       V *);                                                  \
   template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);
@@ -958,10 +1029,10 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
 #define INST_V(V)                                                                            \
   template void launch_it2<V>(hipStream_t, int, int, const V *, const V *, const V *,        \
                               const V *, int, int, const V *, V *, V *, const double *,      \
-                              double *, Scalars *);                                          \
+                              double *, Scalars *, V *, V *, int);                           \
   template void launch_it3<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
                               const V *, const V *, const V *, int, const double *, double *, \
-                              Scalars *, double *, int);                                     \
+                              Scalars *, double *, int, int);                                \
   template void launch_itfin<V>(hipStream_t, int, const double *, Scalars *, double *, int,  \
                                 int);                                                        \
   template void launch_init_p3<V>(hipStream_t, int, int, const V *, const V *, double *);    \

@@ -13,6 +13,7 @@
 #include <future>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "rbicg.h"
@@ -60,6 +61,7 @@ struct DevSell {
   int *sliceptr = nullptr;
   int *col = nullptr;
   void *val = nullptr;
+  float *val32 = nullptr;  // float copy of real values (FP32-inner mode), made on demand
   size_t nnzpad = 0;
   int64_t nnz = 0;
   int vbytes = 0;
@@ -69,16 +71,29 @@ struct DevSell {
     s.nslices = nslices;
     s.sliceptr = sliceptr;
     s.col = col;
-    s.val = (const M *)val;
+    if constexpr (std::is_same<M, float>::value) s.val = val32;
+    else s.val = (const M *)val;
     return s;
   }
   void release() {
     if (sliceptr) (void)hipFree(sliceptr);
     if (col) (void)hipFree(col);
     if (val) (void)hipFree(val);
+    if (val32) (void)hipFree(val32);
     sliceptr = nullptr;
     col = nullptr;
     val = nullptr;
+    val32 = nullptr;
+  }
+  // float copy of the (real, FP64) values
+  int make_f32(hipStream_t st) {
+    if (val32) return 0;
+    if (vbytes != 8) return rbicg_fail(RBICG_EINVAL, "FP32-inner mode needs a real FP64 matrix");
+    HIPCHECK(hipMalloc(&val32, std::max<size_t>(nnzpad, 1) * sizeof(float)));
+    launch_d2f(st, (const double *)val, val32, nnzpad);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
+    return 0;
   }
 };
 
@@ -225,7 +240,7 @@ struct rbicg_s {
   int n = 0;
   int ld = 0;
   hipStream_t st = nullptr;
-  int vkind = 0;  // 0 double, 1 complex
+  int vkind = 0;  // 0 double, 1 complex, 2 float (FP32-inner / FP64-outer mode)
   bool mat_complex = false;
   size_t vb = 8;
   int kcap = 0, scap = 0;
@@ -268,6 +283,10 @@ struct rbicg_s {
   // last solve's log (host copy) for rbicg_get_log
   std::vector<double> last_log;
   int last_count = 0;
+  // FP32-inner mode: FP64 outer residuals, float right-hand sides and corrections
+  double *r64 = nullptr, *rt64 = nullptr;
+  float *b32 = nullptr, *bt32 = nullptr, *d32 = nullptr, *dt32 = nullptr;
+  int last_dev_status = 0;  // device status code of the last solve_impl run
   std::vector<void *> allocs;
 };
 
@@ -298,6 +317,14 @@ int push_scalars(rbicg_s *h) {
   return 0;
 }
 
+// Cosine cut of the biorthogonalization.  FP32-inner mode raises it so that
+// the attainable inner residual, about eps32 ||I - C C~^H|| <= eps32 (1 + 1/tau),
+// stays ten times below the inner tolerance: tau >= 10 eps32 / inner_tol.
+double svd_tol_eff(const rbicg_s *h) {
+  if (h->vkind != 2) return h->opt.svd_tol;
+  return std::max(h->opt.svd_tol, 10.0 * std::ldexp(1.0, -24) / h->opt.inner_tol);
+}
+
 // bytes per algorithmic iteration (matrix streams + 29 vector streams + C, C~ twice)
 double alg_bytes_iter(const rbicg_s *h, int k) {
   const double ba = (double)h->mat->A.vbytes;
@@ -310,6 +337,7 @@ double alg_bytes_iter(const rbicg_s *h, int k) {
 template <class V> struct VK;
 template <> struct VK<double> { static constexpr int kind = 0; };
 template <> struct VK<cd> { static constexpr int kind = 1; };
+template <> struct VK<float> { static constexpr int kind = 0; };
 
 // Gram G = X^H Y (mx x my, complex): enqueue the kernels and the download
 // into h->hG (no synchronization).  Y is processed in column groups so that
@@ -637,7 +665,7 @@ int job_host3(const rbicg_s *h, CycleJob &J) {
       Gtc[2 * (i + j * m)] = c.real(); Gtc[2 * (i + j * m) + 1] = c.imag();
     }
   std::vector<double> TU(2 * m * m), TUt(2 * m * m);
-  const int p = rbicg_host_biorth(m, Gcc.data(), Gtt.data(), Gtc.data(), h->opt.svd_tol, TU.data(), TUt.data());
+  const int p = rbicg_host_biorth(m, Gcc.data(), Gtt.data(), Gtc.data(), svd_tol_eff(h), TU.data(), TUt.data());
   if (p < 0) {
     J.err = std::string("biorthogonalization failed: ") + rbicg_last_error();
     return -1;
@@ -728,7 +756,8 @@ int host_dots(rbicg_s *h, const V *a0, const V *b0, const V *a1, const V *b1, co
 }
 
 template <class V, class M>
-int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbicg_stats *stp) {
+int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbicg_stats *stp,
+               bool inner = false) {
   rbicg_stats st{};
   const int n = h->n, ld = h->ld, s = h->opt.s, nb = h->nb;
   Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
@@ -738,6 +767,10 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   HIPCHECK(hipEventRecord(ev0, h->st));
   const bool update = h->opt.update && h->opt.k > 0;
   h->have_cyc = false;
+  // FP32 storage (inner solves): every iteration re-projects r_{i-1}, r~_{i-1}
+  // onto the complements of range(C), range(C~) inside k_it1/k_it2 (a no-op in
+  // exact arithmetic; see k_it2)
+  const int rp = (inner && VK<V>::kind == 0 && sizeof(V) == 4 && h->ksys > 0) ? 1 : 0;
   V *r = (V *)h->r, *rt = (V *)h->rt;
   const int ks = h->ksys;
   const V *U = (const V *)h->U, *Ut = (const V *)h->Ut, *C = (const V *)h->C, *Ct = (const V *)h->Ct;
@@ -796,6 +829,11 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     hs->btn = btn;
     hs->iter = total;
     hs->maxit = h->opt.maxit;
+    if (inner) {
+      hs->stag_s = h->opt.s;
+      hs->stag_div = ks > 0 ? 1 : 0;
+      hs->stag_lim = std::sqrt(tol);
+    }
     const bool conv0 = rn <= tol * bn && rtn <= tol * btn;
     hs->done = conv0 ? 1 : 0;
     hs->status = conv0 ? ST_CONVERGED : ST_RUNNING;
@@ -953,14 +991,14 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c], h->st));
           launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
                            ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
-                           h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0);
+                           h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 1], h->st));
           launch_it2<V>(h->st, nb, n, (const V *)h->z, (const V *)h->zt, C, Ct, ks, ld, ptn,
-                        (V *)h->q, (V *)h->qt, h->P1, h->P2, h->S);
+                        (V *)h->q, (V *)h->qt, h->P1, h->P2, h->S, r, rt, rp);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 2], h->st));
           const V *qq = ks > 0 ? (const V *)h->q : (const V *)h->z;
           const V *qqt = ks > 0 ? (const V *)h->qt : (const V *)h->zt;
-          launch_it3<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, qq, qqt, ks, h->P2, h->P3, h->S, h->log, it);
+          launch_it3<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, qq, qqt, ks, h->P2, h->P3, h->S, h->log, it, rp);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 3], h->st));
           pc = 1 - pc;
           ++launched;
@@ -1027,6 +1065,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     // Algorithm 2 step 7: x -= U zeta_c, x~ -= U~ zeta~_c
     if (ks > 0)
       launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
+    if (inner) break;  // the FP64 outer loop checks the true residual
     // true residuals
     launch_residual<V, M>(h->st, A, b, x, (V *)h->t1);
     launch_residual<V, M>(h->st, AH, bt, xt, (V *)h->t2);
@@ -1050,7 +1089,10 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   (void)hipEventDestroy(ev1);
   h->last_log = fulllog;
   h->last_count = (int)(fulllog.size() / LOG_STRIDE);
-  st.status = status == ST_CONVERGED ? RBICG_OK : (status == ST_BREAKDOWN ? RBICG_BREAKDOWN : RBICG_NOT_CONVERGED);
+  h->last_dev_status = status;
+  st.status = (status == ST_CONVERGED || status == ST_STAGNATED)
+                  ? RBICG_OK
+                  : (status == ST_BREAKDOWN ? RBICG_BREAKDOWN : RBICG_NOT_CONVERGED);
   st.iters = total;
   st.restarts = restarts;
   st.reseeds = reseeds;
@@ -1077,9 +1119,116 @@ int install_recycle(rbicg_s *h, const void *Usrc, const void *Utsrc, int k) {
   return 0;
 }
 
+// FP32-inner / FP64-outer iterative refinement (RBICG_F32_IN_F64_OUT).  Outer
+// step: r = b - A x, r~ = b~ - A^H x~ with the FP64 matrix; stop when both
+// relative true residuals are <= tol; else round r, r~ to float, solve
+// A d = r, A^H d~ = r~ with the float RBiCG (FP64 reductions, float matrix
+// values and vectors) to inner_tol relative, and add d, d~ to x, x~ in FP64.
+// The latest cycle's recycle space carries over to the next outer step,
+// re-biorthogonalized (cut svd_tol_eff).  Inner solves also stop at a cycle
+// end without progress (stagnated near the tolerance: the iterate is used;
+// diverged: the correction is discarded and the recycle space dropped); a
+// correction that raises max(||r||/||b||, ||r~||/||b~||) is taken back and
+// the recycle space dropped.
+int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double *xt, double tol,
+                rbicg_stats *stp) {
+  rbicg_stats st{};
+  const int n = h->n;
+  const Sell<double> A = h->mat->A.view<double>(), AH = h->mat->AH.view<double>();
+  hipEvent_t ev0, ev1;
+  HIPCHECK(hipEventCreate(&ev0));
+  HIPCHECK(hipEventCreate(&ev1));
+  HIPCHECK(hipEventRecord(ev0, h->st));
+  cplx d[3];
+  TRY(host_dots<double>(h, b, b, bt, bt, nullptr, nullptr, d));
+  double bn = std::sqrt(std::fabs(d[0].real())), btn = std::sqrt(std::fabs(d[1].real()));
+  if (bn == 0.0) bn = 1.0;
+  if (btn == 0.0) btn = 1.0;
+  const int k_first = h->ksys;
+  int outer = 0, inner_total = 0, cycles = 0, status = RBICG_NOT_CONVERGED;
+  double rel = NAN, relt = NAN;
+  double prev = 0.0;     // residual measure before the last applied correction
+  bool applied = false;  // d32, dt32 hold the last applied correction
+  auto residuals = [&]() -> int {
+    launch_residual<double, double>(h->st, A, b, x, h->r64);
+    launch_residual<double, double>(h->st, AH, bt, xt, h->rt64);
+    TRY(host_dots<double>(h, h->r64, h->r64, h->rt64, h->rt64, nullptr, nullptr, d));
+    rel = std::sqrt(std::fabs(d[0].real())) / bn;
+    relt = std::sqrt(std::fabs(d[1].real())) / btn;
+    return 0;
+  };
+  while (true) {
+    TRY(residuals());
+    if (applied && std::max(rel, relt) > prev) {
+      // the correction made things worse: take it back, drop the recycle space
+      launch_add_f2d(h->st, x, h->d32, -1.0, (size_t)n);
+      launch_add_f2d(h->st, xt, h->dt32, -1.0, (size_t)n);
+      h->ksys = 0;
+      h->have_cyc = false;
+      TRY(residuals());
+    }
+    applied = false;
+    if (rel <= tol && relt <= tol) {
+      status = RBICG_OK;
+      break;
+    }
+    if (outer >= h->opt.max_outer || inner_total >= h->opt.maxit) break;
+    if (h->have_cyc) {
+      void *Us = h->Uc[h->cur], *Uts = h->Utc[h->cur];
+      const int kc = h->kcyc;
+      h->have_cyc = false;
+      TRY((install_recycle<float, float>(h, Us, Uts, kc)));
+    }
+    launch_d2f(h->st, h->r64, h->b32, (size_t)n);
+    launch_d2f(h->st, h->rt64, h->bt32, (size_t)n);
+    launch_fill_zero<float>(h->st, h->d32, (size_t)n);
+    launch_fill_zero<float>(h->st, h->dt32, (size_t)n);
+    rbicg_stats ist{};
+    const int rc = solve_impl<float, float>(h, h->b32, h->bt32, h->d32, h->dt32, h->opt.inner_tol, &ist, true);
+    inner_total += ist.iters;
+    cycles += ist.cycles;
+    st.reseeds += ist.reseeds;
+    if (rc == RBICG_BREAKDOWN) {
+      status = RBICG_BREAKDOWN;
+      break;
+    }
+    if (rc < 0) return rc;
+    ++outer;
+    if (h->last_dev_status == ST_DIVERGED) {
+      // discard the correction; continue without a recycle space
+      h->ksys = 0;
+      h->have_cyc = false;
+      continue;
+    }
+    prev = std::max(rel, relt);
+    applied = true;
+    launch_add_f2d(h->st, x, h->d32, 1.0, (size_t)n);
+    launch_add_f2d(h->st, xt, h->dt32, 1.0, (size_t)n);
+    HIPCHECK(hipGetLastError());
+  }
+  HIPCHECK(hipEventRecord(ev1, h->st));
+  HIPCHECK(hipEventSynchronize(ev1));
+  float ms = 0;
+  HIPCHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  st.status = status;
+  st.iters = inner_total;
+  st.outer_steps = outer;
+  st.cycles = cycles;
+  st.k_used = k_first;
+  st.relres = rel;
+  st.relres_dual = relt;
+  st.time_ms = ms;
+  st.alg_bytes = alg_bytes_iter(h, k_first) * inner_total;
+  if (stp) *stp = st;
+  return status;
+}
+
 template <class F>
 int dispatch(rbicg_s *h, F &&f) {
   if (h->vkind == 0) return f((double *)nullptr, (double *)nullptr);
+  if (h->vkind == 2) return f((float *)nullptr, (float *)nullptr);
   if (h->mat_complex) return f((cd *)nullptr, (cd *)nullptr);
   return f((cd *)nullptr, (double *)nullptr);
 }
@@ -1099,6 +1248,14 @@ int alloc_workspace(rbicg_s *h) {
     TRY(dalloc(h, &h->Rt, 2 * vbytes * h->scap));
     TRY(dalloc(h, &h->Z, 2 * vbytes * (h->scap + 1)));
     TRY(dalloc(h, &h->Zt, 2 * vbytes * (h->scap + 1)));
+  }
+  if (h->vkind == 2) {
+    TRY(dalloc(h, (void **)&h->r64, (size_t)h->ld * sizeof(double)));
+    TRY(dalloc(h, (void **)&h->rt64, (size_t)h->ld * sizeof(double)));
+    TRY(dalloc(h, (void **)&h->b32, (size_t)h->ld * sizeof(float)));
+    TRY(dalloc(h, (void **)&h->bt32, (size_t)h->ld * sizeof(float)));
+    TRY(dalloc(h, (void **)&h->d32, (size_t)h->ld * sizeof(float)));
+    TRY(dalloc(h, (void **)&h->dt32, (size_t)h->ld * sizeof(float)));
   }
   TRY(dalloc(h, (void **)&h->S, sizeof(Scalars)));
   HIPCHECK(hipMemset(h->S, 0, sizeof(Scalars)));
@@ -1150,7 +1307,11 @@ int build_matrix(const rbicg_csr *A, const rbicg_csr *AH, rbicg_mat_s *m) {
 int attach_matrix(rbicg_s *h, rbicg_mat_s *m, bool own) {
   if (!m) return rbicg_fail(RBICG_EINVAL, "null matrix");
   if (m->n != h->n) return rbicg_fail(RBICG_EINVAL, "matrix size %d does not match handle n=%d", m->n, h->n);
-  if (m->complex_vals && h->vkind == 0) return rbicg_fail(RBICG_EINVAL, "complex matrix needs a RBICG_C128 handle");
+  if (m->complex_vals && h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "complex matrix needs a RBICG_C128 handle");
+  if (h->vkind == 2) {
+    TRY(m->A.make_f32(h->st));
+    TRY(m->AH.make_f32(h->st));
+  }
   if (h->own_mat && h->mat && h->mat != m) {
     h->mat->A.release();
     h->mat->AH.release();
@@ -1205,8 +1366,8 @@ extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg
   h->n = A->n;
   h->ld = (A->n + 255) / 256 * 256;
   h->st = (hipStream_t)opt->stream;
-  h->vkind = opt->prec == RBICG_C128 ? 1 : 0;
-  h->vb = h->vkind ? 16 : 8;
+  h->vkind = opt->prec == RBICG_C128 ? 1 : (opt->prec == RBICG_F32_IN_F64_OUT ? 2 : 0);
+  h->vb = h->vkind == 1 ? 16 : (h->vkind == 2 ? 4 : 8);
   h->kcap = opt->k;
   h->scap = opt->s;
   int rc = set_matrix(h, A, AH);
@@ -1248,8 +1409,10 @@ static int check_opts(const rbicg_opts *opt) {
     return rbicg_fail(RBICG_EINVAL, "cycle length s=%d out of range", opt->s);
   if (opt->maxit < 1) return rbicg_fail(RBICG_EINVAL, "maxit must be positive");
   if (opt->chunk < 0 || opt->chunk > 256) return rbicg_fail(RBICG_EINVAL, "chunk out of range");
-  if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128)
-    return rbicg_fail(RBICG_EINVAL, "precision mode %d is not available", (int)opt->prec);
+  if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128 && opt->prec != RBICG_F32_IN_F64_OUT)
+    return rbicg_fail(RBICG_EINVAL, "unknown precision mode %d", (int)opt->prec);
+  if (opt->prec == RBICG_F32_IN_F64_OUT && (!(opt->inner_tol > 0) || opt->inner_tol >= 1 || opt->max_outer < 1))
+    return rbicg_fail(RBICG_EINVAL, "FP32-inner mode needs 0 < inner_tol < 1 and max_outer >= 1");
   return 0;
 }
 
@@ -1261,8 +1424,8 @@ extern "C" int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_hand
   h->n = A->n;
   h->ld = (A->n + 255) / 256 * 256;
   h->st = (hipStream_t)opt->stream;
-  h->vkind = opt->prec == RBICG_C128 ? 1 : 0;
-  h->vb = h->vkind ? 16 : 8;
+  h->vkind = opt->prec == RBICG_C128 ? 1 : (opt->prec == RBICG_F32_IN_F64_OUT ? 2 : 0);
+  h->vb = h->vkind == 1 ? 16 : (h->vkind == 2 ? 4 : 8);
   h->kcap = opt->k;
   h->scap = opt->s;
   int rc = attach_matrix(h, A, false);
@@ -1325,6 +1488,8 @@ extern "C" int rbicg_solve_dual(rbicg_handle h, const void *b, const void *bt, v
                                 double tol, rbicg_stats *st) {
   if (!h || !b || !bt || !x || !xt) return rbicg_fail(RBICG_EINVAL, "null argument");
   if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
+  if (h->vkind == 2)
+    return solve_mixed(h, (const double *)b, (const double *)bt, (double *)x, (double *)xt, tol, st);
   return dispatch(h, [&](auto *vp, auto *mp) {
     using V = std::remove_pointer_t<decltype(vp)>;
     using M = std::remove_pointer_t<decltype(mp)>;
@@ -1393,7 +1558,36 @@ extern "C" int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *
 extern "C" int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, double tol, void *value,
                               double *err_est, rbicg_stats *st) {
   if (!h || !u || !w || !value) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
   void *x = nullptr, *xt = nullptr;
+  if (h->vkind == 2) {
+    // FP64 solution vectors around the FP32-inner solve; FP64 correction term
+    const size_t bytes = (size_t)h->ld * sizeof(double);
+    HIPCHECK(hipMalloc(&x, bytes));
+    if (hipMalloc(&xt, bytes) != hipSuccess) {
+      (void)hipFree(x);
+      return rbicg_fail(RBICG_ENOMEM, "hipMalloc failed");
+    }
+    auto run = [&]() -> int {
+      launch_fill_zero<double>(h->st, (double *)x, (size_t)h->n);
+      launch_fill_zero<double>(h->st, (double *)xt, (size_t)h->n);
+      const int r1 = solve_mixed(h, (const double *)w, (const double *)u, (double *)x, (double *)xt, tol, st);
+      if (r1 < 0 && r1 != RBICG_BREAKDOWN) return r1;
+      launch_residual<double, double>(h->st, h->mat->A.view<double>(), (const double *)w, (const double *)x, h->r64);
+      launch_residual<double, double>(h->st, h->mat->AH.view<double>(), (const double *)u, (const double *)xt, h->rt64);
+      cplx dd[3];
+      TRY(host_dots<double>(h, (const double *)u, (const double *)x, (const double *)xt, h->r64, h->r64, h->r64, dd));
+      const double rnorm = std::sqrt(std::fabs(dd[2].real()));
+      ((double *)value)[0] = dd[0].real() + dd[1].real();
+      TRY(host_dots<double>(h, h->rt64, h->rt64, nullptr, nullptr, nullptr, nullptr, dd));
+      if (err_est) *err_est = rnorm * std::sqrt(std::fabs(dd[0].real()));
+      return r1;
+    };
+    const int rc = run();
+    (void)hipFree(x);
+    (void)hipFree(xt);
+    return rc;
+  }
   const size_t bytes = (size_t)h->ld * h->vb;
   HIPCHECK(hipMalloc(&x, bytes));
   HIPCHECK(hipMalloc(&xt, bytes));

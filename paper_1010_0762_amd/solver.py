@@ -93,7 +93,9 @@ class Solver:
         o.stream = _stream_ptr(self.stream)
         self.opts = o
         self.prec = prec
+        # vectors at the boundary (b, x, ...) and the recycle-basis storage type
         self.dtype = torch.complex128 if prec == "c128" else torch.float64
+        self.basis_dtype = torch.float32 if prec == "mixed" else self.dtype
         h = ct.c_void_p()
         if isinstance(A, DeviceMatrix):
             self.matrix = A
@@ -157,8 +159,9 @@ class Solver:
     def set_recycle(self, U, Ut):
         k = 0 if U is None else U.shape[1]
         if k:
-            Ucm = U.t().contiguous()   # column-major: each column contiguous
-            Utcm = Ut.t().contiguous()
+            # column-major (each column contiguous), in the handle's basis type
+            Ucm = U.t().to(self.basis_dtype).contiguous()
+            Utcm = Ut.t().to(self.basis_dtype).contiguous()
             rc = self.lib.rbicg_set_recycle(self.h, ct.c_void_p(Ucm.data_ptr()),
                                             ct.c_void_p(Utcm.data_ptr()), k)
         else:
@@ -167,7 +170,7 @@ class Solver:
 
     def get_recycle(self, next=False, kcap=64):
         """Returns (U, U~, C, C~) as n x k tensors."""
-        bufs = [torch.zeros((kcap, self.n), dtype=self.dtype, device="cuda") for _ in range(4)]
+        bufs = [torch.zeros((kcap, self.n), dtype=self.basis_dtype, device="cuda") for _ in range(4)]
         k = ct.c_int32()
         rc = self.lib.rbicg_get_recycle(self.h, *[ct.c_void_p(b.data_ptr()) for b in bufs],
                                         kcap, 1 if next else 0, ct.byref(k))

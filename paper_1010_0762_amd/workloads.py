@@ -267,3 +267,25 @@ def csr_from_dense(D: np.ndarray, drop: float = 0.0) -> CSR:
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
     return CSR(n, rowptr.astype(np.int32), cols.astype(np.int32), D[rows, cols].copy())
+
+
+def sine_modes(N: int, dim: int, k: int) -> np.ndarray:
+    """The k lowest Dirichlet sine modes of the unit square/cube grid with edge
+    N (lexicographic order, x fastest), as an n x k float64 array with unit
+    2-norm columns.  Modes are ordered by (a^2 + b^2 + c^2, a, b, c) over the
+    wave numbers (a, b, c) >= 1.  A deterministic smooth basis to install as
+    an externally supplied recycle space (U = U~) at any problem size."""
+    ax = np.arange(1, N + 1) / (N + 1.0)
+    m = min(N, k)
+    waves = sorted((sum(c * c for c in w), w)
+                   for w in (tuple(c + 1 for c in t) for t in np.ndindex(*([m] * dim))))[:k]
+    if len(waves) < k:
+        raise ValueError("k exceeds the number of grid modes")
+    out = np.empty((N ** dim, k))
+    for j, (_, w) in enumerate(waves):
+        comps = [np.sin(np.pi * w[d] * ax) for d in range(dim)]
+        v = comps[dim - 1]
+        for d in range(dim - 2, -1, -1):
+            v = np.kron(v, comps[d])
+        out[:, j] = v / np.linalg.norm(v)
+    return out

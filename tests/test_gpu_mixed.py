@@ -1,0 +1,105 @@
+"""GPU parity of the FP32-inner / FP64-outer mode (RBICG_F32_IN_F64_OUT)
+against the oracle's simulation of the same arithmetic (oracle.mixed_refine:
+float32 storage, float64 element operations and reductions, FP64 outer
+residuals), and, at full size, against an FP64 reference solution.
+
+Bars: final FP64 true residual <= 1e-10 on both sides and solutions within
+1e-6 relative of the oracle's for every system.  Iteration counts: with k = 0
+(plain float BiCG inside the refinement) the inner iterations agree within two.
+Once a recycle space is in use (from the second outer step of the first
+system on) the counts move with rounding: float storage behind the oblique
+projector makes the inner solve sensitive to the space's last bits, and the
+oracle itself changes counts (and sometimes takes its divergence guard or
+takes back a correction) when b moves by 1e-7; there the bar is the sequence
+total within 2x of the oracle's."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1010_0762_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                     "cfg4_convdiff3d_128.json")
+
+
+def _t(v):
+    return torch.as_tensor(np.ascontiguousarray(v), device="cuda", dtype=torch.float64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("N,nsys", [(16, 4), (24, 2)])
+def test_mixed_sequence_matches_oracle(N, nsys):
+    from paper_1010_0762_amd.solver import Solver, DeviceMatrix
+    seq = wl.cfg4_sequence(nsys=nsys, N=N)
+    M = DeviceMatrix(seq.mats[0])
+    S = Solver(M, k=seq.k, s=seq.s, prec="mixed", inner_tol=1e-5, max_outer=30)
+    U = Ut = None
+    tot_g = tot_o = 0
+    for j in range(nsys):
+        x, xt, info, (U, Ut) = oracle.mixed_refine(seq.mats[j], seq.b[j], seq.bt[j], U, Ut,
+                                                   k=seq.k, s=seq.s, tol=1e-10, inner_tol=1e-5)
+        if j:
+            S.update_recycle()
+        xg, xtg, st = S.solve(_t(seq.b[j]), _t(seq.bt[j]), tol=1e-10)
+        print(j, "gpu", st["outer_steps"], st["iters"], "oracle", info["outer"], info["inner_iters"],
+              flush=True)
+        assert st["status"] == 0, (j, st)
+        assert st["relres"] <= 1e-10 and st["relres_dual"] <= 1e-10, (j, st)
+        ref = info["inner_iters"]
+        tot_g += st["iters"]
+        tot_o += ref
+        assert _rel(xg.cpu().numpy(), x) <= 1e-6 and _rel(xtg.cpu().numpy(), xt) <= 1e-6
+    assert tot_g <= 2 * tot_o, (tot_g, tot_o)
+
+
+def test_mixed_plain_inner_matches_oracle_inner():
+    """k = 0: the first inner solve is plain BiCG in float storage; its
+    iteration count equals the oracle's, and the refined result agrees."""
+    from paper_1010_0762_amd.solver import Solver
+    seq = wl.cfg4_sequence(nsys=1, N=20)
+    x, xt, info, _ = oracle.mixed_refine(seq.mats[0], seq.b[0], seq.bt[0], None, None, k=0,
+                                         s=seq.s, tol=1e-10, inner_tol=1e-5, update=False)
+    S = Solver(seq.mats[0], k=0, s=seq.s, prec="mixed", update=False, inner_tol=1e-5)
+    xg, xtg, st = S.solve(_t(seq.b[0]), _t(seq.bt[0]), tol=1e-10)
+    assert st["status"] == 0 and st["outer_steps"] == info["outer"]
+    assert abs(st["iters"] - info["inner_iters"]) <= 2, (st["iters"], info["inner_iters"])
+    assert _rel(xg.cpu().numpy(), x) <= 1e-6
+
+
+def test_mixed_full_size_128():
+    """3D conv-diff on 128^3 (n = 2097152), beta = (50, 25, 10), k = 30,
+    s = 40, inner tolerance 1e-5, outer 1e-10: every system reaches an FP64
+    true residual <= 1e-10 on both sides; system 0 agrees with the FP64 BiCG
+    reference on sampled entries."""
+    from paper_1010_0762_amd.solver import Solver, DeviceMatrix
+    with open(GOLD4) as f:
+        g = json.load(f)
+    seq = wl.cfg4_sequence(nsys=3, N=128)
+    M = DeviceMatrix(seq.mats[0])
+    S = Solver(M, k=seq.k, s=seq.s, prec="mixed", inner_tol=1e-5, max_outer=30)
+    idx = np.asarray(g["sample_index"])
+    for j in range(3):
+        if j:
+            S.update_recycle()
+        x, xt, st = S.solve(_t(seq.b[j]), _t(seq.bt[j]), tol=1e-10)
+        print(j, st["iters"], st["outer_steps"], st["k_used"], st["relres"], st["relres_dual"],
+              flush=True)
+        assert st["status"] == 0, (j, st)
+        assert st["relres"] <= 1e-10 and st["relres_dual"] <= 1e-10, (j, st)
+        assert st["outer_steps"] <= 6
+        if j == 0:
+            xs = x.cpu().numpy()[idx]
+            xts = xt.cpu().numpy()[idx]
+            ex = _rel(xs, np.asarray(g["x_sample"]))
+            ext = _rel(xts, np.asarray(g["xt_sample"]))
+            print("sampled error vs FP64 reference", ex, ext, flush=True)
+            assert ex <= 1e-6 and ext <= 1e-6
