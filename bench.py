@@ -25,6 +25,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dual-system solves/sec + HBM GB/s per RBiCG iter; p50/p99 latency served"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per completed k_it1 launch on this workload, from the FETCH_SIZE
+# and WRITE_SIZE counter runs (each scaled by what the counter reads for a
+# 512 MiB device copy), valid only for the kernel source they were taken on
+TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "ab9e20df143befa5", "bytes_per_launch": 99.83e6}
+
+
+def traffic_k_it1():
+    """Counter-measured HBM bytes per k_it1 launch, or None once the kernel
+    source differs from the one the counters were taken on."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1010_0762_amd", "csrc", "kernels.hip")
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if digest != TRAFFIC_K_IT1["kernels_hip_sha256_16"]:
+        return None
+    return TRAFFIC_K_IT1["bytes_per_launch"]
 
 
 def parse():
@@ -35,8 +54,9 @@ def parse():
     ap.add_argument("--N", type=int, default=64, help="grid edge")
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile-timed", type=int, default=1,
-                    help="1: time the iteration kernels with HIP events inside the timed region")
+    ap.add_argument("--profile-timed", type=int, default=16,
+                    help="p > 0: time the iteration kernels of every p-th chunk of iterations "
+                         "with HIP events inside the timed region (0: off)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
@@ -91,7 +111,7 @@ def kernel_at_k20(args, seq, mats, b, bt):
     avg = {name: prof[f"{key}_ms"] / max(prof[f"{key}_n"], 1) * 1e3
            for name, key in (("spmv_restrict", "spmv"), ("expand_sigma", "expand"),
                              ("update_norms", "update"))}
-    gbs = prof["spmv_bytes"] / (avg["spmv_restrict"] * 1e-6) / 1e9
+    gbs = prof["spmv_bytes_total"] / (prof["spmv_ms"] * 1e-3) / 1e9
     per_iter = dt / st["iters"]
     return {"k_used": st["k_used"], "iters": st["iters"], "relres": st["relres"],
             "kernel_avg_us": {k: round(v, 2) for k, v in avg.items()},
@@ -121,7 +141,7 @@ def main():
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     xts = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     S = Solver(mats[0], k=seq.k, s=seq.s, prec="f64", chunk=args.chunk,
-               profile=bool(args.profile_timed))
+               profile=args.profile_timed)
 
     def step():
         S.set_recycle(None, None)
@@ -172,12 +192,18 @@ def main():
     roof = None
     if prof["spmv_n"] > 0:
         avg_ms = prof["spmv_ms"] / prof["spmv_n"]
-        achieved = prof["spmv_bytes"] / (avg_ms * 1e-3) / 1e9
+        bytes_per_launch = prof["spmv_bytes_total"] / prof["spmv_n"]
+        achieved = prof["spmv_bytes_total"] / (prof["spmv_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_iter_spmv (direction update + A p, A^H p~ + restriction)",
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_k_it1(),
+                "kernel": "k_it1 (direction update + A p, A^H p~ + restriction partials)",
                 "avg_us": round(avg_ms * 1e3, 2),
-                "alg_bytes_per_launch": prof["spmv_bytes"]}
+                "alg_bytes_per_launch": round(bytes_per_launch),
+                "launches": prof["spmv_n"]}
+    kernel_gbs = {name: round(prof[f"{key}_bytes_total"] / max(prof[f"{key}_ms"], 1e-12) * 1e-6, 1)
+                  for name, key in (("spmv_restrict", "spmv"), ("expand_sigma", "expand"),
+                                    ("update_norms", "update"))}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
     out = {
         "metric": METRIC,
@@ -206,6 +232,7 @@ def main():
         "kernel_avg_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in kernels.items()},
         "kernel_share": {k: round(v[0] / max(1e-9, sum(u[0] for u in kernels.values())), 3)
                          for k, v in kernels.items()},
+        "kernel_alg_gbs": kernel_gbs,
         "profiled_timed_region": bool(args.profile_timed),
         "roofline": roof,
         "kernel_at_k20": k20,

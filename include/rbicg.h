@@ -97,8 +97,9 @@ typedef struct {
  *   max_outer    outer refinement steps of RBICG_F32_IN_F64_OUT
  *   stream       hipStream_t to run on (NULL: the null stream)
  *   chunk        iterations launched between convergence polls (0: auto)
- *   profile      1: time every iteration kernel with HIP events (read with
- *                rbicg_profile); adds event records between the launches */
+ *   profile      p > 0: time the iteration kernels of every p-th chunk of
+ *                iterations with HIP events recorded between the launches
+ *                (read with rbicg_profile); 0: off */
 typedef struct {
   int32_t k, s, maxit, max_restarts, update;
   double svd_tol;
@@ -147,10 +148,13 @@ int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next);
 /* Kernel timing of the iteration kernels accumulated while opts.profile is
  * set: out[0..5] = total ms and launch count of (1) the fused direction
  * update + paired SpMV + restriction kernel, (2) the expansion + (p~, q)
- * kernel, (3) the recurrence update + norms kernel; out[6] = algorithmic bytes
- * of one launch of kernel (1) with the current recycle dimension, out[7] =
- * algorithmic bytes of one iteration.  reset = 1 clears the counters after
- * reading.  out: host array of 8 doubles. */
+ * kernel, (3) the recurrence update + norms kernel (HIP events recorded
+ * before and after each launch of the sampled chunks); out[6] =
+ * algorithmic bytes of one launch of kernel (1) with the current recycle
+ * dimension, out[7] = algorithmic bytes of one iteration; out[8..10] = total
+ * algorithmic bytes of the timed launches of kernels (1)-(3) (each launch
+ * counted with the recycle dimension it ran with).  reset = 1 clears the
+ * counters after reading.  out: host array of 11 doubles. */
 int rbicg_profile(rbicg_handle h, int32_t reset, double *out);
 
 /* Create a handle for matrix A (problem statement, Sec. 1).  AH may be NULL,

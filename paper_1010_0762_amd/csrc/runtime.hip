@@ -251,6 +251,8 @@ struct rbicg_s {
   hipEvent_t sev[2] = {nullptr, nullptr};
   double prof_ms[3] = {0, 0, 0};
   long prof_n[3] = {0, 0, 0};
+  double prof_bytes[3] = {0, 0, 0};  // algorithmic bytes of the timed launches
+  long prof_chunks = 0;              // chunks launched since the handle was made
   // iteration vectors (x, x~ are the caller's)
   void *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr}, *pt[2] = {nullptr, nullptr};
   void *z = nullptr, *zt = nullptr, *q = nullptr, *qt = nullptr, *t1 = nullptr, *t2 = nullptr;
@@ -325,12 +327,28 @@ double svd_tol_eff(const rbicg_s *h) {
   return std::max(h->opt.svd_tol, 10.0 * std::ldexp(1.0, -24) / h->opt.inner_tol);
 }
 
-// bytes per algorithmic iteration (matrix streams + 29 vector streams + C, C~ twice)
+// Algorithmic bytes of one launch of each iteration kernel (matrix values of
+// the type the kernels read, int32 column indices, one slice pointer per
+// row-slice rounded to one per row): k_it1 reads r, r~, p, p~ and C, C~ rows
+// and writes p, p~, z, z~ (plus r_{i-1}, r~_{i-1}, z, z~ into the cycle rings
+// when updating); k_it2 reads z, z~, C, C~, p~ and writes q, q~ (with k = 0:
+// reads z and p~ only; re-projection adds r, r~ read and written); k_it3 reads
+// x, x~, r, r~, p, p~, q, q~ and writes x, x~, r, r~.
+void kernel_bytes(const rbicg_s *h, int k, double out[3]) {
+  const double ba = h->vkind == 2 ? 4.0 : (double)h->mat->A.vbytes;
+  const double nnz = (double)h->mat->A.nnz, n = h->n, vb = (double)h->vb;
+  const bool cap = h->opt.update && h->opt.k > 0;
+  const bool rp = h->vkind == 2 && k > 0;
+  out[0] = 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (8.0 + 2.0 * k + (cap ? 4.0 : 0.0)) * n * vb;
+  out[1] = (k > 0 ? 5.0 + 2.0 * k + (rp ? 4.0 : 0.0) : 2.0) * n * vb;
+  out[2] = 12.0 * n * vb;
+}
+
+// bytes per algorithmic iteration: the three kernels' total
 double alg_bytes_iter(const rbicg_s *h, int k) {
-  const double ba = (double)h->mat->A.vbytes;
-  const double nnz = (double)h->mat->A.nnz;
-  const double n = h->n;
-  return 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (29.0 + 4.0 * k) * n * (double)h->vb;
+  double kb[3];
+  kernel_bytes(h, k, kb);
+  return kb[0] + kb[1] + kb[2];
 }
 
 // ---------------------------------------------------------- typed helpers
@@ -929,12 +947,15 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       known = std::max(known, completed);
       if (f.prof) {
         const int eb = f.slot * 4 * f.chunk;
+        double kb[3];
+        kernel_bytes(h, ks, kb);
         for (int c = 0; c < completed - f.chunk_start && c < f.chunk; ++c)
           for (int kk = 0; kk < 3; ++kk) {
             float ms = 0;
             HIPCHECK(hipEventElapsedTime(&ms, h->pev[eb + 4 * c + kk], h->pev[eb + 4 * c + kk + 1]));
             h->prof_ms[kk] += ms;
             h->prof_n[kk] += 1;
+            h->prof_bytes[kk] += kb[kk];
           }
       }
       return 0;
@@ -974,7 +995,9 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         if (update) chunk = std::min(chunk, s - (in_run % s));
         chunk = std::min(chunk, h->opt.maxit - launched);
         const int chunk_start = launched;
-        const bool prof = h->opt.profile && (int)h->pev.size() >= 8 * chunk;
+        // profiling: time every opts.profile-th chunk (events between launches)
+        const bool prof = h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
+                          (h->prof_chunks++ % h->opt.profile) == 0;
         const int eb = (slot_next % 2) * 4 * chunk;
         for (int c = 0; c < chunk; ++c) {
           const int it = launched + 1;
@@ -1450,15 +1473,16 @@ extern "C" int rbicg_profile(rbicg_handle h, int32_t reset, double *out) {
     out[2 * k] = h->prof_ms[k];
     out[2 * k + 1] = (double)h->prof_n[k];
   }
-  const double n = h->n, b = (double)h->vb, ba = h->mat->A.vbytes, nnz = (double)h->mat->A.nnz;
-  const int k = h->ksys;
-  const double cap = (h->opt.update && h->opt.k > 0) ? 4.0 : 0.0;
-  out[6] = 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (8.0 + 2.0 * k + cap) * n * b;
-  out[7] = alg_bytes_iter(h, k);
+  double kb[3];
+  kernel_bytes(h, h->ksys, kb);
+  out[6] = kb[0];
+  out[7] = kb[0] + kb[1] + kb[2];
+  for (int kk = 0; kk < 3; ++kk) out[8 + kk] = h->prof_bytes[kk];
   if (reset)
     for (int kk = 0; kk < 3; ++kk) {
       h->prof_ms[kk] = 0;
       h->prof_n[kk] = 0;
+      h->prof_bytes[kk] = 0;
     }
   return RBICG_OK;
 }

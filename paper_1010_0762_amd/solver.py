@@ -88,7 +88,8 @@ class Solver:
         o.update = 1 if update else 0
         o.svd_tol, o.seed, o.prec = svd_tol, seed, _PREC[prec]
         o.inner_tol, o.max_outer, o.chunk = inner_tol, max_outer, chunk
-        o.profile = 1 if profile else 0
+        # profile: False/0 off, True/1 every chunk, p > 1 every p-th chunk
+        o.profile = int(profile)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         o.stream = _stream_ptr(self.stream)
         self.opts = o
@@ -181,11 +182,12 @@ class Solver:
     def profile(self, reset=False):
         """Per-kernel timing (rbicg_profile): dict with ms/launch counts and
         the algorithmic bytes of one SpMV-kernel launch and of one iteration."""
-        out = np.zeros(8)
+        out = np.zeros(11)
         _lib.check(self.lib.rbicg_profile(self.h, 1 if reset else 0, _lib.dptr(out)), "rbicg_profile")
         return {"spmv_ms": out[0], "spmv_n": int(out[1]), "expand_ms": out[2],
                 "expand_n": int(out[3]), "update_ms": out[4], "update_n": int(out[5]),
-                "spmv_bytes": out[6], "iter_bytes": out[7]}
+                "spmv_bytes": out[6], "iter_bytes": out[7], "spmv_bytes_total": out[8],
+                "expand_bytes_total": out[9], "update_bytes_total": out[10]}
 
     def log(self):
         """Per-iteration log of the last solve as an (iters, 10) float64 array."""
