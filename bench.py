@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per completed k_it1 launch on this workload, from the FETCH_SIZE
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
 # 512 MiB device copy), valid only for the kernel source they were taken on
-TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "ab9e20df143befa5", "bytes_per_launch": 99.83e6}
+TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "dd11e851f864965b", "bytes_per_launch": 99.90e6}
 
 
 def traffic_k_it1():
@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--no-shifted", action="store_true",
+                    help="skip the batched shifted-pair leg (48^3, 8 shifts, 6 sweeps)")
     ap.add_argument("--no-k20", action="store_true",
                     help="skip the extra kernel timing with an injected 20-vector recycle space")
     return ap.parse_args()
@@ -120,6 +122,45 @@ def kernel_at_k20(args, seq, mats, b, bt):
             "us_per_iter": round(per_iter * 1e6, 2),
             "alg_bytes_per_iter": prof["iter_bytes"],
             "effective_gbs_per_iter": round(prof["iter_bytes"] / per_iter / 1e9, 1)}
+
+
+def shifted_leg(args):
+    """IRKA-style shifted pairs (Algorithm 3 steps 2-3, E = I) on the 48^3
+    anisotropic operator A = -L_kappa - 0.1 I (n = 110592): 6 sweeps of 8 shifts
+    in conjugate pairs, k = 20 shared recycle space (updated from the shift of
+    smallest modulus), primal warm starts; one pass over the 6 sweeps from an
+    empty recycle space is timed after one untimed pass."""
+    import torch
+    from paper_1010_0762_amd import workloads as wl
+    from paper_1010_0762_amd.solver import Solver
+    A, b, c, sweeps = wl.cfg3_shifts(nsweeps=6, N=48)
+    bt = torch.as_tensor(b.astype(np.complex128), device="cuda")
+    ct = torch.as_tensor(c.astype(np.complex128), device="cuda")
+
+    def one_pass(S):
+        S.set_recycle(None, None)
+        X = torch.zeros((8, A.n), dtype=torch.complex128, device="cuda")
+        its, batch_ms = [], 0.0
+        for sig in sweeps:
+            Xt = torch.zeros_like(X)
+            X, Xt, sts = S.solve_shifted(sig, bt, ct, X, Xt, tol=1e-8)
+            its.append([st["iters"] for st in sts])
+            ok = all(st["status"] == 0 for st in sts)
+            if not ok:
+                raise RuntimeError(f"shifted solve failed: {sts}")
+        return its
+
+    S = Solver(A, k=20, s=40, prec="c128")
+    one_pass(S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = one_pass(S)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    npairs = 8 * len(sweeps)
+    return {"workload": "shifted_aniso3d_48^3_6sweeps_8shifts_k20_s40_tol1e-8", "n": A.n,
+            "pair_solves_per_s": round(npairs / dt, 2), "ms_per_pass": round(dt * 1e3, 2),
+            "iters_per_sweep": its, "precision": "complex FP64"}
 
 
 def main():
@@ -205,6 +246,7 @@ def main():
                   for name, key in (("spmv_restrict", "spmv"), ("expand_sigma", "expand"),
                                     ("update_norms", "update"))}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
+    shifted = None if args.no_shifted else shifted_leg(args)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -236,6 +278,7 @@ def main():
         "profiled_timed_region": bool(args.profile_timed),
         "roofline": roof,
         "kernel_at_k20": k20,
+        "shifted_pairs": shifted,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(seq),
     }
     print(json.dumps(out), flush=True)

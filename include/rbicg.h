@@ -222,15 +222,23 @@ int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *count);
 
 /* Shifted dual pairs of IRKA (Algorithm 3 steps 2-3 with E = I):
  *   (sigma_i I - A) X_i = b,   (sigma_i I - A)^H Xt_i = c,   i < S (S <= 16)
- * for a complex (RBICG_C128) handle.  All shifts share the handle's recycle
- * space U, U~; each shift's C_sigma = sigma U - A U and C~_sigma = conj(sigma)
- * U~ - A^H U~ are biorthogonalized by a per-shift k x k rotation, so one
- * contraction against [U~, A^H U~] and [U, A U] serves all shifts in each
- * iteration.  sigma: host array of S complex values (re, im).  b, c: device
- * n-vectors; X, Xt: device n x S column-major, initial guesses on entry.
- * When opts.update is set the recycle space for the next sweep is built from
- * the cycles of shift index update_from (< 0: the shift of smallest |sigma|).
- * st: host array of S stats (may be NULL). */
+ * for a complex (RBICG_C128) handle on A (real or complex; the shift is
+ * applied on the fly, no shifted matrix is formed).  All shifts share one
+ * recycle space: the one built by the last update (the previous sweep's), else
+ * the installed U, U~ (k <= 32).  Each shift's C_sigma = sigma U - A U and
+ * C~_sigma = conj(sigma) U~ - A^H U~ is biorthogonalized on its own (Sec. 4.3,
+ * from Grams of the shared basis), which is a per-shift k x k map, so one FP64
+ * MFMA contraction of [U~, A^H U~, U, A U] against all shifts' vectors serves
+ * every shift in each iteration; the shifts iterate in lock step in one set of
+ * launches (a shift stops on its own test).  When opts.update is set, shift
+ * update_from (< 0: the one of smallest |sigma|) is solved as a single pair
+ * with the cycle-wise update of Sec. 4, which builds the recycle space for the
+ * next sweep; every other shift runs in the batch.  No restarts in the batch:
+ * a batched shift whose true residual misses tol reports NOT_CONVERGED.
+ * sigma: host array of S complex values (re, im).  b, c: device n-vectors;
+ * X, Xt: device n x S column-major (leading dimension n), initial guesses on
+ * entry, solutions on exit.  st: host array of S stats (required).  Returns 0
+ * when every shift converged, else the first failure code. */
 int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const void *b,
                         const void *c, void *X, void *Xt, double tol, int32_t update_from,
                         rbicg_stats *st);

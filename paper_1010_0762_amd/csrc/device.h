@@ -44,6 +44,10 @@ struct Scalars {
 // Wave-sliced ELL: rows grouped in slices of 64 (one wavefront, one row per
 // lane); entry j of row r sits at sliceptr[r/64] + j*64 + r%64.  Padding
 // entries point at their own row with value 0.
+//
+// A view may carry a shift: with shifted = 1 it stands for sigma I - A
+// (sigma = shr + i shi), applied by the kernels on the fly, so the shifted
+// systems of IRKA (Algorithm 3) need no second matrix.
 template <class M>
 struct Sell {
   int n;
@@ -51,6 +55,40 @@ struct Sell {
   const int *sliceptr;  // nslices + 1 offsets (multiples of 64)
   const int *col;
   const M *val;
+  int shifted;
+  double shr, shi;
 };
 
 #define LOG_STRIDE 10
+
+// ---------------------------------------------------------------- shifts
+// Batched shifted pairs (sigma_i I - A) x_i = b, (sigma_i I - A)^H x~_i = c:
+// per-shift scalars and small per-shift data of one sweep.
+#define SHMAX 16   // shifts per batch
+#define KSH 32     // recycle dimension in the shifted path (2k basis columns <= 64)
+#define SH_LOG 8   // per shift per iteration: alpha (re, im), beta (re, im), rho (re, im), ||r||, ||r~||
+
+struct ShScalars {
+  double tol;
+  int S, k2, maxit, all_done;
+  int done[SHMAX], status[SHMAX], iter[SHMAX], p[SHMAX];
+  double bn[SHMAX], btn[SHMAX];
+  double sig[2 * SHMAX];
+  // per shift: zeta_i, zeta~_i of the current iteration and the running
+  // zeta_c, zeta~_c (complex, p_sigma entries)
+  double zeta[SHMAX][2 * KSH], zetat[SHMAX][2 * KSH];
+  double zc[SHMAX][2 * KSH], zct[SHMAX][2 * KSH];
+};
+
+// Per-shift coefficient matrices of a sweep (complex, interleaved):
+//   K  (p x 2k, row-major)  zeta  = K w,   w  = [U~, A^H U~]^H z
+//   Kt (p x 2k, row-major)  zeta~ = Kt w~, w~ = [U, A U]^H z~
+//   L  (2k x p, row-major)  y  = L zeta:   q  = z  - [U, A U] y
+//   Lt (2k x p, row-major)  y~ = Lt zeta~: q~ = z~ - [U~, A^H U~] y~
+//   T  (k x p, row-major)   x  -= U (T zeta_c),  Tt likewise for x~
+#define SH_MAT (2 * KSH * KSH)  // complex entries reserved per matrix
+struct ShCoef {
+  double K[SHMAX][2 * SH_MAT], Kt[SHMAX][2 * SH_MAT];
+  double L[SHMAX][2 * SH_MAT], Lt[SHMAX][2 * SH_MAT];
+  double T[SHMAX][2 * SH_MAT], Tt[SHMAX][2 * SH_MAT];
+};

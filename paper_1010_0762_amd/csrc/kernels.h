@@ -70,3 +70,20 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
 template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
                    int ld);
+
+// ---- batched shifted pairs (see kernels.hip) ----
+int sh_blocks(int n);      // blocks of k_sh3 (partials of P3)
+int sh_sub_blocks(int n);  // blocks of k_sh_sub (partials of P2)
+template <class M>
+void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
+                const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,
+                const double *P3, int nb3, ShScalars *Sh, double *rec, int it, int first);
+void launch_sh_coef(hipStream_t st, const double *G, ShScalars *Sh, const ShCoef *Co, cd *Y,
+                    cd *Yt, cd *Yx, cd *Yxt, int mode);
+void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
+                   const cd *Zin, cd *Out, int ld, const cd *Ptn, double *P2, int nbe);
+void launch_sh3(hipStream_t st, int nb3, int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
+                const cd *Pn, const cd *Ptn, const cd *Q, const cd *Qt, const double *P2,
+                int nbe, double *P3, ShScalars *Sh, double *rec, int it, int upd);
+void launch_sh_fin(hipStream_t st, const double *P3, int nb3, ShScalars *Sh, double *rec, int it,
+                   int first);

@@ -161,6 +161,28 @@ __device__ __forceinline__ double divide(double a, double b) { return a / b; }
 __device__ __forceinline__ cd divide(cd a, cd b) { return cdiv(a, b); }
 
 // ------------------------------------------------------------ SpMV helpers
+// (sigma I - A) y from A y for a shifted view: sigma y_row - acc
+template <class M, class T>
+__device__ __forceinline__ T shift_apply(const Sell<M> &A, T acc, T yrow);
+template <>
+__device__ __forceinline__ double shift_apply<double, double>(const Sell<double> &A, double acc,
+                                                              double yrow) {
+  return A.shifted ? A.shr * yrow - acc : acc;
+}
+template <>
+__device__ __forceinline__ double shift_apply<float, double>(const Sell<float> &A, double acc,
+                                                             double yrow) {
+  return A.shifted ? A.shr * yrow - acc : acc;
+}
+template <>
+__device__ __forceinline__ cd shift_apply<double, cd>(const Sell<double> &A, cd acc, cd yrow) {
+  return A.shifted ? cd{A.shr, A.shi} * yrow - acc : acc;
+}
+template <>
+__device__ __forceinline__ cd shift_apply<cd, cd>(const Sell<cd> &A, cd acc, cd yrow) {
+  return A.shifted ? cd{A.shr, A.shi} * yrow - acc : acc;
+}
+
 template <class V, class M, class T>
 __device__ __forceinline__ T spmv_dir(const Sell<M> &A, int row, const V *r, const V *p, T beta) {
   const int slice = row >> 6, lane = row & 63;
@@ -171,6 +193,7 @@ __device__ __forceinline__ T spmv_dir(const Sell<M> &A, int row, const V *r, con
     const T pc = up(down<V>(up(r[c]) + beta * up(p[c])));
     acc += up(A.val[e]) * pc;
   }
+  if (A.shifted) acc = shift_apply<M, T>(A, acc, up(down<V>(up(r[row]) + beta * up(p[row]))));
   return acc;
 }
 
@@ -180,6 +203,7 @@ __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
   T acc = zero<T>();
   for (int e = beg + lane; e < end; e += RBICG_WAVE) acc += up(A.val[e]) * up(x[A.col[e]]);
+  if (A.shifted) acc = shift_apply<M, T>(A, acc, up(x[row]));
   return acc;
 }
 
@@ -529,15 +553,6 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_residual(Sell<M> A, const V *b,
   out[row] = down<V>(v);
 }
 
-// Y[:, c] = A X[:, c] for c = blockIdx.y
-template <class V, class M>
-__global__ __launch_bounds__(RBICG_BLOCK) void k_spmm(Sell<M> A, const V *X, V *Y, int ld) {
-  using T = typename Ar<V>::T;
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  if (row >= A.n) return;
-  const size_t off = (size_t)blockIdx.y * ld;
-  Y[off + row] = down<V>(spmv_plain<V, M, T>(A, row, X + off));
-}
 
 // x += sx * U c1; r += sr * C c1; xt += sxt * Ut c2; rt += srt * Ct c2 with
 // coefficients coef = [c1 (k values), c2 (k values)] (doubles, ND per value).
@@ -869,7 +884,375 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V 
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j)
-    if (j < nc) Y[(size_t)(c0 + j) * ld + row] = down<V>(acc[j]);
+    if (j < nc) {
+      if (A.shifted) acc[j] = shift_apply<M, T>(A, acc[j], up(X[(size_t)(c0 + j) * ld + row]));
+      Y[(size_t)(c0 + j) * ld + row] = down<V>(acc[j]);
+    }
+}
+
+// ========================================================= shifted pairs
+// Batched IRKA-style pairs (sigma_s I - A) x_s = b, (sigma_s I - A)^H x~_s = c
+// for S shifts sharing one recycle space (Algorithm 3 steps 2-3 with E = I).
+// The batch vectors are n x S column-major (leading dimension ld), one column
+// per shift.  One iteration of Algorithm 2 for all shifts is
+//   k_sh1      per-shift stopping test and beta; p_s = r_s + beta_s p_s and
+//              z_s = sigma_s p_s - A p_s (dual: conj(sigma_s), A^H), each
+//              matrix entry read once per row for all shifts;
+//   Gram       w = [U~, A^H U~]^H [z_1..z_S], w~ = [U, A U]^H [z~_1..z~_S]
+//              (k_gram_mfma: one FP64-MFMA contraction of the shared basis
+//              against all shifts);
+//   k_sh_coef  zeta_s = K_s w_s, y_s = L_s zeta_s (per-shift rotations);
+//   k_sh_sub   q_s = z_s - [U, A U] y_s (MFMA tall-skinny product) and the
+//              partials of sigma_s = (p~_s, q_s);
+//   k_sh3      alpha_s, zeta_c += alpha zeta, x, x~, r, r~ updates and the
+//              partials of ||r_s||, ||r~_s||, (r~_s, r_s).
+// Shifts that have stopped are skipped.  Per-shift scalars are logged per
+// iteration in rec[(it * SHMAX + s) * SH_LOG + ...].
+
+// Per-shift stopping test of iteration it-1 and beta_{it-1}; act[s] = 1 for
+// the shifts that go on.  Every block computes the same values (all read the
+// same partials in the same order); block 0 records them.
+__device__ void sh_prologue(const double *P3, int nb, ShScalars *Sh, double *rec, int it,
+                            int first, double *tmp, double *red, cd *betas, int *act) {
+  const int S = Sh->S;
+  breduce(P3, nb, 4 * S, tmp, red);
+  const bool b0 = blockIdx.x == 0;
+  if (threadIdx.x < S) {
+    const int s = threadIdx.x;
+    int a = 0;
+    cd beta = {0.0, 0.0};
+    if (!Sh->done[s]) {
+      const double rn = sqrt(red[4 * s]), rtn = sqrt(red[4 * s + 1]);
+      const cd rho = {red[4 * s + 2], red[4 * s + 3]};
+      double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
+      if (b0) {
+        Rm1[4] = rho.x;
+        Rm1[5] = rho.y;
+        Rm1[6] = rn;
+        Rm1[7] = rtn;
+      }
+      int st = ST_RUNNING;
+      if (rn <= Sh->tol * Sh->bn[s] && rtn <= Sh->tol * Sh->btn[s]) st = ST_CONVERGED;
+      else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
+      else if (it > Sh->maxit) st = ST_MAXIT;
+      if (st != ST_RUNNING) {
+        if (b0) {
+          Sh->status[s] = st;
+          Sh->iter[s] = it - 1;
+          Sh->done[s] = 1;
+        }
+      } else {
+        a = 1;
+        if (!first) {
+          const double *Rm2 = rec + ((size_t)(it - 2) * SHMAX + s) * SH_LOG;
+          beta = cdiv(rho, cd{Rm2[4], Rm2[5]});
+        }
+        if (b0) {
+          double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
+          R0[2] = beta.x;
+          R0[3] = beta.y;
+        }
+      }
+    }
+    act[s] = a;
+    betas[s] = beta;
+  }
+  __syncthreads();
+  if (b0 && threadIdx.x == 0) {
+    int any = 0;
+    for (int s = 0; s < S; ++s) any |= act[s];
+    if (!any) Sh->all_done = 1;
+  }
+}
+
+template <class M>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sh1(Sell<M> A, Sell<M> AH, int ld,
+                                                     const cd *__restrict__ R,
+                                                     const cd *__restrict__ Rt,
+                                                     const cd *__restrict__ P,
+                                                     const cd *__restrict__ Pt, cd *__restrict__ Pn,
+                                                     cd *__restrict__ Ptn, cd *__restrict__ Z,
+                                                     cd *__restrict__ Zt, const double *P3,
+                                                     int nb3, ShScalars *Sh, double *rec, int it,
+                                                     int first) {
+  __shared__ double tmp[RBICG_BLOCK];
+  __shared__ double red[4 * SHMAX];
+  __shared__ cd betas[SHMAX];
+  __shared__ int act[SHMAX];
+  if (Sh->all_done) return;
+  sh_prologue(P3, nb3, Sh, rec, it, first, tmp, red, betas, act);
+  const int S = Sh->S;
+  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (row >= A.n) return;
+  for (int s = 0; s < S; ++s) {
+    if (!act[s]) continue;
+    const size_t o = (size_t)s * ld;
+    const cd sig = {Sh->sig[2 * s], Sh->sig[2 * s + 1]};
+    const cd beta = betas[s], betac = cj(beta);
+    {
+      const cd prow = R[o + row] + beta * P[o + row];
+      Pn[o + row] = prow;
+      const int slice = row >> 6, lane = row & 63;
+      const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
+      cd acc = {0.0, 0.0};
+      for (int e = beg + lane; e < end; e += RBICG_WAVE) {
+        const int c = A.col[e];
+        acc += up(A.val[e]) * (R[o + c] + beta * P[o + c]);
+      }
+      Z[o + row] = sig * prow - acc;
+    }
+    {
+      const cd prow = Rt[o + row] + betac * Pt[o + row];
+      Ptn[o + row] = prow;
+      const int slice = row >> 6, lane = row & 63;
+      const int beg = AH.sliceptr[slice], end = AH.sliceptr[slice + 1];
+      cd acc = {0.0, 0.0};
+      for (int e = beg + lane; e < end; e += RBICG_WAVE) {
+        const int c = AH.col[e];
+        acc += up(AH.val[e]) * (Rt[o + c] + betac * Pt[o + c]);
+      }
+      Zt[o + row] = cj(sig) * prow - acc;
+    }
+  }
+}
+
+// Per-shift coefficients (one block).  G: Gram of [U~, A^H U~, U, A U]
+// (rows, 2 k2 of them) against [v_1..v_S, v~_1..v~_S] (my = 2S columns),
+// complex row-major; w_s = G[0..k2)[s], w~_s = G[k2..2k2)[S + s].
+//   mode 0 (iteration): zeta_s = K_s w_s -> Sh->zeta, Y[:, s] = L_s zeta_s
+//                       (dual likewise); stopped shifts get Y = 0;
+//   mode 1 (start):     g_s = K_s w_s: Y[:, s] = L_s g_s (r -= [U, AU] Y) and
+//                       Yx[:, s] = -T_s g_s (x -= U Yx), dual likewise;
+//   mode 2 (finish):    Yx[:, s] = T_s zeta_c,s (x -= U Yx), dual likewise.
+// Y, Yt: k2 x S column-major; Yx, Yxt: (k2/2) x S column-major.
+__global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, ShScalars *Sh,
+                                                 const ShCoef *__restrict__ Co, cd *Y, cd *Yt,
+                                                 cd *Yx, cd *Yxt, int mode) {
+  __shared__ cd zs[SHMAX][KSH], zst[SHMAX][KSH];
+  const int S = Sh->S, k2 = Sh->k2, k = k2 / 2, my = 2 * S;
+  if (mode == 0 && Sh->all_done) return;
+  // phase 1: zeta (or g) per shift
+  for (int t = threadIdx.x; t < 2 * S * KSH; t += blockDim.x) {
+    const int side = t / (S * KSH), s = (t / KSH) % S, l = t % KSH;
+    const int p = Sh->p[s];
+    cd v = {0.0, 0.0};
+    if (l < p && !(mode == 0 && Sh->done[s])) {
+      if (mode == 2) {
+        v = side ? cd{Sh->zct[s][2 * l], Sh->zct[s][2 * l + 1]} : cd{Sh->zc[s][2 * l], Sh->zc[s][2 * l + 1]};
+      } else {
+        const double *Km = side ? Co->Kt[s] : Co->K[s];
+        for (int j = 0; j < k2; ++j) {
+          const int gi = side ? k2 + j : j, gj = side ? S + s : s;
+          const cd w = {G[2 * ((size_t)gi * my + gj)], G[2 * ((size_t)gi * my + gj) + 1]};
+          v += cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]} * w;
+        }
+        if (mode == 0) {
+          double *zo = side ? Sh->zetat[s] : Sh->zeta[s];
+          zo[2 * l] = v.x;
+          zo[2 * l + 1] = v.y;
+        }
+      }
+    }
+    if (side) zst[s][l] = v;
+    else zs[s][l] = v;
+  }
+  __syncthreads();
+  // phase 2: basis coefficients
+  if (mode != 2) {
+    for (int t = threadIdx.x; t < 2 * S * k2; t += blockDim.x) {
+      const int side = t / (S * k2), s = (t / k2) % S, j = t % k2;
+      const int p = Sh->p[s];
+      const double *Lm = side ? Co->Lt[s] : Co->L[s];
+      cd v = {0.0, 0.0};
+      for (int l = 0; l < p; ++l)
+        v += cd{Lm[2 * (j * p + l)], Lm[2 * (j * p + l) + 1]} * (side ? zst[s][l] : zs[s][l]);
+      (side ? Yt : Y)[(size_t)s * k2 + j] = v;
+    }
+  }
+  if (mode != 0) {
+    const double sg = mode == 1 ? -1.0 : 1.0;
+    for (int t = threadIdx.x; t < 2 * S * k; t += blockDim.x) {
+      const int side = t / (S * k), s = (t / k) % S, i = t % k;
+      const int p = Sh->p[s];
+      const double *Tm = side ? Co->Tt[s] : Co->T[s];
+      cd v = {0.0, 0.0};
+      for (int l = 0; l < p; ++l)
+        v += cd{Tm[2 * (i * p + l)], Tm[2 * (i * p + l) + 1]} * (side ? zst[s][l] : zs[s][l]);
+      (side ? Yxt : Yx)[(size_t)s * k + i] = sg * v;
+    }
+  }
+}
+
+// Out[:, c] = Zin[:, c] - sum_l X_l W[l, c] for c < p <= 16 (W: m x p complex,
+// column-major), on FP64 MFMA (Y^T = W^T X^T, one wave per 16 rows, waves
+// stride over the row tiles).  With Ptn, also per-block partials of
+// (Ptn_c, Out_c) into P2[block * p + c] (complex).  Out may alias Zin.
+__global__ __launch_bounds__(256) void k_sh_sub(int n, ColList X, int m, const cd *W, int p,
+                                                const cd *Zin, cd *Out, int ld, const cd *Ptn,
+                                                double *P2) {
+  __shared__ cd part[4][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  cd sp[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sp[v] = cd{0.0, 0.0};
+  const int ntiles = (n + 15) / 16;
+  for (int tile = blockIdx.x * 4 + w; tile < ntiles; tile += gridDim.x * 4) {
+    const int row = tile * 16 + li;
+    d4 ar = d4{0.0, 0.0, 0.0, 0.0}, ai = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      const int kcol = k0 + lk;
+      double xr = 0.0, xi = 0.0;
+      if (kcol < m && row < n) {
+        const cd v = ((const cd *)X.p[kcol])[row];
+        xr = v.x;
+        xi = v.y;
+      }
+      const int c = li;
+      double wr = 0.0, wi = 0.0;
+      if (kcol < m && c < p) {
+        const cd wv = W[(size_t)c * m + kcol];
+        wr = wv.x;
+        wi = wv.y;
+      }
+      ar = mfma(wr, xr, ar);
+      ar = mfma(-wi, xi, ar);
+      ai = mfma(wr, xi, ai);
+      ai = mfma(wi, xr, ai);
+    }
+    if (row < n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = lk + 4 * v;
+        if (c < p) {
+          const size_t o = (size_t)c * ld + row;
+          const cd z = Zin[o];
+          const cd q = {z.x - ar[v], z.y - ai[v]};
+          Out[o] = q;
+          if (Ptn) sp[v] += cj(Ptn[o]) * q;
+        }
+      }
+    }
+  }
+  if (!Ptn) return;
+  // sum over the 16 rows (li) of each lane group, then over the waves
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      sp[v].x += __shfl_xor(sp[v].x, off, 64);
+      sp[v].y += __shfl_xor(sp[v].y, off, 64);
+    }
+  if (li == 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[w][lk + 4 * v] = sp[v];
+  __syncthreads();
+  if (threadIdx.x < p) {
+    cd t = {0.0, 0.0};
+    for (int ww = 0; ww < 4; ++ww) t += part[ww][threadIdx.x];
+    P2[2 * ((size_t)blockIdx.x * p + threadIdx.x)] = t.x;
+    P2[2 * ((size_t)blockIdx.x * p + threadIdx.x) + 1] = t.y;
+  }
+}
+
+// upd = 1: alpha_s = rho_{it-1} / sigma_s (sigma from the P2 partials of
+// k_sh_sub), zeta_c updates, x, x~, r, r~ updates; then (also with upd = 0)
+// per-block partials of ||r_s||^2, ||r~_s||^2, (r~_s, r_s) into P3.
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sh3(int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
+                                                     const cd *Pn, const cd *Ptn, const cd *Q,
+                                                     const cd *Qt, const double *P2, int nbe,
+                                                     double *P3, ShScalars *Sh, double *rec,
+                                                     int it, int upd) {
+  __shared__ double tmp[RBICG_BLOCK];
+  __shared__ double red[2 * SHMAX];
+  __shared__ cd alphas[SHMAX];
+  __shared__ int act[SHMAX];
+  __shared__ double lds[(RBICG_BLOCK / 64) * 4 * SHMAX];
+  if (upd && Sh->all_done) return;
+  const int S = Sh->S;
+  if (upd) {
+    breduce(P2, nbe, 2 * S, tmp, red);
+    if (threadIdx.x < S) {
+      const int s = threadIdx.x;
+      int a = 0;
+      cd al = {0.0, 0.0};
+      if (!Sh->done[s]) {
+        const cd sigma = {red[2 * s], red[2 * s + 1]};
+        if (abs2(sigma) == 0.0 || !isfin(sigma)) {
+          if (blockIdx.x == 0) {
+            Sh->status[s] = ST_BREAKDOWN;
+            Sh->iter[s] = it - 1;
+            Sh->done[s] = 1;
+          }
+        } else {
+          const double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
+          al = cdiv(cd{Rm1[4], Rm1[5]}, sigma);
+          a = 1;
+          if (blockIdx.x == 0) {
+            double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
+            R0[0] = al.x;
+            R0[1] = al.y;
+            const cd alc = cj(al);
+            for (int l = 0; l < Sh->p[s]; ++l) {
+              const cd z = cd{Sh->zc[s][2 * l], Sh->zc[s][2 * l + 1]} +
+                           al * cd{Sh->zeta[s][2 * l], Sh->zeta[s][2 * l + 1]};
+              const cd zt = cd{Sh->zct[s][2 * l], Sh->zct[s][2 * l + 1]} +
+                            alc * cd{Sh->zetat[s][2 * l], Sh->zetat[s][2 * l + 1]};
+              Sh->zc[s][2 * l] = z.x;
+              Sh->zc[s][2 * l + 1] = z.y;
+              Sh->zct[s][2 * l] = zt.x;
+              Sh->zct[s][2 * l + 1] = zt.y;
+            }
+          }
+        }
+      }
+      act[s] = a;
+      alphas[s] = al;
+    }
+    __syncthreads();
+  }
+  double acc[4 * SHMAX];
+#pragma unroll
+  for (int t = 0; t < 4 * SHMAX; ++t) acc[t] = 0.0;
+  const int stride = gridDim.x * RBICG_BLOCK;
+  for (int row = blockIdx.x * RBICG_BLOCK + threadIdx.x; row < n; row += stride) {
+#pragma unroll
+    for (int s = 0; s < SHMAX; ++s) {
+      if (s >= S) break;
+      const size_t o = (size_t)s * ld + row;
+      cd rv = R[o], rtv = Rt[o];
+      if (upd && act[s]) {
+        const cd al = alphas[s], alc = cj(al);
+        X[o] = X[o] + al * Pn[o];
+        Xt[o] = Xt[o] + alc * Ptn[o];
+        rv = rv - al * Q[o];
+        rtv = rtv - alc * Qt[o];
+        R[o] = rv;
+        Rt[o] = rtv;
+      }
+      acc[4 * s] += abs2(rv);
+      acc[4 * s + 1] += abs2(rtv);
+      const cd rho = cj(rtv) * rv;
+      acc[4 * s + 2] += rho.x;
+      acc[4 * s + 3] += rho.y;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4 * SHMAX; ++t)
+    if (t < 4 * S) wput(lds, 4 * SHMAX, t, acc[t]);
+  __syncthreads();
+  bstore(lds, 4 * SHMAX, RBICG_BLOCK / 64, 4 * S, P3);
+}
+
+// Stopping test after the last launched iteration (one block).
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sh_fin(const double *P3, int nb3, ShScalars *Sh,
+                                                        double *rec, int it, int first) {
+  __shared__ double tmp[RBICG_BLOCK];
+  __shared__ double red[4 * SHMAX];
+  __shared__ cd betas[SHMAX];
+  __shared__ int act[SHMAX];
+  if (Sh->all_done) return;
+  sh_prologue(P3, nb3, Sh, rec, it, first, tmp, red, betas, act);
 }
 
 // =============================================================== launchers
@@ -1015,6 +1398,42 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
   const unsigned nb = (unsigned)((n + 63) / 64);
   hipLaunchKernelGGL((k_tsgemm_mfma<V>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
 }
+
+// ------------------------------------------------------- shifted launchers
+int sh_blocks(int n) { return std::max(1, std::min(256, (int)nblk((size_t)n))); }
+int sh_sub_blocks(int n) { return std::max(1, std::min(256, ((n + 15) / 16 + 3) / 4)); }
+
+template <class M>
+void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
+                const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,
+                const double *P3, int nb3, ShScalars *Sh, double *rec, int it, int first) {
+  hipLaunchKernelGGL((k_sh1<M>), dim3(nblk(A.n)), dim3(RBICG_BLOCK), 0, st, A, AH, ld, R, Rt, P,
+                     Pt, Pn, Ptn, Z, Zt, P3, nb3, Sh, rec, it, first);
+}
+void launch_sh_coef(hipStream_t st, const double *G, ShScalars *Sh, const ShCoef *Co, cd *Y,
+                    cd *Yt, cd *Yx, cd *Yxt, int mode) {
+  hipLaunchKernelGGL(k_sh_coef, dim3(1), dim3(256), 0, st, G, Sh, Co, Y, Yt, Yx, Yxt, mode);
+}
+void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
+                   const cd *Zin, cd *Out, int ld, const cd *Ptn, double *P2, int nbe) {
+  hipLaunchKernelGGL(k_sh_sub, dim3(nbe), dim3(256), 0, st, n, X, m, W, p, Zin, Out, ld, Ptn, P2);
+}
+void launch_sh3(hipStream_t st, int nb3, int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
+                const cd *Pn, const cd *Ptn, const cd *Q, const cd *Qt, const double *P2,
+                int nbe, double *P3, ShScalars *Sh, double *rec, int it, int upd) {
+  hipLaunchKernelGGL(k_sh3, dim3(nb3), dim3(RBICG_BLOCK), 0, st, n, ld, X, Xt, R, Rt, Pn, Ptn, Q,
+                     Qt, P2, nbe, P3, Sh, rec, it, upd);
+}
+void launch_sh_fin(hipStream_t st, const double *P3, int nb3, ShScalars *Sh, double *rec, int it,
+                   int first) {
+  hipLaunchKernelGGL(k_sh_fin, dim3(1), dim3(RBICG_BLOCK), 0, st, P3, nb3, Sh, rec, it, first);
+}
+template void launch_sh1<double>(hipStream_t, const Sell<double> &, const Sell<double> &, int,
+                                 const cd *, const cd *, const cd *, const cd *, cd *, cd *,
+                                 cd *, cd *, const double *, int, ShScalars *, double *, int, int);
+template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, int, const cd *,
+                             const cd *, const cd *, const cd *, cd *, cd *, cd *, cd *,
+                             const double *, int, ShScalars *, double *, int, int);
 
 #define INST_VM(V, M)                                                                        \
   template void launch_it1<V, M>(hipStream_t, int, const Sell<M> &, const Sell<M> &,         \

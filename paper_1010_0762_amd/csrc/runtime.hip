@@ -13,6 +13,7 @@
 #include <future>
 #include <memory>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -73,6 +74,9 @@ struct DevSell {
     s.col = col;
     if constexpr (std::is_same<M, float>::value) s.val = val32;
     else s.val = (const M *)val;
+    s.shifted = 0;
+    s.shr = 0.0;
+    s.shi = 0.0;
     return s;
   }
   void release() {
@@ -234,6 +238,32 @@ struct rbicg_mat_s {
   DevSell A, AH;
 };
 
+// Workspace of rbicg_solve_shifted, allocated on the first call (n x S batch
+// vectors, the shared basis [U, A U], [U~, A^H U~], Gram buffers, scalars).
+struct ShiftWs {
+  int Scap = 0, kcap = 0;
+  std::vector<void *> allocs;
+  cd *R = nullptr, *Rt = nullptr, *P[2] = {}, *Pt[2] = {}, *Z = nullptr, *Zt = nullptr;
+  cd *Q = nullptr, *Qt = nullptr, *X = nullptr, *Xt = nullptr;
+  cd *BU = nullptr, *BUt = nullptr;
+  cd *Y = nullptr, *Yt = nullptr, *Yx = nullptr, *Yxt = nullptr;
+  double *gpart = nullptr, *G = nullptr, *P2 = nullptr, *P3 = nullptr, *rec = nullptr;
+  size_t gpart_bytes = 0;
+  int reccap = 0;
+  ShScalars *Sh = nullptr, *hSh = nullptr;
+  ShCoef *Co = nullptr, *hCo = nullptr;
+  double *hG = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~ShiftWs() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (hSh) (void)hipHostFree(hSh);
+    if (hCo) (void)hipHostFree(hCo);
+    if (hG) (void)hipHostFree(hG);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // ====================================================================== handle
 struct rbicg_s {
   rbicg_opts opt{};
@@ -289,6 +319,11 @@ struct rbicg_s {
   double *r64 = nullptr, *rt64 = nullptr;
   float *b32 = nullptr, *bt32 = nullptr, *d32 = nullptr, *dt32 = nullptr;
   int last_dev_status = 0;  // device status code of the last solve_impl run
+  // implicit shift: while set, the handle's matrix stands for sigma I - A
+  // (used for the shifted pairs of IRKA; A^H becomes conj(sigma) I - A^H)
+  bool shifted = false;
+  cplx shift = 0.0;
+  ShiftWs *sw = nullptr;  // workspace of the batched shifted solves
   std::vector<void *> allocs;
 };
 
@@ -349,6 +384,27 @@ double alg_bytes_iter(const rbicg_s *h, int k) {
   double kb[3];
   kernel_bytes(h, k, kb);
   return kb[0] + kb[1] + kb[2];
+}
+
+// views of the handle's matrix and of its conjugate transpose, with the
+// handle's implicit shift attached
+template <class M> Sell<M> view_A(const rbicg_s *h) {
+  Sell<M> v = h->mat->A.view<M>();
+  if (h->shifted) {
+    v.shifted = 1;
+    v.shr = h->shift.real();
+    v.shi = h->shift.imag();
+  }
+  return v;
+}
+template <class M> Sell<M> view_AH(const rbicg_s *h) {
+  Sell<M> v = h->mat->AH.view<M>();
+  if (h->shifted) {
+    v.shifted = 1;
+    v.shr = h->shift.real();
+    v.shi = -h->shift.imag();
+  }
+  return v;
 }
 
 // ---------------------------------------------------------- typed helpers
@@ -650,7 +706,7 @@ int job_stage2(rbicg_s *h, CycleJob &J) {
   if (m > 0) {
     TRY(tsgemm<V>(h, J.XU, J.Wc, m, h->Ua, 4));
     TRY(tsgemm<V>(h, J.XUt, J.Wtc, m, h->Uta, 5));
-    Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
+    Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
     launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
     launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
     HIPCHECK(hipGetLastError());
@@ -739,7 +795,7 @@ int biorth_sync(rbicg_s *h, int m) {
   HIPCHECK(hipEventCreateWithFlags(&J.ev, hipEventDisableTiming));
   int rc = 0;
   if (m > 0) {
-    Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
+    Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
     launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
     launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
     std::vector<const void *> X;
@@ -778,7 +834,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
                bool inner = false) {
   rbicg_stats st{};
   const int n = h->n, ld = h->ld, s = h->opt.s, nb = h->nb;
-  Sell<M> A = h->mat->A.view<M>(), AH = h->mat->AH.view<M>();
+  Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
   hipEvent_t ev0, ev1;
   HIPCHECK(hipEventCreate(&ev0));
   HIPCHECK(hipEventCreate(&ev1));
@@ -930,12 +986,20 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       return 0;
     };
 
-    // read the scalars of the oldest chunk in flight
+    // read the scalars of the oldest chunk in flight; while it runs, move the
+    // cycle jobs along (each stage change is noticed at once instead of once
+    // per chunk, so a job's stages do not wait for the iterations)
     auto read_one = [&]() -> int {
       if (flight.empty()) return 0;
       const Flight f = flight.front();
       flight.pop_front();
-      HIPCHECK(hipEventSynchronize(h->sev[f.slot]));
+      while (true) {
+        const hipError_t q = hipEventQuery(h->sev[f.slot]);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) return rbicg_fail(RBICG_EHIP, "chunk event: %s", hipGetErrorString(q));
+        if (update && !jobs.empty()) TRY(advance(false));
+        std::this_thread::yield();
+      }
       const Scalars &sc = h->hS[f.slot];
       if (sc.done) {
         done = 1;
@@ -1248,6 +1312,342 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
   return status;
 }
 
+// =========================================================== shifted pairs
+int shift_ws(rbicg_s *h, int S) {
+  if (h->sw && h->sw->Scap >= S) return 0;
+  delete h->sw;
+  h->sw = new ShiftWs();
+  ShiftWs &w = *h->sw;
+  w.Scap = SHMAX;
+  w.kcap = std::min(h->kcap, KSH);
+  auto al = [&](void **p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) return rbicg_fail(RBICG_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    w.allocs.push_back(*p);
+    return 0;
+  };
+  const size_t vb = (size_t)h->ld * sizeof(cd) * SHMAX;
+  void **vecs[] = {(void **)&w.R, (void **)&w.Rt, (void **)&w.P[0], (void **)&w.P[1], (void **)&w.Pt[0],
+                   (void **)&w.Pt[1], (void **)&w.Z, (void **)&w.Zt, (void **)&w.Q, (void **)&w.Qt,
+                   (void **)&w.X, (void **)&w.Xt};
+  for (void **v : vecs) TRY(al(v, vb));
+  const size_t bb = (size_t)h->ld * sizeof(cd) * std::max(1, 2 * w.kcap);
+  TRY(al((void **)&w.BU, bb));
+  TRY(al((void **)&w.BUt, bb));
+  TRY(al((void **)&w.Y, sizeof(cd) * 2 * KSH * SHMAX));
+  TRY(al((void **)&w.Yt, sizeof(cd) * 2 * KSH * SHMAX));
+  TRY(al((void **)&w.Yx, sizeof(cd) * KSH * SHMAX));
+  TRY(al((void **)&w.Yxt, sizeof(cd) * KSH * SHMAX));
+  const int mx = std::max(1, 4 * w.kcap), my = std::max(mx, 2 * SHMAX);
+  w.gpart_bytes = (size_t)gram_chunks(h->n) * mx * my * 2 * sizeof(double);
+  TRY(al((void **)&w.gpart, w.gpart_bytes));
+  TRY(al((void **)&w.G, (size_t)mx * my * 2 * sizeof(double)));
+  TRY(al((void **)&w.P2, (size_t)sh_sub_blocks(h->n) * SHMAX * 2 * sizeof(double)));
+  TRY(al((void **)&w.P3, (size_t)sh_blocks(h->n) * SHMAX * 4 * sizeof(double)));
+  w.reccap = h->opt.maxit + 2;
+  TRY(al((void **)&w.rec, (size_t)w.reccap * SHMAX * SH_LOG * sizeof(double)));
+  TRY(al((void **)&w.Sh, sizeof(ShScalars)));
+  TRY(al((void **)&w.Co, sizeof(ShCoef)));
+  HIPCHECK(hipHostMalloc((void **)&w.hSh, 2 * sizeof(ShScalars), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&w.hCo, sizeof(ShCoef), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&w.hG, (size_t)mx * my * 2 * sizeof(double), hipHostMallocDefault));
+  for (auto &e : w.ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return 0;
+}
+
+// G = X^H Y (mx <= 128 columns of X) into w.G on the device, row-major
+// (i, j) complex; my must fit one column group of the Gram kernel.
+int shift_gram(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y) {
+  ShiftWs &w = *h->sw;
+  const int mx = (int)X.size(), my = (int)Y.size();
+  if (mx < 1 || mx > 128 || my < 1 || my > gram_group(mx, 1))
+    return rbicg_fail(RBICG_EINVAL, "shifted Gram shape %d x %d unsupported", mx, my);
+  const int nchunks = gram_chunks(h->n);
+  if ((size_t)nchunks * mx * my * 2 * sizeof(double) > w.gpart_bytes)
+    return rbicg_fail(RBICG_EINVAL, "shifted Gram workspace too small");
+  ColList xl{}, yl{};
+  for (int i = 0; i < mx; ++i) xl.p[i] = X[i];
+  for (int j = 0; j < my; ++j) yl.p[j] = Y[j];
+  launch_gram<cd>(h->st, h->n, xl, mx, yl, my, w.gpart, w.G, nchunks);
+  HIPCHECK(hipGetLastError());
+  return 0;
+}
+
+inline cd *bcol(cd *base, int j, const rbicg_s *h) { return base + (size_t)j * h->ld; }
+
+// C = B S with S = [sigma I; -I] (2k x k): entries of S^H M S for a 2k x 2k
+// Hermitian-form block M (host, row-major complex), as a k x k column-major
+// interleaved array for rbicg_host_biorth.
+static void shifted_form(const std::vector<cplx> &M, int ldm, int r0, int c0, int k, cplx a, cplx b,
+                         std::vector<double> &out) {
+  // out(i, j) = sum_{u, v} conj(S_a(u, i)) M(r0 + u, c0 + v) S_b(v, j),
+  // S_a = [a I; -I], S_b = [b I; -I]
+  out.assign(2 * (size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      const cplx m11 = M[(size_t)(r0 + i) * ldm + c0 + j], m12 = M[(size_t)(r0 + i) * ldm + c0 + k + j];
+      const cplx m21 = M[(size_t)(r0 + k + i) * ldm + c0 + j], m22 = M[(size_t)(r0 + k + i) * ldm + c0 + k + j];
+      const cplx v = std::conj(a) * m11 * b - std::conj(a) * m12 - m21 * b + m22;
+      out[2 * (i + (size_t)j * k)] = v.real();
+      out[2 * (i + (size_t)j * k) + 1] = v.imag();
+    }
+}
+
+template <class M>
+int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, const cd *c, cd *Xc,
+                       cd *Xtc, double tol, int update_from, rbicg_stats *stats) {
+  const int n = h->n, ld = h->ld;
+  std::vector<cplx> sig(S);
+  for (int s = 0; s < S; ++s) sig[s] = cplx(sigma[2 * s], sigma[2 * s + 1]);
+  const bool update = h->opt.update && h->opt.k > 0;
+  int u0 = -1;
+  if (update) {
+    u0 = update_from;
+    if (u0 < 0) {
+      u0 = 0;
+      for (int s = 1; s < S; ++s)
+        if (std::abs(sig[s]) < std::abs(sig[u0])) u0 = s;
+    }
+    if (u0 >= S) return rbicg_fail(RBICG_EINVAL, "update_from %d out of range", u0);
+  }
+  TRY(shift_ws(h, S));
+  ShiftWs &w = *h->sw;
+  const cd *Usrc = (const cd *)(h->have_cyc ? h->Uc[h->cur] : h->U);
+  const cd *Utsrc = (const cd *)(h->have_cyc ? h->Utc[h->cur] : h->Ut);
+  int k = h->have_cyc ? h->kcyc : h->ksys;
+  if (k > w.kcap) return rbicg_fail(RBICG_EINVAL, "recycle dimension %d exceeds %d for shifted solves", k, w.kcap);
+  const int k2 = 2 * k;
+  h->shifted = false;
+  // shared basis [U, A U] and [U~, A^H U~]
+  if (k > 0) {
+    HIPCHECK(hipMemcpy2DAsync(w.BU, ld * sizeof(cd), Usrc, ld * sizeof(cd), n * sizeof(cd), k, hipMemcpyDeviceToDevice, h->st));
+    HIPCHECK(hipMemcpy2DAsync(w.BUt, ld * sizeof(cd), Utsrc, ld * sizeof(cd), n * sizeof(cd), k, hipMemcpyDeviceToDevice, h->st));
+    launch_spmm<cd, M>(h->st, view_A<M>(h), w.BU, bcol(w.BU, k, h), ld, k);
+    launch_spmm<cd, M>(h->st, view_AH<M>(h), w.BUt, bcol(w.BUt, k, h), ld, k);
+    HIPCHECK(hipGetLastError());
+  }
+  // batch = every shift except the update shift
+  std::vector<int> bidx;
+  for (int s = 0; s < S; ++s)
+    if (s != u0) bidx.push_back(s);
+  const int Sb = (int)bidx.size();
+  for (int s = 0; s < S; ++s) stats[s] = rbicg_stats{};
+  hipEvent_t ev0, ev1;
+  HIPCHECK(hipEventCreate(&ev0));
+  HIPCHECK(hipEventCreate(&ev1));
+  if (Sb > 0) {
+    HIPCHECK(hipEventRecord(ev0, h->st));
+    ShScalars *hs = &w.hSh[0];
+    std::memset(hs, 0, sizeof(ShScalars));
+    hs->tol = tol;
+    hs->S = Sb;
+    hs->k2 = k2;
+    hs->maxit = h->opt.maxit;
+    // per-shift biorthogonalization from the basis Grams (Sec. 4.3 for
+    // C_s = sigma_s U - A U, C~_s = conj(sigma_s) U~ - A^H U~)
+    if (k > 0) {
+      std::vector<const void *> Xl;
+      for (int j = 0; j < k2; ++j) Xl.push_back(bcol(w.BU, j, h));
+      for (int j = 0; j < k2; ++j) Xl.push_back(bcol(w.BUt, j, h));
+      // in column groups that fit the Gram kernel; group j0 is row-major m4 x gg
+      const int m4 = 2 * k2, grp = gram_group(m4, 1);
+      for (int j0 = 0; j0 < m4; j0 += grp) {
+        const int gg = std::min(grp, m4 - j0);
+        std::vector<const void *> Yg(Xl.begin() + j0, Xl.begin() + j0 + gg);
+        TRY(shift_gram(h, Xl, Yg));
+        HIPCHECK(hipMemcpyAsync(w.hG + 2 * (size_t)m4 * j0, w.G, (size_t)m4 * gg * 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, h->st));
+        TRY(sync(h));
+      }
+      std::vector<cplx> G((size_t)m4 * m4);
+      for (int j0 = 0; j0 < m4; j0 += grp) {
+        const int gg = std::min(grp, m4 - j0);
+        const double *blk = w.hG + 2 * (size_t)m4 * j0;
+        for (int i = 0; i < m4; ++i)
+          for (int j = 0; j < gg; ++j)
+            G[(size_t)i * m4 + j0 + j] = cplx(blk[2 * ((size_t)i * gg + j)], blk[2 * ((size_t)i * gg + j) + 1]);
+      }
+      std::memset(w.hCo, 0, sizeof(ShCoef));
+      std::vector<double> Gcc, Gtt, Gtc, TU(2 * (size_t)k * k), TUt(2 * (size_t)k * k);
+      for (int j = 0; j < Sb; ++j) {
+        const cplx sg = sig[bidx[j]], sgc = std::conj(sg);
+        // C^H C with C = BU [sg I; -I]; C~^H C~ with C~ = BUt [conj(sg) I; -I];
+        // C~^H C (rows of BUt against columns of BU)
+        shifted_form(G, m4, 0, 0, k, sg, sg, Gcc);
+        shifted_form(G, m4, k2, k2, k, sgc, sgc, Gtt);
+        shifted_form(G, m4, k2, 0, k, sgc, sg, Gtc);
+        const int p = rbicg_host_biorth(k, Gcc.data(), Gtt.data(), Gtc.data(), svd_tol_eff(h), TU.data(), TUt.data());
+        if (p < 0) return rbicg_fail(RBICG_EINVAL, "shift %d: biorthogonalization failed: %s", bidx[j], rbicg_last_error());
+        hs->p[j] = p;
+        auto tu = [&](int i, int l) { return cplx(TU[2 * (i + (size_t)l * k)], TU[2 * (i + (size_t)l * k) + 1]); };
+        auto tut = [&](int i, int l) { return cplx(TUt[2 * (i + (size_t)l * k)], TUt[2 * (i + (size_t)l * k) + 1]); };
+        auto put = [](double *m, size_t idx, cplx v) { m[2 * idx] = v.real(); m[2 * idx + 1] = v.imag(); };
+        // K = TUt^H [sg I, -I]  (zeta = K [U~, A^H U~]^H z), Kt = TU^H [conj(sg) I, -I]
+        // L = [sg I; -I] TU, Lt = [conj(sg) I; -I] TUt, T = TU, Tt = TUt
+        for (int l = 0; l < p; ++l)
+          for (int i = 0; i < k; ++i) {
+            put(w.hCo->K[j], (size_t)l * k2 + i, std::conj(tut(i, l)) * sg);
+            put(w.hCo->K[j], (size_t)l * k2 + k + i, -std::conj(tut(i, l)));
+            put(w.hCo->Kt[j], (size_t)l * k2 + i, std::conj(tu(i, l)) * sgc);
+            put(w.hCo->Kt[j], (size_t)l * k2 + k + i, -std::conj(tu(i, l)));
+            put(w.hCo->L[j], (size_t)i * p + l, sg * tu(i, l));
+            put(w.hCo->L[j], (size_t)(k + i) * p + l, -tu(i, l));
+            put(w.hCo->Lt[j], (size_t)i * p + l, sgc * tut(i, l));
+            put(w.hCo->Lt[j], (size_t)(k + i) * p + l, -tut(i, l));
+            put(w.hCo->T[j], (size_t)i * p + l, tu(i, l));
+            put(w.hCo->Tt[j], (size_t)i * p + l, tut(i, l));
+          }
+      }
+      HIPCHECK(hipMemcpyAsync(w.Co, w.hCo, sizeof(ShCoef), hipMemcpyHostToDevice, h->st));
+    }
+    // norms of b, c
+    cplx d[3];
+    TRY(host_dots<cd>(h, b, b, c, c, nullptr, nullptr, d));
+    double bn = std::sqrt(std::fabs(d[0].real())), cn = std::sqrt(std::fabs(d[1].real()));
+    if (bn == 0.0) bn = 1.0;
+    if (cn == 0.0) cn = 1.0;
+    for (int j = 0; j < Sb; ++j) {
+      hs->bn[j] = bn;
+      hs->btn[j] = cn;
+      hs->sig[2 * j] = sig[bidx[j]].real();
+      hs->sig[2 * j + 1] = sig[bidx[j]].imag();
+    }
+    HIPCHECK(hipMemcpyAsync(w.Sh, hs, sizeof(ShScalars), hipMemcpyHostToDevice, h->st));
+    // x_{-1} and r_{-1} = b - (sigma I - A) x_{-1} per shift (eq. minusXR before the projection)
+    for (int j = 0; j < Sb; ++j) {
+      const int s = bidx[j];
+      HIPCHECK(hipMemcpyAsync(bcol(w.X, j, h), Xc + (size_t)s * n, n * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+      HIPCHECK(hipMemcpyAsync(bcol(w.Xt, j, h), Xtc + (size_t)s * n, n * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+      h->shifted = true;
+      h->shift = sig[s];
+      launch_residual<cd, M>(h->st, view_A<M>(h), b, bcol(w.X, j, h), bcol(w.R, j, h));
+      launch_residual<cd, M>(h->st, view_AH<M>(h), c, bcol(w.Xt, j, h), bcol(w.Rt, j, h));
+      h->shifted = false;
+      launch_fill_zero<cd>(h->st, bcol(w.P[0], j, h), (size_t)n);
+      launch_fill_zero<cd>(h->st, bcol(w.Pt[0], j, h), (size_t)n);
+    }
+    const int nb3 = sh_blocks(n), nbe = sh_sub_blocks(n);
+    ColList BUl{}, BUtl{};
+    for (int j = 0; j < k2; ++j) {
+      BUl.p[j] = bcol(w.BU, j, h);
+      BUtl.p[j] = bcol(w.BUt, j, h);
+    }
+    std::vector<const void *> Xg, Yr, Yz;
+    for (int j = 0; j < k2; ++j) Xg.push_back(bcol(w.BUt, j, h));
+    for (int j = 0; j < k2; ++j) Xg.push_back(bcol(w.BU, j, h));
+    for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.R, j, h));
+    for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.Rt, j, h));
+    for (int j = 0; j < Sb; ++j) Yz.push_back(bcol(w.Z, j, h));
+    for (int j = 0; j < Sb; ++j) Yz.push_back(bcol(w.Zt, j, h));
+    if (k > 0) {
+      // eq. minusXR: g = C~'^H r_{-1}; x += U' g, r -= C' g (dual likewise)
+      TRY(shift_gram(h, Xg, Yr));
+      launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 1);
+      launch_sh_sub(h->st, n, BUl, k2, w.Y, Sb, w.R, w.R, ld, nullptr, nullptr, nbe);
+      launch_sh_sub(h->st, n, BUtl, k2, w.Yt, Sb, w.Rt, w.Rt, ld, nullptr, nullptr, nbe);
+      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nullptr, nullptr, nbe);
+      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nullptr, nullptr, nbe);
+    }
+    launch_sh3(h->st, nb3, n, ld, w.X, w.Xt, w.R, w.Rt, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+               w.P3, w.Sh, w.rec, 0, 0);
+    HIPCHECK(hipGetLastError());
+    // iterations: chunks of 8, two in flight, one scalar download per chunk
+    int launched = 0, pc = 0, slot = 0;
+    const int chunk = h->opt.chunk > 0 ? h->opt.chunk : 8;
+    std::deque<int> flight;
+    bool all_done = false;
+    while (true) {
+      while (!all_done && flight.size() < 2 && launched < h->opt.maxit) {
+        const int cnt = std::min(chunk, h->opt.maxit - launched);
+        for (int t = 0; t < cnt; ++t) {
+          const int it = launched + 1;
+          launch_sh1<M>(h->st, view_A<M>(h), view_AH<M>(h), ld, w.R, w.Rt, w.P[pc], w.Pt[pc], w.P[1 - pc],
+                        w.Pt[1 - pc], w.Z, w.Zt, w.P3, nb3, w.Sh, w.rec, it, it == 1 ? 1 : 0);
+          if (k > 0) {
+            TRY(shift_gram(h, Xg, Yz));
+            launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 0);
+          }
+          launch_sh_sub(h->st, n, BUl, k > 0 ? k2 : 0, w.Y, Sb, w.Z, w.Q, ld, w.Pt[1 - pc], w.P2, nbe);
+          launch_sh_sub(h->st, n, BUtl, k > 0 ? k2 : 0, w.Yt, Sb, w.Zt, w.Qt, ld, nullptr, nullptr, nbe);
+          launch_sh3(h->st, nb3, n, ld, w.X, w.Xt, w.R, w.Rt, w.P[1 - pc], w.Pt[1 - pc], w.Q, w.Qt, w.P2, nbe,
+                     w.P3, w.Sh, w.rec, it, 1);
+          pc = 1 - pc;
+          ++launched;
+        }
+        launch_sh_fin(h->st, w.P3, nb3, w.Sh, w.rec, launched + 1, 0);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(&w.hSh[1 + 0 * slot], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost, h->st));
+        HIPCHECK(hipEventRecord(w.ev[slot], h->st));
+        flight.push_back(slot);
+        slot = 1 - slot;
+      }
+      if (flight.empty()) break;
+      const int sl = flight.front();
+      flight.pop_front();
+      HIPCHECK(hipEventSynchronize(w.ev[sl]));
+      if (w.hSh[1].all_done) all_done = true;
+      if (all_done) {
+        while (!flight.empty()) {
+          HIPCHECK(hipEventSynchronize(w.ev[flight.front()]));
+          flight.pop_front();
+        }
+        break;
+      }
+    }
+    TRY(sync(h));
+    HIPCHECK(hipMemcpy(&w.hSh[1], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost));
+    // Algorithm 2 step 7: x -= U' zeta_c, x~ -= U~' zeta~_c
+    if (k > 0) {
+      launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 2);
+      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nullptr, nullptr, nbe);
+      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nullptr, nullptr, nbe);
+    }
+    HIPCHECK(hipEventRecord(ev1, h->st));
+    HIPCHECK(hipEventSynchronize(ev1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, ev0, ev1));
+    const ShScalars &fs = w.hSh[1];
+    for (int j = 0; j < Sb; ++j) {
+      const int s = bidx[j];
+      HIPCHECK(hipMemcpyAsync(Xc + (size_t)s * n, bcol(w.X, j, h), n * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+      HIPCHECK(hipMemcpyAsync(Xtc + (size_t)s * n, bcol(w.Xt, j, h), n * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+      // true residuals
+      h->shifted = true;
+      h->shift = sig[s];
+      launch_residual<cd, M>(h->st, view_A<M>(h), b, bcol(w.X, j, h), (cd *)h->t1);
+      launch_residual<cd, M>(h->st, view_AH<M>(h), c, bcol(w.Xt, j, h), (cd *)h->t2);
+      h->shifted = false;
+      TRY(host_dots<cd>(h, (cd *)h->t1, (cd *)h->t1, (cd *)h->t2, (cd *)h->t2, nullptr, nullptr, d));
+      rbicg_stats &st = stats[s];
+      st.relres = std::sqrt(std::fabs(d[0].real())) / bn;
+      st.relres_dual = std::sqrt(std::fabs(d[1].real())) / cn;
+      st.iters = fs.done[j] ? fs.iter[j] : launched;
+      const int dst = fs.done[j] ? fs.status[j] : ST_MAXIT;
+      const bool ok = dst == ST_CONVERGED && st.relres <= tol && st.relres_dual <= tol;
+      st.status = ok ? RBICG_OK : (dst == ST_BREAKDOWN ? RBICG_BREAKDOWN : RBICG_NOT_CONVERGED);
+      st.k_used = fs.p[j];
+      st.time_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  // the update shift: a single pair with its own cycle-wise recycle update
+  if (u0 >= 0) {
+    h->shifted = true;
+    h->shift = sig[u0];
+    int rc = 0;
+    if (k > 0) rc = install_recycle<cd, M>(h, w.BU, w.BUt, k);
+    else h->ksys = 0;
+    if (rc >= 0) rc = solve_impl<cd, M>(h, b, c, Xc + (size_t)u0 * n, Xtc + (size_t)u0 * n, tol, &stats[u0]);
+    h->shifted = false;
+    if (rc < 0) return rc;
+  }
+  int worst = RBICG_OK;
+  for (int s = 0; s < S; ++s)
+    if (stats[s].status != RBICG_OK) worst = stats[s].status < 0 ? stats[s].status : (worst < 0 ? worst : stats[s].status);
+  return worst;
+}
+
 template <class F>
 int dispatch(rbicg_s *h, F &&f) {
   if (h->vkind == 0) return f((double *)nullptr, (double *)nullptr);
@@ -1491,6 +1891,8 @@ extern "C" int rbicg_destroy(rbicg_handle h) {
   if (!h) return RBICG_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
+  delete h->sw;
+  h->sw = nullptr;
   if (h->own_mat && h->mat) {
     h->mat->A.release();
     h->mat->AH.release();
@@ -1624,8 +2026,8 @@ extern "C" int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, doub
     int r1 = solve_impl<V, M>(h, (const V *)w, (const V *)u, (V *)x, (V *)xt, tol, st);
     if (r1 < 0 && r1 != RBICG_BREAKDOWN) return r1;
     // value = u^H x + x~^H r with r = w - A x;  ||r||, ||r~||
-    launch_residual<V, M>(h->st, h->mat->A.view<M>(), (const V *)w, (const V *)x, (V *)h->t1);
-    launch_residual<V, M>(h->st, h->mat->AH.view<M>(), (const V *)u, (const V *)xt, (V *)h->t2);
+    launch_residual<V, M>(h->st, view_A<M>(h), (const V *)w, (const V *)x, (V *)h->t1);
+    launch_residual<V, M>(h->st, view_AH<M>(h), (const V *)u, (const V *)xt, (V *)h->t2);
     cplx dd[3];
     TRY(host_dots<V>(h, (const V *)u, (const V *)x, (const V *)xt, (const V *)h->t1,
                      (const V *)h->t1, (const V *)h->t1, dd));
@@ -1647,6 +2049,11 @@ extern "C" int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, doub
 extern "C" int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const void *b,
                                    const void *c, void *X, void *Xt, double tol, int32_t update_from,
                                    rbicg_stats *st) {
-  (void)h; (void)S; (void)sigma; (void)b; (void)c; (void)X; (void)Xt; (void)tol; (void)update_from; (void)st;
-  return rbicg_fail(RBICG_EINVAL, "rbicg_solve_shifted: not built yet");
+  if (!h || !sigma || !b || !c || !X || !Xt || !st) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "shifted solves need a RBICG_C128 handle");
+  if (S < 1 || S > SHMAX) return rbicg_fail(RBICG_EINVAL, "S=%d out of range [1, %d]", S, SHMAX);
+  if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
+  if (h->mat_complex)
+    return solve_shifted_impl<cd>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
+  return solve_shifted_impl<double>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
 }

@@ -208,10 +208,17 @@ class Solver:
         return v, err.value, st.as_dict()
 
     def solve_shifted(self, sigmas, b, c, X=None, Xt=None, tol=1e-8, update_from=-1):
+        """rbicg_solve_shifted: (sigma_s I - A) X[s] = b, (sigma_s I - A)^H Xt[s] = c
+        for every shift; X, Xt are (S, n) complex CUDA tensors (initial guesses
+        on entry).  Returns (X, Xt, [stats per shift])."""
         S = len(sigmas)
         sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.complex128))
         Xcm = torch.zeros((S, self.n), dtype=self.dtype, device="cuda") if X is None else X
         Xtcm = torch.zeros((S, self.n), dtype=self.dtype, device="cuda") if Xt is None else Xt
+        for name, t in (("X", Xcm), ("Xt", Xtcm)):
+            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                    and tuple(t.shape) == (S, self.n)):
+                raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor of shape ({S}, {self.n})")
         sts = (_lib.rbicg_stats * S)()
         rc = self.lib.rbicg_solve_shifted(self.h, S, sig.view(np.float64).ctypes.data_as(_lib._DP),
                                           self._vec(b, "b"), self._vec(c, "c"),

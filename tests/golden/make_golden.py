@@ -6,6 +6,7 @@ Calls only the CPU oracle (oracle/) on seeded synthetic inputs
     python tests/golden/make_golden.py          # both files below
     python tests/golden/make_golden.py cfg2     # cfg2_convdiff3d_64.json
     python tests/golden/make_golden.py cfg4     # cfg4_convdiff3d_128.json
+    python tests/golden/make_golden.py cfg3     # cfg3_shifted_48.json
 
 Contents, for the 3D convection-diffusion sequence on the 64^3 grid
 (k = 20, s = 40, relative tolerance 1e-8):
@@ -116,9 +117,41 @@ def cfg4(N=128):
     print("cfg4 bicg", r.iters, r.relres, r.relres_dual, flush=True)
 
 
+def cfg3(N=48, nsweeps=2):
+    """Shifted pairs (sigma I - A), A = -L_kappa - 0.1 I on 48^3, 8 shifts per
+    sweep, k = 20 shared recycle space updated from the shift of smallest
+    modulus, primal solutions warm-starting the next sweep: per sweep and
+    shift the iteration count, true residuals, retained recycle dimension and
+    256 sampled entries of x and x~."""
+    A, b, c, sweeps = wl.cfg3_shifts(nsweeps=nsweeps, N=N)
+    Asp = as_csr(A)
+    n = Asp.shape[0]
+    idx = np.sort(np.random.default_rng(wl.BASE_SEED + 903).choice(n, 256, replace=False))
+    out = {"workload": f"shifted_aniso3d_{N}^3_8shifts_k20_s40_tol1e-8", "sample_index": idx.tolist(),
+           "sweeps": []}
+    t0 = time.time()
+    U = Ut = None
+    xs = None
+    for sig in sweeps:
+        res, (U, Ut) = oracle.shifted_pairs(Asp, b, c, sig, U, Ut, k=20, s=40, tol=1e-8, x0s=xs)
+        xs = [r.x for r in res]
+        out["sweeps"].append({
+            "sigma": [[float(z.real), float(z.imag)] for z in sig],
+            "iters": [int(r.iters) for r in res],
+            "relres": [[float(r.relres), float(r.relres_dual)] for r in res],
+            "x_sample": [[[float(v.real), float(v.imag)] for v in r.x[idx]] for r in res],
+            "xt_sample": [[[float(v.real), float(v.imag)] for v in r.xt[idx]] for r in res]})
+        print("cfg3 sweep", [r.iters for r in res], flush=True)
+    out["oracle_seconds"] = time.time() - t0
+    with open(os.path.join(HERE, f"cfg3_shifted_{N}.json"), "w") as f:
+        json.dump(out, f)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("cfg2", "all"):
         cfg2()
     if which in ("cfg4", "all"):
         cfg4()
+    if which in ("cfg3", "all"):
+        cfg3()
