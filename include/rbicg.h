@@ -176,9 +176,13 @@ int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
  * with the FP64 matrix, stops when both are <= tol relative, else solves
  * A d = r, A^H d~ = r~ with float matrix values and vectors (every reduction
  * in FP64) to opts.inner_tol relative and adds d, d~ to x, x~ in FP64; the
- * latest cycle's recycle space carries to the next outer step.  st->iters
- * counts inner iterations, st->outer_steps the refinement steps; st->relres
- * is the FP64 true residual.  At most opts.max_outer steps. */
+ * latest cycle's recycle space carries to the next outer step.  An inner
+ * solve stops early at a cycle end without progress: near the tolerance its
+ * iterate is used; otherwise it is discarded, the recycle space dropped and
+ * the next outer step solves in FP64 (plain BiCG).  A correction that raises
+ * the FP64 residual is taken back.  st->iters counts inner iterations,
+ * st->outer_steps the refinement steps, st->restarts the FP64 inner solves;
+ * st->relres is the FP64 true residual.  At most opts.max_outer steps. */
 int rbicg_solve_dual(rbicg_handle h, const void *b, const void *bt, void *x, void *xt,
                      double tol, rbicg_stats *st);
 

@@ -134,6 +134,7 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
     # relative residual max(||r||/||b||, ||r~||/||b~||) by iteration, for the
     # stagnation stop below
     hist = [max(rn / bn, rtn / btn)]
+    best = [hist[0]]     # smallest cycle-end value of hist so far, by cycle
     diverged = False
     it = 0
     while it < maxit and not (rn <= tol * bn and rtn <= tol * btn):
@@ -183,21 +184,27 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
         if rn <= tol * bn and rtn <= tol * btn:
             break
         hist.append(max(rn / bn, rtn / btn))
-        # Cycle-end guards (reading for FP32 storage, not in the paper); both
-        # need a whole cycle without progress (hist[it] >= hist[it - s]):
-        #  stagnation -- float storage behind the oblique projector limits the
-        #    attainable residual to about the inner tolerance; once below
-        #    sqrt(tol), return the iterate and let the FP64 outer loop go on;
-        #  divergence -- for some recycle spaces the deflated iteration is so
-        #    ill conditioned that float rounding keeps it from converging (FP64
-        #    is fine); with a recycle space in use, from the second cycle on,
-        #    a residual not below the initial one gives up on this inner solve
-        #    (the outer loop discards it and drops the recycle space).
-        if it % s == 0 and it >= s and hist[it] >= hist[it - s]:
-            if hist[it] <= np.sqrt(tol):
+        # Cycle-end guards (reading for FP32 storage, not in the paper):
+        #  stagnation -- float storage (behind the oblique projector when a
+        #    recycle space is in use) limits the attainable residual to about
+        #    the inner tolerance; once below sqrt(tol), a cycle that does not
+        #    halve the residual returns the iterate and lets the FP64 outer
+        #    loop go on;
+        #  no progress -- float rounding can keep the iteration from
+        #    converging where FP64 converges (ill-conditioned deflation with
+        #    some recycle spaces; plain BiCG on strongly non-normal operators):
+        #    when the best cycle-end residual has not halved over the last two
+        #    cycles, stop; above sqrt(tol) the solve counts as diverged (the
+        #    outer loop discards it, drops the recycle space and takes its next
+        #    inner solve in FP64), else as stagnated.
+        if it % s == 0 and it >= s:
+            c = it // s
+            best.append(min(best[-1], hist[it]))
+            if hist[it] <= np.sqrt(tol) and hist[it] >= 0.5 * hist[it - s]:
                 break
-            if kc and it >= 2 * s and hist[it] >= hist[0]:
-                diverged = True
+            if c >= 2 and best[c] >= 0.5 * best[c - 2]:
+                if best[c] > np.sqrt(tol):
+                    diverged = True
                 break
         beta = rho_new / rho
         rho = rho_new
@@ -232,14 +239,17 @@ def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
     The recycle space carries over between outer steps (the latest cycle's
     space when one completed), biorthogonalized with the cut of
     mixed_svd_tol.  Safeguards (readings): an inner solve stopped as diverging
-    is discarded; a correction that raises max(||r||/||b||, ||r~||/||b~||) is
-    taken back (x -= d, x~ -= d~); either way the recycle space is dropped.
+    is discarded and the next outer step solves in FP64 (plain BiCG); a
+    correction that raises max(||r||/||b||, ||r~||/||b~||) is taken back
+    (x -= d, x~ -= d~); either way the recycle space is dropped.
     Returns (x, x~, info, (U, U~))."""
     A = as_csr(A).astype(np.float64)
     AH = A.T.tocsr()
     A32 = A.astype(np.float32)
     AH32 = AH.astype(np.float32)
     tau = mixed_svd_tol(svd_tol, inner_tol)
+    escalate = False     # next inner solve in FP64 (after a diverged FP32 one)
+    fp64_inner = 0
     n = A.shape[0]
     x = np.zeros(n); xt = np.zeros(n)
     bn = np.linalg.norm(b); btn = np.linalg.norm(bt)
@@ -263,6 +273,18 @@ def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
         last = None
         if (rel <= tol and relt <= tol) or outer >= max_outer:
             break
+        if escalate:
+            # FP64 inner solve (plain BiCG, Algorithm 1) for this outer step
+            res = rbicg(A, r, rt, tol=inner_tol, maxit=maxit_inner, k=0, update=False)
+            inner_total += res.iters
+            outer += 1
+            fp64_inner += 1
+            escalate = False
+            prev = max(rel, relt)
+            last = (res.x, res.xt)
+            x = x + res.x
+            xt = xt + res.xt
+            continue
         C = Ct = None
         if U is not None and U.shape[1] > 0:
             U, Ut, C, Ct = rc.biorthogonalize(A, AH, U, Ut, tau)
@@ -274,6 +296,7 @@ def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
         outer += 1
         if diverged:
             U = Ut = None
+            escalate = True
             continue
         prev = max(rel, relt)
         last = (d, dt_)
@@ -281,7 +304,8 @@ def mixed_refine(A, b, bt, U=None, Ut=None, k=30, s=40, tol=1e-10,
         xt = xt + dt_
         if cyc.Uj is not None and cyc.Uj.shape[1] > 0:
             U, Ut = cyc.Uj, cyc.Utj
-    info = {"outer": outer, "inner_iters": inner_total, "relres": rel, "relres_dual": relt}
+    info = {"outer": outer, "inner_iters": inner_total, "relres": rel, "relres_dual": relt,
+            "fp64_inner": fp64_inner}
     return x, xt, info, (U, Ut)
 
 

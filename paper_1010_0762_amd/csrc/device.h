@@ -20,11 +20,13 @@ struct cd {
 struct Scalars {
   double tol, bn, btn;
   int iter, done, status, maxit;
-  // FP32-inner solves: at every stag_s-th iteration, when the relative
-  // residual max(||r||/||b||, ||r~||/||b~||) is not below the one stag_s
-  // iterations earlier, stop as stagnated if it is <= stag_lim, or (with
-  // stag_div set: a recycle space is in use) as diverged if, from the second
-  // cycle on, it is not below the initial one (stag_s = 0: off)
+  // FP32-inner solves: at every stag_s-th iteration (cycle end), with the
+  // relative residual max(||r||/||b||, ||r~||/||b~||) now (cur) and at the
+  // previous cycle end (prev): stop as stagnated if cur <= stag_lim and
+  // cur >= prev / 2; with stag_div set (a recycle space is in use), from the
+  // second cycle on, stop when the smallest cycle-end value has not halved
+  // over the last two cycles (diverged if it is above stag_lim, else
+  // stagnated).  stag_s = 0: off
   int stag_s, stag_div;
   double stag_lim;
   double zbuf[4 * KMAXD];

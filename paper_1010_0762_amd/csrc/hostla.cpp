@@ -563,6 +563,413 @@ void pencil_vectors(const PencilSchur &ps, const std::vector<int> &want, CMat &W
   normalize_cols(Y);
 }
 
+// ------------------------------------------------------------- real QZ
+// Real pencils (the harmonic Ritz pencils of real problems) take the real
+// double-shift QZ algorithm of Moler and Stewart: Householder QR of B,
+// Givens reduction of A to Hessenberg form with B kept triangular, then
+// implicit double-shift sweeps (3 x 3 Householder reflections chasing the
+// bulge) until A is quasi-triangular (1 x 1 and 2 x 2 diagonal blocks).
+// Complex eigenvalues of the 2 x 2 blocks come in conjugate pairs.
+struct RMat {
+  int m = 0, n = 0;
+  std::vector<double> a;
+  RMat() {}
+  RMat(int m_, int n_) : m(m_), n(n_), a((size_t)m_ * n_, 0.0) {}
+  double &operator()(int i, int j) { return a[(size_t)i + (size_t)j * m]; }
+  double operator()(int i, int j) const { return a[(size_t)i + (size_t)j * m]; }
+};
+
+// Householder vector of x (len entries): (I - beta v v^T) x = -+||x|| e_0,
+// v[0] = 1 (Golub and Van Loan, Algorithm 5.1.1).
+void house(const double *x, int len, double *v, double &beta) {
+  double sigma = 0.0;
+  for (int i = 1; i < len; ++i) sigma += x[i] * x[i];
+  v[0] = 1.0;
+  for (int i = 1; i < len; ++i) v[i] = x[i];
+  if (sigma == 0.0) {
+    beta = 0.0;
+    return;
+  }
+  const double mu = std::sqrt(x[0] * x[0] + sigma);
+  const double v0 = x[0] <= 0.0 ? x[0] - mu : -sigma / (x[0] + mu);
+  beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+  for (int i = 1; i < len; ++i) v[i] /= v0;
+}
+// rows r0..r0+len-1 of M <- (I - beta v v^T) M, columns c0..c1-1
+void house_left(RMat &M, int r0, int len, const double *v, double beta, int c0, int c1) {
+  if (beta == 0.0) return;
+  for (int j = c0; j < c1; ++j) {
+    double t = 0.0;
+    for (int i = 0; i < len; ++i) t += v[i] * M(r0 + i, j);
+    t *= beta;
+    for (int i = 0; i < len; ++i) M(r0 + i, j) -= t * v[i];
+  }
+}
+// columns c0..c0+len-1 of M <- M (I - beta v v^T), rows r0..r1-1
+void house_right(RMat &M, int c0, int len, const double *v, double beta, int r0, int r1) {
+  if (beta == 0.0) return;
+  for (int i = r0; i < r1; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < len; ++j) t += M(i, c0 + j) * v[j];
+    t *= beta;
+    for (int j = 0; j < len; ++j) M(i, c0 + j) -= t * v[j];
+  }
+}
+// rows (i, i+1) <- G [row i; row i+1] with G = [c s; -s c], columns c0..c1-1
+void grot_rows(RMat &M, int i, double c, double s, int c0, int c1) {
+  for (int j = c0; j < c1; ++j) {
+    const double a = M(i, j), b = M(i + 1, j);
+    M(i, j) = c * a + s * b;
+    M(i + 1, j) = -s * a + c * b;
+  }
+}
+// columns (j, j+1) <- [col j, col j+1] [c -s; s c], rows r0..r1-1
+// (with (c, s) from (M(r, j+1), M(r, j)) this zeroes M(r, j))
+void grot_cols(RMat &M, int j, double c, double s, int r0, int r1) {
+  for (int i = r0; i < r1; ++i) {
+    const double a = M(i, j), b = M(i, j + 1);
+    M(i, j) = c * a - s * b;
+    M(i, j + 1) = s * a + c * b;
+  }
+}
+void givens_r(double a, double b, double &c, double &s) {
+  const double r = std::hypot(a, b);
+  if (r == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else {
+    c = a / r;
+    s = b / r;
+  }
+}
+// zero B(r, j) against B(r, j+1) by a rotation of columns (j, j+1)
+void zero_col_entry(RMat &B, RMat &A, RMat &Z, int r, int j, int arows, int brows) {
+  double c, s;
+  givens_r(B(r, j + 1), B(r, j), c, s);
+  grot_cols(B, j, c, s, 0, brows);
+  grot_cols(A, j, c, s, 0, arows);
+  grot_cols(Z, j, c, s, 0, Z.m);
+  B(r, j) = 0.0;
+}
+
+bool qz_real(RMat &A, RMat &B, RMat &Q, RMat &Z) {
+  const int m = A.m;
+  Q = RMat(m, m);
+  Z = RMat(m, m);
+  for (int i = 0; i < m; ++i) {
+    Q(i, i) = 1.0;
+    Z(i, i) = 1.0;
+  }
+  std::vector<double> x(m), v(m);
+  // B = Q R
+  for (int j = 0; j + 1 < m; ++j) {
+    const int len = m - j;
+    for (int i = 0; i < len; ++i) x[i] = B(j + i, j);
+    double beta;
+    house(x.data(), len, v.data(), beta);
+    house_left(B, j, len, v.data(), beta, j, m);
+    house_left(A, j, len, v.data(), beta, 0, m);
+    house_right(Q, j, len, v.data(), beta, 0, m);
+    for (int i = j + 1; i < m; ++i) B(i, j) = 0.0;
+  }
+  // A to Hessenberg form, B kept upper triangular
+  for (int j = 0; j + 2 < m; ++j)
+    for (int i = m - 1; i > j + 1; --i) {
+      double c, s;
+      givens_r(A(i - 1, j), A(i, j), c, s);
+      grot_rows(A, i - 1, c, s, j, m);
+      grot_rows(B, i - 1, c, s, i - 1, m);
+      // Q <- Q G^T on columns (i-1, i)
+      for (int r = 0; r < m; ++r) {
+        const double a = Q(r, i - 1), b = Q(r, i);
+        Q(r, i - 1) = c * a + s * b;
+        Q(r, i) = -s * a + c * b;
+      }
+      A(i, j) = 0.0;
+      zero_col_entry(B, A, Z, i, i - 1, m, i + 1);
+    }
+  double anorm = 0.0, bnorm = 0.0;
+  for (double z : A.a) anorm = std::max(anorm, std::fabs(z));
+  for (double z : B.a) bnorm = std::max(bnorm, std::fabs(z));
+  if (anorm == 0.0) anorm = 1.0;
+  if (bnorm == 0.0) bnorm = 1.0;
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    while (l > 0) {
+      const double sub = std::fabs(A(l, l - 1));
+      if (sub <= kEps * (std::fabs(A(l - 1, l - 1)) + std::fabs(A(l, l))) || sub <= kEps * anorm * 1e-3) {
+        A(l, l - 1) = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {  // 1 x 1 block
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (l == hi - 1) {  // 2 x 2 block: kept (its eigenvalues come from the quadratic)
+      hi -= 2;
+      iter = 0;
+      continue;
+    }
+    ++iter;
+    if (++total > 60 * m) return false;
+    // tiny diagonal entries of B: floored (infinite eigenvalues become huge)
+    for (int i = l; i <= hi; ++i)
+      if (std::fabs(B(i, i)) < kEps * bnorm) B(i, i) = B(i, i) < 0.0 ? -kEps * bnorm : kEps * bnorm;
+    // shifts: eigenvalues of the trailing 2 x 2 block of M = A B^{-1}
+    double sh, tt;
+    {
+      const double b11 = B(hi - 2, hi - 2), b12 = B(hi - 2, hi - 1), b13 = B(hi - 2, hi);
+      const double b22 = B(hi - 1, hi - 1), b23 = B(hi - 1, hi), b33 = B(hi, hi);
+      const double i12 = -b12 / (b11 * b22), i22 = 1.0 / b22;
+      const double i13 = (b12 * b23 - b13 * b22) / (b11 * b22 * b33), i23 = -b23 / (b22 * b33), i33 = 1.0 / b33;
+      const double m11 = A(hi - 1, hi - 2) * i12 + A(hi - 1, hi - 1) * i22;
+      const double m12 = A(hi - 1, hi - 2) * i13 + A(hi - 1, hi - 1) * i23 + A(hi - 1, hi) * i33;
+      const double m21 = A(hi, hi - 1) * i22;
+      const double m22 = A(hi, hi - 1) * i23 + A(hi, hi) * i33;
+      sh = m11 + m22;
+      tt = m11 * m22 - m12 * m21;
+      if (iter % 10 == 0) {  // exceptional shift
+        const double w = std::fabs(A(hi, hi - 1) / B(hi - 1, hi - 1)) +
+                         std::fabs(A(hi - 1, hi - 2) / B(hi - 2, hi - 2));
+        sh = 1.5 * w;
+        tt = w * w;
+      }
+    }
+    // first column of (M - a1 I)(M - a2 I) restricted to rows l..l+2
+    double v0, v1, v2;
+    {
+      const double bll = B(l, l), bl1 = B(l, l + 1), b22 = B(l + 1, l + 1);
+      const double y1 = A(l, l) / bll, y2 = A(l + 1, l) / bll;
+      const double u2 = y2 / b22, u1 = (y1 - bl1 * u2) / bll;
+      const double w0 = A(l, l) * u1 + A(l, l + 1) * u2;
+      const double w1 = A(l + 1, l) * u1 + A(l + 1, l + 1) * u2;
+      const double w2 = A(l + 2, l + 1) * u2;
+      v0 = w0 - sh * y1 + tt;
+      v1 = w1 - sh * y2;
+      v2 = w2;
+      const double sc = std::max(std::fabs(v0), std::max(std::fabs(v1), std::fabs(v2)));
+      if (sc > 0.0) {
+        v0 /= sc;
+        v1 /= sc;
+        v2 /= sc;
+      }
+    }
+    for (int k = l; k <= hi - 2; ++k) {
+      if (k > l) {
+        v0 = A(k, k - 1);
+        v1 = A(k + 1, k - 1);
+        v2 = A(k + 2, k - 1);
+      }
+      double xv[3] = {v0, v1, v2}, hv[3], beta;
+      house(xv, 3, hv, beta);
+      const int c0 = k > l ? k - 1 : l;
+      house_left(A, k, 3, hv, beta, c0, m);
+      house_left(B, k, 3, hv, beta, k, m);
+      house_right(Q, k, 3, hv, beta, 0, m);
+      if (k > l) {
+        A(k + 1, k - 1) = 0.0;
+        A(k + 2, k - 1) = 0.0;
+      }
+      // restore B: zero B(k+2, k), B(k+2, k+1) by a reflection of columns
+      // k..k+2 built from the reversed row, then B(k+1, k) by a rotation
+      {
+        double xr[3] = {B(k + 2, k + 2), B(k + 2, k + 1), B(k + 2, k)}, vr[3], br;
+        house(xr, 3, vr, br);
+        double vv[3] = {vr[2], vr[1], vr[0]};
+        const int ar = std::min(k + 4, hi + 1);
+        house_right(B, k, 3, vv, br, 0, k + 3);
+        house_right(A, k, 3, vv, br, 0, ar);
+        house_right(Z, k, 3, vv, br, 0, m);
+        B(k + 2, k) = 0.0;
+        B(k + 2, k + 1) = 0.0;
+        zero_col_entry(B, A, Z, k + 1, k, ar, k + 2);
+      }
+    }
+    // last step: rows (hi-1, hi), then B(hi, hi-1)
+    {
+      double c, s;
+      givens_r(A(hi - 1, hi - 2), A(hi, hi - 2), c, s);
+      grot_rows(A, hi - 1, c, s, hi - 2, m);
+      grot_rows(B, hi - 1, c, s, hi - 1, m);
+      for (int r = 0; r < m; ++r) {
+        const double a = Q(r, hi - 1), b = Q(r, hi);
+        Q(r, hi - 1) = c * a + s * b;
+        Q(r, hi) = -s * a + c * b;
+      }
+      A(hi, hi - 2) = 0.0;
+      zero_col_entry(B, A, Z, hi, hi - 1, hi + 1, hi + 1);
+    }
+  }
+  for (int j = 0; j < m; ++j)
+    for (int i = j + 1; i < m; ++i) {
+      B(i, j) = 0.0;
+      if (i > j + 1) A(i, j) = 0.0;
+    }
+  return true;
+}
+
+// Generalized real Schur form and eigenvalues (blk[i] = 1 when i starts a
+// 2 x 2 block, 2 for its second row, 0 for a 1 x 1 block).
+struct RPencil {
+  RMat S, T, Q, Z;
+  std::vector<cplx> lam;
+  std::vector<int> blk;
+};
+bool rpencil_schur(const CMat &P, const CMat &Qc, RPencil &ps) {
+  const int m = P.m;
+  RMat A(m, m), B(m, m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      A(i, j) = P(i, j).real();
+      B(i, j) = Qc(i, j).real();
+    }
+  if (!qz_real(A, B, ps.Q, ps.Z)) return false;
+  ps.S = A;
+  ps.T = B;
+  ps.lam.assign(m, cplx(0.0));
+  ps.blk.assign(m, 0);
+  for (int i = 0; i < m;) {
+    if (i + 1 < m && A(i + 1, i) != 0.0) {
+      ps.blk[i] = 1;
+      ps.blk[i + 1] = 2;
+      // det(S_b - lambda T_b) = 0, T_b upper triangular
+      const double s11 = A(i, i), s12 = A(i, i + 1), s21 = A(i + 1, i), s22 = A(i + 1, i + 1);
+      const double t11 = B(i, i), t12 = B(i, i + 1), t22 = B(i + 1, i + 1);
+      const double qa = t11 * t22, qb = -(s11 * t22 + s22 * t11 - s21 * t12), qc = s11 * s22 - s12 * s21;
+      const cplx disc = std::sqrt(cplx(qb * qb - 4.0 * qa * qc, 0.0));
+      if (qa == 0.0) {
+        ps.lam[i] = ps.lam[i + 1] = cplx(INFINITY, 0.0);
+      } else {
+        // the root of larger modulus from the stable form, the other from the product
+        const cplx q = -0.5 * (cplx(qb, 0.0) + (qb >= 0.0 ? disc : -disc));
+        cplx r1 = q / qa, r2 = q != cplx(0.0) ? cplx(qc, 0.0) / q : cplx(0.0);
+        if (r1.imag() < r2.imag() || (r1.imag() == r2.imag() && r1.real() < r2.real())) std::swap(r1, r2);
+        ps.lam[i] = r1;
+        ps.lam[i + 1] = r2;
+      }
+      i += 2;
+    } else {
+      ps.lam[i] = B(i, i) != 0.0 ? cplx(A(i, i) / B(i, i), 0.0) : cplx(INFINITY, 0.0);
+      ++i;
+    }
+  }
+  return true;
+}
+
+// Right (w: P w = lambda Q w) and left (y: y^H P = lambda y^H Q) eigenvectors
+// of the eigenvalue indices in `want`, by complex back- and forward
+// substitution on the quasi-triangular form.
+void rpencil_vectors(const RPencil &ps, const std::vector<int> &want, CMat &W, CMat &Y) {
+  const RMat &S = ps.S, &T = ps.T;
+  const int m = S.m, nw = (int)want.size();
+  double snorm = 0;
+  for (double z : S.a) snorm = std::max(snorm, std::fabs(z));
+  for (double z : T.a) snorm = std::max(snorm, std::fabs(z));
+  const double small = std::max(snorm * kEps, 1e-300);
+  W = CMat(m, nw);
+  Y = CMat(m, nw);
+  std::vector<cplx> yr(m), yl(m);
+  auto D = [&](int i, int j, cplx lj) { return cplx(S(i, j), 0.0) - lj * T(i, j); };
+  auto solve2 = [&](cplx a, cplx b, cplx c, cplx d, cplx r0, cplx r1, cplx &x0, cplx &x1) {
+    cplx det = a * d - b * c;
+    if (cabs(det) < small * small) det = small * small;
+    x0 = (r0 * d - b * r1) / det;
+    x1 = (a * r1 - c * r0) / det;
+  };
+  for (int cidx = 0; cidx < nw; ++cidx) {
+    const int j = want[cidx];
+    const cplx lj = ps.lam[j];
+    const int js = ps.blk[j] == 2 ? j - 1 : j;             // first row of j's block
+    const int je = ps.blk[j] == 1 || ps.blk[j] == 2 ? js + 1 : j;  // last row
+    std::fill(yr.begin(), yr.end(), cplx(0.0));
+    std::fill(yl.begin(), yl.end(), cplx(0.0));
+    // right vector: null vector of the block, then rows js-1 .. 0
+    if (js == je) {
+      yr[js] = 1.0;
+    } else {
+      const cplx a = D(js, js, lj), b = D(js, je, lj), c = D(je, js, lj), d = D(je, je, lj);
+      if (cabs(a) + cabs(b) >= cabs(c) + cabs(d)) {
+        yr[js] = -b;
+        yr[je] = a;
+      } else {
+        yr[js] = d;
+        yr[je] = -c;
+      }
+    }
+    for (int i = js - 1; i >= 0;) {
+      if (ps.blk[i] == 2) {  // rows (i-1, i) form a block
+        cplx r0 = 0, r1 = 0;
+        for (int q = i + 1; q <= je; ++q) {
+          r0 -= D(i - 1, q, lj) * yr[q];
+          r1 -= D(i, q, lj) * yr[q];
+        }
+        solve2(D(i - 1, i - 1, lj), D(i - 1, i, lj), D(i, i - 1, lj), D(i, i, lj), r0, r1, yr[i - 1], yr[i]);
+        i -= 2;
+      } else {
+        cplx acc = 0;
+        for (int q = i + 1; q <= je; ++q) acc += D(i, q, lj) * yr[q];
+        cplx d = D(i, i, lj);
+        if (cabs(d) < small) d = small;
+        yr[i] = -acc / d;
+        --i;
+      }
+    }
+    // left vector: u^H (S - lam T) = 0, i.e. (S - lam T)^H u = 0, supported on js..m-1
+    if (js == je) {
+      yl[js] = 1.0;
+    } else {
+      // rows of (S - lam T)^H on the block: conj of the block's columns
+      const cplx a = std::conj(D(js, js, lj)), b = std::conj(D(je, js, lj));
+      const cplx c = std::conj(D(js, je, lj)), d = std::conj(D(je, je, lj));
+      if (cabs(a) + cabs(b) >= cabs(c) + cabs(d)) {
+        yl[js] = -b;
+        yl[je] = a;
+      } else {
+        yl[js] = d;
+        yl[je] = -c;
+      }
+    }
+    for (int i = je + 1; i < m;) {
+      if (ps.blk[i] == 1) {  // rows (i, i+1) form a block
+        cplx r0 = 0, r1 = 0;
+        for (int q = js; q < i; ++q) {
+          r0 -= std::conj(D(q, i, lj)) * yl[q];
+          r1 -= std::conj(D(q, i + 1, lj)) * yl[q];
+        }
+        solve2(std::conj(D(i, i, lj)), std::conj(D(i + 1, i, lj)), std::conj(D(i, i + 1, lj)),
+               std::conj(D(i + 1, i + 1, lj)), r0, r1, yl[i], yl[i + 1]);
+        i += 2;
+      } else {
+        cplx acc = 0;
+        for (int q = js; q < i; ++q) acc += std::conj(D(q, i, lj)) * yl[q];
+        cplx d = std::conj(D(i, i, lj));
+        if (cabs(d) < small) d = small;
+        yl[i] = -acc / d;
+        ++i;
+      }
+    }
+    for (int i = 0; i < m; ++i) {
+      cplx a = 0, b = 0;
+      for (int l = 0; l <= je; ++l) a += ps.Z(i, l) * yr[l];
+      for (int l = js; l < m; ++l) b += ps.Q(i, l) * yl[l];
+      W(i, cidx) = a;
+      Y(i, cidx) = b;
+    }
+  }
+  normalize_cols(W);
+  normalize_cols(Y);
+}
+
+bool is_real(const CMat &M) {
+  for (const cplx &z : M.a)
+    if (z.imag() != 0.0) return false;
+  return true;
+}
+
 bool finite(cplx z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
 
 }  // namespace
@@ -577,13 +984,21 @@ extern "C" int rbicg_host_eig(int32_t m, const double *P, const double *Q, doubl
   } else {
     for (int i = 0; i < m; ++i) Qm(i, i) = 1.0;
   }
-  PencilSchur ps;
-  if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig: QZ iteration did not converge");
-  std::vector<cplx> &ev = ps.lam;
+  std::vector<cplx> ev;
   CMat X, Y;
   std::vector<int> all(m);
   std::iota(all.begin(), all.end(), 0);
-  if (W || Wl) pencil_vectors(ps, all, X, Y);
+  if (is_real(Pm) && is_real(Qm)) {
+    RPencil rp;
+    if (!rpencil_schur(Pm, Qm, rp)) return rbicg_fail(-1, "host_eig: QZ iteration did not converge");
+    ev = rp.lam;
+    if (W || Wl) rpencil_vectors(rp, all, X, Y);
+  } else {
+    PencilSchur ps;
+    if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig: QZ iteration did not converge");
+    ev = ps.lam;
+    if (W || Wl) pencil_vectors(ps, all, X, Y);
+  }
   if (lam)
     for (int i = 0; i < m; ++i) { lam[2 * i] = ev[i].real(); lam[2 * i + 1] = ev[i].imag(); }
   if (W) store(X, W);
@@ -737,14 +1152,24 @@ extern "C" int rbicg_host_eig_select(int32_t m, const double *P, const double *Q
   } else {
     for (int i = 0; i < m; ++i) Qm(i, i) = 1.0;
   }
-  PencilSchur ps;
-  if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig_select: QZ iteration did not converge");
   int ncols = 0;
-  const std::vector<SelItem> sel = select_indices(ps.lam, k, real_problem != 0, ncols);
-  std::vector<int> want;
-  for (const auto &it : sel) want.push_back(it.idx);
+  std::vector<SelItem> sel;
   CMat W, Y;
-  pencil_vectors(ps, want, W, Y);
+  if (is_real(Pm) && is_real(Qm)) {
+    RPencil rp;
+    if (!rpencil_schur(Pm, Qm, rp)) return rbicg_fail(-1, "host_eig_select: QZ iteration did not converge");
+    sel = select_indices(rp.lam, k, real_problem != 0, ncols);
+    std::vector<int> want;
+    for (const auto &it : sel) want.push_back(it.idx);
+    rpencil_vectors(rp, want, W, Y);
+  } else {
+    PencilSchur ps;
+    if (!pencil_schur(Pm, Qm, ps)) return rbicg_fail(-1, "host_eig_select: QZ iteration did not converge");
+    sel = select_indices(ps.lam, k, real_problem != 0, ncols);
+    std::vector<int> want;
+    for (const auto &it : sel) want.push_back(it.idx);
+    pencil_vectors(ps, want, W, Y);
+  }
   auto colW = [&](int t) {
     std::vector<cplx> v(m);
     for (int i = 0; i < m; ++i) v[i] = W(i, t);

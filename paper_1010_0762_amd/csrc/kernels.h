@@ -57,6 +57,7 @@ void launch_reseed(hipStream_t st, V *x, size_t n, unsigned long long seed);
 // out = (float)in; x += sgn (double)d (FP32-inner mode)
 void launch_d2f(hipStream_t st, const double *in, float *out, size_t n);
 void launch_add_f2d(hipStream_t st, double *x, const float *d, double sgn, size_t n);
+void launch_add_d2d(hipStream_t st, double *x, const double *d, double sgn, size_t n);
 // row chunks (blocks) of the Gram kernel for n rows
 int gram_chunks(int n);
 // Gram kernel: LDS budget per block (gfx950 has 160 KB per CU)

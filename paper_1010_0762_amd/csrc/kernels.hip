@@ -197,6 +197,40 @@ __device__ __forceinline__ T spmv_dir(const Sell<M> &A, int row, const V *r, con
   return acc;
 }
 
+// One row of z = A p with p = r + beta p formed at the gathered columns.  A
+// slice of at most 8 entries per row (every stencil here) loads all of the
+// row's column indices and values first and then issues all gathers, so that
+// up to 24 independent loads per thread are in flight; the sum runs in entry
+// order, as in spmv_dir.  Wider slices take spmv_dir.
+template <class V, class M, class T>
+__device__ __forceinline__ T spmv_dir8(const Sell<M> &A, int row, const V *r, const V *p, T beta) {
+  const int slice = row >> 6, lane = row & 63;
+  const int b0 = A.sliceptr[slice];
+  const int w = (A.sliceptr[slice + 1] - b0) >> 6;
+  if (w > 8) return spmv_dir<V, M, T>(A, row, r, p, beta);
+  int c[8];
+  M v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < w) {
+      c[j] = A.col[b0 + lane + RBICG_WAVE * j];
+      v[j] = A.val[b0 + lane + RBICG_WAVE * j];
+    }
+  V g[8], h[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < w) {
+      g[j] = r[c[j]];
+      h[j] = p[c[j]];
+    }
+  T a = zero<T>();
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < w) a += up(v[j]) * up(down<V>(up(g[j]) + beta * up(h[j])));
+  if (A.shifted) a = shift_apply<M, T>(A, a, up(down<V>(up(r[row]) + beta * up(p[row]))));
+  return a;
+}
+
 template <class V, class M, class T>
 __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   const int slice = row >> 6, lane = row & 63;
@@ -230,14 +264,20 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
   else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
   else if (it > S->maxit) st = ST_MAXIT;
   else if (S->stag_s > 0 && (it - 1) % S->stag_s == 0 && it - 1 >= S->stag_s) {
-    const double *Rp = rec + (size_t)(it - 1 - S->stag_s) * LOG_STRIDE;
+    // cycle end c = (it-1)/s: the smallest cycle-end value so far is kept in
+    // slot 9 of the cycle-end rows (the host writes that slot only after the run)
+    const int s = S->stag_s, c = (it - 1) / s;
+    auto h = [&](int cc) {
+      const double *R = rec + (size_t)cc * s * LOG_STRIDE;
+      return fmax(R[6] / S->bn, R[7] / S->btn);
+    };
+    auto best_of = [&](int cc) { return cc == 0 ? h(0) : rec[(size_t)cc * s * LOG_STRIDE + 9]; };
     const double cur = fmax(rn / S->bn, rtn / S->btn);
-    const double prev = fmax(Rp[6] / S->bn, Rp[7] / S->btn);
-    if (cur >= prev) {
-      if (cur <= S->stag_lim) st = ST_STAGNATED;
-      else if (S->stag_div && it - 1 >= 2 * S->stag_s && cur >= fmax(rec[6] / S->bn, rec[7] / S->btn))
-        st = ST_DIVERGED;
-    }
+    const double best = fmin(best_of(c - 1), cur);
+    if (lead) Rm1[9] = best;
+    if (cur <= S->stag_lim && cur >= 0.5 * h(c - 1)) st = ST_STAGNATED;
+    else if (S->stag_div && c >= 2 && best >= 0.5 * best_of(c - 2))
+      st = best > S->stag_lim ? ST_DIVERGED : ST_STAGNATED;
   }
   if (st != ST_RUNNING) {
     if (lead) {
@@ -263,7 +303,7 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
 }  // namespace
 
 // ===================================================================== kernels
-template <class V, class M>
+template <class V, class M, int RPT>
 __global__ __launch_bounds__(IB) void k_it1(
     Sell<M> A, Sell<M> AH, const V *__restrict__ r, const V *__restrict__ p,
     const V *__restrict__ rt, const V *__restrict__ pt, V *__restrict__ pn, V *__restrict__ ptn,
@@ -281,9 +321,9 @@ __global__ __launch_bounds__(IB) void k_it1(
   const int n = A.n;
   const int stride = gridDim.x * IB;
   const int row0 = blockIdx.x * IB + threadIdx.x;
-  T zr[RMAX], ztr[RMAX], rr_[RMAX], rtr_[RMAX];
+  T zr[RPT], ztr[RPT], rr_[RPT], rtr_[RPT];
 #pragma unroll
-  for (int q = 0; q < RMAX; ++q) {
+  for (int q = 0; q < RPT; ++q) {
     zr[q] = zero<T>();
     ztr[q] = zero<T>();
     rr_[q] = zero<T>();
@@ -295,8 +335,17 @@ __global__ __launch_bounds__(IB) void k_it1(
       rtr_[q] = up(rtv);
       pn[row] = down<V>(up(rv) + beta * up(p[row]));
       ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
-      const T zz = up(down<V>(spmv_dir<V, M, T>(A, row, r, p, beta)));
-      const T zzt = up(down<V>(spmv_dir<V, M, T>(AH, row, rt, pt, betac)));
+      // one row per thread: the unrolled gathers fit the register budget
+      T za, zb;
+      if constexpr (RPT == 1) {
+        za = spmv_dir8<V, M, T>(A, row, r, p, beta);
+        zb = spmv_dir8<V, M, T>(AH, row, rt, pt, betac);
+      } else {
+        za = spmv_dir<V, M, T>(A, row, r, p, beta);
+        zb = spmv_dir<V, M, T>(AH, row, rt, pt, betac);
+      }
+      const T zz = up(down<V>(za));
+      const T zzt = up(down<V>(zb));
       zr[q] = zz;
       ztr[q] = zzt;
       z[row] = down<V>(zz);
@@ -314,7 +363,7 @@ __global__ __launch_bounds__(IB) void k_it1(
   for (int j = 0; j < k; ++j) {
     T a = zero<T>(), b = zero<T>(), c = zero<T>(), d = zero<T>();
 #pragma unroll
-    for (int q = 0; q < RMAX; ++q) {
+    for (int q = 0; q < RPT; ++q) {
       const int row = row0 + q * stride;
       if (row < n) {
         const T ctv = cj(up(Ct[(size_t)j * ld + row])), cv = cj(up(C[(size_t)j * ld + row]));
@@ -601,7 +650,8 @@ __global__ void k_d2f(const double *__restrict__ in, float *__restrict__ out, si
   const size_t i = (size_t)blockIdx.x * RBICG_BLOCK + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
 }
-__global__ void k_add_f2d(double *__restrict__ x, const float *__restrict__ d, double sgn, size_t n) {
+template <class S>
+__global__ void k_add_to_d(double *__restrict__ x, const S *__restrict__ d, double sgn, size_t n) {
   const size_t i = (size_t)blockIdx.x * RBICG_BLOCK + threadIdx.x;
   if (i < n) x[i] += sgn * (double)d[i];
 }
@@ -1211,18 +1261,16 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sh3(int n, int ld, cd *X, cd *X
     }
     __syncthreads();
   }
-  double acc[4 * SHMAX];
-#pragma unroll
-  for (int t = 0; t < 4 * SHMAX; ++t) acc[t] = 0.0;
+  // shifts outer, rows inner: four accumulators per thread at a time
   const int stride = gridDim.x * RBICG_BLOCK;
-  for (int row = blockIdx.x * RBICG_BLOCK + threadIdx.x; row < n; row += stride) {
-#pragma unroll
-    for (int s = 0; s < SHMAX; ++s) {
-      if (s >= S) break;
+  for (int s = 0; s < S; ++s) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const bool on = upd && act[s];
+    const cd al = on ? alphas[s] : cd{0.0, 0.0}, alc = cj(al);
+    for (int row = blockIdx.x * RBICG_BLOCK + threadIdx.x; row < n; row += stride) {
       const size_t o = (size_t)s * ld + row;
       cd rv = R[o], rtv = Rt[o];
-      if (upd && act[s]) {
-        const cd al = alphas[s], alc = cj(al);
+      if (on) {
         X[o] = X[o] + al * Pn[o];
         Xt[o] = Xt[o] + alc * Ptn[o];
         rv = rv - al * Q[o];
@@ -1230,16 +1278,17 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sh3(int n, int ld, cd *X, cd *X
         R[o] = rv;
         Rt[o] = rtv;
       }
-      acc[4 * s] += abs2(rv);
-      acc[4 * s + 1] += abs2(rtv);
+      a0 += abs2(rv);
+      a1 += abs2(rtv);
       const cd rho = cj(rtv) * rv;
-      acc[4 * s + 2] += rho.x;
-      acc[4 * s + 3] += rho.y;
+      a2 += rho.x;
+      a3 += rho.y;
     }
+    wput(lds, 4 * SHMAX, 4 * s, a0);
+    wput(lds, 4 * SHMAX, 4 * s + 1, a1);
+    wput(lds, 4 * SHMAX, 4 * s + 2, a2);
+    wput(lds, 4 * SHMAX, 4 * s + 3, a3);
   }
-#pragma unroll
-  for (int t = 0; t < 4 * SHMAX; ++t)
-    if (t < 4 * S) wput(lds, 4 * SHMAX, t, acc[t]);
   __syncthreads();
   bstore(lds, 4 * SHMAX, RBICG_BLOCK / 64, 4 * S, P3);
 }
@@ -1271,8 +1320,13 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
                 const V *p, const V *rt, const V *pt, V *pn, V *ptn, V *z, V *zt, const V *C,
                 const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
                 const double *P3, double *P1, Scalars *S, double *rec, int it, int first, int rp) {
-  hipLaunchKernelGGL((k_it1<V, M>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn, z,
-                     zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
+  // one row per thread when the grid covers the rows, else up to RMAX
+  if ((size_t)nb * IB >= (size_t)A.n)
+    hipLaunchKernelGGL((k_it1<V, M, 1>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn, z,
+                       zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
+  else
+    hipLaunchKernelGGL((k_it1<V, M, RMAX>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn,
+                       z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
 }
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
@@ -1346,7 +1400,11 @@ void launch_d2f(hipStream_t st, const double *in, float *out, size_t n) {
 }
 void launch_add_f2d(hipStream_t st, double *x, const float *d, double sgn, size_t n) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_add_f2d, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
+  hipLaunchKernelGGL(k_add_to_d<float>, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
+}
+void launch_add_d2d(hipStream_t st, double *x, const double *d, double sgn, size_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_add_to_d<double>, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
 }
 int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
 

@@ -316,8 +316,9 @@ struct rbicg_s {
   std::vector<double> last_log;
   int last_count = 0;
   // FP32-inner mode: FP64 outer residuals, float right-hand sides and corrections
-  double *r64 = nullptr, *rt64 = nullptr;
+  double *r64 = nullptr, *rt64 = nullptr, *d64 = nullptr, *dt64 = nullptr;
   float *b32 = nullptr, *bt32 = nullptr, *d32 = nullptr, *dt32 = nullptr;
+  rbicg_s *h64 = nullptr;  // FP64 inner solves after a diverged FP32 one (made on demand)
   int last_dev_status = 0;  // device status code of the last solve_impl run
   // implicit shift: while set, the handle's matrix stands for sigma I - A
   // (used for the shifted pairs of IRKA; A^H becomes conj(sigma) I - A^H)
@@ -905,7 +906,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     hs->maxit = h->opt.maxit;
     if (inner) {
       hs->stag_s = h->opt.s;
-      hs->stag_div = ks > 0 ? 1 : 0;
+      hs->stag_div = 1;
       hs->stag_lim = std::sqrt(tol);
     }
     const bool conv0 = rn <= tol * bn && rtn <= tol * btn;
@@ -1214,9 +1215,9 @@ int install_recycle(rbicg_s *h, const void *Usrc, const void *Utsrc, int k) {
 // The latest cycle's recycle space carries over to the next outer step,
 // re-biorthogonalized (cut svd_tol_eff).  Inner solves also stop at a cycle
 // end without progress (stagnated near the tolerance: the iterate is used;
-// diverged: the correction is discarded and the recycle space dropped); a
-// correction that raises max(||r||/||b||, ||r~||/||b~||) is taken back and
-// the recycle space dropped.
+// diverged: the correction is discarded, the recycle space dropped and the
+// next inner solve taken in FP64 by plain BiCG); a correction that raises
+// max(||r||/||b||, ||r~||/||b~||) is taken back and the recycle space dropped.
 int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double *xt, double tol,
                 rbicg_stats *stp) {
   rbicg_stats st{};
@@ -1235,7 +1236,9 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
   int outer = 0, inner_total = 0, cycles = 0, status = RBICG_NOT_CONVERGED;
   double rel = NAN, relt = NAN;
   double prev = 0.0;     // residual measure before the last applied correction
-  bool applied = false;  // d32, dt32 hold the last applied correction
+  bool applied = false;  // d32, dt32 (or d64, dt64) hold the last applied correction
+  bool applied64 = false, escalate = false;
+  int fp64_inner = 0;
   auto residuals = [&]() -> int {
     launch_residual<double, double>(h->st, A, b, x, h->r64);
     launch_residual<double, double>(h->st, AH, bt, xt, h->rt64);
@@ -1248,8 +1251,13 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
     TRY(residuals());
     if (applied && std::max(rel, relt) > prev) {
       // the correction made things worse: take it back, drop the recycle space
-      launch_add_f2d(h->st, x, h->d32, -1.0, (size_t)n);
-      launch_add_f2d(h->st, xt, h->dt32, -1.0, (size_t)n);
+      if (applied64) {
+        launch_add_d2d(h->st, x, h->d64, -1.0, (size_t)n);
+        launch_add_d2d(h->st, xt, h->dt64, -1.0, (size_t)n);
+      } else {
+        launch_add_f2d(h->st, x, h->d32, -1.0, (size_t)n);
+        launch_add_f2d(h->st, xt, h->dt32, -1.0, (size_t)n);
+      }
       h->ksys = 0;
       h->have_cyc = false;
       TRY(residuals());
@@ -1260,6 +1268,33 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
       break;
     }
     if (outer >= h->opt.max_outer || inner_total >= h->opt.maxit) break;
+    if (escalate) {
+      // FP64 inner solve (plain BiCG) for this outer step, after a diverged FP32 one
+      if (!h->h64) {
+        rbicg_opts o = h->opt;
+        o.prec = RBICG_F64;
+        o.k = 0;
+        o.update = 0;
+        o.profile = 0;
+        TRY(rbicg_create_on(h->mat, &o, &h->h64));
+      }
+      launch_fill_zero<double>(h->st, h->d64, (size_t)n);
+      launch_fill_zero<double>(h->st, h->dt64, (size_t)n);
+      rbicg_stats ist{};
+      const int rc = solve_impl<double, double>(h->h64, h->r64, h->rt64, h->d64, h->dt64, h->opt.inner_tol, &ist);
+      inner_total += ist.iters;
+      ++outer;
+      ++fp64_inner;
+      escalate = false;
+      if (rc < 0 && rc != RBICG_BREAKDOWN) return rc;
+      prev = std::max(rel, relt);
+      applied = true;
+      applied64 = true;
+      launch_add_d2d(h->st, x, h->d64, 1.0, (size_t)n);
+      launch_add_d2d(h->st, xt, h->dt64, 1.0, (size_t)n);
+      HIPCHECK(hipGetLastError());
+      continue;
+    }
     if (h->have_cyc) {
       void *Us = h->Uc[h->cur], *Uts = h->Utc[h->cur];
       const int kc = h->kcyc;
@@ -1282,13 +1317,16 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
     if (rc < 0) return rc;
     ++outer;
     if (h->last_dev_status == ST_DIVERGED) {
-      // discard the correction; continue without a recycle space
+      // discard the correction; continue without a recycle space, the next
+      // inner solve in FP64
       h->ksys = 0;
       h->have_cyc = false;
+      escalate = true;
       continue;
     }
     prev = std::max(rel, relt);
     applied = true;
+    applied64 = false;
     launch_add_f2d(h->st, x, h->d32, 1.0, (size_t)n);
     launch_add_f2d(h->st, xt, h->dt32, 1.0, (size_t)n);
     HIPCHECK(hipGetLastError());
@@ -1302,6 +1340,7 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
   st.status = status;
   st.iters = inner_total;
   st.outer_steps = outer;
+  st.restarts = fp64_inner;
   st.cycles = cycles;
   st.k_used = k_first;
   st.relres = rel;
@@ -1675,6 +1714,8 @@ int alloc_workspace(rbicg_s *h) {
   if (h->vkind == 2) {
     TRY(dalloc(h, (void **)&h->r64, (size_t)h->ld * sizeof(double)));
     TRY(dalloc(h, (void **)&h->rt64, (size_t)h->ld * sizeof(double)));
+    TRY(dalloc(h, (void **)&h->d64, (size_t)h->ld * sizeof(double)));
+    TRY(dalloc(h, (void **)&h->dt64, (size_t)h->ld * sizeof(double)));
     TRY(dalloc(h, (void **)&h->b32, (size_t)h->ld * sizeof(float)));
     TRY(dalloc(h, (void **)&h->bt32, (size_t)h->ld * sizeof(float)));
     TRY(dalloc(h, (void **)&h->d32, (size_t)h->ld * sizeof(float)));
@@ -1893,6 +1934,10 @@ extern "C" int rbicg_destroy(rbicg_handle h) {
   else (void)hipDeviceSynchronize();
   delete h->sw;
   h->sw = nullptr;
+  if (h->h64) {
+    rbicg_destroy(h->h64);
+    h->h64 = nullptr;
+  }
   if (h->own_mat && h->mat) {
     h->mat->A.release();
     h->mat->AH.release();

@@ -160,3 +160,38 @@ def test_host_eig_ill_conditioned_pencil_matches_qz():
     for j in np.argsort(np.abs(lam))[:8]:
         res = np.linalg.norm(P @ W[:, j] - lam[j] * (Q @ W[:, j]))
         assert res <= 1e-12 * (np.linalg.norm(P, 2) + abs(lam[j]) * np.linalg.norm(Q, 2))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_host_eig_real_pencils_backward_error(seed):
+    """Real pencils take the real double-shift QZ: every right and left
+    eigenpair has a backward error at rounding level, conjugate pairs stay
+    paired, and the eigenvalues match scipy's, also with an ill-conditioned Q
+    (condition 1e9, as the harmonic Ritz pencils reach)."""
+    lib = _lib.load()
+    rng = np.random.default_rng(100 + seed)
+    m = int(rng.integers(5, 61))
+    P = rng.standard_normal((m, m))
+    Q = rng.standard_normal((m, m))
+    if seed % 2:
+        U, _, Vt = np.linalg.svd(Q)
+        Q = U @ np.diag(np.logspace(0, -9, m)) @ Vt
+    lam = np.zeros(2 * m); W = np.zeros(2 * m * m); Wl = np.zeros(2 * m * m)
+    Pb, Qb = _c(P), _c(Q)
+    assert lib.rbicg_host_eig(m, _lib.dptr(Pb), _lib.dptr(Qb), _lib.dptr(lam), _lib.dptr(W),
+                              _lib.dptr(Wl)) == 0
+    lam = lam.view(np.complex128)
+    W = _uc(W, m, m); Wl = _uc(Wl, m, m)
+    nP, nQ = np.linalg.norm(P, 2), np.linalg.norm(Q, 2)
+    for i in range(m):
+        if not np.isfinite(lam[i]) or abs(lam[i]) > 1e8:
+            continue
+        sc = nP + abs(lam[i]) * nQ
+        assert np.linalg.norm(P @ W[:, i] - lam[i] * (Q @ W[:, i])) <= 1e-12 * sc
+        assert np.linalg.norm(Wl[:, i].conj() @ P - lam[i] * (Wl[:, i].conj() @ Q)) <= 1e-12 * sc
+        if abs(lam[i].imag) > 1e-8 * abs(lam[i]):
+            assert np.min(np.abs(lam - np.conj(lam[i]))) <= 1e-8 * abs(lam[i])
+    ref = sla.eigvals(P, Q)
+    ref = ref[np.isfinite(ref) & (np.abs(ref) < 1e6)]
+    for z in ref:
+        assert np.min(np.abs(lam - z)) <= 1e-6 * max(1.0, abs(z))
