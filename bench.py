@@ -60,6 +60,11 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving trace (continuous batching, p50/p99 latency) instead")
+    ap.add_argument("--serving-n", type=int, default=40, help="requests in the serving trace")
+    ap.add_argument("--serving-lam", type=float, default=50.0, help="arrival rate (req/s)")
+    ap.add_argument("--serving-slots", type=int, default=4, help="concurrent request slots")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-inner / FP64-outer leg (128^3, 8 systems)")
     ap.add_argument("--no-shifted", action="store_true",
@@ -197,12 +202,72 @@ def mixed_leg(args):
     sts = one_pass()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same systems with plain FP64 RBiCG (same k, s) to the same true residual
+    S64 = Solver(M, k=seq.k, s=seq.s, prec="f64", maxit=20000)
+    xs = torch.zeros_like(bs[0])
+    xts = torch.zeros_like(bts[0])
+
+    def pass64():
+        S64.set_recycle(None, None)
+        out = []
+        for j in range(len(bs)):
+            if j:
+                S64.update_recycle()
+            xs.zero_()
+            xts.zero_()
+            _, _, st = S64.solve(bs[j], bts[j], xs, xts, tol=seq.tol)
+            out.append(st)
+        return out
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s64 = pass64()
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t1
+    fp64 = {"solves_per_s": round(len(s64) / dt64, 3), "ms_per_pass": round(dt64 * 1e3, 1),
+            "iters": [st["iters"] for st in s64],
+            "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in s64),
+            "all_converged": all(st["status"] == 0 for st in s64)}
     return {"workload": "convdiff3d_128^3_beta(50,25,10)_8systems_k30_s40_fp32inner_fp64outer_tol1e-10",
+            "fp64_rbicg_same_accuracy": fp64,
+            "fp64_inner_fallbacks": [st["restarts"] for st in sts],
             "n": M.n, "solves_per_s": round(len(sts) / dt, 3), "ms_per_pass": round(dt * 1e3, 1),
             "inner_iters": [st["iters"] for st in sts], "outer_steps": [st["outer_steps"] for st in sts],
             "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in sts),
             "all_converged": all(st["status"] == 0 for st in sts),
             "precision": "FP32 storage and SpMV inside FP64 refinement"}
+
+
+def serving_main(args):
+    """Config-5 serving: a Poisson trace of requests (each 4-12 dual systems of
+    3D convection-diffusion, grid edge in {32, 48, 64, 96, 128}, beta ~
+    U[1,50]^3, k in {10, 20}), FP32-inner / FP64-outer to an FP64 true
+    residual of 1e-8, served with continuous batching; then the same trace
+    through one-at-a-time plain FP64 RBiCG at the same accuracy.  Prints one
+    JSON line with p50 / p99 latency and throughput of both."""
+    import torch
+    from paper_1010_0762_amd import serving
+    from paper_1010_0762_amd import workloads as wl
+    torch.cuda.set_device(0)
+    trace = wl.cfg5_trace(nreq=args.serving_n, lam=args.serving_lam)
+    # warm-up: one small request through each mode (library load, first launches)
+    warm = [wl.Request(10 ** 6, 0.0, 32, (10.0, 5.0, 2.0), 2, 10, 1)]
+    serving.Server(slots=1, prec="mixed").run(warm)
+    serving.Server(slots=1, prec="f64").run(warm)
+    out = {"metric": "p50/p99 latency served (config 5 trace)", "unit": "s",
+           "trace": {"requests": len(trace), "lambda_per_s": args.serving_lam,
+                     "systems": sum(r.nsys for r in trace),
+                     "edges": sorted({r.edge for r in trace})}}
+    for name, slots, prec in (("batched_fp32_inner", args.serving_slots, "mixed"),
+                              ("one_at_a_time_fp64", 1, "f64")):
+        srv = serving.Server(slots=slots, prec=prec, tol=1e-8)
+        srv.prepare(trace)
+        torch.cuda.synchronize()
+        res = srv.run(trace)
+        summ = serving.latency_summary(res)
+        summ["slots"] = slots
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -211,6 +276,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.serving:
+        serving_main(args)
+        return
     import torch
     from paper_1010_0762_amd import workloads as wl
     from paper_1010_0762_amd.solver import Solver, DeviceMatrix

@@ -151,6 +151,9 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
         else:
             q, qt = z, zt
         sigma = float(pt.astype(f64) @ q.astype(f64))
+        if sigma == 0.0 or not np.isfinite(sigma):
+            diverged = True      # breakdown in float storage: treated as divergence
+            break
         alpha = rho / sigma
         if kc:
             zeta_c += alpha * zeta
@@ -178,6 +181,9 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
         rt = _f32(rt.astype(f64) - alpha * qt.astype(f64))
         rho_new = float(rt.astype(f64) @ r.astype(f64))
         rn = np.linalg.norm(r.astype(f64)); rtn = np.linalg.norm(rt.astype(f64))
+        if rho_new == 0.0 or not (np.isfinite(rho_new) and np.isfinite(rn) and np.isfinite(rtn)):
+            diverged = True
+            break
         if update and len(V) == s:
             cyc.update(A64, AH64, V, Vt, np.asarray(ca), np.asarray(cb), np.asarray(cr))
             V, Vt, ca, cb, cr = [], [], [], [], []

@@ -218,6 +218,7 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
     restarts = 0
     reseeds = 0
     bn = btn = None
+    x_init, xt_init = x.copy(), xt.copy()
     while True:
         # steps 1-2: eq. minusXR
         r_m1 = b - A @ x
@@ -255,6 +256,8 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
         V, Vt, c_alpha, c_beta, c_rn = [], [], [], [], []
         converged = rn <= tol * bn and rtn <= tol * btn
         status = "ok" if converged else "maxit"
+        # cycle-end values of max(||r||/||b||, ||r~||/||b~||), smallest so far
+        best = [max(rn / bn, rtn / btn)]
         i = 0
         while not converged and total < maxit:
             i += 1
@@ -305,8 +308,29 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
                 status = "ok"; break
             if rho_new == 0 or not np.isfinite(rho_new):
                 status = "breakdown"; break
+            if kc and i % s == 0:
+                # Stall guard (reading, not in the paper): an oblique projector
+                # with nearly orthogonal C and C~ can keep the iteration from
+                # converging on strongly non-normal operators.  When the
+                # smallest cycle-end residual has not halved over four cycles,
+                # the solve starts again from its initial guess without the
+                # recycle space.
+                c = i // s
+                best.append(min(best[-1], max(rn / bn, rtn / btn)))
+                if c >= 4 and best[c] >= 0.5 * best[c - 4]:
+                    status = "stalled"; break
             beta = rho_new / rho
             rho = rho_new
+        if status == "stalled":
+            x, xt = x_init.copy(), xt_init.copy()
+            U = Ut = C = Ct = None
+            kc = 0
+            cyc = _CycleState(None, None, kk, s, real_problem, svd_tol)
+            if restarts < max_restarts and total < maxit:
+                restarts += 1
+                continue
+            status = "maxit"
+            break
         # step 7
         if kc:
             x = x - U @ zeta_c

@@ -20,14 +20,16 @@ struct cd {
 struct Scalars {
   double tol, bn, btn;
   int iter, done, status, maxit;
-  // FP32-inner solves: at every stag_s-th iteration (cycle end), with the
-  // relative residual max(||r||/||b||, ||r~||/||b~||) now (cur) and at the
-  // previous cycle end (prev): stop as stagnated if cur <= stag_lim and
-  // cur >= prev / 2; with stag_div set (a recycle space is in use), from the
-  // second cycle on, stop when the smallest cycle-end value has not halved
-  // over the last two cycles (diverged if it is above stag_lim, else
-  // stagnated).  stag_s = 0: off
-  int stag_s, stag_div;
+  // Cycle-end guards.  At every stag_s-th iteration of the run that started
+  // after iteration stag_base (a cycle end), with the relative residual
+  // max(||r||/||b||, ||r~||/||b~||) now (cur) and at the previous cycle end
+  // (prev): stop as stagnated if cur <= stag_lim and cur >= prev / 2; with
+  // stag_div set, from cycle stag_w on, stop when the smallest cycle-end
+  // value has not halved over the last stag_w cycles (diverged if it is above
+  // stag_lim, else stagnated).  stag_s = 0: off.  FP32-inner solves use
+  // stag_w = 2 and stag_lim = sqrt(inner tol); solves with a recycle space
+  // use stag_w = 4 and stag_lim = 0 (the stall guard).
+  int stag_s, stag_div, stag_w, stag_base;
   double stag_lim;
   double zbuf[4 * KMAXD];
   double zc[4 * KMAXD];

@@ -263,20 +263,20 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
   if (rn <= S->tol * S->bn && rtn <= S->tol * S->btn) st = ST_CONVERGED;
   else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
   else if (it > S->maxit) st = ST_MAXIT;
-  else if (S->stag_s > 0 && (it - 1) % S->stag_s == 0 && it - 1 >= S->stag_s) {
-    // cycle end c = (it-1)/s: the smallest cycle-end value so far is kept in
+  else if (S->stag_s > 0 && (it - 1 - S->stag_base) % S->stag_s == 0 && it - 1 - S->stag_base >= S->stag_s) {
+    // cycle end c of the run: the smallest cycle-end value so far is kept in
     // slot 9 of the cycle-end rows (the host writes that slot only after the run)
-    const int s = S->stag_s, c = (it - 1) / s;
+    const int s = S->stag_s, base = S->stag_base, c = (it - 1 - base) / s;
     auto h = [&](int cc) {
-      const double *R = rec + (size_t)cc * s * LOG_STRIDE;
+      const double *R = rec + (size_t)(base + cc * s) * LOG_STRIDE;
       return fmax(R[6] / S->bn, R[7] / S->btn);
     };
-    auto best_of = [&](int cc) { return cc == 0 ? h(0) : rec[(size_t)cc * s * LOG_STRIDE + 9]; };
+    auto best_of = [&](int cc) { return cc == 0 ? h(0) : rec[(size_t)(base + cc * s) * LOG_STRIDE + 9]; };
     const double cur = fmax(rn / S->bn, rtn / S->btn);
     const double best = fmin(best_of(c - 1), cur);
     if (lead) Rm1[9] = best;
     if (cur <= S->stag_lim && cur >= 0.5 * h(c - 1)) st = ST_STAGNATED;
-    else if (S->stag_div && c >= 2 && best >= 0.5 * best_of(c - 2))
+    else if (S->stag_div && c >= S->stag_w && best >= 0.5 * best_of(c - S->stag_w))
       st = best > S->stag_lim ? ST_DIVERGED : ST_STAGNATED;
   }
   if (st != ST_RUNNING) {

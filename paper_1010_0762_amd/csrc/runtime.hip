@@ -285,6 +285,7 @@ struct rbicg_s {
   long prof_chunks = 0;              // chunks launched since the handle was made
   // iteration vectors (x, x~ are the caller's)
   void *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr}, *pt[2] = {nullptr, nullptr};
+  void *xs0 = nullptr, *xts0 = nullptr;  // initial guesses of the current solve
   void *z = nullptr, *zt = nullptr, *q = nullptr, *qt = nullptr, *t1 = nullptr, *t2 = nullptr;
   // recycle space of the current system
   void *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr;
@@ -845,9 +846,9 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   // FP32 storage (inner solves): every iteration re-projects r_{i-1}, r~_{i-1}
   // onto the complements of range(C), range(C~) inside k_it1/k_it2 (a no-op in
   // exact arithmetic; see k_it2)
-  const int rp = (inner && VK<V>::kind == 0 && sizeof(V) == 4 && h->ksys > 0) ? 1 : 0;
+  int rp = 0;
   V *r = (V *)h->r, *rt = (V *)h->rt;
-  const int ks = h->ksys;
+  int ks = h->ksys;  // recycle dimension of the current run (a stalled run drops it)
   const V *U = (const V *)h->U, *Ut = (const V *)h->Ut, *C = (const V *)h->C, *Ct = (const V *)h->Ct;
   cplx d[3];
   TRY(host_dots<V>(h, b, b, bt, bt, nullptr, nullptr, d));
@@ -857,7 +858,12 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   bool first = true;
   std::vector<double> fulllog;
   std::deque<std::unique_ptr<CycleJob>> jobs;
+  if (ks > 0 && !inner) {  // initial guesses, for a restart after a stall
+    HIPCHECK(hipMemcpyAsync(h->xs0, x, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+    HIPCHECK(hipMemcpyAsync(h->xts0, xt, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+  }
   while (true) {
+    rp = (inner && VK<V>::kind == 0 && sizeof(V) == 4 && ks > 0) ? 1 : 0;
     // eq. minusXR: r_{-1} = b - A x, projection with C, C~
     launch_residual<V, M>(h->st, A, b, x, r);
     launch_residual<V, M>(h->st, AH, bt, xt, rt);
@@ -904,10 +910,17 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     hs->btn = btn;
     hs->iter = total;
     hs->maxit = h->opt.maxit;
+    hs->stag_base = total;
     if (inner) {
       hs->stag_s = h->opt.s;
+      hs->stag_w = 2;
       hs->stag_div = 1;
       hs->stag_lim = std::sqrt(tol);
+    } else if (ks > 0) {
+      hs->stag_s = h->opt.s;
+      hs->stag_w = 4;
+      hs->stag_div = 1;
+      hs->stag_lim = 0.0;
     }
     const bool conv0 = rn <= tol * bn && rtn <= tol * btn;
     hs->done = conv0 ? 1 : 0;
@@ -1150,6 +1163,21 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       for (size_t t = 0; t < tmp.size(); t += LOG_STRIDE) tmp[t + 9] = restarts;
       fulllog.insert(fulllog.end(), tmp.begin(), tmp.end());
     }
+    if (status == ST_DIVERGED && !inner) {
+      // stall guard: start again from the initial guesses without the
+      // recycle space (the cycle spaces of the stalled run are dropped too)
+      HIPCHECK(hipMemcpyAsync(x, h->xs0, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+      HIPCHECK(hipMemcpyAsync(xt, h->xts0, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+      ks = 0;
+      h->ksys = 0;
+      h->have_cyc = false;
+      if (restarts < h->opt.max_restarts && total < h->opt.maxit) {
+        ++restarts;
+        continue;
+      }
+      status = ST_MAXIT;
+      break;
+    }
     // Algorithm 2 step 7: x -= U zeta_c, x~ -= U~ zeta~_c
     if (ks > 0)
       launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
@@ -1287,6 +1315,10 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
       ++fp64_inner;
       escalate = false;
       if (rc < 0 && rc != RBICG_BREAKDOWN) return rc;
+      if (rc == RBICG_BREAKDOWN) {
+        status = RBICG_BREAKDOWN;
+        break;
+      }
       prev = std::max(rel, relt);
       applied = true;
       applied64 = true;
@@ -1310,13 +1342,9 @@ int solve_mixed(rbicg_s *h, const double *b, const double *bt, double *x, double
     inner_total += ist.iters;
     cycles += ist.cycles;
     st.reseeds += ist.reseeds;
-    if (rc == RBICG_BREAKDOWN) {
-      status = RBICG_BREAKDOWN;
-      break;
-    }
-    if (rc < 0) return rc;
+    if (rc < 0 && rc != RBICG_BREAKDOWN) return rc;
     ++outer;
-    if (h->last_dev_status == ST_DIVERGED) {
+    if (h->last_dev_status == ST_DIVERGED || h->last_dev_status == ST_BREAKDOWN) {
       // discard the correction; continue without a recycle space, the next
       // inner solve in FP64
       h->ksys = 0;
@@ -1698,7 +1726,7 @@ int dispatch(rbicg_s *h, F &&f) {
 int alloc_workspace(rbicg_s *h) {
   const size_t vbytes = (size_t)h->ld * h->vb;
   void **vecs[] = {&h->r, &h->rt, &h->p[0], &h->p[1], &h->pt[0], &h->pt[1], &h->z, &h->zt,
-                   &h->q, &h->qt, &h->t1, &h->t2};
+                   &h->q, &h->qt, &h->t1, &h->t2, &h->xs0, &h->xts0};
   for (void **v : vecs) TRY(dalloc(h, v, vbytes));
   const size_t kb = vbytes * std::max(1, h->kcap);
   void **bases[] = {&h->U, &h->Ut, &h->C, &h->Ct, &h->Ua, &h->Uta, &h->Ca, &h->Cta,
