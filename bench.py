@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per completed k_it1 launch on this workload, from the FETCH_SIZE
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
 # 512 MiB device copy), valid only for the kernel source they were taken on
-TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "dd11e851f864965b", "bytes_per_launch": 99.90e6}
+TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "270da939cf506cbb", "bytes_per_launch": 100.72e6}
 
 
 def traffic_k_it1():
@@ -118,8 +118,7 @@ def kernel_at_k20(args, seq, mats, b, bt):
     dt = time.perf_counter() - t0
     prof = S.profile(reset=True)
     avg = {name: prof[f"{key}_ms"] / max(prof[f"{key}_n"], 1) * 1e3
-           for name, key in (("spmv_restrict", "spmv"), ("expand_sigma", "expand"),
-                             ("update_norms", "update"))}
+           for name, key in (("spmv_restrict", "spmv"), ("expand_update", "update"))}
     gbs = prof["spmv_bytes_total"] / (prof["spmv_ms"] * 1e-3) / 1e9
     per_iter = dt / st["iters"]
     return {"k_used": st["k_used"], "iters": st["iters"], "relres": st["relres"],
@@ -337,8 +336,7 @@ def main():
     eff_gbs = iter_bytes * tot_iters / elapsed / 1e9
     kernels = {
         "spmv_restrict": (prof["spmv_ms"], prof["spmv_n"]),
-        "expand_sigma": (prof["expand_ms"], prof["expand_n"]),
-        "update_norms": (prof["update_ms"], prof["update_n"]),
+        "expand_update": (prof["update_ms"], prof["update_n"]),
     }
     roof = None
     if prof["spmv_n"] > 0:
@@ -353,8 +351,13 @@ def main():
                 "alg_bytes_per_launch": round(bytes_per_launch),
                 "launches": prof["spmv_n"]}
     kernel_gbs = {name: round(prof[f"{key}_bytes_total"] / max(prof[f"{key}_ms"], 1e-12) * 1e-6, 1)
-                  for name, key in (("spmv_restrict", "spmv"), ("expand_sigma", "expand"),
-                                    ("update_norms", "update"))}
+                  for name, key in (("spmv_restrict", "spmv"), ("expand_update", "update"))}
+    nup = max(prof["cycle_updates"], 1)
+    cycle_end = {"updates": prof["cycle_updates"],
+                 "eig_ms_avg": round(prof["cycle_eig_ms"] / nup, 3),
+                 "biorth_ms_avg": round(prof["cycle_biorth_ms"] / nup, 3),
+                 "latency_ms_avg": round(prof["cycle_latency_ms"] / nup, 3),
+                 "iteration_wait_ms_total": round(prof["cycle_wait_ms"], 2)}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
     shifted = None if args.no_shifted else shifted_leg(args)
     mixed = None if args.no_mixed else mixed_leg(args)
@@ -387,6 +390,7 @@ def main():
                          for k, v in kernels.items()},
         "kernel_alg_gbs": kernel_gbs,
         "profiled_timed_region": bool(args.profile_timed),
+        "cycle_end": cycle_end,
         "roofline": roof,
         "kernel_at_k20": k20,
         "shifted_pairs": shifted,

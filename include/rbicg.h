@@ -146,15 +146,20 @@ int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);
 int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next);
 
 /* Kernel timing of the iteration kernels accumulated while opts.profile is
- * set: out[0..5] = total ms and launch count of (1) the fused direction
- * update + paired SpMV + restriction kernel, (2) the expansion + (p~, q)
- * kernel, (3) the recurrence update + norms kernel (HIP events recorded
- * before and after each launch of the sampled chunks); out[6] =
- * algorithmic bytes of one launch of kernel (1) with the current recycle
- * dimension, out[7] = algorithmic bytes of one iteration; out[8..10] = total
- * algorithmic bytes of the timed launches of kernels (1)-(3) (each launch
- * counted with the recycle dimension it ran with).  reset = 1 clears the
- * counters after reading.  out: host array of 11 doubles. */
+ * set: out[0..3] = total ms and launch count of (1) the fused direction
+ * update + paired SpMV + restriction kernel and (2) the fused expansion +
+ * recurrence update + norms kernel (HIP events recorded before and after
+ * each launch of the sampled chunks); out[4] = algorithmic bytes of one
+ * launch of kernel (1) with the current recycle dimension, out[5] =
+ * algorithmic bytes of one iteration; out[6..7] = total algorithmic bytes of
+ * the timed launches of kernels (1) and (2) (each launch counted with the
+ * recycle dimension it ran with); out[8..12] = cycle-end telemetry (kept
+ * whether or not opts.profile is set): recycle-space updates completed, total
+ * host ms of their harmonic Ritz eigenproblems, total host ms of their
+ * biorthogonalizations, total ms from each update's first enqueue to its
+ * last, total ms the iteration launches waited for an update to release its
+ * cycle buffers.  reset = 1 clears the counters after reading.  out: host
+ * array of 13 doubles. */
 int rbicg_profile(rbicg_handle h, int32_t reset, double *out);
 
 /* Create a handle for matrix A (problem statement, Sec. 1).  AH may be NULL,

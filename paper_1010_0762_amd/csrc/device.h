@@ -13,10 +13,9 @@ struct cd {
 };
 
 // Per-handle scalar block in device memory.  Vectors of k complex or real
-// values are stored as doubles (ND = 1 or 2 per value): zbuf holds
-// [zeta_i | zeta~_i] of the current iteration, zc holds [zeta_c | zeta~_c],
-// gbuf holds host-requested restrictions, red the results of host-requested
-// dot products.
+// values are stored as doubles (ND = 1 or 2 per value): zc holds
+// [zeta_c | zeta~_c], gbuf holds host-requested restrictions, red the
+// results of host-requested dot products.
 struct Scalars {
   double tol, bn, btn;
   int iter, done, status, maxit;
@@ -31,7 +30,6 @@ struct Scalars {
   // use stag_w = 4 and stag_lim = 0 (the stall guard).
   int stag_s, stag_div, stag_w, stag_base;
   double stag_lim;
-  double zbuf[4 * KMAXD];
   double zc[4 * KMAXD];
   double gbuf[4 * KMAXD];
   double red[32];

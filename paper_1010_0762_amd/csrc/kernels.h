@@ -21,13 +21,9 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
                 const double *P3, double *P1, Scalars *S, double *rec, int it, int first,
                 int rp);
 template <class V>
-void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
-                const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
-                double *P2, Scalars *S, V *r, V *rt, int rp);
-template <class V>
-void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
-                const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
-                Scalars *S, double *rec, int it, int rp);
+void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
+                const V *ptn, const V *z, const V *zt, const V *C, const V *Ct, int k, int ld,
+                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp);
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
                   int first);

@@ -1,7 +1,7 @@
 // gfx950 kernels of the RBiCG hot path (Algorithm 2) and of the cycle-end
 // recycle-space computations (Sec. 4).
 //
-// One iteration i of Algorithm 2 is three launches.  No kernel synchronizes
+// One iteration i of Algorithm 2 is two launches.  No kernel synchronizes
 // its grid: each writes one partial sum per block, and every block of the
 // NEXT kernel reduces those partials itself, in a fixed order (so every block
 // obtains bit-identical scalars and runs are deterministic; no atomics, no
@@ -10,21 +10,22 @@
 //          test; beta_{i-1} = rho_{i-1} / rho_{i-2};
 //          p = r + beta p, p~ = r~ + conj(beta) p~ (own rows written, gathered
 //          rows recomputed on the fly), z = A p, z~ = A^H p~ from the two
-//          sliced-ELL matrices (no atomics), partials of zeta = C~^H z and
-//          zeta~ = C^H z~;
-//   k_it2  reduce zeta, zeta~; q = z - C zeta, q~ = z~ - C~ zeta~; partials of
-//          sigma = (p~, q);
-//   k_it3  reduce sigma; alpha = rho_{i-1} / sigma, zeta_c += alpha zeta,
-//          zeta~_c += conj(alpha) zeta~; x += alpha p, x~ += conj(alpha) p~,
-//          r -= alpha q, r~ -= conj(alpha) q~; partials of ||r||^2, ||r~||^2,
-//          (r~, r).
+//          sliced-ELL matrices (no atomics), partials of zeta = C~^H z,
+//          zeta~ = C^H z~, e = p~^H C and (p~, z);
+//   k_it2  reduce them; sigma = (p~, q) for q = z - C zeta is assembled as
+//          (p~, z) - e zeta (the same sum by linearity, so q need not exist
+//          before sigma); alpha = rho_{i-1} / sigma, zeta_c += alpha zeta,
+//          zeta~_c += conj(alpha) zeta~; per row q = z - C zeta,
+//          q~ = z~ - C~ zeta~ (kept in registers), x += alpha p,
+//          x~ += conj(alpha) p~, r -= alpha q, r~ -= conj(alpha) q~; partials
+//          of ||r||^2, ||r~||^2, (r~, r).
 // In FP32-storage inner solves (flag rp) k_it1 also forms partials of
 // g = C~^H r_{i-1}, g~ = C^H r~_{i-1}; k_it2 re-projects r_{i-1} -= C g,
-// r~_{i-1} -= C~ g~ and k_it3 subtracts g, g~ from zeta_c, zeta~_c, which
-// keeps x - U zeta_c consistent.  In exact arithmetic g = 0 (the recurrences
-// keep r orthogonal to range(C~), Sec. 3.1); in float storage the rounding of
-// every update feeds C~^H r, the oblique projector amplifies it and the
-// iteration stagnates without this step.
+// r~_{i-1} -= C~ g~ before its update and subtracts g, g~ from zeta_c,
+// zeta~_c, which keeps x - U zeta_c consistent.  In exact arithmetic g = 0
+// (the recurrences keep r orthogonal to range(C~), Sec. 3.1); in float
+// storage the rounding of every update feeds C~^H r, the oblique projector
+// amplifies it and the iteration stagnates without this step.
 // Block 0 records the scalars of every iteration for the host.  Every launch
 // first reads the device 'done' flag and returns at once after the stopping
 // test has fired, so the host may enqueue iterations ahead of the test.
@@ -123,6 +124,36 @@ template <> __device__ __forceinline__ cd get<cd>(const double *v, int idx) {
 template <class T> __device__ __forceinline__ void set(double *v, int idx, T x) {
 #pragma unroll
   for (int c = 0; c < ND<T>::v; ++c) v[idx * ND<T>::v + c] = comp(x, c);
+}
+
+// Sum over the 64 lanes of a wave of 16 values per lane, by recursive
+// halving: at offset o the lanes l and l^o split the values they still hold,
+// each keeps one half and adds the partner's copy of it.  After offsets 32,
+// 16, 8 and 4 lane l holds value (l >> 2) summed over the 16 lanes that share
+// bits 0-1 of l; offsets 1 and 2 complete the sum, so every lane of a quad
+// returns the same total.  17 exchanges replace the 16 x 6 of separate wave
+// sums, and the independent exchanges of one step issue back to back.  The
+// order is fixed, so the bits are reproducible.
+template <int H>
+__device__ __forceinline__ void halve_step(double (&v)[16], int lane, int o) {
+  const bool hi = lane & o;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = hi ? v[i] : v[i + H];
+    const double keep = hi ? v[i + H] : v[i];
+    v[i] = keep + __shfl_xor(send, o, 64);
+  }
+}
+__device__ __forceinline__ double wave_sum16(double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  halve_step<8>(v, lane, 32);
+  halve_step<4>(v, lane, 16);
+  halve_step<2>(v, lane, 8);
+  halve_step<1>(v, lane, 4);
+  double s = v[0];
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  return s;
 }
 
 // Block partial: P[block * nv + t] = sum over the waves (fixed order) of the
@@ -300,6 +331,58 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
   return true;
 }
 
+// LDS row stride (doubles) of the k_it1 partials: (3k + 1) values, plus 2k
+// with re-projection, times the components of T
+#define P1S (6 * KMAXD + 2)
+
+// Restriction partials of one group of GC columns per pass over the block's
+// rows (one row per thread): C~_j^H u, C_j^H u~ and, with NPC = 3, the row's
+// share of (p~^H C)_j.  All 2 GC column loads of a group are in flight
+// together (clamped indices; columns past k are zeroed) and the group's 16
+// wave sums share one halving exchange.  The three kinds go to LDS values
+// base_a + j, base_b + j, base_e + j.
+template <int NPC, class V, class T>
+__device__ __forceinline__ void restrict_group(const V *__restrict__ C, const V *__restrict__ Ct,
+                                               int k, int ld, size_t rowc, T u, T ut, T cpt,
+                                               double *lds, int base_a, int base_b, int base_e) {
+  constexpr int NDV = ND<T>::v;
+  constexpr int GC = 16 / (NPC * NDV);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < k; j0 += GC) {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0.0;
+#pragma unroll
+    for (int g = 0; g < GC; ++g) {
+      const int j = j0 + g;
+      const size_t off = (size_t)(j < k ? j : k - 1) * ld + rowc;
+      T ctv = up(Ct[off]), cv = up(C[off]);
+      if (j >= k) {
+        ctv = zero<T>();
+        cv = zero<T>();
+      }
+      const T a = cj(ctv) * u, b = cj(cv) * ut;
+#pragma unroll
+      for (int c = 0; c < NDV; ++c) {
+        v[g * NDV + c] = comp(a, c);
+        v[(GC + g) * NDV + c] = comp(b, c);
+      }
+      if constexpr (NPC == 3) {
+        const T e = cpt * cv;
+#pragma unroll
+        for (int c = 0; c < NDV; ++c) v[(2 * GC + g) * NDV + c] = comp(e, c);
+      }
+    }
+    const double sum = wave_sum16(v);
+    const int id = lane >> 2;
+    if ((lane & 3) == 0 && id < NPC * GC * NDV) {
+      const int h = id / (GC * NDV), g = (id % (GC * NDV)) / NDV, c = id % NDV, j = j0 + g;
+      const int base = h == 0 ? base_a : (h == 1 ? base_b : base_e);
+      if (j < k) lds[wv * P1S + (base + j) * NDV + c] = sum;
+    }
+  }
+}
+
 }  // namespace
 
 // ===================================================================== kernels
@@ -312,7 +395,8 @@ __global__ __launch_bounds__(IB) void k_it1(
     double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp) {
   using T = typename Ar<V>::T;
   if (S->done) return;
-  __shared__ double lds[NW * 4 * KMAXD];
+  rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
+  __shared__ double lds[NW * P1S];
   __shared__ double tmp[IB];
   __shared__ double red[8];
   T beta;
@@ -321,20 +405,25 @@ __global__ __launch_bounds__(IB) void k_it1(
   const int n = A.n;
   const int stride = gridDim.x * IB;
   const int row0 = blockIdx.x * IB + threadIdx.x;
-  T zr[RPT], ztr[RPT], rr_[RPT], rtr_[RPT];
+  // per row: z, z~, r_{i-1}, r~_{i-1} and conj(p~) as stored
+  T zr[RPT], ztr[RPT], rr_[RPT], rtr_[RPT], cpt[RPT];
+  T s0 = zero<T>();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     zr[q] = zero<T>();
     ztr[q] = zero<T>();
     rr_[q] = zero<T>();
     rtr_[q] = zero<T>();
+    cpt[q] = zero<T>();
     const int row = row0 + q * stride;
     if (row < n) {
       const V rv = r[row], rtv = rt[row];
       rr_[q] = up(rv);
       rtr_[q] = up(rtv);
       pn[row] = down<V>(up(rv) + beta * up(p[row]));
-      ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
+      const V ptv = down<V>(up(rtv) + betac * up(pt[row]));
+      ptn[row] = ptv;
+      cpt[q] = cj(up(ptv));
       // one row per thread: the unrolled gathers fit the register budget
       T za, zb;
       if constexpr (RPT == 1) {
@@ -348,6 +437,7 @@ __global__ __launch_bounds__(IB) void k_it1(
       const T zzt = up(down<V>(zb));
       zr[q] = zz;
       ztr[q] = zzt;
+      s0 += cpt[q] * zz;
       z[row] = down<V>(zz);
       zt[row] = down<V>(zzt);
       if (capR) {
@@ -358,105 +448,83 @@ __global__ __launch_bounds__(IB) void k_it1(
       }
     }
   }
-  if (k == 0) return;
-  const int ls = 4 * KMAXD;
-  for (int j = 0; j < k; ++j) {
-    T a = zero<T>(), b = zero<T>(), c = zero<T>(), d = zero<T>();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int row = row0 + q * stride;
-      if (row < n) {
-        const T ctv = cj(up(Ct[(size_t)j * ld + row])), cv = cj(up(C[(size_t)j * ld + row]));
-        a += ctv * zr[q];
-        b += cv * ztr[q];
-        c += ctv * rr_[q];
-        d += cv * rtr_[q];
-      }
-    }
-    put<T>(lds, ls, j, a);
-    put<T>(lds, ls, k + j, b);
-    if (rp) {
-      put<T>(lds, ls, 2 * k + j, c);
-      put<T>(lds, ls, 3 * k + j, d);
-    }
-  }
-  __syncthreads();
-  bstore(lds, ls, NW, (rp ? 4 : 2) * k * ND<T>::v, P1);
-}
-
-//          with rp set (FP32 storage), also r_{i-1} -= C g, r~_{i-1} -= C~ g~
-//          for the g = C~^H r_{i-1}, g~ = C^H r~_{i-1} whose partials k_it1
-//          wrote (re-projection; block 0 keeps g, g~ in S->gbuf for k_it3).
-template <class V>
-__global__ __launch_bounds__(IB) void k_it2(int n, const V *__restrict__ z,
-                                            const V *__restrict__ zt, const V *__restrict__ C,
-                                            const V *__restrict__ Ct, int k, int ld,
-                                            const V *__restrict__ ptn, V *__restrict__ q,
-                                            V *__restrict__ qt, const double *__restrict__ P1,
-                                            double *__restrict__ P2, Scalars *S,
-                                            V *__restrict__ r, V *__restrict__ rt, int rp) {
-  using T = typename Ar<V>::T;
-  if (S->done) return;
-  __shared__ double lds[NW * 2];
-  __shared__ double tmp[IB];
-  __shared__ double zl[4 * KMAXD];
-  const int nz = 2 * k * ND<T>::v;
-  const int nv1 = (rp ? 2 : 1) * nz;
+  // partial layout (values of T): zeta = C~^H z at [0, k), zeta~ = C^H z~ at
+  // [k, 2k), e = (p~^H C) at [2k, 3k), (p~, z) at 3k; with rp also
+  // g = C~^H r_{i-1} at [3k+1, 4k+1) and g~ = C^H r~_{i-1} at [4k+1, 5k+1).
+  // k_it2 assembles sigma = (p~, q) = (p~, z) - e zeta from them.
+  put<T>(lds, P1S, 3 * k, s0);
   if (k > 0) {
-    breduce(P1, gridDim.x, nv1, tmp, zl);
-    if (blockIdx.x == 0) {
-      for (int t = threadIdx.x; t < nz; t += IB) S->zbuf[t] = zl[t];
-      if (rp)
-        for (int t = threadIdx.x; t < nz; t += IB) S->gbuf[t] = zl[nz + t];
-    }
-  }
-  const int stride = gridDim.x * IB;
-  T part = zero<T>();
-  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
-    T qq = up(z[row]);
-    T qqt = up(zt[row]);
-    if (k > 0) {
-      T s = zero<T>(), st = zero<T>(), g = zero<T>(), gt = zero<T>();
+    if constexpr (RPT > 1 || sizeof(M) > 8) {
+      // several rows per thread (their loads already overlap) or complex
+      // matrix values (register budget): one column at a time
       for (int j = 0; j < k; ++j) {
-        const T cv = up(C[(size_t)j * ld + row]), ctv = up(Ct[(size_t)j * ld + row]);
-        s += cv * get<T>(zl, j);
-        st += ctv * get<T>(zl, k + j);
-        if (rp) {
-          g += cv * get<T>(zl, 2 * k + j);
-          gt += ctv * get<T>(zl, 3 * k + j);
+        T a = zero<T>(), b = zero<T>(), e = zero<T>();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int row = row0 + q * stride;
+          if (row < n) {
+            const T ctv = up(Ct[(size_t)j * ld + row]), cv = up(C[(size_t)j * ld + row]);
+            a += cj(ctv) * zr[q];
+            b += cj(cv) * ztr[q];
+            e += cpt[q] * cv;
+          }
         }
+        put<T>(lds, P1S, j, a);
+        put<T>(lds, P1S, k + j, b);
+        put<T>(lds, P1S, 2 * k + j, e);
       }
-      qq = up(down<V>(qq - s));
-      qqt = up(down<V>(qqt - st));
-      q[row] = down<V>(qq);
-      qt[row] = down<V>(qqt);
-      if (rp) {
-        r[row] = down<V>(up(r[row]) - g);
-        rt[row] = down<V>(up(rt[row]) - gt);
+      // r_{i-1} read again (cached) rather than held in registers
+      for (int j = 0; rp && j < k; ++j) {
+        T c = zero<T>(), d = zero<T>();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int row = row0 + q * stride;
+          if (row < n) {
+            c += cj(up(Ct[(size_t)j * ld + row])) * up(r[row]);
+            d += cj(up(C[(size_t)j * ld + row])) * up(rt[row]);
+          }
+        }
+        put<T>(lds, P1S, 3 * k + 1 + j, c);
+        put<T>(lds, P1S, 4 * k + 1 + j, d);
       }
+    } else {
+      const size_t rowc = row0 < n ? row0 : n - 1;  // rows past n carry zero factors
+      restrict_group<3, V, T>(C, Ct, k, ld, rowc, zr[0], ztr[0], cpt[0], lds, 0, k, 2 * k);
+      if (rp)
+        restrict_group<2, V, T>(C, Ct, k, ld, rowc, rr_[0], rtr_[0], zero<T>(), lds, 3 * k + 1,
+                                4 * k + 1, 0);
     }
-    part += cj(up(ptn[row])) * qq;
   }
-  put<T>(lds, 2, 0, part);
   __syncthreads();
-  bstore(lds, 2, NW, ND<T>::v, P2);
+  bstore(lds, P1S, NW, (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v, P1);
 }
 
+// Reduce the k_it1 partials; sigma = (p~, z) - sum_j e_j zeta_j (= (p~, q));
+// alpha = rho_{i-1} / sigma; zeta_c += alpha zeta, zeta~_c += conj(alpha)
+// zeta~; per row q = z - C zeta, q~ = z~ - C~ zeta~ (not stored),
+// x += alpha p, x~ += conj(alpha) p~, r -= alpha q, r~ -= conj(alpha) q~;
+// partials of ||r||^2, ||r~||^2, (r~, r).  With rp set (FP32 storage) first
+// r_{i-1} -= C g, r~_{i-1} -= C~ g~ (re-projection, each rounded to storage
+// as a stored intermediate would be) and zeta_c -= g, zeta~_c -= g~.
 template <class V>
-__global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restrict__ xt,
+__global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restrict__ xt,
                                             V *__restrict__ r, V *__restrict__ rt,
                                             const V *__restrict__ pn, const V *__restrict__ ptn,
-                                            const V *__restrict__ q, const V *__restrict__ qt,
-                                            int k, const double *__restrict__ P2,
+                                            const V *__restrict__ z, const V *__restrict__ zt,
+                                            const V *__restrict__ C, const V *__restrict__ Ct,
+                                            int k, int ld, const double *__restrict__ P1,
                                             double *__restrict__ P3, Scalars *S, double *rec,
                                             int it, int rp) {
   using T = typename Ar<V>::T;
   if (S->done) return;
+  rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
   __shared__ double lds[NW * 4];
   __shared__ double tmp[IB];
-  __shared__ double red[4];
-  breduce(P2, gridDim.x, ND<T>::v, tmp, red);
-  const T sigma = get<T>(red, 0);
+  __shared__ double zl[P1S];
+  const int nv1 = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
+  breduce(P1, gridDim.x, nv1, tmp, zl);
+  T sigma = get<T>(zl, 3 * k);
+  for (int j = 0; j < k; ++j) sigma -= get<T>(zl, 2 * k + j) * get<T>(zl, j);
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   double *Ri = rec + (size_t)it * LOG_STRIDE;
   if (abs2(sigma) == 0.0 || !isfin(sigma)) {
@@ -474,11 +542,11 @@ __global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restr
     if (ND<T>::v == 1) Ri[1] = 0.0;
     Ri[8] = comp(sigma, 0);
     for (int j = 0; j < k; ++j) {
-      T u = get<T>(S->zc, j) + al * get<T>(S->zbuf, j);
-      T ut = get<T>(S->zc, k + j) + alc * get<T>(S->zbuf, k + j);
+      T u = get<T>(S->zc, j) + al * get<T>(zl, j);
+      T ut = get<T>(S->zc, k + j) + alc * get<T>(zl, k + j);
       if (rp) {
-        u = u - get<T>(S->gbuf, j);
-        ut = ut - get<T>(S->gbuf, k + j);
+        u = u - get<T>(zl, 3 * k + 1 + j);
+        ut = ut - get<T>(zl, 4 * k + 1 + j);
       }
       set<T>(S->zc, j, u);
       set<T>(S->zc, k + j, ut);
@@ -488,10 +556,30 @@ __global__ __launch_bounds__(IB) void k_it3(int n, V *__restrict__ x, V *__restr
   double rr = 0.0, rtrt = 0.0;
   T rho = zero<T>();
   for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
+    T qq = up(z[row]), qqt = up(zt[row]);
+    T rv = up(r[row]), rtv = up(rt[row]);
+    if (k > 0) {
+      T s = zero<T>(), st = zero<T>(), g = zero<T>(), gt = zero<T>();
+      for (int j = 0; j < k; ++j) {
+        const T cv = up(C[(size_t)j * ld + row]), ctv = up(Ct[(size_t)j * ld + row]);
+        s += cv * get<T>(zl, j);
+        st += ctv * get<T>(zl, k + j);
+        if (rp) {
+          g += cv * get<T>(zl, 3 * k + 1 + j);
+          gt += ctv * get<T>(zl, 4 * k + 1 + j);
+        }
+      }
+      qq = up(down<V>(qq - s));
+      qqt = up(down<V>(qqt - st));
+      if (rp) {
+        rv = up(down<V>(rv - g));
+        rtv = up(down<V>(rtv - gt));
+      }
+    }
     x[row] = down<V>(up(x[row]) + al * up(pn[row]));
     xt[row] = down<V>(up(xt[row]) + alc * up(ptn[row]));
-    const T rv = up(down<V>(up(r[row]) - al * up(q[row])));
-    const T rtv = up(down<V>(up(rt[row]) - alc * up(qt[row])));
+    rv = up(down<V>(rv - al * qq));
+    rtv = up(down<V>(rtv - alc * qqt));
     r[row] = down<V>(rv);
     rt[row] = down<V>(rtv);
     rr += abs2(rv);
@@ -1329,18 +1417,11 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
                        z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
 }
 template <class V>
-void launch_it2(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *C,
-                const V *Ct, int k, int ld, const V *ptn, V *q, V *qt, const double *P1,
-                double *P2, Scalars *S, V *r, V *rt, int rp) {
-  hipLaunchKernelGGL((k_it2<V>), dim3(nb), dim3(IB), 0, st, n, z, zt, C, Ct, k, ld, ptn, q, qt,
-                     P1, P2, S, r, rt, rp);
-}
-template <class V>
-void launch_it3(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
-                const V *ptn, const V *q, const V *qt, int k, const double *P2, double *P3,
-                Scalars *S, double *rec, int it, int rp) {
-  hipLaunchKernelGGL((k_it3<V>), dim3(nb), dim3(IB), 0, st, n, x, xt, r, rt, pn, ptn, q, qt, k,
-                     P2, P3, S, rec, it, rp);
+void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
+                const V *ptn, const V *z, const V *zt, const V *C, const V *Ct, int k, int ld,
+                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp) {
+  hipLaunchKernelGGL((k_it2<V>), dim3(nb), dim3(IB), 0, st, n, x, xt, r, rt, pn, ptn, z, zt, C,
+                     Ct, k, ld, P1, P3, S, rec, it, rp);
 }
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
@@ -1504,12 +1585,9 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
   template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);
 
 #define INST_V(V)                                                                            \
-  template void launch_it2<V>(hipStream_t, int, int, const V *, const V *, const V *,        \
-                              const V *, int, int, const V *, V *, V *, const double *,      \
-                              double *, Scalars *, V *, V *, int);                           \
-  template void launch_it3<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
-                              const V *, const V *, const V *, int, const double *, double *, \
-                              Scalars *, double *, int, int);                                \
+  template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
+                              const V *, const V *, const V *, const V *, const V *, int, int, \
+                              const double *, double *, Scalars *, double *, int, int);      \
   template void launch_itfin<V>(hipStream_t, int, const double *, Scalars *, double *, int,  \
                                 int);                                                        \
   template void launch_init_p3<V>(hipStream_t, int, int, const V *, const V *, double *);    \

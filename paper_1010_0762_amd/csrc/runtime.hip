@@ -270,6 +270,10 @@ struct rbicg_s {
   int n = 0;
   int ld = 0;
   hipStream_t st = nullptr;
+  // cycle-end work (recycle-space update for the next system) runs on its own
+  // stream, concurrently with the iterations it does not feed
+  hipStream_t jst = nullptr;
+  hipEvent_t jev = nullptr;
   int vkind = 0;  // 0 double, 1 complex, 2 float (FP32-inner / FP64-outer mode)
   bool mat_complex = false;
   size_t vb = 8;
@@ -279,14 +283,18 @@ struct rbicg_s {
   // optional per-kernel timing of the iteration kernels (opts.profile)
   std::vector<hipEvent_t> pev;
   hipEvent_t sev[2] = {nullptr, nullptr};
-  double prof_ms[3] = {0, 0, 0};
-  long prof_n[3] = {0, 0, 0};
-  double prof_bytes[3] = {0, 0, 0};  // algorithmic bytes of the timed launches
+  double prof_ms[2] = {0, 0};
+  long prof_n[2] = {0, 0};
+  double prof_bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
+  // cycle-end telemetry (always on): jobs finished, host ms of the two host
+  // parts, ms from a job's first enqueue to its last, ms the iteration
+  // launches waited for a job (ring reuse)
+  double prof_cyc[5] = {0, 0, 0, 0, 0};
   long prof_chunks = 0;              // chunks launched since the handle was made
   // iteration vectors (x, x~ are the caller's)
   void *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr}, *pt[2] = {nullptr, nullptr};
   void *xs0 = nullptr, *xts0 = nullptr;  // initial guesses of the current solve
-  void *z = nullptr, *zt = nullptr, *q = nullptr, *qt = nullptr, *t1 = nullptr, *t2 = nullptr;
+  void *z = nullptr, *zt = nullptr, *t1 = nullptr, *t2 = nullptr;
   // recycle space of the current system
   void *U = nullptr, *Ut = nullptr, *C = nullptr, *Ct = nullptr;
   int ksys = 0;
@@ -302,7 +310,7 @@ struct rbicg_s {
   double *log = nullptr;
   int logcap = 0;
   double *partial = nullptr;  // host-requested reductions
-  double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;  // iteration partials
+  double *P1 = nullptr, *P3 = nullptr;  // iteration partials
   int nb = 1;                 // blocks of the iteration kernels
   double *gpart = nullptr;
   size_t gpart_bytes = 0;
@@ -368,24 +376,21 @@ double svd_tol_eff(const rbicg_s *h) {
 // the type the kernels read, int32 column indices, one slice pointer per
 // row-slice rounded to one per row): k_it1 reads r, r~, p, p~ and C, C~ rows
 // and writes p, p~, z, z~ (plus r_{i-1}, r~_{i-1}, z, z~ into the cycle rings
-// when updating); k_it2 reads z, z~, C, C~, p~ and writes q, q~ (with k = 0:
-// reads z and p~ only; re-projection adds r, r~ read and written); k_it3 reads
-// x, x~, r, r~, p, p~, q, q~ and writes x, x~, r, r~.
-void kernel_bytes(const rbicg_s *h, int k, double out[3]) {
+// when updating); k_it2 reads x, x~, r, r~, p, p~, z, z~ and C, C~ rows and
+// writes x, x~, r, r~.
+void kernel_bytes(const rbicg_s *h, int k, double out[2]) {
   const double ba = h->vkind == 2 ? 4.0 : (double)h->mat->A.vbytes;
   const double nnz = (double)h->mat->A.nnz, n = h->n, vb = (double)h->vb;
   const bool cap = h->opt.update && h->opt.k > 0;
-  const bool rp = h->vkind == 2 && k > 0;
   out[0] = 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (8.0 + 2.0 * k + (cap ? 4.0 : 0.0)) * n * vb;
-  out[1] = (k > 0 ? 5.0 + 2.0 * k + (rp ? 4.0 : 0.0) : 2.0) * n * vb;
-  out[2] = 12.0 * n * vb;
+  out[1] = (12.0 + 2.0 * k) * n * vb;
 }
 
-// bytes per algorithmic iteration: the three kernels' total
+// bytes per algorithmic iteration: the two kernels' total
 double alg_bytes_iter(const rbicg_s *h, int k) {
-  double kb[3];
+  double kb[2];
   kernel_bytes(h, k, kb);
-  return kb[0] + kb[1] + kb[2];
+  return kb[0] + kb[1];
 }
 
 // views of the handle's matrix and of its conjugate transpose, with the
@@ -491,6 +496,14 @@ int tsgemm(rbicg_s *h, const std::vector<const void *> &X, const std::vector<cpl
 // Jobs run one after another.  The cycle's captured vectors live in one of two
 // ring sets; the iterations of cycle c+2 (which overwrite that set) are
 // enqueued only after the job of cycle c has enqueued its last ring read.
+// Points h->st at the handle's job stream for the enclosed enqueues.
+struct JobStream {
+  rbicg_s *h;
+  hipStream_t saved;
+  explicit JobStream(rbicg_s *hh) : h(hh), saved(hh->st) { h->st = h->jst; }
+  ~JobStream() { h->st = saved; }
+};
+
 struct CycleJob {
   int cycle = 0, e = 0, set = 0, run_start = 0;
   int stage = 0;          // 0 pending, 1 begun, 2 host1, 3 stage2 done, 4 host3, 5 finished
@@ -499,8 +512,11 @@ struct CycleJob {
   cplx rho0;
   int kp = 0, mm = 0, mz = 0, gy = 0;
   std::vector<const void *> XU, XUt;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;     // the job's last enqueued stage (job stream)
+  hipEvent_t ready = nullptr;  // the cycle's last iteration (iteration stream)
   std::future<int> fut;
+  double host_ms[2] = {0, 0};
+  std::chrono::steady_clock::time_point t_begin;
   int m = 0, p = 0;
   std::vector<cplx> Wc, Wtc, TU, TUt;
   int g2y = 0;
@@ -516,10 +532,13 @@ inline char *ring_col(void *base, int set, int slots, int c, const rbicg_s *h) {
   return (char *)base + ((size_t)set * slots + c) * h->ld * h->vb;
 }
 
+// Stages 1, 2 and 4 enqueue on h->st, which the caller points at the job
+// stream (JobStream).
 template <class V>
 int job_begin(rbicg_s *h, CycleJob &J) {
   const int s = h->opt.s;
   const int lo = J.e - s;
+  HIPCHECK(hipStreamWaitEvent(h->st, J.ready, 0));
   HIPCHECK(hipMemcpyAsync(h->hlog, h->log + (size_t)lo * LOG_STRIDE,
                           (size_t)(s + 1) * LOG_STRIDE * sizeof(double), hipMemcpyDeviceToHost, h->st));
   J.XU.clear();
@@ -957,12 +976,19 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         progress = false;
         CycleJob &J = *jobs.front();
         if (J.stage == 0) {
+          JobStream js(h);
+          J.t_begin = std::chrono::steady_clock::now();
           TRY(job_begin<V>(h, J));
           progress = true;
         } else if (J.stage == 1) {
           const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
           if (q == hipSuccess) {
-            J.fut = std::async(std::launch::async, [h, &J, real_problem]() { return job_host1(h, J, real_problem); });
+            J.fut = std::async(std::launch::async, [h, &J, real_problem]() {
+              const auto t0 = std::chrono::steady_clock::now();
+              const int r = job_host1(h, J, real_problem);
+              J.host_ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+              return r;
+            });
             J.stage = 2;
             progress = true;
           } else if (q != hipErrorNotReady) {
@@ -971,13 +997,19 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         } else if (J.stage == 2) {
           if (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready) {
             if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
+            JobStream js(h);
             TRY((job_stage2<V, M>(h, J)));
             progress = true;
           }
         } else if (J.stage == 3) {
           const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
           if (q == hipSuccess) {
-            J.fut = std::async(std::launch::async, [h, &J]() { return job_host3(h, J); });
+            J.fut = std::async(std::launch::async, [h, &J]() {
+              const auto t0 = std::chrono::steady_clock::now();
+              const int r = job_host3(h, J);
+              J.host_ms[1] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+              return r;
+            });
             J.stage = 4;
             progress = true;
           } else if (q != hipErrorNotReady) {
@@ -988,9 +1020,17 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           if (J.e <= known &&
               (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready)) {
             if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
-            TRY(job_stage4<V>(h, J));
+            {
+              JobStream js(h);
+              TRY(job_stage4<V>(h, J));
+            }
+            h->prof_cyc[0] += 1;
+            h->prof_cyc[1] += J.host_ms[0];
+            h->prof_cyc[2] += J.host_ms[1];
+            h->prof_cyc[3] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - J.t_begin).count();
             st.cycles++;
             (void)hipEventDestroy(J.ev);
+            (void)hipEventDestroy(J.ready);
             jobs.pop_front();
             progress = true;
           }
@@ -1024,13 +1064,13 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       }
       known = std::max(known, completed);
       if (f.prof) {
-        const int eb = f.slot * 4 * f.chunk;
-        double kb[3];
+        const int eb = f.slot * 3 * f.chunk;
+        double kb[2];
         kernel_bytes(h, ks, kb);
         for (int c = 0; c < completed - f.chunk_start && c < f.chunk; ++c)
-          for (int kk = 0; kk < 3; ++kk) {
+          for (int kk = 0; kk < 2; ++kk) {
             float ms = 0;
-            HIPCHECK(hipEventElapsedTime(&ms, h->pev[eb + 4 * c + kk], h->pev[eb + 4 * c + kk + 1]));
+            HIPCHECK(hipEventElapsedTime(&ms, h->pev[eb + 3 * c + kk], h->pev[eb + 3 * c + kk + 1]));
             h->prof_ms[kk] += ms;
             h->prof_n[kk] += 1;
             h->prof_bytes[kk] += kb[kk];
@@ -1052,16 +1092,22 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
               if (j->cycle <= cyc - 2 && j->stage < 3) return true;
             return false;
           };
+          const auto tw = std::chrono::steady_clock::now();
           while (!done && must_wait()) {
             const int before = jobs.front()->stage;
             const size_t nj = jobs.size();
             TRY(advance(true));
             if (jobs.size() == nj && jobs.front()->stage == before) TRY(read_one());
           }
+          h->prof_cyc[4] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw).count();
           if (done) break;
+          // the job stream's reads of this ring set (job of cycle cyc-2, its
+          // stages 1-2 enqueued: checked just above) precede this cycle's writes
+          if (in_run % s == 0)
+            for (const auto &j : jobs)
+              if (j->cycle <= cyc - 2) HIPCHECK(hipStreamWaitEvent(h->st, j->ev, 0));
           // first chunk of cycle cyc >= 1: the z of cycle cyc-1's last iteration
-          // seeds slot 0 of this cycle's set (whose previous reader, the job of
-          // cycle cyc-2, has enqueued its reads: checked just above)
+          // seeds slot 0 of this cycle's set
           if (cyc >= 1 && in_run % s == 0) {
             HIPCHECK(hipMemcpyAsync(ring_col(h->Z, cyc % 2, s + 1, 0, h), ring_col(h->Z, (cyc - 1) % 2, s + 1, s, h),
                                     (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
@@ -1076,7 +1122,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         // profiling: time every opts.profile-th chunk (events between launches)
         const bool prof = h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
                           (h->prof_chunks++ % h->opt.profile) == 0;
-        const int eb = (slot_next % 2) * 4 * chunk;
+        const int eb = (slot_next % 2) * 3 * chunk;
         for (int c = 0; c < chunk; ++c) {
           const int it = launched + 1;
           const int pos = (it - 1 - run_start) % s;
@@ -1089,18 +1135,14 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             capZt = (V *)ring_col(h->Zt, set, s + 1, pos + 1, h);
           }
           V *pn = (V *)h->p[1 - pc], *ptn = (V *)h->pt[1 - pc];
-          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c], h->st));
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c], h->st));
           launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
                            ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
                            h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
-          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 1], h->st));
-          launch_it2<V>(h->st, nb, n, (const V *)h->z, (const V *)h->zt, C, Ct, ks, ld, ptn,
-                        (V *)h->q, (V *)h->qt, h->P1, h->P2, h->S, r, rt, rp);
-          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 2], h->st));
-          const V *qq = ks > 0 ? (const V *)h->q : (const V *)h->z;
-          const V *qqt = ks > 0 ? (const V *)h->qt : (const V *)h->zt;
-          launch_it3<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, qq, qqt, ks, h->P2, h->P3, h->S, h->log, it, rp);
-          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 4 * c + 3], h->st));
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 1], h->st));
+          launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C,
+                        Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp);
+          if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 2], h->st));
           pc = 1 - pc;
           ++launched;
         }
@@ -1122,6 +1164,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           J->rn0 = rn;
           J->rho0 = rho;
           HIPCHECK(hipEventCreateWithFlags(&J->ev, hipEventDisableTiming));
+          HIPCHECK(hipEventCreateWithFlags(&J->ready, hipEventDisableTiming));
+          HIPCHECK(hipEventRecord(J->ready, h->st));
           jobs.push_back(std::move(J));
         }
       }
@@ -1149,10 +1193,16 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       if (J.stage == 2 || J.stage == 4) J.fut.wait();
       if (J.stage >= 1) (void)hipEventSynchronize(J.ev);
       (void)hipEventDestroy(J.ev);
+      (void)hipEventDestroy(J.ready);
       jobs.pop_back();
     }
-    // finish the remaining updates of this run
+    // finish the remaining updates of this run; later work on the iteration
+    // stream (next run, next system's recycle space) is ordered after them
     while (!jobs.empty()) TRY(advance(true));
+    if (update) {
+      HIPCHECK(hipEventRecord(h->jev, h->jst));
+      HIPCHECK(hipStreamWaitEvent(h->st, h->jev, 0));
+    }
     total = completed;
     status = dev_status;
     // keep this run's log
@@ -1724,9 +1774,11 @@ int dispatch(rbicg_s *h, F &&f) {
 }
 
 int alloc_workspace(rbicg_s *h) {
+  HIPCHECK(hipStreamCreateWithFlags(&h->jst, hipStreamNonBlocking));
+  HIPCHECK(hipEventCreateWithFlags(&h->jev, hipEventDisableTiming));
   const size_t vbytes = (size_t)h->ld * h->vb;
   void **vecs[] = {&h->r, &h->rt, &h->p[0], &h->p[1], &h->pt[0], &h->pt[1], &h->z, &h->zt,
-                   &h->q, &h->qt, &h->t1, &h->t2, &h->xs0, &h->xts0};
+                   &h->t1, &h->t2, &h->xs0, &h->xts0};
   for (void **v : vecs) TRY(dalloc(h, v, vbytes));
   const size_t kb = vbytes * std::max(1, h->kcap);
   void **bases[] = {&h->U, &h->Ut, &h->C, &h->Ct, &h->Ua, &h->Uta, &h->Ca, &h->Cta,
@@ -1755,8 +1807,7 @@ int alloc_workspace(rbicg_s *h) {
   TRY(dalloc(h, (void **)&h->log, (size_t)h->logcap * LOG_STRIDE * sizeof(double)));
   h->nb = iter_grid(h->n);
   TRY(dalloc(h, (void **)&h->partial, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
-  TRY(dalloc(h, (void **)&h->P1, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
-  TRY(dalloc(h, (void **)&h->P2, (size_t)h->nb * 4 * sizeof(double)));
+  TRY(dalloc(h, (void **)&h->P1, (size_t)h->nb * (6 * KMAXD + 2) * sizeof(double)));
   TRY(dalloc(h, (void **)&h->P3, (size_t)h->nb * 8 * sizeof(double)));
   const int wx = std::max(2 * h->kcap, h->kcap + h->scap + 1);
   const int wy = std::max(2 * h->kcap, 2 * (h->kcap + h->scap) + 1);
@@ -1938,21 +1989,24 @@ extern "C" int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next) {
 
 extern "C" int rbicg_profile(rbicg_handle h, int32_t reset, double *out) {
   if (!h || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 2; ++k) {
     out[2 * k] = h->prof_ms[k];
     out[2 * k + 1] = (double)h->prof_n[k];
   }
-  double kb[3];
+  double kb[2];
   kernel_bytes(h, h->ksys, kb);
-  out[6] = kb[0];
-  out[7] = kb[0] + kb[1] + kb[2];
-  for (int kk = 0; kk < 3; ++kk) out[8 + kk] = h->prof_bytes[kk];
-  if (reset)
-    for (int kk = 0; kk < 3; ++kk) {
+  out[4] = kb[0];
+  out[5] = kb[0] + kb[1];
+  for (int kk = 0; kk < 2; ++kk) out[6 + kk] = h->prof_bytes[kk];
+  for (int kk = 0; kk < 5; ++kk) out[8 + kk] = h->prof_cyc[kk];
+  if (reset) {
+    for (int kk = 0; kk < 2; ++kk) {
       h->prof_ms[kk] = 0;
       h->prof_n[kk] = 0;
       h->prof_bytes[kk] = 0;
     }
+    for (int kk = 0; kk < 5; ++kk) h->prof_cyc[kk] = 0;
+  }
   return RBICG_OK;
 }
 
@@ -1960,6 +2014,11 @@ extern "C" int rbicg_destroy(rbicg_handle h) {
   if (!h) return RBICG_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
+  if (h->jst) {
+    (void)hipStreamSynchronize(h->jst);
+    (void)hipStreamDestroy(h->jst);
+  }
+  if (h->jev) (void)hipEventDestroy(h->jev);
   delete h->sw;
   h->sw = nullptr;
   if (h->h64) {

@@ -182,12 +182,13 @@ class Solver:
     def profile(self, reset=False):
         """Per-kernel timing (rbicg_profile): dict with ms/launch counts and
         the algorithmic bytes of one SpMV-kernel launch and of one iteration."""
-        out = np.zeros(11)
+        out = np.zeros(13)
         _lib.check(self.lib.rbicg_profile(self.h, 1 if reset else 0, _lib.dptr(out)), "rbicg_profile")
-        return {"spmv_ms": out[0], "spmv_n": int(out[1]), "expand_ms": out[2],
-                "expand_n": int(out[3]), "update_ms": out[4], "update_n": int(out[5]),
-                "spmv_bytes": out[6], "iter_bytes": out[7], "spmv_bytes_total": out[8],
-                "expand_bytes_total": out[9], "update_bytes_total": out[10]}
+        return {"spmv_ms": out[0], "spmv_n": int(out[1]), "update_ms": out[2],
+                "update_n": int(out[3]), "spmv_bytes": out[4], "iter_bytes": out[5],
+                "spmv_bytes_total": out[6], "update_bytes_total": out[7],
+                "cycle_updates": int(out[8]), "cycle_eig_ms": out[9], "cycle_biorth_ms": out[10],
+                "cycle_latency_ms": out[11], "cycle_wait_ms": out[12]}
 
     def log(self):
         """Per-iteration log of the last solve as an (iters, 10) float64 array."""
