@@ -331,8 +331,8 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
   return true;
 }
 
-// LDS row stride (doubles) of the k_it1 partials: (3k + 1) values, plus 2k
-// with re-projection, times the components of T
+// Most doubles of k_it1 partials per block: (3k + 1) values, plus 2k with
+// re-projection, times the components of T
 #define P1S (6 * KMAXD + 2)
 
 // Restriction partials of one group of GC columns per pass over the block's
@@ -344,7 +344,8 @@ __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, i
 template <int NPC, class V, class T>
 __device__ __forceinline__ void restrict_group(const V *__restrict__ C, const V *__restrict__ Ct,
                                                int k, int ld, size_t rowc, T u, T ut, T cpt,
-                                               double *lds, int base_a, int base_b, int base_e) {
+                                               double *lds, int ls, int base_a, int base_b,
+                                               int base_e) {
   constexpr int NDV = ND<T>::v;
   constexpr int GC = 16 / (NPC * NDV);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -378,7 +379,7 @@ __device__ __forceinline__ void restrict_group(const V *__restrict__ C, const V 
     if ((lane & 3) == 0 && id < NPC * GC * NDV) {
       const int h = id / (GC * NDV), g = (id % (GC * NDV)) / NDV, c = id % NDV, j = j0 + g;
       const int base = h == 0 ? base_a : (h == 1 ? base_b : base_e);
-      if (j < k) lds[wv * P1S + (base + j) * NDV + c] = sum;
+      if (j < k) lds[wv * ls + (base + j) * NDV + c] = sum;
     }
   }
 }
@@ -396,7 +397,10 @@ __global__ __launch_bounds__(IB) void k_it1(
   using T = typename Ar<V>::T;
   if (S->done) return;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
-  __shared__ double lds[NW * P1S];
+  // wave partials, NW rows of ls values (dynamic: sized by the recycle
+  // dimension, so that the block leaves room on its CU for cycle-end kernels)
+  extern __shared__ double lds[];
+  const int ls = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
   __shared__ double tmp[IB];
   __shared__ double red[8];
   T beta;
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(IB) void k_it1(
   // [k, 2k), e = (p~^H C) at [2k, 3k), (p~, z) at 3k; with rp also
   // g = C~^H r_{i-1} at [3k+1, 4k+1) and g~ = C^H r~_{i-1} at [4k+1, 5k+1).
   // k_it2 assembles sigma = (p~, q) = (p~, z) - e zeta from them.
-  put<T>(lds, P1S, 3 * k, s0);
+  put<T>(lds, ls, 3 * k, s0);
   if (k > 0) {
     if constexpr (RPT > 1 || sizeof(M) > 8) {
       // several rows per thread (their loads already overlap) or complex
@@ -469,9 +473,9 @@ __global__ __launch_bounds__(IB) void k_it1(
             e += cpt[q] * cv;
           }
         }
-        put<T>(lds, P1S, j, a);
-        put<T>(lds, P1S, k + j, b);
-        put<T>(lds, P1S, 2 * k + j, e);
+        put<T>(lds, ls, j, a);
+        put<T>(lds, ls, k + j, b);
+        put<T>(lds, ls, 2 * k + j, e);
       }
       // r_{i-1} read again (cached) rather than held in registers
       for (int j = 0; rp && j < k; ++j) {
@@ -484,19 +488,19 @@ __global__ __launch_bounds__(IB) void k_it1(
             d += cj(up(C[(size_t)j * ld + row])) * up(rt[row]);
           }
         }
-        put<T>(lds, P1S, 3 * k + 1 + j, c);
-        put<T>(lds, P1S, 4 * k + 1 + j, d);
+        put<T>(lds, ls, 3 * k + 1 + j, c);
+        put<T>(lds, ls, 4 * k + 1 + j, d);
       }
     } else {
       const size_t rowc = row0 < n ? row0 : n - 1;  // rows past n carry zero factors
-      restrict_group<3, V, T>(C, Ct, k, ld, rowc, zr[0], ztr[0], cpt[0], lds, 0, k, 2 * k);
+      restrict_group<3, V, T>(C, Ct, k, ld, rowc, zr[0], ztr[0], cpt[0], lds, ls, 0, k, 2 * k);
       if (rp)
-        restrict_group<2, V, T>(C, Ct, k, ld, rowc, rr_[0], rtr_[0], zero<T>(), lds, 3 * k + 1,
-                                4 * k + 1, 0);
+        restrict_group<2, V, T>(C, Ct, k, ld, rowc, rr_[0], rtr_[0], zero<T>(), lds, ls,
+                                3 * k + 1, 4 * k + 1, 0);
     }
   }
   __syncthreads();
-  bstore(lds, P1S, NW, (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v, P1);
+  bstore(lds, ls, NW, ls, P1);
 }
 
 // Reduce the k_it1 partials; sigma = (p~, z) - sum_j e_j zeta_j (= (p~, q));
@@ -927,71 +931,81 @@ __global__ void k_gram_reduce(const double *partial, int nchunks, int count, dou
 // column-major; p <= 64) computed as Y^T = W^T X^T on MFMA so that both the X
 // loads and the Y stores are contiguous 16-row segments.  Each wave owns 16
 // rows.
-template <class V>
+template <class V, int JT>
 __global__ __launch_bounds__(256) void k_tsgemm_mfma(int n, ColList X, int m, const cd *W, int p,
                                                      V *Y, int ld) {
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
+  __shared__ const V *cols[RBICG_MAXCOLS];
+  for (int t = threadIdx.x; t < m; t += 256) cols[t] = (const V *)X.p[t];
+  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = (blockIdx.x * 4 + w) * 16;
   if (row0 >= n) return;
+  // rows past n (within the columns' padded length) feed only output rows
+  // that are not stored
   const int row = row0 + li;
-  const int JT = (p + 15) / 16;
-  d4 acc[4][ndv];
+  d4 acc[JT][ndv];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < JT; ++t)
 #pragma unroll
     for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < m; k0 += 4) {
-    const int kcol = k0 + lk;
-    double xr = 0.0, xi = 0.0;
-    if (kcol < m && row < n) {
-      const V v = ((const V *)X.p[kcol])[row];
+  // 16 columns per step: the four X loads and 4 JT W loads of a lane are
+  // issued together (column pointers from LDS, clamped indices, factors
+  // zeroed after the load), so that a wave has them all in flight at once
+#pragma unroll 1
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    double xr[4], xi[4], wr[4][JT], wi[4][JT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kcol = k0 + 4 * u + lk;
+      const int kc = min(kcol, m - 1);
+      const V v = cols[kc][row];
       if constexpr (ndv == 2) {
-        xr = ((const cd &)v).x;
-        xi = ((const cd &)v).y;
+        xr[u] = ((const cd &)v).x;
+        xi[u] = ((const cd &)v).y;
       } else {
-        xr = (double)v;
+        xr[u] = (double)v;
+        xi[u] = 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < JT; ++t) {
+        const int c = t * 16 + li;
+        const cd wv = W[(size_t)min(c, p - 1) * m + kc];
+        const bool in = kcol < m && c < p;
+        wr[u][t] = in ? wv.x : 0.0;
+        wi[u][t] = in ? wv.y : 0.0;
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < JT) {
-        const int c = t * 16 + li;
-        double wr = 0.0, wi = 0.0;
-        if (kcol < m && c < p) {
-          const cd wv = W[(size_t)c * m + kcol];
-          wr = wv.x;
-          wi = wv.y;
-        }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < JT; ++t) {
         if constexpr (ndv == 1) {
-          acc[t][0] = mfma(wr, xr, acc[t][0]);
+          acc[t][0] = mfma(wr[u][t], xr[u], acc[t][0]);  // real bases take Re W
         } else {
           // (W^T X^T): re = wr xr - wi xi, im = wr xi + wi xr
-          acc[t][0] = mfma(wr, xr, acc[t][0]);
-          acc[t][0] = mfma(-wi, xi, acc[t][0]);
-          acc[t][1] = mfma(wr, xi, acc[t][1]);
-          acc[t][1] = mfma(wi, xr, acc[t][1]);
+          acc[t][0] = mfma(wr[u][t], xr[u], acc[t][0]);
+          acc[t][0] = mfma(-wi[u][t], xi[u], acc[t][0]);
+          acc[t][1] = mfma(wr[u][t], xi[u], acc[t][1]);
+          acc[t][1] = mfma(wi[u][t], xr[u], acc[t][1]);
         }
       }
-    }
   }
   if (row >= n) return;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t < JT) {
+  for (int t = 0; t < JT; ++t) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = t * 16 + lk + 4 * v;
-        if (c < p) {
-          if constexpr (ndv == 2) {
-            cd o;
-            o.x = acc[t][0][v];
-            o.y = acc[t][1][v];
-            ((cd *)Y)[(size_t)c * ld + row] = o;
-          } else {
-            Y[(size_t)c * ld + row] = (V)acc[t][0][v];
-          }
+    for (int v = 0; v < 4; ++v) {
+      const int c = t * 16 + lk + 4 * v;
+      if (c < p) {
+        if constexpr (ndv == 2) {
+          cd o;
+          o.x = acc[t][0][v];
+          o.y = acc[t][1][v];
+          ((cd *)Y)[(size_t)c * ld + row] = o;
+        } else {
+          Y[(size_t)c * ld + row] = (V)acc[t][0][v];
         }
       }
     }
@@ -1409,12 +1423,16 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
                 const V *Ct, int k, int ld, V *capR, V *capRt, V *capZ, V *capZt,
                 const double *P3, double *P1, Scalars *S, double *rec, int it, int first, int rp) {
   // one row per thread when the grid covers the rows, else up to RMAX
+  const int ndv = sizeof(V) == 16 ? 2 : 1;
+  const int rpv = sizeof(V) == 4 ? rp : 0;
+  const size_t lds = (size_t)NW * (3 * k + 1 + (rpv ? 2 * k : 0)) * ndv * sizeof(double);
   if ((size_t)nb * IB >= (size_t)A.n)
-    hipLaunchKernelGGL((k_it1<V, M, 1>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn, z,
-                       zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
-  else
-    hipLaunchKernelGGL((k_it1<V, M, RMAX>), dim3(nb), dim3(IB), 0, st, A, AH, r, p, rt, pt, pn, ptn,
+    hipLaunchKernelGGL((k_it1<V, M, 1>), dim3(nb), dim3(IB), lds, st, A, AH, r, p, rt, pt, pn, ptn,
                        z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first, rp);
+  else
+    hipLaunchKernelGGL((k_it1<V, M, RMAX>), dim3(nb), dim3(IB), lds, st, A, AH, r, p, rt, pt, pn,
+                       ptn, z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first,
+                       rp);
 }
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
@@ -1491,7 +1509,7 @@ int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
 
 int gram_group(int mx, int complex_vals) {
   const int TX = (mx + 15) / 16;
-  int g = std::min(96, (4 * GRAM_MAXT / TX) * 16);
+  int g = std::min(128, (4 * GRAM_MAXT / TX) * 16);
   // the short-slab variant holds up to 282 (real) / 266 (complex) columns
   const int mxp = TX * 16;
   const int lim = (complex_vals ? 266 : 282) / 16 * 16;
@@ -1535,7 +1553,15 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
                    int ld) {
   if (p <= 0) return;
   const unsigned nb = (unsigned)((n + 63) / 64);
-  hipLaunchKernelGGL((k_tsgemm_mfma<V>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+  const int jt = (p + 15) / 16;  // p <= KMAXD = 64
+  if (jt == 1)
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 1>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+  else if (jt == 2)
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 2>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+  else if (jt == 3)
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 3>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+  else
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 4>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
 }
 
 // ------------------------------------------------------- shifted launchers

@@ -1812,7 +1812,7 @@ int alloc_workspace(rbicg_s *h) {
   const int wx = std::max(2 * h->kcap, h->kcap + h->scap + 1);
   const int wy = std::max(2 * h->kcap, 2 * (h->kcap + h->scap) + 1);
   const int w = std::max(wx, wy);
-  h->gpart_bytes = (size_t)gram_chunks(h->n) * wx * 96 * 2 * sizeof(double);
+  h->gpart_bytes = (size_t)gram_chunks(h->n) * wx * 128 * 2 * sizeof(double);
   TRY(dalloc(h, (void **)&h->gpart, h->gpart_bytes));
   TRY(dalloc(h, (void **)&h->Gd, (size_t)wx * wy * 2 * sizeof(double)));
   TRY(dalloc(h, (void **)&h->Wd, 6 * RBICG_WSLOT * sizeof(cd)));
