@@ -1524,17 +1524,21 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
   const int rpc = (int)(((size_t)n + nchunks - 1) / nchunks);
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
   const int ncol = mxp + myp;
-  // longest slab (contiguous run per column) whose two LDS buffers fit
-  const int sr_big = ndv == 2 ? 32 : 64;
-  const bool big = 2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES;
+  // longest slab (contiguous run per column) whose two LDS buffers fit.
+  // Real data take the variants with 18 prefetch slots per thread (fewer
+  // registers, at most ~80 KB of LDS): a Gram block then leaves room on its
+  // CU for a block of the iteration kernels running on the other stream.
+  const int sr_big = 32;
+  const bool big = ndv == 2 ? 2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES
+                            : (size_t)ncol * sr_big <= 18 * GRAM_BLOCK;
   const int sr = big ? sr_big : sr_big / 2;
   const size_t lds = 2 * (size_t)ncol * (sr + 2) * ndv * sizeof(double);
   if (ndv == 1) {
     if (big)
-      hipLaunchKernelGGL((k_gram_mfma<V, 64, 36>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+      hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
                          mx, Y, my, rpc, partial);
     else
-      hipLaunchKernelGGL((k_gram_mfma<V, 32, 36>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
+      hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
                          mx, Y, my, rpc, partial);
   } else {
     if (big)

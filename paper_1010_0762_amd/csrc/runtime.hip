@@ -870,8 +870,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   int ks = h->ksys;  // recycle dimension of the current run (a stalled run drops it)
   const V *U = (const V *)h->U, *Ut = (const V *)h->Ut, *C = (const V *)h->C, *Ct = (const V *)h->Ct;
   cplx d[3];
-  TRY(host_dots<V>(h, b, b, bt, bt, nullptr, nullptr, d));
-  double bn = std::sqrt(std::fabs(d[0].real())), btn = std::sqrt(std::fabs(d[1].real()));
+  double bn = 0.0, btn = 0.0;  // from the first pass's scalar read (below)
+  const int nd = ndv<V>();
   int total = 0, restarts = 0, reseeds = 0, status = ST_MAXIT;
   double relres = NAN, relres_dual = NAN;
   bool first = true;
@@ -883,16 +883,16 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   }
   while (true) {
     rp = (inner && VK<V>::kind == 0 && sizeof(V) == 4 && ks > 0) ? 1 : 0;
-    // eq. minusXR: r_{-1} = b - A x, projection with C, C~
+    // eq. minusXR: r_{-1} = b - A x, projection with C, C~.  On the first
+    // pass ||b||, ||b~|| and the unprojected ||r||, ||r~|| (the scale when b
+    // or b~ vanishes) go to red[16..] and red[24..] and come back with the
+    // initial scalars: one host round trip.
+    if (first)
+      launch_dots<V>(h->st, nb, n, b, b, bt, bt, nullptr, nullptr, h->partial, h->S->red + 16);
     launch_residual<V, M>(h->st, A, b, x, r);
     launch_residual<V, M>(h->st, AH, bt, xt, rt);
-    if (first && (bn == 0.0 || btn == 0.0)) {
-      TRY(host_dots<V>(h, r, r, rt, rt, nullptr, nullptr, d));
-      if (bn == 0.0) bn = std::sqrt(std::fabs(d[0].real()));
-      if (btn == 0.0) btn = std::sqrt(std::fabs(d[1].real()));
-      if (bn == 0.0) bn = 1.0;
-      if (btn == 0.0) btn = 1.0;
-    }
+    if (first)
+      launch_dots<V>(h->st, nb, n, r, r, rt, rt, nullptr, nullptr, h->partial, h->S->red + 24);
     if (ks > 0) {
       launch_restrict<V>(h->st, nb, n, r, Ct, rt, C, ks, ld, h->partial, h->S->gbuf);
       launch_expand2<V>(h->st, n, x, U, 1.0, r, C, -1.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, h->S->gbuf);
@@ -901,6 +901,15 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     launch_fin_red(h->st, h->P3, nb, 2 + ndv<V>(), h->S->red);
     HIPCHECK(hipGetLastError());
     TRY(pull_scalars(h));
+    if (first) {
+      const double *rd = h->hS->red;
+      bn = std::sqrt(std::fabs(rd[16]));
+      btn = std::sqrt(std::fabs(rd[16 + nd]));
+      if (bn == 0.0) bn = std::sqrt(std::fabs(rd[24]));
+      if (btn == 0.0) btn = std::sqrt(std::fabs(rd[24 + nd]));
+      if (bn == 0.0) bn = 1.0;
+      if (btn == 0.0) btn = 1.0;
+    }
     double rn = std::sqrt(std::fabs(h->hS->red[0])), rtn = std::sqrt(std::fabs(h->hS->red[1]));
     cplx rho(h->hS->red[2], ndv<V>() == 2 ? h->hS->red[3] : 0.0);
     // Algorithm 2 step 3: re-seed x~ if (r_0, r~_0) vanishes
@@ -970,6 +979,20 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     const bool real_problem = (VK<V>::kind == 0);
 
     // advance the job queue; blocking: wait for what the front job needs
+    // blocking: spin on the event (a sleeping wait adds wake-up latency to
+    // the cycle-end chain) and run the host parts on this thread (deferred),
+    // which saves the start of a worker when nothing else is left to overlap
+    auto ev_ready = [&](hipEvent_t ev, bool blocking) -> hipError_t {
+      hipError_t q = hipEventQuery(ev);
+      while (blocking && q == hipErrorNotReady) {
+        std::this_thread::yield();
+        q = hipEventQuery(ev);
+      }
+      return q;
+    };
+    auto fut_ready = [](std::future<int> &f, bool blocking) {
+      return blocking || f.wait_for(std::chrono::seconds(0)) != std::future_status::timeout;
+    };
     auto advance = [&](bool blocking) -> int {
       bool progress = true;
       while (progress && !jobs.empty()) {
@@ -981,9 +1004,9 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           TRY(job_begin<V>(h, J));
           progress = true;
         } else if (J.stage == 1) {
-          const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
+          const hipError_t q = ev_ready(J.ev, blocking);
           if (q == hipSuccess) {
-            J.fut = std::async(std::launch::async, [h, &J, real_problem]() {
+            J.fut = std::async(blocking ? std::launch::deferred : std::launch::async, [h, &J, real_problem]() {
               const auto t0 = std::chrono::steady_clock::now();
               const int r = job_host1(h, J, real_problem);
               J.host_ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -995,16 +1018,16 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             return rbicg_fail(RBICG_EHIP, "cycle event: %s", hipGetErrorString(q));
           }
         } else if (J.stage == 2) {
-          if (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready) {
+          if (fut_ready(J.fut, blocking)) {
             if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
             JobStream js(h);
             TRY((job_stage2<V, M>(h, J)));
             progress = true;
           }
         } else if (J.stage == 3) {
-          const hipError_t q = blocking ? hipEventSynchronize(J.ev) : hipEventQuery(J.ev);
+          const hipError_t q = ev_ready(J.ev, blocking);
           if (q == hipSuccess) {
-            J.fut = std::async(std::launch::async, [h, &J]() {
+            J.fut = std::async(blocking ? std::launch::deferred : std::launch::async, [h, &J]() {
               const auto t0 = std::chrono::steady_clock::now();
               const int r = job_host3(h, J);
               J.host_ms[1] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1017,8 +1040,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           }
         } else if (J.stage == 4) {
           // install only once the cycle is known to have been completed
-          if (J.e <= known &&
-              (blocking || J.fut.wait_for(std::chrono::seconds(0)) == std::future_status::ready)) {
+          if (J.e <= known && fut_ready(J.fut, blocking)) {
             if (J.fut.get() < 0) return rbicg_fail(RBICG_EINVAL, "%s", J.err.c_str());
             {
               JobStream js(h);
