@@ -1237,11 +1237,201 @@ CMat mul(const CMat &A, const CMat &B, bool conjA = false) {
     }
   return C;
 }
+
+// Real counterparts of herm_jacobi, svd_jacobi and whitening for real Gram
+// matrices (real problems): the same rotations, with the phase e = a_pq / |a_pq|
+// reduced to a sign, in real arithmetic (a quarter of the complex work).
+void sym_jacobi(RMat A, std::vector<double> &w, RMat &V) {
+  const int m = A.m;
+  V = RMat(m, m);
+  for (int i = 0; i < m; ++i) V(i, i) = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        tot += A(i, j) * A(i, j);
+        if (i != j) off += A(i, j) * A(i, j);
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A(p, q), b = std::fabs(apq);
+        if (b == 0.0) continue;
+        const double app = A(p, p), aqq = A(q, q), e = apq / b;
+        const double tau = (aqq - app) / (2.0 * b);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        const double se = sn * e, ce = c * e;
+        for (int r = 0; r < m; ++r) {
+          const double akp = A(r, p), akq = A(r, q);
+          A(r, p) = c * akp - se * akq;
+          A(r, q) = sn * akp + ce * akq;
+        }
+        for (int r = 0; r < m; ++r) {
+          const double apk = A(p, r), aqk = A(q, r);
+          A(p, r) = c * apk - se * aqk;
+          A(q, r) = sn * apk + ce * aqk;
+        }
+        for (int r = 0; r < m; ++r) {
+          const double vkp = V(r, p), vkq = V(r, q);
+          V(r, p) = c * vkp - se * vkq;
+          V(r, q) = sn * vkp + ce * vkq;
+        }
+      }
+  }
+  w.resize(m);
+  for (int i = 0; i < m; ++i) w[i] = A(i, i);
+  std::vector<int> idx(m);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] < w[b]; });
+  RMat V2(m, m);
+  std::vector<double> w2(m);
+  for (int j = 0; j < m; ++j) {
+    w2[j] = w[idx[j]];
+    for (int i = 0; i < m; ++i) V2(i, j) = V(i, idx[j]);
+  }
+  w = w2;
+  V = V2;
+}
+
+void svd_jacobi_real(const RMat &A, RMat &U, std::vector<double> &s, RMat &V) {
+  const int m = A.m, n = A.n;
+  U = A;
+  V = RMat(n, n);
+  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double alpha = 0, beta = 0, gamma = 0;
+        for (int i = 0; i < m; ++i) {
+          alpha += U(i, p) * U(i, p);
+          beta += U(i, q) * U(i, q);
+          gamma += U(i, p) * U(i, q);
+        }
+        const double g = std::fabs(gamma);
+        if (g == 0.0 || g <= 1e-15 * std::sqrt(alpha * beta)) continue;
+        rotated = true;
+        const double e = gamma / g;
+        const double tau = (beta - alpha) / (2.0 * g);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        const double se = sn * e, ce = c * e;
+        for (int i = 0; i < m; ++i) {
+          const double up = U(i, p), uq = U(i, q);
+          U(i, p) = c * up - se * uq;
+          U(i, q) = sn * up + ce * uq;
+        }
+        for (int i = 0; i < n; ++i) {
+          const double vp = V(i, p), vq = V(i, q);
+          V(i, p) = c * vp - se * vq;
+          V(i, q) = sn * vp + ce * vq;
+        }
+      }
+    if (!rotated) break;
+  }
+  s.resize(n);
+  for (int j = 0; j < n; ++j) {
+    double t = 0;
+    for (int i = 0; i < m; ++i) t += U(i, j) * U(i, j);
+    s[j] = std::sqrt(t);
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return s[a] > s[b]; });
+  RMat U2(m, n), V2(n, n);
+  std::vector<double> s2(n);
+  for (int j = 0; j < n; ++j) {
+    const int o = idx[j];
+    s2[j] = s[o];
+    for (int i = 0; i < m; ++i) U2(i, j) = (s[o] > 0) ? U(i, o) / s[o] : (i == j ? 1.0 : 0.0);
+    for (int i = 0; i < n; ++i) V2(i, j) = V(i, o);
+  }
+  U = U2;
+  V = V2;
+  s = s2;
+}
+
+RMat load_real(int m, int n, const double *p) {
+  RMat A(m, n);
+  for (size_t t = 0; t < (size_t)m * n; ++t) A.a[t] = p[2 * t];
+  return A;
+}
+RMat whitening_real(const RMat &G) {
+  std::vector<double> w;
+  RMat V;
+  sym_jacobi(G, w, V);
+  const int k = G.m;
+  double wmax = 0;
+  for (double x : w) wmax = std::max(wmax, x);
+  std::vector<int> keep;
+  for (int i = k - 1; i >= 0; --i)
+    if (w[i] > 1e-13 * wmax && w[i] > 0) keep.push_back(i);
+  RMat L(k, (int)keep.size());
+  for (size_t j = 0; j < keep.size(); ++j) {
+    const double f = 1.0 / std::sqrt(w[keep[j]]);
+    for (int i = 0; i < k; ++i) L(i, (int)j) = V(i, keep[j]) * f;
+  }
+  return L;
+}
+RMat mul_real(const RMat &A, const RMat &B, bool transA = false) {
+  const int m = transA ? A.n : A.m, kk = transA ? A.m : A.n;
+  RMat C(m, B.n);
+  for (int j = 0; j < B.n; ++j)
+    for (int i = 0; i < m; ++i) {
+      double s = 0;
+      for (int l = 0; l < kk; ++l) s += (transA ? A(l, i) : A(i, l)) * B(l, j);
+      C(i, j) = s;
+    }
+  return C;
+}
+bool all_real(int k, const double *G) {
+  for (size_t t = 0; t < (size_t)k * k; ++t)
+    if (G[2 * t + 1] != 0.0) return false;
+  return true;
+}
+
+// rbicg_host_biorth for real Grams (same steps, real arithmetic)
+int biorth_real(int k, const double *Gcc, const double *Gtt, const double *Gtc, double tol,
+                double *TU, double *TUt) {
+  RMat L = whitening_real(load_real(k, k, Gcc));
+  RMat Lt = whitening_real(load_real(k, k, Gtt));
+  if (L.n == 0 || Lt.n == 0) return 0;
+  RMat K = mul_real(Lt, mul_real(load_real(k, k, Gtc), L), true);  // Q~^T Q
+  RMat M, N;
+  std::vector<double> sv;
+  if (K.m >= K.n) {
+    svd_jacobi_real(K, M, sv, N);
+  } else {
+    RMat KT(K.n, K.m);
+    for (int i = 0; i < K.m; ++i)
+      for (int j = 0; j < K.n; ++j) KT(j, i) = K(i, j);
+    svd_jacobi_real(KT, N, sv, M);
+  }
+  int p = 0;
+  for (double x : sv)
+    if (std::isfinite(x) && x >= tol) ++p;
+  for (int j = 0; j < p; ++j) {
+    const double f = 1.0 / std::sqrt(sv[j]);
+    for (int i = 0; i < k; ++i) {
+      double a = 0, b = 0;
+      for (int l = 0; l < L.n; ++l) a += L(i, l) * N(l, j);
+      for (int l = 0; l < Lt.n; ++l) b += Lt(i, l) * M(l, j);
+      TU[2 * (i + j * k)] = a * f;
+      TU[2 * (i + j * k) + 1] = 0.0;
+      TUt[2 * (i + j * k)] = b * f;
+      TUt[2 * (i + j * k) + 1] = 0.0;
+    }
+  }
+  return p;
+}
 }  // namespace
 
 extern "C" int rbicg_host_biorth(int32_t k, const double *Gcc, const double *Gtt,
                                  const double *Gtc, double tol, double *TU, double *TUt) {
   if (k <= 0 || !Gcc || !Gtt || !Gtc || !TU || !TUt) return rbicg_fail(-1, "host_biorth: bad arguments");
+  if (all_real(k, Gcc) && all_real(k, Gtt) && all_real(k, Gtc))
+    return biorth_real(k, Gcc, Gtt, Gtc, tol, TU, TUt);
   CMat L = whitening(load(k, k, Gcc));
   CMat Lt = whitening(load(k, k, Gtt));
   if (L.n == 0 || Lt.n == 0) return 0;
