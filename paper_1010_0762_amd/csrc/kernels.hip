@@ -765,6 +765,19 @@ __global__ void k_reseed(V *x, size_t n, unsigned long long seed) {
 }
 
 // ----------------------------------------------------- cycle-end kernels
+// Load through a pointer known to point at device global memory (pointers
+// read back from LDS tables would otherwise produce flat loads).
+template <class V>
+__device__ __forceinline__ V gload(const V *p, size_t i) {
+  return ((const __attribute__((address_space(1))) V *)p)[i];
+}
+template <>
+__device__ __forceinline__ cd gload<cd>(const cd *p, size_t i) {
+  const __attribute__((address_space(1))) double *q =
+      (const __attribute__((address_space(1))) double *)p + 2 * i;
+  return cd{q[0], q[1]};
+}
+
 // FP64 MFMA 16x16x4 (one wave): A operand A[i][kk] in lane i + 16 kk, B operand
 // B[kk][j] in lane j + 16 kk, accumulator D[i][j] in lane j + 16 (i % 4),
 // register i / 4.
@@ -960,7 +973,7 @@ __global__ __launch_bounds__(256) void k_tsgemm_mfma(int n, ColList X, int m, co
     for (int u = 0; u < 4; ++u) {
       const int kcol = k0 + 4 * u + lk;
       const int kc = min(kcol, m - 1);
-      const V v = cols[kc][row];
+      const V v = gload(cols[kc], row);
       if constexpr (ndv == 2) {
         xr[u] = ((const cd &)v).x;
         xi[u] = ((const cd &)v).y;
