@@ -262,6 +262,50 @@ __device__ __forceinline__ T spmv_dir8(const Sell<M> &A, int row, const V *r, co
   return a;
 }
 
+// One row of a sliced-ELL matrix of at most 8 entries per row, split into
+// phases: the column indices and values, the gathers of r and p at those
+// columns, and the sum with p = r + beta p formed at each gathered column (as
+// in spmv_dir8).  The first two phases do not depend on beta, so k_it1 issues
+// them before it reduces the previous iteration's partials.
+template <class V, class M>
+struct Row8 {
+  int w;
+  int c[8];
+  M v[8];
+  V g[8], h[8];
+};
+template <class V, class M>
+__device__ __forceinline__ void row8_index(const Sell<M> &A, int row, Row8<V, M> &L) {
+  const int slice = row >> 6, lane = row & 63;
+  const int b0 = A.sliceptr[slice];
+  L.w = (A.sliceptr[slice + 1] - b0) >> 6;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < L.w) {
+      L.c[j] = A.col[b0 + lane + RBICG_WAVE * j];
+      L.v[j] = A.val[b0 + lane + RBICG_WAVE * j];
+    }
+}
+template <class V, class M>
+__device__ __forceinline__ void row8_gather(const V *r, const V *p, Row8<V, M> &L) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < L.w) {
+      L.g[j] = r[L.c[j]];
+      L.h[j] = p[L.c[j]];
+    }
+}
+template <class V, class M, class T>
+__device__ __forceinline__ T row8_sum(const Sell<M> &A, const Row8<V, M> &L, T beta, V rrow,
+                                      V prow) {
+  T a = zero<T>();
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < L.w) a += up(L.v[j]) * up(down<V>(up(L.g[j]) + beta * up(L.h[j])));
+  if (A.shifted) a = shift_apply<M, T>(A, a, up(down<V>(up(rrow) + beta * up(prow))));
+  return a;
+}
+
 template <class V, class M, class T>
 __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   const int slice = row >> 6, lane = row & 63;
@@ -403,12 +447,30 @@ __global__ __launch_bounds__(IB) void k_it1(
   const int ls = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
   __shared__ double tmp[IB];
   __shared__ double red[8];
-  T beta;
-  if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
-  const T betac = cj(beta);
   const int n = A.n;
   const int stride = gridDim.x * IB;
   const int row0 = blockIdx.x * IB + threadIdx.x;
+  // one row per thread: the row's own entries, A's indices, values and
+  // gathers and A^H's indices and values are loaded before the partials of
+  // the previous iteration are reduced (none of them depends on beta)
+  Row8<V, M> LA, LB;
+  V pre[4] = {};  // r, r~, p, p~ at the row
+  bool fast = false;
+  if constexpr (RPT == 1 && sizeof(M) <= 8 && sizeof(V) <= 8) {  // real data (register budget)
+    if (row0 < n) {
+      pre[0] = r[row0];
+      pre[1] = rt[row0];
+      pre[2] = p[row0];
+      pre[3] = pt[row0];
+      row8_index(A, row0, LA);
+      row8_index(AH, row0, LB);
+      fast = LA.w <= 8 && LB.w <= 8;
+      if (fast) row8_gather(r, p, LA);
+    }
+  }
+  T beta;
+  if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
+  const T betac = cj(beta);
   // per row: z, z~, r_{i-1}, r~_{i-1} and conj(p~) as stored
   T zr[RPT], ztr[RPT], rr_[RPT], rtr_[RPT], cpt[RPT];
   T s0 = zero<T>();
@@ -421,16 +483,21 @@ __global__ __launch_bounds__(IB) void k_it1(
     cpt[q] = zero<T>();
     const int row = row0 + q * stride;
     if (row < n) {
-      const V rv = r[row], rtv = rt[row];
+      const V rv = fast ? pre[0] : r[row], rtv = fast ? pre[1] : rt[row];
+      const V pv = fast ? pre[2] : p[row], ptv0 = fast ? pre[3] : pt[row];
       rr_[q] = up(rv);
       rtr_[q] = up(rtv);
-      pn[row] = down<V>(up(rv) + beta * up(p[row]));
-      const V ptv = down<V>(up(rtv) + betac * up(pt[row]));
+      pn[row] = down<V>(up(rv) + beta * up(pv));
+      const V ptv = down<V>(up(rtv) + betac * up(ptv0));
       ptn[row] = ptv;
       cpt[q] = cj(up(ptv));
       // one row per thread: the unrolled gathers fit the register budget
       T za, zb;
-      if constexpr (RPT == 1) {
+      if (fast) {
+        row8_gather(rt, pt, LB);
+        za = row8_sum<V, M, T>(A, LA, beta, rv, pv);
+        zb = row8_sum<V, M, T>(AH, LB, betac, rtv, ptv0);
+      } else if constexpr (RPT == 1) {
         za = spmv_dir8<V, M, T>(A, row, r, p, beta);
         zb = spmv_dir8<V, M, T>(AH, row, rt, pt, betac);
       } else {
@@ -525,6 +592,30 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
   __shared__ double lds[NW * 4];
   __shared__ double tmp[IB];
   __shared__ double zl[P1S];
+  // The first row's streams (and its first KPF columns of C, C~) do not
+  // depend on the scalars: their loads are issued before the partials are
+  // reduced, so that the reduction runs under their latency.
+  constexpr int KPF = 4;
+  const int stride = gridDim.x * IB;
+  const int row0 = blockIdx.x * IB + threadIdx.x;
+  V f[8] = {};
+  V fc[KPF] = {}, fct[KPF] = {};
+  if (row0 < n) {
+    f[0] = z[row0];
+    f[1] = zt[row0];
+    f[2] = r[row0];
+    f[3] = rt[row0];
+    f[4] = x[row0];
+    f[5] = xt[row0];
+    f[6] = pn[row0];
+    f[7] = ptn[row0];
+#pragma unroll
+    for (int j = 0; j < KPF; ++j)
+      if (j < k) {
+        fc[j] = C[(size_t)j * ld + row0];
+        fct[j] = Ct[(size_t)j * ld + row0];
+      }
+  }
   const int nv1 = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
   breduce(P1, gridDim.x, nv1, tmp, zl);
   T sigma = get<T>(zl, 3 * k);
@@ -556,16 +647,33 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
       set<T>(S->zc, k + j, ut);
     }
   }
-  const int stride = gridDim.x * IB;
   double rr = 0.0, rtrt = 0.0;
   T rho = zero<T>();
-  for (int row = blockIdx.x * IB + threadIdx.x; row < n; row += stride) {
-    T qq = up(z[row]), qqt = up(zt[row]);
-    T rv = up(r[row]), rtv = up(rt[row]);
+  for (int row = row0; row < n; row += stride) {
+    const bool pre = row == row0;
+    if (!pre) {
+      f[0] = z[row];
+      f[1] = zt[row];
+      f[2] = r[row];
+      f[3] = rt[row];
+      f[4] = x[row];
+      f[5] = xt[row];
+      f[6] = pn[row];
+      f[7] = ptn[row];
+    }
+    T qq = up(f[0]), qqt = up(f[1]);
+    T rv = up(f[2]), rtv = up(f[3]);
     if (k > 0) {
       T s = zero<T>(), st = zero<T>(), g = zero<T>(), gt = zero<T>();
       for (int j = 0; j < k; ++j) {
-        const T cv = up(C[(size_t)j * ld + row]), ctv = up(Ct[(size_t)j * ld + row]);
+        T cv, ctv;
+        if (pre && j < KPF) {
+          cv = up(fc[j < KPF ? j : 0]);
+          ctv = up(fct[j < KPF ? j : 0]);
+        } else {
+          cv = up(C[(size_t)j * ld + row]);
+          ctv = up(Ct[(size_t)j * ld + row]);
+        }
         s += cv * get<T>(zl, j);
         st += ctv * get<T>(zl, k + j);
         if (rp) {
@@ -580,8 +688,8 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
         rtv = up(down<V>(rtv - gt));
       }
     }
-    x[row] = down<V>(up(x[row]) + al * up(pn[row]));
-    xt[row] = down<V>(up(xt[row]) + alc * up(ptn[row]));
+    x[row] = down<V>(up(f[4]) + al * up(f[6]));
+    xt[row] = down<V>(up(f[5]) + alc * up(f[7]));
     rv = up(down<V>(rv - al * qq));
     rtv = up(down<V>(rtv - alc * qqt));
     r[row] = down<V>(rv);
