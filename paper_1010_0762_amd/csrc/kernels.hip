@@ -439,7 +439,6 @@ __global__ __launch_bounds__(IB) void k_it1(
     int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, const double *__restrict__ P3,
     double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp) {
   using T = typename Ar<V>::T;
-  if (S->done) return;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
   // wave partials, NW rows of ls values (dynamic: sized by the recycle
   // dimension, so that the block leaves room on its CU for cycle-end kernels)
@@ -468,6 +467,9 @@ __global__ __launch_bounds__(IB) void k_it1(
       if (fast) row8_gather(r, p, LA);
     }
   }
+  // after the loads above are in flight (a launch past the stopping test
+  // reads and discards them)
+  if (S->done) return;
   T beta;
   if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
   const T betac = cj(beta);
@@ -587,7 +589,6 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
                                             double *__restrict__ P3, Scalars *S, double *rec,
                                             int it, int rp) {
   using T = typename Ar<V>::T;
-  if (S->done) return;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
   __shared__ double lds[NW * 4];
   __shared__ double tmp[IB];
@@ -616,6 +617,7 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
         fct[j] = Ct[(size_t)j * ld + row0];
       }
   }
+  if (S->done) return;  // after the loads above are in flight
   const int nv1 = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
   breduce(P1, gridDim.x, nv1, tmp, zl);
   T sigma = get<T>(zl, 3 * k);
