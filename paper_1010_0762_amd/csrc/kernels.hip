@@ -908,16 +908,17 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 template <class V, int SR, int GRAM_NLD>
 __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int mx, ColList Y,
                                                           int my, int rows_per_chunk,
-                                                          double *partial) {
+                                                          double *partial, int same) {
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
   constexpr int PC = SR + 2;
   extern __shared__ double sm[];
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
-  const size_t bufsz = (size_t)ndv * (mxp + myp) * PC;
+  // same: Y is X (a Hermitian Gram); its columns are staged once
+  const int ncol = same ? mxp : mxp + myp;
+  const size_t bufsz = (size_t)ndv * ncol * PC;
   const int TY = myp / 16, T = (mxp / 16) * TY;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ncol = mxp + myp;
   const int nval = ncol * SR;
   d4 acc[GRAM_MAXT][ndv];
 #pragma unroll
@@ -994,7 +995,7 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
         if (tile < T) {
           const int ti = tile / TY, tj = tile % TY;
           const double *xa = buf + (size_t)(ti * 16 + li) * PC + lk;
-          const double *yb = buf + (size_t)(mxp + tj * 16 + li) * PC + lk;
+          const double *yb = buf + (size_t)((same ? 0 : mxp) + tj * 16 + li) * PC + lk;
           const double ar = xa[kk], br = yb[kk];
           if constexpr (ndv == 1) {
             acc[t][0] = mfma(ar, br, acc[t][0]);
@@ -1646,11 +1647,11 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
   const int rpc = (int)(((size_t)n + nchunks - 1) / nchunks);
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
-  const int ncol = mxp + myp;
-  // longest slab (contiguous run per column) whose two LDS buffers fit.
-  // Real data take the variants with 18 prefetch slots per thread (fewer
-  // registers, at most ~80 KB of LDS): a Gram block then leaves room on its
-  // CU for a block of the iteration kernels running on the other stream.
+  bool same = mx == my;
+  for (int c = 0; same && c < mx; ++c) same = X.p[c] == Y.p[c];
+  const int ncol = same ? mxp : mxp + myp;
+  // Slabs of 32 rows while the columns fit 18 prefetch slots per thread
+  // (and, complex, the two LDS buffers), else 16 rows.
   const int sr_big = 32;
   const bool big = ndv == 2 ? 2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES
                             : (size_t)ncol * sr_big <= 18 * GRAM_BLOCK;
@@ -1659,17 +1660,17 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
   if (ndv == 1) {
     if (big)
       hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial);
+                         mx, Y, my, rpc, partial, same ? 1 : 0);
     else
       hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial);
+                         mx, Y, my, rpc, partial, same ? 1 : 0);
   } else {
     if (big)
       hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial);
+                         mx, Y, my, rpc, partial, same ? 1 : 0);
     else
       hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial);
+                         mx, Y, my, rpc, partial, same ? 1 : 0);
   }
   const int count = 2 * mx * my;
   hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count)), dim3(RBICG_BLOCK), 0, st, partial,
