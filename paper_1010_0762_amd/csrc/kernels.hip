@@ -316,6 +316,15 @@ __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   return acc;
 }
 
+// Row chunk of block b of an iteration kernel.  Blocks are dispatched
+// round-robin over the 8 XCDs (block b on XCD b mod 8), so b -> (b mod 8)
+// nb/8 + b/8 gives each XCD one contiguous range of rows: the neighbour planes
+// that its stencil rows gather (rows +-N^2 away) then mostly sit in the same
+// XCD's L2 instead of being fetched again by another XCD.
+__device__ __forceinline__ int xcd_chunk(int b, int nb) {
+  return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // Stopping test of iteration it-1 and beta_{it-1} (start of iteration it).
 // Every block computes the same values; block 0 records them.  Returns false
 // (uniformly) when the solve must stop.
@@ -448,7 +457,7 @@ __global__ __launch_bounds__(IB) void k_it1(
   __shared__ double red[8];
   const int n = A.n;
   const int stride = gridDim.x * IB;
-  const int row0 = blockIdx.x * IB + threadIdx.x;
+  const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x;
   // one row per thread: the row's own entries, A's indices, values and
   // gathers and A^H's indices and values are loaded before the partials of
   // the previous iteration are reduced (none of them depends on beta)
@@ -598,7 +607,7 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
   // reduced, so that the reduction runs under their latency.
   constexpr int KPF = 4;
   const int stride = gridDim.x * IB;
-  const int row0 = blockIdx.x * IB + threadIdx.x;
+  const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x;
   V f[8] = {};
   V fc[KPF] = {}, fct[KPF] = {};
   if (row0 < n) {
