@@ -1032,10 +1032,10 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
       for (int v = 0; v < 4; ++v) {
         const int gi = ti * 16 + lk + 4 * v;
         if (gi < mx && gj < my) {
-          double *o = partial + ((size_t)blockIdx.x * mx * my + (size_t)gi * my + gj) * 2;
+          // real data: one double per entry (the reduction fills in Im = 0)
+          double *o = partial + ((size_t)blockIdx.x * mx * my + (size_t)gi * my + gj) * ndv;
           o[0] = acc[t][0][v];
           if constexpr (ndv == 2) o[1] = acc[t][ndv - 1][v];
-          else o[1] = 0.0;
         }
       }
     }
@@ -1043,21 +1043,35 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
 }
 
 // G = sum over chunks of the partials (fixed order); G is mx x my complex,
-// stored row-major by (i, j) as in the partials.
-__global__ void k_gram_reduce(const double *partial, int nchunks, int count, double *G) {
-  const int t = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  if (t >= count) return;
-  // four independent chains keep several loads in flight; fixed order
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int c = 0;
-  for (; c + 4 <= nchunks; c += 4) {
-    s0 += partial[(size_t)c * count + t];
-    s1 += partial[(size_t)(c + 1) * count + t];
-    s2 += partial[(size_t)(c + 2) * count + t];
-    s3 += partial[(size_t)(c + 3) * count + t];
+// stored row-major by (i, j) as in the partials.  real: the partials hold
+// count real values and G[2t], G[2t + 1] = (sum, 0).
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *partial, int nchunks, int count,
+                                                     double *G, int real) {
+  // 8 lanes per entry, each summing every 8th chunk in two chains; the 8
+  // sums are then added in a fixed order, so the bits do not depend on timing
+  __shared__ double sub[256];
+  const int e = blockIdx.x * 32 + (threadIdx.x >> 3), sl = threadIdx.x & 7;
+  double s0 = 0.0, s1 = 0.0;
+  if (e < count) {
+    int c = sl;
+    for (; c + 8 < nchunks; c += 16) {
+      s0 += partial[(size_t)c * count + e];
+      s1 += partial[(size_t)(c + 8) * count + e];
+    }
+    if (c < nchunks) s0 += partial[(size_t)c * count + e];
   }
-  for (; c < nchunks; ++c) s0 += partial[(size_t)c * count + t];
-  G[t] = (s0 + s1) + (s2 + s3);
+  sub[threadIdx.x] = s0 + s1;
+  __syncthreads();
+  if (sl == 0 && e < count) {
+    const double *q = sub + threadIdx.x;
+    const double sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    if (real) {
+      G[2 * (size_t)e] = sum;
+      G[2 * (size_t)e + 1] = 0.0;
+    } else {
+      G[e] = sum;
+    }
+  }
 }
 
 // Tall-skinny product Y[:, c] = sum_l X_l W[l, c] (W: m x p complex,
@@ -1638,7 +1652,8 @@ void launch_add_d2d(hipStream_t st, double *x, const double *d, double sgn, size
   if (n == 0) return;
   hipLaunchKernelGGL(k_add_to_d<double>, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
 }
-int gram_chunks(int n) { return std::max(1, std::min(256, (n + 1023) / 1024)); }
+// two chunks per CU at full size (the per-block slab loop is latency-bound)
+int gram_chunks(int n) { return std::max(1, std::min(512, (n + 511) / 512)); }
 
 int gram_group(int mx, int complex_vals) {
   const int TX = (mx + 15) / 16;
@@ -1659,11 +1674,11 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
   bool same = mx == my;
   for (int c = 0; same && c < mx; ++c) same = X.p[c] == Y.p[c];
   const int ncol = same ? mxp : mxp + myp;
-  // Slabs of 32 rows while the columns fit 18 prefetch slots per thread
-  // (and, complex, the two LDS buffers), else 16 rows.
+  // Slabs of 32 rows while the columns fit 18 prefetch slots per thread and
+  // the two LDS buffers leave room for a second block on the CU, else 16.
   const int sr_big = 32;
-  const bool big = ndv == 2 ? 2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES
-                            : (size_t)ncol * sr_big <= 18 * GRAM_BLOCK;
+  const bool big = (size_t)ncol * sr_big <= 18 * GRAM_BLOCK &&
+                   2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES / 2;
   const int sr = big ? sr_big : sr_big / 2;
   const size_t lds = 2 * (size_t)ncol * (sr + 2) * ndv * sizeof(double);
   if (ndv == 1) {
@@ -1681,9 +1696,9 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
       hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
                          mx, Y, my, rpc, partial, same ? 1 : 0);
   }
-  const int count = 2 * mx * my;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count)), dim3(RBICG_BLOCK), 0, st, partial,
-                     nchunks, count, G);
+  const int count = ndv * mx * my;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((count + 31) / 32), dim3(256), 0, st, partial, nchunks,
+                     count, G, ndv == 1 ? 1 : 0);
 }
 template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
