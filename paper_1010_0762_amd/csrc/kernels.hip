@@ -676,21 +676,35 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
     T rv = up(f[2]), rtv = up(f[3]);
     if (k > 0) {
       T s = zero<T>(), st = zero<T>(), g = zero<T>(), gt = zero<T>();
-      for (int j = 0; j < k; ++j) {
-        T cv, ctv;
-        if (pre && j < KPF) {
-          cv = up(fc[j < KPF ? j : 0]);
-          ctv = up(fct[j < KPF ? j : 0]);
-        } else {
-          cv = up(C[(size_t)j * ld + row]);
-          ctv = up(Ct[(size_t)j * ld + row]);
-        }
+      auto acc = [&](int j, T cv, T ctv) {
         s += cv * get<T>(zl, j);
         st += ctv * get<T>(zl, k + j);
         if (rp) {
           g += cv * get<T>(zl, 3 * k + 1 + j);
           gt += ctv * get<T>(zl, 4 * k + 1 + j);
         }
+      };
+      int j = 0;
+      if (pre) {
+#pragma unroll
+        for (int u = 0; u < KPF; ++u)
+          if (u < k) acc(u, up(fc[u]), up(fct[u]));
+        j = min(KPF, k);
+      }
+      // the rest in groups whose loads are all issued before the sums
+      // (clamped indices; the sums run in column order)
+      constexpr int GE = sizeof(V) == 16 ? 4 : 8;
+      for (; j < k; j += GE) {
+        V cb[GE], ctb[GE];
+#pragma unroll
+        for (int u = 0; u < GE; ++u) {
+          const size_t off = (size_t)min(j + u, k - 1) * ld + row;
+          cb[u] = C[off];
+          ctb[u] = Ct[off];
+        }
+#pragma unroll
+        for (int u = 0; u < GE; ++u)
+          if (j + u < k) acc(j + u, up(cb[u]), up(ctb[u]));
       }
       qq = up(down<V>(qq - s));
       qqt = up(down<V>(qqt - st));
