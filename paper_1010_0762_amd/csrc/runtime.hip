@@ -901,21 +901,15 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     launch_fin_red(h->st, h->P3, nb, 2 + ndv<V>(), h->S->red);
     HIPCHECK(hipGetLastError());
     TRY(pull_scalars(h));
-    if (first) {
-      const double *rd = h->hS->red;
-      bn = std::sqrt(std::fabs(rd[16]));
-      btn = std::sqrt(std::fabs(rd[16 + nd]));
-      if (bn == 0.0) bn = std::sqrt(std::fabs(rd[24]));
-      if (btn == 0.0) btn = std::sqrt(std::fabs(rd[24 + nd]));
-      if (bn == 0.0) bn = 1.0;
-      if (btn == 0.0) btn = 1.0;
-    }
     double rn = std::sqrt(std::fabs(h->hS->red[0])), rtn = std::sqrt(std::fabs(h->hS->red[1]));
     cplx rho(h->hS->red[2], ndv<V>() == 2 ? h->hS->red[3] : 0.0);
     // Algorithm 2 step 3: re-seed x~ if (r_0, r~_0) vanishes
     while (std::abs(rho) <= 1e-14 * rn * rtn && rn > 0 && reseeds < 3) {
       launch_reseed<V>(h->st, xt, (size_t)n, (unsigned long long)(h->opt.seed + reseeds));
       launch_residual<V, M>(h->st, AH, bt, xt, rt);
+      if (first)  // the unprojected dual residual of the re-seeded guess (scale when b~ = 0)
+        launch_dots<V>(h->st, nb, n, rt, rt, nullptr, nullptr, nullptr, nullptr, h->partial,
+                       h->S->red + 24 + nd);
       if (ks > 0) {
         launch_restrict<V>(h->st, nb, n, r, Ct, rt, C, ks, ld, h->partial, h->S->gbuf);
         launch_expand2<V>(h->st, n, nullptr, U, 0.0, nullptr, C, 0.0, xt, Ut, 1.0, rt, Ct, -1.0, ks, ld, h->S->gbuf);
@@ -927,6 +921,17 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       rtn = std::sqrt(std::fabs(h->hS->red[1]));
       rho = cplx(h->hS->red[2], ndv<V>() == 2 ? h->hS->red[3] : 0.0);
       ++reseeds;
+    }
+    if (first) {
+      // reference norms ||b||, ||b~||; a vanishing one is replaced by the
+      // unprojected initial residual (after any re-seed)
+      const double *rd = h->hS->red;
+      bn = std::sqrt(std::fabs(rd[16]));
+      btn = std::sqrt(std::fabs(rd[16 + nd]));
+      if (bn == 0.0) bn = std::sqrt(std::fabs(rd[24]));
+      if (btn == 0.0) btn = std::sqrt(std::fabs(rd[24 + nd]));
+      if (bn == 0.0) bn = 1.0;
+      if (btn == 0.0) btn = 1.0;
     }
     first = false;
     const int run_start = total;

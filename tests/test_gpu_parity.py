@@ -154,6 +154,28 @@ def test_reseed_matches_oracle():
     assert _rel(_np(xt), ref.xt) <= 1e-8
 
 
+@pytest.mark.parametrize("xt0", ["random", "zero"])
+def test_zero_dual_rhs_matches_oracle(xt0):
+    """b~ = 0: the unprojected initial dual residual replaces ||b~|| as the
+    dual scale; with x~_0 = 0 that residual vanishes, (r~_0, r_0) = 0 forces a
+    re-seed, and the scale is taken after it (as in the oracle)."""
+    A = wl.convdiff(10, 2, [3.0, 1.0])
+    rng = np.random.default_rng(77)
+    b = rng.standard_normal(A.n)
+    bt = np.zeros(A.n)
+    xt = rng.standard_normal(A.n) if xt0 == "random" else np.zeros(A.n)
+    ref = oracle.rbicg(A, b, bt, xt=xt.copy(), tol=1e-9, maxit=400, update=False)
+    S = _solver(A, k=0, s=40, update=False)
+    x0 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    x, xtg, st = S.solve(_t(b), _t(bt), x0, _t(xt), tol=1e-9)
+    assert st["status"] == 0, st
+    assert st["reseeds"] == ref.reseeds == (1 if xt0 == "zero" else 0)
+    assert abs(st["iters"] - ref.iters) <= 1, (st["iters"], ref.iters)
+    assert st["relres"] <= 1e-9 and st["relres_dual"] <= 1e-9
+    assert abs(st["relres_dual"] - ref.relres_dual) <= 1e-10
+    assert _rel(_np(x), ref.x) <= 1e-8
+
+
 def test_bilinear_form():
     A = wl.convdiff(20, 2, [5.0, 2.0])
     D = A.to_dense()
