@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--serving-slots", type=int, default=4, help="concurrent request slots")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-inner / FP64-outer leg (128^3, 8 systems)")
+    ap.add_argument("--no-irka", action="store_true", help="skip the IRKA leg")
     ap.add_argument("--no-shifted", action="store_true",
                     help="skip the batched shifted-pair leg (48^3, 8 shifts, 6 sweeps)")
     ap.add_argument("--no-k20", action="store_true",
@@ -168,6 +169,47 @@ def shifted_leg(args):
     return {"workload": "shifted_aniso3d_48^3_6sweeps_8shifts_k20_s40_tol1e-8", "n": A.n,
             "pair_solves_per_s": round(npairs / dt, 2), "ms_per_pass": round(dt * 1e3, 2),
             "iters_per_sweep": its, "all_converged": all(oks), "precision": "complex FP64"}
+
+
+def irka_leg(args):
+    """IRKA (Algorithm 3, E = I) on the 48^3 anisotropic operator (n = 110592),
+    r = 8 shifts from logspace(0, 4), nearly collocated b, c; shifted pairs to
+    1e-10, IRKA tolerance 1e-6 on the relative shift change.  Run once with a
+    k = 20 recycle space rebuilt every step from the shift of smallest modulus
+    and once without recycling (k = 0), each after an untimed warm-up run."""
+    import torch
+    from paper_1010_0762_amd import workloads as wl
+    from paper_1010_0762_amd.solver import Solver
+    from paper_1010_0762_amd.irka import irka
+    A, b, c, s0 = wl.irka_problem(N=48, r=8)
+    bt = torch.as_tensor(b.astype(np.complex128), device="cuda")
+    ct = torch.as_tensor(c.astype(np.complex128), device="cuda")
+    from paper_1010_0762_amd.solver import DeviceMatrix
+    out = {"workload": "irka_aniso3d_48^3_r8_tol1e-6_solves1e-10", "n": A.n}
+    M = DeviceMatrix(A)
+    for name, k in (("per_shift_recycling_k20", 20), ("shared_recycling_k20", 20),
+                    ("no_recycling", 0)):
+        if name.startswith("per_shift"):
+            S = [Solver(M, k=k, s=40, prec="c128", stream=torch.cuda.Stream()) for _ in range(8)]
+        else:
+            S = Solver(M, k=k, s=40, prec="c128", update=k > 0)
+        irka(S, bt, ct, s0, tol=1e-6, maxit=40, solve_tol=1e-10)
+        torch.cuda.synchronize()
+        for Si in (S if isinstance(S, list) else [S]):
+            Si.set_recycle(None, None)
+        t0 = time.perf_counter()
+        run = irka(S, bt, ct, s0, tol=1e-6, maxit=40, solve_tol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tot = int(sum(sum(v) for v in run.iters))
+        out[name] = {"steps": run.steps, "converged": run.converged, "all_solved": run.all_solved,
+                     "seconds": round(dt, 3), "pair_solves_per_s": round(8 * run.steps / dt, 2),
+                     "total_iters": tot, "iters_per_step": [int(sum(v)) for v in run.iters],
+                     "final_shifts": [round(float(x.real), 4) for x in run.shifts[-1]]}
+    n0 = out["no_recycling"]["total_iters"]
+    for name in ("per_shift_recycling_k20", "shared_recycling_k20"):
+        out[name]["iteration_saving_vs_none"] = round(1.0 - out[name]["total_iters"] / max(1, n0), 3)
+    return out
 
 
 def mixed_leg(args):
@@ -360,6 +402,7 @@ def main():
                  "iteration_wait_ms_total": round(prof["cycle_wait_ms"], 2)}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
     shifted = None if args.no_shifted else shifted_leg(args)
+    irka_res = None if args.no_irka else irka_leg(args)
     mixed = None if args.no_mixed else mixed_leg(args)
     out = {
         "metric": METRIC,
@@ -394,6 +437,7 @@ def main():
         "roofline": roof,
         "kernel_at_k20": k20,
         "shifted_pairs": shifted,
+        "irka": irka_res,
         "mixed_precision": mixed,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(seq),
     }

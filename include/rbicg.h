@@ -252,6 +252,19 @@ int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const vo
                         const void *c, void *X, void *Xt, double tol, int32_t update_from,
                         rbicg_stats *st);
 
+/* Reduced pencil of IRKA (Algorithm 3 step 4, and step 5 with E = I):
+ *   Ar = Xt^H A X,  Er = Xt^H X,  br = Xt^H b,  cr = X^H c   (m <= 32)
+ * for a RBICG_C128 handle on A (the unshifted matrix, whatever shifts the
+ * handle last solved with).  X, Xt: device n x m column-major complex (leading
+ * dimension n, as rbicg_solve_shifted writes them); b, c: device n-vectors or
+ * NULL (then br, cr are not written).  Ar, Er: host m x m complex, column-major
+ * interleaved; br, cr: host m complex.  A X is formed by the SpMM kernel and
+ * the projections by the FP64 MFMA Gram kernel; the call allocates and frees
+ * an n x (m + 2) device buffer and returns after the results are on the
+ * host. */
+int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
+                  const void *c, double *Ar, double *Er, double *br, double *cr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,9 +18,10 @@ extern "C" {
 
 /* Generalized eigenproblem P w = lambda Q w (Q = NULL: standard problem), the
  * form of eq. finalGenEigValue (Sec. 4.1) and of the first-cycle problem
- * T w = lambda w (Sec. 4.2).  Q must be nonsingular: the pencil is reduced to
- * Q^{-1} P by an LU solve, then Hessenberg reduction and shifted complex QR
- * give the Schur form.  Outputs (any may be NULL):
+ * T w = lambda w (Sec. 4.2), by the QZ algorithm of Moler and Stewart on the
+ * pencil itself (the real double-shift variant when P and Q are real, the
+ * complex single-shift variant otherwise); Q may be singular (infinite
+ * eigenvalues are returned as inf).  Outputs (any may be NULL):
  *   lam[2m]    eigenvalues
  *   W[2m*m]    right eigenvectors (unit 2-norm columns)
  *   Wl[2m*m]   left eigenvectors y: y^H P = lambda y^H Q (unit 2-norm),

@@ -15,6 +15,8 @@ Modules
   drivers  -- sequences of dual systems, shifted pairs (sigma I - A) sharing one
               recycle space, FP32-inner / FP64-outer refinement, bilinear forms.
   rng      -- SplitMix64 counter generator used when x~ must be re-seeded.
+  irka     -- IRKA (Algorithm 3, E = I) with direct solves, and transfer
+              functions of the full and reduced models.
 
 Pinned against: dense direct solves, CG and SciPy's BiCG iterates (textbook
 special cases), exact-eigenvector deflation, biorthogonality, the T-from-scalars
@@ -27,6 +29,7 @@ from .recycle import (t_from_scalars, harmonic_pencils, select_eigvecs,
                       biorthogonalize, first_cycle_eigvecs)
 from .drivers import (rbicg_sequence, shifted_pairs, mixed_refine, bilinear)
 from .rng import splitmix64, reseed_vector
+from . import irka
 
 __all__ = ["bicg", "rbicg", "SolveResult", "as_csr", "t_from_scalars",
            "harmonic_pencils", "select_eigvecs", "biorthogonalize",

@@ -72,6 +72,7 @@ SIGNATURES = {
     "rbicg_create_on": (ct.c_int, [_P, ct.POINTER(rbicg_opts), ct.POINTER(_P)]),
     "rbicg_update_recycle_on": (ct.c_int, [_P, _P]),
     "rbicg_profile": (ct.c_int, [_P, _I, _DP]),
+    "rbicg_project": (ct.c_int, [_P, _I, _P, _P, _P, _P, _DP, _DP, _DP, _DP]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),
     "rbicg_host_select": (ct.c_int, [_I, _DP, _DP, _DP, _I, _I, _DP, _DP]),
     "rbicg_host_eig_select": (ct.c_int, [_I, _DP, _DP, _I, _I, _DP, _DP]),

@@ -2216,3 +2216,72 @@ extern "C" int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigm
     return solve_shifted_impl<cd>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
   return solve_shifted_impl<double>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
 }
+
+extern "C" int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
+                             const void *c, double *Ar, double *Er, double *br, double *cr) {
+  if (!h || !X || !Xt || !Ar || !Er) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "projection needs a RBICG_C128 handle");
+  if (m < 1 || m > 32) return rbicg_fail(RBICG_EINVAL, "m=%d out of range [1, 32]", m);
+  if ((b == nullptr) != (c == nullptr) || (b && (!br || !cr)))
+    return rbicg_fail(RBICG_EINVAL, "b and c (with br, cr) must be given together");
+  const int n = h->n, nb = b ? 2 : 0;
+  // n x (m + 2) scratch: A X, then copies of b and c as extra Gram columns
+  cd *AX = nullptr;
+  HIPCHECK(hipMalloc((void **)&AX, (size_t)n * (m + 2) * sizeof(cd)));
+  int rc = 0;
+  {
+    if (h->mat_complex)
+      launch_spmm<cd, cd>(h->st, h->mat->A.view<cd>(), (const cd *)X, AX, n, m);
+    else
+      launch_spmm<cd, double>(h->st, h->mat->A.view<double>(), (const cd *)X, AX, n, m);
+    if (b) {
+      (void)hipMemcpyAsync(AX + (size_t)m * n, b, (size_t)n * sizeof(cd), hipMemcpyDeviceToDevice, h->st);
+      (void)hipMemcpyAsync(AX + (size_t)(m + 1) * n, c, (size_t)n * sizeof(cd), hipMemcpyDeviceToDevice, h->st);
+    }
+    // G1 = Xt^H [A X, X, b]  (m x (2m + 1)),  G2 = X^H c  (m x 1)
+    std::vector<const void *> Xl, Yl;
+    for (int j = 0; j < m; ++j) Xl.push_back((const cd *)Xt + (size_t)j * n);
+    for (int j = 0; j < m; ++j) Yl.push_back(AX + (size_t)j * n);
+    for (int j = 0; j < m; ++j) Yl.push_back((const cd *)X + (size_t)j * n);
+    if (b) Yl.push_back(AX + (size_t)m * n);
+    const int my = (int)Yl.size();
+    const int gy = gram_group(m, 1);
+    rc = gram_enqueue<cd>(h, Xl, Yl);
+    if (rc >= 0) rc = sync(h);
+    if (rc >= 0) {
+      const std::vector<cplx> G = gram_parse(h->hG, m, my, gy);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          const cplx a = G[(size_t)i * my + j], e = G[(size_t)i * my + m + j];
+          Ar[2 * (i + (size_t)j * m)] = a.real();
+          Ar[2 * (i + (size_t)j * m) + 1] = a.imag();
+          Er[2 * (i + (size_t)j * m)] = e.real();
+          Er[2 * (i + (size_t)j * m) + 1] = e.imag();
+        }
+      if (b)
+        for (int i = 0; i < m; ++i) {
+          const cplx v = G[(size_t)i * my + 2 * m];
+          br[2 * i] = v.real();
+          br[2 * i + 1] = v.imag();
+        }
+    }
+    if (rc >= 0 && nb) {
+      std::vector<const void *> Xc, Yc{AX + (size_t)(m + 1) * n};
+      for (int j = 0; j < m; ++j) Xc.push_back((const cd *)X + (size_t)j * n);
+      const int gy2 = gram_group(m, 1);
+      rc = gram_enqueue<cd>(h, Xc, Yc);
+      if (rc >= 0) rc = sync(h);
+      if (rc >= 0) {
+        const std::vector<cplx> G = gram_parse(h->hG, m, 1, gy2);
+        for (int i = 0; i < m; ++i) {
+          cr[2 * i] = G[i].real();
+          cr[2 * i + 1] = G[i].imag();
+        }
+      }
+    }
+  }
+  const hipError_t e = hipFree(AX);
+  if (rc < 0) return rc;
+  if (e != hipSuccess) return rbicg_fail(RBICG_EHIP, "hipFree: %s", hipGetErrorString(e));
+  return RBICG_OK;
+}

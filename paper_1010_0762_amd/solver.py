@@ -208,6 +208,31 @@ class Solver:
         v = complex(val[0], val[1]) if self.prec == "c128" else float(val[0])
         return v, err.value, st.as_dict()
 
+    def project(self, X, Xt, b=None, c=None):
+        """rbicg_project: Ar = Xt^H A X, Er = Xt^H X (and br = Xt^H b, cr = X^H c
+        when b, c are given) for (m, n) complex CUDA tensors X, Xt.  Returns
+        numpy (Ar, Er) or (Ar, Er, br, cr)."""
+        m = X.shape[0]
+        for name, t in (("X", X), ("Xt", Xt)):
+            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                    and tuple(t.shape) == (m, self.n)):
+                raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor of shape ({m}, {self.n})")
+        Ar = np.zeros(m * m, np.complex128)  # column-major m x m
+        Er = np.zeros(m * m, np.complex128)
+        br = np.zeros(m, np.complex128)
+        cr = np.zeros(m, np.complex128)
+        with_bc = b is not None
+        rc = self.lib.rbicg_project(
+            self.h, m, ct.c_void_p(X.data_ptr()), ct.c_void_p(Xt.data_ptr()),
+            self._vec(b, "b") if with_bc else None, self._vec(c, "c") if with_bc else None,
+            Ar.view(np.float64).ctypes.data_as(_lib._DP), Er.view(np.float64).ctypes.data_as(_lib._DP),
+            br.view(np.float64).ctypes.data_as(_lib._DP) if with_bc else None,
+            cr.view(np.float64).ctypes.data_as(_lib._DP) if with_bc else None)
+        _lib.check(rc, "rbicg_project")
+        Ar = Ar.reshape((m, m), order="F")
+        Er = Er.reshape((m, m), order="F")
+        return (Ar, Er, br, cr) if with_bc else (Ar, Er)
+
     def solve_shifted(self, sigmas, b, c, X=None, Xt=None, tol=1e-8, update_from=-1):
         """rbicg_solve_shifted: (sigma_s I - A) X[s] = b, (sigma_s I - A)^H Xt[s] = c
         for every shift; X, Xt are (S, n) complex CUDA tensors (initial guesses

@@ -153,6 +153,19 @@ def cfg2_sequence(nsys: int = 10, N: int = 64) -> DualSequence:
     return DualSequence(f"convdiff3d_{N}", mats, [b] * nsys, [bt] * nsys, 20, 40, 1e-8)
 
 
+def irka_problem(N: int = 48, r: int = 8, eps: float = 0.3):
+    """IRKA (Algorithm 3, E = I) on A = -L_kappa - 0.1 I (N^3, symmetric
+    negative definite like the rail model's A): input b ~ N(0,1), output
+    c = b + eps g with g ~ N(0,1) (a nearly collocated SISO pair), r initial
+    shifts logarithmically spaced on [1, 1e4].  Returns (A, b, c, sigma0)."""
+    rng = np.random.default_rng(BASE_SEED + 6)
+    A = aniso_diffusion(N)
+    n = N ** 3
+    b = rng.standard_normal(n)
+    c = b + eps * rng.standard_normal(n)
+    return A, b, c, np.logspace(0.0, 4.0, r).astype(np.complex128)
+
+
 def cfg3_shifts(nsweeps: int = 6, N: int = 48):
     """Shifted pairs (sigma I - A) x = b, (sigma I - A)^H x~ = c with
     A = -L_kappa - 0.1 I on N^3 (default 48^3, n=110592).  Per sweep 8 shifts in
