@@ -179,6 +179,44 @@ class Solver:
         kk = min(k.value, kcap)
         return tuple(b[:kk].t() for b in bufs)
 
+    def save_recycle(self, path, next=True):
+        """Write the recycle space to an .npz file, so that a sequence can be
+        resumed in another process: U, U~ (n x k) -- the space the cycle
+        updates built for the next system when next is set and one exists,
+        else the installed one -- with n and the precision mode.  Plain arrays
+        only (no pickled objects)."""
+        U, Ut, _, _ = self.get_recycle(next=next)
+        if next and U.shape[1] == 0:
+            U, Ut, _, _ = self.get_recycle(next=False)
+        np.savez(path, U=U.cpu().numpy(), Ut=Ut.cpu().numpy(), n=np.int64(self.n),
+                 prec=np.array(self.prec))
+
+    def load_recycle(self, path):
+        """Install a space written by save_recycle: C = A U, C~ = A^H U~ and the
+        biorthogonalization (Sec. 4.3) are recomputed for this handle's matrix,
+        as rbicg_update_recycle does for a space built in the same process."""
+        with np.load(path, allow_pickle=False) as f:
+            if int(f["n"]) != self.n:
+                raise ValueError(f"recycle space of size {int(f['n'])} for a handle of size {self.n}")
+            if str(f["prec"]) != self.prec:
+                raise ValueError(f"recycle space of precision {f['prec']} for a {self.prec} handle")
+            U = torch.as_tensor(f["U"], device="cuda")
+            Ut = torch.as_tensor(f["Ut"], device="cuda")
+        self.set_recycle(U if U.shape[1] else None, Ut if U.shape[1] else None)
+
+    def bilinear_sequence(self, items, tol=1e-8):
+        """Bilinear forms u_j^H A_j^{-1} w_j along a sequence (Sec. 1; e.g. one
+        form per sample of a parameter-dependent A): items = [(A_j, u_j, w_j)]
+        with A_j a DeviceMatrix, CSR or None (same matrix).  The recycle space
+        built while solving form j is installed for form j+1.  Returns
+        [(value, error bound, stats)] as bilinear does."""
+        out = []
+        for j, (A, u, w) in enumerate(items):
+            if j:
+                self.update_recycle(A)
+            out.append(self.bilinear(u, w, tol))
+        return out
+
     def profile(self, reset=False):
         """Per-kernel timing (rbicg_profile): dict with ms/launch counts and
         the algorithmic bytes of one SpMV-kernel launch and of one iteration."""
