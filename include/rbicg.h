@@ -261,7 +261,8 @@ int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const vo
  * interleaved; br, cr: host m complex.  A X is formed by the SpMM kernel and
  * the projections by the FP64 MFMA Gram kernel; the call allocates and frees
  * an n x (m + 2) device buffer and returns after the results are on the
- * host. */
+ * host.  RBICG_EINVAL for m out of range, b without c, or an m x (2m + 1) Gram
+ * larger than the handle's Gram buffers (sized by its k and s). */
 int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
                   const void *c, double *Ar, double *Er, double *br, double *cr);
 

@@ -314,6 +314,7 @@ struct rbicg_s {
   int nb = 1;                 // blocks of the iteration kernels
   double *gpart = nullptr;
   size_t gpart_bytes = 0;
+  size_t gram_cap = 0;  // complex entries of Gd / hG (mx * my of one Gram)
   double *Gd = nullptr;
   cd *Wd = nullptr;
   // pinned host staging
@@ -428,6 +429,8 @@ template <class V>
 int gram_enqueue(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y) {
   const int mx = (int)X.size(), my = (int)Y.size();
   if (mx > 128 || mx < 1 || my < 1) return rbicg_fail(RBICG_EINVAL, "gram shape %d x %d unsupported", mx, my);
+  if ((size_t)mx * my > h->gram_cap)
+    return rbicg_fail(RBICG_EINVAL, "gram %d x %d exceeds the handle's Gram buffers (k, s too small)", mx, my);
   const int gy = gram_group(mx, sizeof(V) == 16 ? 1 : 0);
   const int nchunks = gram_chunks(h->n);
   ColList xl{};
@@ -1842,6 +1845,7 @@ int alloc_workspace(rbicg_s *h) {
   h->gpart_bytes = (size_t)gram_chunks(h->n) * wx * 128 * 2 * sizeof(double);
   TRY(dalloc(h, (void **)&h->gpart, h->gpart_bytes));
   TRY(dalloc(h, (void **)&h->Gd, (size_t)wx * wy * 2 * sizeof(double)));
+  h->gram_cap = (size_t)wx * wy;
   TRY(dalloc(h, (void **)&h->Wd, 6 * RBICG_WSLOT * sizeof(cd)));
   if (h->opt.profile) {
     const int nev = 8 * std::max(8, h->opt.chunk);
