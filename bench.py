@@ -95,6 +95,38 @@ def cpu_baseline(seq):
                        f"vector/basis work on {threads} BLAS threads")}
 
 
+def bicg_leg(args, seq, mats, b, bt):
+    """Context for the headline: the same 10-system sequence solved by plain
+    BiCG (k = 0, Algorithm 1) on the same kernels, timed after one untimed
+    pass.  On this operator recycling does not lower the iteration count
+    (the retained spaces are small), so this shows what the cycle-end work
+    costs."""
+    import torch
+    from paper_1010_0762_amd.solver import Solver
+    S = Solver(mats[0], k=0, s=seq.s, update=False, chunk=args.chunk)
+    x = torch.zeros_like(b)
+    xt = torch.zeros_like(bt)
+
+    def one_pass():
+        its = []
+        for j in range(len(mats)):
+            S.update_recycle(mats[j])
+            x.zero_()
+            xt.zero_()
+            _, _, st = S.solve(b, bt, x, xt, tol=seq.tol)
+            its.append(st["iters"])
+        return its
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = one_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"solves_per_s": round(len(mats) / dt, 3), "ms_per_sequence": round(dt * 1e3, 2),
+            "iters_per_system": its, "us_per_iter": round(dt / sum(its) * 1e6, 2)}
+
+
 def kernel_at_k20(args, seq, mats, b, bt):
     """Iteration-kernel timing with a full 20-vector recycle space installed
     (the 20 lowest sine modes as U = U~, no updates) on system 0, outside the
@@ -401,6 +433,7 @@ def main():
                  "latency_ms_avg": round(prof["cycle_latency_ms"] / nup, 3),
                  "iteration_wait_ms_total": round(prof["cycle_wait_ms"], 2)}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
+    bicg = None if args.no_k20 else bicg_leg(args, seq, mats, b, bt)
     shifted = None if args.no_shifted else shifted_leg(args)
     irka_res = None if args.no_irka else irka_leg(args)
     mixed = None if args.no_mixed else mixed_leg(args)
@@ -436,6 +469,7 @@ def main():
         "cycle_end": cycle_end,
         "roofline": roof,
         "kernel_at_k20": k20,
+        "bicg_same_sequence": bicg,
         "shifted_pairs": shifted,
         "irka": irka_res,
         "mixed_precision": mixed,

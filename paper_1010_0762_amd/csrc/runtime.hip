@@ -1226,6 +1226,24 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       (void)hipEventDestroy(J.ready);
       jobs.pop_back();
     }
+    total = completed;
+    status = dev_status;
+    const bool stalled = status == ST_DIVERGED && !inner;
+    // Algorithm 2 step 7 and the true residuals need nothing from the cycle
+    // updates still in flight: they are enqueued before the drain below, and
+    // their reductions are read after it
+    if (!stalled) {
+      // x -= U zeta_c, x~ -= U~ zeta~_c
+      if (ks > 0)
+        launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
+      if (!inner) {
+        launch_residual<V, M>(h->st, A, b, x, (V *)h->t1);
+        launch_residual<V, M>(h->st, AH, bt, xt, (V *)h->t2);
+        launch_dots<V>(h->st, nb, n, (V *)h->t1, (V *)h->t1, (V *)h->t2, (V *)h->t2, nullptr, nullptr,
+                       h->partial, h->S->red);
+        HIPCHECK(hipGetLastError());
+      }
+    }
     // finish the remaining updates of this run; later work on the iteration
     // stream (next run, next system's recycle space) is ordered after them
     while (!jobs.empty()) TRY(advance(true));
@@ -1233,8 +1251,6 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       HIPCHECK(hipEventRecord(h->jev, h->jst));
       HIPCHECK(hipStreamWaitEvent(h->st, h->jev, 0));
     }
-    total = completed;
-    status = dev_status;
     // keep this run's log
     if (total > run_start) {
       std::vector<double> tmp((size_t)(total - run_start) * LOG_STRIDE);
@@ -1243,7 +1259,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       for (size_t t = 0; t < tmp.size(); t += LOG_STRIDE) tmp[t + 9] = restarts;
       fulllog.insert(fulllog.end(), tmp.begin(), tmp.end());
     }
-    if (status == ST_DIVERGED && !inner) {
+    if (stalled) {
       // stall guard: start again from the initial guesses without the
       // recycle space (the cycle spaces of the stalled run are dropped too)
       HIPCHECK(hipMemcpyAsync(x, h->xs0, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
@@ -1258,15 +1274,10 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       status = ST_MAXIT;
       break;
     }
-    // Algorithm 2 step 7: x -= U zeta_c, x~ -= U~ zeta~_c
-    if (ks > 0)
-      launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
     if (inner) break;  // the FP64 outer loop checks the true residual
-    // true residuals
-    launch_residual<V, M>(h->st, A, b, x, (V *)h->t1);
-    launch_residual<V, M>(h->st, AH, bt, xt, (V *)h->t2);
-    TRY(host_dots<V>(h, (V *)h->t1, (V *)h->t1, (V *)h->t2, (V *)h->t2, nullptr, nullptr, d));
-    const double tr = std::sqrt(std::fabs(d[0].real())), trt = std::sqrt(std::fabs(d[1].real()));
+    // true residuals (reductions enqueued before the drain)
+    TRY(pull_scalars(h));
+    const double tr = std::sqrt(std::fabs(h->hS->red[0])), trt = std::sqrt(std::fabs(h->hS->red[nd]));
     relres = tr / bn;
     relres_dual = trt / btn;
     const bool true_ok = tr <= tol * bn && trt <= tol * btn;
