@@ -76,9 +76,11 @@ struct ShScalars {
   int done[SHMAX], status[SHMAX], iter[SHMAX], p[SHMAX];
   double bn[SHMAX], btn[SHMAX];
   double sig[2 * SHMAX];
-  // per shift: zeta_i, zeta~_i of the current iteration and the running
-  // zeta_c, zeta~_c (complex, p_sigma entries)
-  double zeta[SHMAX][2 * KSH], zetat[SHMAX][2 * KSH];
+  // per shift: beta and whether the iteration goes on (act1, from the
+  // stopping test), alpha and whether it updates (act, after sigma)
+  double beta[2 * SHMAX], alpha[2 * SHMAX];
+  int act1[SHMAX], act[SHMAX];
+  // per shift: the running zeta_c, zeta~_c (complex, p_sigma entries)
   double zc[SHMAX][2 * KSH], zct[SHMAX][2 * KSH];
 };
 

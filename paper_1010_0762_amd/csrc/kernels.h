@@ -69,18 +69,20 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
                    int ld);
 
 // ---- batched shifted pairs (see kernels.hip) ----
-int sh_blocks(int n);      // blocks of k_sh3 (partials of P3)
-int sh_sub_blocks(int n);  // blocks of k_sh_sub (partials of P2)
+int sh_blocks(int n);      // blocks of k_sh2 (partials of P3)
+int sh_sub_blocks(int n);  // blocks of k_sh_sub
+void launch_sh_state(hipStream_t st, int S, const double *P3, int nb3, ShScalars *Sh, double *rec,
+                     int it, int first);
 template <class M>
 void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
                 const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,
-                const double *P3, int nb3, ShScalars *Sh, double *rec, int it, int first);
-void launch_sh_coef(hipStream_t st, const double *G, ShScalars *Sh, const ShCoef *Co, cd *Y,
-                    cd *Yt, cd *Yx, cd *Yxt, int mode);
+                const ShScalars *Sh);
+void launch_sh_coef(hipStream_t st, int S, const double *G, int my, ShScalars *Sh,
+                    const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode, double *rec, int it);
 void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
-                   const cd *Zin, cd *Out, int ld, const cd *Ptn, double *P2, int nbe);
-void launch_sh3(hipStream_t st, int nb3, int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
-                const cd *Pn, const cd *Ptn, const cd *Q, const cd *Qt, const double *P2,
-                int nbe, double *P3, ShScalars *Sh, double *rec, int it, int upd);
-void launch_sh_fin(hipStream_t st, const double *P3, int nb3, ShScalars *Sh, double *rec, int it,
-                   int first);
+                   const cd *Zin, cd *Out, int ld, int nbe);
+// B, Bt: n x k2 column-major bases (leading dimension ld); ld * 9 * 16 < 2^32
+void launch_sh2(hipStream_t st, int n, int ld, int S, cd *X, cd *Xt, cd *R, cd *Rt, const cd *Pn,
+                const cd *Ptn, const cd *Z, const cd *Zt, const cd *B, const cd *Bt, int k2,
+                const cd *Y, const cd *Yt, ShScalars *Sh, double *P3, int nb, int upd);
+

@@ -1207,75 +1207,114 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V 
 // Batched IRKA-style pairs (sigma_s I - A) x_s = b, (sigma_s I - A)^H x~_s = c
 // for S shifts sharing one recycle space (Algorithm 3 steps 2-3 with E = I).
 // The batch vectors are n x S column-major (leading dimension ld), one column
-// per shift.  One iteration of Algorithm 2 for all shifts is
-//   k_sh1      per-shift stopping test and beta; p_s = r_s + beta_s p_s and
-//              z_s = sigma_s p_s - A p_s (dual: conj(sigma_s), A^H), each
-//              matrix entry read once per row for all shifts;
-//   Gram       w = [U~, A^H U~]^H [z_1..z_S], w~ = [U, A U]^H [z~_1..z~_S]
-//              (k_gram_mfma: one FP64-MFMA contraction of the shared basis
-//              against all shifts);
-//   k_sh_coef  zeta_s = K_s w_s, y_s = L_s zeta_s (per-shift rotations);
-//   k_sh_sub   q_s = z_s - [U, A U] y_s (MFMA tall-skinny product) and the
-//              partials of sigma_s = (p~_s, q_s);
-//   k_sh3      alpha_s, zeta_c += alpha zeta, x, x~, r, r~ updates and the
-//              partials of ||r_s||, ||r~_s||, (r~_s, r_s).
+// per shift.  One iteration of Algorithm 2 for all shifts is five launches:
+//   k_sh_state one block per shift: the stopping test of the previous
+//              iteration from the k_sh2 partials and beta_s;
+//   k_sh1      p_s = r_s + beta_s p_s and z_s = sigma_s p_s - A p_s (dual:
+//              conj(beta_s), conj(sigma_s), A^H); one block per (row block,
+//              side) for all shifts, the matrix row read once;
+//   Gram       [U~, A^H U~, U, A U, p~_1..p~_S]^H [z_1..z_S, z~_1..z~_S,
+//              p~_1..p~_S] (k_gram_mfma: one FP64-MFMA contraction of the
+//              shared bases against all shifts);
+//   k_sh_coef  one block per shift: zeta_s = K_s w_s, y_s = L_s zeta_s (and
+//              the dual), sigma_s = (p~_s, q_s) = (p~_s, z_s) - (p~_s^H
+//              [U, A U]) y_s, alpha_s and the zeta_c updates;
+//   k_sh2      per row q_s = z_s - [U, A U] y_s and q~_s (in registers, never
+//              stored), the x, x~, r, r~ updates and the partials of ||r_s||,
+//              ||r~_s||, (r~_s, r_s).
 // Shifts that have stopped are skipped.  Per-shift scalars are logged per
-// iteration in rec[(it * SHMAX + s) * SH_LOG + ...].
+// iteration in rec[(it * SHMAX + s) * SH_LOG + ...]; k_sh2 writes its
+// partials to P3[(s * nb + block) * 4 + i].
 
-// Per-shift stopping test of iteration it-1 and beta_{it-1}; act[s] = 1 for
-// the shifts that go on.  Every block computes the same values (all read the
-// same partials in the same order); block 0 records them.
-__device__ void sh_prologue(const double *P3, int nb, ShScalars *Sh, double *rec, int it,
-                            int first, double *tmp, double *red, cd *betas, int *act) {
-  const int S = Sh->S;
-  breduce(P3, nb, 4 * S, tmp, red);
-  const bool b0 = blockIdx.x == 0;
-  if (threadIdx.x < S) {
-    const int s = threadIdx.x;
-    int a = 0;
-    cd beta = {0.0, 0.0};
-    if (!Sh->done[s]) {
-      const double rn = sqrt(red[4 * s]), rtn = sqrt(red[4 * s + 1]);
-      const cd rho = {red[4 * s + 2], red[4 * s + 3]};
-      double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
-      if (b0) {
-        Rm1[4] = rho.x;
-        Rm1[5] = rho.y;
-        Rm1[6] = rn;
-        Rm1[7] = rtn;
-      }
-      int st = ST_RUNNING;
-      if (rn <= Sh->tol * Sh->bn[s] && rtn <= Sh->tol * Sh->btn[s]) st = ST_CONVERGED;
-      else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
-      else if (it > Sh->maxit) st = ST_MAXIT;
-      if (st != ST_RUNNING) {
-        if (b0) {
-          Sh->status[s] = st;
-          Sh->iter[s] = it - 1;
-          Sh->done[s] = 1;
-        }
-      } else {
-        a = 1;
-        if (!first) {
-          const double *Rm2 = rec + ((size_t)(it - 2) * SHMAX + s) * SH_LOG;
-          beta = cdiv(rho, cd{Rm2[4], Rm2[5]});
-        }
-        if (b0) {
-          double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
-          R0[2] = beta.x;
-          R0[3] = beta.y;
-        }
-      }
+// Block s: stopping test of iteration it-1 and beta_{it-1} for shift s of the
+// batch (act1, beta for k_sh1); records them in rec and, when the shift
+// stops, its status.  Also the final test after the last launched iteration.
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sh_state(const double *__restrict__ P3, int nb,
+                                                          ShScalars *Sh, double *rec, int it,
+                                                          int first) {
+  __shared__ double tmp[RBICG_BLOCK];
+  __shared__ double red[4];
+  const int s = blockIdx.x;
+  if (Sh->done[s]) {  // only this block writes done[s] in this launch
+    if (threadIdx.x == 0) Sh->act1[s] = 0;
+    return;
+  }
+  breduce(P3 + (size_t)s * nb * 4, nb, 4, tmp, red);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(red[0]), rtn = sqrt(red[1]);
+  const cd rho = {red[2], red[3]};
+  double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
+  Rm1[4] = rho.x;
+  Rm1[5] = rho.y;
+  Rm1[6] = rn;
+  Rm1[7] = rtn;
+  int st = ST_RUNNING;
+  if (rn <= Sh->tol * Sh->bn[s] && rtn <= Sh->tol * Sh->btn[s]) st = ST_CONVERGED;
+  else if (abs2(rho) == 0.0 || !isfin(rho) || !isfinite(rn) || !isfinite(rtn)) st = ST_BREAKDOWN;
+  else if (it > Sh->maxit) st = ST_MAXIT;
+  if (st != ST_RUNNING) {
+    Sh->status[s] = st;
+    Sh->iter[s] = it - 1;
+    Sh->done[s] = 1;
+    Sh->act1[s] = 0;
+    return;
+  }
+  cd b = {0.0, 0.0};
+  if (!first) {
+    const double *Rm2 = rec + ((size_t)(it - 2) * SHMAX + s) * SH_LOG;
+    b = cdiv(rho, cd{Rm2[4], Rm2[5]});
+  }
+  double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
+  R0[2] = b.x;
+  R0[3] = b.y;
+  Sh->beta[2 * s] = b.x;
+  Sh->beta[2 * s + 1] = b.y;
+  Sh->act1[s] = 1;
+}
+
+// Block b of k_sh1 -> (row block, side).  With nrb a multiple of 8 the blocks
+// of one XCD (b mod 8) cover one contiguous range of row blocks, both sides.
+__device__ __forceinline__ void sh1_block(int b, int nrb, int &rb, int &side) {
+  if ((nrb & 7) == 0) {
+    const int i = b >> 3;
+    rb = (b & 7) * (nrb >> 3) + (i >> 1);
+    side = i & 1;
+  } else {
+    rb = b >> 1;
+    side = b & 1;
+  }
+}
+
+// One row of (sigma I - A) (r + beta p) for two shifts at once from the row's
+// column byte offsets co and values v (w <= 8 entries): all gathers of both
+// shifts are issued before the sums (entry order, as spmv_dir).
+template <class M>
+__device__ __forceinline__ void sh1_pair(int w, const unsigned (&co)[8], const M (&v)[8],
+                                         const char *ra, const char *pa, const char *rb_,
+                                         const char *pb, unsigned roff, cd ba, cd bb, cd sa,
+                                         cd sb, cd &pna, cd &za, cd &pnb, cd &zb) {
+  cd ga[8], ha[8], gb[8], hb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < w) {
+      ga[j] = *(const cd *)(ra + co[j]);
+      ha[j] = *(const cd *)(pa + co[j]);
+      gb[j] = *(const cd *)(rb_ + co[j]);
+      hb[j] = *(const cd *)(pb + co[j]);
     }
-    act[s] = a;
-    betas[s] = beta;
-  }
-  __syncthreads();
-  if (b0 && threadIdx.x == 0) {
-    int any = 0;
-    for (int s = 0; s < S; ++s) any |= act[s];
-    if (!any) Sh->all_done = 1;
-  }
+  const cd ra0 = *(const cd *)(ra + roff), pa0 = *(const cd *)(pa + roff);
+  const cd rb0 = *(const cd *)(rb_ + roff), pb0 = *(const cd *)(pb + roff);
+  cd acca = {0.0, 0.0}, accb = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < w) {
+      acca += up(v[j]) * (ga[j] + ba * ha[j]);
+      accb += up(v[j]) * (gb[j] + bb * hb[j]);
+    }
+  pna = ra0 + ba * pa0;
+  pnb = rb0 + bb * pb0;
+  za = sa * pna - acca;
+  zb = sb * pnb - accb;
 }
 
 template <class M>
@@ -1285,130 +1324,201 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sh1(Sell<M> A, Sell<M> AH, int 
                                                      const cd *__restrict__ P,
                                                      const cd *__restrict__ Pt, cd *__restrict__ Pn,
                                                      cd *__restrict__ Ptn, cd *__restrict__ Z,
-                                                     cd *__restrict__ Zt, const double *P3,
-                                                     int nb3, ShScalars *Sh, double *rec, int it,
-                                                     int first) {
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double red[4 * SHMAX];
-  __shared__ cd betas[SHMAX];
-  __shared__ int act[SHMAX];
+                                                     cd *__restrict__ Zt, const ShScalars *Sh,
+                                                     int nrb) {
+  __shared__ cd bet[SHMAX], sgs[SHMAX];
+  __shared__ int acts[SHMAX];
   if (Sh->all_done) return;
-  sh_prologue(P3, nb3, Sh, rec, it, first, tmp, red, betas, act);
   const int S = Sh->S;
-  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
-  if (row >= A.n) return;
-  for (int s = 0; s < S; ++s) {
-    if (!act[s]) continue;
-    const size_t o = (size_t)s * ld;
-    const cd sig = {Sh->sig[2 * s], Sh->sig[2 * s + 1]};
-    const cd beta = betas[s], betac = cj(beta);
-    {
-      const cd prow = R[o + row] + beta * P[o + row];
-      Pn[o + row] = prow;
-      const int slice = row >> 6, lane = row & 63;
-      const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
-      cd acc = {0.0, 0.0};
-      for (int e = beg + lane; e < end; e += RBICG_WAVE) {
-        const int c = A.col[e];
-        acc += up(A.val[e]) * (R[o + c] + beta * P[o + c]);
-      }
-      Z[o + row] = sig * prow - acc;
+  int rb, side;
+  sh1_block(blockIdx.x, nrb, rb, side);
+  const bool primal = side == 0;
+  if (threadIdx.x < S) {
+    const int s = threadIdx.x;
+    acts[s] = Sh->act1[s];
+    const cd b = {Sh->beta[2 * s], Sh->beta[2 * s + 1]};
+    bet[s] = primal ? b : cj(b);
+    sgs[s] = cd{Sh->sig[2 * s], primal ? Sh->sig[2 * s + 1] : -Sh->sig[2 * s + 1]};
+  }
+  __syncthreads();
+  const Sell<M> &Am = primal ? A : AH;
+  const int row = rb * RBICG_BLOCK + threadIdx.x;
+  if (row >= Am.n) return;
+  const char *rbase = (const char *)(primal ? R : Rt), *pbase = (const char *)(primal ? P : Pt);
+  char *pnbase = (char *)(primal ? Pn : Ptn), *zbase = (char *)(primal ? Z : Zt);
+  const size_t colb = (size_t)ld * sizeof(cd);
+  // byte offsets of the row and of its columns (ld * 9 * 16 < 2^32)
+  const unsigned roff = (unsigned)row * (unsigned)sizeof(cd);
+  const int slice = row >> 6, lane = row & 63;
+  const int b0 = Am.sliceptr[slice];
+  const int w = (Am.sliceptr[slice + 1] - b0) >> 6;
+  unsigned co[8];
+  M v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    co[j] = 0;
+    v[j] = M{};
+    if (j < w) {
+      co[j] = (unsigned)Am.col[b0 + lane + RBICG_WAVE * j] * (unsigned)sizeof(cd);
+      v[j] = Am.val[b0 + lane + RBICG_WAVE * j];
     }
-    {
-      const cd prow = Rt[o + row] + betac * Pt[o + row];
-      Ptn[o + row] = prow;
-      const int slice = row >> 6, lane = row & 63;
-      const int beg = AH.sliceptr[slice], end = AH.sliceptr[slice + 1];
-      cd acc = {0.0, 0.0};
-      for (int e = beg + lane; e < end; e += RBICG_WAVE) {
-        const int c = AH.col[e];
-        acc += up(AH.val[e]) * (Rt[o + c] + betac * Pt[o + c]);
-      }
-      Zt[o + row] = cj(sig) * prow - acc;
+  }
+  for (int s0 = 0; s0 < S; s0 += 2) {
+    const int sb = min(s0 + 1, S - 1);
+    const int aa = __builtin_amdgcn_readfirstlane(acts[s0]);
+    const int ab = s0 + 1 < S ? __builtin_amdgcn_readfirstlane(acts[sb]) : 0;
+    if (!aa && !ab) continue;
+    // an inactive shift of the pair reads the other one's columns (cache
+    // hits) and stores nothing
+    const int ca = aa ? s0 : sb, cb = ab ? sb : s0;
+    const size_t oa = ca * colb, ob = cb * colb;
+    cd pna, za, pnb, zb;
+    if (w <= 8) {
+      sh1_pair<M>(w, co, v, rbase + oa, pbase + oa, rbase + ob, pbase + ob, roff, bet[ca],
+                  bet[cb], sgs[ca], sgs[cb], pna, za, pnb, zb);
+    } else {
+      const cd *ra = (const cd *)(rbase + oa), *pa = (const cd *)(pbase + oa);
+      const cd *rbv = (const cd *)(rbase + ob), *pbv = (const cd *)(pbase + ob);
+      pna = ra[row] + bet[ca] * pa[row];
+      pnb = rbv[row] + bet[cb] * pbv[row];
+      za = sgs[ca] * pna - spmv_dir<cd, M, cd>(Am, row, ra, pa, bet[ca]);
+      zb = sgs[cb] * pnb - spmv_dir<cd, M, cd>(Am, row, rbv, pbv, bet[cb]);
+    }
+    if (aa) {
+      *(cd *)(pnbase + oa + roff) = pna;
+      *(cd *)(zbase + oa + roff) = za;
+    }
+    if (ab) {
+      *(cd *)(pnbase + ob + roff) = pnb;
+      *(cd *)(zbase + ob + roff) = zb;
     }
   }
 }
 
-// Per-shift coefficients (one block).  G: Gram of [U~, A^H U~, U, A U]
-// (rows, 2 k2 of them) against [v_1..v_S, v~_1..v~_S] (my = 2S columns),
-// complex row-major; w_s = G[0..k2)[s], w~_s = G[k2..2k2)[S + s].
-//   mode 0 (iteration): zeta_s = K_s w_s -> Sh->zeta, Y[:, s] = L_s zeta_s
-//                       (dual likewise); stopped shifts get Y = 0;
-//   mode 1 (start):     g_s = K_s w_s: Y[:, s] = L_s g_s (r -= [U, AU] Y) and
-//                       Yx[:, s] = -T_s g_s (x -= U Yx), dual likewise;
-//   mode 2 (finish):    Yx[:, s] = T_s zeta_c,s (x -= U Yx), dual likewise.
+// One block per shift s of the batch.
+//   mode 0 (iteration): zeta = K w, zeta~ = Kt w~ from the Gram
+//     G = [U~, A^H U~, U, A U, p~..]^H [z.., z~.., p~..] (row-major, my
+//     columns); y = L zeta, y~ = Lt zeta~; sigma = G[2 k2 + s, s]
+//     - sum_j conj(G[k2 + j, 2S + s]) y_j (= (p~, z) - (p~^H [U, A U]) y);
+//     alpha = rho_{it-1} / sigma;
+//     zeta_c += alpha zeta, zeta~_c += conj(alpha) zeta~; act/alpha for k_sh2.
+//   mode 1 (start): g = K w from G = [..]^H [r.., r~..]; Y = L g and
+//     Yx = -T g (x += U' g, r -= C' g).
+//   mode 2 (finish): Yx = T zeta_c (x -= U zeta_c).
 // Y, Yt: k2 x S column-major; Yx, Yxt: (k2/2) x S column-major.
-__global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, ShScalars *Sh,
-                                                 const ShCoef *__restrict__ Co, cd *Y, cd *Yt,
-                                                 cd *Yx, cd *Yxt, int mode) {
-  __shared__ cd zs[SHMAX][KSH], zst[SHMAX][KSH];
-  const int S = Sh->S, k2 = Sh->k2, k = k2 / 2, my = 2 * S;
-  if (mode == 0 && Sh->all_done) return;
-  // phase 1: zeta (or g) per shift
-  for (int t = threadIdx.x; t < 2 * S * KSH; t += blockDim.x) {
-    const int side = t / (S * KSH), s = (t / KSH) % S, l = t % KSH;
-    const int p = Sh->p[s];
+__global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, int my,
+                                                 ShScalars *Sh, const ShCoef *__restrict__ Co,
+                                                 cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode,
+                                                 double *rec, int it) {
+  __shared__ cd zs[2][KSH];
+  __shared__ cd ys[2 * KSH];
+  __shared__ cd alsh;
+  __shared__ int flag;
+  const int s = blockIdx.x, S = Sh->S, k2 = Sh->k2, k = k2 / 2;
+  if (mode == 0) {
+    if (threadIdx.x == 0) flag = Sh->done[s];
+    __syncthreads();
+    if (flag) {
+      if (threadIdx.x == 0) Sh->act[s] = 0;
+      return;
+    }
+  }
+  const int p = Sh->p[s];
+  // zeta (or g, or zeta_c) of both sides
+  for (int t = threadIdx.x; t < 2 * KSH; t += blockDim.x) {
+    const int side = t / KSH, l = t % KSH;
     cd v = {0.0, 0.0};
-    if (l < p && !(mode == 0 && Sh->done[s])) {
+    if (l < p) {
       if (mode == 2) {
-        v = side ? cd{Sh->zct[s][2 * l], Sh->zct[s][2 * l + 1]} : cd{Sh->zc[s][2 * l], Sh->zc[s][2 * l + 1]};
+        const double *zc = side ? Sh->zct[s] : Sh->zc[s];
+        v = cd{zc[2 * l], zc[2 * l + 1]};
       } else {
         const double *Km = side ? Co->Kt[s] : Co->K[s];
+        const int gj = side ? S + s : s;
         for (int j = 0; j < k2; ++j) {
-          const int gi = side ? k2 + j : j, gj = side ? S + s : s;
-          const cd w = {G[2 * ((size_t)gi * my + gj)], G[2 * ((size_t)gi * my + gj) + 1]};
-          v += cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]} * w;
-        }
-        if (mode == 0) {
-          double *zo = side ? Sh->zetat[s] : Sh->zeta[s];
-          zo[2 * l] = v.x;
-          zo[2 * l + 1] = v.y;
+          const size_t gi = (size_t)(side ? k2 + j : j) * my + gj;
+          v += cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]} * cd{G[2 * gi], G[2 * gi + 1]};
         }
       }
     }
-    if (side) zst[s][l] = v;
-    else zs[s][l] = v;
+    zs[side][l] = v;
   }
   __syncthreads();
-  // phase 2: basis coefficients
-  if (mode != 2) {
-    for (int t = threadIdx.x; t < 2 * S * k2; t += blockDim.x) {
-      const int side = t / (S * k2), s = (t / k2) % S, j = t % k2;
-      const int p = Sh->p[s];
+  if (mode != 2)
+    for (int t = threadIdx.x; t < 2 * k2; t += blockDim.x) {
+      const int side = t / k2, j = t % k2;
       const double *Lm = side ? Co->Lt[s] : Co->L[s];
       cd v = {0.0, 0.0};
       for (int l = 0; l < p; ++l)
-        v += cd{Lm[2 * (j * p + l)], Lm[2 * (j * p + l) + 1]} * (side ? zst[s][l] : zs[s][l]);
+        v += cd{Lm[2 * (j * p + l)], Lm[2 * (j * p + l) + 1]} * zs[side][l];
       (side ? Yt : Y)[(size_t)s * k2 + j] = v;
+      if (!side) ys[j] = v;
     }
-  }
   if (mode != 0) {
     const double sg = mode == 1 ? -1.0 : 1.0;
-    for (int t = threadIdx.x; t < 2 * S * k; t += blockDim.x) {
-      const int side = t / (S * k), s = (t / k) % S, i = t % k;
-      const int p = Sh->p[s];
+    for (int t = threadIdx.x; t < 2 * k; t += blockDim.x) {
+      const int side = t / k, i = t % k;
       const double *Tm = side ? Co->Tt[s] : Co->T[s];
       cd v = {0.0, 0.0};
       for (int l = 0; l < p; ++l)
-        v += cd{Tm[2 * (i * p + l)], Tm[2 * (i * p + l) + 1]} * (side ? zst[s][l] : zs[s][l]);
+        v += cd{Tm[2 * (i * p + l)], Tm[2 * (i * p + l) + 1]} * zs[side][l];
       (side ? Yxt : Yx)[(size_t)s * k + i] = sg * v;
     }
+    return;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    cd c = {0.0, 0.0};
+    for (int j = threadIdx.x; j < k2; j += 64) {
+      const size_t gi = (size_t)(k2 + j) * my + 2 * S + s;
+      c += cj(cd{G[2 * gi], G[2 * gi + 1]}) * ys[j];
+    }
+    c.x = wave_sum(c.x);
+    c.y = wave_sum(c.y);
+    if (threadIdx.x == 0) {
+      const size_t gd = (size_t)(2 * k2 + s) * my + s;
+      const cd sigma = {G[2 * gd] - c.x, G[2 * gd + 1] - c.y};
+      int a = 0;
+      cd al = {0.0, 0.0};
+      if (abs2(sigma) == 0.0 || !isfin(sigma)) {
+        Sh->status[s] = ST_BREAKDOWN;
+        Sh->iter[s] = it - 1;
+        Sh->done[s] = 1;
+      } else {
+        const double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
+        al = cdiv(cd{Rm1[4], Rm1[5]}, sigma);
+        a = 1;
+        double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
+        R0[0] = al.x;
+        R0[1] = al.y;
+      }
+      Sh->act[s] = a;
+      Sh->alpha[2 * s] = al.x;
+      Sh->alpha[2 * s + 1] = al.y;
+      flag = a;
+      alsh = al;
+    }
+  }
+  __syncthreads();
+  if (!flag) return;
+  for (int t = threadIdx.x; t < 2 * p; t += blockDim.x) {
+    const int side = t / p, l = t % p;
+    const cd a = side ? cj(alsh) : alsh;
+    double *zc = side ? Sh->zct[s] : Sh->zc[s];
+    const cd v = cd{zc[2 * l], zc[2 * l + 1]} + a * zs[side][l];
+    zc[2 * l] = v.x;
+    zc[2 * l + 1] = v.y;
   }
 }
 
 // Out[:, c] = Zin[:, c] - sum_l X_l W[l, c] for c < p <= 16 (W: m x p complex,
 // column-major), on FP64 MFMA (Y^T = W^T X^T, one wave per 16 rows, waves
-// stride over the row tiles).  With Ptn, also per-block partials of
-// (Ptn_c, Out_c) into P2[block * p + c] (complex).  Out may alias Zin.
+// stride over the row tiles).  Out may alias Zin.  Used at the start and the
+// end of a batched solve.
 __global__ __launch_bounds__(256) void k_sh_sub(int n, ColList X, int m, const cd *W, int p,
-                                                const cd *Zin, cd *Out, int ld, const cd *Ptn,
-                                                double *P2) {
-  __shared__ cd part[4][16];
+                                                const cd *Zin, cd *Out, int ld) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  cd sp[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) sp[v] = cd{0.0, 0.0};
   const int ntiles = (n + 15) / 16;
   for (int tile = blockIdx.x * 4 + w; tile < ntiles; tile += gridDim.x * 4) {
     const int row = tile * 16 + li;
@@ -1440,131 +1550,163 @@ __global__ __launch_bounds__(256) void k_sh_sub(int n, ColList X, int m, const c
         if (c < p) {
           const size_t o = (size_t)c * ld + row;
           const cd z = Zin[o];
-          const cd q = {z.x - ar[v], z.y - ai[v]};
-          Out[o] = q;
-          if (Ptn) sp[v] += cj(Ptn[o]) * q;
+          Out[o] = cd{z.x - ar[v], z.y - ai[v]};
         }
       }
     }
   }
-  if (!Ptn) return;
-  // sum over the 16 rows (li) of each lane group, then over the waves
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      sp[v].x += __shfl_xor(sp[v].x, off, 64);
-      sp[v].y += __shfl_xor(sp[v].y, off, 64);
-    }
-  if (li == 0)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) part[w][lk + 4 * v] = sp[v];
-  __syncthreads();
-  if (threadIdx.x < p) {
-    cd t = {0.0, 0.0};
-    for (int ww = 0; ww < 4; ++ww) t += part[ww][threadIdx.x];
-    P2[2 * ((size_t)blockIdx.x * p + threadIdx.x)] = t.x;
-    P2[2 * ((size_t)blockIdx.x * p + threadIdx.x) + 1] = t.y;
-  }
 }
 
-// upd = 1: alpha_s = rho_{it-1} / sigma_s (sigma from the P2 partials of
-// k_sh_sub), zeta_c updates, x, x~, r, r~ updates; then (also with upd = 0)
-// per-block partials of ||r_s||^2, ||r~_s||^2, (r~_s, r_s) into P3.
-__global__ __launch_bounds__(RBICG_BLOCK) void k_sh3(int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
-                                                     const cd *Pn, const cd *Ptn, const cd *Q,
-                                                     const cd *Qt, const double *P2, int nbe,
-                                                     double *P3, ShScalars *Sh, double *rec,
-                                                     int it, int upd) {
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double red[2 * SHMAX];
-  __shared__ cd alphas[SHMAX];
-  __shared__ int act[SHMAX];
-  __shared__ double lds[(RBICG_BLOCK / 64) * 4 * SHMAX];
-  if (upd && Sh->all_done) return;
-  const int S = Sh->S;
-  if (upd) {
-    breduce(P2, nbe, 2 * S, tmp, red);
-    if (threadIdx.x < S) {
-      const int s = threadIdx.x;
-      int a = 0;
-      cd al = {0.0, 0.0};
-      if (!Sh->done[s]) {
-        const cd sigma = {red[2 * s], red[2 * s + 1]};
-        if (abs2(sigma) == 0.0 || !isfin(sigma)) {
-          if (blockIdx.x == 0) {
-            Sh->status[s] = ST_BREAKDOWN;
-            Sh->iter[s] = it - 1;
-            Sh->done[s] = 1;
-          }
-        } else {
-          const double *Rm1 = rec + ((size_t)(it - 1) * SHMAX + s) * SH_LOG;
-          al = cdiv(cd{Rm1[4], Rm1[5]}, sigma);
-          a = 1;
-          if (blockIdx.x == 0) {
-            double *R0 = rec + ((size_t)it * SHMAX + s) * SH_LOG;
-            R0[0] = al.x;
-            R0[1] = al.y;
-            const cd alc = cj(al);
-            for (int l = 0; l < Sh->p[s]; ++l) {
-              const cd z = cd{Sh->zc[s][2 * l], Sh->zc[s][2 * l + 1]} +
-                           al * cd{Sh->zeta[s][2 * l], Sh->zeta[s][2 * l + 1]};
-              const cd zt = cd{Sh->zct[s][2 * l], Sh->zct[s][2 * l + 1]} +
-                            alc * cd{Sh->zetat[s][2 * l], Sh->zetat[s][2 * l + 1]};
-              Sh->zc[s][2 * l] = z.x;
-              Sh->zc[s][2 * l + 1] = z.y;
-              Sh->zct[s][2 * l] = zt.x;
-              Sh->zct[s][2 * l + 1] = zt.y;
-            }
-          }
+// k_sh2 for the NS shifts [s0, s0 + NS) of the batch.  With upd set, per row
+// and shift q = z - [U, A U] y and q~ = z~ - [U~, A^H U~] y~ (the bases are
+// n x k2 column-major with leading dimension ld at Bb, Btb; each basis row
+// is read once for all NS shifts; y, y~ are staged in LDS), then for the
+// shifts still active x += alpha p, x~ += conj(alpha) p~, r -= alpha q,
+// r~ -= conj(alpha) q~.  Then (also with upd = 0, the start of a solve)
+// partials of ||r||^2, ||r~||^2, (r~, r) into P3[(s * gridDim.x + block) * 4
+// + i].  Blocks stride over the row blocks of 256 rows, XCD-contiguous.
+// Every load is unconditional, so that the compiler keeps them all in flight:
+// an inactive shift reads the row of an active one (a cache hit) and its
+// results are dropped; basis columns past k2 read column k2 - 1 again and
+// meet zero coefficients.
+template <int NS>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sh2(
+    int n, int ld, int s0, cd *__restrict__ X, cd *__restrict__ Xt, cd *__restrict__ R,
+    cd *__restrict__ Rt, const cd *__restrict__ Pn, const cd *__restrict__ Ptn,
+    const cd *__restrict__ Z, const cd *__restrict__ Zt, const cd *__restrict__ Bb,
+    const cd *__restrict__ Btb, int k2, const cd *__restrict__ Y, const cd *__restrict__ Yt,
+    ShScalars *Sh, double *__restrict__ P3, int upd) {
+  constexpr int GB = 8;  // basis columns per load group
+  __shared__ double lds[(RBICG_BLOCK / 64) * 4 * NS];
+  __shared__ cd ysh[2][NS][2 * KSH];
+  __shared__ cd als[NS];
+  __shared__ int acts[NS];
+  const int kpad = (k2 + 2 * GB - 1) / (2 * GB) * (2 * GB);  // <= 2 KSH
+  if (threadIdx.x < NS) {
+    const int s = s0 + threadIdx.x;
+    const int on = upd ? Sh->act[s] : 0;
+    acts[threadIdx.x] = on;
+    als[threadIdx.x] = on ? cd{Sh->alpha[2 * s], Sh->alpha[2 * s + 1]} : cd{0.0, 0.0};
+  }
+  if (upd)
+    for (int i = threadIdx.x; i < 2 * NS * kpad; i += blockDim.x) {
+      const int side = i / (NS * kpad), t = (i / kpad) % NS, j = i % kpad;
+      ysh[side][t][j] = j < k2 ? (side ? Yt : Y)[(size_t)(s0 + t) * k2 + j] : cd{0.0, 0.0};
+    }
+  if (upd && s0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    // every shift's state of this iteration is final here
+    int all = 1;
+    for (int s = 0; s < Sh->S; ++s) all &= Sh->done[s];
+    if (all) Sh->all_done = 1;
+  }
+  __syncthreads();
+  // block-uniform flags and 32-bit byte offsets (the host checks
+  // (9 ld) * 16 < 2^32): shift t of an array at base + s0 ld + toff[t]
+  const unsigned ldb = (unsigned)ld * (unsigned)sizeof(cd);
+  int on[NS], tfirst = -1;
+  unsigned toff[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    on[t] = __builtin_amdgcn_readfirstlane(acts[t]);
+    if (on[t] && tfirst < 0) tfirst = t;
+  }
+#pragma unroll
+  for (int t = 0; t < NS; ++t) toff[t] = (unsigned)(on[t] ? t : (tfirst < 0 ? 0 : tfirst)) * ldb;
+  double a[NS][4];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) a[t][0] = a[t][1] = a[t][2] = a[t][3] = 0.0;
+  const int nrb = (n + RBICG_BLOCK - 1) / RBICG_BLOCK, nb = gridDim.x;
+  for (int rb = xcd_chunk(blockIdx.x, nb); rb < nrb; rb += nb) {
+    const int row = rb * RBICG_BLOCK + threadIdx.x;
+    if (row >= n) continue;
+    const unsigned boff = (unsigned)row * (unsigned)sizeof(cd);
+    cd rn[NS], rtn[NS];
+    auto side_pass = [&](const int side, cd(&out)[NS]) {
+      char *xb = (char *)((side ? Xt : X) + (size_t)s0 * ld);
+      char *rbs = (char *)((side ? Rt : R) + (size_t)s0 * ld);
+      if (!upd) {
+#pragma unroll
+        for (int t = 0; t < NS; ++t) out[t] = *(const cd *)(rbs + boff + (unsigned)t * ldb);
+        return;
+      }
+      if (tfirst < 0) {
+#pragma unroll
+        for (int t = 0; t < NS; ++t) out[t] = cd{0.0, 0.0};
+        return;
+      }
+      const char *pb = (const char *)((side ? Ptn : Pn) + (size_t)s0 * ld);
+      const char *zb = (const char *)((side ? Zt : Z) + (size_t)s0 * ld);
+      const cd *bb = side ? Btb : Bb;
+      cd q[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) q[t] = *(const cd *)(zb + boff + toff[t]);
+      cd b0[GB], b1[GB];
+      auto load_group = [&](cd(&g)[GB], int j0) {
+#pragma unroll
+        for (int u = 0; u < GB; ++u)
+          g[u] = *(const cd *)((const char *)(bb + (size_t)min(j0 + u, k2 - 1) * ld) + boff);
+      };
+      auto use_group = [&](const cd(&g)[GB], int j0) {
+#pragma unroll
+        for (int u = 0; u < GB; ++u)
+#pragma unroll
+          for (int t = 0; t < NS; ++t) q[t] -= g[u] * ysh[side][t][j0 + u];
+      };
+      if (k2 > 0) {
+        load_group(b0, 0);
+        for (int j0 = 0; j0 < kpad; j0 += 2 * GB) {
+          load_group(b1, j0 + GB);
+          use_group(b0, j0);
+          load_group(b0, j0 + 2 * GB);
+          use_group(b1, j0 + GB);
         }
       }
-      act[s] = a;
-      alphas[s] = al;
-    }
-    __syncthreads();
-  }
-  // shifts outer, rows inner: four accumulators per thread at a time
-  const int stride = gridDim.x * RBICG_BLOCK;
-  for (int s = 0; s < S; ++s) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const bool on = upd && act[s];
-    const cd al = on ? alphas[s] : cd{0.0, 0.0}, alc = cj(al);
-    for (int row = blockIdx.x * RBICG_BLOCK + threadIdx.x; row < n; row += stride) {
-      const size_t o = (size_t)s * ld + row;
-      cd rv = R[o], rtv = Rt[o];
-      if (on) {
-        X[o] = X[o] + al * Pn[o];
-        Xt[o] = Xt[o] + alc * Ptn[o];
-        rv = rv - al * Q[o];
-        rtv = rtv - alc * Qt[o];
-        R[o] = rv;
-        Rt[o] = rtv;
+      cd ro[NS], xo[NS], po[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        ro[t] = *(const cd *)(rbs + boff + toff[t]);
+        xo[t] = *(const cd *)(xb + boff + toff[t]);
+        po[t] = *(const cd *)(pb + boff + toff[t]);
       }
-      a0 += abs2(rv);
-      a1 += abs2(rtv);
-      const cd rho = cj(rtv) * rv;
-      a2 += rho.x;
-      a3 += rho.y;
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const cd al = side ? cj(als[t]) : als[t];
+        const cd xn = xo[t] + al * po[t], rn_ = ro[t] - al * q[t];
+        out[t] = on[t] ? rn_ : cd{0.0, 0.0};
+        if (on[t]) {
+          *(cd *)(xb + boff + toff[t]) = xn;
+          *(cd *)(rbs + boff + toff[t]) = rn_;
+        }
+      }
+    };
+    side_pass(0, rn);
+    side_pass(1, rtn);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      a[t][0] += abs2(rn[t]);
+      a[t][1] += abs2(rtn[t]);
+      const cd rho = cj(rtn[t]) * rn[t];
+      a[t][2] += rho.x;
+      a[t][3] += rho.y;
     }
-    wput(lds, 4 * SHMAX, 4 * s, a0);
-    wput(lds, 4 * SHMAX, 4 * s + 1, a1);
-    wput(lds, 4 * SHMAX, 4 * s + 2, a2);
-    wput(lds, 4 * SHMAX, 4 * s + 3, a3);
+  }
+  // wave sums, 16 values at a time (lane 4i holds value i of its group)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c0 = 0; c0 < 4 * NS; c0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = c0 + i < 4 * NS ? a[(c0 + i) / 4][(c0 + i) % 4] : 0.0;
+    const double sum = wave_sum16(v);
+    const int id = c0 + (lane >> 2);
+    if ((lane & 3) == 0 && id < 4 * NS) lds[wv * 4 * NS + id] = sum;
   }
   __syncthreads();
-  bstore(lds, 4 * SHMAX, RBICG_BLOCK / 64, 4 * S, P3);
-}
-
-// Stopping test after the last launched iteration (one block).
-__global__ __launch_bounds__(RBICG_BLOCK) void k_sh_fin(const double *P3, int nb3, ShScalars *Sh,
-                                                        double *rec, int it, int first) {
-  __shared__ double tmp[RBICG_BLOCK];
-  __shared__ double red[4 * SHMAX];
-  __shared__ cd betas[SHMAX];
-  __shared__ int act[SHMAX];
-  if (Sh->all_done) return;
-  sh_prologue(P3, nb3, Sh, rec, it, first, tmp, red, betas, act);
+  if (threadIdx.x < 4 * NS) {
+    double t = 0.0;
+    for (int w = 0; w < RBICG_BLOCK / 64; ++w) t += lds[w * 4 * NS + threadIdx.x];
+    P3[((size_t)(s0 + threadIdx.x / 4) * nb + blockIdx.x) * 4 + threadIdx.x % 4] = t;
+  }
 }
 
 // =============================================================== launchers
@@ -1667,7 +1809,9 @@ void launch_add_d2d(hipStream_t st, double *x, const double *d, double sgn, size
   hipLaunchKernelGGL(k_add_to_d<double>, dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, x, d, sgn, n);
 }
 // two chunks per CU at full size (the per-block slab loop is latency-bound)
-int gram_chunks(int n) { return std::max(1, std::min(512, (n + 511) / 512)); }
+// Row chunks of a Gram: at least 128 rows each, at most 512 chunks (two per
+// CU), so that a short basis still gives every CU a block.
+int gram_chunks(int n) { return std::max(1, std::min(512, (n + 127) / 128)); }
 
 int gram_group(int mx, int complex_vals) {
   const int TX = (mx + 15) / 16;
@@ -1731,40 +1875,51 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
 }
 
 // ------------------------------------------------------- shifted launchers
-int sh_blocks(int n) { return std::max(1, std::min(256, (int)nblk((size_t)n))); }
+int sh_blocks(int n) { return std::max(1, std::min(1024, (int)nblk((size_t)n))); }
 int sh_sub_blocks(int n) { return std::max(1, std::min(256, ((n + 15) / 16 + 3) / 4)); }
 
+void launch_sh_state(hipStream_t st, int S, const double *P3, int nb3, ShScalars *Sh, double *rec,
+                     int it, int first) {
+  hipLaunchKernelGGL(k_sh_state, dim3(S), dim3(RBICG_BLOCK), 0, st, P3, nb3, Sh, rec, it, first);
+}
 template <class M>
 void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
                 const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,
-                const double *P3, int nb3, ShScalars *Sh, double *rec, int it, int first) {
-  hipLaunchKernelGGL((k_sh1<M>), dim3(nblk(A.n)), dim3(RBICG_BLOCK), 0, st, A, AH, ld, R, Rt, P,
-                     Pt, Pn, Ptn, Z, Zt, P3, nb3, Sh, rec, it, first);
+                const ShScalars *Sh) {
+  const int nrb = std::max(1, (int)nblk((size_t)A.n));
+  hipLaunchKernelGGL((k_sh1<M>), dim3((unsigned)nrb * 2), dim3(RBICG_BLOCK), 0, st, A, AH, ld, R,
+                     Rt, P, Pt, Pn, Ptn, Z, Zt, Sh, nrb);
 }
-void launch_sh_coef(hipStream_t st, const double *G, ShScalars *Sh, const ShCoef *Co, cd *Y,
-                    cd *Yt, cd *Yx, cd *Yxt, int mode) {
-  hipLaunchKernelGGL(k_sh_coef, dim3(1), dim3(256), 0, st, G, Sh, Co, Y, Yt, Yx, Yxt, mode);
+void launch_sh_coef(hipStream_t st, int S, const double *G, int my, ShScalars *Sh,
+                    const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode, double *rec, int it) {
+  hipLaunchKernelGGL(k_sh_coef, dim3(S), dim3(256), 0, st, G, my, Sh, Co, Y, Yt, Yx, Yxt, mode, rec,
+                     it);
 }
 void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
-                   const cd *Zin, cd *Out, int ld, const cd *Ptn, double *P2, int nbe) {
-  hipLaunchKernelGGL(k_sh_sub, dim3(nbe), dim3(256), 0, st, n, X, m, W, p, Zin, Out, ld, Ptn, P2);
+                   const cd *Zin, cd *Out, int ld, int nbe) {
+  hipLaunchKernelGGL(k_sh_sub, dim3(nbe), dim3(256), 0, st, n, X, m, W, p, Zin, Out, ld);
 }
-void launch_sh3(hipStream_t st, int nb3, int n, int ld, cd *X, cd *Xt, cd *R, cd *Rt,
-                const cd *Pn, const cd *Ptn, const cd *Q, const cd *Qt, const double *P2,
-                int nbe, double *P3, ShScalars *Sh, double *rec, int it, int upd) {
-  hipLaunchKernelGGL(k_sh3, dim3(nb3), dim3(RBICG_BLOCK), 0, st, n, ld, X, Xt, R, Rt, Pn, Ptn, Q,
-                     Qt, P2, nbe, P3, Sh, rec, it, upd);
-}
-void launch_sh_fin(hipStream_t st, const double *P3, int nb3, ShScalars *Sh, double *rec, int it,
-                   int first) {
-  hipLaunchKernelGGL(k_sh_fin, dim3(1), dim3(RBICG_BLOCK), 0, st, P3, nb3, Sh, rec, it, first);
+void launch_sh2(hipStream_t st, int n, int ld, int S, cd *X, cd *Xt, cd *R, cd *Rt, const cd *Pn,
+                const cd *Ptn, const cd *Z, const cd *Zt, const cd *B, const cd *Bt, int k2,
+                const cd *Y, const cd *Yt, ShScalars *Sh, double *P3, int nb, int upd) {
+  for (int s0 = 0; s0 < S; s0 += 8) {
+#define SH2(NS)                                                                               \
+  case NS:                                                                                    \
+    hipLaunchKernelGGL((k_sh2<NS>), dim3(nb), dim3(RBICG_BLOCK), 0, st, n, ld, s0, X, Xt, R, Rt, \
+                       Pn, Ptn, Z, Zt, B, Bt, k2, Y, Yt, Sh, P3, upd);                         \
+    break;
+    switch (std::min(8, S - s0)) {
+      SH2(1) SH2(2) SH2(3) SH2(4) SH2(5) SH2(6) SH2(7) SH2(8)
+    }
+#undef SH2
+  }
 }
 template void launch_sh1<double>(hipStream_t, const Sell<double> &, const Sell<double> &, int,
                                  const cd *, const cd *, const cd *, const cd *, cd *, cd *,
-                                 cd *, cd *, const double *, int, ShScalars *, double *, int, int);
+                                 cd *, cd *, const ShScalars *);
 template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, int, const cd *,
                              const cd *, const cd *, const cd *, cd *, cd *, cd *, cd *,
-                             const double *, int, ShScalars *, double *, int, int);
+                             const ShScalars *);
 
 #define INST_VM(V, M)                                                                        \
   template void launch_it1<V, M>(hipStream_t, int, const Sell<M> &, const Sell<M> &,         \

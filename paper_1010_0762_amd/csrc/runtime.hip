@@ -244,10 +244,10 @@ struct ShiftWs {
   int Scap = 0, kcap = 0;
   std::vector<void *> allocs;
   cd *R = nullptr, *Rt = nullptr, *P[2] = {}, *Pt[2] = {}, *Z = nullptr, *Zt = nullptr;
-  cd *Q = nullptr, *Qt = nullptr, *X = nullptr, *Xt = nullptr;
+  cd *X = nullptr, *Xt = nullptr;
   cd *BU = nullptr, *BUt = nullptr;
   cd *Y = nullptr, *Yt = nullptr, *Yx = nullptr, *Yxt = nullptr;
-  double *gpart = nullptr, *G = nullptr, *P2 = nullptr, *P3 = nullptr, *rec = nullptr;
+  double *gpart = nullptr, *G = nullptr, *P3 = nullptr, *rec = nullptr;
   size_t gpart_bytes = 0;
   int reccap = 0;
   ShScalars *Sh = nullptr, *hSh = nullptr;
@@ -1486,8 +1486,7 @@ int shift_ws(rbicg_s *h, int S) {
   };
   const size_t vb = (size_t)h->ld * sizeof(cd) * SHMAX;
   void **vecs[] = {(void **)&w.R, (void **)&w.Rt, (void **)&w.P[0], (void **)&w.P[1], (void **)&w.Pt[0],
-                   (void **)&w.Pt[1], (void **)&w.Z, (void **)&w.Zt, (void **)&w.Q, (void **)&w.Qt,
-                   (void **)&w.X, (void **)&w.Xt};
+                   (void **)&w.Pt[1], (void **)&w.Z, (void **)&w.Zt, (void **)&w.X, (void **)&w.Xt};
   for (void **v : vecs) TRY(al(v, vb));
   const size_t bb = (size_t)h->ld * sizeof(cd) * std::max(1, 2 * w.kcap);
   TRY(al((void **)&w.BU, bb));
@@ -1496,11 +1495,13 @@ int shift_ws(rbicg_s *h, int S) {
   TRY(al((void **)&w.Yt, sizeof(cd) * 2 * KSH * SHMAX));
   TRY(al((void **)&w.Yx, sizeof(cd) * KSH * SHMAX));
   TRY(al((void **)&w.Yxt, sizeof(cd) * KSH * SHMAX));
-  const int mx = std::max(1, 4 * w.kcap), my = std::max(mx, 2 * SHMAX);
-  w.gpart_bytes = (size_t)gram_chunks(h->n) * mx * my * 2 * sizeof(double);
+  // Gram shapes: the bases against themselves (4k x 4k at most) at the start
+  // of a sweep, [bases, p~..] (4k + S columns) against [z.., z~.., p~..] (3S)
+  // in every iteration
+  const size_t mx = (size_t)std::max(1, 4 * w.kcap), gmax = std::max(mx * mx, (mx + SHMAX) * 3 * SHMAX);
+  w.gpart_bytes = (size_t)gram_chunks(h->n) * gmax * 2 * sizeof(double);
   TRY(al((void **)&w.gpart, w.gpart_bytes));
-  TRY(al((void **)&w.G, (size_t)mx * my * 2 * sizeof(double)));
-  TRY(al((void **)&w.P2, (size_t)sh_sub_blocks(h->n) * SHMAX * 2 * sizeof(double)));
+  TRY(al((void **)&w.G, gmax * 2 * sizeof(double)));
   TRY(al((void **)&w.P3, (size_t)sh_blocks(h->n) * SHMAX * 4 * sizeof(double)));
   w.reccap = h->opt.maxit + 2;
   TRY(al((void **)&w.rec, (size_t)w.reccap * SHMAX * SH_LOG * sizeof(double)));
@@ -1508,7 +1509,7 @@ int shift_ws(rbicg_s *h, int S) {
   TRY(al((void **)&w.Co, sizeof(ShCoef)));
   HIPCHECK(hipHostMalloc((void **)&w.hSh, 2 * sizeof(ShScalars), hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&w.hCo, sizeof(ShCoef), hipHostMallocDefault));
-  HIPCHECK(hipHostMalloc((void **)&w.hG, (size_t)mx * my * 2 * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&w.hG, gmax * 2 * sizeof(double), hipHostMallocDefault));
   for (auto &e : w.ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return 0;
 }
@@ -1518,7 +1519,7 @@ int shift_ws(rbicg_s *h, int S) {
 int shift_gram(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y) {
   ShiftWs &w = *h->sw;
   const int mx = (int)X.size(), my = (int)Y.size();
-  if (mx < 1 || mx > 128 || my < 1 || my > gram_group(mx, 1))
+  if (mx < 1 || mx > RBICG_MAXCOLS || my < 1 || my > gram_group(mx, 1))
     return rbicg_fail(RBICG_EINVAL, "shifted Gram shape %d x %d unsupported", mx, my);
   const int nchunks = gram_chunks(h->n);
   if ((size_t)nchunks * mx * my * 2 * sizeof(double) > w.gpart_bytes)
@@ -1568,6 +1569,10 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
     }
     if (u0 >= S) return rbicg_fail(RBICG_EINVAL, "update_from %d out of range", u0);
   }
+  // the batch kernels address 9 columns of ld complex entries with 32-bit
+  // byte offsets
+  if ((size_t)ld * 9 * sizeof(cd) >= ((size_t)1 << 32))
+    return rbicg_fail(RBICG_EINVAL, "n = %d too large for batched shifted solves", n);
   TRY(shift_ws(h, S));
   ShiftWs &w = *h->sw;
   const cd *Usrc = (const cd *)(h->have_cyc ? h->Uc[h->cur] : h->U);
@@ -1690,24 +1695,32 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       BUl.p[j] = bcol(w.BU, j, h);
       BUtl.p[j] = bcol(w.BUt, j, h);
     }
-    std::vector<const void *> Xg, Yr, Yz;
+    // Gram operands: the bases [U~, A^H U~, U, A U] against [r.., r~..] at
+    // the start; in every iteration [bases, p~..] against [z.., z~.., p~..]
+    // (p~ is the direction buffer the iteration writes, which alternates)
+    std::vector<const void *> Xg, Yr, Xz[2], Yz[2];
     for (int j = 0; j < k2; ++j) Xg.push_back(bcol(w.BUt, j, h));
     for (int j = 0; j < k2; ++j) Xg.push_back(bcol(w.BU, j, h));
     for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.R, j, h));
     for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.Rt, j, h));
-    for (int j = 0; j < Sb; ++j) Yz.push_back(bcol(w.Z, j, h));
-    for (int j = 0; j < Sb; ++j) Yz.push_back(bcol(w.Zt, j, h));
+    for (int c = 0; c < 2; ++c) {
+      Xz[c] = Xg;
+      for (int j = 0; j < Sb; ++j) Xz[c].push_back(bcol(w.Pt[1 - c], j, h));
+      for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Z, j, h));
+      for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Zt, j, h));
+      for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Pt[1 - c], j, h));
+    }
     if (k > 0) {
       // eq. minusXR: g = C~'^H r_{-1}; x += U' g, r -= C' g (dual likewise)
       TRY(shift_gram(h, Xg, Yr));
-      launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 1);
-      launch_sh_sub(h->st, n, BUl, k2, w.Y, Sb, w.R, w.R, ld, nullptr, nullptr, nbe);
-      launch_sh_sub(h->st, n, BUtl, k2, w.Yt, Sb, w.Rt, w.Rt, ld, nullptr, nullptr, nbe);
-      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nullptr, nullptr, nbe);
-      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nullptr, nullptr, nbe);
+      launch_sh_coef(h->st, Sb, w.G, 2 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 1, w.rec, 0);
+      launch_sh_sub(h->st, n, BUl, k2, w.Y, Sb, w.R, w.R, ld, nbe);
+      launch_sh_sub(h->st, n, BUtl, k2, w.Yt, Sb, w.Rt, w.Rt, ld, nbe);
+      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nbe);
+      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nbe);
     }
-    launch_sh3(h->st, nb3, n, ld, w.X, w.Xt, w.R, w.Rt, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
-               w.P3, w.Sh, w.rec, 0, 0);
+    launch_sh2(h->st, n, ld, Sb, w.X, w.Xt, w.R, w.Rt, nullptr, nullptr, nullptr, nullptr, w.BU, w.BUt, 0,
+               w.Y, w.Yt, w.Sh, w.P3, nb3, 0);
     HIPCHECK(hipGetLastError());
     // iterations: chunks of 8, two in flight, one scalar download per chunk
     int launched = 0, pc = 0, slot = 0;
@@ -1719,20 +1732,17 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
         const int cnt = std::min(chunk, h->opt.maxit - launched);
         for (int t = 0; t < cnt; ++t) {
           const int it = launched + 1;
-          launch_sh1<M>(h->st, view_A<M>(h), view_AH<M>(h), ld, w.R, w.Rt, w.P[pc], w.Pt[pc], w.P[1 - pc],
-                        w.Pt[1 - pc], w.Z, w.Zt, w.P3, nb3, w.Sh, w.rec, it, it == 1 ? 1 : 0);
-          if (k > 0) {
-            TRY(shift_gram(h, Xg, Yz));
-            launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 0);
-          }
-          launch_sh_sub(h->st, n, BUl, k > 0 ? k2 : 0, w.Y, Sb, w.Z, w.Q, ld, w.Pt[1 - pc], w.P2, nbe);
-          launch_sh_sub(h->st, n, BUtl, k > 0 ? k2 : 0, w.Yt, Sb, w.Zt, w.Qt, ld, nullptr, nullptr, nbe);
-          launch_sh3(h->st, nb3, n, ld, w.X, w.Xt, w.R, w.Rt, w.P[1 - pc], w.Pt[1 - pc], w.Q, w.Qt, w.P2, nbe,
-                     w.P3, w.Sh, w.rec, it, 1);
+          launch_sh_state(h->st, Sb, w.P3, nb3, w.Sh, w.rec, it, it == 1 ? 1 : 0);
+          launch_sh1<M>(h->st, view_A<M>(h), view_AH<M>(h), ld, w.R, w.Rt, w.P[pc], w.Pt[pc],
+                        w.P[1 - pc], w.Pt[1 - pc], w.Z, w.Zt, w.Sh);
+          TRY(shift_gram(h, Xz[pc], Yz[pc]));
+          launch_sh_coef(h->st, Sb, w.G, 3 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 0, w.rec, it);
+          launch_sh2(h->st, n, ld, Sb, w.X, w.Xt, w.R, w.Rt, w.P[1 - pc], w.Pt[1 - pc], w.Z, w.Zt, w.BU, w.BUt,
+                     k2, w.Y, w.Yt, w.Sh, w.P3, nb3, 1);
           pc = 1 - pc;
           ++launched;
         }
-        launch_sh_fin(h->st, w.P3, nb3, w.Sh, w.rec, launched + 1, 0);
+        launch_sh_state(h->st, Sb, w.P3, nb3, w.Sh, w.rec, launched + 1, 0);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(&w.hSh[1 + 0 * slot], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost, h->st));
         HIPCHECK(hipEventRecord(w.ev[slot], h->st));
@@ -1743,7 +1753,10 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       const int sl = flight.front();
       flight.pop_front();
       HIPCHECK(hipEventSynchronize(w.ev[sl]));
-      if (w.hSh[1].all_done) all_done = true;
+      // every shift stopped (the device flag lags the last stopping test)
+      bool every = true;
+      for (int j = 0; j < Sb; ++j) every = every && w.hSh[1].done[j];
+      if (every || w.hSh[1].all_done) all_done = true;
       if (all_done) {
         while (!flight.empty()) {
           HIPCHECK(hipEventSynchronize(w.ev[flight.front()]));
@@ -1756,9 +1769,9 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
     HIPCHECK(hipMemcpy(&w.hSh[1], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost));
     // Algorithm 2 step 7: x -= U' zeta_c, x~ -= U~' zeta~_c
     if (k > 0) {
-      launch_sh_coef(h->st, w.G, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 2);
-      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nullptr, nullptr, nbe);
-      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nullptr, nullptr, nbe);
+      launch_sh_coef(h->st, Sb, w.G, 3 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 2, w.rec, 0);
+      launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nbe);
+      launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nbe);
     }
     HIPCHECK(hipEventRecord(ev1, h->st));
     HIPCHECK(hipEventSynchronize(ev1));
