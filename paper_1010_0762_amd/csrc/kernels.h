@@ -64,6 +64,12 @@ int gram_group(int mx, int complex_vals);
 template <class V>
 void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
                  double *partial, double *G, int nchunks);
+// Two Grams in one launch: G = [X[0, mx)^H Y[0, my), X[x1, x1 + mx1)^H
+// Y[y1, y1 + my1)], each row-major, the second after the first (mx1 = 0:
+// launch_gram).  partial holds nchunks (mx my + mx1 my1) entries.
+template <class V>
+void launch_gram2(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my, int x1,
+                  int mx1, int y1, int my1, double *partial, double *G, int nchunks);
 template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
                    int ld);
@@ -77,8 +83,9 @@ template <class M>
 void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
                 const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,
                 const ShScalars *Sh);
-void launch_sh_coef(hipStream_t st, int S, const double *G, int my, ShScalars *Sh,
-                    const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode, double *rec, int it);
+void launch_sh_coef(hipStream_t st, int S, const double *G, int ld0, int g1, int ld1,
+                    ShScalars *Sh, const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode,
+                    double *rec, int it);
 void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
                    const cd *Zin, cd *Out, int ld, int nbe);
 // B, Bt: n x k2 column-major bases (leading dimension ld); ld * 9 * 16 < 2^32

@@ -928,13 +928,29 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // SR + 2 doubles keeps the MFMA operand reads free of bank conflicts), double
 // buffered: the next slab's loads are in flight while the MFMAs consume the
 // current one.  All 16 x 16 output tiles of the block accumulate on MFMA.
-template <class V, int SR, int GRAM_NLD>
+// With gridDim.y = 2 the launch holds two independent Grams: blocks with
+// blockIdx.y = 1 contract X[x1, x1 + mx1) against Y[y1, y1 + my1) and write
+// their entries after the mx x my entries of the first in each chunk's
+// partial row.
+template <class V, int SR, int GRAM_NLD, int MAXT>
 __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int mx, ColList Y,
                                                           int my, int rows_per_chunk,
-                                                          double *partial, int same) {
+                                                          double *partial, int same, int x1,
+                                                          int mx1, int y1, int my1) {
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
   constexpr int PC = SR + 2;
   extern __shared__ double sm[];
+  const size_t tot = (size_t)mx * my + (gridDim.y > 1 ? (size_t)mx1 * my1 : 0);
+  size_t base = 0;
+  int xo = 0, yo = 0;
+  if (blockIdx.y == 1) {
+    base = (size_t)mx * my;
+    xo = x1;
+    yo = y1;
+    mx = mx1;
+    my = my1;
+    same = 0;
+  }
   const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
   // same: Y is X (a Hermitian Gram); its columns are staged once
   const int ncol = same ? mxp : mxp + myp;
@@ -943,9 +959,9 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nval = ncol * SR;
-  d4 acc[GRAM_MAXT][ndv];
+  d4 acc[MAXT][ndv];
 #pragma unroll
-  for (int t = 0; t < GRAM_MAXT; ++t)
+  for (int t = 0; t < MAXT; ++t)
 #pragma unroll
     for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
   const int r0 = blockIdx.x * rows_per_chunk;
@@ -964,7 +980,8 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
     rrs[t] = idx % SR;
     const bool isx = c < mxp;
     const int cc = isx ? c : c - mxp;
-    colp[t] = (idx < nval && cc < (isx ? mx : my)) ? (const V *)(isx ? X.p[cc] : Y.p[cc]) : nullptr;
+    colp[t] = (idx < nval && cc < (isx ? mx : my)) ? (const V *)(isx ? X.p[xo + cc] : Y.p[yo + cc])
+                                                   : nullptr;
   }
   // global -> registers for slab `sl`
   auto load = [&](int sl) {
@@ -1013,7 +1030,7 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
 #pragma unroll
     for (int kk = 0; kk < SR; kk += 4) {
 #pragma unroll
-      for (int t = 0; t < GRAM_MAXT; ++t) {
+      for (int t = 0; t < MAXT; ++t) {
         const int tile = w + 4 * t;
         if (tile < T) {
           const int ti = tile / TY, tj = tile % TY;
@@ -1037,7 +1054,7 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < GRAM_MAXT; ++t) {
+  for (int t = 0; t < MAXT; ++t) {
     const int tile = w + 4 * t;
     if (tile < T) {
       const int ti = tile / TY, tj = tile % TY;
@@ -1047,7 +1064,7 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
         const int gi = ti * 16 + lk + 4 * v;
         if (gi < mx && gj < my) {
           // real data: one double per entry (the reduction fills in Im = 0)
-          double *o = partial + ((size_t)blockIdx.x * mx * my + (size_t)gi * my + gj) * ndv;
+          double *o = partial + ((size_t)blockIdx.x * tot + base + (size_t)gi * my + gj) * ndv;
           o[0] = acc[t][0][v];
           if constexpr (ndv == 2) o[1] = acc[t][ndv - 1][v];
         }
@@ -1059,26 +1076,32 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram_mfma(int n, ColList X, int 
 // G = sum over chunks of the partials (fixed order); G is mx x my complex,
 // stored row-major by (i, j) as in the partials.  real: the partials hold
 // count real values and G[2t], G[2t + 1] = (sum, 0).
+template <int L>
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *partial, int nchunks, int count,
                                                      double *G, int real) {
-  // 8 lanes per entry, each summing every 8th chunk in two chains; the 8
-  // sums are then added in a fixed order, so the bits do not depend on timing
+  // L lanes per entry, each summing every L-th chunk in two chains; the L
+  // sums are then added pairwise in a fixed order, so the bits do not depend
+  // on timing
   __shared__ double sub[256];
-  const int e = blockIdx.x * 32 + (threadIdx.x >> 3), sl = threadIdx.x & 7;
+  const int e = blockIdx.x * (256 / L) + threadIdx.x / L, sl = threadIdx.x % L;
   double s0 = 0.0, s1 = 0.0;
   if (e < count) {
     int c = sl;
-    for (; c + 8 < nchunks; c += 16) {
+    for (; c + L < nchunks; c += 2 * L) {
       s0 += partial[(size_t)c * count + e];
-      s1 += partial[(size_t)(c + 8) * count + e];
+      s1 += partial[(size_t)(c + L) * count + e];
     }
     if (c < nchunks) s0 += partial[(size_t)c * count + e];
   }
   sub[threadIdx.x] = s0 + s1;
   __syncthreads();
+#pragma unroll
+  for (int h = L / 2; h >= 1; h /= 2) {
+    if (sl < h) sub[threadIdx.x] += sub[threadIdx.x + h];
+    __syncthreads();
+  }
   if (sl == 0 && e < count) {
-    const double *q = sub + threadIdx.x;
-    const double sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    const double sum = sub[threadIdx.x];
     if (real) {
       G[2 * (size_t)e] = sum;
       G[2 * (size_t)e + 1] = 0.0;
@@ -1213,9 +1236,9 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V 
 //   k_sh1      p_s = r_s + beta_s p_s and z_s = sigma_s p_s - A p_s (dual:
 //              conj(beta_s), conj(sigma_s), A^H); one block per (row block,
 //              side) for all shifts, the matrix row read once;
-//   Gram       [U~, A^H U~, U, A U, p~_1..p~_S]^H [z_1..z_S, z~_1..z~_S,
-//              p~_1..p~_S] (k_gram_mfma: one FP64-MFMA contraction of the
-//              shared bases against all shifts);
+//   Gram       [U~, A^H U~, p~_1..p~_S]^H [z_1..z_S] and [U, A U]^H
+//              [z~_1..z~_S, p~_1..p~_S] (k_gram_mfma, both in one launch: FP64
+//              MFMA contractions of the shared bases against all shifts);
 //   k_sh_coef  one block per shift: zeta_s = K_s w_s, y_s = L_s zeta_s (and
 //              the dual), sigma_s = (p~_s, q_s) = (p~_s, z_s) - (p~_s^H
 //              [U, A U]) y_s, alpha_s and the zeta_c updates;
@@ -1395,19 +1418,22 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sh1(Sell<M> A, Sell<M> AH, int 
   }
 }
 
-// One block per shift s of the batch.
-//   mode 0 (iteration): zeta = K w, zeta~ = Kt w~ from the Gram
-//     G = [U~, A^H U~, U, A U, p~..]^H [z.., z~.., p~..] (row-major, my
-//     columns); y = L zeta, y~ = Lt zeta~; sigma = G[2 k2 + s, s]
-//     - sum_j conj(G[k2 + j, 2S + s]) y_j (= (p~, z) - (p~^H [U, A U]) y);
+// One block per shift s of the batch.  G holds two Grams: G0 (rows of ld0
+// entries) = [U~, A^H U~, p~..]^H [z..] (iteration) or [U~, A^H U~]^H [r..]
+// (start), and from entry g1 on G1 (rows of ld1 entries) = [U, A U]^H
+// [z~.., p~..] or [U, A U]^H [r~..].
+//   mode 0 (iteration): zeta = K w, zeta~ = Kt w~ with w = G0[:k2, s],
+//     w~ = G1[:, s]; y = L zeta, y~ = Lt zeta~; sigma = G0[k2 + s, s]
+//     - sum_j conj(G1[j, S + s]) y_j (= (p~, z) - (p~^H [U, A U]) y);
 //     alpha = rho_{it-1} / sigma;
 //     zeta_c += alpha zeta, zeta~_c += conj(alpha) zeta~; act/alpha for k_sh2.
-//   mode 1 (start): g = K w from G = [..]^H [r.., r~..]; Y = L g and
+//   mode 1 (start): g = K w; Y = L g and
 //     Yx = -T g (x += U' g, r -= C' g).
 //   mode 2 (finish): Yx = T zeta_c (x -= U zeta_c).
 // Y, Yt: k2 x S column-major; Yx, Yxt: (k2/2) x S column-major.
-__global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, int my,
-                                                 ShScalars *Sh, const ShCoef *__restrict__ Co,
+__global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, int ld0, int g1,
+                                                 int ld1, ShScalars *Sh,
+                                                 const ShCoef *__restrict__ Co,
                                                  cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode,
                                                  double *rec, int it) {
   __shared__ cd zs[2][KSH];
@@ -1434,9 +1460,8 @@ __global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, i
         v = cd{zc[2 * l], zc[2 * l + 1]};
       } else {
         const double *Km = side ? Co->Kt[s] : Co->K[s];
-        const int gj = side ? S + s : s;
         for (int j = 0; j < k2; ++j) {
-          const size_t gi = (size_t)(side ? k2 + j : j) * my + gj;
+          const size_t gi = side ? (size_t)g1 + (size_t)j * ld1 + s : (size_t)j * ld0 + s;
           v += cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]} * cd{G[2 * gi], G[2 * gi + 1]};
         }
       }
@@ -1470,13 +1495,13 @@ __global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, i
   if (threadIdx.x < 64) {
     cd c = {0.0, 0.0};
     for (int j = threadIdx.x; j < k2; j += 64) {
-      const size_t gi = (size_t)(k2 + j) * my + 2 * S + s;
+      const size_t gi = (size_t)g1 + (size_t)j * ld1 + S + s;
       c += cj(cd{G[2 * gi], G[2 * gi + 1]}) * ys[j];
     }
     c.x = wave_sum(c.x);
     c.y = wave_sum(c.y);
     if (threadIdx.x == 0) {
-      const size_t gd = (size_t)(2 * k2 + s) * my + s;
+      const size_t gd = (size_t)(k2 + s) * ld0 + s;
       const cd sigma = {G[2 * gd] - c.x, G[2 * gd + 1] - c.y};
       int a = 0;
       cd al = {0.0, 0.0};
@@ -1824,12 +1849,14 @@ int gram_group(int mx, int complex_vals) {
 }
 
 template <class V>
-void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
-                 double *partial, double *G, int nchunks) {
+void launch_gram2(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my, int x1,
+                  int mx1, int y1, int my1, double *partial, double *G, int nchunks) {
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
+  const int two = mx1 > 0 && my1 > 0;
   const int rpc = (int)(((size_t)n + nchunks - 1) / nchunks);
-  const int mxp = (mx + 15) / 16 * 16, myp = (my + 15) / 16 * 16;
-  bool same = mx == my;
+  const int mxp = (std::max(mx, two ? mx1 : 0) + 15) / 16 * 16;
+  const int myp = (std::max(my, two ? my1 : 0) + 15) / 16 * 16;
+  bool same = !two && mx == my;
   for (int c = 0; same && c < mx; ++c) same = X.p[c] == Y.p[c];
   const int ncol = same ? mxp : mxp + myp;
   // Slabs of 32 rows while the columns fit 18 prefetch slots per thread and
@@ -1839,24 +1866,36 @@ void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList 
                    2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES / 2;
   const int sr = big ? sr_big : sr_big / 2;
   const size_t lds = 2 * (size_t)ncol * (sr + 2) * ndv * sizeof(double);
-  if (ndv == 1) {
-    if (big)
-      hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial, same ? 1 : 0);
-    else
-      hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial, same ? 1 : 0);
+  const dim3 grid(nchunks, two ? 2 : 1);
+  // at most one 16 x 16 output tile per wave (skinny products): a variant
+  // with one accumulator tile and 16-row slabs, small enough in registers
+  // and LDS for several blocks per CU
+  const int tiles = (mxp / 16) * (myp / 16);
+  if (tiles <= 4 && ncol * 16 <= 8 * GRAM_BLOCK) {
+    const size_t lds1 = 2 * (size_t)ncol * (16 + 2) * ndv * sizeof(double);
+    hipLaunchKernelGGL((k_gram_mfma<V, 16, 8, 1>), grid, dim3(GRAM_BLOCK), lds1, st, n, X, mx, Y,
+                       my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
+  } else if (big) {
+    hipLaunchKernelGGL((k_gram_mfma<V, 32, 18, GRAM_MAXT>), grid, dim3(GRAM_BLOCK), lds, st, n, X,
+                       mx, Y, my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
   } else {
-    if (big)
-      hipLaunchKernelGGL((k_gram_mfma<V, 32, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial, same ? 1 : 0);
-    else
-      hipLaunchKernelGGL((k_gram_mfma<V, 16, 18>), dim3(nchunks), dim3(GRAM_BLOCK), lds, st, n, X,
-                         mx, Y, my, rpc, partial, same ? 1 : 0);
+    hipLaunchKernelGGL((k_gram_mfma<V, 16, 18, GRAM_MAXT>), grid, dim3(GRAM_BLOCK), lds, st, n, X,
+                       mx, Y, my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
   }
-  const int count = ndv * mx * my;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((count + 31) / 32), dim3(256), 0, st, partial, nchunks,
-                     count, G, ndv == 1 ? 1 : 0);
+  const int count = ndv * (mx * my + (two ? mx1 * my1 : 0));
+  // few entries: 32 lanes per entry, so that the reduction still spreads
+  // over the chip
+  if (count < 8192)
+    hipLaunchKernelGGL(k_gram_reduce<32>, dim3((count + 7) / 8), dim3(256), 0, st, partial, nchunks,
+                       count, G, ndv == 1 ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_gram_reduce<8>, dim3((count + 31) / 32), dim3(256), 0, st, partial,
+                       nchunks, count, G, ndv == 1 ? 1 : 0);
+}
+template <class V>
+void launch_gram(hipStream_t st, int n, const ColList &X, int mx, const ColList &Y, int my,
+                 double *partial, double *G, int nchunks) {
+  launch_gram2<V>(st, n, X, mx, Y, my, 0, 0, 0, 0, partial, G, nchunks);
 }
 template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
@@ -1890,10 +1929,11 @@ void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, con
   hipLaunchKernelGGL((k_sh1<M>), dim3((unsigned)nrb * 2), dim3(RBICG_BLOCK), 0, st, A, AH, ld, R,
                      Rt, P, Pt, Pn, Ptn, Z, Zt, Sh, nrb);
 }
-void launch_sh_coef(hipStream_t st, int S, const double *G, int my, ShScalars *Sh,
-                    const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode, double *rec, int it) {
-  hipLaunchKernelGGL(k_sh_coef, dim3(S), dim3(256), 0, st, G, my, Sh, Co, Y, Yt, Yx, Yxt, mode, rec,
-                     it);
+void launch_sh_coef(hipStream_t st, int S, const double *G, int ld0, int g1, int ld1,
+                    ShScalars *Sh, const ShCoef *Co, cd *Y, cd *Yt, cd *Yx, cd *Yxt, int mode,
+                    double *rec, int it) {
+  hipLaunchKernelGGL(k_sh_coef, dim3(S), dim3(256), 0, st, G, ld0, g1, ld1, Sh, Co, Y, Yt, Yx, Yxt,
+                     mode, rec, it);
 }
 void launch_sh_sub(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p,
                    const cd *Zin, cd *Out, int ld, int nbe) {
@@ -1947,6 +1987,8 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
                                   int, int, const double *);                                 \
   template void launch_fill_zero<V>(hipStream_t, V *, size_t);                               \
   template void launch_reseed<V>(hipStream_t, V *, size_t, unsigned long long);              \
+  template void launch_gram2<V>(hipStream_t, int, const ColList &, int, const ColList &, int,  \
+                                int, int, int, int, double *, double *, int);                \
   template void launch_gram<V>(hipStream_t, int, const ColList &, int, const ColList &, int, \
                                double *, double *, int);                                     \
   template void launch_tsgemm<V>(hipStream_t, int, const ColList &, int, const cd *, int, V *, \

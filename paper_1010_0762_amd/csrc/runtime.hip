@@ -248,7 +248,7 @@ struct ShiftWs {
   cd *BU = nullptr, *BUt = nullptr;
   cd *Y = nullptr, *Yt = nullptr, *Yx = nullptr, *Yxt = nullptr;
   double *gpart = nullptr, *G = nullptr, *P3 = nullptr, *rec = nullptr;
-  size_t gpart_bytes = 0;
+  size_t gpart_bytes = 0, G_bytes = 0;
   int reccap = 0;
   ShScalars *Sh = nullptr, *hSh = nullptr;
   ShCoef *Co = nullptr, *hCo = nullptr;
@@ -1501,7 +1501,8 @@ int shift_ws(rbicg_s *h, int S) {
   const size_t mx = (size_t)std::max(1, 4 * w.kcap), gmax = std::max(mx * mx, (mx + SHMAX) * 3 * SHMAX);
   w.gpart_bytes = (size_t)gram_chunks(h->n) * gmax * 2 * sizeof(double);
   TRY(al((void **)&w.gpart, w.gpart_bytes));
-  TRY(al((void **)&w.G, gmax * 2 * sizeof(double)));
+  w.G_bytes = gmax * 2 * sizeof(double);
+  TRY(al((void **)&w.G, w.G_bytes));
   TRY(al((void **)&w.P3, (size_t)sh_blocks(h->n) * SHMAX * 4 * sizeof(double)));
   w.reccap = h->opt.maxit + 2;
   TRY(al((void **)&w.rec, (size_t)w.reccap * SHMAX * SH_LOG * sizeof(double)));
@@ -1528,6 +1529,29 @@ int shift_gram(rbicg_s *h, const std::vector<const void *> &X, const std::vector
   for (int i = 0; i < mx; ++i) xl.p[i] = X[i];
   for (int j = 0; j < my; ++j) yl.p[j] = Y[j];
   launch_gram<cd>(h->st, h->n, xl, mx, yl, my, w.gpart, w.G, nchunks);
+  HIPCHECK(hipGetLastError());
+  return 0;
+}
+
+// Two Grams in one launch into w.G: X[0, mx0)^H Y[0, my0), then (mx1 > 0)
+// X[x1, x1 + mx1)^H Y[y1, y1 + my1), each row-major.
+int shift_gram2(rbicg_s *h, const std::vector<const void *> &X, const std::vector<const void *> &Y,
+                int mx0, int my0, int x1, int mx1, int y1, int my1) {
+  ShiftWs &w = *h->sw;
+  const int nx = (int)X.size(), ny = (int)Y.size();
+  const int mxm = std::max(mx0, mx1), mym = std::max(my0, my1);
+  if (nx > RBICG_MAXCOLS || ny > RBICG_MAXCOLS || mx0 < 1 || my0 < 1 || mx0 > nx || my0 > ny ||
+      mx1 < 0 || (mx1 > 0 && (x1 < 0 || x1 + mx1 > nx || y1 < 0 || my1 < 1 || y1 + my1 > ny)) ||
+      mym > gram_group(mxm, 1))
+    return rbicg_fail(RBICG_EINVAL, "shifted Gram shapes %d x %d, %d x %d unsupported", mx0, my0, mx1, my1);
+  const int nchunks = gram_chunks(h->n);
+  const size_t ent = (size_t)mx0 * my0 + (mx1 > 0 ? (size_t)mx1 * my1 : 0);
+  if ((size_t)nchunks * ent * 2 * sizeof(double) > w.gpart_bytes || ent * 2 * sizeof(double) > w.G_bytes)
+    return rbicg_fail(RBICG_EINVAL, "shifted Gram workspace too small");
+  ColList xl{}, yl{};
+  for (int i = 0; i < nx; ++i) xl.p[i] = X[i];
+  for (int j = 0; j < ny; ++j) yl.p[j] = Y[j];
+  launch_gram2<cd>(h->st, h->n, xl, mx0, yl, my0, x1, mx1, y1, mx1 > 0 ? my1 : 0, w.gpart, w.G, nchunks);
   HIPCHECK(hipGetLastError());
   return 0;
 }
@@ -1695,8 +1719,8 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       BUl.p[j] = bcol(w.BU, j, h);
       BUtl.p[j] = bcol(w.BUt, j, h);
     }
-    // Gram operands: the bases [U~, A^H U~, U, A U] against [r.., r~..] at
-    // the start; in every iteration [bases, p~..] against [z.., z~.., p~..]
+    // Gram operands: [U~, A^H U~]^H [r..] and [U, A U]^H [r~..] at the start;
+    // in every iteration [U~, A^H U~, p~..]^H [z..] and [U, A U]^H [z~.., p~..]
     // (p~ is the direction buffer the iteration writes, which alternates)
     std::vector<const void *> Xg, Yr, Xz[2], Yz[2];
     for (int j = 0; j < k2; ++j) Xg.push_back(bcol(w.BUt, j, h));
@@ -1704,16 +1728,18 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
     for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.R, j, h));
     for (int j = 0; j < Sb; ++j) Yr.push_back(bcol(w.Rt, j, h));
     for (int c = 0; c < 2; ++c) {
-      Xz[c] = Xg;
+      for (int j = 0; j < k2; ++j) Xz[c].push_back(bcol(w.BUt, j, h));
       for (int j = 0; j < Sb; ++j) Xz[c].push_back(bcol(w.Pt[1 - c], j, h));
+      for (int j = 0; j < k2; ++j) Xz[c].push_back(bcol(w.BU, j, h));
       for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Z, j, h));
       for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Zt, j, h));
       for (int j = 0; j < Sb; ++j) Yz[c].push_back(bcol(w.Pt[1 - c], j, h));
     }
+    const int g1 = (k2 + Sb) * Sb;  // second Gram of an iteration
     if (k > 0) {
       // eq. minusXR: g = C~'^H r_{-1}; x += U' g, r -= C' g (dual likewise)
-      TRY(shift_gram(h, Xg, Yr));
-      launch_sh_coef(h->st, Sb, w.G, 2 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 1, w.rec, 0);
+      TRY(shift_gram2(h, Xg, Yr, k2, Sb, k2, k2, Sb, Sb));
+      launch_sh_coef(h->st, Sb, w.G, Sb, k2 * Sb, Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 1, w.rec, 0);
       launch_sh_sub(h->st, n, BUl, k2, w.Y, Sb, w.R, w.R, ld, nbe);
       launch_sh_sub(h->st, n, BUtl, k2, w.Yt, Sb, w.Rt, w.Rt, ld, nbe);
       launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nbe);
@@ -1735,8 +1761,8 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
           launch_sh_state(h->st, Sb, w.P3, nb3, w.Sh, w.rec, it, it == 1 ? 1 : 0);
           launch_sh1<M>(h->st, view_A<M>(h), view_AH<M>(h), ld, w.R, w.Rt, w.P[pc], w.Pt[pc],
                         w.P[1 - pc], w.Pt[1 - pc], w.Z, w.Zt, w.Sh);
-          TRY(shift_gram(h, Xz[pc], Yz[pc]));
-          launch_sh_coef(h->st, Sb, w.G, 3 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 0, w.rec, it);
+          TRY(shift_gram2(h, Xz[pc], Yz[pc], k2 + Sb, Sb, k2 + Sb, k2, Sb, 2 * Sb));
+          launch_sh_coef(h->st, Sb, w.G, Sb, g1, 2 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 0, w.rec, it);
           launch_sh2(h->st, n, ld, Sb, w.X, w.Xt, w.R, w.Rt, w.P[1 - pc], w.Pt[1 - pc], w.Z, w.Zt, w.BU, w.BUt,
                      k2, w.Y, w.Yt, w.Sh, w.P3, nb3, 1);
           pc = 1 - pc;
@@ -1769,7 +1795,7 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
     HIPCHECK(hipMemcpy(&w.hSh[1], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost));
     // Algorithm 2 step 7: x -= U' zeta_c, x~ -= U~' zeta~_c
     if (k > 0) {
-      launch_sh_coef(h->st, Sb, w.G, 3 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 2, w.rec, 0);
+      launch_sh_coef(h->st, Sb, w.G, Sb, g1, 2 * Sb, w.Sh, w.Co, w.Y, w.Yt, w.Yx, w.Yxt, 2, w.rec, 0);
       launch_sh_sub(h->st, n, BUl, k, w.Yx, Sb, w.X, w.X, ld, nbe);
       launch_sh_sub(h->st, n, BUtl, k, w.Yxt, Sb, w.Xt, w.Xt, ld, nbe);
     }

