@@ -1,17 +1,18 @@
-"""IRKA (Algorithm 3) for E = I with direct sparse solves -- TEST INFRASTRUCTURE.
+"""IRKA (Algorithm 3) with direct sparse solves -- TEST INFRASTRUCTURE.
 
 Only tests/, the package smoke check and the benchmark's CPU-baseline leg may
 import this module; the product path never does.
 
-Algorithm 3 (Sec. 5): starting from shifts sigma_1..sigma_r, repeat
-    V = [(sigma_i I - A)^{-1} b],  W = [(sigma_i I - A)^{-H} c],
-    A_r = W^H A V,  E_r = W^H V,
+The model is G(s) = c^H (s E - A)^{-1} b (eq. orginalModel, Sec. 5; E = I
+when not given).  Algorithm 3: starting from shifts sigma_1..sigma_r, repeat
+    V = [(sigma_i E - A)^{-1} b],  W = [(sigma_i E - A)^{-H} c],
+    A_r = W^H A V,  E_r = W^H E V,
     sigma_i <- -lambda_i(A_r, E_r)
 until the relative change of the shifts is below tol; the reduced model is
 (E_r, A_r, b_r = W^H b, c_r = V^H c) with transfer function
 G_r(s) = c_r^H (s E_r - A_r)^{-1} b_r.  Reading: step 4 of the printed
-algorithm writes E_r = W_r^* A V_r; for E = I the pencil's second matrix is
-W^H E V = W^H V (the Petrov-Galerkin projection of E), which is what is used.
+algorithm writes E_r = W_r^* A V_r; the pencil's second matrix is the
+Petrov-Galerkin projection of E, W^H E V, which is what is used.
 
 At a fixed point G_r Hermite-interpolates G at the shifts (the first-order
 H2-optimality conditions quoted in Sec. 5), which the pins check.
@@ -37,12 +38,17 @@ def order_shifts(sig: np.ndarray) -> np.ndarray:
     return sig[key]
 
 
-def transfer(A, b, c, s) -> complex:
-    """G(s) = c^H (s I - A)^{-1} b by a direct solve."""
+def _pencil(A, E, s):
+    """s E - A as a complex CSC matrix (E = I when None)."""
     A = as_csr(A)
     n = A.shape[0]
-    M = (s * sp.identity(n, dtype=np.complex128, format="csc") - A.astype(np.complex128)).tocsc()
-    return complex(np.vdot(c, spla.spsolve(M, b.astype(np.complex128))))
+    En = sp.identity(n, dtype=np.complex128, format="csr") if E is None else as_csr(E)
+    return (s * En.astype(np.complex128) - A.astype(np.complex128)).tocsc()
+
+
+def transfer(A, b, c, s, E=None) -> complex:
+    """G(s) = c^H (s E - A)^{-1} b by a direct solve."""
+    return complex(np.vdot(c, spla.spsolve(_pencil(A, E, s), b.astype(np.complex128))))
 
 
 def transfer_reduced(Ar, Er, br, cr, s) -> complex:
@@ -55,14 +61,13 @@ def transfer_reduced_deriv(Ar, Er, br, cr, s) -> complex:
     return complex(-np.vdot(cr, np.linalg.solve(M, Er @ np.linalg.solve(M, br))))
 
 
-def transfer_deriv(A, b, c, s) -> complex:
-    """G'(s) = -c^H (s I - A)^{-2} b."""
-    A = as_csr(A)
-    n = A.shape[0]
-    M = (s * sp.identity(n, dtype=np.complex128, format="csc") - A.astype(np.complex128)).tocsc()
-    lu = spla.splu(M)
-    y = lu.solve(lu.solve(b.astype(np.complex128)))
-    return complex(-np.vdot(c, y))
+def transfer_deriv(A, b, c, s, E=None) -> complex:
+    """G'(s) = -c^H (s E - A)^{-1} E (s E - A)^{-1} b."""
+    lu = spla.splu(_pencil(A, E, s))
+    y = lu.solve(b.astype(np.complex128))
+    if E is not None:
+        y = as_csr(E) @ y
+    return complex(-np.vdot(c, lu.solve(y)))
 
 
 @dataclass
@@ -77,11 +82,13 @@ class IrkaResult:
     cr: np.ndarray = None
 
 
-def irka(A, b, c, sigma0, tol=1e-6, maxit=50) -> IrkaResult:
-    """Algorithm 3 with E = I; every shifted pair by a direct sparse LU."""
+def irka(A, b, c, sigma0, tol=1e-6, maxit=50, E=None) -> IrkaResult:
+    """Algorithm 3 (E = I when not given); every shifted pair by a direct
+    sparse LU of sigma_i E - A."""
     A = as_csr(A).astype(np.complex128)
     n = A.shape[0]
-    I = sp.identity(n, dtype=np.complex128, format="csc")
+    En = sp.identity(n, dtype=np.complex128, format="csr") if E is None else \
+        as_csr(E).astype(np.complex128)
     b = np.asarray(b, dtype=np.complex128)
     c = np.asarray(c, dtype=np.complex128)
     sig = order_shifts(sigma0)
@@ -90,11 +97,11 @@ def irka(A, b, c, sigma0, tol=1e-6, maxit=50) -> IrkaResult:
         V = np.empty((n, len(sig)), np.complex128)
         W = np.empty((n, len(sig)), np.complex128)
         for i, s in enumerate(sig):
-            lu = spla.splu((s * I - A).tocsc())
+            lu = spla.splu((s * En - A).tocsc())
             V[:, i] = lu.solve(b)
             W[:, i] = lu.solve(c, trans="H")
         Ar = W.conj().T @ (A @ V)
-        Er = W.conj().T @ V
+        Er = W.conj().T @ (En @ V)
         res.shifts.append(sig.copy())
         res.Ar, res.Er = Ar, Er
         res.br, res.cr = W.conj().T @ b, V.conj().T @ c

@@ -166,6 +166,21 @@ def irka_problem(N: int = 48, r: int = 8, eps: float = 0.3):
     return A, b, c, np.logspace(0.0, 4.0, r).astype(np.complex128)
 
 
+def mass_like(N: int) -> CSR:
+    """An SPD matrix on the 7-point pattern of an N^3 grid: 0.6 on the
+    diagonal, 1/12 for each of the six neighbours (strictly diagonally
+    dominant), standing in for a finite-element mass matrix E."""
+    return _stencil([N, N, N], 0.6, [1.0 / 12] * 3, [1.0 / 12] * 3)
+
+
+def irka_problem_e(N: int = 48, r: int = 8, eps: float = 0.3):
+    """IRKA with E != I (the model E x' = A x + b v, y = c^* x of Sec. 5): A
+    as in irka_problem, E = mass_like(N) on A's sparsity pattern, b, c and
+    the initial shifts as in irka_problem.  Returns (A, E, b, c, sigma0)."""
+    A, b, c, s0 = irka_problem(N, r, eps)
+    return A, mass_like(N), b, c, s0
+
+
 def cfg3_shifts(nsweeps: int = 6, N: int = 48):
     """Shifted pairs (sigma I - A) x = b, (sigma I - A)^H x~ = c with
     A = -L_kappa - 0.1 I on N^3 (default 48^3, n=110592).  Per sweep 8 shifts in

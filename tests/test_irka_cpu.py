@@ -1,4 +1,4 @@
-"""Pins of the oracle's IRKA (Algorithm 3, E = I; oracle/irka.py) against what
+"""Pins of the oracle's IRKA (Algorithm 3; oracle/irka.py) against what
 the interpolation theory of Sec. 5 fixes, independently of the algorithm's own
 arithmetic:
   - Petrov-Galerkin projection with V = (sigma I - A)^{-1} b columns and
@@ -72,3 +72,77 @@ def test_hermite_interpolation_at_complex_shifts():
         assert _rel(transfer_reduced(res.Ar, res.Er, res.br, res.cr, s), transfer(A, b, c, s)) <= 1e-10
         assert _rel(transfer_reduced_deriv(res.Ar, res.Er, res.br, res.cr, s),
                     transfer_deriv(A, b, c, s)) <= 1e-9
+
+
+# ---------------------------------------------------------------- E != I
+# The model G(s) = c^H (s E - A)^{-1} b of Sec. 5 with an SPD E on A's
+# pattern.  Derivatives are checked by central differences of G itself, so
+# that the pins do not reuse the derivative formula.
+
+def _fd(f, s, h):
+    return (f(s + h) - f(s - h)) / (2 * h)
+
+
+@pytest.fixture(scope="module")
+def run6e():
+    A, E, b, c, s0 = wl.irka_problem_e(N=6, r=4)
+    return A, E, b, c, irka(A, b, c, s0, tol=1e-8, maxit=80, E=E)
+
+
+def test_hermite_interpolation_with_e(run6e):
+    A, E, b, c, res = run6e
+    assert res.converged
+    Ed = E.to_dense()
+    for s in res.shifts[-1]:
+        # G from a dense solve of (s E - A), G' by central differences
+        g = np.vdot(c, np.linalg.solve(s * Ed - A.to_dense(), b))
+        h = 1e-4 * abs(s)
+        d = _fd(lambda z: transfer(A, b, c, z, E=E), s, h)
+        assert _rel(transfer_reduced(res.Ar, res.Er, res.br, res.cr, s), g) <= 1e-10
+        assert _rel(transfer_reduced_deriv(res.Ar, res.Er, res.br, res.cr, s), d) <= 1e-6
+    # the E = I model is a different one: its interpolant misses G here
+    s = res.shifts[-1][0]
+    res_i = irka(A, b, c, res.shifts[-1], tol=1e-6, maxit=1)
+    assert _rel(transfer_reduced(res_i.Ar, res_i.Er, res_i.br, res_i.cr, s),
+                transfer(A, b, c, s, E=E)) > 1e-3
+
+
+def test_diagonal_e_equals_rescaled_identity_model():
+    """With E = D diagonal, (s D - A)^{-1} = D^{-1/2} (s I - A^)^{-1} D^{-1/2}
+    for A^ = D^{-1/2} A D^{-1/2}: IRKA on (D, A, b, c) and on (I, A^,
+    D^{-1/2} b, D^{-1/2} c) build the same reduced pencils and shifts."""
+    import scipy.sparse as sp
+    A, b, c, s0 = wl.irka_problem(N=5, r=4)
+    rng = np.random.default_rng(5)
+    d = rng.uniform(0.5, 2.0, A.n)
+    As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    Dm = sp.diags(d).tocsr()
+    Dh = sp.diags(1.0 / np.sqrt(d))
+    r1 = irka(As, b, c, s0, tol=1e-9, maxit=60, E=Dm)
+    r2 = irka((Dh @ As @ Dh).tocsr(), b / np.sqrt(d), c / np.sqrt(d), s0, tol=1e-9, maxit=60)
+    assert r1.converged and r2.converged and r1.steps == r2.steps
+    assert np.max(np.abs(r1.shifts[-1] - r2.shifts[-1]) / np.abs(r2.shifts[-1])) <= 1e-8
+    for s in (2.0 + 1j, 30.0):
+        assert _rel(transfer_reduced(r1.Ar, r1.Er, r1.br, r1.cr, s),
+                    transfer_reduced(r2.Ar, r2.Er, r2.br, r2.cr, s)) <= 1e-9
+
+
+def test_full_order_is_exact_with_e():
+    A = wl.aniso_diffusion(2)
+    E = wl.mass_like(2)
+    rng = np.random.default_rng(7)
+    b, c = rng.standard_normal(8), rng.standard_normal(8)
+    s0 = np.array([1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0, 200.0], dtype=np.complex128)
+    res = irka(A, b, c, s0, tol=1e-6, maxit=1, E=E)
+    Ad, Ed = A.to_dense(), E.to_dense()
+    for s in rng.uniform(0.5, 300.0, 5) + 1j * rng.uniform(-10.0, 10.0, 5):
+        g = np.vdot(c, np.linalg.solve(s * Ed - Ad, b))
+        assert _rel(transfer_reduced(res.Ar, res.Er, res.br, res.cr, s), g) <= 1e-9
+
+
+def test_transfer_deriv_with_e_matches_differences():
+    A, E, b, c, _ = wl.irka_problem_e(N=4, r=2)
+    for s in (3.0 + 2.0j, 150.0 + 0.0j):
+        h = 1e-4 * abs(s)
+        assert _rel(transfer_deriv(A, b, c, s, E=E),
+                    _fd(lambda z: transfer(A, b, c, z, E=E), s, h)) <= 1e-6
