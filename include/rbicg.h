@@ -135,8 +135,27 @@ void rbicg_default_opts(rbicg_opts *opts);
  * Blocks until the upload is complete. */
 int rbicg_matrix_create(const rbicg_csr *A, const rbicg_csr *AH, rbicg_matrix *out);
 
-/* Free a matrix made by rbicg_matrix_create (no handle may still use it). */
+/* Free a matrix made by rbicg_matrix_create or rbicg_matrix_pencil (no
+ * handle may still use it). */
 int rbicg_matrix_destroy(rbicg_matrix m);
+
+/* The pencil P = alpha E + beta A of two resident matrices, with its
+ * conjugate transpose conj(alpha) E^H + conj(beta) A^H: the shifted operators
+ * sigma E - A (alpha = sigma, beta = -1) of IRKA with E != I (Algorithm 3,
+ * step 2).  alpha, beta: complex numbers as (re, im) pairs (host).  E must be
+ * given on A's sparsity pattern (explicit zeros allowed); P is complex and
+ * needs RBICG_C128 handles.
+ *   *out == NULL: a new matrix with A's layout is made (the layouts are
+ *     compared on the host, once) and its values are set.
+ *   *out from an earlier call with the same A and E: only the values are
+ *     overwritten, by one device pass on `stream` (asynchronous; the caller
+ *     orders it against the handles that use *out, e.g. by using their
+ *     stream or synchronizing).
+ * Errors: RBICG_EINVAL for null arguments, a size or pattern mismatch, or an
+ * *out that is not a pencil of A and E; RBICG_ENOMEM / RBICG_EHIP otherwise.
+ * Free with rbicg_matrix_destroy. */
+int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double *alpha, const double *beta,
+                        void *stream, rbicg_matrix *out);
 
 /* As rbicg_create, on a preloaded matrix (not owned by the handle). */
 int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);

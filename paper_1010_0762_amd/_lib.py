@@ -69,6 +69,7 @@ SIGNATURES = {
     "rbicg_matrix_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(rbicg_csr),
                                        ct.POINTER(_P)]),
     "rbicg_matrix_destroy": (ct.c_int, [_P]),
+    "rbicg_matrix_pencil": (ct.c_int, [_P, _P, _DP, _DP, _P, ct.POINTER(_P)]),
     "rbicg_create_on": (ct.c_int, [_P, ct.POINTER(rbicg_opts), ct.POINTER(_P)]),
     "rbicg_update_recycle_on": (ct.c_int, [_P, _P]),
     "rbicg_profile": (ct.c_int, [_P, _I, _DP]),

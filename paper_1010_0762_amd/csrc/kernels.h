@@ -74,6 +74,10 @@ template <class V>
 void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, int p, V *Y,
                    int ld);
 
+// out[i] = alpha e[i] + beta a[i] over m sliced-ELL entries (a, e real or complex)
+void launch_pencil(hipStream_t st, size_t m, const void *a, int acplx, const void *e, int ecplx,
+                   cd alpha, cd beta, cd *out);
+
 // ---- batched shifted pairs (see kernels.hip) ----
 int sh_blocks(int n);      // blocks of k_sh2 (partials of P3)
 int sh_sub_blocks(int n);  // blocks of k_sh_sub

@@ -897,6 +897,18 @@ __global__ void k_reseed(V *x, size_t n, unsigned long long seed) {
   if (i < n) x[i] = reseed_val<V>(seed, i);
 }
 
+// Values of the pencil alpha E + beta A on a shared sliced-ELL layout (the
+// shifted operators sigma E - A of Algorithm 3 with E != I).  a, e: real
+// (acplx / ecplx = 0) or complex entries; padding entries are zero in both.
+__global__ void k_pencil(size_t m, const void *a, int acplx, const void *e, int ecplx, cd alpha,
+                         cd beta, cd *out) {
+  const size_t i = (size_t)blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i >= m) return;
+  const cd av = acplx ? ((const cd *)a)[i] : cd{((const double *)a)[i], 0.0};
+  const cd ev = ecplx ? ((const cd *)e)[i] : cd{((const double *)e)[i], 0.0};
+  out[i] = alpha * ev + beta * av;
+}
+
 // ----------------------------------------------------- cycle-end kernels
 // Load through a pointer known to point at device global memory (pointers
 // read back from LDS tables would otherwise produce flat loads).
@@ -1911,6 +1923,13 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
     hipLaunchKernelGGL((k_tsgemm_mfma<V, 3>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
   else
     hipLaunchKernelGGL((k_tsgemm_mfma<V, 4>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+}
+
+void launch_pencil(hipStream_t st, size_t m, const void *a, int acplx, const void *e, int ecplx,
+                   cd alpha, cd beta, cd *out) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_pencil, dim3((unsigned)nblk(m)), dim3(RBICG_BLOCK), 0, st, m, a, acplx, e,
+                     ecplx, alpha, beta, out);
 }
 
 // ------------------------------------------------------- shifted launchers

@@ -236,6 +236,8 @@ struct rbicg_mat_s {
   int n = 0;
   bool complex_vals = false;
   DevSell A, AH;
+  // set for a pencil alpha E + beta A made by rbicg_matrix_pencil
+  const rbicg_mat_s *pencil_a = nullptr, *pencil_e = nullptr;
 };
 
 // Workspace of rbicg_solve_shifted, allocated on the first call (n x S batch
@@ -2015,6 +2017,78 @@ extern "C" int rbicg_matrix_create(const rbicg_csr *A, const rbicg_csr *AH, rbic
     return rc;
   }
   *out = m;
+  return RBICG_OK;
+}
+
+namespace {
+// Same sliced-ELL layout (sizes, slice pointers and column indices).
+int same_layout(const DevSell &a, const DevSell &b) {
+  if (a.n != b.n || a.nslices != b.nslices || a.nnzpad != b.nnzpad)
+    return rbicg_fail(RBICG_EINVAL, "E and A have different sparsity layouts");
+  std::vector<int> x(a.nslices + 1), y(a.nslices + 1);
+  HIPCHECK(hipMemcpy(x.data(), a.sliceptr, x.size() * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(y.data(), b.sliceptr, y.size() * sizeof(int), hipMemcpyDeviceToHost));
+  if (x != y) return rbicg_fail(RBICG_EINVAL, "E and A have different sparsity layouts");
+  x.resize(a.nnzpad);
+  y.resize(a.nnzpad);
+  if (a.nnzpad) {
+    HIPCHECK(hipMemcpy(x.data(), a.col, a.nnzpad * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(y.data(), b.col, a.nnzpad * sizeof(int), hipMemcpyDeviceToHost));
+  }
+  if (x != y) return rbicg_fail(RBICG_EINVAL, "E must be given on A's sparsity pattern");
+  return 0;
+}
+
+// A complex sliced-ELL matrix with src's layout (values uninitialized).
+int alloc_like(const DevSell &src, DevSell &d) {
+  d.n = src.n;
+  d.nslices = src.nslices;
+  d.nnzpad = src.nnzpad;
+  d.nnz = src.nnz;
+  d.vbytes = 16;
+  HIPCHECK(hipMalloc((void **)&d.sliceptr, (size_t)(src.nslices + 1) * sizeof(int)));
+  HIPCHECK(hipMalloc((void **)&d.col, std::max<size_t>(src.nnzpad, 1) * sizeof(int)));
+  HIPCHECK(hipMalloc(&d.val, std::max<size_t>(src.nnzpad, 1) * sizeof(cd)));
+  HIPCHECK(hipMemcpy(d.sliceptr, src.sliceptr, (size_t)(src.nslices + 1) * sizeof(int), hipMemcpyDeviceToDevice));
+  if (src.nnzpad)
+    HIPCHECK(hipMemcpy(d.col, src.col, src.nnzpad * sizeof(int), hipMemcpyDeviceToDevice));
+  return 0;
+}
+}  // namespace
+
+extern "C" int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double *alpha,
+                                   const double *beta, void *stream, rbicg_matrix *out) {
+  if (!A || !E || !alpha || !beta || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (A->n != E->n) return rbicg_fail(RBICG_EINVAL, "E is %d x %d, A is %d x %d", E->n, E->n, A->n, A->n);
+  hipStream_t st = (hipStream_t)stream;
+  rbicg_mat_s *m = *out;
+  if (!m) {
+    TRY(same_layout(A->A, E->A));
+    TRY(same_layout(A->AH, E->AH));
+    m = new rbicg_mat_s();
+    m->n = A->n;
+    m->complex_vals = true;
+    m->pencil_a = A;
+    m->pencil_e = E;
+    int rc = alloc_like(A->A, m->A);
+    if (rc >= 0) rc = alloc_like(A->AH, m->AH);
+    if (rc < 0) {
+      m->A.release();
+      m->AH.release();
+      delete m;
+      return rc;
+    }
+    *out = m;
+  } else if (m->pencil_a != A || m->pencil_e != E) {
+    return rbicg_fail(RBICG_EINVAL, "out is not a pencil of these matrices");
+  }
+  const cd al = {alpha[0], alpha[1]}, be = {beta[0], beta[1]};
+  // alpha E + beta A and its conjugate transpose conj(alpha) E^H + conj(beta) A^H
+  launch_pencil(st, m->A.nnzpad, A->A.val, A->A.vbytes == 16, E->A.val, E->A.vbytes == 16, al, be,
+                (cd *)m->A.val);
+  launch_pencil(st, m->AH.nnzpad, A->AH.val, A->AH.vbytes == 16, E->AH.val, E->AH.vbytes == 16,
+                cd{al.x, -al.y}, cd{be.x, -be.y}, (cd *)m->AH.val);
+  HIPCHECK(hipGetLastError());
   return RBICG_OK;
 }
 

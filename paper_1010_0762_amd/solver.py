@@ -60,6 +60,27 @@ class DeviceMatrix:
         _lib.check(rc, "rbicg_matrix_create")
         self.h = h
 
+    @classmethod
+    def pencil(cls, A: "DeviceMatrix", E: "DeviceMatrix", alpha, beta=-1.0, out=None,
+               stream=None) -> "DeviceMatrix":
+        """alpha E + beta A (default beta = -1: the shifted operator alpha E - A)
+        on A's layout, by rbicg_matrix_pencil.  With out (an earlier pencil of
+        the same A and E) its values are overwritten in place on `stream`
+        (default: the current stream)."""
+        lib = _lib.load()
+        al = np.array([complex(alpha).real, complex(alpha).imag])
+        be = np.array([complex(beta).real, complex(beta).imag])
+        h = ct.c_void_p(out.h.value if out is not None else None)
+        rc = lib.rbicg_matrix_pencil(A.h, E.h, al.ctypes.data_as(_lib._DP),
+                                     be.ctypes.data_as(_lib._DP),
+                                     ct.c_void_p(_stream_ptr(stream)), ct.byref(h))
+        _lib.check(rc, "rbicg_matrix_pencil")
+        if out is not None:
+            return out
+        m = cls.__new__(cls)
+        m.lib, m.h, m.n, m.complex = lib, h, A.n, True
+        return m
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.rbicg_matrix_destroy(self.h)
