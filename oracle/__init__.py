@@ -15,8 +15,10 @@ Modules
   drivers  -- sequences of dual systems, shifted pairs (sigma I - A) sharing one
               recycle space, FP32-inner / FP64-outer refinement, bilinear forms.
   rng      -- SplitMix64 counter generator used when x~ must be re-seeded.
-  irka     -- IRKA (Algorithm 3, E = I) with direct solves, and transfer
-              functions of the full and reduced models.
+  irka     -- IRKA (Algorithm 3, E = I or general E) with direct solves, and
+              transfer functions of the full and reduced models.
+  precond  -- split ILU(0) preconditioning in red-black ordering and
+              sequences of split-preconditioned RBiCG solves.
 
 Pinned against: dense direct solves, CG and SciPy's BiCG iterates (textbook
 special cases), exact-eigenvector deflation, biorthogonality, the T-from-scalars
@@ -28,6 +30,7 @@ from .krylov import bicg, rbicg, SolveResult, as_csr
 from .recycle import (t_from_scalars, harmonic_pencils, select_eigvecs,
                       biorthogonalize, first_cycle_eigvecs)
 from .drivers import (rbicg_sequence, shifted_pairs, mixed_refine, bilinear)
+from . import precond
 from .rng import splitmix64, reseed_vector
 from . import irka
 

@@ -1,0 +1,166 @@
+"""Split ILU(0) preconditioning in red-black ordering -- TEST INFRASTRUCTURE.
+
+Only tests/, the package smoke check and the benchmark's CPU-baseline leg may
+import this module; the product path never does.
+
+The experiments of Sec. 6 split-precondition every system with an incomplete
+LU factorization (ILUT / ILUTP) and recycle spaces of the preconditioned
+systems.  Reading: the threshold and pivoting variants are tied to MATLAB's
+implementation; the no-fill factorization ILU(0) is used here, on the
+red-black ordering of the unknowns (red first), for matrices whose
+off-diagonal graph is two-colourable (the 5- and 7-point stencils of the
+convection-diffusion problems).  With P the red-black permutation and
+P A P^T = L U + R the ILU(0) factorization, the dual pair
+    A x = b,   A^H x~ = b~
+becomes the split-preconditioned pair
+    A^ y = L^{-1} P b,   A^^H y~ = U^{-H} P b~,   A^ = L^{-1} P A P^T U^{-1},
+    x = P^T U^{-1} y,    x~ = P^T L^{-H} y~.
+In red-black ordering A^ is block diagonal, [[I, 0], [0, M_B]] (the pins
+check this on the explicit product), so the red part of y is the red part of
+the preconditioned right-hand side and RBiCG runs on the black block M_B,
+whose recycle spaces are those of the preconditioned systems.  Stopping is on
+the preconditioned (black) residual.
+"""
+from __future__ import annotations
+
+from collections import deque
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .krylov import as_csr, rbicg
+from . import recycle as rc
+
+
+def two_coloring(A) -> np.ndarray:
+    """0 (red) / 1 (black) per unknown by breadth-first search over the
+    off-diagonal graph of A + A^T, each component starting red at its lowest
+    index; ValueError if an off-diagonal entry joins two unknowns of one
+    colour."""
+    A = as_csr(A)
+    n = A.shape[0]
+    G = (abs(A) + abs(A).T).tocsr()
+    col = -np.ones(n, dtype=np.int64)
+    for s in range(n):
+        if col[s] >= 0:
+            continue
+        col[s] = 0
+        q = deque([s])
+        while q:
+            i = q.popleft()
+            for j in G.indices[G.indptr[i]:G.indptr[i + 1]]:
+                if j == i:
+                    continue
+                if col[j] < 0:
+                    col[j] = 1 - col[i]
+                    q.append(j)
+                elif col[j] == col[i]:
+                    raise ValueError("the off-diagonal graph is not two-colourable")
+    return col
+
+
+def rb_permutation(color) -> np.ndarray:
+    """perm[new] = old: the red unknowns in ascending order, then the black."""
+    color = np.asarray(color)
+    return np.concatenate([np.flatnonzero(color == 0), np.flatnonzero(color == 1)])
+
+
+def ilu0(M):
+    """ILU(0) of a square sparse matrix by the row-wise (IKJ) elimination
+    restricted to the pattern of M: returns (L unit lower, U upper) with
+    (L U)_ij = M_ij on the pattern.  Plain loops (small matrices only)."""
+    M = as_csr(M).astype(np.complex128)
+    M.sort_indices()
+    n = M.shape[0]
+    ptr, idx = M.indptr, M.indices
+    val = M.data.copy()
+    pos = [dict(zip(idx[ptr[i]:ptr[i + 1]], range(ptr[i], ptr[i + 1]))) for i in range(n)]
+    for i in range(n):
+        for p in range(ptr[i], ptr[i + 1]):
+            k = idx[p]
+            if k >= i:
+                break
+            val[p] /= val[pos[k][k]]
+            for q in range(ptr[k], ptr[k + 1]):
+                j = idx[q]
+                if j > k and j in pos[i]:
+                    val[pos[i][j]] -= val[p] * val[q]
+    F = sp.csr_matrix((val, idx.copy(), ptr.copy()), shape=(n, n))
+    L = (sp.tril(F, -1) + sp.identity(n, format="csr")).tocsr()
+    U = sp.triu(F).tocsr()
+    return L, U
+
+
+class SplitSystem:
+    """The split-preconditioned form of one matrix."""
+
+    def __init__(self, A):
+        A = as_csr(A).astype(np.complex128)
+        self.n = A.shape[0]
+        self.color = two_coloring(A)
+        self.perm = rb_permutation(self.color)
+        self.nr = int(np.sum(self.color == 0))
+        P = sp.csr_matrix((np.ones(self.n), (np.arange(self.n), self.perm)), shape=(self.n, self.n))
+        self.P = P
+        self.At = (P @ A @ P.T).tocsr()
+        self.L, self.U = ilu0(self.At)
+
+    def operator(self) -> np.ndarray:
+        """A^ = L^{-1} P A P^T U^{-1} as a dense array (small n)."""
+        Ad = self.At.toarray()
+        X = spla.spsolve_triangular(self.L.tocsr(), Ad, lower=True)
+        return spla.spsolve_triangular(self.U.T.tocsr(), X.T, lower=True).T
+
+    def black_block(self) -> sp.csr_matrix:
+        return sp.csr_matrix(self.operator()[self.nr:, self.nr:])
+
+    def rhs(self, b, bt):
+        """(L^{-1} P b, U^{-H} P b~)."""
+        bh = spla.spsolve_triangular(self.L.tocsr(), self.P @ np.asarray(b, np.complex128), lower=True)
+        ch = spla.spsolve_triangular(self.U.conj().T.tocsr(), self.P @ np.asarray(bt, np.complex128),
+                                     lower=True)
+        return bh, ch
+
+    def solution(self, y, yt):
+        """(P^T U^{-1} y, P^T L^{-H} y~)."""
+        x = spla.spsolve_triangular(self.U.tocsr(), np.asarray(y, np.complex128), lower=False)
+        xt = spla.spsolve_triangular(self.L.conj().T.tocsr(), np.asarray(yt, np.complex128), lower=False)
+        return self.P.T @ x, self.P.T @ xt
+
+
+def rbicg_split_sequence(mats, bs, bts, k, s, tol, maxit=5000, update=True, svd_tol=1e-2,
+                         seed=0, max_restarts=2, real=True):
+    """The dual pairs in order, each split-preconditioned by its own RB
+    ILU(0), RBiCG on the black blocks with the recycle space carried between
+    them (built for the preconditioned operators).  Zero initial guesses.
+    Returns (solutions [(x, x~)], results of the black solves)."""
+    U = Ut = None
+    sols, out = [], []
+    for j, A in enumerate(mats):
+        ss = SplitSystem(A)
+        MB = ss.black_block()
+        if real:
+            MB = MB.real.tocsr()
+        MBH = MB.conj().T.tocsr()
+        bh, ch = ss.rhs(bs[j], bts[j])
+        bB, cB = bh[ss.nr:], ch[ss.nr:]
+        if real:
+            bB, cB = bB.real, cB.real
+        C = Ct = None
+        if U is not None and U.shape[1] > 0 and k > 0:
+            U, Ut, C, Ct = rc.biorthogonalize(MB, MBH, U, Ut, svd_tol)
+            if C is None:
+                U = Ut = None
+        res = rbicg(MB, bB, cB, None, None, U, Ut, C, Ct, tol=tol, maxit=maxit, s=s, k=k,
+                    update=(update and k > 0), seed=seed, max_restarts=max_restarts,
+                    svd_tol=svd_tol)
+        y = np.concatenate([bh[:ss.nr], res.x])
+        yt = np.concatenate([ch[:ss.nr], res.xt])
+        x, xt = ss.solution(y, yt)
+        if real:
+            x, xt = x.real, xt.real
+        sols.append((x, xt))
+        out.append(res)
+        U, Ut = res.U_next, res.Ut_next
+    return sols, out

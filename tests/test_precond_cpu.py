@@ -1,0 +1,98 @@
+"""Pins of the oracle's split ILU(0) preconditioning in red-black ordering
+(oracle/precond.py) against facts fixed independently of its code:
+  - ILU(0) of a tridiagonal matrix is the exact LU factorization (no fill);
+  - ILU(0) reproduces the matrix on its pattern, (L U)_ij = M_ij;
+  - in red-black ordering the split-preconditioned operator is block
+    diagonal with an identity red block, and its black block is the Schur
+    complement right-scaled by the kept pivots,
+    M_B = (D_B - A_BR D_R^{-1} A_RB) diag(...)^{-1};
+  - the back-transformed solutions solve the original dual pair."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle.precond import SplitSystem, ilu0, rbicg_split_sequence, two_coloring
+from paper_1010_0762_amd import workloads as wl
+
+
+def test_ilu0_of_tridiagonal_is_exact_lu():
+    rng = np.random.default_rng(1)
+    n = 30
+    T = sp.diags([rng.uniform(-1, 0, n - 1), rng.uniform(3, 4, n), rng.uniform(-1, 0, n - 1)],
+                 [-1, 0, 1]).tocsr()
+    L, U = ilu0(T)
+    assert np.abs((L @ U - T).toarray()).max() <= 1e-13
+
+
+def test_ilu0_matches_matrix_on_pattern():
+    A = wl.convdiff(5, 3, [20.0, 10.0, 5.0])
+    ss = SplitSystem(A)
+    LU = (ss.L @ ss.U).tocsr()
+    At = ss.At.tocoo()
+    err = max(abs(LU[i, j] - v) for i, j, v in zip(At.row, At.col, At.data))
+    assert err <= 1e-12 * np.abs(At.data).max()
+    # outside the pattern the product differs (the dropped fill)
+    D = (LU - ss.At).toarray()
+    assert np.abs(D).max() > 1e-6
+
+
+def test_two_coloring_and_rejection():
+    A = wl.convdiff(4, 2, [1.0, 1.0])
+    col = two_coloring(A)
+    Ac = A if not hasattr(A, "rowptr") else sp.csr_matrix((A.vals, A.colind, A.rowptr))
+    r, c = Ac.nonzero()
+    off = r != c
+    assert np.all(col[r[off]] != col[c[off]])
+    tri = sp.csr_matrix(np.array([[2.0, 1, 1], [1, 2, 1], [1, 1, 2]]))
+    with pytest.raises(ValueError):
+        two_coloring(tri)
+
+
+def test_operator_block_structure_and_schur_block():
+    A = wl.convdiff(5, 3, [20.0, 10.0, 5.0])
+    ss = SplitSystem(A)
+    Ah = ss.operator()
+    nr = ss.nr
+    assert np.abs(Ah[:nr, :nr] - np.eye(nr)).max() <= 1e-13
+    assert np.abs(Ah[:nr, nr:]).max() <= 1e-13 and np.abs(Ah[nr:, :nr]).max() <= 1e-13
+    # closed form from the blocks of P A P^T
+    At = ss.At.toarray()
+    dR = np.diag(At)[:nr]
+    ABR, ARB, DB = At[nr:, :nr], At[:nr, nr:], np.diag(np.diag(At)[nr:])
+    S = DB - ABR @ np.diag(1.0 / dR) @ ARB
+    MB = S @ np.diag(1.0 / np.diag(S))
+    assert np.abs(Ah[nr:, nr:] - MB).max() <= 1e-12 * np.abs(MB).max()
+
+
+def test_split_sequence_solves_the_original_pairs():
+    rng = np.random.default_rng(4)
+    N = 8
+    mats = [wl.convdiff(N, 3, [20.0 * (1 + 0.02 * j), 10.0, 5.0]) for j in range(3)]
+    b, bt = rng.standard_normal(N ** 3), rng.standard_normal(N ** 3)
+    sols, res = rbicg_split_sequence(mats, [b] * 3, [bt] * 3, k=6, s=20, tol=1e-10)
+    for A, (x, xt), r in zip(mats, sols, res):
+        As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+        assert r.status == "ok"
+        assert np.linalg.norm(b - As @ x) <= 1e-7 * np.linalg.norm(b)
+        assert np.linalg.norm(bt - As.T @ xt) <= 1e-7 * np.linalg.norm(bt)
+    # the preconditioned black systems converge faster than plain BiCG on A
+    plain = oracle.bicg(mats[0], b, bt, tol=1e-10, maxit=5000)
+    assert res[0].iters < plain.iters
+
+
+def test_split_solve_complex_pair():
+    """Complex values (a missing conjugation in a dual transform fails here)."""
+    rng = np.random.default_rng(6)
+    A = wl.convdiff(6, 3, [20.0, 10.0, 5.0])
+    As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n)).astype(np.complex128)
+    As = (As + 1j * sp.diags(rng.uniform(1.0, 5.0, A.n)) +
+          1j * 0.3 * sp.csr_matrix((rng.uniform(-1, 1, A.nnz), A.colind, A.rowptr),
+                                   shape=(A.n, A.n))).tocsr()
+    b = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+    bt = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+    sols, res = rbicg_split_sequence([As], [b], [bt], k=0, s=20, tol=1e-11, real=False)
+    x, xt = sols[0]
+    assert res[0].status == "ok"
+    assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(bt - As.conj().T @ xt) <= 1e-8 * np.linalg.norm(bt)
