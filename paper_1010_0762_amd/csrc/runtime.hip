@@ -1902,7 +1902,11 @@ int alloc_workspace(rbicg_s *h) {
   if (h->opt.profile) {
     const int nev = 8 * std::max(8, h->opt.chunk);
     h->pev.resize(nev);
-    for (auto &e : h->pev) HIPCHECK(hipEventCreate(&e));
+    // timing-only events: no system-scope fence (cache writeback and
+    // invalidation) when they are recorded, so that a bracket holds the
+    // kernel and not a flush the untimed launches never pay; the chunk's
+    // synchronizing event, recorded after them, orders their read-back
+    for (auto &e : h->pev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   HIPCHECK(hipHostMalloc((void **)&h->hS, 2 * sizeof(Scalars), hipHostMallocDefault));
   for (auto &e : h->sev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
