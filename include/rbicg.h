@@ -157,6 +157,34 @@ int rbicg_matrix_destroy(rbicg_matrix m);
 int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double *alpha, const double *beta,
                         void *stream, rbicg_matrix *out);
 
+/* Split ILU(0) preconditioning in red-black ordering (Sec. 6 solves every
+ * system split-preconditioned, with recycle spaces of the preconditioned
+ * systems).  The unknowns of A are coloured so that every off-diagonal entry
+ * joins a red and a black unknown (5- and 7-point stencils); with P the
+ * red-black permutation and P A P^T = L U + R its ILU(0) factorization, the
+ * split-preconditioned operator L^{-1} P A P^T U^{-1} is block diagonal with
+ * an identity red block and the black block
+ *   M_B = (D_B - A_BR D_R^{-1} A_RB) S_B^{-1}
+ * (S_B: the black ILU(0) pivots).  A dual pair A x = b, A^H x~ = b~ is solved
+ * as M_B y_B = b^_B, M_B^H y~_B = c^_B (an ordinary handle on *black) with
+ * the transforms below.
+ *   rbicg_rbilu_create: host set-up from A (host or device CSR, real or
+ *     complex): *out (the transforms' device data), *black (M_B and M_B^H,
+ *     resident; free with rbicg_matrix_destroy) and *nb (its order).
+ *     RBICG_EINVAL if A has a zero diagonal entry or zero pivot or its
+ *     off-diagonal graph is not two-colourable.
+ *   rbicg_rbilu_rhs: b^_B, c^_B (nb entries each) from b, b~ (n entries).
+ *   rbicg_rbilu_solution: x, x~ (n entries) from y_B, y~_B and b, b~.
+ * Vectors are device arrays of A's value type (double or interleaved
+ * complex), used on `stream`; calls on one preconditioner must not overlap
+ * (they share a scratch vector).  Free with rbicg_rbilu_destroy. */
+typedef struct rbicg_rbilu_s *rbicg_rbilu;
+int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_matrix *black, int32_t *nb);
+int rbicg_rbilu_rhs(rbicg_rbilu P, const void *b, const void *bt, void *bB, void *btB, void *stream);
+int rbicg_rbilu_solution(rbicg_rbilu P, const void *b, const void *bt, const void *yB,
+                         const void *ytB, void *x, void *xt, void *stream);
+int rbicg_rbilu_destroy(rbicg_rbilu P);
+
 /* As rbicg_create, on a preloaded matrix (not owned by the handle). */
 int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);
 

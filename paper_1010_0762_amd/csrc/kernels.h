@@ -97,3 +97,20 @@ void launch_sh2(hipStream_t st, int n, int ld, int S, cd *X, cd *Xt, cd *R, cd *
                 const cd *Ptn, const cd *Z, const cd *Zt, const cd *B, const cd *Bt, int k2,
                 const cd *Y, const cd *Yt, ShScalars *Sh, double *P3, int nb, int upd);
 
+// ---- split ILU(0) preconditioning in red-black ordering (precond.hip) ----
+// Device data of a preconditioner: CSR rows of A (rp, ci, av) and of A^H
+// (hrp, hci, hv), the diagonal d of A, the black index of each unknown
+// (bidx, -1 for red) and the black ILU(0) pivots sb (length nb); values are
+// double or complex (cd) as the matrix.
+struct RbDev {
+  int n = 0, nb = 0;
+  const int *rp = nullptr, *ci = nullptr, *hrp = nullptr, *hci = nullptr, *bidx = nullptr;
+  const void *av = nullptr, *hv = nullptr, *d = nullptr, *sb = nullptr;
+};
+// b^_B, c^_B (length nb) from b, b~ (length n); cR: n-long scratch
+template <class V>
+void launch_rb_rhs(hipStream_t st, const RbDev &P, const V *b, const V *bt, V *bB, V *cB, V *cR);
+// x, x~ (length n) from the black solutions y_B, y~_B and b, b~
+template <class V>
+void launch_rb_solution(hipStream_t st, const RbDev &P, const V *b, const V *bt, const V *yB,
+                        const V *ytB, V *x, V *xt);

@@ -2096,6 +2096,222 @@ extern "C" int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double 
   return RBICG_OK;
 }
 
+// ------------------------------------------- split ILU(0), red-black
+// Host set-up of the red-black ILU(0) split preconditioner (the transforms
+// run in precond.hip): two-colouring, pivots, the black block
+// M_B = (D_B - A_BR D_R^{-1} A_RB) S_B^{-1} of the split-preconditioned
+// operator, and the device data of the transforms.
+struct rbicg_rbilu_s {
+  int n = 0, nb = 0;
+  bool complex_vals = false;
+  RbDev dev;
+  void *cR = nullptr;  // n-long scratch of the right-hand-side transform
+  std::vector<void *> allocs;
+  ~rbicg_rbilu_s() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+template <class T>
+int rb_upload(rbicg_rbilu_s *P, const void **dst, const T *src, size_t count) {
+  void *p = nullptr;
+  HIPCHECK(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+  P->allocs.push_back(p);
+  if (count) HIPCHECK(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  *dst = p;
+  return 0;
+}
+
+// values as the device type: double (real matrices) or interleaved complex
+std::vector<double> rb_values(const std::vector<cplx> &v, bool cplxv) {
+  std::vector<double> o(cplxv ? 2 * v.size() : v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (cplxv) {
+      o[2 * i] = v[i].real();
+      o[2 * i + 1] = v[i].imag();
+    } else {
+      o[i] = v[i].real();
+    }
+  }
+  return o;
+}
+
+int rb_upload_vals(rbicg_rbilu_s *P, const void **dst, const std::vector<cplx> &v) {
+  const std::vector<double> o = rb_values(v, P->complex_vals);
+  return rb_upload(P, dst, o.data(), o.size());
+}
+}  // namespace
+
+extern "C" int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_matrix *black,
+                                  int32_t *nb) {
+  if (!A || !out || !black || !nb) return rbicg_fail(RBICG_EINVAL, "null argument");
+  HostCsr hA;
+  TRY(read_csr(A, hA));
+  const int n = hA.n;
+  const HostCsr hAH = conj_transpose(hA);
+  std::vector<cplx> d(n, cplx(0.0, 0.0));
+  for (int i = 0; i < n; ++i)
+    for (int e = hA.rowptr[i]; e < hA.rowptr[i + 1]; ++e)
+      if (hA.col[e] == i) d[i] += hA.val[e];
+  for (int i = 0; i < n; ++i)
+    if (d[i] == cplx(0.0, 0.0)) return rbicg_fail(RBICG_EINVAL, "zero diagonal entry in row %d", i);
+  // two-colouring of the off-diagonal graph of A + A^T (breadth first; each
+  // component starts red at its lowest index)
+  std::vector<int> color(n, -1), queue;
+  queue.reserve(n);
+  for (int s0 = 0; s0 < n; ++s0) {
+    if (color[s0] >= 0) continue;
+    color[s0] = 0;
+    queue.assign(1, s0);
+    for (size_t q = 0; q < queue.size(); ++q) {
+      const int i = queue[q];
+      for (const HostCsr *M : {(const HostCsr *)&hA, &hAH})
+        for (int e = M->rowptr[i]; e < M->rowptr[i + 1]; ++e) {
+          const int j = M->col[e];
+          if (j == i) continue;
+          if (color[j] < 0) {
+            color[j] = 1 - color[i];
+            queue.push_back(j);
+          } else if (color[j] == color[i]) {
+            return rbicg_fail(RBICG_EINVAL, "the off-diagonal graph of A is not two-colourable");
+          }
+        }
+    }
+  }
+  std::vector<int> bidx(n, -1), blist;
+  for (int i = 0; i < n; ++i)
+    if (color[i] == 1) {
+      bidx[i] = (int)blist.size();
+      blist.push_back(i);
+    }
+  const int nbk = (int)blist.size();
+  if (nbk == 0) return rbicg_fail(RBICG_EINVAL, "no black unknowns");
+  // rows of S = D_B - A_BR D_R^{-1} A_RB (black numbering), then S_B = diag(S)
+  HostCsr hS;
+  hS.n = nbk;
+  hS.complex_vals = hA.complex_vals;
+  hS.rowptr.assign(nbk + 1, 0);
+  std::vector<cplx> acc(nbk, cplx(0.0, 0.0));
+  std::vector<int> mark(nbk, -1), cols;
+  for (int bi = 0; bi < nbk; ++bi) {
+    const int i = blist[bi];
+    cols.clear();
+    auto touch = [&](int bj) {
+      if (mark[bj] != bi) {
+        mark[bj] = bi;
+        acc[bj] = cplx(0.0, 0.0);
+        cols.push_back(bj);
+      }
+    };
+    touch(bi);
+    acc[bi] += d[i];
+    for (int e = hA.rowptr[i]; e < hA.rowptr[i + 1]; ++e) {
+      const int k = hA.col[e];
+      if (k == i) continue;
+      const cplx f = hA.val[e] / d[k];
+      for (int g = hA.rowptr[k]; g < hA.rowptr[k + 1]; ++g) {
+        const int j = hA.col[g];
+        if (j == k) continue;
+        touch(bidx[j]);
+        acc[bidx[j]] -= f * hA.val[g];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int bj : cols) {
+      hS.col.push_back(bj);
+      hS.val.push_back(acc[bj]);
+    }
+    hS.rowptr[bi + 1] = (int)hS.col.size();
+  }
+  std::vector<cplx> sb(nbk, cplx(0.0, 0.0));
+  for (int bi = 0; bi < nbk; ++bi)
+    for (int e = hS.rowptr[bi]; e < hS.rowptr[bi + 1]; ++e)
+      if (hS.col[e] == bi) sb[bi] = hS.val[e];
+  for (int bi = 0; bi < nbk; ++bi)
+    if (sb[bi] == cplx(0.0, 0.0)) return rbicg_fail(RBICG_EINVAL, "zero ILU(0) pivot at unknown %d", blist[bi]);
+  for (size_t e = 0; e < hS.col.size(); ++e) hS.val[e] /= sb[hS.col[e]];
+  // the black block, resident with its conjugate transpose
+  rbicg_mat_s *m = new rbicg_mat_s();
+  m->n = nbk;
+  m->complex_vals = hS.complex_vals;
+  int rc = upload_sell(hS, m->complex_vals ? 1 : 0, m->A);
+  if (rc >= 0) rc = upload_sell(conj_transpose(hS), m->complex_vals ? 1 : 0, m->AH);
+  if (rc < 0) {
+    m->A.release();
+    m->AH.release();
+    delete m;
+    return rc;
+  }
+  // device data of the transforms
+  rbicg_rbilu_s *P = new rbicg_rbilu_s();
+  P->n = n;
+  P->nb = nbk;
+  P->complex_vals = hA.complex_vals;
+  P->dev.n = n;
+  P->dev.nb = nbk;
+  rc = rb_upload(P, (const void **)&P->dev.rp, hA.rowptr.data(), hA.rowptr.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->dev.ci, hA.col.data(), hA.col.size());
+  if (rc >= 0) rc = rb_upload_vals(P, &P->dev.av, hA.val);
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->dev.hrp, hAH.rowptr.data(), hAH.rowptr.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->dev.hci, hAH.col.data(), hAH.col.size());
+  if (rc >= 0) rc = rb_upload_vals(P, &P->dev.hv, hAH.val);
+  if (rc >= 0) rc = rb_upload_vals(P, &P->dev.d, d);
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->dev.bidx, bidx.data(), bidx.size());
+  if (rc >= 0) rc = rb_upload_vals(P, &P->dev.sb, sb);
+  if (rc >= 0) {
+    const std::vector<cplx> zero(n, cplx(0.0, 0.0));
+    const void *z = nullptr;
+    rc = rb_upload_vals(P, &z, zero);
+    P->cR = const_cast<void *>(z);
+  }
+  if (rc < 0) {
+    delete P;
+    m->A.release();
+    m->AH.release();
+    delete m;
+    return rc;
+  }
+  *out = P;
+  *black = m;
+  *nb = nbk;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_rbilu_rhs(rbicg_rbilu P, const void *b, const void *bt, void *bB, void *btB,
+                               void *stream) {
+  if (!P || !b || !bt || !bB || !btB) return rbicg_fail(RBICG_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (P->complex_vals)
+    launch_rb_rhs<cd>(st, P->dev, (const cd *)b, (const cd *)bt, (cd *)bB, (cd *)btB, (cd *)P->cR);
+  else
+    launch_rb_rhs<double>(st, P->dev, (const double *)b, (const double *)bt, (double *)bB,
+                          (double *)btB, (double *)P->cR);
+  HIPCHECK(hipGetLastError());
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_rbilu_solution(rbicg_rbilu P, const void *b, const void *bt, const void *yB,
+                                    const void *ytB, void *x, void *xt, void *stream) {
+  if (!P || !b || !bt || !yB || !ytB || !x || !xt) return rbicg_fail(RBICG_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (P->complex_vals)
+    launch_rb_solution<cd>(st, P->dev, (const cd *)b, (const cd *)bt, (const cd *)yB,
+                           (const cd *)ytB, (cd *)x, (cd *)xt);
+  else
+    launch_rb_solution<double>(st, P->dev, (const double *)b, (const double *)bt,
+                               (const double *)yB, (const double *)ytB, (double *)x, (double *)xt);
+  HIPCHECK(hipGetLastError());
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_rbilu_destroy(rbicg_rbilu P) {
+  if (!P) return RBICG_OK;
+  (void)hipDeviceSynchronize();
+  delete P;
+  return RBICG_OK;
+}
+
 extern "C" int rbicg_matrix_destroy(rbicg_matrix m) {
   if (!m) return RBICG_OK;
   (void)hipDeviceSynchronize();

@@ -93,6 +93,100 @@ class DeviceMatrix:
             pass
 
 
+class RBILU:
+    """Split ILU(0) preconditioner in red-black ordering of one matrix
+    (rbicg_rbilu_*): ``black`` is the black block M_B of the split-
+    preconditioned operator (a DeviceMatrix of order ``nb``), on which an
+    ordinary Solver runs; ``rhs`` and ``solution`` map a dual pair's
+    right-hand sides to the black system and its solutions back."""
+
+    def __init__(self, A):
+        self.lib = _lib.load()
+        keep = []
+        a = _csr_struct(A, keep)
+        h, mb, nb = ct.c_void_p(), ct.c_void_p(), ct.c_int32()
+        rc = self.lib.rbicg_rbilu_create(ct.byref(a), ct.byref(h), ct.byref(mb), ct.byref(nb))
+        _lib.check(rc, "rbicg_rbilu_create")
+        self.h, self.n, self.nb = h, a.n, nb.value
+        self.complex = bool(a.values_complex)
+        self.dtype = torch.complex128 if self.complex else torch.float64
+        m = DeviceMatrix.__new__(DeviceMatrix)
+        m.lib, m.h, m.n, m.complex = self.lib, mb, self.nb, self.complex
+        self.black = m
+
+    def _v(self, v, n, name):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == self.dtype
+                and v.is_contiguous() and v.numel() == n):
+            raise TypeError(f"{name} must be a contiguous CUDA {self.dtype} tensor of length {n}")
+        return ct.c_void_p(v.data_ptr())
+
+    def rhs(self, b, bt, stream=None):
+        """(b^_B, c^_B) of the black system."""
+        bB = torch.empty(self.nb, dtype=self.dtype, device="cuda")
+        cB = torch.empty_like(bB)
+        rc = self.lib.rbicg_rbilu_rhs(self.h, self._v(b, self.n, "b"), self._v(bt, self.n, "bt"),
+                                      self._v(bB, self.nb, "bB"), self._v(cB, self.nb, "cB"),
+                                      ct.c_void_p(_stream_ptr(stream)))
+        _lib.check(rc, "rbicg_rbilu_rhs")
+        return bB, cB
+
+    def solution(self, b, bt, yB, ytB, stream=None):
+        """(x, x~) of the original pair from the black solutions."""
+        x = torch.empty(self.n, dtype=self.dtype, device="cuda")
+        xt = torch.empty_like(x)
+        rc = self.lib.rbicg_rbilu_solution(
+            self.h, self._v(b, self.n, "b"), self._v(bt, self.n, "bt"),
+            self._v(yB, self.nb, "yB"), self._v(ytB, self.nb, "ytB"), self._v(x, self.n, "x"),
+            self._v(xt, self.n, "xt"), ct.c_void_p(_stream_ptr(stream)))
+        _lib.check(rc, "rbicg_rbilu_solution")
+        return x, xt
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbicg_rbilu_destroy(self.h)
+            self.h = None
+        if getattr(self, "black", None) is not None:
+            self.black.close()
+            self.black = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_split_sequence(mats, bs, bts, *, k=20, s=40, tol=1e-8, maxit=10000, **opts):
+    """Split-preconditioned RBiCG over a sequence of dual pairs (Sec. 6): each
+    matrix gets its red-black ILU(0) preconditioner, one handle solves the
+    black systems in order (recycle spaces of the preconditioned systems,
+    carried and updated between them).  bs, bts: CUDA tensors.  Returns a list
+    of (x, x~, stats) with stats of the black solves."""
+    out, S, prev = [], None, None
+    try:
+        for j, A in enumerate(mats):
+            P = RBILU(A)
+            if S is None:
+                S = Solver(P.black, k=k, s=s, maxit=maxit, **opts)
+            else:
+                S.update_recycle(P.black)
+            bB, cB = P.rhs(bs[j], bts[j], stream=S.stream)
+            yB, ytB, st = S.solve(bB, cB, tol=tol)
+            x, xt = P.solution(bs[j], bts[j], yB, ytB, stream=S.stream)
+            out.append((x, xt, st))
+            if prev is not None:
+                S.stream.synchronize()
+                prev.close()
+            prev = P
+    finally:
+        if S is not None:
+            S.stream.synchronize()
+            S.close()
+        if prev is not None:
+            prev.close()
+    return out
+
+
 class Solver:
     """One handle: a matrix (and its explicit conjugate transpose), a recycle
     space and the device workspace, kept across the systems of a sequence.
