@@ -164,3 +164,64 @@ def test_cfg3_shifted_full_size():
             xts = np.asarray([complex(a, b_) for a, b_ in gs["xt_sample"][i]])
             assert np.linalg.norm(Xn[i][idx] - xs) / np.linalg.norm(xs) <= 1e-6
             assert np.linalg.norm(Xtn[i][idx] - xts) / np.linalg.norm(xts) <= 1e-6
+
+
+def test_cfg2_split_preconditioned_full_size():
+    """Red-black ILU(0) split preconditioning at 64^3 (first 3 systems of the
+    sequence): sampled entries of M_B v against the definition
+    M_B[i, j] = (delta_ij a_ii - sum_k a_ik a_kj / a_kk) / S_jj (S_jj the same
+    sum at (j, j)), and the solutions' true residuals."""
+    import scipy.sparse as sp
+    from paper_1010_0762_amd.solver import RBILU, Solver, solve_split_sequence
+    seq = wl.cfg2_sequence(nsys=3, N=64)
+    A = seq.mats[0]
+    As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    N = 64
+    idx = np.arange(A.n)
+    color = (idx % N + (idx // N) % N + idx // (N * N)) % 2
+    black = np.flatnonzero(color == 1)
+    bpos = -np.ones(A.n, dtype=np.int64)
+    bpos[black] = np.arange(black.size)
+    diag = As.diagonal()
+
+    def s_entry(i, j):   # S_ij over original indices i, j (both black)
+        v = diag[i] if i == j else 0.0
+        for k, aik in zip(As.indices[As.indptr[i]:As.indptr[i + 1]],
+                          As.data[As.indptr[i]:As.indptr[i + 1]]):
+            if k == i:
+                continue
+            akj = As[k, j]
+            v -= aik * akj / diag[k]
+        return v
+
+    P = RBILU(A)
+    assert P.nb == black.size
+    rng = np.random.default_rng(12)
+    v = rng.standard_normal(P.nb)
+    rows = rng.choice(P.nb, 6, replace=False)
+    X = np.zeros((6, P.nb), np.complex128)
+    X[0] = v
+    Xt = np.zeros((6, P.nb), np.complex128)
+    Xt[np.arange(6), rows] = 1.0
+    S = Solver(P.black, k=0, s=40, prec="c128")
+    G, _ = S.project(torch.as_tensor(X, device="cuda"), torch.as_tensor(Xt, device="cuda"))
+    for a, bi in enumerate(rows):
+        i = black[bi]
+        # black neighbours of i within two steps
+        js = set()
+        for k in As.indices[As.indptr[i]:As.indptr[i + 1]]:
+            js.update(As.indices[As.indptr[k]:As.indptr[k + 1]])
+        js = [j for j in js if color[j] == 1]
+        ref = sum(s_entry(i, j) / s_entry(j, j) * v[bpos[j]] for j in js)
+        assert abs(G[a, 0] - ref) <= 1e-12 * max(1.0, abs(ref))
+    S.close()
+    P.close()
+    b = torch.as_tensor(seq.b[0], device="cuda")
+    bt = torch.as_tensor(seq.bt[0], device="cuda")
+    out = solve_split_sequence(seq.mats, [b] * 3, [bt] * 3, k=20, s=40, tol=1e-8)
+    bh, bth = seq.b[0], seq.bt[0]
+    for Aj, (x, xt, st) in zip(seq.mats, out):
+        Aj = sp.csr_matrix((Aj.vals, Aj.colind, Aj.rowptr), shape=(Aj.n, Aj.n))
+        assert st["status"] == 0 and st["iters"] < 200
+        assert np.linalg.norm(bh - Aj @ x.cpu().numpy()) <= 1e-7 * np.linalg.norm(bh)
+        assert np.linalg.norm(bth - Aj.T @ xt.cpu().numpy()) <= 1e-7 * np.linalg.norm(bth)
