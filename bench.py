@@ -133,26 +133,34 @@ def precond_leg(args, seq, mats, b, bt):
     """The benchmark's 10-system 64^3 sequence split-preconditioned as in
     Sec. 6, with ILU(0) in red-black ordering: RBiCG (k = 20, s = 40) on the
     black blocks of the preconditioned operators, recycling between them,
-    tolerance 1e-8 on the preconditioned residual.  The 10 preconditioners
-    are set up once (host colouring, pivots and Schur block, then upload;
-    timed separately), then one pass over the sequence (right-hand-side
-    transform, solve, solution transform per system) is timed after an
-    untimed one.  True residuals of the original pairs are checked after
-    the timed pass."""
+    tolerance 1e-8 on the preconditioned residual.  The host set-up
+    (colouring, pattern of the Schur block, maps) runs once for the
+    sequence's pattern and is timed apart, and the matrices' values are
+    resident on the device beforehand (as the other legs preload their
+    matrices); inside the timed pass every system takes its preconditioner
+    by a device refresh from its values (pivots, Schur block), then the right-hand-side
+    transform, the solve and the solution transform.  One pass is timed after
+    an untimed one; true residuals of the original pairs are checked after
+    it."""
     import torch
     import scipy.sparse as sp
     from paper_1010_0762_amd.solver import RBILU, Solver
     t0 = time.perf_counter()
-    Ps = [RBILU(A) for A in seq.mats]
-    setup_ms = (time.perf_counter() - t0) * 1e3 / len(Ps)
-    S = Solver(Ps[0].black, k=seq.k, s=seq.s, chunk=args.chunk)
+    P = RBILU(seq.mats[0])
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    S = Solver(P.black, k=seq.k, s=seq.s, chunk=args.chunk)
+    # the matrices' values resident on the device beforehand, as the other
+    # legs preload their matrices
+    vals = [torch.as_tensor(A.vals, device="cuda") for A in seq.mats]
     sols = []
 
     def one_pass():
         its = []
         sols.clear()
         S.set_recycle(None, None)
-        for j, P in enumerate(Ps):
+        for j, A in enumerate(seq.mats):
+            S.stream.synchronize()
+            P.refresh_values(vals[j], stream=S.stream)
             S.update_recycle(P.black)
             bB, cB = P.rhs(b, bt, stream=S.stream)
             yB, ytB, st = S.solve(bB, cB, tol=seq.tol)
@@ -172,13 +180,13 @@ def precond_leg(args, seq, mats, b, bt):
         As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
         rel.append(max(np.linalg.norm(bh - As @ x.cpu().numpy()) / np.linalg.norm(bh),
                        np.linalg.norm(bth - As.T @ xt.cpu().numpy()) / np.linalg.norm(bth)))
+    nb = P.nb
     S.close()
-    for P in Ps:
-        P.close()
+    P.close()
     return {"workload": "convdiff3d_64^3_seq10_k20_s40_tol1e-8_split_rb_ilu0",
-            "black_unknowns": Ps[0].nb if Ps else 0,
+            "black_unknowns": nb,
             "solves_per_s": round(len(mats) / dt, 3), "ms_per_sequence": round(dt * 1e3, 2),
-            "setup_ms_per_system": round(setup_ms, 1), "iters_per_system": its,
+            "host_setup_ms_once": round(setup_ms, 1), "iters_per_system": its,
             "us_per_iter": round(dt / max(1, sum(its)) * 1e6, 2),
             "max_true_relres": float(max(rel))}
 

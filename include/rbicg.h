@@ -170,16 +170,30 @@ int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double *alpha, con
  * the transforms below.
  *   rbicg_rbilu_create: host set-up from A (host or device CSR, real or
  *     complex): *out (the transforms' device data), *black (M_B and M_B^H,
- *     resident; free with rbicg_matrix_destroy) and *nb (its order).
- *     RBICG_EINVAL if A has a zero diagonal entry or zero pivot or its
- *     off-diagonal graph is not two-colourable.
+ *     resident, owned by *out: valid until rbicg_rbilu_destroy, never passed
+ *     to rbicg_matrix_destroy) and *nb (its order).  RBICG_EINVAL if A has a
+ *     zero diagonal entry or zero pivot or its off-diagonal graph is not
+ *     two-colourable.
+ *   rbicg_rbilu_refresh: new values of A (A_next: same pattern, host or
+ *     device CSR) -- the pivots and M_B (in place in *black) recomputed on
+ *     the device on `stream`, so that a sequence of matrices on one pattern
+ *     (eq. initialSys) needs one host set-up; handles on *black then take
+ *     rbicg_update_recycle_on(h, black) (C = M_B U).  The pattern is compared
+ *     on the host (a device A_next is copied back for that).  RBICG_EINVAL if
+ *     the pattern, size or value type differ.
+ *   rbicg_rbilu_refresh_values: the same from a device array of the new
+ *     values alone, in the order of the CSR given at creation (the caller
+ *     guarantees the pattern; nothing is checked).
  *   rbicg_rbilu_rhs: b^_B, c^_B (nb entries each) from b, b~ (n entries).
  *   rbicg_rbilu_solution: x, x~ (n entries) from y_B, y~_B and b, b~.
  * Vectors are device arrays of A's value type (double or interleaved
  * complex), used on `stream`; calls on one preconditioner must not overlap
- * (they share a scratch vector).  Free with rbicg_rbilu_destroy. */
+ * (they share a scratch vector).  Free with rbicg_rbilu_destroy (which also
+ * frees *black; no handle may still use it). */
 typedef struct rbicg_rbilu_s *rbicg_rbilu;
 int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_matrix *black, int32_t *nb);
+int rbicg_rbilu_refresh(rbicg_rbilu P, const rbicg_csr *A_next, void *stream);
+int rbicg_rbilu_refresh_values(rbicg_rbilu P, const void *values, void *stream);
 int rbicg_rbilu_rhs(rbicg_rbilu P, const void *b, const void *bt, void *bB, void *btB, void *stream);
 int rbicg_rbilu_solution(rbicg_rbilu P, const void *b, const void *bt, const void *yB,
                          const void *ytB, void *x, void *xt, void *stream);

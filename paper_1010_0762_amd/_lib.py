@@ -73,6 +73,8 @@ SIGNATURES = {
     "rbicg_rbilu_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(_P), ct.POINTER(_P),
                                       ct.POINTER(ct.c_int32)]),
     "rbicg_rbilu_rhs": (ct.c_int, [_P, _P, _P, _P, _P, _P]),
+    "rbicg_rbilu_refresh": (ct.c_int, [_P, ct.POINTER(rbicg_csr), _P]),
+    "rbicg_rbilu_refresh_values": (ct.c_int, [_P, _P, _P]),
     "rbicg_rbilu_solution": (ct.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "rbicg_rbilu_destroy": (ct.c_int, [_P]),
     "rbicg_create_on": (ct.c_int, [_P, ct.POINTER(rbicg_opts), ct.POINTER(_P)]),

@@ -107,6 +107,20 @@ struct RbDev {
   const int *rp = nullptr, *ci = nullptr, *hrp = nullptr, *hci = nullptr, *bidx = nullptr;
   const void *av = nullptr, *hv = nullptr, *d = nullptr, *sb = nullptr;
 };
+// Maps of the device refresh (new values of A on the same pattern): amap[e]
+// the A^H entry of A's entry e, blist the original index of each black
+// unknown, M_B's CSR pattern (mrp, mci, black numbering; nnzm entries) and
+// the sliced-ELL positions of its entries in M_B (msell) and M_B^H (mhsell),
+// whose value arrays are mval, mhval.
+struct RbRefresh {
+  int nnzm = 0;
+  const int *amap = nullptr, *blist = nullptr, *mrp = nullptr, *mci = nullptr;
+  const int *msell = nullptr, *mhsell = nullptr;
+  void *mval = nullptr, *mhval = nullptr;
+};
+// from P.av (new values of A): A^H values, d, the black pivots and M_B
+template <class V>
+void launch_rb_refresh(hipStream_t st, const RbDev &P, const RbRefresh &R);
 // b^_B, c^_B (length nb) from b, b~ (length n); cR: n-long scratch
 template <class V>
 void launch_rb_rhs(hipStream_t st, const RbDev &P, const V *b, const V *bt, V *bB, V *cB, V *cR);

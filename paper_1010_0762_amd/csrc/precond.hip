@@ -12,7 +12,9 @@
 //   x_B[i]   = y_B[i] / S_B[i],   x_R[k] = (b_k - sum_j a_kj x_B[j]) / d_k
 //   x~_B[i]  = y~_B[i],           x~_R[k] = c^_R[k] - sum_j (A^H)_kj x~_B[j] / conj(d_k)
 // Each is one pass over CSR rows of A or A^H, one thread per unknown; they
-// run once per solve.
+// run once per solve.  For a new matrix on the same pattern the values of
+// A^H, the diagonal, the black pivots and the Schur block are recomputed on
+// the device (k_rbr_*), so that a sequence needs one host set-up.
 #include "kernels.h"
 
 namespace {
@@ -108,8 +110,93 @@ __global__ void k_rb_sol2(int n, const int *__restrict__ rp, const int *__restri
   xt[k] = divv(subv(bt[k], t), dc);
 }
 
+// ---- device refresh for new values of A on the same pattern ----
+// (the sums run in the order of the host set-up: the diagonal first, then
+// the red neighbours k of i in row order, each term (a_ik / d_k) a_kj)
+
+template <class V>
+__device__ __forceinline__ V rb_entry(const int *__restrict__ rp, const int *__restrict__ ci,
+                                      const V *__restrict__ av, int k, int j) {
+  V v = zerov<V>();
+  for (int e = rp[k]; e < rp[k + 1]; ++e)
+    if (ci[e] == j) v = addv(v, av[e]);
+  return v;
+}
+
+// A^H values and the diagonal
+template <class V>
+__global__ void k_rbr_prep(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const V *__restrict__ av, const int *__restrict__ amap,
+                           V *__restrict__ hv, V *__restrict__ d) {
+  const int i = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  V s = zerov<V>();
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    hv[amap[e]] = conjv(av[e]);
+    if (ci[e] == i) s = addv(s, av[e]);
+  }
+  d[i] = s;
+}
+
+// black pivots S_B = d_i - sum_k (a_ik / d_k) a_ki
+template <class V>
+__global__ void k_rbr_pivot(int nb, const int *__restrict__ blist, const int *__restrict__ rp,
+                            const int *__restrict__ ci, const V *__restrict__ av,
+                            const V *__restrict__ d, V *__restrict__ sb) {
+  const int bi = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (bi >= nb) return;
+  const int i = blist[bi];
+  V s = d[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int k = ci[e];
+    if (k == i) continue;
+    s = subv(s, mulv(divv(av[e], d[k]), rb_entry(rp, ci, av, k, i)));
+  }
+  sb[bi] = s;
+}
+
+// M_B entries (d_i delta_ij - sum_k (a_ik / d_k) a_kj) / S_B[j] into the
+// sliced-ELL values of M_B and (conjugated) of M_B^H
+template <class V>
+__global__ void k_rbr_schur(int nb, const int *__restrict__ blist, const int *__restrict__ mrp,
+                            const int *__restrict__ mci, const int *__restrict__ rp,
+                            const int *__restrict__ ci, const V *__restrict__ av,
+                            const V *__restrict__ d, const V *__restrict__ sb,
+                            const int *__restrict__ msell, const int *__restrict__ mhsell,
+                            V *__restrict__ mval, V *__restrict__ mhval) {
+  const int bi = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (bi >= nb) return;
+  const int i = blist[bi];
+  for (int e = mrp[bi]; e < mrp[bi + 1]; ++e) {
+    const int bj = mci[e], j = blist[bj];
+    V v = bj == bi ? d[i] : zerov<V>();
+    for (int g = rp[i]; g < rp[i + 1]; ++g) {
+      const int k = ci[g];
+      if (k == i) continue;
+      v = subv(v, mulv(divv(av[g], d[k]), rb_entry(rp, ci, av, k, j)));
+    }
+    v = divv(v, sb[bj]);
+    mval[msell[e]] = v;
+    mhval[mhsell[e]] = conjv(v);
+  }
+}
+
 namespace {
 inline unsigned rb_blocks(int n) { return (unsigned)((n + RBICG_BLOCK - 1) / RBICG_BLOCK); }
+}
+
+template <class V>
+void launch_rb_refresh(hipStream_t st, const RbDev &P, const RbRefresh &R) {
+  V *hv = (V *)const_cast<void *>(P.hv), *d = (V *)const_cast<void *>(P.d);
+  V *sb = (V *)const_cast<void *>(P.sb);
+  const V *av = (const V *)P.av;
+  hipLaunchKernelGGL((k_rbr_prep<V>), dim3(rb_blocks(P.n)), dim3(RBICG_BLOCK), 0, st, P.n, P.rp,
+                     P.ci, av, R.amap, hv, d);
+  hipLaunchKernelGGL((k_rbr_pivot<V>), dim3(rb_blocks(P.nb)), dim3(RBICG_BLOCK), 0, st, P.nb,
+                     R.blist, P.rp, P.ci, av, (const V *)d, sb);
+  hipLaunchKernelGGL((k_rbr_schur<V>), dim3(rb_blocks(P.nb)), dim3(RBICG_BLOCK), 0, st, P.nb,
+                     R.blist, R.mrp, R.mci, P.rp, P.ci, av, (const V *)d, (const V *)sb, R.msell,
+                     R.mhsell, (V *)R.mval, (V *)R.mhval);
 }
 
 template <class V>
@@ -139,3 +226,5 @@ template void launch_rb_solution<double>(hipStream_t, const RbDev &, const doubl
                                          double *);
 template void launch_rb_solution<cd>(hipStream_t, const RbDev &, const cd *, const cd *,
                                      const cd *, const cd *, cd *, cd *);
+template void launch_rb_refresh<double>(hipStream_t, const RbDev &, const RbRefresh &);
+template void launch_rb_refresh<cd>(hipStream_t, const RbDev &, const RbRefresh &);

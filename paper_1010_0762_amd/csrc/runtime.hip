@@ -146,7 +146,12 @@ int read_csr(const rbicg_csr *A, HostCsr &out) {
 }
 
 // Conjugate transpose by a counting sort over columns (O(nnz)).
-HostCsr conj_transpose(const HostCsr &A) {
+// Conjugate transpose by a counting sort over columns (O(nnz)); with map,
+// map[e] is the entry of the result that entry e of A became.
+HostCsr conj_transpose_map(const HostCsr &A, std::vector<int> *map);
+HostCsr conj_transpose(const HostCsr &A) { return conj_transpose_map(A, nullptr); }
+HostCsr conj_transpose_map(const HostCsr &A, std::vector<int> *map) {
+  if (map) map->assign(A.col.size(), 0);
   HostCsr T;
   T.n = A.n;
   T.complex_vals = A.complex_vals;
@@ -162,8 +167,28 @@ HostCsr conj_transpose(const HostCsr &A) {
       const int d = fill[c]++;
       T.col[d] = i;
       T.val[d] = std::conj(A.val[e]);
+      if (map) (*map)[e] = d;
     }
   return T;
+}
+
+// Position in the wave-sliced ELL layout of upload_sell of every CSR entry
+// of A (entry j of row r at slice(r) + j 64 + r mod 64).
+std::vector<int> sell_index(const HostCsr &A) {
+  const int n = A.n;
+  const int ns = (n + RBICG_WAVE - 1) / RBICG_WAVE;
+  std::vector<int> idx(A.col.size());
+  int base = 0;
+  for (int s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int r = s * RBICG_WAVE; r < std::min(n, (s + 1) * RBICG_WAVE); ++r)
+      w = std::max(w, A.rowptr[r + 1] - A.rowptr[r]);
+    for (int r = s * RBICG_WAVE; r < std::min(n, (s + 1) * RBICG_WAVE); ++r)
+      for (int e = A.rowptr[r]; e < A.rowptr[r + 1]; ++e)
+        idx[e] = base + (e - A.rowptr[r]) * RBICG_WAVE + (r - s * RBICG_WAVE);
+    base += w * RBICG_WAVE;
+  }
+  return idx;
 }
 
 // Repack CSR into the wave-sliced ELL layout and upload.  vkind: 0 double,
@@ -2105,10 +2130,18 @@ struct rbicg_rbilu_s {
   int n = 0, nb = 0;
   bool complex_vals = false;
   RbDev dev;
+  RbRefresh ref;                  // device maps of rbicg_rbilu_refresh
+  std::vector<int> rowptr, col;   // A's pattern, for the refresh's check
+  rbicg_mat_s *black = nullptr;   // M_B and M_B^H (owned)
   void *cR = nullptr;  // n-long scratch of the right-hand-side transform
   std::vector<void *> allocs;
   ~rbicg_rbilu_s() {
     for (void *p : allocs) (void)hipFree(p);
+    if (black) {
+      black->A.release();
+      black->AH.release();
+      delete black;
+    }
   }
 };
 
@@ -2149,7 +2182,8 @@ extern "C" int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_ma
   HostCsr hA;
   TRY(read_csr(A, hA));
   const int n = hA.n;
-  const HostCsr hAH = conj_transpose(hA);
+  std::vector<int> amap;
+  const HostCsr hAH = conj_transpose_map(hA, &amap);
   std::vector<cplx> d(n, cplx(0.0, 0.0));
   for (int i = 0; i < n; ++i)
     for (int e = hA.rowptr[i]; e < hA.rowptr[i + 1]; ++e)
@@ -2235,8 +2269,16 @@ extern "C" int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_ma
   rbicg_mat_s *m = new rbicg_mat_s();
   m->n = nbk;
   m->complex_vals = hS.complex_vals;
+  std::vector<int> smap;
+  const HostCsr hSH = conj_transpose_map(hS, &smap);
+  const std::vector<int> sidx = sell_index(hS), shidx = sell_index(hSH);
+  std::vector<int> msell(hS.col.size()), mhsell(hS.col.size());
+  for (size_t e = 0; e < hS.col.size(); ++e) {
+    msell[e] = sidx[e];
+    mhsell[e] = shidx[smap[e]];
+  }
   int rc = upload_sell(hS, m->complex_vals ? 1 : 0, m->A);
-  if (rc >= 0) rc = upload_sell(conj_transpose(hS), m->complex_vals ? 1 : 0, m->AH);
+  if (rc >= 0) rc = upload_sell(hSH, m->complex_vals ? 1 : 0, m->AH);
   if (rc < 0) {
     m->A.release();
     m->AH.release();
@@ -2265,16 +2307,69 @@ extern "C" int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_ma
     rc = rb_upload_vals(P, &z, zero);
     P->cR = const_cast<void *>(z);
   }
+  // maps of the device refresh
+  P->ref.nnzm = (int)hS.col.size();
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.amap, amap.data(), amap.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.blist, blist.data(), blist.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.mrp, hS.rowptr.data(), hS.rowptr.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.mci, hS.col.data(), hS.col.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.msell, msell.data(), msell.size());
+  if (rc >= 0) rc = rb_upload(P, (const void **)&P->ref.mhsell, mhsell.data(), mhsell.size());
+  P->ref.mval = m->A.val;
+  P->ref.mhval = m->AH.val;
+  P->rowptr = hA.rowptr;
+  P->col = hA.col;
+  P->black = m;
   if (rc < 0) {
     delete P;
-    m->A.release();
-    m->AH.release();
-    delete m;
     return rc;
   }
   *out = P;
   *black = m;
   *nb = nbk;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_rbilu_refresh(rbicg_rbilu P, const rbicg_csr *A_next, void *stream) {
+  if (!P || !A_next) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (A_next->n != P->n || A_next->nnz != (int64_t)P->col.size() ||
+      (A_next->values_complex != 0) != P->complex_vals)
+    return rbicg_fail(RBICG_EINVAL, "A_next does not match the preconditioner's matrix");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nnz = P->col.size();
+  bool same;
+  if (A_next->on_device) {
+    std::vector<int> rp(P->n + 1), ci(nnz);
+    HIPCHECK(hipMemcpy(rp.data(), A_next->rowptr, rp.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (nnz) HIPCHECK(hipMemcpy(ci.data(), A_next->colind, nnz * sizeof(int), hipMemcpyDeviceToHost));
+    same = rp == P->rowptr && ci == P->col;
+  } else {
+    same = std::memcmp(A_next->rowptr, P->rowptr.data(), P->rowptr.size() * sizeof(int)) == 0 &&
+           (nnz == 0 || std::memcmp(A_next->colind, P->col.data(), nnz * sizeof(int)) == 0);
+  }
+  if (!same)
+    return rbicg_fail(RBICG_EINVAL, "A_next's sparsity pattern differs from the preconditioner's");
+  const size_t vb = P->complex_vals ? sizeof(cd) : sizeof(double);
+  if (nnz)
+    HIPCHECK(hipMemcpyAsync(const_cast<void *>(P->dev.av), A_next->values, nnz * vb,
+                            A_next->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (P->complex_vals) launch_rb_refresh<cd>(st, P->dev, P->ref);
+  else launch_rb_refresh<double>(st, P->dev, P->ref);
+  HIPCHECK(hipGetLastError());
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_rbilu_refresh_values(rbicg_rbilu P, const void *values, void *stream) {
+  if (!P || !values) return rbicg_fail(RBICG_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nnz = P->col.size();
+  const size_t vb = P->complex_vals ? sizeof(cd) : sizeof(double);
+  if (nnz)
+    HIPCHECK(hipMemcpyAsync(const_cast<void *>(P->dev.av), values, nnz * vb,
+                            hipMemcpyDeviceToDevice, st));
+  if (P->complex_vals) launch_rb_refresh<cd>(st, P->dev, P->ref);
+  else launch_rb_refresh<double>(st, P->dev, P->ref);
+  HIPCHECK(hipGetLastError());
   return RBICG_OK;
 }
 

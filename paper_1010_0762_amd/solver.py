@@ -120,6 +120,26 @@ class RBILU:
             raise TypeError(f"{name} must be a contiguous CUDA {self.dtype} tensor of length {n}")
         return ct.c_void_p(v.data_ptr())
 
+    def refresh(self, A_next, stream=None):
+        """New values of the matrix (same pattern): pivots and M_B recomputed
+        on the device in place (rbicg_rbilu_refresh); handles on ``black``
+        then need update_recycle(black)."""
+        keep = []
+        a = _csr_struct(A_next, keep)
+        rc = self.lib.rbicg_rbilu_refresh(self.h, ct.byref(a), ct.c_void_p(_stream_ptr(stream)))
+        _lib.check(rc, "rbicg_rbilu_refresh")
+
+    def refresh_values(self, values, stream=None):
+        """As refresh, from a CUDA tensor of the new values in the order of
+        the CSR given at creation (rbicg_rbilu_refresh_values; the pattern is
+        the caller's guarantee)."""
+        if not (isinstance(values, torch.Tensor) and values.is_cuda and values.dtype == self.dtype
+                and values.is_contiguous()):
+            raise TypeError(f"values must be a contiguous CUDA {self.dtype} tensor")
+        rc = self.lib.rbicg_rbilu_refresh_values(self.h, ct.c_void_p(values.data_ptr()),
+                                                 ct.c_void_p(_stream_ptr(stream)))
+        _lib.check(rc, "rbicg_rbilu_refresh_values")
+
     def rhs(self, b, bt, stream=None):
         """(b^_B, c^_B) of the black system."""
         bB = torch.empty(self.nb, dtype=self.dtype, device="cuda")
@@ -142,12 +162,12 @@ class RBILU:
         return x, xt
 
     def close(self):
+        if getattr(self, "black", None) is not None:
+            self.black.h = None   # owned by the preconditioner
+            self.black = None
         if getattr(self, "h", None):
             self.lib.rbicg_rbilu_destroy(self.h)
             self.h = None
-        if getattr(self, "black", None) is not None:
-            self.black.close()
-            self.black = None
 
     def __del__(self):
         try:
@@ -160,30 +180,39 @@ def solve_split_sequence(mats, bs, bts, *, k=20, s=40, tol=1e-8, maxit=10000, **
     """Split-preconditioned RBiCG over a sequence of dual pairs (Sec. 6): each
     matrix gets its red-black ILU(0) preconditioner, one handle solves the
     black systems in order (recycle spaces of the preconditioned systems,
-    carried and updated between them).  bs, bts: CUDA tensors.  Returns a list
-    of (x, x~, stats) with stats of the black solves."""
-    out, S, prev = [], None, None
+    carried and updated between them).  Matrices on one pattern reuse the
+    first set-up and refresh the values on the device.  bs, bts: CUDA
+    tensors.  Returns a list of (x, x~, stats) with stats of the black solves."""
+    out, S, P = [], None, None
     try:
         for j, A in enumerate(mats):
-            P = RBILU(A)
-            if S is None:
+            if P is None:
+                P = RBILU(A)
                 S = Solver(P.black, k=k, s=s, maxit=maxit, **opts)
             else:
-                S.update_recycle(P.black)
+                S.stream.synchronize()   # the previous solve no longer reads M_B
+                try:
+                    P.refresh(A, stream=S.stream)
+                except _lib.RBiCGError as e:
+                    if e.code != _lib.RBICG_EINVAL:
+                        raise
+                    # another pattern: a new set-up (the handle moves to it)
+                    Pn = RBILU(A)
+                    S.update_recycle(Pn.black)
+                    P.close()
+                    P = Pn
+                else:
+                    S.update_recycle(P.black)
             bB, cB = P.rhs(bs[j], bts[j], stream=S.stream)
             yB, ytB, st = S.solve(bB, cB, tol=tol)
             x, xt = P.solution(bs[j], bts[j], yB, ytB, stream=S.stream)
             out.append((x, xt, st))
-            if prev is not None:
-                S.stream.synchronize()
-                prev.close()
-            prev = P
     finally:
         if S is not None:
             S.stream.synchronize()
             S.close()
-        if prev is not None:
-            prev.close()
+        if P is not None:
+            P.close()
     return out
 
 

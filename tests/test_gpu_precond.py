@@ -99,3 +99,47 @@ def test_rbilu_refuses_odd_cycles():
     T = sp.csr_matrix(np.array([[4.0, 1, 1], [1, 4, 1], [1, 1, 4]]))
     with pytest.raises(RBiCGError):
         RBILU(T)
+
+
+def test_refresh_matches_fresh_setup():
+    """New values on the same pattern, recomputed on the device, against a
+    fresh host set-up of the new matrix; another pattern is refused."""
+    from paper_1010_0762_amd.solver import RBILU, Solver
+    from paper_1010_0762_amd._lib import RBiCGError
+    A0 = wl.convdiff(7, 3, [20.0, 10.0, 5.0])
+    A1 = wl.convdiff(7, 3, [23.0, 9.0, 6.5])
+    P = RBILU(A0)
+    P.refresh(A1)
+    Q = RBILU(A1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    m = 3
+    X = (rng.standard_normal((m, P.nb)) + 0j).astype(np.complex128)
+    Xt = (rng.standard_normal((m, P.nb)) + 0j).astype(np.complex128)
+    SP = Solver(P.black, k=0, s=40, prec="c128")
+    SQ = Solver(Q.black, k=0, s=40, prec="c128")
+    GP, _ = SP.project(_t(X), _t(Xt))
+    GQ, _ = SQ.project(_t(X), _t(Xt))
+    assert np.allclose(GP, GQ, rtol=1e-13, atol=1e-12 * np.abs(GQ).max())
+    b, bt = rng.standard_normal(A1.n), rng.standard_normal(A1.n)
+    (u, v), (uq, vq) = P.rhs(_t(b), _t(bt)), Q.rhs(_t(b), _t(bt))
+    assert np.allclose(u.cpu().numpy(), uq.cpu().numpy(), rtol=1e-13, atol=1e-13)
+    assert np.allclose(v.cpu().numpy(), vq.cpu().numpy(), rtol=1e-13, atol=1e-13)
+    yB, ytB = _t(rng.standard_normal(P.nb)), _t(rng.standard_normal(P.nb))
+    xp, xtp = P.solution(_t(b), _t(bt), yB, ytB)
+    xq, xtq = Q.solution(_t(b), _t(bt), yB, ytB)
+    assert np.allclose(xp.cpu().numpy(), xq.cpu().numpy(), rtol=1e-13, atol=1e-13)
+    assert np.allclose(xtp.cpu().numpy(), xtq.cpu().numpy(), rtol=1e-13, atol=1e-13)
+    with pytest.raises(RBiCGError):
+        P.refresh(wl.aniso_diffusion(6))
+    # the values-only form gives the same block
+    P2 = RBILU(A0)
+    P2.refresh_values(_t(A1.vals))
+    torch.cuda.synchronize()
+    S2 = Solver(P2.black, k=0, s=40, prec="c128")
+    G2, _ = S2.project(_t(X), _t(Xt))
+    assert np.array_equal(G2, GP)
+    for h in (SP, SQ, S2):
+        h.close()
+    for h in (P, Q, P2):
+        h.close()
