@@ -1507,10 +1507,21 @@ __global__ __launch_bounds__(256) void k_sh_coef(const double *__restrict__ G, i
         const double *zc = side ? Sh->zct[s] : Sh->zc[s];
         v = cd{zc[2 * l], zc[2 * l + 1]};
       } else {
+        // 8 terms at a time, their loads issued together (a term-by-term
+        // loop waits out one cache round trip per term)
         const double *Km = side ? Co->Kt[s] : Co->K[s];
-        for (int j = 0; j < k2; ++j) {
-          const size_t gi = side ? (size_t)g1 + (size_t)j * ld1 + s : (size_t)j * ld0 + s;
-          v += cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]} * cd{G[2 * gi], G[2 * gi + 1]};
+        for (int j0 = 0; j0 < k2; j0 += 8) {
+          cd kv[8], gv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u, k2 - 1);
+            const size_t gi = side ? (size_t)g1 + (size_t)j * ld1 + s : (size_t)j * ld0 + s;
+            kv[u] = cd{Km[2 * (l * k2 + j)], Km[2 * (l * k2 + j) + 1]};
+            gv[u] = cd{G[2 * gi], G[2 * gi + 1]};
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (j0 + u < k2) v += kv[u] * gv[u];
         }
       }
     }
