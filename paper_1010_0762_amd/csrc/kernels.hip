@@ -175,8 +175,18 @@ __device__ __forceinline__ void breduce(const double *P, int nb, int nv, double 
   const int G = min((int)blockDim.x / nv, 32);
   const int t = threadIdx.x, j = t % nv, g = t / nv;
   if (g < G) {
+    // the same sequential sum over b, with 8 loads issued at a time (a
+    // load-then-add loop waits out one cache round trip per partial)
     double s = 0.0;
-    for (int b = g; b < nb; b += G) s += P[(size_t)b * nv + j];
+    int b = g;
+    for (; b + 7 * G < nb; b += 8 * G) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = P[(size_t)(b + u * G) * nv + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < nb; b += G) s += P[(size_t)b * nv + j];
     tmp[g * nv + j] = s;
   }
   __syncthreads();
@@ -1135,6 +1145,17 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *partial, int 
   double s0 = 0.0, s1 = 0.0;
   if (e < count) {
     int c = sl;
+    // four steps' loads issued together, added in the same order
+    for (; c + 7 * L < nchunks; c += 8 * L) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(c + u * L) * count + e];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        s0 += v[u];
+        s1 += v[u + 1];
+      }
+    }
     for (; c + L < nchunks; c += 2 * L) {
       s0 += partial[(size_t)c * count + e];
       s1 += partial[(size_t)(c + L) * count + e];
