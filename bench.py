@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per completed k_it1 launch on this workload, from the FETCH_SIZE
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
 # 512 MiB device copy), valid only for the kernel source they were taken on
-TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "de42709d052d6e39", "bytes_per_launch": 99.37e6}
+TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "2336d9047df52277", "bytes_per_launch": 99.41e6}
 
 
 def traffic_k_it1():
