@@ -27,21 +27,30 @@ METRIC = "dual-system solves/sec + HBM GB/s per RBiCG iter; p50/p99 latency serv
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per completed k_it1 launch on this workload, from the FETCH_SIZE
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
-# 512 MiB device copy), valid only for the kernel source they were taken on
-TRAFFIC_K_IT1 = {"kernels_hip_sha256_16": "2336d9047df52277", "bytes_per_launch": 99.41e6}
+# 512 MiB device copy), valid only for the kernel source and the matrix
+# layout code (runtime.hip) they were taken on
+TRAFFIC_K_IT1 = {"sources_sha256_16": "cdc3af5ede9ad398", "bytes_per_launch": 89.59e6}
+TRAFFIC_SOURCES = ("kernels.hip", "runtime.hip")
+
+
+def sources_digest():
+    """sha256 prefix of the sources the k_it1 traffic depends on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1010_0762_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_k_it1():
-    """Counter-measured HBM bytes per k_it1 launch, or None once the kernel
-    source differs from the one the counters were taken on."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_1010_0762_amd", "csrc", "kernels.hip")
+    """Counter-measured HBM bytes per k_it1 launch, or None once the sources
+    differ from the ones the counters were taken on."""
     try:
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()[:16]
+        digest = sources_digest()
     except OSError:
         return None
-    if digest != TRAFFIC_K_IT1["kernels_hip_sha256_16"]:
+    if digest != TRAFFIC_K_IT1["sources_sha256_16"]:
         return None
     return TRAFFIC_K_IT1["bytes_per_launch"]
 

@@ -139,6 +139,15 @@ int rbicg_matrix_create(const rbicg_csr *A, const rbicg_csr *AH, rbicg_matrix *o
  * handle may still use it). */
 int rbicg_matrix_destroy(rbicg_matrix m);
 
+/* Layout of a resident matrix, into info[0..4] (host array of 5 int64):
+ * order n, stored entries nnz, entries of the padded sliced-ELL layout
+ * (64-row slices, each as wide as its longest row), 1 if A^H shares A's
+ * slice pointers and column indices (A^H has A's pattern with rows in the
+ * same column order, e.g. a structurally symmetric stencil with sorted rows;
+ * the iteration kernels then read the indices once per row), 1 if the values
+ * are complex.  RBICG_EINVAL for null arguments; no device work. */
+int rbicg_matrix_info(rbicg_matrix m, int64_t *info);
+
 /* The pencil P = alpha E + beta A of two resident matrices, with its
  * conjugate transpose conj(alpha) E^H + conj(beta) A^H: the shifted operators
  * sigma E - A (alpha = sigma, beta = -1) of IRKA with E != I (Algorithm 3,

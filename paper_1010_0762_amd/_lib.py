@@ -69,6 +69,7 @@ SIGNATURES = {
     "rbicg_matrix_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(rbicg_csr),
                                        ct.POINTER(_P)]),
     "rbicg_matrix_destroy": (ct.c_int, [_P]),
+    "rbicg_matrix_info": (ct.c_int, [_P, ct.POINTER(ct.c_int64)]),
     "rbicg_matrix_pencil": (ct.c_int, [_P, _P, _DP, _DP, _P, ct.POINTER(_P)]),
     "rbicg_rbilu_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(_P), ct.POINTER(_P),
                                       ct.POINTER(ct.c_int32)]),

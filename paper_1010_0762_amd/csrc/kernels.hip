@@ -332,6 +332,22 @@ __device__ __forceinline__ void row8_index(const Sell<M> &A, int row, Row8<V, M>
       L.v[j] = A.val[b0 + lane + RBICG_WAVE * j];
     }
 }
+// The same for a matrix whose slice pointers and column indices are those
+// of the matrix P was loaded from (a conjugate transpose that shares the
+// pattern): the indices are copied, only the values are loaded.
+template <class V, class M>
+__device__ __forceinline__ void row8_values(const Sell<M> &A, int row, const Row8<V, M> &P,
+                                            Row8<V, M> &L) {
+  const int slice = row >> 6, lane = row & 63;
+  const int b0 = A.sliceptr[slice];
+  L.w = P.w;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < L.w) {
+      L.c[j] = P.c[j];
+      L.v[j] = A.val[b0 + lane + RBICG_WAVE * j];
+    }
+}
 template <class V, class M>
 __device__ __forceinline__ void row8_gather(const V *r, const V *p, Row8<V, M> &L) {
 #pragma unroll
@@ -517,7 +533,8 @@ __global__ __launch_bounds__(IB) void k_it1(
       pre[2] = p[row0];
       pre[3] = pt[row0];
       row8_index(A, row0, LA);
-      row8_index(AH, row0, LB);
+      if (AH.col == A.col) row8_values(AH, row0, LA, LB);  // uniform branch
+      else row8_index(AH, row0, LB);
       fast = LA.w <= 8 && LB.w <= 8;
       if (fast) row8_gather(r, p, LA);
     }

@@ -66,6 +66,9 @@ struct DevSell {
   size_t nnzpad = 0;
   int64_t nnz = 0;
   int vbytes = 0;
+  // sliceptr and col belong to another DevSell of the same matrix object (a
+  // conjugate transpose with the matrix's own pattern) and are not freed here
+  bool borrowed = false;
   template <class M> Sell<M> view() const {
     Sell<M> s;
     s.n = n;
@@ -80,8 +83,9 @@ struct DevSell {
     return s;
   }
   void release() {
-    if (sliceptr) (void)hipFree(sliceptr);
-    if (col) (void)hipFree(col);
+    if (sliceptr && !borrowed) (void)hipFree(sliceptr);
+    if (col && !borrowed) (void)hipFree(col);
+    borrowed = false;
     if (val) (void)hipFree(val);
     if (val32) (void)hipFree(val32);
     sliceptr = nullptr;
@@ -254,6 +258,22 @@ int upload_sell(const HostCsr &A, int vkind, DevSell &D) {
   return 0;
 }
 
+// When the conjugate transpose has the matrix's own pattern (rows with the
+// same column indices in the same order, e.g. any structurally symmetric
+// stencil with sorted rows), its sliced-ELL slice pointers and column indices
+// equal the matrix's (upload_sell depends on rowptr and col only): keep one
+// copy, so that a pass over both reads the indices once.
+int share_pattern(const HostCsr &hA, const HostCsr &hAH, DevSell &A, DevSell &AH) {
+  if (hA.rowptr != hAH.rowptr || hA.col != hAH.col) return 0;
+  if (AH.nnzpad != A.nnzpad || AH.nslices != A.nslices) return 0;
+  HIPCHECK(hipFree(AH.sliceptr));
+  HIPCHECK(hipFree(AH.col));
+  AH.sliceptr = A.sliceptr;
+  AH.col = A.col;
+  AH.borrowed = true;
+  return 0;
+}
+
 }  // namespace
 
 // A device-resident matrix: A and its explicit conjugate transpose, repacked.
@@ -410,7 +430,10 @@ void kernel_bytes(const rbicg_s *h, int k, double out[2]) {
   const double ba = h->vkind == 2 ? 4.0 : (double)h->mat->A.vbytes;
   const double nnz = (double)h->mat->A.nnz, n = h->n, vb = (double)h->vb;
   const bool cap = h->opt.update && h->opt.k > 0;
-  out[0] = 2.0 * (nnz * (ba + 4.0) + 4.0 * (n + 1.0)) + (8.0 + 2.0 * k + (cap ? 4.0 : 0.0)) * n * vb;
+  // the index arrays once when A^H shares A's pattern
+  const double ix = h->mat->AH.borrowed ? 1.0 : 2.0;
+  out[0] = 2.0 * nnz * ba + ix * (4.0 * nnz + 4.0 * (n + 1.0)) +
+           (8.0 + 2.0 * k + (cap ? 4.0 : 0.0)) * n * vb;
   out[1] = (12.0 + 2.0 * k) * n * vb;
 }
 
@@ -1956,6 +1979,7 @@ int build_matrix(const rbicg_csr *A, const rbicg_csr *AH, rbicg_mat_s *m) {
   const int kind = m->complex_vals ? 1 : 0;
   TRY(upload_sell(hA, kind, m->A));
   TRY(upload_sell(hAH, kind, m->AH));
+  TRY(share_pattern(hA, hAH, m->A, m->AH));
   return 0;
 }
 
@@ -2068,13 +2092,21 @@ int same_layout(const DevSell &a, const DevSell &b) {
   return 0;
 }
 
-// A complex sliced-ELL matrix with src's layout (values uninitialized).
-int alloc_like(const DevSell &src, DevSell &d) {
+// A complex sliced-ELL matrix with src's layout (values uninitialized).  If
+// src borrows its layout, d borrows that of owner (the new matrix's own A).
+int alloc_like(const DevSell &src, DevSell &d, const DevSell *owner = nullptr) {
   d.n = src.n;
   d.nslices = src.nslices;
   d.nnzpad = src.nnzpad;
   d.nnz = src.nnz;
   d.vbytes = 16;
+  if (src.borrowed && owner) {
+    d.sliceptr = owner->sliceptr;
+    d.col = owner->col;
+    d.borrowed = true;
+    HIPCHECK(hipMalloc(&d.val, std::max<size_t>(src.nnzpad, 1) * sizeof(cd)));
+    return 0;
+  }
   HIPCHECK(hipMalloc((void **)&d.sliceptr, (size_t)(src.nslices + 1) * sizeof(int)));
   HIPCHECK(hipMalloc((void **)&d.col, std::max<size_t>(src.nnzpad, 1) * sizeof(int)));
   HIPCHECK(hipMalloc(&d.val, std::max<size_t>(src.nnzpad, 1) * sizeof(cd)));
@@ -2100,7 +2132,7 @@ extern "C" int rbicg_matrix_pencil(rbicg_matrix A, rbicg_matrix E, const double 
     m->pencil_a = A;
     m->pencil_e = E;
     int rc = alloc_like(A->A, m->A);
-    if (rc >= 0) rc = alloc_like(A->AH, m->AH);
+    if (rc >= 0) rc = alloc_like(A->AH, m->AH, &m->A);
     if (rc < 0) {
       m->A.release();
       m->AH.release();
@@ -2279,6 +2311,7 @@ extern "C" int rbicg_rbilu_create(const rbicg_csr *A, rbicg_rbilu *out, rbicg_ma
   }
   int rc = upload_sell(hS, m->complex_vals ? 1 : 0, m->A);
   if (rc >= 0) rc = upload_sell(hSH, m->complex_vals ? 1 : 0, m->AH);
+  if (rc >= 0) rc = share_pattern(hS, hSH, m->A, m->AH);
   if (rc < 0) {
     m->A.release();
     m->AH.release();
@@ -2413,6 +2446,16 @@ extern "C" int rbicg_matrix_destroy(rbicg_matrix m) {
   m->A.release();
   m->AH.release();
   delete m;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_matrix_info(rbicg_matrix m, int64_t *info) {
+  if (!m || !info) return rbicg_fail(RBICG_EINVAL, "null argument");
+  info[0] = m->n;
+  info[1] = m->A.nnz;
+  info[2] = (int64_t)m->A.nnzpad;
+  info[3] = m->AH.borrowed ? 1 : 0;
+  info[4] = m->complex_vals ? 1 : 0;
   return RBICG_OK;
 }
 

@@ -81,6 +81,13 @@ class DeviceMatrix:
         m.lib, m.h, m.n, m.complex = lib, h, A.n, True
         return m
 
+    def info(self) -> dict:
+        """Layout of the resident matrix (rbicg_matrix_info)."""
+        v = (ct.c_int64 * 5)()
+        _lib.check(self.lib.rbicg_matrix_info(self.h, v), "rbicg_matrix_info")
+        return {"n": v[0], "nnz": v[1], "nnz_padded": v[2], "shared_pattern": bool(v[3]),
+                "complex": bool(v[4])}
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.rbicg_matrix_destroy(self.h)
