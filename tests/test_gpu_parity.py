@@ -151,6 +151,17 @@ def test_layout_sharing_and_unshared_real_sequence():
     assert ic["shared_pattern"] and not ic["complex"]
     assert ic["n"] == Ac.n and ic["nnz"] == len(Ac.colind) and ic["nnz_padded"] >= ic["nnz"]
     mc.close()
+    # a pencil sigma E - A inherits the sharing; so does a red-black black block
+    from paper_1010_0762_amd.solver import RBILU
+    A5, E5 = DeviceMatrix(wl.aniso_diffusion(5)), DeviceMatrix(wl.mass_like(5))
+    P5 = DeviceMatrix.pencil(A5, E5, 2.0 + 1.0j)
+    ip = P5.info()
+    assert ip["shared_pattern"] and ip["complex"] and ip["nnz_padded"] == A5.info()["nnz_padded"]
+    for m in (P5, A5, E5):
+        m.close()
+    rb = RBILU(wl.convdiff(8, 3, [4.0, 2.0, 1.0]))
+    assert rb.black.info()["shared_pattern"]
+    rb.close()
     A = wl.random_sparse(700, 6, 33, 6.0)
     m = DeviceMatrix(A)
     assert not m.info()["shared_pattern"]
