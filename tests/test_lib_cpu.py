@@ -195,3 +195,13 @@ def test_host_eig_real_pencils_backward_error(seed):
     ref = ref[np.isfinite(ref) & (np.abs(ref) < 1e6)]
     for z in ref:
         assert np.min(np.abs(lam - z)) <= 1e-6 * max(1.0, abs(z))
+
+
+def test_matrix_info_rejects_null_arguments():
+    """rbicg_matrix_info is host-only: null arguments are RBICG_EINVAL with a
+    message, and no device call is made."""
+    lib = _lib.load()
+    info = (ct.c_int64 * 5)()
+    assert lib.rbicg_matrix_info(None, info) == _lib.RBICG_EINVAL
+    assert b"null" in lib.rbicg_last_error()
+    assert lib.rbicg_matrix_info(None, None) == _lib.RBICG_EINVAL
