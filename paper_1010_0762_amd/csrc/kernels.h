@@ -26,7 +26,7 @@ void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V
                 const double *P1, double *P3, Scalars *S, double *rec, int it, int rp);
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
-                  int first);
+                  int first, Scalars *hs);
 template <class V>
 void launch_init_p3(hipStream_t st, int nb, int n, const V *r, const V *rt, double *P3);
 // dots (a_i, b_i), i < 3, reduced into out[0 .. 3*ND)

@@ -797,13 +797,24 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
 // Stopping test after the last launched iteration (one block).
 template <class V>
 __global__ __launch_bounds__(IB) void k_itfin(const double *__restrict__ P3, int nb,
-                                              Scalars *S, double *rec, int it, int first) {
+                                              Scalars *S, double *rec, int it, int first,
+                                              Scalars *hs) {
   using T = typename Ar<V>::T;
-  if (S->done) return;
   __shared__ double tmp[IB];
   __shared__ double red[8];
-  T beta;
-  (void)it_prologue<T>(P3, nb, S, rec, it, first, tmp, red, beta);
+  // one block; only its thread 0 (the prologue's lead) writes S->done, after
+  // the prologue's barriers, so every wave reads the same value here
+  if (!S->done) {
+    T beta;
+    (void)it_prologue<T>(P3, nb, S, rec, it, first, tmp, red, beta);
+  }
+  // the stopping test's outcome straight into the host's slot (mapped host
+  // memory, read after the event recorded behind this launch completes)
+  if (threadIdx.x == 0) {
+    hs->done = S->done;
+    hs->status = S->status;
+    hs->iter = S->iter;
+  }
 }
 
 // P3-layout partials (||r||^2, ||r~||^2, (r~, r)) of the initial residuals.
@@ -1868,8 +1879,8 @@ void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V
 }
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
-                  int first) {
-  hipLaunchKernelGGL((k_itfin<V>), dim3(1), dim3(IB), 0, st, P3, nb, S, rec, it, first);
+                  int first, Scalars *hs) {
+  hipLaunchKernelGGL((k_itfin<V>), dim3(1), dim3(IB), 0, st, P3, nb, S, rec, it, first, hs);
 }
 template <class V>
 void launch_init_p3(hipStream_t st, int nb, int n, const V *r, const V *rt, double *P3) {
@@ -2080,7 +2091,7 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
                               const V *, const V *, const V *, const V *, const V *, int, int, \
                               const double *, double *, Scalars *, double *, int, int);      \
   template void launch_itfin<V>(hipStream_t, int, const double *, Scalars *, double *, int,  \
-                                int);                                                        \
+                                int, Scalars *);                                             \
   template void launch_init_p3<V>(hipStream_t, int, int, const V *, const V *, double *);    \
   template void launch_dots<V>(hipStream_t, int, int, const V *, const V *, const V *,       \
                                const V *, const V *, const V *, double *, double *);         \

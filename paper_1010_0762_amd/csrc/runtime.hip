@@ -366,6 +366,7 @@ struct rbicg_s {
   cd *Wd = nullptr;
   // pinned host staging
   Scalars *hS = nullptr;
+  Scalars *hSd = nullptr;  // device view of hS (k_itfin writes the stopping outcome there)
   double *hG = nullptr;
   cd *hW = nullptr;
   double *hlog = nullptr;
@@ -1228,9 +1229,11 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         }
         // stopping test of the chunk's last iteration, then its scalars to the host
         const int slot = slot_next % 2;
-        launch_itfin<V>(h->st, nb, h->P3, h->S, h->log, launched + 1, launched == run_start ? 1 : 0);
+        // (k_itfin writes done, status and iter into host slot `slot` itself; the
+        // event's completion makes them visible to the host)
+        launch_itfin<V>(h->st, nb, h->P3, h->S, h->log, launched + 1, launched == run_start ? 1 : 0,
+                        h->hSd + slot);
         HIPCHECK(hipGetLastError());
-        HIPCHECK(hipMemcpyAsync(&h->hS[slot], h->S, sizeof(Scalars), hipMemcpyDeviceToHost, h->st));
         HIPCHECK(hipEventRecord(h->sev[slot], h->st));
         flight.push_back({launched, slot, chunk_start, chunk, prof});
         ++slot_next;
@@ -1957,6 +1960,7 @@ int alloc_workspace(rbicg_s *h) {
     for (auto &e : h->pev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   HIPCHECK(hipHostMalloc((void **)&h->hS, 2 * sizeof(Scalars), hipHostMallocDefault));
+  HIPCHECK(hipHostGetDevicePointer((void **)&h->hSd, h->hS, 0));
   for (auto &e : h->sev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIPCHECK(hipHostMalloc((void **)&h->hG, (size_t)wx * wy * 2 * sizeof(double), hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&h->hW, 6 * RBICG_WSLOT * sizeof(cd), hipHostMallocDefault));
