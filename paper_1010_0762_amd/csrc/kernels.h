@@ -82,7 +82,7 @@ void launch_pencil(hipStream_t st, size_t m, const void *a, int acplx, const voi
 int sh_blocks(int n);      // blocks of k_sh2 (partials of P3)
 int sh_sub_blocks(int n);  // blocks of k_sh_sub
 void launch_sh_state(hipStream_t st, int S, const double *P3, int nb3, ShScalars *Sh, double *rec,
-                     int it, int first);
+                     int it, int first, ShScalars *hs = nullptr);
 template <class M>
 void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,
                 const cd *Rt, const cd *P, const cd *Pt, cd *Pn, cd *Ptn, cd *Z, cd *Zt,

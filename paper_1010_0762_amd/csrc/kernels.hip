@@ -1348,15 +1348,20 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V 
 
 // Block s: stopping test of iteration it-1 and beta_{it-1} for shift s of the
 // batch (act1, beta for k_sh1); records them in rec and, when the shift
-// stops, its status.  Also the final test after the last launched iteration.
+// stops, its status.  Also the final test after the last launched iteration;
+// that launch (hs != null) also writes every shift's done flag into the
+// host's slot hs (mapped host memory, read after the event behind it).
 __global__ __launch_bounds__(RBICG_BLOCK) void k_sh_state(const double *__restrict__ P3, int nb,
                                                           ShScalars *Sh, double *rec, int it,
-                                                          int first) {
+                                                          int first, ShScalars *hs) {
   __shared__ double tmp[RBICG_BLOCK];
   __shared__ double red[4];
   const int s = blockIdx.x;
   if (Sh->done[s]) {  // only this block writes done[s] in this launch
-    if (threadIdx.x == 0) Sh->act1[s] = 0;
+    if (threadIdx.x == 0) {
+      Sh->act1[s] = 0;
+      if (hs) hs->done[s] = 1;
+    }
     return;
   }
   breduce(P3 + (size_t)s * nb * 4, nb, 4, tmp, red);
@@ -1377,8 +1382,10 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sh_state(const double *__restri
     Sh->iter[s] = it - 1;
     Sh->done[s] = 1;
     Sh->act1[s] = 0;
+    if (hs) hs->done[s] = 1;
     return;
   }
+  if (hs) hs->done[s] = 0;
   cd b = {0.0, 0.0};
   if (!first) {
     const double *Rm2 = rec + ((size_t)(it - 2) * SHMAX + s) * SH_LOG;
@@ -2033,8 +2040,9 @@ int sh_blocks(int n) { return std::max(1, std::min(1024, (int)nblk((size_t)n)));
 int sh_sub_blocks(int n) { return std::max(1, std::min(256, ((n + 15) / 16 + 3) / 4)); }
 
 void launch_sh_state(hipStream_t st, int S, const double *P3, int nb3, ShScalars *Sh, double *rec,
-                     int it, int first) {
-  hipLaunchKernelGGL(k_sh_state, dim3(S), dim3(RBICG_BLOCK), 0, st, P3, nb3, Sh, rec, it, first);
+                     int it, int first, ShScalars *hs) {
+  hipLaunchKernelGGL(k_sh_state, dim3(S), dim3(RBICG_BLOCK), 0, st, P3, nb3, Sh, rec, it, first,
+                     hs);
 }
 template <class M>
 void launch_sh1(hipStream_t st, const Sell<M> &A, const Sell<M> &AH, int ld, const cd *R,

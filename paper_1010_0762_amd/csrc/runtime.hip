@@ -298,6 +298,7 @@ struct ShiftWs {
   size_t gpart_bytes = 0, G_bytes = 0;
   int reccap = 0;
   ShScalars *Sh = nullptr, *hSh = nullptr;
+  ShScalars *hShd = nullptr;  // device view of hSh (chunk-end done flags)
   ShCoef *Co = nullptr, *hCo = nullptr;
   double *hG = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1562,6 +1563,7 @@ int shift_ws(rbicg_s *h, int S) {
   TRY(al((void **)&w.Sh, sizeof(ShScalars)));
   TRY(al((void **)&w.Co, sizeof(ShCoef)));
   HIPCHECK(hipHostMalloc((void **)&w.hSh, 2 * sizeof(ShScalars), hipHostMallocDefault));
+  HIPCHECK(hipHostGetDevicePointer((void **)&w.hShd, w.hSh, 0));
   HIPCHECK(hipHostMalloc((void **)&w.hCo, sizeof(ShCoef), hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&w.hG, gmax * 2 * sizeof(double), hipHostMallocDefault));
   for (auto &e : w.ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1821,9 +1823,12 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
           pc = 1 - pc;
           ++launched;
         }
-        launch_sh_state(h->st, Sb, w.P3, nb3, w.Sh, w.rec, launched + 1, 0);
+        // the chunk's final stopping test writes every shift's done flag into
+        // host slot 1 itself; the two chunks in flight share the slot: the
+        // device's flags only become set, so a read after the older chunk's
+        // event sees that chunk's flags or newer ones
+        launch_sh_state(h->st, Sb, w.P3, nb3, w.Sh, w.rec, launched + 1, 0, w.hShd + 1);
         HIPCHECK(hipGetLastError());
-        HIPCHECK(hipMemcpyAsync(&w.hSh[1 + 0 * slot], w.Sh, sizeof(ShScalars), hipMemcpyDeviceToHost, h->st));
         HIPCHECK(hipEventRecord(w.ev[slot], h->st));
         flight.push_back(slot);
         slot = 1 - slot;
@@ -1832,10 +1837,10 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       const int sl = flight.front();
       flight.pop_front();
       HIPCHECK(hipEventSynchronize(w.ev[sl]));
-      // every shift stopped (the device flag lags the last stopping test)
+      // every shift stopped (the device's all_done flag lags the last stopping test)
       bool every = true;
       for (int j = 0; j < Sb; ++j) every = every && w.hSh[1].done[j];
-      if (every || w.hSh[1].all_done) all_done = true;
+      if (every) all_done = true;
       if (all_done) {
         while (!flight.empty()) {
           HIPCHECK(hipEventSynchronize(w.ev[flight.front()]));
