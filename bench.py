@@ -392,16 +392,18 @@ def mixed_leg(args):
     sts = one_pass()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # the same systems with plain FP64 RBiCG (same k, s) to the same true residual
-    S64 = Solver(M, k=seq.k, s=seq.s, prec="f64", maxit=20000)
+    # the same systems in FP64 to the same true residual: RBiCG (same k, s;
+    # plain Algorithm 2 diverges on some of these systems, so the stall guard
+    # restarts them without recycling) and plain BiCG; each pass timed after
+    # an untimed one, the faster of the two is the FP64 baseline
     xs = torch.zeros_like(bs[0])
     xts = torch.zeros_like(bts[0])
 
-    def pass64():
+    def pass64(S64, recycle):
         S64.set_recycle(None, None)
         out = []
         for j in range(len(bs)):
-            if j:
+            if j and recycle:
                 S64.update_recycle()
             xs.zero_()
             xts.zero_()
@@ -409,17 +411,25 @@ def mixed_leg(args):
             out.append(st)
         return out
 
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s64 = pass64()
-    torch.cuda.synchronize()
-    dt64 = time.perf_counter() - t1
-    fp64 = {"solves_per_s": round(len(s64) / dt64, 3), "ms_per_pass": round(dt64 * 1e3, 1),
-            "iters": [st["iters"] for st in s64],
-            "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in s64),
-            "all_converged": all(st["status"] == 0 for st in s64)}
+    fp64 = {}
+    for name, kk in (("rbicg", seq.k), ("bicg", 0)):
+        S64 = Solver(M, k=kk, s=seq.s, prec="f64", maxit=20000, update=kk > 0, stall_window=4)
+        pass64(S64, kk > 0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s64 = pass64(S64, kk > 0)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t1
+        S64.close()
+        fp64[name] = {"solves_per_s": round(len(s64) / dt64, 3), "ms_per_pass": round(dt64 * 1e3, 1),
+                      "iters": [st["iters"] for st in s64],
+                      "restarts": [st["restarts"] for st in s64],  # stall + true-residual
+                      "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in s64),
+                      "all_converged": all(st["status"] == 0 for st in s64)}
+    best64 = max(fp64.values(), key=lambda v: v["solves_per_s"])
+    fp64["speedup_vs_faster_fp64"] = round(len(sts) / dt / best64["solves_per_s"], 3)
     return {"workload": "convdiff3d_128^3_beta(50,25,10)_8systems_k30_s40_fp32inner_fp64outer_tol1e-10",
-            "fp64_rbicg_same_accuracy": fp64,
+            "fp64_same_accuracy": fp64,
             "fp64_inner_fallbacks": [st["restarts"] for st in sts],
             "n": M.n, "solves_per_s": round(len(sts) / dt, 3), "ms_per_pass": round(dt * 1e3, 1),
             "inner_iters": [st["iters"] for st in sts], "outer_steps": [st["outer_steps"] for st in sts],

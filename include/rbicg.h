@@ -99,7 +99,14 @@ typedef struct {
  *   chunk        iterations launched between convergence polls (0: auto)
  *   profile      p > 0: time the iteration kernels of every p-th chunk of
  *                iterations with HIP events recorded between the launches
- *                (read with rbicg_profile); 0: off */
+ *                (read with rbicg_profile); 0: off
+ *   stall_window w > 0 (FP64 / complex solves with a recycle space; not in
+ *                the paper): at every cycle end, if the smallest cycle-end
+ *                value of max(||r||/||b||, ||r~||/||b~||) has not halved over
+ *                the last w cycles, the solve restarts from its initial
+ *                guesses without the recycle space (one of max_restarts; the
+ *                restarted run builds a new space from its own cycles).
+ *                0 (default): off, plain Algorithm 2. */
 typedef struct {
   int32_t k, s, maxit, max_restarts, update;
   double svd_tol;
@@ -110,6 +117,7 @@ typedef struct {
   void *stream;
   int32_t chunk;
   int32_t profile;
+  int32_t stall_window;
 } rbicg_opts;
 
 /* A matrix repacked and resident in device memory (A and its explicit A^H),
@@ -127,7 +135,7 @@ typedef struct {
 
 /* Fill *opts with defaults: k=20, s=40, maxit=10000, max_restarts=2,
  * update=1, svd_tol=1e-2, seed=0, prec=RBICG_F64, inner_tol=1e-5,
- * max_outer=30, stream=NULL, chunk=0, profile=0. */
+ * max_outer=30, stream=NULL, chunk=0, profile=0, stall_window=0. */
 void rbicg_default_opts(rbicg_opts *opts);
 
 /* Repack A (and A^H, built on the host by a counting sort when AH is NULL)

@@ -14,6 +14,10 @@
                     stores vectors and matrix values in FP32 (not in the paper).
   bilinear       -- u^H A^{-1} w from one dual solve with the correction term
                     x~^H r (error r~^H A^{-1} r, quadratic in the residuals).
+  rbicg_restart_on_stall -- not in the paper: Algorithm 2 with the opt-in
+                    stall stop of ``rbicg``; a stalled recycled run is
+                    followed by a fresh run from the initial guesses without
+                    the recycle space.
 """
 from __future__ import annotations
 
@@ -24,11 +28,49 @@ from .krylov import rbicg, as_csr, SolveResult, _dot
 from . import recycle as rc
 
 
+def rbicg_restart_on_stall(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
+                           tol=1e-8, maxit=1000, s=40, k=None, update=True, seed=0,
+                           max_restarts=2, svd_tol=1e-2, stall_window=4) -> SolveResult:
+    """Restart without recycling after a stall (a heuristic of this
+    implementation, not part of the paper).  An oblique projector I - C C~^H
+    with nearly orthogonal C and C~ can keep a recycled iteration from
+    converging on strongly non-normal operators.  First ``rbicg`` runs with
+    ``stall_window`` (it stops with status "stalled" when the smallest
+    cycle-end residual has not halved over that many cycles); then, if it
+    stalled and a restart is left, a second ``rbicg`` runs from the initial
+    guesses x, x~ with no recycle space (its cycles build a new one) and the
+    remaining iteration budget.  Iteration counts and logs accumulate; the
+    stall counts as one of the ``max_restarts``.  Returns a SolveResult whose
+    ``restarts`` includes the stall restart."""
+    A = as_csr(A)
+    first = rbicg(A, b, bt, x, xt, U, Ut, C, Ct, tol=tol, maxit=maxit, s=s, k=k, update=update,
+                  seed=seed, max_restarts=max_restarts, svd_tol=svd_tol,
+                  stall_window=stall_window)
+    if first.status != "stalled":
+        return first
+    if max_restarts < 1 or first.iters >= maxit:
+        first.status = "maxit"
+        return first
+    kk = k if k is not None else (U.shape[1] if U is not None else None)
+    second = rbicg(A, b, bt, x, xt, None, None, None, None, tol=tol, maxit=maxit - first.iters,
+                   s=s, k=kk, update=update, seed=seed + first.reseeds,
+                   max_restarts=max_restarts - 1, svd_tol=svd_tol)
+    second.iters += first.iters
+    second.restarts += 1
+    second.reseeds += first.reseeds
+    second.log = {key: np.concatenate([np.asarray(first.log[key]), np.asarray(second.log[key])])
+                  for key in second.log}
+    second.stalled_at = first.iters
+    return second
+
+
 def rbicg_sequence(mats, bs, bts, k, s, tol, maxit=5000, x0s=None, xt0s=None,
                    update=True, svd_tol=1e-2, seed=0, max_restarts=2,
-                   U0=None, Ut0=None):
+                   U0=None, Ut0=None, stall_window=None):
     """Solve the dual pairs in order, recycling between them.  With k=0 (or
-    update=False and no U0) this is plain BiCG on every pair.
+    update=False and no U0) this is plain BiCG on every pair.  With
+    ``stall_window`` every pair goes through ``rbicg_restart_on_stall``
+    instead of plain ``rbicg``.
     Returns (results, (U, U~)) with the recycle space left after the last pair."""
     U, Ut = U0, Ut0
     out = []
@@ -42,9 +84,13 @@ def rbicg_sequence(mats, bs, bts, k, s, tol, maxit=5000, x0s=None, xt0s=None,
                 U = Ut = None
         x0 = None if x0s is None else x0s[j]
         xt0 = None if xt0s is None else xt0s[j]
-        res = rbicg(A, bs[j], bts[j], x0, xt0, U, Ut, C, Ct, tol=tol, maxit=maxit,
-                    s=s, k=k, update=(update and k > 0), seed=seed,
-                    max_restarts=max_restarts, svd_tol=svd_tol)
+        kw = dict(tol=tol, maxit=maxit, s=s, k=k, update=(update and k > 0), seed=seed,
+                  max_restarts=max_restarts, svd_tol=svd_tol)
+        if stall_window:
+            res = rbicg_restart_on_stall(A, bs[j], bts[j], x0, xt0, U, Ut, C, Ct,
+                                         stall_window=stall_window, **kw)
+        else:
+            res = rbicg(A, bs[j], bts[j], x0, xt0, U, Ut, C, Ct, **kw)
         out.append(res)
         U, Ut = res.U_next, res.Ut_next
     return out, (U, Ut)

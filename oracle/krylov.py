@@ -54,7 +54,7 @@ class SolveResult:
     x: np.ndarray
     xt: np.ndarray
     iters: int
-    status: str                       # "ok", "maxit", "breakdown"
+    status: str                       # "ok", "maxit", "breakdown", "stalled"
     relres: float = np.nan            # true ||b - A x|| / ||b||
     relres_dual: float = np.nan
     restarts: int = 0
@@ -189,13 +189,21 @@ class _CycleState:
 def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
           tol=1e-8, maxit=1000, s=40, k=None, update=True, seed=0,
           max_restarts=2, svd_tol=1e-2, keep_history=False,
-          keep_lanczos=False) -> SolveResult:
+          keep_lanczos=False, stall_window=None) -> SolveResult:
     """Algorithm 2 (RBiCG) for one dual pair with a fixed recycle space U, U~
     (C = A U, C~ = A^H U~, C~^H C = I required), plus the cycle-wise update of
     Sec. 4 producing the recycle space for the next system (``U_next``).
 
     With an empty recycle space and ``update=False`` this is bitwise Algorithm 1:
     the projection steps are skipped and every other operation is the same.
+
+    ``stall_window`` (default None: off, plain Algorithm 2) is an opt-in stop
+    that is not part of the paper: with a recycle space in use, at every cycle
+    end (i mod s = 0) the smallest cycle-end value of
+    max(||r||/||b||, ||r~||/||b~||) so far is compared with the one
+    ``stall_window`` cycles earlier; if it has not halved, the iteration stops
+    with status "stalled" (iterates as they are, no final correction, no
+    restart).  ``drivers.rbicg_restart_on_stall`` builds the restart on it.
     """
     A = as_csr(A)
     AH = _hop(A)
@@ -218,7 +226,6 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
     restarts = 0
     reseeds = 0
     bn = btn = None
-    x_init, xt_init = x.copy(), xt.copy()
     while True:
         # steps 1-2: eq. minusXR
         r_m1 = b - A @ x
@@ -308,28 +315,15 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
                 status = "ok"; break
             if rho_new == 0 or not np.isfinite(rho_new):
                 status = "breakdown"; break
-            if kc and i % s == 0:
-                # Stall guard (reading, not in the paper): an oblique projector
-                # with nearly orthogonal C and C~ can keep the iteration from
-                # converging on strongly non-normal operators.  When the
-                # smallest cycle-end residual has not halved over four cycles,
-                # the solve starts again from its initial guess without the
-                # recycle space.
+            if stall_window and kc and i % s == 0:
+                # opt-in stop (not in the paper; see the docstring)
                 c = i // s
                 best.append(min(best[-1], max(rn / bn, rtn / btn)))
-                if c >= 4 and best[c] >= 0.5 * best[c - 4]:
+                if c >= stall_window and best[c] >= 0.5 * best[c - stall_window]:
                     status = "stalled"; break
             beta = rho_new / rho
             rho = rho_new
         if status == "stalled":
-            x, xt = x_init.copy(), xt_init.copy()
-            U = Ut = C = Ct = None
-            kc = 0
-            cyc = _CycleState(None, None, kk, s, real_problem, svd_tol)
-            if restarts < max_restarts and total < maxit:
-                restarts += 1
-                continue
-            status = "maxit"
             break
         # step 7
         if kc:

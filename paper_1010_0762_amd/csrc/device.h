@@ -27,7 +27,8 @@ struct Scalars {
   // value has not halved over the last stag_w cycles (diverged if it is above
   // stag_lim, else stagnated).  stag_s = 0: off.  FP32-inner solves use
   // stag_w = 2 and stag_lim = sqrt(inner tol); solves with a recycle space
-  // use stag_w = 4 and stag_lim = 0 (the stall guard).
+  // and opts.stall_window = w > 0 use stag_w = w and stag_lim = 0 (the stall
+  // guard).
   int stag_s, stag_div, stag_w, stag_base;
   double stag_lim;
   double zc[4 * KMAXD];

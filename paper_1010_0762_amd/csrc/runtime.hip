@@ -932,7 +932,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   bool first = true;
   std::vector<double> fulllog;
   std::deque<std::unique_ptr<CycleJob>> jobs;
-  if (ks > 0 && !inner) {  // initial guesses, for a restart after a stall
+  const bool guard = !inner && h->opt.stall_window > 0;
+  if (ks > 0 && guard) {  // initial guesses, for a restart after a stall
     HIPCHECK(hipMemcpyAsync(h->xs0, x, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
     HIPCHECK(hipMemcpyAsync(h->xts0, xt, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
   }
@@ -1004,9 +1005,10 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       hs->stag_w = 2;
       hs->stag_div = 1;
       hs->stag_lim = std::sqrt(tol);
-    } else if (ks > 0) {
+    } else if (ks > 0 && guard) {
+      // stall guard (opts.stall_window; not in the paper)
       hs->stag_s = h->opt.s;
-      hs->stag_w = 4;
+      hs->stag_w = h->opt.stall_window;
       hs->stag_div = 1;
       hs->stag_lim = 0.0;
     }
@@ -1282,7 +1284,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     }
     total = completed;
     status = dev_status;
-    const bool stalled = status == ST_DIVERGED && !inner;
+    const bool stalled = status == ST_DIVERGED && guard;
     // Algorithm 2 step 7 and the true residuals need nothing from the cycle
     // updates still in flight: they are enqueued before the drain below, and
     // their reductions are read after it
@@ -2042,6 +2044,8 @@ extern "C" void rbicg_default_opts(rbicg_opts *o) {
   o->max_outer = 30;
   o->stream = nullptr;
   o->chunk = 0;
+  o->profile = 0;
+  o->stall_window = 0;
 }
 
 extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
@@ -2474,6 +2478,7 @@ static int check_opts(const rbicg_opts *opt) {
     return rbicg_fail(RBICG_EINVAL, "cycle length s=%d out of range", opt->s);
   if (opt->maxit < 1) return rbicg_fail(RBICG_EINVAL, "maxit must be positive");
   if (opt->chunk < 0 || opt->chunk > 256) return rbicg_fail(RBICG_EINVAL, "chunk out of range");
+  if (opt->stall_window < 0) return rbicg_fail(RBICG_EINVAL, "stall_window must be >= 0");
   if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128 && opt->prec != RBICG_F32_IN_F64_OUT)
     return rbicg_fail(RBICG_EINVAL, "unknown precision mode %d", (int)opt->prec);
   if (opt->prec == RBICG_F32_IN_F64_OUT && (!(opt->inner_tol > 0) || opt->inner_tol >= 1 || opt->max_outer < 1))

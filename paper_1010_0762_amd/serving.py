@@ -98,8 +98,11 @@ class Server:
         A = cache.pop(req.rid) if cache and req.rid in cache else wl.convdiff(req.edge, 3, req.beta)
         with torch.cuda.stream(stream):
             M = DeviceMatrix(A)
+            # FP64 RBiCG restarts a stalled recycled solve without recycling
+            # (stall guard; plain Algorithm 2 diverges on some of the larger
+            # strongly convective systems)
             S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
-                       max_outer=30, stream=stream)
+                       max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0)
             stats, sols = [], []
             for j in range(req.nsys):
                 b, bt = wl.request_rhs(req, j)

@@ -231,7 +231,7 @@ class Solver:
 
     def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
                  svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
-                 stream=None, profile=False):
+                 stream=None, profile=False, stall_window=0):
         self.lib = _lib.load()
         o = _lib.rbicg_opts()
         self.lib.rbicg_default_opts(ct.byref(o))
@@ -241,6 +241,8 @@ class Solver:
         o.inner_tol, o.max_outer, o.chunk = inner_tol, max_outer, chunk
         # profile: False/0 off, True/1 every chunk, p > 1 every p-th chunk
         o.profile = int(profile)
+        # restart without recycling after a stall (not in the paper; 0: off)
+        o.stall_window = int(stall_window)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         o.stream = _stream_ptr(self.stream)
         self.opts = o

@@ -244,3 +244,70 @@ def test_maxit_and_bad_args():
         S.solve(_t(b[:10]), _t(b), tol=1e-8)
     with pytest.raises(_lib.RBiCGError):
         _solver(A, k=65)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_first_cycle_spaces_are_eigenvectors(cplx):
+    """First cycle of the first system on the GPU (Sec. 4.2, eigenvectors of
+    T_1 from the iteration scalars): with b, b~ in invariant subspaces of
+    dimension m = s, the space built for the next system is the right and
+    the left eigenvectors of the k eigenvalues of smallest modulus, as the
+    oracle's is."""
+    from scipy.linalg import subspace_angles
+    from cases import eig_case
+    m, k = 6, 3
+    A, b, bt, S_, Y = eig_case(cplx, m=m)
+    ref = oracle.rbicg(A, b, bt, tol=1e-10, maxit=50, s=m, k=k, update=True)
+    S = _solver(sp_csr(A), k=k, s=m, prec="c128" if cplx else "f64")
+    x, xt, st = S.solve(_t(b), _t(bt), tol=1e-10)
+    assert st["status"] == 0 and st["iters"] == ref.iters == m
+    U, Ut, _, _ = S.get_recycle(next=True, kcap=k)
+    U, Ut = _np(U), _np(Ut)
+    assert U.shape[1] == Ut.shape[1] == k
+    assert subspace_angles(U, S_[:, :k]).max() <= 1e-7
+    assert subspace_angles(Ut, Y[:, :k]).max() <= 1e-7
+    assert subspace_angles(U, ref.U_next).max() <= 1e-7
+    assert subspace_angles(Ut, ref.Ut_next).max() <= 1e-7
+    S.close()
+
+
+def sp_csr(A):
+    import scipy.sparse as sp
+    return sp.csr_matrix(A)
+
+
+def test_stall_guard_matches_oracle_driver():
+    """Stall guard (opts.stall_window, not in the paper) against the oracle's
+    restart driver on a case where plain Algorithm 2 does not converge: the
+    GPU stalls at a cycle end (iteration a multiple of s, at least four
+    cycles in), restarts without the recycle space and converges; the
+    restarted run's count is within 5% of the oracle's fresh run, and the
+    solution matches the oracle's.  Without the guard the GPU, like plain
+    Algorithm 2, runs to maxit."""
+    from cases import stall_case
+    A, b, bt, U, Ut, C, Ct = stall_case()
+    s, tol = 20, 1e-10
+    ref = oracle.drivers.rbicg_restart_on_stall(A, b, bt, None, None, U, Ut, C, Ct, tol=tol,
+                                                maxit=1500, s=s, k=6, stall_window=4)
+    assert ref.status == "ok" and ref.restarts == 1
+    fresh_ref = ref.iters - ref.stalled_at
+    S = _solver(A, k=6, s=s, svd_tol=1e-7, maxit=1500, stall_window=4)
+    S.set_recycle(_t(U), _t(Ut))
+    x, xt, st = S.solve(_t(b), _t(bt), tol=tol)
+    assert st["status"] == 0 and st["restarts"] >= 1
+    assert st["relres"] <= tol and st["relres_dual"] <= tol
+    lg = S.log()
+    at = int(np.argmax(lg[:, 9] >= 1))      # first iteration of the restarted run
+    assert at % s == 0 and at >= 4 * s
+    assert _iters_close(st["iters"] - at, fresh_ref)
+    assert _rel(_np(x), ref.x) <= 1e-6 and _rel(_np(xt), ref.xt) <= 1e-6
+    S.close()
+    from paper_1010_0762_amd import _lib
+    P = _solver(A, k=6, s=s, svd_tol=1e-7, maxit=600, update=True)
+    P.set_recycle(_t(U), _t(Ut))
+    try:
+        x, xt, st = P.solve(_t(b), _t(bt), tol=tol)
+        assert st["status"] == 1 and st["iters"] == 600 and st["restarts"] == 0
+    except _lib.RBiCGError as e:   # a drifting iteration may also break down
+        assert e.code == _lib.RBICG_BREAKDOWN
+    P.close()

@@ -14,6 +14,8 @@ from oracle import recycle as rc
 from oracle.krylov import as_csr
 from paper_1010_0762_amd import workloads as wl
 
+from cases import eig_case, stall_case
+
 
 def _rand_nonsym(n, seed, cplx=False, shift=6.0):
     rng = np.random.default_rng(seed)
@@ -313,3 +315,104 @@ def test_shifted_pairs_shared_recycle():
             d = np.linalg.norm(res[i + 1].x - np.conj(res[i].x)) / np.linalg.norm(res[i].x)
             assert d <= 4 * kappa * 1e-8
     assert U is not None and U.shape[1] > 0
+
+
+# ---------------------------------------------------------- added pins
+@pytest.mark.parametrize("cplx", [False, True])
+def test_first_cycle_dual_space_is_left_eigenvectors(cplx):
+    """First cycle of the first system (Sec. 4.2): U_1 = V_1 W_1 from the
+    right and U~_1 = V~_1 W~_1 from the left eigenvectors of T_1.  With b in
+    the span of m right eigenvectors of A = S Lambda S^{-1} and b~ in the span
+    of the matching left eigenvectors (columns of S^{-H}), a cycle of s = m
+    iterations spans exactly those invariant subspaces, so U_1 and U~_1 are
+    the right and left eigenvectors of the k eigenvalues of smallest modulus.
+    A swap of left and right vectors, or a wrong conjugation, moves U~_1 by
+    an O(1) angle."""
+    m, k = 6, 3
+    A, b, bt, S, Y = eig_case(cplx, m=m)
+    res = oracle.rbicg(A, b, bt, tol=1e-10, maxit=50, s=m, k=k, update=True)
+    assert res.status == "ok" and res.iters == m and res.cycles == 1
+    assert res.U_next.shape[1] == k and res.Ut_next.shape[1] == k
+    assert sla.subspace_angles(res.U_next, S[:, :k]).max() <= 1e-8
+    assert sla.subspace_angles(res.Ut_next, Y[:, :k]).max() <= 1e-8
+    # the dual space is not the right eigenvector space (the pin can fail)
+    assert sla.subspace_angles(res.Ut_next, S[:, :k]).max() >= 0.1
+
+
+def test_plain_rbicg_has_no_stall_stop():
+    """Without stall_window the oracle is plain Algorithm 2: on the stall case
+    it runs to maxit (no restart, no stop of its own)."""
+    A, b, bt, U, Ut, C, Ct = stall_case()
+    assert U.shape[1] == 4
+    res = oracle.rbicg(A, b, bt, None, None, U, Ut, C, Ct, tol=1e-10, maxit=600, s=20, k=6)
+    assert res.status == "maxit" and res.iters == 600 and res.restarts == 0
+    assert res.relres > 1e-6
+
+
+def test_restart_on_stall_driver():
+    """The restart driver (not in the paper): its first run is plain
+    Algorithm 2 up to the stall (same iterates as the run without the stop);
+    the stall is at a cycle end where the smallest cycle-end residual has
+    not halved over four cycles; the second run is bitwise the plain run
+    from the initial guesses without recycling; the result solves the
+    systems (dense solve)."""
+    A, b, bt, U, Ut, C, Ct = stall_case()
+    s, tol = 20, 1e-10
+    res = oracle.drivers.rbicg_restart_on_stall(A, b, bt, None, None, U, Ut, C, Ct, tol=tol,
+                                                maxit=1500, s=s, k=6, stall_window=4)
+    at = res.stalled_at
+    assert at % s == 0 and at >= 4 * s and res.restarts == 1 and res.status == "ok"
+    plain = oracle.rbicg(A, b, bt, None, None, U, Ut, C, Ct, tol=tol, maxit=at, s=s, k=6)
+    np.testing.assert_array_equal(res.log["rnorm"][:at], plain.log["rnorm"])
+    bn, btn = np.linalg.norm(b), np.linalg.norm(bt)
+    h = np.maximum(plain.log["rnorm"] / bn, plain.log["rtnorm"] / btn)
+    # cycle-end values, with the projected initial residuals r_0 = b - C C~^H b,
+    # r~_0 = b~ - C~ C^H b~ (eq. minusXR with x = x~ = 0) in front
+    h0 = max(np.linalg.norm(b - C @ (Ct.T @ b)) / bn, np.linalg.norm(bt - Ct @ (C.T @ bt)) / btn)
+    ends = [h0] + [h[c * s - 1] for c in range(1, at // s + 1)]
+    best = np.minimum.accumulate(ends)
+    cs = at // s
+    assert best[cs] >= 0.5 * best[cs - 4]
+    assert all(best[c] < 0.5 * best[c - 4] for c in range(4, cs))
+    fresh = oracle.rbicg(A, b, bt, None, None, tol=tol, maxit=1500 - at, s=s, k=6)
+    assert res.iters == at + fresh.iters
+    np.testing.assert_array_equal(res.x, fresh.x)
+    D = A.toarray()
+    xs = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) <= 10 * kappa * tol
+    assert res.relres <= tol and res.relres_dual <= tol
+
+
+def test_fp32_simulation_is_bicg_on_rounded_data():
+    """FP32 storage (k = 0, no guard firing): the simulated iterates equal
+    FP64 BiCG on the float-rounded matrix and right-hand sides up to float
+    rounding.  After one iteration the difference is one rounding of
+    x_1 = alpha p (at most 2 eps32, and not zero: the simulation does round);
+    after a few iterations it stays at float-rounding level; the converged
+    corrections solve the rounded systems to the inner tolerance in BiCG's
+    iteration count (+-1)."""
+    from oracle.drivers import rbicg_fp32_inner, EPS32
+    A = as_csr(wl.convdiff(12, 2, [10.0, 5.0]))
+    AH = A.T.tocsr()
+    A32, AH32 = A.astype(np.float32), AH.astype(np.float32)
+    Ar = A32.astype(np.float64)
+    rng = np.random.default_rng(3)
+    b, bt = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    b32 = b.astype(np.float32).astype(np.float64)
+    bt32 = bt.astype(np.float32).astype(np.float64)
+    for j, bound in ((1, 2 * EPS32), (2, 1e-5), (5, 1e-5)):
+        d, dt, it, _, div = rbicg_fp32_inner(A32, AH32, b, bt, None, None, None, None, 1e-30, j,
+                                             40, 0, False, A64=A, AH64=AH)
+        ref = oracle.bicg(Ar, b32, bt32, tol=1e-30, maxit=j)
+        assert it == j and not div
+        for got, want in ((d, ref.x), (dt, ref.xt)):
+            e = np.linalg.norm(got - want) / np.linalg.norm(want)
+            assert 1e-10 <= e <= bound
+    d, dt, it, _, div = rbicg_fp32_inner(A32, AH32, b, bt, None, None, None, None, 1e-5, 1000, 40,
+                                         0, False, A64=A, AH64=AH)
+    ref = oracle.bicg(Ar, b32, bt32, tol=1e-5, maxit=1000)
+    assert not div and abs(it - ref.iters) <= 1
+    assert np.linalg.norm(b32 - Ar @ d) / np.linalg.norm(b32) <= 2e-5
+    assert np.linalg.norm(bt32 - Ar.T @ dt) / np.linalg.norm(bt32) <= 2e-5
+    assert np.linalg.norm(d - ref.x) / np.linalg.norm(ref.x) <= 1e-3
