@@ -267,6 +267,15 @@ class Solver:
         self.h = h
 
     # --------------------------------------------------------------- helpers
+    def _order(self):
+        """Order the handle's stream after the caller's current stream, so that
+        tensors the caller (or this wrapper) filled there are complete before
+        the library reads or writes them on the handle's stream.  The library
+        calls below return only after their work on that stream is done."""
+        cur = torch.cuda.current_stream()
+        if self.stream != cur:
+            self.stream.wait_stream(cur)
+
     def _vec(self, v, name):
         if not (isinstance(v, torch.Tensor) and v.is_cuda):
             raise TypeError(f"{name} must be a CUDA tensor")
@@ -291,6 +300,7 @@ class Solver:
         x = torch.zeros_like(b) if x is None else x
         xt = torch.zeros_like(bt) if xt is None else xt
         st = _lib.rbicg_stats()
+        self._order()
         rc = self.lib.rbicg_solve_dual(self.h, self._vec(b, "b"), self._vec(bt, "bt"),
                                        self._vec(x, "x"), self._vec(xt, "xt"), float(tol),
                                        ct.byref(st))
@@ -316,6 +326,7 @@ class Solver:
             # column-major (each column contiguous), in the handle's basis type
             Ucm = U.t().to(self.basis_dtype).contiguous()
             Utcm = Ut.t().to(self.basis_dtype).contiguous()
+            self._order()
             rc = self.lib.rbicg_set_recycle(self.h, ct.c_void_p(Ucm.data_ptr()),
                                             ct.c_void_p(Utcm.data_ptr()), k)
         else:
@@ -326,6 +337,7 @@ class Solver:
         """Returns (U, U~, C, C~) as n x k tensors."""
         bufs = [torch.zeros((kcap, self.n), dtype=self.basis_dtype, device="cuda") for _ in range(4)]
         k = ct.c_int32()
+        self._order()
         rc = self.lib.rbicg_get_recycle(self.h, *[ct.c_void_p(b.data_ptr()) for b in bufs],
                                         kcap, 1 if next else 0, ct.byref(k))
         _lib.check(rc, "rbicg_get_recycle")
@@ -393,6 +405,7 @@ class Solver:
         val = np.zeros(2)
         err = ct.c_double()
         st = _lib.rbicg_stats()
+        self._order()
         rc = self.lib.rbicg_bilinear(self.h, self._vec(u, "u"), self._vec(w, "w"), float(tol),
                                      ct.c_void_p(val.ctypes.data), ct.byref(err), ct.byref(st))
         _lib.check(rc, "rbicg_bilinear", (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED))
@@ -413,6 +426,7 @@ class Solver:
         br = np.zeros(m, np.complex128)
         cr = np.zeros(m, np.complex128)
         with_bc = b is not None
+        self._order()
         rc = self.lib.rbicg_project(
             self.h, m, ct.c_void_p(X.data_ptr()), ct.c_void_p(Xt.data_ptr()),
             self._vec(b, "b") if with_bc else None, self._vec(c, "c") if with_bc else None,
@@ -437,6 +451,7 @@ class Solver:
                     and tuple(t.shape) == (S, self.n)):
                 raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor of shape ({S}, {self.n})")
         sts = (_lib.rbicg_stats * S)()
+        self._order()
         rc = self.lib.rbicg_solve_shifted(self.h, S, sig.view(np.float64).ctypes.data_as(_lib._DP),
                                           self._vec(b, "b"), self._vec(c, "c"),
                                           ct.c_void_p(Xcm.data_ptr()), ct.c_void_p(Xtcm.data_ptr()),
