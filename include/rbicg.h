@@ -344,6 +344,37 @@ int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const vo
 int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
                   const void *c, double *Ar, double *Er, double *br, double *cr);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not touch the allocator):
+ * the same dual solve as rbicg_solve_dual on a handle with opts.k = 0, i.e.
+ * plain BiCG (Algorithm 1; Algorithm 2 with an empty recycle space), on a
+ * matrix already resident (rbicg_matrix_create), with no handle and no
+ * allocation of any kind.  The kernels, their launch order and the options'
+ * meaning are those of rbicg_solve_dual, so for equal inputs and options the
+ * two return the same iterates, counts and residuals.
+ *   A        resident matrix (real or complex values).
+ *   opt      k must be 0; prec RBICG_F64 (real matrix, double vectors) or
+ *            RBICG_C128 (complex vectors; real or complex matrix); maxit in
+ *            [1, RBICG_NOALLOC_MAXIT]; max_restarts, seed, chunk and stream as
+ *            for a handle; the other fields are ignored.
+ *   b, bt    device n-vectors (caller-owned, read only).
+ *   x, xt    device n-vectors: initial guesses on entry, solutions on exit.
+ *   tol, st  as for rbicg_solve_dual (st may be NULL).
+ * Every intermediate buffer (work vectors, block partial sums, the scalar
+ * block, the iteration log) lives in one static device array of
+ * RBICG_NOALLOC_SCRATCH_BYTES per GPU, held by the process until it ends:
+ * n * bytes per element must be <= 2 MiB after padding n to a multiple of
+ * 256 (n <= 262144 real, 131072 complex); larger inputs or maxit return
+ * RBICG_EINVAL with a message, before any work.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on the same GPU (two host threads,
+ * or two streams) race and give wrong results; serialize them.  The first call
+ * on a device looks up the array's device address once.  Host-side waits are
+ * stream synchronizations (no events are created). */
+#define RBICG_NOALLOC_SCRATCH_BYTES (20 * 1024 * 1024)
+#define RBICG_NOALLOC_MAXIT 20000
+int rbicg_solve_dual_noalloc(rbicg_matrix A, const rbicg_opts *opt, const void *b, const void *bt,
+                             void *x, void *xt, double tol, rbicg_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,8 @@ SIGNATURES = {
     "rbicg_update_recycle_on": (ct.c_int, [_P, _P]),
     "rbicg_profile": (ct.c_int, [_P, _I, _DP]),
     "rbicg_project": (ct.c_int, [_P, _I, _P, _P, _P, _P, _DP, _DP, _DP, _DP]),
+    "rbicg_solve_dual_noalloc": (ct.c_int, [_P, ct.POINTER(rbicg_opts), _P, _P, _P, _P, _D,
+                                            ct.POINTER(rbicg_stats)]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),
     "rbicg_host_select": (ct.c_int, [_I, _DP, _DP, _DP, _I, _I, _DP, _DP]),
     "rbicg_host_eig_select": (ct.c_int, [_I, _DP, _DP, _I, _I, _DP, _DP]),

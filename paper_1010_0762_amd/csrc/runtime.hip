@@ -22,6 +22,7 @@
 #include "device.h"
 #include "errors.h"
 #include "kernels.h"
+#include "matviews.h"
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -2469,6 +2470,22 @@ extern "C" int rbicg_matrix_info(rbicg_matrix m, int64_t *info) {
   info[2] = (int64_t)m->A.nnzpad;
   info[3] = m->AH.borrowed ? 1 : 0;
   info[4] = m->complex_vals ? 1 : 0;
+  return RBICG_OK;
+}
+
+int rbicg_matrix_views(rbicg_matrix m, MatViews *out) {
+  if (!m || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  out->n = m->n;
+  out->complex_vals = m->complex_vals ? 1 : 0;
+  out->shared_pattern = m->AH.borrowed ? 1 : 0;
+  out->nnz = m->A.nnz;
+  if (m->complex_vals) {
+    out->Ac = m->A.view<cd>();
+    out->AHc = m->AH.view<cd>();
+  } else {
+    out->A = m->A.view<double>();
+    out->AH = m->AH.view<double>();
+  }
   return RBICG_OK;
 }
 
