@@ -138,6 +138,12 @@ def shifted_pairs(A, b, c, sigmas, U=None, Ut=None, k=20, s=40, tol=1e-8,
     return out, (Unext, Utnext)
 
 
+# No-progress window of the FP32 inner solve, in cycles (reading for FP32
+# storage): BiCG's residual norms are not monotone and plateau for a few
+# cycles on convection-dominated operators before dropping again.
+FP32_NOPROGRESS_CYCLES = 6
+
+
 def _f32(v):
     return np.asarray(v).astype(np.float32)
 
@@ -245,7 +251,7 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
         #  no progress -- float rounding can keep the iteration from
         #    converging where FP64 converges (ill-conditioned deflation with
         #    some recycle spaces; plain BiCG on strongly non-normal operators):
-        #    when the best cycle-end residual has not halved over the last two
+        #    when the best cycle-end residual has not halved over the last six
         #    cycles, stop; above sqrt(tol) the solve counts as diverged (the
         #    outer loop discards it, drops the recycle space and takes its next
         #    inner solve in FP64), else as stagnated.
@@ -254,7 +260,7 @@ def rbicg_fp32_inner(A32, AH32, b, bt, U, Ut, C, Ct, tol, maxit, s, k, update,
             best.append(min(best[-1], hist[it]))
             if hist[it] <= np.sqrt(tol) and hist[it] >= 0.5 * hist[it - s]:
                 break
-            if c >= 2 and best[c] >= 0.5 * best[c - 2]:
+            if c >= FP32_NOPROGRESS_CYCLES and best[c] >= 0.5 * best[c - FP32_NOPROGRESS_CYCLES]:
                 if best[c] > np.sqrt(tol):
                     diverged = True
                 break

@@ -415,6 +415,12 @@ int push_scalars(rbicg_s *h) {
   return 0;
 }
 
+// No-progress window of FP32 inner solves, in cycles: BiCG's residual norms
+// are not monotone and can plateau for a few cycles on convection-dominated
+// operators before they drop again, so a shorter window would discard float
+// solves that converge.
+constexpr int FP32_NOPROGRESS_CYCLES = 6;
+
 // Cosine cut of the biorthogonalization.  FP32-inner mode raises it so that
 // the attainable inner residual, about eps32 ||I - C C~^H|| <= eps32 (1 + 1/tau),
 // stays ten times below the inner tolerance: tau >= 10 eps32 / inner_tol.
@@ -1003,7 +1009,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     hs->stag_base = total;
     if (inner) {
       hs->stag_s = h->opt.s;
-      hs->stag_w = 2;
+      hs->stag_w = FP32_NOPROGRESS_CYCLES;
       hs->stag_div = 1;
       hs->stag_lim = std::sqrt(tol);
     } else if (ks > 0 && guard) {
