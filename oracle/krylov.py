@@ -27,6 +27,7 @@ import scipy.sparse as sp
 
 from .rng import reseed_vector
 from . import recycle as rc
+from . import sec44 as s44
 
 
 def as_csr(A):
@@ -65,6 +66,7 @@ class SolveResult:
     log: dict = field(default_factory=dict)
     history: list = field(default_factory=list)
     lanczos: dict = field(default_factory=dict)
+    pencils: list = field(default_factory=list)
 
 
 def _refnorms(b, bt, r_m1, rt_m1):
@@ -147,22 +149,42 @@ def bicg(A, b, bt, x=None, xt=None, tol=1e-8, maxit=1000, seed=0,
 class _CycleState:
     """Recycle-space update state carried across the cycles of one solve."""
 
-    def __init__(self, U, Ut, k, s, real_problem, svd_tol):
+    def __init__(self, U, Ut, k, s, real_problem, svd_tol, setup="explicit", Ct=None):
         self.U, self.Ut = U, Ut            # current system's recycle space
+        self.Ct = Ct                        # C~ = A^H U~ of that space
         self.Uj = None                      # U_j, U~_j of the last completed cycle
         self.Utj = None
         self.k, self.s = k, s
         self.real = real_problem
         self.svd_tol = svd_tol
         self.cycles = 0
+        if setup not in ("explicit", "recurrence"):
+            raise ValueError(f"unknown pencil set-up {setup!r}")
+        self.setup = setup
+        # Sec. 4.4 state: blocks carried to the next cycle and the run they
+        # belong to (a restart starts a new Lanczos process)
+        self.blocks = None
+        self.blocks_run = None
+        self.pencils = []                   # per cycle of the recurrence set-up: case, P, Q (+ inputs)
+        self.keep_bases = False
 
-    def update(self, A, AH, V, Vt, alpha, beta_prev, rnorm):
+    def update(self, A, AH, V, Vt, alpha, beta_prev, rnorm, rec=None):
         """End of a cycle: V, Vt are the s Lanczos vectors of the cycle;
-        alpha, beta_prev (beta_{i-1}), rnorm (||r_{i-1}||) the cycle's scalars."""
+        alpha, beta_prev (beta_{i-1}), rnorm (||r_{i-1}||) the cycle's scalars.
+        ``rec`` (recurrence set-up) carries what Sec. 4.4 needs beyond them:
+        run, rn_end, beta_end, the restrictions zeta_i, zeta~_i of the cycle
+        and the one before, the dual scale factors, v~_{js+1}, and the previous
+        cycle's last alpha, ||r|| and v~."""
         V = np.stack(V, axis=1)
         Vt = np.stack(Vt, axis=1)
         have_prev = self.Uj is not None
         have_sys = self.U is not None and self.U.shape[1] > 0
+        if self.setup == "recurrence" and rec is not None:
+            done = self._update_sec44(A, AH, V, Vt, alpha, beta_prev, rnorm, rec,
+                                      have_prev, have_sys)
+            if done:
+                self.cycles += 1
+                return
         if not have_prev and not have_sys:
             # first cycle of the first system: eigenvectors of T (Sec. 4.2)
             T = rc.t_from_scalars(alpha, beta_prev, rnorm)
@@ -183,13 +205,76 @@ class _CycleState:
         if m > 0:
             Uj, Utj, _, _ = rc.biorthogonalize(A, AH, Uj, Utj, self.svd_tol)
         self.Uj, self.Utj = Uj, Utj
+        self.blocks = None
         self.cycles += 1
+
+    def _keep(self, case, P, Q, Phi, Phit, X, YtU, B, Bt, G, Gt):
+        d = {"case": case, "P": P, "Q": Q}
+        if self.keep_bases:
+            d.update(Phi=Phi, Phit=Phit, X=X, YtU=YtU, B=B, Bt=Bt, G=G, Gt=Gt)
+        self.pencils.append(d)
+
+    def _update_sec44(self, A, AH, V, Vt, alpha, beta_prev, rnorm, rec, have_prev, have_sys):
+        """The cycle update with the pencil set up by the recurrences of
+        Sec. 4.4 (module sec44).  Returns False when they do not apply (the
+        first cycle of a restarted run that carries a cycle space: its Lanczos
+        vectors are not biorthogonal to the earlier cycles' spaces)."""
+        s = self.s
+        run = rec["run"]
+        first_of_run = rec["alpha_before"] is None
+        G, Gt = s44.gamma_blocks(alpha, beta_prev, rnorm, rec["rn_end"], rec["beta_end"],
+                                 rec["alpha_before"], rec["rnorm_before"])
+        kC = self.U.shape[1] if have_sys else 0
+        if kC:
+            B, Bt = s44.b_blocks(rec["zeta"], rec["zetat"], rec["zeta_before"], rec["zetat_before"],
+                                 beta_prev, 1.0 / np.asarray(rnorm), rec["vtscale"])
+        else:
+            B = np.zeros((0, s)); Bt = np.zeros((0, s))
+        if not have_prev and not have_sys:
+            case = "T"
+            T = rc.t_from_scalars(alpha, beta_prev, rnorm)
+            W, Wt, _ = rc.first_cycle_eigvecs(T, self.k, self.real)
+            Phi, Phit = V, Vt
+            X = s44.empty_blocks(s, G.dtype)
+        elif not have_prev and first_of_run:
+            case = "first"
+            CtU = self.Ct.conj().T @ self.U
+            VtU = np.concatenate([Vt, rec["vt_end"][:, None]], axis=1).conj().T @ self.U
+            P, Q = s44.pencil_first_cycle(CtU, VtU, B, Bt, G, Gt)
+            W, Wt, _ = rc.pencil_eigvecs(P, Q, self.k, self.real)
+            Phi = np.concatenate([self.U, V], axis=1)
+            Phit = np.concatenate([self.Ut, Vt], axis=1)
+            X = s44.system_start_blocks(CtU, s)
+            self._keep(case, P, Q, Phi, Phit, X, VtU, B, Bt, G, Gt)
+        elif have_prev and self.blocks is not None and self.blocks_run == run and not first_of_run:
+            case = "general"
+            Ups_t = np.concatenate([rec["vt_before"][:, None], Vt, rec["vt_end"][:, None]], axis=1)
+            YtU = Ups_t.conj().T @ self.Uj
+            P, Q = s44.pencil_general(self.blocks, YtU, B, Bt, G, Gt)
+            W, Wt, _ = rc.pencil_eigvecs(P, Q, self.k, self.real)
+            Phi = np.concatenate([self.Uj, V], axis=1)
+            Phit = np.concatenate([self.Utj, Vt], axis=1)
+            X = self.blocks
+            self._keep(case, P, Q, Phi, Phit, X, YtU, B, Bt, G, Gt)
+        else:
+            return False
+        m = min(W.shape[1], Wt.shape[1])
+        W, Wt = W[:, :m], Wt[:, :m]
+        if m > 0:
+            TU, TUt = rc.biorth_transforms(A, AH, Phi @ W, Phit @ Wt, self.svd_tol)
+        else:
+            TU = np.zeros((0, 0)); TUt = np.zeros((0, 0))
+        WN, WtM = W @ TU, Wt @ TUt
+        self.Uj, self.Utj = Phi @ WN, Phit @ WtM
+        self.blocks = s44.next_blocks(X, WN, WtM, B, Bt, G, Gt)
+        self.blocks_run = run
+        return True
 
 
 def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
           tol=1e-8, maxit=1000, s=40, k=None, update=True, seed=0,
           max_restarts=2, svd_tol=1e-2, keep_history=False,
-          keep_lanczos=False, stall_window=None) -> SolveResult:
+          keep_lanczos=False, stall_window=None, pencil_setup="explicit") -> SolveResult:
     """Algorithm 2 (RBiCG) for one dual pair with a fixed recycle space U, U~
     (C = A U, C~ = A^H U~, C~^H C = I required), plus the cycle-wise update of
     Sec. 4 producing the recycle space for the next system (``U_next``).
@@ -204,6 +289,12 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
     ``stall_window`` cycles earlier; if it has not halved, the iteration stops
     with status "stalled" (iterates as they are, no final correction, no
     restart).  ``drivers.rbicg_restart_on_stall`` builds the restart on it.
+
+    ``pencil_setup``: "explicit" (default) forms the harmonic Ritz pencil from
+    the explicit products A Phi_j, A^H Phi~_j (its plain definition);
+    "recurrence" sets it up by the recurrences of Sec. 4.4 (module sec44),
+    which are exact in exact arithmetic; the first cycle of a restarted run
+    with a carried cycle space falls back to the explicit products.
     """
     A = as_csr(A)
     AH = _hop(A)
@@ -218,7 +309,10 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
     b = b.astype(dt); bt = bt.astype(dt)
     kk = k if k is not None else max(kc, 1)
     real_problem = not np.iscomplexobj(np.zeros(0, dt))
-    cyc = _CycleState(U if kc else None, Ut if kc else None, kk, s, real_problem, svd_tol)
+    cyc = _CycleState(U if kc else None, Ut if kc else None, kk, s, real_problem, svd_tol,
+                      setup=pencil_setup, Ct=Ct if kc else None)
+    cyc.keep_bases = keep_lanczos
+    rec_on = pencil_setup == "recurrence" and update
     res = SolveResult(x, xt, 0, "maxit")
     lg = {"alpha": [], "beta": [], "rnorm": [], "rtnorm": [], "rho": []}
     lz = {"V": [], "Vt": []}
@@ -261,6 +355,11 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
         rho = _dot(rt, r)
         rn, rtn = np.linalg.norm(r), np.linalg.norm(rt)
         V, Vt, c_alpha, c_beta, c_rn = [], [], [], [], []
+        # Sec. 4.4 data: restrictions and dual scales of the cycle, and the
+        # previous cycle's last values (none at the start of a run)
+        c_zeta, c_zetat, c_vts = [], [], []
+        before = {"alpha_before": None, "rnorm_before": None, "zeta_before": None,
+                  "zetat_before": None, "vt_before": None}
         converged = rn <= tol * bn and rtn <= tol * btn
         status = "ok" if converged else "maxit"
         # cycle-end values of max(||r||/||b||, ||r~||/||b~||), smallest so far
@@ -291,8 +390,13 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
             if update:
                 v = r / rn
                 V.append(v)
-                Vt.append(rt / _dot(v, rt))
+                vts = 1.0 / _dot(v, rt)
+                Vt.append(rt * vts)
                 c_alpha.append(alpha); c_beta.append(beta); c_rn.append(rn)
+                if rec_on:
+                    c_vts.append(vts)
+                    if kc:
+                        c_zeta.append(zeta); c_zetat.append(zetat)
             if keep_lanczos:
                 v = r / rn
                 lz["V"].append(v); lz["Vt"].append(rt / _dot(v, rt))
@@ -308,9 +412,20 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
                 res.history.append(x.copy())
             converged = rn <= tol * bn and rtn <= tol * btn
             if update and len(V) == s:
+                rec = None
+                if rec_on:
+                    v_end = r / rn
+                    rec = dict(before, run=restarts, rn_end=rn, beta_end=rho_new / rho,
+                               zeta=c_zeta, zetat=c_zetat, vtscale=np.asarray(c_vts),
+                               vt_end=rt / _dot(v_end, rt))
+                    before = {"alpha_before": c_alpha[-1], "rnorm_before": c_rn[-1],
+                              "zeta_before": c_zeta[-1] if kc else None,
+                              "zetat_before": c_zetat[-1] if kc else None,
+                              "vt_before": Vt[-1]}
                 cyc.update(A, AH, V, Vt, np.asarray(c_alpha), np.asarray(c_beta),
-                           np.asarray(c_rn))
+                           np.asarray(c_rn), rec)
                 V, Vt, c_alpha, c_beta, c_rn = [], [], [], [], []
+                c_zeta, c_zetat, c_vts = [], [], []
             if converged:
                 status = "ok"; break
             if rho_new == 0 or not np.isfinite(rho_new):
@@ -352,5 +467,6 @@ def rbicg(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, Ct=None,
     else:
         res.U_next, res.Ut_next = U, Ut
     res.log = {kname: np.asarray(v) for kname, v in lg.items()}
+    res.pencils = cyc.pencils
     res.lanczos = lz
     return res

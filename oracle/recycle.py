@@ -177,19 +177,29 @@ def biorthogonalize(A, AH, U: np.ndarray, Ut: np.ndarray, svd_tol: float = 1e-2)
     the same.)  Returns (U, Ut, C, Ct); C, Ct are None when p = 0."""
     if U is None or U.shape[1] == 0:
         return U, Ut, None, None
+    TU, TUt = biorth_transforms(A, AH, U, Ut, svd_tol)
+    if TU.shape[1] == 0:
+        return U[:, :0], Ut[:, :0], None, None
+    U = U @ TU
+    Ut = Ut @ TUt
+    C = A @ U
+    Ct = AH @ Ut
+    return U, Ut, C, Ct
+
+
+def biorth_transforms(A, AH, U: np.ndarray, Ut: np.ndarray, svd_tol: float = 1e-2):
+    """The transforms of ``biorthogonalize``: (TU, TU~) with
+    U <- U TU, U~ <- U~ TU~ (m x p each; p = 0 when nothing is kept)."""
     C = A @ U
     Ct = AH @ Ut
     Q, R = np.linalg.qr(C)
     Qt, Rt = np.linalg.qr(Ct)
     M, sig, NH = np.linalg.svd(Qt.conj().T @ Q)
     p = int(np.sum(sig >= svd_tol))
+    m = U.shape[1]
     if p == 0 or not np.all(np.isfinite(sig)):
-        return U[:, :0], Ut[:, :0], None, None
+        return np.zeros((m, 0), U.dtype), np.zeros((m, 0), Ut.dtype)
     s_inv_half = 1.0 / np.sqrt(sig[:p])
     TU = sla.solve_triangular(R, NH.conj().T[:, :p]) * s_inv_half
     TUt = sla.solve_triangular(Rt, M[:, :p]) * s_inv_half
-    U = U @ TU
-    Ut = Ut @ TUt
-    C = A @ U
-    Ct = AH @ Ut
-    return U, Ut, C, Ct
+    return TU, TUt
