@@ -85,6 +85,10 @@ def parse():
                     help="skip the batched shifted-pair leg (48^3, 8 shifts, 6 sweeps)")
     ap.add_argument("--no-k20", action="store_true",
                     help="skip the extra kernel timing with an injected 20-vector recycle space")
+    ap.add_argument("--pencil-setup", type=int, default=0, choices=(0, 1),
+                    help="cycle-end pencil of the headline: 0 device Grams, 1 Sec. 4.4 recurrences")
+    ap.add_argument("--no-other-setup", action="store_true",
+                    help="skip the headline sequence with the other pencil set-up")
     return ap.parse_args()
 
 
@@ -138,6 +142,49 @@ def bicg_leg(args, seq, mats, b, bt):
     dt = time.perf_counter() - t0
     return {"solves_per_s": round(len(mats) / dt, 3), "ms_per_sequence": round(dt * 1e3, 2),
             "iters_per_system": its, "us_per_iter": round(dt / sum(its) * 1e6, 2)}
+
+
+def pencil_setup_leg(args, seq, mats, b, bt, setup):
+    """The headline's sequence (same workload, same kernels) with the other
+    cycle-end pencil set-up: 0 device Grams of the cycle's vectors, 1 the
+    recurrences of Sec. 4.4 (one (s+2) x k Gram per cycle); one pass timed
+    after an untimed one."""
+    import torch
+    from paper_1010_0762_amd.solver import Solver
+    S = Solver(mats[0], k=seq.k, s=seq.s, chunk=args.chunk, pencil_setup=setup)
+    x = torch.zeros_like(b)
+    xt = torch.zeros_like(bt)
+
+    def one_pass():
+        S.set_recycle(None, None)
+        sts = []
+        for j in range(len(mats)):
+            S.update_recycle(mats[j])
+            x.zero_()
+            xt.zero_()
+            _, _, st = S.solve(b, bt, x, xt, tol=seq.tol)
+            sts.append(st)
+        return sts
+
+    one_pass()
+    torch.cuda.synchronize()
+    S.profile(reset=True)
+    t0 = time.perf_counter()
+    sts = one_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = S.profile(reset=True)
+    S.close()
+    its = [st["iters"] for st in sts]
+    nup = max(prof["cycle_updates"], 1)
+    return {"pencil_setup": setup, "solves_per_s": round(len(mats) / dt, 3),
+            "ms_per_sequence": round(dt * 1e3, 2), "iters_per_system": its,
+            "k_used_per_system": [st["k_used"] for st in sts],
+            "us_per_iter": round(dt / sum(its) * 1e6, 2),
+            "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in sts),
+            "all_converged": all(st["status"] == 0 for st in sts),
+            "cycle_latency_ms_avg": round(prof["cycle_latency_ms"] / nup, 3),
+            "cycle_eig_ms_avg": round(prof["cycle_eig_ms"] / nup, 3)}
 
 
 def precond_leg(args, seq, mats, b, bt):
@@ -521,7 +568,7 @@ def main():
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     xts = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     S = Solver(mats[0], k=seq.k, s=seq.s, prec="f64", chunk=args.chunk,
-               profile=args.profile_timed)
+               profile=args.profile_timed, pencil_setup=args.pencil_setup)
 
     def step():
         S.set_recycle(None, None)
@@ -590,6 +637,8 @@ def main():
                  "iteration_wait_ms_total": round(prof["cycle_wait_ms"], 2)}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
     bicg = None if args.no_k20 else bicg_leg(args, seq, mats, b, bt)
+    other = (None if args.no_other_setup
+             else pencil_setup_leg(args, seq, mats, b, bt, 1 - args.pencil_setup))
     precond = None if args.no_precond else precond_leg(args, seq, mats, b, bt)
     shifted = None if args.no_shifted else shifted_leg(args)
     irka_res = None if args.no_irka else irka_leg(args)
@@ -613,7 +662,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"convdiff3d_{args.N}^3_seq{args.nsys}_k{seq.k}_s{seq.s}_tol1e-8",
                    "n": n, "nnz": seq.mats[0].nnz, "systems_per_step": args.nsys, "k": seq.k,
-                   "s": seq.s, "tol": seq.tol, "precision": "FP64"},
+                   "s": seq.s, "tol": seq.tol, "precision": "FP64",
+                   "pencil_setup": ("Sec. 4.4 recurrences" if args.pencil_setup
+                                    else "device Grams of the cycle vectors")},
         "iters_per_system": iters,
         "total_iters": tot_iters,
         "us_per_iter": round(elapsed / tot_iters * 1e6, 2),
@@ -632,6 +683,7 @@ def main():
         "copy_reference": copy_ref,
         "kernel_at_k20": k20,
         "bicg_same_sequence": bicg,
+        "other_pencil_setup": other,
         "shifted_pairs": shifted,
         "irka": irka_res,
         "mixed_precision": mixed,

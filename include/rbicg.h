@@ -106,7 +106,15 @@ typedef struct {
  *                the last w cycles, the solve restarts from its initial
  *                guesses without the recycle space (one of max_restarts; the
  *                restarted run builds a new space from its own cycles).
- *                0 (default): off, plain Algorithm 2. */
+ *                0 (default): off, plain Algorithm 2.
+ *   pencil_setup how the cycle-end harmonic Ritz pencil (eq. finalGenEigValue)
+ *                is set up: 0 (default) from device Gram matrices of the
+ *                cycle's vectors (the captured A p_i give A Phi_j); 1 by the
+ *                recurrences of Sec. 4.4, which carry the blocks of
+ *                Psi~^H Psi and Psi~^H Phi from cycle to cycle so that only
+ *                Upsilon~_j^H U_{j-1} ((s+2) x k) is formed over the n rows
+ *                (FP64 and complex handles; FP32-inner solves and the first
+ *                cycle of a restarted run use 0). */
 typedef struct {
   int32_t k, s, maxit, max_restarts, update;
   double svd_tol;
@@ -118,6 +126,7 @@ typedef struct {
   int32_t chunk;
   int32_t profile;
   int32_t stall_window;
+  int32_t pencil_setup;
 } rbicg_opts;
 
 /* A matrix repacked and resident in device memory (A and its explicit A^H),
@@ -135,7 +144,8 @@ typedef struct {
 
 /* Fill *opts with defaults: k=20, s=40, maxit=10000, max_restarts=2,
  * update=1, svd_tol=1e-2, seed=0, prec=RBICG_F64, inner_tol=1e-5,
- * max_outer=30, stream=NULL, chunk=0, profile=0, stall_window=0. */
+ * max_outer=30, stream=NULL, chunk=0, profile=0, stall_window=0,
+ * pencil_setup=0. */
 void rbicg_default_opts(rbicg_opts *opts);
 
 /* Repack A (and A^H, built on the host by a counting sort when AH is NULL)
@@ -329,6 +339,28 @@ int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *count);
 int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigma, const void *b,
                         const void *c, void *X, void *Xt, double tol, int32_t update_from,
                         rbicg_stats *st);
+
+/* Batched bilinear forms u_i^H A^{-1} w_i, i < S <= 16 (Sec. 1: bilinear
+ * forms of the inverse, e.g. one per sample of a QMC estimate), on one matrix
+ * and one recycle space, for a RBICG_C128 handle (real or complex A).  The S
+ * dual pairs A x_i = w_i, A^H x~_i = u_i are solved by the batched shifted
+ * kernels of rbicg_solve_shifted with sigma = 0: they iterate in lock step in
+ * one set of launches per iteration, sharing the matrix reads and the
+ * recycle space's restriction and expansion (one FP64 MFMA contraction for
+ * all pairs); pair 0 is solved on its own with the cycle-wise update of
+ * Sec. 4 when opts.update is set, which builds the recycle space of the next
+ * batch (installed by rbicg_update_recycle).  Each value is
+ * u_i^H x_i + x~_i^H r_i with r_i = w_i - A x_i, whose error r~_i^H A^{-1} r_i
+ * is quadratic in the residuals.
+ *   U, W     device n x S complex column-major (leading dimension n).
+ *   values   host array of 2 S doubles (re, im per form).
+ *   err_est  host array of S doubles (may be NULL): ||r_i|| ||r~_i||, the
+ *            error bound without the factor ||A^{-1}||.
+ *   st       host array of S stats (required).
+ * The call allocates and frees two n x S device buffers for the solutions.
+ * Returns 0 when every pair converged, else the first failure code. */
+int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, const void *W, double tol,
+                         double *values, double *err_est, rbicg_stats *st);
 
 /* Reduced pencil of IRKA (Algorithm 3 step 4, and step 5 with E = I):
  *   Ar = Xt^H A X,  Er = Xt^H X,  br = Xt^H b,  cr = X^H c   (m <= 32)

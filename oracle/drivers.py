@@ -66,7 +66,7 @@ def rbicg_restart_on_stall(A, b, bt, x=None, xt=None, U=None, Ut=None, C=None, C
 
 def rbicg_sequence(mats, bs, bts, k, s, tol, maxit=5000, x0s=None, xt0s=None,
                    update=True, svd_tol=1e-2, seed=0, max_restarts=2,
-                   U0=None, Ut0=None, stall_window=None):
+                   U0=None, Ut0=None, stall_window=None, pencil_setup="explicit"):
     """Solve the dual pairs in order, recycling between them.  With k=0 (or
     update=False and no U0) this is plain BiCG on every pair.  With
     ``stall_window`` every pair goes through ``rbicg_restart_on_stall``
@@ -86,6 +86,8 @@ def rbicg_sequence(mats, bs, bts, k, s, tol, maxit=5000, x0s=None, xt0s=None,
         xt0 = None if xt0s is None else xt0s[j]
         kw = dict(tol=tol, maxit=maxit, s=s, k=k, update=(update and k > 0), seed=seed,
                   max_restarts=max_restarts, svd_tol=svd_tol)
+        if pencil_setup != "explicit":
+            kw["pencil_setup"] = pencil_setup
         if stall_window:
             res = rbicg_restart_on_stall(A, bs[j], bts[j], x0, xt0, U, Ut, C, Ct,
                                          stall_window=stall_window, **kw)

@@ -34,7 +34,7 @@ class rbicg_opts(ct.Structure):
                 ("svd_tol", ct.c_double), ("seed", ct.c_uint64), ("prec", ct.c_int),
                 ("inner_tol", ct.c_double), ("max_outer", ct.c_int32),
                 ("stream", ct.c_void_p), ("chunk", ct.c_int32), ("profile", ct.c_int32),
-                ("stall_window", ct.c_int32)]
+                ("stall_window", ct.c_int32), ("pencil_setup", ct.c_int32)]
 
 
 class rbicg_stats(ct.Structure):
@@ -83,6 +83,7 @@ SIGNATURES = {
     "rbicg_update_recycle_on": (ct.c_int, [_P, _P]),
     "rbicg_profile": (ct.c_int, [_P, _I, _DP]),
     "rbicg_project": (ct.c_int, [_P, _I, _P, _P, _P, _P, _DP, _DP, _DP, _DP]),
+    "rbicg_bilinear_batch": (ct.c_int, [_P, _I, _P, _P, _D, _DP, _DP, ct.POINTER(rbicg_stats)]),
     "rbicg_solve_dual_noalloc": (ct.c_int, [_P, ct.POINTER(rbicg_opts), _P, _P, _P, _P, _D,
                                             ct.POINTER(rbicg_stats)]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),

@@ -23,7 +23,8 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
                 const V *ptn, const V *z, const V *zt, const V *C, const V *Ct, int k, int ld,
-                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp);
+                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp,
+                double *zlog = nullptr, int zstride = 0);
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
                   int first, Scalars *hs);

@@ -659,7 +659,7 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
                                             const V *__restrict__ C, const V *__restrict__ Ct,
                                             int k, int ld, const double *__restrict__ P1,
                                             double *__restrict__ P3, Scalars *S, double *rec,
-                                            int it, int rp) {
+                                            int it, int rp, double *zlog, int zstride) {
   using T = typename Ar<V>::T;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
   __shared__ double lds[NW * 4];
@@ -719,6 +719,12 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
       }
       set<T>(S->zc, j, u);
       set<T>(S->zc, k + j, ut);
+    }
+    // the restrictions zeta_i, zeta~_i of this iteration, for the cycle-end
+    // set-up of Sec. 4.4 (B_j from A r_{i-1} = z_i - beta_{i-1} z_{i-1})
+    if (zlog) {
+      double *zr = zlog + (size_t)it * zstride;
+      for (int j = 0; j < 2 * k; ++j) set<T>(zr, j, get<T>(zl, j));
     }
   }
   double rr = 0.0, rtrt = 0.0;
@@ -1880,9 +1886,10 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
                 const V *ptn, const V *z, const V *zt, const V *C, const V *Ct, int k, int ld,
-                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp) {
+                const double *P1, double *P3, Scalars *S, double *rec, int it, int rp,
+                double *zlog, int zstride) {
   hipLaunchKernelGGL((k_it2<V>), dim3(nb), dim3(IB), 0, st, n, x, xt, r, rt, pn, ptn, z, zt, C,
-                     Ct, k, ld, P1, P3, S, rec, it, rp);
+                     Ct, k, ld, P1, P3, S, rec, it, rp, zlog, zstride);
 }
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
@@ -2097,7 +2104,8 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
 #define INST_V(V)                                                                            \
   template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
                               const V *, const V *, const V *, const V *, const V *, int, int, \
-                              const double *, double *, Scalars *, double *, int, int);      \
+                              const double *, double *, Scalars *, double *, int, int,       \
+                              double *, int);                                                \
   template void launch_itfin<V>(hipStream_t, int, const double *, Scalars *, double *, int,  \
                                 int, Scalars *);                                             \
   template void launch_init_p3<V>(hipStream_t, int, int, const V *, const V *, double *);    \

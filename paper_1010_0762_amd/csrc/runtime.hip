@@ -23,6 +23,7 @@
 #include "errors.h"
 #include "kernels.h"
 #include "matviews.h"
+#include "sec44.h"
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -385,6 +386,18 @@ struct rbicg_s {
   bool shifted = false;
   cplx shift = 0.0;
   ShiftWs *sw = nullptr;  // workspace of the batched shifted solves
+  // Sec. 4.4 set-up (opts.pencil_setup = 1): per-iteration restrictions
+  // zeta_i, zeta~_i (zstride doubles per iteration, indexed like log), their
+  // pinned staging for one cycle, and the blocks carried to the next cycle
+  double *zlog = nullptr, *hzlog = nullptr;
+  int zstride = 0;
+  struct RecState {
+    bool valid = false;
+    int run_start = -1, cycle = -1;  // the cycle whose job produced the blocks
+    sec44::Blocks X;
+    double rn_last2 = 0.0;   // ||r_{e-1}|| of that cycle (e its last iteration)
+    cplx at_last = 0.0;      // scale of its last dual Lanczos vector
+  } rec;
   std::vector<void *> allocs;
 };
 
@@ -583,6 +596,15 @@ struct CycleJob {
   std::vector<cplx> Wc, Wtc, TU, TUt;
   int g2y = 0;
   std::string err;
+  // Sec. 4.4 set-up: 0 explicit Grams, 1 later cycle of the same Lanczos run,
+  // 2 first cycle of a later system, 3 eigenvectors of T (first cycle of the
+  // first system) with the recurrence state started
+  int setup = 0;
+  sec44::Mat Wn, Wtn;            // eigenvectors in terms of Phi_j (normalized v)
+  sec44::Mat B, Bt, G, Gt;       // B_j, B~_j, Gamma_j, Gamma~_j
+  sec44::Blocks X, Xnext;        // carried blocks used, and those for the next cycle
+  double rn_last2 = 0.0;
+  cplx at_last = 0.0;
 };
 
 struct LogEntry {
@@ -593,6 +615,11 @@ struct LogEntry {
 inline char *ring_col(void *base, int set, int slots, int c, const rbicg_s *h) {
   return (char *)base + ((size_t)set * slots + c) * h->ld * h->vb;
 }
+// Dual residual ring: slots 0..s-1 hold r~_{i-1} of the cycle's iterations,
+// slot s the residual r~ after the cycle's last iteration, slot s+1 the
+// previous cycle's last r~_{i-1} (copied at the start of the cycle); the two
+// extra slots give the set-up of Sec. 4.4 the whole Upsilon~_j of the cycle.
+inline char *rt_col(const rbicg_s *h, int set, int c) { return ring_col(h->Rt, set, h->opt.s + 2, c, h); }
 
 // Stages 1, 2 and 4 enqueue on h->st, which the caller points at the job
 // stream (JobStream).
@@ -606,10 +633,49 @@ int job_begin(rbicg_s *h, CycleJob &J) {
   J.XU.clear();
   J.XUt.clear();
   J.tpath = !h->have_cyc && h->ksys == 0;
-  if (J.tpath) {
+  const bool rec_mode = h->zlog != nullptr;
+  J.setup = 0;
+  if (rec_mode) {
+    if (J.tpath) J.setup = 3;
+    else if (!h->have_cyc && h->ksys > 0 && J.cycle == 0) J.setup = 2;
+    else if (h->have_cyc && h->rec.valid && h->rec.run_start == J.run_start && h->rec.cycle == J.cycle - 1)
+      J.setup = 1;
+  }
+  if (J.setup == 0) h->rec.valid = false;
+  if (h->zlog && h->ksys > 0 && (J.setup == 1 || J.setup == 2))
+    HIPCHECK(hipMemcpyAsync(h->hzlog, h->zlog + (size_t)lo * h->zstride,
+                            (size_t)(s + 1) * h->zstride * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  if (J.setup == 1 || J.setup == 2) {
+    // Phi_j = [U_{j-1}, V_j] for the products U_j = Phi_j W (as below); the one
+    // O(n) product of the set-up: Upsilon~_j^H U_{j-1}, or in the first cycle
+    // of a later system [V~_1 underbar, C~]^H U
+    const bool first = J.setup == 2;
+    void *Up = first ? h->U : h->Uc[h->cur];
+    void *Utp = first ? h->Ut : h->Utc[h->cur];
+    const int kp = first ? h->ksys : h->kcyc;
+    J.kp = kp;
+    J.mm = kp + s;
+    std::vector<const void *> X, Y;
+    for (int j = 0; j < kp; ++j) {
+      J.XU.push_back(col_ptr(Up, j, h));
+      J.XUt.push_back(col_ptr(Utp, j, h));
+      Y.push_back(col_ptr(Up, j, h));
+    }
     for (int c = 0; c < s; ++c) {
       J.XU.push_back(ring_col(h->R, J.set, s, c, h));
-      J.XUt.push_back(ring_col(h->Rt, J.set, s, c, h));
+      J.XUt.push_back(rt_col(h, J.set, c));
+    }
+    if (!first) X.push_back(rt_col(h, J.set, s + 1));
+    for (int c = 0; c <= s; ++c) X.push_back(rt_col(h, J.set, c));
+    if (first)
+      for (int j = 0; j < kp; ++j) X.push_back(col_ptr(h->Ct, j, h));
+    J.mz = (int)X.size();
+    J.gy = gram_group(J.mz, sizeof(V) == 16 ? 1 : 0);
+    TRY(gram_enqueue<V>(h, X, Y));
+  } else if (J.tpath) {
+    for (int c = 0; c < s; ++c) {
+      J.XU.push_back(ring_col(h->R, J.set, s, c, h));
+      J.XUt.push_back(rt_col(h, J.set, c));
     }
   } else {
     void *Up = h->have_cyc ? h->Uc[h->cur] : h->U;
@@ -635,13 +701,123 @@ int job_begin(rbicg_s *h, CycleJob &J) {
     for (int c = 0; c < s; ++c) {
       Yall.push_back(ring_col(h->R, J.set, s, c, h));
       J.XU.push_back(ring_col(h->R, J.set, s, c, h));
-      J.XUt.push_back(ring_col(h->Rt, J.set, s, c, h));
+      J.XUt.push_back(rt_col(h, J.set, c));
     }
     J.gy = gram_group((int)X1.size(), sizeof(V) == 16 ? 1 : 0);
     TRY(gram_enqueue<V>(h, X1, Yall));
   }
   HIPCHECK(hipEventRecord(J.ev, h->st));
   J.stage = 1;
+  return 0;
+}
+
+// Gamma_j, Gamma~_j and B_j, B~_j of the cycle (Sec. 4.1, Sec. 4.4) from the
+// logged scalars and restrictions.  L[t] is the log row of iteration
+// e - s + t; a[c], at[c] scale r_{i-1}, r~_{i-1} to v_i, v~_i.
+int job_rec_cycle_blocks(const rbicg_s *h, CycleJob &J, const std::vector<LogEntry> &L,
+                         const std::vector<double> &a, const std::vector<cplx> &at,
+                         const std::vector<cplx> &alpha, const std::vector<cplx> &beta) {
+  const int s = h->opt.s;
+  sec44::CycleScalars cs;
+  cs.s = s;
+  cs.alpha = alpha;
+  cs.beta = beta;
+  cs.rn.resize(s);
+  for (int c = 0; c < s; ++c) cs.rn[c] = L[c].rn;
+  cs.rn_end = L[s].rn;
+  cs.beta_end = L[s].rho / L[s - 1].rho;
+  cs.first = J.cycle == 0;
+  if (!cs.first) {
+    cs.alpha_before = L[0].alpha;
+    cs.rn_before = h->rec.rn_last2;
+  }
+  sec44::gamma_blocks(cs, J.G, J.Gt);
+  const int kC = J.setup == 3 ? 0 : h->ksys;
+  J.B = sec44::Mat(kC, s);
+  J.Bt = sec44::Mat(kC, s);
+  if (kC > 0) {
+    const int nd = h->vkind == 1 ? 2 : 1;
+    auto zeta = [&](int row, int j) -> cplx {  // restriction j (< 2 kC) of log row e - s + row
+      const double *z = h->hzlog + (size_t)row * h->zstride + (size_t)j * nd;
+      return nd == 2 ? cplx(z[0], z[1]) : cplx(z[0], 0.0);
+    };
+    for (int c = 0; c < s; ++c)
+      for (int j = 0; j < kC; ++j) {
+        cplx d = zeta(c + 1, j), dt = zeta(c + 1, kC + j);
+        if (beta[c] != cplx(0.0)) {
+          d -= beta[c] * zeta(c, j);
+          dt -= std::conj(beta[c]) * zeta(c, kC + j);
+        }
+        J.B(j, c) = d * a[c];
+        J.Bt(j, c) = dt * at[c];
+      }
+  }
+  J.rn_last2 = L[s - 1].rn;
+  J.at_last = at[s - 1];
+  return 0;
+}
+
+// Host part 1 with the Sec. 4.4 set-up (J.setup 1 or 2): the pencil from the
+// carried blocks and the cycle's small Gram, its eigenvectors, and the
+// coefficient matrices of U_j = Phi_j W, U~_j = Phi~_j W~.
+int job_host1_sec44(const rbicg_s *h, CycleJob &J, const std::vector<LogEntry> &L,
+                    const std::vector<double> &a, const std::vector<cplx> &at,
+                    const std::vector<cplx> &alpha, const std::vector<cplx> &beta, bool real_problem) {
+  const int s = h->opt.s, k = h->opt.k, kp = J.kp, mm = J.mm;
+  TRY(job_rec_cycle_blocks(h, J, L, a, at, alpha, beta));
+  // the Gram X^H Y of job_begin: X = raw dual residuals (and C~), Y = U_{j-1}
+  const std::vector<cplx> Gr = gram_parse(h->hG, J.mz, kp, J.gy);
+  const cplx at_end = L[s].rn / std::conj(L[s].rho);
+  sec44::Mat P, Q;
+  if (J.setup == 1) {
+    // rows: v~_{e-s}, V~_j, v~_{e+1}
+    sec44::Mat YtU(s + 2, kp);
+    for (int i = 0; i < s + 2; ++i) {
+      const cplx sc = std::conj(i == 0 ? h->rec.at_last : (i <= s ? at[i - 1] : at_end));
+      for (int j = 0; j < kp; ++j) YtU(i, j) = sc * Gr[(size_t)i * kp + j];
+    }
+    J.X = h->rec.X;
+    sec44::pencil_general(J.X, YtU, J.B, J.Bt, J.G, J.Gt, P, Q);
+  } else {
+    // rows: V~_1, v~_{s+1}, then C~
+    sec44::Mat VtU(s + 1, kp), CtU(kp, kp);
+    for (int i = 0; i < s + 1; ++i) {
+      const cplx sc = std::conj(i < s ? at[i] : at_end);
+      for (int j = 0; j < kp; ++j) VtU(i, j) = sc * Gr[(size_t)i * kp + j];
+    }
+    for (int i = 0; i < kp; ++i)
+      for (int j = 0; j < kp; ++j) CtU(i, j) = Gr[(size_t)(s + 1 + i) * kp + j];
+    J.X = sec44::system_start_blocks(CtU, s);
+    sec44::pencil_first(CtU, VtU, J.B, J.Bt, J.G, J.Gt, P, Q);
+  }
+  std::vector<double> Pd(2 * (size_t)mm * mm), Qd(2 * (size_t)mm * mm);
+  for (int j = 0; j < mm; ++j)
+    for (int i = 0; i < mm; ++i) {
+      Pd[2 * (i + (size_t)j * mm)] = P(i, j).real();
+      Pd[2 * (i + (size_t)j * mm) + 1] = P(i, j).imag();
+      Qd[2 * (i + (size_t)j * mm)] = Q(i, j).real();
+      Qd[2 * (i + (size_t)j * mm) + 1] = Q(i, j).imag();
+    }
+  std::vector<double> Ws(2 * (size_t)mm * mm), Wls(2 * (size_t)mm * mm);
+  const int m = rbicg_host_eig_select(mm, Pd.data(), Qd.data(), k, real_problem ? 1 : 0, Ws.data(), Wls.data());
+  if (m < 0) {
+    J.err = std::string("harmonic Ritz problem failed: ") + rbicg_last_error();
+    return -1;
+  }
+  J.Wn = sec44::Mat(mm, m);
+  J.Wtn = sec44::Mat(mm, m);
+  J.Wc.assign((size_t)mm * m, 0.0);
+  J.Wtc.assign((size_t)mm * m, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int l = 0; l < mm; ++l) {
+      const cplx w = cplx(Ws[2 * (l + (size_t)c * mm)], Ws[2 * (l + (size_t)c * mm) + 1]);
+      const cplx wl = cplx(Wls[2 * (l + (size_t)c * mm)], Wls[2 * (l + (size_t)c * mm) + 1]);
+      J.Wn(l, c) = w;
+      J.Wtn(l, c) = wl;
+      J.Wc[l + (size_t)c * mm] = (l < kp ? cplx(1.0) : cplx(a[l - kp])) * w;
+      J.Wtc[l + (size_t)c * mm] = (l < kp ? cplx(1.0) : at[l - kp]) * wl;
+    }
+  J.m = m;
   return 0;
 }
 
@@ -701,6 +877,22 @@ int job_host1(const rbicg_s *h, CycleJob &J, bool real_problem) {
         J.Wc[l + c * s] = a[l] * cplx(Ws[2 * (l + c * s)], Ws[2 * (l + c * s) + 1]);
         J.Wtc[l + c * s] = at[l] * cplx(Wls[2 * (l + c * s)], Wls[2 * (l + c * s) + 1]);
       }
+    if (J.setup == 3) {
+      // start of the Sec. 4.4 recurrences: Phi_1 = V_1, nothing carried
+      J.kp = 0;
+      J.Wn = sec44::Mat(s, m);
+      J.Wtn = sec44::Mat(s, m);
+      for (int c = 0; c < m; ++c)
+        for (int l = 0; l < s; ++l) {
+          J.Wn(l, c) = cplx(Ws[2 * (l + c * s)], Ws[2 * (l + c * s) + 1]);
+          J.Wtn(l, c) = cplx(Wls[2 * (l + c * s)], Wls[2 * (l + c * s) + 1]);
+        }
+      J.X = sec44::empty_blocks(s);
+      TRY(job_rec_cycle_blocks(h, J, L, a, at, alpha, beta));
+    }
+  } else if (J.setup == 1 || J.setup == 2) {
+    TRY(job_host1_sec44(h, J, L, a, at, alpha, beta, real_problem));
+    m = J.m;
   } else {
     const int kp = J.kp, mm = J.mm, mz = J.mz;
     const std::vector<cplx> G = gram_parse(h->hG, mz, mz + mm, J.gy);
@@ -834,6 +1026,16 @@ int job_host3(const rbicg_s *h, CycleJob &J) {
     J.TU[t] = cplx(TU[2 * t], TU[2 * t + 1]);
     J.TUt[t] = cplx(TUt[2 * t], TUt[2 * t + 1]);
   }
+  if (J.setup != 0 && p > 0) {
+    // blocks for the next cycle (Sec. 4.4): U_j = Phi_j (W TU), U~_j = Phi~_j (W~ TU~)
+    sec44::Mat T1(m, p), T2(m, p);
+    for (int c = 0; c < p; ++c)
+      for (int i = 0; i < m; ++i) {
+        T1(i, c) = J.TU[i + (size_t)c * m];
+        T2(i, c) = J.TUt[i + (size_t)c * m];
+      }
+    J.Xnext = sec44::next_blocks(J.X, sec44::mul(J.Wn, T1), sec44::mul(J.Wtn, T2), J.B, J.Bt, J.G, J.Gt);
+  }
   return 0;
 }
 
@@ -864,6 +1066,16 @@ int job_stage4(rbicg_s *h, CycleJob &J) {
     h->cur = nxt;
     h->kcyc = J.p;
     h->have_cyc = true;
+  }
+  // the Sec. 4.4 blocks carry to the next cycle only after a cycle set up by
+  // them (or by T) that kept a space
+  h->rec.valid = J.setup != 0 && J.p > 0;
+  if (h->rec.valid) {
+    h->rec.run_start = J.run_start;
+    h->rec.cycle = J.cycle;
+    h->rec.X = std::move(J.Xnext);
+    h->rec.rn_last2 = J.rn_last2;
+    h->rec.at_last = J.at_last;
   }
   J.stage = 5;
   return 0;
@@ -924,6 +1136,10 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   HIPCHECK(hipEventRecord(ev0, h->st));
   const bool update = h->opt.update && h->opt.k > 0;
   h->have_cyc = false;
+  h->rec.valid = false;
+  // Sec. 4.4 set-up: the cycle jobs read the restrictions and two extra dual
+  // ring slots (rt_col)
+  const bool rec_mode = update && h->zlog != nullptr;
   // FP32 storage (inner solves): every iteration re-projects r_{i-1}, r~_{i-1}
   // onto the complements of range(C), range(C~) inside k_it1/k_it2 (a no-op in
   // exact arithmetic; see k_it2)
@@ -1204,6 +1420,9 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
                                     (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
             HIPCHECK(hipMemcpyAsync(ring_col(h->Zt, cyc % 2, s + 1, 0, h), ring_col(h->Zt, (cyc - 1) % 2, s + 1, s, h),
                                     (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
+            if (rec_mode)  // v~_{(j-1)s} of Upsilon~_j: the previous cycle's last r~_{i-1}
+              HIPCHECK(hipMemcpyAsync(rt_col(h, cyc % 2, s + 1), rt_col(h, (cyc - 1) % 2, s - 1),
+                                      (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
           }
         }
         int chunk = chunk_def;
@@ -1221,7 +1440,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
           V *capR = nullptr, *capRt = nullptr, *capZ = nullptr, *capZt = nullptr;
           if (update) {
             capR = (V *)ring_col(h->R, set, s, pos, h);
-            capRt = (V *)ring_col(h->Rt, set, s, pos, h);
+            capRt = (V *)rt_col(h, set, pos);
             capZ = (V *)ring_col(h->Z, set, s + 1, pos + 1, h);
             capZt = (V *)ring_col(h->Zt, set, s + 1, pos + 1, h);
           }
@@ -1232,7 +1451,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
                            h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 1], h->st));
           launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C,
-                        Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp);
+                        Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp,
+                        rec_mode && ks > 0 ? h->zlog : nullptr, h->zstride);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 2], h->st));
           pc = 1 - pc;
           ++launched;
@@ -1249,6 +1469,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         ++slot_next;
         if (update && (launched - run_start) % s == 0) {
           const int c = (launched - run_start) / s - 1;  // cycle c just ended
+          if (rec_mode)  // v~_{js+1} of Upsilon~_j: the dual residual after the cycle
+            HIPCHECK(hipMemcpyAsync(rt_col(h, c % 2, s), rt, (size_t)n * h->vb, hipMemcpyDeviceToDevice, h->st));
           auto J = std::make_unique<CycleJob>();
           J->cycle = c;
           J->e = launched;
@@ -1642,8 +1864,11 @@ static void shifted_form(const std::vector<cplx> &M, int ldm, int r0, int c0, in
 
 template <class M>
 int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, const cd *c, cd *Xc,
-                       cd *Xtc, double tol, int update_from, rbicg_stats *stats) {
+                       cd *Xtc, double tol, int update_from, rbicg_stats *stats, size_t rhs_stride = 0) {
+  // rhs_stride 0: one b, c for every shift; n: column s of b, c for shift s
   const int n = h->n, ld = h->ld;
+  auto bcol_of = [&](int s) { return b + (size_t)s * rhs_stride; };
+  auto ccol_of = [&](int s) { return c + (size_t)s * rhs_stride; };
   std::vector<cplx> sig(S);
   for (int s = 0; s < S; ++s) sig[s] = cplx(sigma[2 * s], sigma[2 * s + 1]);
   const bool update = h->opt.update && h->opt.k > 0;
@@ -1751,15 +1976,19 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       }
       HIPCHECK(hipMemcpyAsync(w.Co, w.hCo, sizeof(ShCoef), hipMemcpyHostToDevice, h->st));
     }
-    // norms of b, c
+    // norms of b, c (per shift when every shift has its own right-hand sides)
     cplx d[3];
-    TRY(host_dots<cd>(h, b, b, c, c, nullptr, nullptr, d));
-    double bn = std::sqrt(std::fabs(d[0].real())), cn = std::sqrt(std::fabs(d[1].real()));
-    if (bn == 0.0) bn = 1.0;
-    if (cn == 0.0) cn = 1.0;
     for (int j = 0; j < Sb; ++j) {
-      hs->bn[j] = bn;
-      hs->btn[j] = cn;
+      if (j == 0 || rhs_stride) {
+        TRY(host_dots<cd>(h, bcol_of(bidx[j]), bcol_of(bidx[j]), ccol_of(bidx[j]), ccol_of(bidx[j]),
+                          nullptr, nullptr, d));
+        double bn = std::sqrt(std::fabs(d[0].real())), cn = std::sqrt(std::fabs(d[1].real()));
+        hs->bn[j] = bn == 0.0 ? 1.0 : bn;
+        hs->btn[j] = cn == 0.0 ? 1.0 : cn;
+      } else {
+        hs->bn[j] = hs->bn[0];
+        hs->btn[j] = hs->btn[0];
+      }
       hs->sig[2 * j] = sig[bidx[j]].real();
       hs->sig[2 * j + 1] = sig[bidx[j]].imag();
     }
@@ -1771,8 +2000,8 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       HIPCHECK(hipMemcpyAsync(bcol(w.Xt, j, h), Xtc + (size_t)s * n, n * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
       h->shifted = true;
       h->shift = sig[s];
-      launch_residual<cd, M>(h->st, view_A<M>(h), b, bcol(w.X, j, h), bcol(w.R, j, h));
-      launch_residual<cd, M>(h->st, view_AH<M>(h), c, bcol(w.Xt, j, h), bcol(w.Rt, j, h));
+      launch_residual<cd, M>(h->st, view_A<M>(h), bcol_of(s), bcol(w.X, j, h), bcol(w.R, j, h));
+      launch_residual<cd, M>(h->st, view_AH<M>(h), ccol_of(s), bcol(w.Xt, j, h), bcol(w.Rt, j, h));
       h->shifted = false;
       launch_fill_zero<cd>(h->st, bcol(w.P[0], j, h), (size_t)n);
       launch_fill_zero<cd>(h->st, bcol(w.Pt[0], j, h), (size_t)n);
@@ -1878,13 +2107,13 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
       // true residuals
       h->shifted = true;
       h->shift = sig[s];
-      launch_residual<cd, M>(h->st, view_A<M>(h), b, bcol(w.X, j, h), (cd *)h->t1);
-      launch_residual<cd, M>(h->st, view_AH<M>(h), c, bcol(w.Xt, j, h), (cd *)h->t2);
+      launch_residual<cd, M>(h->st, view_A<M>(h), bcol_of(s), bcol(w.X, j, h), (cd *)h->t1);
+      launch_residual<cd, M>(h->st, view_AH<M>(h), ccol_of(s), bcol(w.Xt, j, h), (cd *)h->t2);
       h->shifted = false;
       TRY(host_dots<cd>(h, (cd *)h->t1, (cd *)h->t1, (cd *)h->t2, (cd *)h->t2, nullptr, nullptr, d));
       rbicg_stats &st = stats[s];
-      st.relres = std::sqrt(std::fabs(d[0].real())) / bn;
-      st.relres_dual = std::sqrt(std::fabs(d[1].real())) / cn;
+      st.relres = std::sqrt(std::fabs(d[0].real())) / hs->bn[j];
+      st.relres_dual = std::sqrt(std::fabs(d[1].real())) / hs->btn[j];
       st.iters = fs.done[j] ? fs.iter[j] : launched;
       const int dst = fs.done[j] ? fs.status[j] : ST_MAXIT;
       const bool ok = dst == ST_CONVERGED && st.relres <= tol && st.relres_dual <= tol;
@@ -1902,7 +2131,9 @@ int solve_shifted_impl(rbicg_s *h, int S, const double *sigma, const cd *b, cons
     int rc = 0;
     if (k > 0) rc = install_recycle<cd, M>(h, w.BU, w.BUt, k);
     else h->ksys = 0;
-    if (rc >= 0) rc = solve_impl<cd, M>(h, b, c, Xc + (size_t)u0 * n, Xtc + (size_t)u0 * n, tol, &stats[u0]);
+    if (rc >= 0)
+      rc = solve_impl<cd, M>(h, bcol_of(u0), ccol_of(u0), Xc + (size_t)u0 * n, Xtc + (size_t)u0 * n, tol,
+                             &stats[u0]);
     h->shifted = false;
     if (rc < 0) return rc;
   }
@@ -1934,7 +2165,7 @@ int alloc_workspace(rbicg_s *h) {
   for (void **v : bases) TRY(dalloc(h, v, kb));
   if (h->kcap > 0 && h->opt.update) {
     TRY(dalloc(h, &h->R, 2 * vbytes * h->scap));
-    TRY(dalloc(h, &h->Rt, 2 * vbytes * h->scap));
+    TRY(dalloc(h, &h->Rt, 2 * vbytes * (h->scap + 2)));
     TRY(dalloc(h, &h->Z, 2 * vbytes * (h->scap + 1)));
     TRY(dalloc(h, &h->Zt, 2 * vbytes * (h->scap + 1)));
   }
@@ -1952,6 +2183,12 @@ int alloc_workspace(rbicg_s *h) {
   HIPCHECK(hipMemset(h->S, 0, sizeof(Scalars)));
   h->logcap = h->opt.maxit + 2;
   TRY(dalloc(h, (void **)&h->log, (size_t)h->logcap * LOG_STRIDE * sizeof(double)));
+  if (h->opt.pencil_setup && h->kcap > 0 && h->opt.update && h->vkind != 2) {
+    h->zstride = 2 * h->kcap * (h->vkind == 1 ? 2 : 1);
+    TRY(dalloc(h, (void **)&h->zlog, (size_t)h->logcap * h->zstride * sizeof(double)));
+    HIPCHECK(hipHostMalloc((void **)&h->hzlog, (size_t)(h->scap + 1) * h->zstride * sizeof(double),
+                           hipHostMallocDefault));
+  }
   h->nb = iter_grid(h->n);
   TRY(dalloc(h, (void **)&h->partial, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
   TRY(dalloc(h, (void **)&h->P1, (size_t)h->nb * (6 * KMAXD + 2) * sizeof(double)));
@@ -2053,6 +2290,7 @@ extern "C" void rbicg_default_opts(rbicg_opts *o) {
   o->chunk = 0;
   o->profile = 0;
   o->stall_window = 0;
+  o->pencil_setup = 0;
 }
 
 extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
@@ -2502,6 +2740,8 @@ static int check_opts(const rbicg_opts *opt) {
   if (opt->maxit < 1) return rbicg_fail(RBICG_EINVAL, "maxit must be positive");
   if (opt->chunk < 0 || opt->chunk > 256) return rbicg_fail(RBICG_EINVAL, "chunk out of range");
   if (opt->stall_window < 0) return rbicg_fail(RBICG_EINVAL, "stall_window must be >= 0");
+  if (opt->pencil_setup != 0 && opt->pencil_setup != 1)
+    return rbicg_fail(RBICG_EINVAL, "pencil_setup must be 0 or 1");
   if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128 && opt->prec != RBICG_F32_IN_F64_OUT)
     return rbicg_fail(RBICG_EINVAL, "unknown precision mode %d", (int)opt->prec);
   if (opt->prec == RBICG_F32_IN_F64_OUT && (!(opt->inner_tol > 0) || opt->inner_tol >= 1 || opt->max_outer < 1))
@@ -2588,6 +2828,7 @@ extern "C" int rbicg_destroy(rbicg_handle h) {
   if (h->hG) (void)hipHostFree(h->hG);
   if (h->hW) (void)hipHostFree(h->hW);
   if (h->hlog) (void)hipHostFree(h->hlog);
+  if (h->hzlog) (void)hipHostFree(h->hzlog);
   delete h;
   return RBICG_OK;
 }
@@ -2738,6 +2979,72 @@ extern "C" int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigm
   if (h->mat_complex)
     return solve_shifted_impl<cd>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
   return solve_shifted_impl<double>(h, S, sigma, (const cd *)b, (const cd *)c, (cd *)X, (cd *)Xt, tol, update_from, st);
+}
+
+// u_i^H A^{-1} w_i for i < S in one batched solve (see rbicg.h).
+template <class M>
+int bilinear_batch_impl(rbicg_s *h, int S, const cd *U, const cd *W, double tol, double *values,
+                        double *err_est, rbicg_stats *st, cd *X, cd *Xt) {
+  const int n = h->n;
+  // sigma = 0: the shifted solves take (0 I - A) X = W, (0 I - A)^H X~ = U,
+  // so X = -A^{-1} W and X~ = -A^{-H} U
+  std::vector<double> zero(2 * (size_t)S, 0.0);
+  int rc = solve_shifted_impl<M>(h, S, zero.data(), W, U, X, Xt, tol, -1, st, (size_t)n);
+  if (rc < 0 && rc != RBICG_BREAKDOWN) return rc;
+  h->shifted = true;
+  h->shift = 0.0;
+  for (int i = 0; i < S; ++i) {
+    const cd *u = U + (size_t)i * n, *w = W + (size_t)i * n;
+    const cd *x = X + (size_t)i * n, *xt = Xt + (size_t)i * n;
+    // r = w - (0 I - A) x = w - A y and r~ = u - A^H y~ with y = -x, y~ = -x~:
+    // the value u^H y + y~^H r = -(u^H x + x~^H r) (its error r~^H A^{-1} r is
+    // quadratic in the residuals, Sec. 1)
+    launch_residual<cd, M>(h->st, view_A<M>(h), w, x, (cd *)h->t1);
+    launch_residual<cd, M>(h->st, view_AH<M>(h), u, xt, (cd *)h->t2);
+    cplx d[3];
+    int r2 = host_dots<cd>(h, u, x, xt, (const cd *)h->t1, (const cd *)h->t1, (const cd *)h->t1, d);
+    if (r2 < 0) {
+      h->shifted = false;
+      return r2;
+    }
+    const cplx v = -(d[0] + d[1]);
+    values[2 * i] = v.real();
+    values[2 * i + 1] = v.imag();
+    const double rn = std::sqrt(std::fabs(d[2].real()));
+    r2 = host_dots<cd>(h, (const cd *)h->t2, (const cd *)h->t2, nullptr, nullptr, nullptr, nullptr, d);
+    if (r2 < 0) {
+      h->shifted = false;
+      return r2;
+    }
+    if (err_est) err_est[i] = rn * std::sqrt(std::fabs(d[0].real()));
+  }
+  h->shifted = false;
+  return rc;
+}
+
+extern "C" int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, const void *W, double tol,
+                                    double *values, double *err_est, rbicg_stats *st) {
+  if (!h || !U || !W || !values || !st) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "batched bilinear forms need a RBICG_C128 handle");
+  if (S < 1 || S > SHMAX) return rbicg_fail(RBICG_EINVAL, "S=%d out of range [1, %d]", S, SHMAX);
+  if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
+  // solution buffers: the library's own (n x S each), freed before return
+  cd *X = nullptr, *Xt = nullptr;
+  const size_t bytes = (size_t)h->n * S * sizeof(cd);
+  HIPCHECK(hipMalloc((void **)&X, bytes));
+  if (hipMalloc((void **)&Xt, bytes) != hipSuccess) {
+    (void)hipFree(X);
+    return rbicg_fail(RBICG_ENOMEM, "hipMalloc(%zu) failed", bytes);
+  }
+  launch_fill_zero<cd>(h->st, X, (size_t)h->n * S);
+  launch_fill_zero<cd>(h->st, Xt, (size_t)h->n * S);
+  const int rc = h->mat_complex
+                     ? bilinear_batch_impl<cd>(h, S, (const cd *)U, (const cd *)W, tol, values, err_est, st, X, Xt)
+                     : bilinear_batch_impl<double>(h, S, (const cd *)U, (const cd *)W, tol, values, err_est, st, X, Xt);
+  (void)hipStreamSynchronize(h->st);
+  (void)hipFree(X);
+  (void)hipFree(Xt);
+  return rc;
 }
 
 extern "C" int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,

@@ -231,7 +231,7 @@ class Solver:
 
     def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
                  svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
-                 stream=None, profile=False, stall_window=0):
+                 stream=None, profile=False, stall_window=0, pencil_setup=0):
         self.lib = _lib.load()
         o = _lib.rbicg_opts()
         self.lib.rbicg_default_opts(ct.byref(o))
@@ -243,6 +243,8 @@ class Solver:
         o.profile = int(profile)
         # restart without recycling after a stall (not in the paper; 0: off)
         o.stall_window = int(stall_window)
+        # cycle-end pencil: 0 device Grams, 1 the recurrences of Sec. 4.4
+        o.pencil_setup = int(pencil_setup)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         o.stream = _stream_ptr(self.stream)
         self.opts = o
@@ -411,6 +413,25 @@ class Solver:
         _lib.check(rc, "rbicg_bilinear", (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED))
         v = complex(val[0], val[1]) if self.prec == "c128" else float(val[0])
         return v, err.value, st.as_dict()
+
+    def bilinear_batch(self, U, W, tol=1e-8):
+        """rbicg_bilinear_batch: u_i^H A^{-1} w_i for the rows of (S, n) complex
+        CUDA tensors U, W, in one batched solve.  Returns a list of
+        (value, error bound, stats) as bilinear does."""
+        S = U.shape[0]
+        for name, t in (("U", U), ("W", W)):
+            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                    and tuple(t.shape) == (S, self.n)):
+                raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor of shape ({S}, {self.n})")
+        vals = np.zeros(2 * S)
+        errs = np.zeros(S)
+        sts = (_lib.rbicg_stats * S)()
+        self._order()
+        rc = self.lib.rbicg_bilinear_batch(self.h, S, ct.c_void_p(U.data_ptr()), ct.c_void_p(W.data_ptr()),
+                                           float(tol), _lib.dptr(vals), _lib.dptr(errs), sts)
+        _lib.check(rc, "rbicg_bilinear_batch", (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED))
+        return [(complex(vals[2 * i], vals[2 * i + 1]), float(errs[i]), sts[i].as_dict())
+                for i in range(S)]
 
     def project(self, X, Xt, b=None, c=None):
         """rbicg_project: Ar = Xt^H A X, Er = Xt^H X (and br = Xt^H b, cr = X^H c
