@@ -74,6 +74,12 @@ def parse():
     ap.add_argument("--serving-n", type=int, default=40, help="requests in the serving trace")
     ap.add_argument("--serving-lam", type=float, default=50.0, help="arrival rate (req/s)")
     ap.add_argument("--serving-slots", type=int, default=4, help="concurrent request slots")
+    ap.add_argument("--leg", default=None,
+                    choices=("mixed", "shifted", "irka", "serving"),
+                    help="run only this leg and print its JSON (for profiling one workload)")
+    ap.add_argument("--mixed-nsys", type=int, default=8, help="systems of the mixed-precision leg")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (p50/p99 latency of the config-5 trace)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-inner / FP64-outer leg (128^3, 8 systems)")
     ap.add_argument("--no-irka", action="store_true", help="skip the IRKA leg")
@@ -417,7 +423,7 @@ def mixed_leg(args):
     import torch
     from paper_1010_0762_amd import workloads as wl
     from paper_1010_0762_amd.solver import Solver, DeviceMatrix
-    seq = wl.cfg4_sequence(nsys=8, N=128)
+    seq = wl.cfg4_sequence(nsys=args.mixed_nsys, N=128)
     M = DeviceMatrix(seq.mats[0])
     bs = [torch.as_tensor(v, device="cuda") for v in seq.b]
     bts = [torch.as_tensor(v, device="cuda") for v in seq.bt]
@@ -486,16 +492,22 @@ def mixed_leg(args):
 
 
 def serving_main(args):
+    """Config-5 serving on its own: prints one JSON line (serving_leg)."""
+    import torch
+    torch.cuda.set_device(0)
+    print(json.dumps(serving_leg(args)), flush=True)
+
+
+def serving_leg(args):
     """Config-5 serving: a Poisson trace of requests (each 4-12 dual systems of
     3D convection-diffusion, grid edge in {32, 48, 64, 96, 128}, beta ~
     U[1,50]^3, k in {10, 20}), FP32-inner / FP64-outer to an FP64 true
     residual of 1e-8, served with continuous batching; then the same trace
-    through one-at-a-time plain FP64 RBiCG at the same accuracy.  Prints one
-    JSON line with p50 / p99 latency and throughput of both."""
+    through one-at-a-time plain FP64 RBiCG at the same accuracy.  Returns p50
+    / p99 latency and throughput of both."""
     import torch
     from paper_1010_0762_amd import serving
     from paper_1010_0762_amd import workloads as wl
-    torch.cuda.set_device(0)
     trace = wl.cfg5_trace(nreq=args.serving_n, lam=args.serving_lam)
     # warm-up: one small request through each mode (library load, first launches)
     warm = [wl.Request(10 ** 6, 0.0, 32, (10.0, 5.0, 2.0), 2, 10, 1)]
@@ -514,7 +526,19 @@ def serving_main(args):
         summ = serving.latency_summary(res)
         summ["slots"] = slots
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def copy_calibration(mb):
+    """One plain device copy of known size (reads and writes mb MiB once each),
+    for scaling the HBM byte counters of a profiled run."""
+    import torch
+    src = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def copy_reference(kernel_bytes):
@@ -555,6 +579,15 @@ def main():
     if args.serving:
         serving_main(args)
         return
+    if args.leg in ("mixed", "shifted", "irka", "serving"):
+        import torch
+        torch.cuda.set_device(0)
+        if args.copy_mb > 0:
+            copy_calibration(args.copy_mb)
+        fn = {"mixed": mixed_leg, "shifted": shifted_leg, "irka": irka_leg,
+              "serving": serving_leg}[args.leg]
+        print(json.dumps({"leg": args.leg, "result": fn(args)}), flush=True)
+        return
     import torch
     from paper_1010_0762_amd import workloads as wl
     from paper_1010_0762_amd.solver import Solver, DeviceMatrix
@@ -582,13 +615,7 @@ def main():
         return stats
 
     if args.copy_mb > 0:
-        # a plain copy of known size: reads and writes copy_mb MiB once each
-        src = torch.ones(args.copy_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(args.copy_mb)
 
     for _ in range(args.warmup):
         step()
@@ -603,6 +630,7 @@ def main():
     prof = S.profile(reset=True)
 
     iters = [st["iters"] for st in all_stats[-1]]
+    k_used = [st["k_used"] for st in all_stats[-1]]
     deterministic = all([st["iters"] for st in stp] == iters for stp in all_stats)
     tot_iters = sum(sum(st["iters"] for st in stp) for stp in all_stats)
     relres = max(max(st["relres"], st["relres_dual"]) for stp in all_stats for st in stp)
@@ -643,6 +671,7 @@ def main():
     shifted = None if args.no_shifted else shifted_leg(args)
     irka_res = None if args.no_irka else irka_leg(args)
     mixed = None if args.no_mixed else mixed_leg(args)
+    served = None if args.no_serving else serving_leg(args)
     copy_ref = None
     if not args.no_copy_ref and args.copy_mb == 0 and roof is not None:
         copy_ref = copy_reference(roof["traffic"] or roof["alg_bytes_per_launch"])
@@ -663,9 +692,11 @@ def main():
         "config": {"workload": f"convdiff3d_{args.N}^3_seq{args.nsys}_k{seq.k}_s{seq.s}_tol1e-8",
                    "n": n, "nnz": seq.mats[0].nnz, "systems_per_step": args.nsys, "k": seq.k,
                    "s": seq.s, "tol": seq.tol, "precision": "FP64",
+                   "k_retained_mean": round(float(np.mean(k_used)), 2),
                    "pencil_setup": ("Sec. 4.4 recurrences" if args.pencil_setup
                                     else "device Grams of the cycle vectors")},
         "iters_per_system": iters,
+        "k_retained_per_system": k_used,
         "total_iters": tot_iters,
         "us_per_iter": round(elapsed / tot_iters * 1e6, 2),
         "effective_gbs_per_iter": round(eff_gbs, 1),
@@ -688,6 +719,7 @@ def main():
         "irka": irka_res,
         "mixed_precision": mixed,
         "split_preconditioned": precond,
+        "serving": served,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(seq),
     }
     print(json.dumps(out), flush=True)

@@ -526,17 +526,30 @@ __global__ __launch_bounds__(IB) void k_it1(
   Row8<V, M> LA, LB;
   V pre[4] = {};  // r, r~, p, p~ at the row
   bool fast = false;
-  if constexpr (RPT == 1 && sizeof(M) <= 8 && sizeof(V) <= 8) {  // real data (register budget)
+  // real data (register budget): the same row routine for every row a
+  // thread owns; the first row's loads go out before the prologue
+  constexpr bool ROWFAST = sizeof(M) <= 8 && sizeof(V) <= 8;
+  auto row_loads = [&](int row) {
+    pre[0] = r[row];
+    pre[1] = rt[row];
+    pre[2] = p[row];
+    pre[3] = pt[row];
+    row8_index(A, row, LA);
+    if (AH.col == A.col) row8_values(AH, row, LA, LB);  // uniform branch
+    else row8_index(AH, row, LB);
+    fast = LA.w <= 8 && LB.w <= 8;
+    if (fast) row8_gather(r, p, LA);
+  };
+  if constexpr (ROWFAST && RPT == 1) {
+    if (row0 < n) row_loads(row0);
+  } else if constexpr (ROWFAST) {
     if (row0 < n) {
       pre[0] = r[row0];
       pre[1] = rt[row0];
       pre[2] = p[row0];
       pre[3] = pt[row0];
       row8_index(A, row0, LA);
-      if (AH.col == A.col) row8_values(AH, row0, LA, LB);  // uniform branch
-      else row8_index(AH, row0, LB);
-      fast = LA.w <= 8 && LB.w <= 8;
-      if (fast) row8_gather(r, p, LA);
+      if (LA.w <= 8) row8_gather(r, p, LA);
     }
   }
   // after the loads above are in flight (a launch past the stopping test
@@ -545,6 +558,111 @@ __global__ __launch_bounds__(IB) void k_it1(
   T beta;
   if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
   const T betac = cj(beta);
+  if constexpr (ROWFAST && RPT > 1) {
+    // Several rows per thread: each row in turn, A's indices, values and
+    // gathers in flight together, then A^H's (one set of row registers for
+    // both, reusing A's indices when A^H shares the pattern); z, z~ and p~ go
+    // to memory and the restriction re-reads them (cache hits) column group
+    // by column group instead of keeping them in registers per row.  The
+    // first row's A loads were issued before the prologue (LA).
+    T s0 = zero<T>();
+    const bool shared = AH.col == A.col;
+#pragma unroll 1
+    for (int q = 0; q < RPT; ++q) {
+      const int row = row0 + q * stride;
+      if (row >= n) break;  // rows grow with q
+      if (q > 0) {
+        pre[0] = r[row];
+        pre[1] = rt[row];
+        pre[2] = p[row];
+        pre[3] = pt[row];
+        row8_index(A, row, LA);
+        if (LA.w <= 8) row8_gather(r, p, LA);
+      }
+      const V rv = pre[0], rtv = pre[1], pv = pre[2], ptv0 = pre[3];
+      pn[row] = down<V>(up(rv) + beta * up(pv));
+      const V ptv = down<V>(up(rtv) + betac * up(ptv0));
+      ptn[row] = ptv;
+      const T za = LA.w <= 8 ? row8_sum<V, M, T>(A, LA, beta, rv, pv)
+                             : spmv_dir<V, M, T>(A, row, r, p, beta);
+      if (shared) row8_values(AH, row, LA, LA);
+      else row8_index(AH, row, LA);
+      T zb;
+      if (LA.w <= 8) {
+        row8_gather(rt, pt, LA);
+        zb = row8_sum<V, M, T>(AH, LA, betac, rtv, ptv0);
+      } else {
+        zb = spmv_dir<V, M, T>(AH, row, rt, pt, betac);
+      }
+      const T zz = up(down<V>(za));
+      const T zzt = up(down<V>(zb));
+      s0 += cj(up(ptv)) * zz;
+      z[row] = down<V>(zz);
+      zt[row] = down<V>(zzt);
+      if (capR) {
+        capR[row] = rv;
+        capRt[row] = rtv;
+        capZ[row] = down<V>(zz);
+        capZt[row] = down<V>(zzt);
+      }
+    }
+    put<T>(lds, ls, 3 * k, s0);
+    // restriction: groups of G columns, rows in the same order as above
+    constexpr int G = sizeof(V) == 8 ? 4 : 8;
+    for (int j0 = 0; j0 < k; j0 += G) {
+      T a[G], b[G], e[G], c[G], d[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        a[g] = zero<T>();
+        b[g] = zero<T>();
+        e[g] = zero<T>();
+        c[g] = zero<T>();
+        d[g] = zero<T>();
+      }
+      for (int q = 0; q < RPT; ++q) {
+        const int row = row0 + q * stride;
+        if (row >= n) break;
+        const T zz = up(z[row]), zzt = up(zt[row]), cptv = cj(up(ptn[row]));
+        T rv = zero<T>(), rtv = zero<T>();
+        if (rp) {
+          rv = up(r[row]);
+          rtv = up(rt[row]);
+        }
+        V cb[G], ctb[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const size_t off = (size_t)min(j0 + g, k - 1) * ld + row;
+          cb[g] = C[off];
+          ctb[g] = Ct[off];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const T cv = up(cb[g]), ctv = up(ctb[g]);
+          a[g] += cj(ctv) * zz;
+          b[g] += cj(cv) * zzt;
+          e[g] += cptv * cv;
+          if (rp) {
+            c[g] += cj(ctv) * rv;
+            d[g] += cj(cv) * rtv;
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (j0 + g < k) {
+          put<T>(lds, ls, j0 + g, a[g]);
+          put<T>(lds, ls, k + j0 + g, b[g]);
+          put<T>(lds, ls, 2 * k + j0 + g, e[g]);
+          if (rp) {
+            put<T>(lds, ls, 3 * k + 1 + j0 + g, c[g]);
+            put<T>(lds, ls, 4 * k + 1 + j0 + g, d[g]);
+          }
+        }
+    }
+    __syncthreads();
+    bstore(lds, ls, NW, ls, P1);
+    return;
+  }
   // per row: z, z~, r_{i-1}, r~_{i-1} and conj(p~) as stored
   T zr[RPT], ztr[RPT], rr_[RPT], rtr_[RPT], cpt[RPT];
   T s0 = zero<T>();
@@ -729,17 +847,25 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
   }
   double rr = 0.0, rtrt = 0.0;
   T rho = zero<T>();
+  // several rows per thread: the next row's streams are loaded while this
+  // row is computed
+  V fn[8] = {};
   for (int row = row0; row < n; row += stride) {
     const bool pre = row == row0;
     if (!pre) {
-      f[0] = z[row];
-      f[1] = zt[row];
-      f[2] = r[row];
-      f[3] = rt[row];
-      f[4] = x[row];
-      f[5] = xt[row];
-      f[6] = pn[row];
-      f[7] = ptn[row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f[u] = fn[u];
+    }
+    const int nxt = row + stride;
+    if (nxt < n) {
+      fn[0] = z[nxt];
+      fn[1] = zt[nxt];
+      fn[2] = r[nxt];
+      fn[3] = rt[nxt];
+      fn[4] = x[nxt];
+      fn[5] = xt[nxt];
+      fn[6] = pn[nxt];
+      fn[7] = ptn[nxt];
     }
     T qq = up(f[0]), qqt = up(f[1]);
     T rv = up(f[2]), rtv = up(f[3]);

@@ -7,6 +7,7 @@ Calls only the CPU oracle (oracle/) on seeded synthetic inputs
     python tests/golden/make_golden.py cfg2     # cfg2_convdiff3d_64.json
     python tests/golden/make_golden.py cfg4     # cfg4_convdiff3d_128.json
     python tests/golden/make_golden.py cfg3     # cfg3_shifted_48.json
+    python tests/golden/make_golden.py cfg2seq  # cfg2seq_convdiff3d_64.json
 
 Contents, for the 3D convection-diffusion sequence on the 64^3 grid
 (k = 20, s = 40, relative tolerance 1e-8):
@@ -97,6 +98,44 @@ def cfg2(N=64, nsys=10):
     print("injected", inj["p"], inj["iters"], spread)
 
 
+NPERT_SEQ = 3
+
+
+def cfg2seq(N=64, nsys=10):
+    """The benchmark's whole recycled sequence (Algorithm 2 with the update of
+    Sec. 4.1-4.3, the space of system j carried to system j+1): per system the
+    iteration count, true residuals, retained dimension and sampled x, x~ of
+    the unperturbed run, and the iteration counts of NPERT_SEQ runs whose b, b~
+    are perturbed entrywise by 1e-13 relative (the oracle's own spread: the
+    recycled counts move with rounding on this operator)."""
+    seq = wl.cfg2_sequence(nsys=nsys, N=N)
+    n = seq.mats[0].n
+    idx = np.sort(np.random.default_rng(wl.BASE_SEED + 905).choice(n, NSAMPLE, replace=False))
+    out = {"workload": f"convdiff3d_{N}^3_seq{nsys}_k{seq.k}_s{seq.s}_tol{seq.tol}_recycled",
+           "tol": seq.tol, "k": seq.k, "s": seq.s, "sample_index": idx.tolist()}
+    t0 = time.time()
+    res, _ = oracle.rbicg_sequence(seq.mats, seq.b, seq.bt, seq.k, seq.s, seq.tol, maxit=20000)
+    out["iters"] = [int(r.iters) for r in res]
+    out["status"] = [r.status for r in res]
+    out["relres"] = [[float(r.relres), float(r.relres_dual)] for r in res]
+    out["k_used"] = [0] + [int(r.U_next.shape[1]) if r.U_next is not None else 0 for r in res[:-1]]
+    out["x_sample"] = [r.x[idx].tolist() for r in res]
+    out["xt_sample"] = [r.xt[idx].tolist() for r in res]
+    out["x_norm"] = [float(np.linalg.norm(r.x)) for r in res]
+    print("seq", out["iters"], flush=True)
+    spread = [out["iters"]]
+    for j in range(NPERT_SEQ):
+        bp = [_perturbed(v, 200 + 10 * j + i) for i, v in enumerate(seq.b)]
+        btp = [_perturbed(v, 300 + 10 * j + i) for i, v in enumerate(seq.bt)]
+        rp, _ = oracle.rbicg_sequence(seq.mats, bp, btp, seq.k, seq.s, seq.tol, maxit=20000)
+        spread.append([int(r.iters) for r in rp])
+        print("seq pert", j, spread[-1], flush=True)
+    out["iters_runs"] = spread
+    out["oracle_seconds"] = time.time() - t0
+    with open(os.path.join(HERE, f"cfg2seq_convdiff3d_{N}.json"), "w") as f:
+        json.dump(out, f)
+
+
 def cfg4(N=128):
     """Mixed-precision workload (3D conv-diff 128^3, beta = (50, 25, 10)):
     the FP64 BiCG solution of system 0 to 1e-10 relative, sampled, as the FP64
@@ -155,3 +194,5 @@ if __name__ == "__main__":
         cfg4()
     if which in ("cfg3", "all"):
         cfg3()
+    if which in ("cfg2seq", "all"):
+        cfg2seq()
