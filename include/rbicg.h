@@ -376,6 +376,30 @@ int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, const void *W
 int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
                   const void *c, double *Ar, double *Er, double *br, double *cr);
 
+/* Continuous batching of iteration launches across handles (serving several
+ * requests at once).  A batch owns a HIP stream.  Every handle attached to it
+ * keeps its own host thread, stream, matrix, recycle space and workspace, but
+ * hands each chunk of iterations (the arguments of its iteration kernels) to
+ * the batch instead of launching it; the batch launches the chunks of all
+ * attached handles that are iterating in one set of launches -- per
+ * iteration one k_it1_multi and one k_it2_multi covering every handle's
+ * rows (each handle its own range of blocks, its own partial sums), then one
+ * stopping-test launch -- once every iterating handle has handed in a chunk
+ * or the oldest chunk has waited window_us microseconds.  Each handle's
+ * arithmetic is that of its unbatched launches, so results are bitwise the
+ * same alone and batched.  At most max_slots (<= 16) chunks per launch.
+ * Handles of different vector types batch in separate launches.  Per-kernel
+ * event profiling (opts.profile) is off for attached handles. */
+typedef struct rbicg_batch_s *rbicg_batch;
+int rbicg_batch_create(int32_t max_slots, double window_us, rbicg_batch *out);
+/* Attach h to b (NULL detaches); not while h is solving.  The batch must
+ * outlive the attachment. */
+int rbicg_batch_attach(rbicg_handle h, rbicg_batch b);
+/* out[0..3]: launches, chunks launched, handle-iterations launched, most chunks
+ * in one launch. */
+int rbicg_batch_stats(rbicg_batch b, double *out);
+int rbicg_batch_destroy(rbicg_batch b);
+
 /* For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc, code that must not touch the allocator):
  * the same dual solve as rbicg_solve_dual on a handle with opts.k = 0, i.e.

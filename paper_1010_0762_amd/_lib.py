@@ -84,6 +84,10 @@ SIGNATURES = {
     "rbicg_profile": (ct.c_int, [_P, _I, _DP]),
     "rbicg_project": (ct.c_int, [_P, _I, _P, _P, _P, _P, _DP, _DP, _DP, _DP]),
     "rbicg_bilinear_batch": (ct.c_int, [_P, _I, _P, _P, _D, _DP, _DP, ct.POINTER(rbicg_stats)]),
+    "rbicg_batch_create": (ct.c_int, [_I, _D, ct.POINTER(_P)]),
+    "rbicg_batch_attach": (ct.c_int, [_P, _P]),
+    "rbicg_batch_stats": (ct.c_int, [_P, _DP]),
+    "rbicg_batch_destroy": (ct.c_int, [_P]),
     "rbicg_solve_dual_noalloc": (ct.c_int, [_P, ct.POINTER(rbicg_opts), _P, _P, _P, _P, _D,
                                             ct.POINTER(rbicg_stats)]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),

@@ -13,6 +13,8 @@ struct ColList {
 
 // Blocks of the iteration kernels for n rows (at most 8 rows per thread).
 int iter_grid(int n);
+// whether nb iteration blocks cover n rows with one row per thread
+bool iter_one_row(int n, int nb);
 
 template <class V, class M>
 void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, const V *r,
@@ -28,6 +30,62 @@ void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V
 template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
                   int first, Scalars *hs);
+
+// ---- batched launches: several independent systems ("slots") per launch ----
+#define RBICG_BATCH_SLOTS 16
+// Arguments of one slot of k_it1_multi / k_it2_multi: those of launch_it1 /
+// launch_it2 for that system, and the slot's first block b0 and block count
+// nb (slots in increasing b0, contiguous).
+template <class V, class M>
+struct It1Args {
+  Sell<M> A, AH;
+  const V *r, *p, *rt, *pt;
+  V *pn, *ptn, *z, *zt;
+  const V *C, *Ct;
+  int k, ld;
+  V *capR, *capRt, *capZ, *capZt;
+  const double *P3;
+  double *P1;
+  Scalars *S;
+  double *rec;
+  int it, first, rp;
+  int b0, nb;
+};
+template <class V>
+struct It2Args {
+  int n;
+  V *x, *xt, *r, *rt;
+  const V *pn, *ptn, *z, *zt, *C, *Ct;
+  int k, ld;
+  const double *P1;
+  double *P3;
+  Scalars *S;
+  double *rec;
+  int it, rp;
+  double *zlog;
+  int zstride;
+  int b0, nb;
+};
+struct ItfinArgs {
+  const double *P3;
+  int nb;
+  Scalars *S;
+  double *rec;
+  int it, first;
+  Scalars *hs;
+};
+// dtab: device arrays of nslot entries; nblocks = sum of the slots' nb; rpt1:
+// every slot covers its rows with one row per thread (else RMAX rows)
+template <class V, class M>
+void launch_it1_multi(hipStream_t st, const It1Args<V, M> *dtab, int nslot, int nblocks,
+                      size_t lds_bytes, bool rpt1);
+template <class V>
+void launch_it2_multi(hipStream_t st, const It2Args<V> *dtab, int nslot, int nblocks);
+template <class V>
+void launch_itfin_multi(hipStream_t st, const ItfinArgs *dtab, int nslot);
+// dynamic LDS bytes of k_it1 for recycle dimension k (and re-projection rp)
+template <class V>
+size_t it1_lds_bytes(int k, int rp);
 template <class V>
 void launch_init_p3(hipStream_t st, int nb, int n, const V *r, const V *rt, double *P3);
 // dots (a_i, b_i), i < 3, reduced into out[0 .. 3*ND)

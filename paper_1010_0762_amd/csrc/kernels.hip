@@ -159,11 +159,11 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
 // Block partial: P[block * nv + t] = sum over the waves (fixed order) of the
 // wave sums in lds (caller synchronizes before).
 __device__ __forceinline__ void bstore(const double *lds, int stride, int nwaves, int nv,
-                                       double *P) {
+                                       double *P, int bid) {
   for (int t = threadIdx.x; t < nv; t += blockDim.x) {
     double s = 0.0;
     for (int w = 0; w < nwaves; ++w) s += lds[w * stride + t];
-    P[(size_t)blockIdx.x * nv + t] = s;
+    P[(size_t)bid * nv + t] = s;
   }
 }
 
@@ -392,12 +392,12 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
 // (uniformly) when the solve must stop.
 template <class T>
 __device__ bool it_prologue(const double *P3, int nb, Scalars *S, double *rec, int it, int first,
-                            double *tmp, double *red, T &beta) {
+                            double *tmp, double *red, T &beta, bool block0 = true) {
   constexpr int nv = 2 + ND<T>::v;
   breduce(P3, nb, nv, tmp, red);
   const double rn = sqrt(red[0]), rtn = sqrt(red[1]);
   const T rho = get<T>(red + 2, 0);
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool lead = block0 && threadIdx.x == 0;
   double *Rm1 = rec + (size_t)(it - 1) * LOG_STRIDE;
   if (lead) {
     set<T>(Rm1 + 4, 0, rho);
@@ -502,24 +502,26 @@ __device__ __forceinline__ void restrict_group(const V *__restrict__ C, const V 
 }  // namespace
 
 // ===================================================================== kernels
+// Body of k_it1 for block bid of the nbl blocks that own the system (the
+// whole grid, or one slot of a batched launch); lds holds the wave partials,
+// NW rows of ls values (dynamic: sized by the recycle dimension, so that the
+// block leaves room on its CU for cycle-end kernels).
 template <class V, class M, int RPT>
-__global__ __launch_bounds__(IB) void k_it1(
+__device__ __forceinline__ void it1_body(
     Sell<M> A, Sell<M> AH, const V *__restrict__ r, const V *__restrict__ p,
     const V *__restrict__ rt, const V *__restrict__ pt, V *__restrict__ pn, V *__restrict__ ptn,
     V *__restrict__ z, V *__restrict__ zt, const V *__restrict__ C, const V *__restrict__ Ct,
     int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, const double *__restrict__ P3,
-    double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp) {
+    double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp, int bid, int nbl,
+    double *lds) {
   using T = typename Ar<V>::T;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
-  // wave partials, NW rows of ls values (dynamic: sized by the recycle
-  // dimension, so that the block leaves room on its CU for cycle-end kernels)
-  extern __shared__ double lds[];
   const int ls = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
   __shared__ double tmp[IB];
   __shared__ double red[8];
   const int n = A.n;
-  const int stride = gridDim.x * IB;
-  const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x;
+  const int stride = nbl * IB;
+  const int row0 = xcd_chunk(bid, nbl) * IB + threadIdx.x;
   // one row per thread: the row's own entries, A's indices, values and
   // gathers and A^H's indices and values are loaded before the partials of
   // the previous iteration are reduced (none of them depends on beta)
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(IB) void k_it1(
   // reads and discards them)
   if (S->done) return;
   T beta;
-  if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta)) return;
+  if (!it_prologue<T>(P3, nbl, S, rec, it, first, tmp, red, beta, bid == 0)) return;
   const T betac = cj(beta);
   if constexpr (ROWFAST && RPT > 1) {
     // Several rows per thread: each row in turn, A's indices, values and
@@ -660,7 +662,7 @@ __global__ __launch_bounds__(IB) void k_it1(
         }
     }
     __syncthreads();
-    bstore(lds, ls, NW, ls, P1);
+    bstore(lds, ls, NW, ls, P1, bid);
     return;
   }
   // per row: z, z~, r_{i-1}, r~_{i-1} and conj(p~) as stored
@@ -759,7 +761,43 @@ __global__ __launch_bounds__(IB) void k_it1(
     }
   }
   __syncthreads();
-  bstore(lds, ls, NW, ls, P1);
+  bstore(lds, ls, NW, ls, P1, bid);
+}
+
+template <class V, class M, int RPT>
+__global__ __launch_bounds__(IB) void k_it1(
+    Sell<M> A, Sell<M> AH, const V *__restrict__ r, const V *__restrict__ p,
+    const V *__restrict__ rt, const V *__restrict__ pt, V *__restrict__ pn, V *__restrict__ ptn,
+    V *__restrict__ z, V *__restrict__ zt, const V *__restrict__ C, const V *__restrict__ Ct,
+    int k, int ld, V *capR, V *capRt, V *capZ, V *capZt, const double *__restrict__ P3,
+    double *__restrict__ P1, Scalars *S, double *rec, int it, int first, int rp) {
+  extern __shared__ double lds_dyn[];
+  it1_body<V, M, RPT>(A, AH, r, p, rt, pt, pn, ptn, z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt,
+                      P3, P1, S, rec, it, first, rp, blockIdx.x, gridDim.x, lds_dyn);
+}
+
+// Slot of block blockIdx.x in a batched launch: the last slot s with
+// tab[s].b0 <= blockIdx.x (slots in increasing b0, at most RBICG_BATCH_SLOTS;
+// a slot's blocks are tab[s].b0 .. tab[s].b0 + tab[s].nb - 1, and the blocks
+// up to the next slot's b0 are idle, so that every slot starts on a multiple
+// of the XCD count).
+template <class A>
+__device__ __forceinline__ int batch_slot(const A *tab, int nslot) {
+  int s = 0;
+  while (s + 1 < nslot && tab[s + 1].b0 <= (int)blockIdx.x) ++s;
+  return s;
+}
+
+// One iteration's first kernel for several independent systems (one slot
+// per system, each with its own matrix, vectors, partials and scalars).
+template <class V, class M, int RPT>
+__global__ __launch_bounds__(IB) void k_it1_multi(const It1Args<V, M> *__restrict__ tab, int nslot) {
+  extern __shared__ double lds_dyn[];
+  const It1Args<V, M> &a = tab[batch_slot(tab, nslot)];
+  if ((int)blockIdx.x - a.b0 >= a.nb) return;  // alignment gap before the next slot
+  it1_body<V, M, RPT>(a.A, a.AH, a.r, a.p, a.rt, a.pt, a.pn, a.ptn, a.z, a.zt, a.C, a.Ct, a.k, a.ld,
+                      a.capR, a.capRt, a.capZ, a.capZt, a.P3, a.P1, a.S, a.rec, a.it, a.first, a.rp,
+                      (int)blockIdx.x - a.b0, a.nb, lds_dyn);
 }
 
 // Reduce the k_it1 partials; sigma = (p~, z) - sum_j e_j zeta_j (= (p~, q));
@@ -770,14 +808,14 @@ __global__ __launch_bounds__(IB) void k_it1(
 // r_{i-1} -= C g, r~_{i-1} -= C~ g~ (re-projection, each rounded to storage
 // as a stored intermediate would be) and zeta_c -= g, zeta~_c -= g~.
 template <class V>
-__global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restrict__ xt,
-                                            V *__restrict__ r, V *__restrict__ rt,
-                                            const V *__restrict__ pn, const V *__restrict__ ptn,
-                                            const V *__restrict__ z, const V *__restrict__ zt,
-                                            const V *__restrict__ C, const V *__restrict__ Ct,
-                                            int k, int ld, const double *__restrict__ P1,
-                                            double *__restrict__ P3, Scalars *S, double *rec,
-                                            int it, int rp, double *zlog, int zstride) {
+__device__ __forceinline__ void it2_body(int n, V *__restrict__ x, V *__restrict__ xt,
+                                         V *__restrict__ r, V *__restrict__ rt,
+                                         const V *__restrict__ pn, const V *__restrict__ ptn,
+                                         const V *__restrict__ z, const V *__restrict__ zt,
+                                         const V *__restrict__ C, const V *__restrict__ Ct,
+                                         int k, int ld, const double *__restrict__ P1,
+                                         double *__restrict__ P3, Scalars *S, double *rec,
+                                         int it, int rp, double *zlog, int zstride, int bid, int nbl) {
   using T = typename Ar<V>::T;
   rp = sizeof(V) == 4 ? rp : 0;  // re-projection exists for float storage only
   __shared__ double lds[NW * 4];
@@ -787,8 +825,8 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
   // depend on the scalars: their loads are issued before the partials are
   // reduced, so that the reduction runs under their latency.
   constexpr int KPF = 4;
-  const int stride = gridDim.x * IB;
-  const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x;
+  const int stride = nbl * IB;
+  const int row0 = xcd_chunk(bid, nbl) * IB + threadIdx.x;
   V f[8] = {};
   V fc[KPF] = {}, fct[KPF] = {};
   if (row0 < n) {
@@ -809,10 +847,10 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
   }
   if (S->done) return;  // after the loads above are in flight
   const int nv1 = (3 * k + 1 + (rp ? 2 * k : 0)) * ND<T>::v;
-  breduce(P1, gridDim.x, nv1, tmp, zl);
+  breduce(P1, nbl, nv1, tmp, zl);
   T sigma = get<T>(zl, 3 * k);
   for (int j = 0; j < k; ++j) sigma -= get<T>(zl, 2 * k + j) * get<T>(zl, j);
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool lead = bid == 0 && threadIdx.x == 0;
   double *Ri = rec + (size_t)it * LOG_STRIDE;
   if (abs2(sigma) == 0.0 || !isfin(sigma)) {
     if (lead) {
@@ -923,7 +961,28 @@ __global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restr
 #pragma unroll
   for (int c = 0; c < ND<T>::v; ++c) wput(lds, 4, 2 + c, comp(rho, c));
   __syncthreads();
-  bstore(lds, 4, NW, 2 + ND<T>::v, P3);
+  bstore(lds, 4, NW, 2 + ND<T>::v, P3, bid);
+}
+
+template <class V>
+__global__ __launch_bounds__(IB) void k_it2(int n, V *__restrict__ x, V *__restrict__ xt,
+                                            V *__restrict__ r, V *__restrict__ rt,
+                                            const V *__restrict__ pn, const V *__restrict__ ptn,
+                                            const V *__restrict__ z, const V *__restrict__ zt,
+                                            const V *__restrict__ C, const V *__restrict__ Ct,
+                                            int k, int ld, const double *__restrict__ P1,
+                                            double *__restrict__ P3, Scalars *S, double *rec,
+                                            int it, int rp, double *zlog, int zstride) {
+  it2_body<V>(n, x, xt, r, rt, pn, ptn, z, zt, C, Ct, k, ld, P1, P3, S, rec, it, rp, zlog, zstride,
+              blockIdx.x, gridDim.x);
+}
+
+template <class V>
+__global__ __launch_bounds__(IB) void k_it2_multi(const It2Args<V> *__restrict__ tab, int nslot) {
+  const It2Args<V> &a = tab[batch_slot(tab, nslot)];
+  if ((int)blockIdx.x - a.b0 >= a.nb) return;  // alignment gap before the next slot
+  it2_body<V>(a.n, a.x, a.xt, a.r, a.rt, a.pn, a.ptn, a.z, a.zt, a.C, a.Ct, a.k, a.ld, a.P1, a.P3, a.S,
+              a.rec, a.it, a.rp, a.zlog, a.zstride, (int)blockIdx.x - a.b0, a.nb);
 }
 
 // Stopping test after the last launched iteration (one block).
@@ -949,6 +1008,24 @@ __global__ __launch_bounds__(IB) void k_itfin(const double *__restrict__ P3, int
   }
 }
 
+// k_itfin for several systems: block s is slot s's stopping test.
+template <class V>
+__global__ __launch_bounds__(IB) void k_itfin_multi(const ItfinArgs *__restrict__ tab) {
+  using T = typename Ar<V>::T;
+  __shared__ double tmp[IB];
+  __shared__ double red[8];
+  const ItfinArgs &a = tab[blockIdx.x];
+  if (!a.S->done) {
+    T beta;
+    (void)it_prologue<T>(a.P3, a.nb, a.S, a.rec, a.it, a.first, tmp, red, beta, true);
+  }
+  if (threadIdx.x == 0) {
+    a.hs->done = a.S->done;
+    a.hs->status = a.S->status;
+    a.hs->iter = a.S->iter;
+  }
+}
+
 // P3-layout partials (||r||^2, ||r~||^2, (r~, r)) of the initial residuals.
 template <class V>
 __global__ __launch_bounds__(IB) void k_init_p3(int n, const V *__restrict__ r,
@@ -969,7 +1046,7 @@ __global__ __launch_bounds__(IB) void k_init_p3(int n, const V *__restrict__ r,
 #pragma unroll
   for (int c = 0; c < ND<T>::v; ++c) wput(lds, 4, 2 + c, comp(rho, c));
   __syncthreads();
-  bstore(lds, 4, NW, 2 + ND<T>::v, P3);
+  bstore(lds, 4, NW, 2 + ND<T>::v, P3, blockIdx.x);
 }
 
 // Up to three dot products (a_i, b_i) as block partials (3 * ND values).
@@ -989,7 +1066,7 @@ __global__ __launch_bounds__(IB) void k_dots(int n, const V *a0, const V *b0, co
   put<T>(lds, 8, 1, d1);
   put<T>(lds, 8, 2, d2);
   __syncthreads();
-  bstore(lds, 8, NW, 3 * ND<T>::v, P);
+  bstore(lds, 8, NW, 3 * ND<T>::v, P, blockIdx.x);
 }
 
 // Restriction partials: [B^H u (k values), B2^H u2 (k values)].
@@ -1010,7 +1087,7 @@ __global__ __launch_bounds__(IB) void k_restrict(int n, const V *u, const V *B, 
     put<T>(lds, ls, k + j, b);
   }
   __syncthreads();
-  bstore(lds, ls, NW, 2 * k * ND<T>::v, P);
+  bstore(lds, ls, NW, 2 * k * ND<T>::v, P, blockIdx.x);
 }
 
 // One block: out[t] = fixed-order sum of the nb block partials.
@@ -1986,6 +2063,8 @@ namespace {
 inline unsigned nblk(size_t n) { return (unsigned)((n + RBICG_BLOCK - 1) / RBICG_BLOCK); }
 }
 
+bool iter_one_row(int n, int nb) { return (size_t)nb * IB >= (size_t)n; }
+
 int iter_grid(int n) {
   const int a = (n + IB - 1) / IB;
   const int b = (n + IB * RMAX - 1) / (IB * RMAX);
@@ -2008,6 +2087,29 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
     hipLaunchKernelGGL((k_it1<V, M, RMAX>), dim3(nb), dim3(IB), lds, st, A, AH, r, p, rt, pt, pn,
                        ptn, z, zt, C, Ct, k, ld, capR, capRt, capZ, capZt, P3, P1, S, rec, it, first,
                        rp);
+}
+template <class V>
+size_t it1_lds_bytes(int k, int rp) {
+  const int ndv = sizeof(V) == 16 ? 2 : 1;
+  const int rpv = sizeof(V) == 4 ? rp : 0;
+  return (size_t)NW * (3 * k + 1 + (rpv ? 2 * k : 0)) * ndv * sizeof(double);
+}
+template <class V, class M>
+void launch_it1_multi(hipStream_t st, const It1Args<V, M> *dtab, int nslot, int nblocks,
+                      size_t lds_bytes, bool rpt1) {
+  if (rpt1)
+    hipLaunchKernelGGL((k_it1_multi<V, M, 1>), dim3(nblocks), dim3(IB), lds_bytes, st, dtab, nslot);
+  else
+    hipLaunchKernelGGL((k_it1_multi<V, M, RMAX>), dim3(nblocks), dim3(IB), lds_bytes, st, dtab,
+                       nslot);
+}
+template <class V>
+void launch_it2_multi(hipStream_t st, const It2Args<V> *dtab, int nslot, int nblocks) {
+  hipLaunchKernelGGL((k_it2_multi<V>), dim3(nblocks), dim3(IB), 0, st, dtab, nslot);
+}
+template <class V>
+void launch_itfin_multi(hipStream_t st, const ItfinArgs *dtab, int nslot) {
+  hipLaunchKernelGGL((k_itfin_multi<V>), dim3(nslot), dim3(IB), 0, st, dtab);
 }
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
@@ -2225,9 +2327,14 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
                                  int);                                                       \
   template void launch_residual<V, M>(hipStream_t, const Sell<M> &, const V *, const V *,    \
                                       V *);                                                  \
-  template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);
+  template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);      \
+  template void launch_it1_multi<V, M>(hipStream_t, const It1Args<V, M> *, int, int, size_t, \
+                                       bool);
 
 #define INST_V(V)                                                                            \
+  template size_t it1_lds_bytes<V>(int, int);                                                \
+  template void launch_it2_multi<V>(hipStream_t, const It2Args<V> *, int, int);              \
+  template void launch_itfin_multi<V>(hipStream_t, const ItfinArgs *, int);                  \
   template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
                               const V *, const V *, const V *, const V *, const V *, int, int, \
                               const double *, double *, Scalars *, double *, int, int,       \

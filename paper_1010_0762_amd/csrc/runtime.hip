@@ -24,6 +24,7 @@
 #include "kernels.h"
 #include "matviews.h"
 #include "sec44.h"
+#include "batch.h"
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -386,6 +387,7 @@ struct rbicg_s {
   bool shifted = false;
   cplx shift = 0.0;
   ShiftWs *sw = nullptr;  // workspace of the batched shifted solves
+  rbicg_batch batch = nullptr;  // iteration chunks launched through this batch (rbicg_batch_attach)
   // Sec. 4.4 set-up (opts.pencil_setup = 1): per-iteration restrictions
   // zeta_i, zeta~_i (zstride doubles per iteration, indexed like log), their
   // pinned staging for one cycle, and the blocks carried to the next cycle
@@ -488,6 +490,9 @@ template <class M> Sell<M> view_AH(const rbicg_s *h) {
 }
 
 // ---------------------------------------------------------- typed helpers
+template <class V, class M> constexpr int batch_kind() {
+  return sizeof(V) == 4 ? BK_F32 : (sizeof(V) == 8 ? BK_F64 : (sizeof(M) == 16 ? BK_C128 : BK_C128_REAL_A));
+}
 template <class V> struct VK;
 template <> struct VK<double> { static constexpr int kind = 0; };
 template <> struct VK<cd> { static constexpr int kind = 1; };
@@ -1386,6 +1391,17 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       return 0;
     };
 
+    // while this run iterates, a batch it is attached to counts it among the
+    // solves whose chunks it waits for
+    struct BatchGuard {
+      rbicg_batch b;
+      explicit BatchGuard(rbicg_batch bb) : b(bb) {
+        if (b) batch_enter(b);
+      }
+      ~BatchGuard() {
+        if (b) batch_leave(b);
+      }
+    } batch_guard(h->batch);
     while (true) {
       // keep up to two chunks in flight
       while (!done && (int)flight.size() < 2 && launched < h->opt.maxit) {
@@ -1430,9 +1446,11 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         chunk = std::min(chunk, h->opt.maxit - launched);
         const int chunk_start = launched;
         // profiling: time every opts.profile-th chunk (events between launches)
-        const bool prof = h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
+        const bool prof = !h->batch && h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
                           (h->prof_chunks++ % h->opt.profile) == 0;
         const int eb = (slot_next % 2) * 3 * chunk;
+        // attached to a batch: the chunk's kernel arguments are handed to it
+        BatchChunk bc;
         for (int c = 0; c < chunk; ++c) {
           const int it = launched + 1;
           const int pos = (it - 1 - run_start) % s;
@@ -1445,14 +1463,27 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             capZt = (V *)ring_col(h->Zt, set, s + 1, pos + 1, h);
           }
           V *pn = (V *)h->p[1 - pc], *ptn = (V *)h->pt[1 - pc];
+          double *zl = rec_mode && ks > 0 ? h->zlog : nullptr;
+          if (h->batch) {
+            const It1Args<V, M> a1{A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn, ptn,
+                                   (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt,
+                                   h->P3, h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp,
+                                   0, 0};
+            const It2Args<V> a2{n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C, Ct,
+                                ks, ld, h->P1, h->P3, h->S, h->log, it, rp, zl, h->zstride, 0, 0};
+            bc.it1.insert(bc.it1.end(), (const char *)&a1, (const char *)&a1 + sizeof(a1));
+            bc.it2.insert(bc.it2.end(), (const char *)&a2, (const char *)&a2 + sizeof(a2));
+            pc = 1 - pc;
+            ++launched;
+            continue;
+          }
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c], h->st));
           launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
                            ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
                            h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 1], h->st));
           launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C,
-                        Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp,
-                        rec_mode && ks > 0 ? h->zlog : nullptr, h->zstride);
+                        Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp, zl, h->zstride);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 2], h->st));
           pc = 1 - pc;
           ++launched;
@@ -1461,8 +1492,20 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         const int slot = slot_next % 2;
         // (k_itfin writes done, status and iter into host slot `slot` itself; the
         // event's completion makes them visible to the host)
-        launch_itfin<V>(h->st, nb, h->P3, h->S, h->log, launched + 1, launched == run_start ? 1 : 0,
-                        h->hSd + slot);
+        if (h->batch) {
+          bc.kind = batch_kind<V, M>();
+          bc.one_row = iter_one_row(n, nb);
+          bc.nb = nb;
+          bc.lds = it1_lds_bytes<V>(ks, rp);
+          bc.len = chunk;
+          bc.fin = ItfinArgs{h->P3, nb, h->S, h->log, launched + 1, launched == run_start ? 1 : 0,
+                             h->hSd + slot};
+          bc.st = h->st;
+          TRY(batch_submit(h->batch, bc));
+        } else {
+          launch_itfin<V>(h->st, nb, h->P3, h->S, h->log, launched + 1, launched == run_start ? 1 : 0,
+                          h->hSd + slot);
+        }
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipEventRecord(h->sev[slot], h->st));
         flight.push_back({launched, slot, chunk_start, chunk, prof});
@@ -3020,6 +3063,12 @@ int bilinear_batch_impl(rbicg_s *h, int S, const cd *U, const cd *W, double tol,
   }
   h->shifted = false;
   return rc;
+}
+
+extern "C" int rbicg_batch_attach(rbicg_handle h, rbicg_batch b) {
+  if (!h) return rbicg_fail(RBICG_EINVAL, "null handle");
+  h->batch = b;
+  return RBICG_OK;
 }
 
 extern "C" int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, const void *W, double tol,

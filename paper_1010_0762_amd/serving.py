@@ -12,6 +12,10 @@ mix.
 
 The scheduler is plain Python threads: the solves run inside librbicg.so (the
 ctypes calls release the interpreter lock), the threads only hand out work.
+With ``batched=True`` every admitted request's handle is attached to one
+rbicg batch, so the iteration kernels of all requests that are iterating run
+in one set of launches (continuous batching at the launch level); results are
+bitwise those of the unbatched handles.
 """
 from __future__ import annotations
 
@@ -65,8 +69,15 @@ class Server:
     def __init__(self, slots: int = 4, hbm_budget: Optional[int] = None, prec: str = "mixed",
                  tol: float = 1e-8, inner_tol: float = 1e-5, s: int = 40,
                  keep_solutions: bool = False,
-                 execute: Optional[Callable] = None):
+                 execute: Optional[Callable] = None, batched: bool = False,
+                 window_us: float = 50.0):
         self.slots = slots
+        # continuous batching: the admitted requests' iteration chunks go
+        # through one rbicg batch (one set of launches for all of them)
+        self.batch = None
+        if batched:
+            from .solver import Batch
+            self.batch = Batch(max_slots=min(16, slots), window_us=window_us)
         self.prec = prec
         self.tol = tol
         self.inner_tol = inner_tol
@@ -102,7 +113,8 @@ class Server:
             # (stall guard; plain Algorithm 2 diverges on some of the larger
             # strongly convective systems)
             S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
-                       max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0)
+                       max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0,
+                       batch=self.batch)
             stats, sols = [], []
             for j in range(req.nsys):
                 b, bt = wl.request_rhs(req, j)

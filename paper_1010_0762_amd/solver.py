@@ -223,6 +223,38 @@ def solve_split_sequence(mats, bs, bts, *, k=20, s=40, tol=1e-8, maxit=10000, **
     return out
 
 
+class Batch:
+    """Continuous batching of iteration launches across solver handles
+    (rbicg_batch_*): handles created with ``batch=`` hand their chunks of
+    iterations to it, and it launches the chunks of all handles that are
+    iterating together."""
+
+    def __init__(self, max_slots=16, window_us=50.0):
+        self.lib = _lib.load()
+        h = ct.c_void_p()
+        _lib.check(self.lib.rbicg_batch_create(int(max_slots), float(window_us), ct.byref(h)),
+                   "rbicg_batch_create")
+        self.h = h
+
+    def stats(self) -> dict:
+        out = np.zeros(4)
+        _lib.check(self.lib.rbicg_batch_stats(self.h, _lib.dptr(out)), "rbicg_batch_stats")
+        return {"launches": int(out[0]), "chunks": int(out[1]), "handle_iterations": int(out[2]),
+                "max_chunks_per_launch": int(out[3]),
+                "chunks_per_launch": float(out[1] / max(out[0], 1))}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbicg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One handle: a matrix (and its explicit conjugate transpose), a recycle
     space and the device workspace, kept across the systems of a sequence.
@@ -231,7 +263,7 @@ class Solver:
 
     def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
                  svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
-                 stream=None, profile=False, stall_window=0, pencil_setup=0):
+                 stream=None, profile=False, stall_window=0, pencil_setup=0, batch=None):
         self.lib = _lib.load()
         o = _lib.rbicg_opts()
         self.lib.rbicg_default_opts(ct.byref(o))
@@ -267,6 +299,9 @@ class Solver:
                                        ct.byref(o), ct.byref(h))
             _lib.check(rc, "rbicg_create")
         self.h = h
+        self.batch = batch
+        if batch is not None:
+            _lib.check(self.lib.rbicg_batch_attach(self.h, batch.h), "rbicg_batch_attach")
 
     # --------------------------------------------------------------- helpers
     def _order(self):

@@ -14,8 +14,11 @@ oracle's own count changes by several percent when b is perturbed by 1e-13.
 The bars are therefore: plain BiCG iterates and counts as for any other size;
 with an injected recycle space, the count inside the oracle's own perturbation
 spread widened by 5%, sampled solution entries to 1e-6 and the first
-iterations' scalars to 1e-8; with the GPU's own recycle updates, properties
-that hold at any size (true residuals, C~^H C = I, determinism, no stagnation).
+iterations' scalars to 1e-8; with the GPU's own recycle updates over the whole
+sequence, every system's count inside the spread of the oracle's recycled
+sequence (tests/golden/cfg2seq_convdiff3d_64.json) widened by 5% and sampled
+solutions to 1e-6, plus properties that hold at any size (true residuals,
+C~^H C = I, determinism).
 """
 import json
 import os
@@ -130,6 +133,32 @@ def test_cfg2_sequence_properties(gold, setup):
         assert st["iters"] == st2["iters"] and st["k_used"] == st2["k_used"]
         assert torch.equal(x, x2) and torch.equal(xt, xt2)
     assert run1[0][0]["cycles"] == run1[0][0]["iters"] // seq.s
+
+
+GOLDSEQ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "cfg2seq_convdiff3d_64.json")
+
+
+def test_cfg2_recycled_sequence_matches_oracle(setup):
+    """The benchmark's whole sequence with the GPU's own cycle updates (Sec.
+    4.1-4.3) against the oracle's recycled sequence (Algorithm 2, the space of
+    system j carried to system j+1): every system's iteration count inside
+    the range of the oracle's runs (unperturbed and with b, b~ perturbed by
+    1e-13 relative), widened by 5%, and sampled solution entries of every
+    system to 1e-6 of the oracle's."""
+    seq, mats, b, bt = setup
+    with open(GOLDSEQ) as f:
+        g = json.load(f)
+    idx = np.asarray(g["sample_index"])
+    runs = np.asarray(g["iters_runs"])
+    out = _sequence(seq, mats, b, bt)
+    for j, (st, x, xt) in enumerate(out):
+        lo, hi = runs[:, j].min(), runs[:, j].max()
+        print(j, "gpu", st["iters"], "k", st["k_used"], "oracle range", lo, hi, flush=True)
+        assert st["status"] == 0 and st["relres"] <= seq.tol and st["relres_dual"] <= seq.tol
+        assert 0.95 * lo <= st["iters"] <= 1.05 * hi, (j, st["iters"], lo, hi)
+        assert _sample_rel(x, idx, g["x_sample"][j]) <= 1e-6, j
+        assert _sample_rel(xt, idx, g["xt_sample"][j]) <= 1e-6, j
 
 
 GOLD3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_shifted_48.json")
