@@ -73,7 +73,9 @@ def parse():
                     help="run the serving trace (continuous batching, p50/p99 latency) instead")
     ap.add_argument("--serving-n", type=int, default=40, help="requests in the serving trace")
     ap.add_argument("--serving-lam", type=float, default=50.0, help="arrival rate (req/s)")
-    ap.add_argument("--serving-slots", type=int, default=4, help="concurrent request slots")
+    ap.add_argument("--serving-slots", type=int, default=8, help="concurrent request slots")
+    ap.add_argument("--serving-window", type=float, default=20.0,
+                    help="microseconds a batched launch waits for the other iterating requests")
     ap.add_argument("--leg", default=None,
                     choices=("mixed", "shifted", "irka", "serving"),
                     help="run only this leg and print its JSON (for profiling one workload)")
@@ -517,14 +519,20 @@ def serving_leg(args):
            "trace": {"requests": len(trace), "lambda_per_s": args.serving_lam,
                      "systems": sum(r.nsys for r in trace),
                      "edges": sorted({r.edge for r in trace})}}
-    for name, slots, prec in (("batched_fp32_inner", args.serving_slots, "mixed"),
-                              ("one_at_a_time_fp64", 1, "f64")):
-        srv = serving.Server(slots=slots, prec=prec, tol=1e-8)
+    for name, slots, prec, batched in (
+            ("batched_fp32_inner", args.serving_slots, "mixed", True),
+            ("concurrent_unbatched_fp32_inner", args.serving_slots, "mixed", False),
+            ("one_at_a_time_fp64", 1, "f64", False)):
+        srv = serving.Server(slots=slots, prec=prec, tol=1e-8, batched=batched,
+                             window_us=args.serving_window)
         srv.prepare(trace)
         torch.cuda.synchronize()
         res = srv.run(trace)
         summ = serving.latency_summary(res)
         summ["slots"] = slots
+        if srv.batch is not None:
+            summ["batch"] = srv.batch.stats()
+            srv.batch.close()
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
     return out
 

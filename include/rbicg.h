@@ -377,7 +377,7 @@ int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, cons
                   const void *c, double *Ar, double *Er, double *br, double *cr);
 
 /* Continuous batching of iteration launches across handles (serving several
- * requests at once).  A batch owns a HIP stream.  Every handle attached to it
+ * requests at once).  A batch owns four HIP streams.  Every handle attached to it
  * keeps its own host thread, stream, matrix, recycle space and workspace, but
  * hands each chunk of iterations (the arguments of its iteration kernels) to
  * the batch instead of launching it; the batch launches the chunks of all

@@ -45,14 +45,16 @@ struct Pending {
   int rc = 0;
 };
 
-constexpr int NBUF = 4;  // table buffers in flight
+constexpr int NBUF = 8;  // table buffers in flight
+constexpr int NSTREAM = 4;  // batch streams (launches rotate over them)
 
 }  // namespace
 
 struct rbicg_batch_s {
   std::mutex mu;
   std::condition_variable cv;
-  hipStream_t st = nullptr;
+  hipStream_t sts[NSTREAM] = {};
+  hipStream_t st = nullptr;  // stream of the launch being built
   int max_slots = RBICG_BATCH_SLOTS;
   std::chrono::microseconds window{50};
   int active = 0;
@@ -171,6 +173,10 @@ size_t group_bytes(const std::vector<Pending *> &g, size_t a1, size_t a2) {
 // Enqueue the chunks in take on the batch stream (called by one thread at a
 // time, without the batch lock).
 int launch(rbicg_batch b, std::vector<Pending *> &take) {
+  // launches rotate over the batch streams, so that a long launch does not
+  // hold up the next one (each slot's chunks stay ordered through its own
+  // stream's events)
+  b->st = b->sts[(int)b->stat[0] % NSTREAM];
   // the batch runs after every slot's prior work
   for (auto *p : take) B_HIPCHECK(hipStreamWaitEvent(b->st, p->in, 0));
   // groups by kind and rows-per-thread mode, in hand-in order
@@ -297,10 +303,13 @@ extern "C" int rbicg_batch_create(int32_t max_slots, double window_us, rbicg_bat
   rbicg_batch b = new rbicg_batch_s();
   b->max_slots = max_slots;
   b->window = std::chrono::microseconds((long)window_us);
-  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
-    delete b;
-    return rbicg_fail(RBICG_EHIP, "hipStreamCreate failed");
-  }
+  for (int i = 0; i < NSTREAM; ++i)
+    if (hipStreamCreateWithFlags(&b->sts[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(b->sts[j]);
+      delete b;
+      return rbicg_fail(RBICG_EHIP, "hipStreamCreate failed");
+    }
+  b->st = b->sts[0];
   *out = b;
   return RBICG_OK;
 }
@@ -314,14 +323,14 @@ extern "C" int rbicg_batch_stats(rbicg_batch b, double *out) {
 
 extern "C" int rbicg_batch_destroy(rbicg_batch b) {
   if (!b) return RBICG_OK;
-  (void)hipStreamSynchronize(b->st);
+  for (int i = 0; i < NSTREAM; ++i) (void)hipStreamSynchronize(b->sts[i]);
   for (int i = 0; i < NBUF; ++i) {
     if (b->host[i]) (void)hipHostFree(b->host[i]);
     if (b->dev[i]) (void)hipFree(b->dev[i]);
     if (b->used[i]) (void)hipEventDestroy(b->used[i]);
   }
   for (auto e : b->events) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(b->st);
+  for (int i = 0; i < NSTREAM; ++i) (void)hipStreamDestroy(b->sts[i]);
   delete b;
   return RBICG_OK;
 }

@@ -70,8 +70,12 @@ class Server:
                  tol: float = 1e-8, inner_tol: float = 1e-5, s: int = 40,
                  keep_solutions: bool = False,
                  execute: Optional[Callable] = None, batched: bool = False,
-                 window_us: float = 50.0):
+                 window_us: float = 50.0, batch_max_rows: int = 262144):
         self.slots = slots
+        # requests of at most batch_max_rows unknowns go through the batch;
+        # larger ones fill the GPU on their own and keep their own launches
+        # (in one batch stream their long chunks would hold up the small ones)
+        self.batch_max_rows = batch_max_rows
         # continuous batching: the admitted requests' iteration chunks go
         # through one rbicg batch (one set of launches for all of them)
         self.batch = None
@@ -114,7 +118,7 @@ class Server:
             # strongly convective systems)
             S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
                        max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0,
-                       batch=self.batch)
+                       batch=self.batch if A.n <= self.batch_max_rows else None)
             stats, sols = [], []
             for j in range(req.nsys):
                 b, bt = wl.request_rhs(req, j)
