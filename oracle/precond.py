@@ -164,3 +164,139 @@ def rbicg_split_sequence(mats, bs, bts, k, s, tol, maxit=5000, update=True, svd_
         out.append(res)
         U, Ut = res.U_next, res.Ut_next
     return sols, out
+
+
+# ---------------------------------------------------------------- ILUT
+# General split preconditioning (Sec. 6 uses ILUT / ILUTP): the dual-threshold
+# incomplete factorization ILUT(tau, p) by row-wise (IKJ) elimination.
+# Reading (the paper's experiments use MATLAB's ILU with a drop tolerance and
+# give no more): row-wise (IKJ) elimination without pivoting, with the drop
+# rule scaled as MATLAB's: when the elimination of row i reaches column k < i,
+# the entry w_k (before division by the pivot u_kk) is dropped if
+# |w_k| < tau ||A(:, k)||_2, and a dropped multiplier updates nothing; after
+# the elimination an entry w_j, j > i, is dropped if |w_j| < tau ||A(:, j)||_2;
+# the diagonal is never dropped.  Afterwards at most p entries (the largest in
+# modulus, ties by column) are kept in the L part and in the U part besides
+# the diagonal (p = None: no count limit).  tau = 0 and p = None give the
+# complete LU factorization (no pivoting).
+
+
+def ilut(A, tau, p=None):
+    """ILUT(tau, p) of a square sparse matrix: (L unit lower, U upper) as
+    scipy CSR (complex128).  Plain loops over a dictionary working row, for
+    small matrices (the pins and parity cases)."""
+    import heapq
+    A = as_csr(A).astype(np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    cn = np.sqrt(np.asarray(abs(A).power(2).sum(axis=0)).ravel())   # column norms
+    Lrows, Urows = [], []   # per row: dict col -> value (U includes the diagonal)
+    for i in range(n):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        w = dict(zip(A.indices[lo:hi].tolist(), A.data[lo:hi].tolist()))
+        heap = [j for j in w if j < i]
+        heapq.heapify(heap)
+        seen = set(heap)
+        lpart = {}
+        while heap:
+            k = heapq.heappop(heap)
+            wk = w.pop(k)
+            if abs(wk) < tau * cn[k]:
+                continue                      # dropped multiplier
+            wk = wk / Urows[k][k]
+            lpart[k] = wk
+            for j, ukj in Urows[k].items():
+                if j <= k:
+                    continue
+                w[j] = w.get(j, 0.0) - wk * ukj
+                if j < i and j not in seen:
+                    seen.add(j)
+                    heapq.heappush(heap, j)
+        # finished row: drop small entries (never the diagonal), keep the p largest
+        lkeep = lpart
+        ukeep = {j: v for j, v in w.items() if j > i and abs(v) >= tau * cn[j]}
+        if p is not None:
+            lkeep = dict(sorted(lkeep.items(), key=lambda t: (-abs(t[1]), t[0]))[:p])
+            ukeep = dict(sorted(ukeep.items(), key=lambda t: (-abs(t[1]), t[0]))[:p])
+        d = w.get(i, 0.0)
+        if d == 0:
+            raise ZeroDivisionError(f"ILUT: zero pivot in row {i}")
+        ukeep[i] = d
+        Lrows.append(lkeep)
+        Urows.append(ukeep)
+
+    def to_csr(rows, unit):
+        r, c, v = [], [], []
+        for i, row in enumerate(rows):
+            for j in sorted(row):
+                r.append(i); c.append(j); v.append(row[j])
+            if unit:
+                r.append(i); c.append(i); v.append(1.0)
+        M = sp.csr_matrix((np.asarray(v, np.complex128), (r, c)), shape=(n, n))
+        M.sort_indices()
+        return M
+    return to_csr(Lrows, True), to_csr(Urows, False)
+
+
+class IlutSystem:
+    """Split preconditioning of one matrix by its ILUT factors (no
+    reordering): the dual pair A x = b, A^H x~ = b~ becomes
+        A^ y = L^{-1} b,   A^^H y~ = U^{-H} b~,   A^ = L^{-1} A U^{-1},
+        x = U^{-1} y,      x~ = L^{-H} y~."""
+
+    def __init__(self, A, tau, p=None):
+        self.A = as_csr(A).astype(np.complex128)
+        self.n = self.A.shape[0]
+        self.L, self.U = ilut(self.A, tau, p)
+
+    def operator(self) -> sp.csr_matrix:
+        """A^ = L^{-1} A U^{-1}, formed explicitly (dense, small n): the plain
+        definition of the operator RBiCG iterates with."""
+        Ad = self.A.toarray()
+        X = spla.spsolve_triangular(self.L.tocsr(), Ad, lower=True)              # L^{-1} A
+        Y = spla.spsolve_triangular(self.U.T.tocsr(), X.T, lower=True).T         # (L^{-1} A) U^{-1}
+        return sp.csr_matrix(Y)
+
+    def rhs(self, b, bt):
+        bh = spla.spsolve_triangular(self.L.tocsr(), np.asarray(b, np.complex128), lower=True)
+        ch = spla.spsolve_triangular(self.U.conj().T.tocsr(), np.asarray(bt, np.complex128), lower=True)
+        return bh, ch
+
+    def solution(self, y, yt):
+        x = spla.spsolve_triangular(self.U.tocsr(), np.asarray(y, np.complex128), lower=False)
+        xt = spla.spsolve_triangular(self.L.conj().T.tocsr(), np.asarray(yt, np.complex128), lower=False)
+        return x, xt
+
+
+def rbicg_ilut_sequence(mats, bs, bts, k, s, tol, tau, p=None, maxit=5000, update=True,
+                        svd_tol=1e-2, seed=0, max_restarts=2, real=True):
+    """The dual pairs in order, each split-preconditioned by its own
+    ILUT(tau, p), RBiCG on the preconditioned operators with the recycle
+    space carried between them.  Zero initial guesses; stopping on the
+    preconditioned residuals.  Returns (solutions [(x, x~)], results)."""
+    U = Ut = None
+    sols, out = [], []
+    for j, A in enumerate(mats):
+        ss = IlutSystem(A, tau, p)
+        M = ss.operator()
+        if real:
+            M = M.real.tocsr()
+        MH = M.conj().T.tocsr()
+        bh, ch = ss.rhs(bs[j], bts[j])
+        if real:
+            bh, ch = bh.real, ch.real
+        C = Ct = None
+        if U is not None and U.shape[1] > 0 and k > 0:
+            U, Ut, C, Ct = rc.biorthogonalize(M, MH, U, Ut, svd_tol)
+            if C is None:
+                U = Ut = None
+        res = rbicg(M, bh, ch, None, None, U, Ut, C, Ct, tol=tol, maxit=maxit, s=s, k=k,
+                    update=(update and k > 0), seed=seed, max_restarts=max_restarts,
+                    svd_tol=svd_tol)
+        x, xt = ss.solution(res.x, res.xt)
+        if real:
+            x, xt = x.real, xt.real
+        sols.append((x, xt))
+        out.append(res)
+        U, Ut = res.U_next, res.Ut_next
+    return sols, out

@@ -13,6 +13,7 @@ import scipy.sparse as sp
 
 import oracle
 from oracle.precond import SplitSystem, ilu0, rbicg_split_sequence, two_coloring
+import oracle.precond as pc
 from paper_1010_0762_amd import workloads as wl
 
 
@@ -96,3 +97,72 @@ def test_split_solve_complex_pair():
     assert res[0].status == "ok"
     assert np.linalg.norm(b - As @ x) <= 1e-8 * np.linalg.norm(b)
     assert np.linalg.norm(bt - As.conj().T @ xt) <= 1e-8 * np.linalg.norm(bt)
+
+
+# ------------------------------------------------------------ ILUT (general)
+def _rand_dd(n, seed, cplx=False):
+    A = wl.random_sparse(n, 5, seed, diag_shift=12.0, complex_vals=cplx)
+    return sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(n, n))
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_ilut_without_dropping_is_lu(cplx):
+    """tau = 0, no count limit: the complete LU factorization without
+    pivoting, which is unique: L unit lower, U upper, L U = A."""
+    A = _rand_dd(60, 3, cplx)
+    L, U = pc.ilut(A, 0.0)
+    assert sp.triu(L, 1).nnz == 0 and sp.tril(U, -1).nnz == 0
+    assert np.allclose(L.diagonal(), 1.0)
+    assert np.abs((L @ U - A).toarray()).max() <= 1e-12 * abs(A).max()
+
+
+def test_ilut_drop_rule_hand_example():
+    """A = [[4, 1, 0], [1, 4, 1], [2, 1, 4]] worked by hand; column norms
+    ||A(:,0)|| = sqrt(21) = 4.583, ||A(:,1)|| = sqrt(18) = 4.243,
+    ||A(:,2)|| = sqrt(17) = 4.123.
+    tau = 0.2 (thresholds 0.917, 0.849, 0.825): row 1 keeps w_0 = 1
+    (l_10 = 0.25), w_1 = 4 - 0.25 = 3.75, keeps w_2 = 1; row 2 keeps w_0 = 2
+    (l_20 = 0.5), then w_1 = 1 - 0.5 = 0.5 < 0.849 is dropped (no update), so
+    u_22 = 4.  tau = 0.25 (thresholds 1.146, 1.061, 1.031): row 1 drops w_0 = 1
+    and the U entry w_2 = 1, so u_11 = 4 and u_12 = 0; row 2 as before."""
+    A = sp.csr_matrix(np.array([[4.0, 1.0, 0.0], [1.0, 4.0, 1.0], [2.0, 1.0, 4.0]]))
+    L, U = pc.ilut(A, 0.2)
+    assert np.allclose(L.toarray().real, [[1, 0, 0], [0.25, 1, 0], [0.5, 0, 1]])
+    assert np.allclose(U.toarray().real, [[4, 1, 0], [0, 3.75, 1], [0, 0, 4]])
+    L, U = pc.ilut(A, 0.25)
+    assert np.allclose(L.toarray().real, [[1, 0, 0], [0, 1, 0], [0.5, 0, 1]])
+    assert np.allclose(U.toarray().real, [[4, 0, 0], [0, 4, 0], [0, 0, 4]])
+
+
+def test_ilut_limits():
+    """Huge tau: only the diagonal survives (L = I, U = diag A); p = 1: at
+    most one off-diagonal entry per row in each factor, the largest; no
+    fill on a tridiagonal matrix: ILUT = LU for every tau below the
+    entries' scale."""
+    A = _rand_dd(40, 9)
+    L, U = pc.ilut(A, 1e12)
+    assert (L - sp.identity(40)).nnz == 0 or np.abs((L - sp.identity(40)).toarray()).max() == 0
+    assert np.allclose(U.toarray(), np.diag(A.diagonal()))
+    L, U = pc.ilut(A, 0.0, p=1)
+    assert max(np.diff(sp.tril(L, -1).tocsr().indptr)) <= 1
+    assert max(np.diff(sp.triu(U, 1).tocsr().indptr)) <= 1
+    T = sp.diags([np.full(29, -1.0), np.full(30, 4.0), np.full(29, -2.0)], [-1, 0, 1], format="csr")
+    L, U = pc.ilut(T, 1e-3)
+    assert np.abs((L @ U - T).toarray()).max() <= 1e-13
+
+
+def test_ilut_split_system_solves_original_pair():
+    """The split-preconditioned pair recovers the original solutions: with
+    tau = 0 the operator L^{-1} A U^{-1} is the identity (one iteration), and
+    for tau = 0.05 RBiCG on it gives x, x~ with small original residuals."""
+    A = wl.convdiff(16, 2, (10.0, 5.0))
+    As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+    rng = np.random.default_rng(4)
+    b, bt = rng.uniform(size=A.n), rng.uniform(size=A.n)
+    ss = pc.IlutSystem(A, 0.0)
+    assert np.abs(ss.operator().toarray() - np.eye(A.n)).max() <= 1e-10
+    sols, res = pc.rbicg_ilut_sequence([A], [b], [bt], 0, 40, 1e-10, tau=0.05, update=False)
+    x, xt = sols[0]
+    assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(bt - As.T @ xt) / np.linalg.norm(bt) <= 1e-8
+    assert res[0].iters < 40
