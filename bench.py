@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--serving-window", type=float, default=20.0,
                     help="microseconds a batched launch waits for the other iterating requests")
     ap.add_argument("--leg", default=None,
-                    choices=("mixed", "shifted", "irka", "serving"),
+                    choices=("mixed", "shifted", "irka", "serving", "ilut"),
                     help="run only this leg and print its JSON (for profiling one workload)")
     ap.add_argument("--mixed-nsys", type=int, default=8, help="systems of the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true",
@@ -86,7 +86,7 @@ def parse():
                     help="skip the FP32-inner / FP64-outer leg (128^3, 8 systems)")
     ap.add_argument("--no-irka", action="store_true", help="skip the IRKA leg")
     ap.add_argument("--no-precond", action="store_true",
-                    help="skip the split-preconditioned (red-black ILU(0)) leg")
+                    help="skip the split-preconditioned legs (red-black ILU(0), ILUT)")
     ap.add_argument("--no-copy-ref", action="store_true",
                     help="skip the device-copy bandwidth reference")
     ap.add_argument("--no-shifted", action="store_true",
@@ -255,6 +255,97 @@ def precond_leg(args, seq, mats, b, bt):
             "host_setup_ms_once": round(setup_ms, 1), "iters_per_system": its,
             "us_per_iter": round(dt / max(1, sum(its)) * 1e6, 2),
             "max_true_relres": float(max(rel))}
+
+
+def ilut_leg(args, seq, mats, b, bt):
+    """Split ILUT preconditioning (Sec. 6) with device level-scheduled
+    triangular solves, in two settings: (a) the 2D experiment's shape of
+    Sec. 6.1 -- convection-diffusion with central differences on the
+    h = 1/64 grid (n = 3969; a checkerboard diffusion coefficient with jumps
+    of 1e3 stands in for the paper's, which only a figure gives), ILUT(0.05),
+    the same dual pair solved four times, k = 10, s = 40, tol 1e-8 -- with
+    recycling and with k = 0 (plain BiCG); (b) the
+    benchmark's 10-system 64^3 sequence, ILUT(0.05) per system, k = 20 and
+    k = 0.  The host factorizations run before the timed passes (timed
+    apart); a timed pass covers, per system, the right-hand-side transform,
+    the recycle-space move to the new preconditioned operator, the solve and
+    the solution transform.  One pass is timed after an untimed one; true
+    residuals of the original pairs are checked after it."""
+    import torch
+    import scipy.sparse as sp
+    from paper_1010_0762_amd import workloads as wl
+    from paper_1010_0762_amd.solver import ILUT, DeviceMatrix, Solver
+
+    def run(hmats, dmats, bs, bts, k, s, tol, tau):
+        # one factorization per distinct matrix (host), timed apart
+        t0 = time.perf_counter()
+        cache = {}
+        for A in hmats:
+            if id(A) not in cache:
+                cache[id(A)] = ILUT(A, tau)
+        Ps = [cache[id(A)] for A in hmats]
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        S = Solver(dmats[0], k=k, s=s, chunk=args.chunk)
+        sols = []
+
+        def one_pass():
+            its = []
+            sols.clear()
+            S.set_recycle(None, None)
+            for j in range(len(hmats)):
+                S.stream.synchronize()
+                S.attach_ilu(Ps[j])
+                # the handle on system j's matrix, the carried space against
+                # the new preconditioned operator
+                S.update_recycle(None if S.matrix is dmats[j] else dmats[j])
+                S._order()
+                bh, ch = Ps[j].rhs(bs[j], bts[j], stream=S.stream)
+                y, yt, st = S.solve(bh, ch, tol=tol)
+                sols.append(Ps[j].solution(y, yt, stream=S.stream))
+                its.append(st["iters"])
+            return its
+
+        one_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = one_pass()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rel = []
+        for A, (x, xt), bb, bbt in zip(hmats, sols, bs, bts):
+            As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+            bh_, bth_ = bb.cpu().numpy(), bbt.cpu().numpy()
+            rel.append(max(np.linalg.norm(bh_ - As @ x.cpu().numpy()) / np.linalg.norm(bh_),
+                           np.linalg.norm(bth_ - As.T @ xt.cpu().numpy()) / np.linalg.norm(bth_)))
+        info = Ps[0].info()
+        S.close()
+        for P in cache.values():
+            P.close()
+        print(f"ilut leg: k={k} n={hmats[0].n} systems={len(hmats)} iters={its} "
+              f"{dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        return {"solves_per_s": round(len(hmats) / dt, 3), "ms_per_sequence": round(dt * 1e3, 2),
+                "host_factorization_ms": round(setup_ms, 1), "iters_per_system": its,
+                "us_per_iter": round(dt / max(1, sum(its)) * 1e6, 2),
+                "max_true_relres": float(max(rel)),
+                "factor": {kk: info[kk] for kk in ("nnz_L", "nnz_U", "levels_L", "levels_U")}}
+
+    out = {}
+    # (a) Sec. 6.1 shape: one pair solved four times on the h = 1/64 grid,
+    # central differences, a jumping diffusion coefficient
+    A2 = wl.jump_convdiff2d()
+    rng = np.random.default_rng(wl.BASE_SEED + 61)
+    b2 = torch.as_tensor(rng.standard_normal(A2.n), device="cuda")
+    bt2 = torch.as_tensor(rng.standard_normal(A2.n), device="cuda")
+    D2 = DeviceMatrix(A2)
+    for k in (10, 0):
+        out[f"jump_convdiff2d_63^2_same_pair_x4_ilut0.05_k{k}_s40"] = run(
+            [A2] * 4, [D2] * 4, [b2] * 4, [bt2] * 4, k, 40, 1e-8, 0.05)
+    D2.close()
+    # (b) the benchmark's sequence
+    for k in (seq.k, 0):
+        out[f"convdiff3d_{args.N}^3_seq{len(mats)}_ilut0.05_k{k}_s{seq.s}"] = run(
+            seq.mats, mats, [b] * len(mats), [bt] * len(mats), k, seq.s, seq.tol, 0.05)
+    return out
 
 
 def kernel_at_k20(args, seq, mats, b, bt):
@@ -606,6 +697,9 @@ def main():
     mats = [DeviceMatrix(A) for A in seq.mats]
     b = torch.as_tensor(seq.b[0], device="cuda")
     bt = torch.as_tensor(seq.bt[0], device="cuda")
+    if args.leg == "ilut":
+        print(json.dumps({"leg": "ilut", "result": ilut_leg(args, seq, mats, b, bt)}), flush=True)
+        return
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     xts = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.nsys)]
     S = Solver(mats[0], k=seq.k, s=seq.s, prec="f64", chunk=args.chunk,
@@ -676,6 +770,7 @@ def main():
     other = (None if args.no_other_setup
              else pencil_setup_leg(args, seq, mats, b, bt, 1 - args.pencil_setup))
     precond = None if args.no_precond else precond_leg(args, seq, mats, b, bt)
+    ilut = None if args.no_precond else ilut_leg(args, seq, mats, b, bt)
     shifted = None if args.no_shifted else shifted_leg(args)
     irka_res = None if args.no_irka else irka_leg(args)
     mixed = None if args.no_mixed else mixed_leg(args)
@@ -727,6 +822,7 @@ def main():
         "irka": irka_res,
         "mixed_precision": mixed,
         "split_preconditioned": precond,
+        "split_ilut": ilut,
         "serving": served,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(seq),
     }

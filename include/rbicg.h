@@ -226,6 +226,53 @@ int rbicg_rbilu_solution(rbicg_rbilu P, const void *b, const void *bt, const voi
                          const void *ytB, void *x, void *xt, void *stream);
 int rbicg_rbilu_destroy(rbicg_rbilu P);
 
+/* Split ILUT preconditioning (Sec. 6 solves every system of its experiments
+ * split-preconditioned by an incomplete LU factorization with a drop
+ * tolerance, ILUT(0.05) in Sec. 6.1).  For A = L U + E (L unit lower, U upper)
+ * the dual pair A x = b, A^H x~ = b~ becomes
+ *   A^ y = b^,  A^^H y~ = c^,   A^ = L^{-1} A U^{-1},  b^ = L^{-1} b,
+ *   c^ = U^{-H} b~,   x = U^{-1} y,   x~ = L^{-H} y~,
+ * and RBiCG (with its recycle spaces) runs on A^ without forming it: every
+ * application of A^ (A^^H) is a triangular solve with U (L^H), one SpMV with
+ * A (A^H) and a triangular solve with L (U^H), each triangular solve one
+ * level-scheduled device kernel without barriers between levels (the
+ * primal and dual directions' solves share launches).
+ *   rbicg_ilut_create: host factorization of A (host or device CSR, real or
+ *     complex) by ILUT(droptol, fill) -- the drop rules of rbicg_host_ilut
+ *     (fill < 0: no per-row count limit) -- level schedules of L, U, L^H,
+ *     U^H, and their upload.  RBICG_EINVAL on a zero pivot.
+ *   rbicg_ilu_attach: h iterates with A^ of P from its next call on (NULL
+ *     detaches).  P must have h's order and value type (real / complex);
+ *     attach it before the rbicg_update_recycle* call that moves h to A, so
+ *     that the carried space is biorthogonalized against A^ (C = A^ U).  With
+ *     P attached, rbicg_solve_dual solves the
+ *     preconditioned pair: b, b~ are b^, c^; x, x~ are y, y~; stats and the
+ *     stopping test refer to the preconditioned residuals.  Not for
+ *     RBICG_F32_IN_F64_OUT handles, shifted solves, bilinear forms or handles
+ *     attached to a batch.  One handle at a time may use P.
+ *   rbicg_ilu_rhs: b^, c^ from b, b~; rbicg_ilu_solution: x, x~ from y, y~.
+ *     Device n-vectors, double (complex_vectors = 0; real P only) or
+ *     interleaved complex; on `stream`; calls on one P must not overlap.
+ *   rbicg_ilu_info: info[0..6] = n, nnz(L) (strict), nnz(U) (with the
+ *     diagonal), levels of L, levels of U, 1 if a triangular solve's bounded
+ *     wait ever gave up (results since are invalid), 1 if complex.
+ *   rbicg_ilu_set_waves: how many 64-lane waves work through the chunks of
+ *     a triangular solve (default 512; [4, 65536]); fewer waves poll less,
+ *     more cover wider levels.  Affects speed only, never results.
+ * A triangular solve whose dependency wait exceeds its bound (it cannot in a
+ * correct schedule) sets an error flag; the solve that used it returns
+ * RBICG_EHIP. */
+typedef struct rbicg_ilu_s *rbicg_ilu;
+int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, rbicg_ilu *out);
+int rbicg_ilu_attach(rbicg_handle h, rbicg_ilu P);
+int rbicg_ilu_rhs(rbicg_ilu P, const void *b, const void *bt, void *bh, void *ch,
+                  int32_t complex_vectors, void *stream);
+int rbicg_ilu_solution(rbicg_ilu P, const void *y, const void *yt, void *x, void *xt,
+                       int32_t complex_vectors, void *stream);
+int rbicg_ilu_info(rbicg_ilu P, int64_t *info);
+int rbicg_ilu_set_waves(rbicg_ilu P, int32_t waves);
+int rbicg_ilu_destroy(rbicg_ilu P);
+
 /* As rbicg_create, on a preloaded matrix (not owned by the handle). */
 int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);
 

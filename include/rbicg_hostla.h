@@ -62,6 +62,34 @@ int rbicg_host_heig(int32_t m, const double *A, double *w, double *V);
 int rbicg_host_biorth(int32_t k, const double *Gcc, const double *Gtt, const double *Gtc,
                       double tol, double *TU, double *TUt);
 
+/* ILUT(tau, p) of the split preconditioning of Sec. 6 (the factorization the
+ * library's rbicg_ilut_create uses), by row-wise elimination without
+ * pivoting.  The n x n matrix is CSR (rowptr[n+1], colind, values interleaved
+ * complex: real matrices carry zero imaginary parts).  Drop rules, scaled as
+ * MATLAB's drop tolerance: when row i's elimination reaches column k < i the
+ * entry w_k (before division by the pivot u_kk) is dropped if
+ * |w_k| < tau ||A(:,k)||_2, and a dropped entry updates nothing; after the
+ * elimination an entry w_j, j > i, is dropped if |w_j| < tau ||A(:,j)||_2; the
+ * diagonal is kept; p >= 0 keeps at most p off-diagonal entries per row in
+ * each factor (largest modulus first, ties by column), p < 0 no limit.
+ * Outputs: nnz[0] = entries of L (strictly lower, unit diagonal implied),
+ * nnz[1] = entries of U (with the diagonal); with Lrp/Lci/Lv (n+1, nnz[0],
+ * 2*nnz[0]) and Urp/Uci/Uv non-NULL the factors in CSR, columns ascending
+ * (call once with them NULL for the sizes).  -1 on bad arguments or a zero
+ * pivot. */
+int rbicg_host_ilut(int32_t n, const int32_t *rowptr, const int32_t *colind,
+                    const double *values, double tau, int32_t p, int64_t *nnz, int32_t *Lrp,
+                    int32_t *Lci, double *Lv, int32_t *Urp, int32_t *Uci, double *Uv);
+
+/* Level schedule of a triangular solve with the CSR matrix T (lower = 1: row
+ * i depends on its columns j < i, else on j > i; other entries are ignored):
+ * level(i) = 1 + the largest level of the rows it depends on (0 if none).
+ * order lists the rows level by level (ascending inside a level), each level
+ * padded with -1 to a multiple of pad; *len its length (order NULL: length
+ * only).  Returns the number of levels, or -1. */
+int rbicg_host_levels(int32_t n, const int32_t *rowptr, const int32_t *colind, int32_t lower,
+                      int32_t pad, int32_t *order, int64_t *len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -293,6 +293,7 @@ def rbicg_ilut_sequence(mats, bs, bts, k, s, tol, tau, p=None, maxit=5000, updat
         res = rbicg(M, bh, ch, None, None, U, Ut, C, Ct, tol=tol, maxit=maxit, s=s, k=k,
                     update=(update and k > 0), seed=seed, max_restarts=max_restarts,
                     svd_tol=svd_tol)
+        res.k_used = 0 if U is None else U.shape[1]   # recycle dimension the solve started with
         x, xt = ss.solution(res.x, res.xt)
         if real:
             x, xt = x.real, xt.real

@@ -63,7 +63,7 @@ def build(verbose: bool = False) -> str:
     objs = [j[-1] for j in jobs]
     tmp = LIB + ".tmp"
     _run([cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs,
-          "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+          "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"])
     os.replace(tmp, LIB)
     return LIB
 

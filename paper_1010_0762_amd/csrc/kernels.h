@@ -31,6 +31,36 @@ template <class V>
 void launch_itfin(hipStream_t st, int nb, const double *P3, Scalars *S, double *rec, int it,
                   int first, Scalars *hs);
 
+// ---- split preconditioning by triangular factors (ILUT) ----
+// A triangular factor for k_sptrsv: the strictly triangular part in CSR (rp,
+// ci, v over the n rows), the diagonal (NULL: unit), and the level-scheduled
+// row order (len entries, -1 padding; levels padded to whole waves).
+template <class M>
+struct TriDev {
+  int n, len;
+  const int *order, *rp, *ci;
+  const M *v, *diag;
+};
+template <class V>
+void launch_op_dir(hipStream_t st, int nb, int n, const V *r, const V *p, const V *rt, const V *pt,
+                   V *pn, V *ptn, V *capR, V *capRt, const double *P3, Scalars *S, double *rec,
+                   int it, int first);
+template <class V>
+void launch_op_restr(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *ptn,
+                     const V *C, const V *Ct, int k, int ld, V *capZ, V *capZt, double *P1,
+                     const Scalars *S);
+// y = A x; S may be NULL (else nothing happens after the stopping test)
+template <class V, class M>
+void launch_spmv(hipStream_t st, const Sell<M> &A, const V *x, V *y, const Scalars *S);
+// T0 x0 = b0 and, when T1 is given, T1 x1 = b1 (see k_sptrsv): two launches
+// (x0, x1 marked pending and the counter cleared, then the solves on `waves`
+// waves); V double or complex; b must alias neither x
+template <class V, class M>
+void launch_sptrsv(hipStream_t st, const TriDev<M> &T0, const V *b0, V *x0, const TriDev<M> *T1,
+                   const V *b1, V *x1, int *counter, int waves, const Scalars *S, int *err);
+template <class V>
+void launch_rsub(hipStream_t st, int n, const V *b, const V *t, V *out);
+
 // ---- batched launches: several independent systems ("slots") per launch ----
 #define RBICG_BATCH_SLOTS 16
 // Arguments of one slot of k_it1_multi / k_it2_multi: those of launch_it1 /

@@ -1008,6 +1008,242 @@ __global__ __launch_bounds__(IB) void k_itfin(const double *__restrict__ P3, int
   }
 }
 
+// ------------------------------------------------- split preconditioning
+// Iteration with the split-preconditioned operator A^ = L^{-1} A U^{-1}
+// (ILUT factors): k_it1's work in three steps, because A^ p needs whole
+// triangular solves between the SpMV and the restriction:
+//   k_op_dir    prologue (stopping test, beta) and p = r + beta p,
+//               p~ = r~ + conj(beta) p~ (cycle captures of r_{i-1}, r~_{i-1});
+//   A^ p, A^^H p~ by k_sptrsv (U, L^H) / k_spmv / k_sptrsv (L, U^H);
+//   k_op_restr  the partials k_it2 reads: zeta = C~^H z, zeta~ = C^H z~,
+//               p~^H C and (p~, z) (cycle captures of z, z~).
+template <class V>
+__global__ __launch_bounds__(IB) void k_op_dir(int n, const V *__restrict__ r,
+                                               const V *__restrict__ p, const V *__restrict__ rt,
+                                               const V *__restrict__ pt, V *__restrict__ pn,
+                                               V *__restrict__ ptn, V *capR, V *capRt,
+                                               const double *__restrict__ P3, Scalars *S,
+                                               double *rec, int it, int first) {
+  using T = typename Ar<V>::T;
+  __shared__ double tmp[IB];
+  __shared__ double red[8];
+  if (S->done) return;
+  T beta;
+  if (!it_prologue<T>(P3, gridDim.x, S, rec, it, first, tmp, red, beta, blockIdx.x == 0)) return;
+  const T betac = cj(beta);
+  const int stride = gridDim.x * IB;
+  for (int row = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x; row < n; row += stride) {
+    const V rv = r[row], rtv = rt[row];
+    pn[row] = down<V>(up(rv) + beta * up(p[row]));
+    ptn[row] = down<V>(up(rtv) + betac * up(pt[row]));
+    if (capR) {
+      capR[row] = rv;
+      capRt[row] = rtv;
+    }
+  }
+}
+
+template <class V>
+__global__ __launch_bounds__(IB) void k_op_restr(int n, const V *__restrict__ z,
+                                                 const V *__restrict__ zt,
+                                                 const V *__restrict__ ptn,
+                                                 const V *__restrict__ C, const V *__restrict__ Ct,
+                                                 int k, int ld, V *capZ, V *capZt,
+                                                 double *__restrict__ P1, const Scalars *S) {
+  using T = typename Ar<V>::T;
+  extern __shared__ double lds[];
+  if (S->done) return;
+  const int ls = (3 * k + 1) * ND<T>::v;
+  const int stride = gridDim.x * IB;
+  const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * IB + threadIdx.x;
+  T s0 = zero<T>();
+  for (int row = row0; row < n; row += stride) {
+    const V zz = z[row], zzt = zt[row];
+    s0 += cj(up(ptn[row])) * up(zz);
+    if (capZ) {
+      capZ[row] = zz;
+      capZt[row] = zzt;
+    }
+  }
+  put<T>(lds, ls, 3 * k, s0);
+  constexpr int G = sizeof(V) == 16 ? 2 : 4;
+  for (int j0 = 0; j0 < k; j0 += G) {
+    T a[G], b[G], e[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      a[g] = zero<T>();
+      b[g] = zero<T>();
+      e[g] = zero<T>();
+    }
+    for (int row = row0; row < n; row += stride) {
+      const T zz = up(z[row]), zzt = up(zt[row]), cptv = cj(up(ptn[row]));
+      V cb[G], ctb[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const size_t off = (size_t)min(j0 + g, k - 1) * ld + row;
+        cb[g] = C[off];
+        ctb[g] = Ct[off];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const T cv = up(cb[g]), ctv = up(ctb[g]);
+        a[g] += cj(ctv) * zz;
+        b[g] += cj(cv) * zzt;
+        e[g] += cptv * cv;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (j0 + g < k) {
+        put<T>(lds, ls, j0 + g, a[g]);
+        put<T>(lds, ls, k + j0 + g, b[g]);
+        put<T>(lds, ls, 2 * k + j0 + g, e[g]);
+      }
+  }
+  __syncthreads();
+  bstore(lds, ls, NW, ls, P1, blockIdx.x);
+}
+
+// 1 / d as the vector type (d real or complex)
+template <class T> __device__ __forceinline__ T inv_as(double d);
+template <> __device__ __forceinline__ double inv_as<double>(double d) { return 1.0 / d; }
+template <> __device__ __forceinline__ cd inv_as<cd>(double d) { return cd{1.0 / d, 0.0}; }
+template <class T> __device__ __forceinline__ T inv_as(cd d);
+template <> __device__ __forceinline__ cd inv_as<cd>(cd d) { return cdiv(cd{1.0, 0.0}, d); }
+
+// y = A x (sliced ELL, one row per thread); nothing after the stopping test.
+template <class V, class M>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_spmv(Sell<M> A, const V *__restrict__ x,
+                                                      V *__restrict__ y, const Scalars *S) {
+  using T = typename Ar<V>::T;
+  if (S && S->done) return;
+  const int row = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (row < A.n) y[row] = down<V>(spmv_plain<V, M, T>(A, row, x));
+}
+
+// Triangular solves T x = b by level schedule, without barriers between
+// levels, two independent solves per launch (the primal and the dual
+// direction of one step of A^ p / A^^H p~).  Work unit: a chunk of 64
+// consecutive positions of a solve's order (one wave; order lists the rows
+// level by level, each level padded with -1 to whole chunks, so a chunk's
+// rows never depend on each other).  A fixed number of waves take chunks from
+// a counter, the two solves' chunks interleaved; a row waits only for rows of
+// earlier chunks of its solve, which were taken earlier by waves that are
+// running, so the waits end.  Keeping the number of waves near the width of a
+// few levels (rather than one wave per chunk) keeps the polling traffic to
+// the frontier.  The values carry their own readiness: x is first filled with
+// TRSV_PENDING (k_trsv_pending), a signalling NaN that no arithmetic produces
+// (operations return quiet NaNs); a row polls each value it needs with
+// device-coherent 64-bit loads until it differs from the sentinel (a complex
+// value is two such words, each polled) and publishes its own with
+// device-coherent stores: the polled word is the datum, so neither flags nor
+// cache invalidations are needed.  The wait is bounded: past SPIN_MAX polls,
+// or once another row has set *err, the row sets *err and goes on (the caller
+// reports an error).
+#define SPIN_MAX (1 << 22)
+#define TRSV_PENDING 0x7FF4C0DE5E471E00ULL
+#define TRSV_QNAN 0x7FF8000000000000ULL
+
+// x0 (n0 values) and x1 (n1; may be absent) to the sentinel, the chunk
+// counter to zero
+template <class V>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_trsv_pending(int n0, V *x0, int n1, V *x1,
+                                                              int *counter, const Scalars *S) {
+  constexpr int NWD = sizeof(V) / 8;
+  if (S && S->done) return;
+  const int i = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i == 0) *counter = 0;
+  if (i < n0) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(x0) + (size_t)i * NWD;
+#pragma unroll
+    for (int c = 0; c < NWD; ++c) w[c] = TRSV_PENDING;
+  }
+  if (x1 && i < n1) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(x1) + (size_t)i * NWD;
+#pragma unroll
+    for (int c = 0; c < NWD; ++c) w[c] = TRSV_PENDING;
+  }
+}
+
+// One row of T x = b (row < 0: padding, nothing to do).
+template <class V, class M>
+__device__ __forceinline__ void trsv_row(const TriDev<M> &Tm, const V *__restrict__ b, V *x,
+                                         int row, int *err) {
+  using T = typename Ar<V>::T;
+  constexpr int NWD = sizeof(V) / 8;
+  if (row < 0) return;
+  unsigned long long *xw = reinterpret_cast<unsigned long long *>(x);
+  T acc = up(b[row]);
+  for (int e = Tm.rp[row]; e < Tm.rp[row + 1]; ++e) {
+    const unsigned long long *src = xw + (size_t)Tm.ci[e] * NWD;
+    unsigned long long wv[NWD];
+#pragma unroll
+    for (int c = 0; c < NWD; ++c) {
+      int spins = 0;
+      while ((wv[c] = __hip_atomic_load(src + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ==
+             TRSV_PENDING) {
+        // past the bound, or once any row has given up: stop waiting
+        if (++spins > SPIN_MAX ||
+            ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    V xv;
+    __builtin_memcpy(&xv, wv, sizeof(V));
+    acc -= up(Tm.v[e]) * up(xv);
+  }
+  if (Tm.diag) acc = acc * inv_as<T>(up(Tm.diag[row]));
+  const V out = down<V>(acc);
+  unsigned long long ow[NWD];
+  __builtin_memcpy(ow, &out, sizeof(V));
+#pragma unroll
+  for (int c = 0; c < NWD; ++c) {
+    if (ow[c] == TRSV_PENDING) ow[c] = TRSV_QNAN;  // an input that carried the sentinel itself
+    __hip_atomic_store(xw + (size_t)row * NWD + c, ow[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ns = 1 or 2 solves (T0, b0, x0) and (T1, b1, x1); len of both a multiple of 64
+template <class V, class M>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_sptrsv(TriDev<M> T0, const V *__restrict__ b0,
+                                                        V *x0, TriDev<M> T1,
+                                                        const V *__restrict__ b1, V *x1, int ns,
+                                                        int *counter, const Scalars *S, int *err) {
+  if (S && S->done) return;
+  const int lane = threadIdx.x & 63;
+  const int nc0 = T0.len >> 6, nc1 = ns > 1 ? T1.len >> 6 : 0;
+  const int both = 2 * min(nc0, nc1), total = nc0 + nc1;
+  while (true) {
+    int c = 0;
+    if (lane == 0) c = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c = __builtin_amdgcn_readfirstlane(c);
+    if (c >= total) break;
+    // interleave the two solves while both have chunks left
+    bool first;
+    int lc;
+    if (c < both) {
+      first = (c & 1) == 0;
+      lc = c >> 1;
+    } else {
+      first = nc0 > nc1;
+      lc = (c - both) + (both >> 1);
+    }
+    if (first) trsv_row<V, M>(T0, b0, x0, T0.order[lc * 64 + lane], err);
+    else trsv_row<V, M>(T1, b1, x1, T1.order[lc * 64 + lane], err);
+  }
+}
+
+// out = b - t (out may be t)
+template <class V>
+__global__ void k_rsub(int n, const V *__restrict__ b, const V *t, V *out) {
+  using T = typename Ar<V>::T;
+  const int i = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i < n) out[i] = down<V>(up(b[i]) - up(t[i]));
+}
+
 // k_itfin for several systems: block s is slot s's stopping test.
 template <class V>
 __global__ __launch_bounds__(IB) void k_itfin_multi(const ItfinArgs *__restrict__ tab) {
@@ -2089,6 +2325,43 @@ void launch_it1(hipStream_t st, int nb, const Sell<M> &A, const Sell<M> &AH, con
                        rp);
 }
 template <class V>
+void launch_op_dir(hipStream_t st, int nb, int n, const V *r, const V *p, const V *rt, const V *pt,
+                   V *pn, V *ptn, V *capR, V *capRt, const double *P3, Scalars *S, double *rec,
+                   int it, int first) {
+  hipLaunchKernelGGL((k_op_dir<V>), dim3(nb), dim3(IB), 0, st, n, r, p, rt, pt, pn, ptn, capR,
+                     capRt, P3, S, rec, it, first);
+}
+template <class V>
+void launch_op_restr(hipStream_t st, int nb, int n, const V *z, const V *zt, const V *ptn,
+                     const V *C, const V *Ct, int k, int ld, V *capZ, V *capZt, double *P1,
+                     const Scalars *S) {
+  const size_t lds = it1_lds_bytes<V>(k, 0);
+  hipLaunchKernelGGL((k_op_restr<V>), dim3(nb), dim3(IB), lds, st, n, z, zt, ptn, C, Ct, k, ld,
+                     capZ, capZt, P1, S);
+}
+template <class V, class M>
+void launch_spmv(hipStream_t st, const Sell<M> &A, const V *x, V *y, const Scalars *S) {
+  hipLaunchKernelGGL((k_spmv<V, M>), dim3(nblk(A.n)), dim3(RBICG_BLOCK), 0, st, A, x, y, S);
+}
+template <class V, class M>
+void launch_sptrsv(hipStream_t st, const TriDev<M> &T0, const V *b0, V *x0, const TriDev<M> *T1,
+                   const V *b1, V *x1, int *counter, int waves, const Scalars *S, int *err) {
+  const int ns = T1 ? 2 : 1;
+  const long chunks = (long)(T0.len >> 6) + (T1 ? (T1->len >> 6) : 0);
+  if (chunks == 0) return;
+  const int n1 = T1 ? T1->n : 0;
+  hipLaunchKernelGGL((k_trsv_pending<V>), dim3(nblk(std::max(T0.n, n1))), dim3(RBICG_BLOCK), 0, st,
+                     T0.n, x0, n1, T1 ? x1 : nullptr, counter, S);
+  const int w = (int)std::min<long>(chunks, std::max(4, waves));
+  const int blocks = (w + 3) / 4;  // four waves per block
+  hipLaunchKernelGGL((k_sptrsv<V, M>), dim3(blocks), dim3(RBICG_BLOCK), 0, st, T0, b0, x0,
+                     T1 ? *T1 : T0, b1, x1, ns, counter, S, err);
+}
+template <class V>
+void launch_rsub(hipStream_t st, int n, const V *b, const V *t, V *out) {
+  hipLaunchKernelGGL((k_rsub<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, b, t, out);
+}
+template <class V>
 size_t it1_lds_bytes(int k, int rp) {
   const int ndv = sizeof(V) == 16 ? 2 : 1;
   const int rpv = sizeof(V) == 4 ? rp : 0;
@@ -2329,10 +2602,19 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
                                       V *);                                                  \
   template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);      \
   template void launch_it1_multi<V, M>(hipStream_t, const It1Args<V, M> *, int, int, size_t, \
-                                       bool);
+                                       bool);                                                 \
+  template void launch_spmv<V, M>(hipStream_t, const Sell<M> &, const V *, V *,              \
+                                  const Scalars *);
 
 #define INST_V(V)                                                                            \
   template size_t it1_lds_bytes<V>(int, int);                                                \
+  template void launch_op_dir<V>(hipStream_t, int, int, const V *, const V *, const V *,     \
+                                 const V *, V *, V *, V *, V *, const double *, Scalars *,   \
+                                 double *, int, int);                                         \
+  template void launch_op_restr<V>(hipStream_t, int, int, const V *, const V *, const V *,   \
+                                   const V *, const V *, int, int, V *, V *, double *,       \
+                                   const Scalars *);                                          \
+  template void launch_rsub<V>(hipStream_t, int, const V *, const V *, V *);                 \
   template void launch_it2_multi<V>(hipStream_t, const It2Args<V> *, int, int);              \
   template void launch_itfin_multi<V>(hipStream_t, const ItfinArgs *, int);                  \
   template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
@@ -2362,6 +2644,16 @@ INST_VM(double, double)
 INST_VM(cd, double)
 INST_VM(cd, cd)
 INST_VM(float, float)
+// triangular solves: FP64 words only (real and complex vectors)
+template void launch_sptrsv<double, double>(hipStream_t, const TriDev<double> &, const double *,
+                                            double *, const TriDev<double> *, const double *,
+                                            double *, int *, int, const Scalars *, int *);
+template void launch_sptrsv<cd, double>(hipStream_t, const TriDev<double> &, const cd *, cd *,
+                                        const TriDev<double> *, const cd *, cd *, int *, int,
+                                        const Scalars *, int *);
+template void launch_sptrsv<cd, cd>(hipStream_t, const TriDev<cd> &, const cd *, cd *,
+                                    const TriDev<cd> *, const cd *, cd *, int *, int,
+                                    const Scalars *, int *);
 INST_V(double)
 INST_V(cd)
 INST_V(float)

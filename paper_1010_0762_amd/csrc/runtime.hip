@@ -25,6 +25,7 @@
 #include "matviews.h"
 #include "sec44.h"
 #include "batch.h"
+#include "ilut.h"
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -315,6 +316,44 @@ struct ShiftWs {
   }
 };
 
+// ==================================================== split preconditioner
+// ILUT factors of one matrix on the device: L (unit lower), U (upper), and
+// their conjugate transposes for the dual operator, each as its strictly
+// triangular part, its diagonal (U, U^H) and a level-scheduled row order;
+// three workspaces (iteration stream, cycle-end stream, rhs/solution calls),
+// each with four n-vectors and the chunk counter of the triangular solves.
+struct rbicg_ilu_s {
+  int n = 0;
+  bool complex_vals = false;
+  int waves = 512;  // waves that work through the chunks of a triangular solve
+  struct Tri {
+    int len = 0, levels = 0;
+    int64_t nnz = 0;
+    int *order = nullptr, *rp = nullptr, *ci = nullptr;
+    void *v = nullptr, *diag = nullptr;
+  } L, U, LH, UH;
+  struct Ws {
+    void *q[4] = {};
+    int *counter = nullptr;
+  } ws[3];
+  int *err = nullptr;
+  std::vector<void *> allocs;
+  ~rbicg_ilu_s() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+  template <class M> TriDev<M> view(const Tri &t) const {
+    TriDev<M> d;
+    d.n = n;
+    d.len = t.len;
+    d.order = t.order;
+    d.rp = t.rp;
+    d.ci = t.ci;
+    d.v = (const M *)t.v;
+    d.diag = (const M *)t.diag;
+    return d;
+  }
+};
+
 // ====================================================================== handle
 struct rbicg_s {
   rbicg_opts opt{};
@@ -388,6 +427,7 @@ struct rbicg_s {
   cplx shift = 0.0;
   ShiftWs *sw = nullptr;  // workspace of the batched shifted solves
   rbicg_batch batch = nullptr;  // iteration chunks launched through this batch (rbicg_batch_attach)
+  rbicg_ilu ilu = nullptr;      // split preconditioner: the operator is L^{-1} A U^{-1} (rbicg_ilu_attach)
   // Sec. 4.4 set-up (opts.pencil_setup = 1): per-iteration restrictions
   // zeta_i, zeta~_i (zstride doubles per iteration, indexed like log), their
   // pinned staging for one cycle, and the blocks carried to the next cycle
@@ -465,7 +505,20 @@ void kernel_bytes(const rbicg_s *h, int k, double out[2]) {
 double alg_bytes_iter(const rbicg_s *h, int k) {
   double kb[2];
   kernel_bytes(h, k, kb);
-  return kb[0] + kb[1];
+  double b = kb[0] + kb[1];
+  if (h->ilu) {
+    // per triangular solve: the factor (values, columns, row pointers, level
+    // order, diagonal), b read, x and the flags written; the SpMVs' vectors
+    // (x read, y written, both directions) and the split kernels' re-reads
+    // of p, p~ (the direction update) and p~ (the restriction)
+    const rbicg_ilu_s *P = h->ilu;
+    const double bm = (double)h->mat->A.vbytes, n = h->n, vb = (double)h->vb;
+    for (const rbicg_ilu_s::Tri *T : {&P->L, &P->U, &P->LH, &P->UH})
+      b += (double)T->nnz * (bm + 4.0) + 4.0 * (n + 1.0) + 4.0 * T->len +
+           (T->diag ? n * bm : 0.0) + 2.0 * n * vb + 4.0 * n;
+    b += 4.0 * n * vb + 3.0 * n * vb;
+  }
+  return b;
 }
 
 // views of the handle's matrix and of its conjugate transpose, with the
@@ -487,6 +540,96 @@ template <class M> Sell<M> view_AH(const rbicg_s *h) {
     v.shi = -h->shift.imag();
   }
   return v;
+}
+
+// ------------------------------------------------ operator of the handle
+// The handle iterates with A, or with a split preconditioner attached with
+// A^ = L^{-1} A U^{-1} (dual A^^H = U^{-H} A^H L^{-H}), applied as two
+// triangular solves around one SpMV.  The cycle-end stream (jst) and the
+// iteration stream use separate workspaces, so that both may apply A^ at once.
+rbicg_ilu_s::Ws &ilu_ws(rbicg_s *h) { return h->ilu->ws[h->st == h->jst ? 1 : 0]; }
+
+// x0 = T_f0^{-1} b0 and, when f1 >= 0, x1 = T_f1^{-1} b1 in one pair of
+// launches; factors 0 L, 1 U, 2 L^H, 3 U^H.
+template <class V, class M>
+void ilu_trsv(hipStream_t st, rbicg_ilu_s *P, rbicg_ilu_s::Ws &w, int f0, const V *b0, V *x0,
+              int f1, const V *b1, V *x1, const Scalars *S) {
+  auto tri = [&](int f) -> const rbicg_ilu_s::Tri & {
+    return f == 0 ? P->L : f == 1 ? P->U : f == 2 ? P->LH : P->UH;
+  };
+  const TriDev<M> T0 = P->view<M>(tri(f0));
+  if (f1 >= 0) {
+    const TriDev<M> T1 = P->view<M>(tri(f1));
+    launch_sptrsv<V, M>(st, T0, b0, x0, &T1, b1, x1, w.counter, P->waves, S, P->err);
+  } else {
+    launch_sptrsv<V, M>(st, T0, b0, x0, nullptr, (const V *)nullptr, (V *)nullptr, w.counter,
+                        P->waves, S, P->err);
+  }
+}
+
+// y0 = A^ x0 and y1 = A^^H x1 (either pair may be absent; y0, y1 must not be
+// workspace vectors or alias the x's): the two directions' triangular solves
+// share launches.  S: the kernels do nothing once the stopping test has
+// fired (NULL: always run).  FP64 and complex vectors only (FP32 handles
+// never carry a preconditioner).
+template <class V, class M>
+void ilu_apply(rbicg_s *h, const V *x0, V *y0, const V *x1, V *y1, const Scalars *S) {
+  if constexpr (sizeof(V) >= 8) {
+    rbicg_ilu_s *P = h->ilu;
+    rbicg_ilu_s::Ws &w = ilu_ws(h);
+    V *a1 = (V *)w.q[0], *a2 = (V *)w.q[1], *d1 = (V *)w.q[2], *d2 = (V *)w.q[3];
+    if (x0 && x1) {
+      ilu_trsv<V, M>(h->st, P, w, 1, x0, a1, 2, x1, d1, S);  // U^{-1} x0, L^{-H} x1
+      launch_spmv<V, M>(h->st, view_A<M>(h), a1, a2, S);
+      launch_spmv<V, M>(h->st, view_AH<M>(h), d1, d2, S);
+      ilu_trsv<V, M>(h->st, P, w, 0, a2, y0, 3, d2, y1, S);  // L^{-1} ., U^{-H} .
+    } else if (x0) {
+      ilu_trsv<V, M>(h->st, P, w, 1, x0, a1, -1, (const V *)nullptr, (V *)nullptr, S);
+      launch_spmv<V, M>(h->st, view_A<M>(h), a1, a2, S);
+      ilu_trsv<V, M>(h->st, P, w, 0, a2, y0, -1, (const V *)nullptr, (V *)nullptr, S);
+    } else if (x1) {
+      ilu_trsv<V, M>(h->st, P, w, 2, x1, d1, -1, (const V *)nullptr, (V *)nullptr, S);
+      launch_spmv<V, M>(h->st, view_AH<M>(h), d1, d2, S);
+      ilu_trsv<V, M>(h->st, P, w, 3, d2, y1, -1, (const V *)nullptr, (V *)nullptr, S);
+    }
+  }
+}
+
+// out = b - Op x (x NULL: out = b), Op = A or A^ (dual: A^H or A^^H)
+template <class V, class M>
+void op_residual(rbicg_s *h, bool dual, const V *b, const V *x, V *out) {
+  if (!h->ilu || !x) {
+    launch_residual<V, M>(h->st, dual ? view_AH<M>(h) : view_A<M>(h), b, x, out);
+    return;
+  }
+  // A^ x into out, then out = b - out
+  if (dual) ilu_apply<V, M>(h, nullptr, nullptr, x, out, nullptr);
+  else ilu_apply<V, M>(h, x, out, nullptr, nullptr, nullptr);
+  launch_rsub<V>(h->st, h->n, b, out, out);
+}
+
+// Y = Op X for m columns of leading dimension ld
+template <class V, class M>
+void op_spmm(rbicg_s *h, bool dual, const V *X, V *Y, int ld, int m) {
+  if (!h->ilu) {
+    launch_spmm<V, M>(h->st, dual ? view_AH<M>(h) : view_A<M>(h), X, Y, ld, m);
+    return;
+  }
+  for (int j = 0; j < m; ++j) {
+    const V *x = X + (size_t)j * ld;
+    V *y = Y + (size_t)j * ld;
+    if (dual) ilu_apply<V, M>(h, nullptr, nullptr, x, y, nullptr);
+    else ilu_apply<V, M>(h, x, y, nullptr, nullptr, nullptr);
+  }
+}
+
+// The attached preconditioner fits the handle's current matrix and mode
+int ilu_check(const rbicg_s *h) {
+  if (!h->ilu) return 0;
+  if (h->ilu->n != h->n || h->ilu->complex_vals != h->mat->complex_vals)
+    return rbicg_fail(RBICG_EINVAL, "the attached preconditioner does not match the handle's matrix");
+  if (h->vkind == 2) return rbicg_fail(RBICG_EINVAL, "split preconditioning needs an FP64 or complex handle");
+  return 0;
 }
 
 // ---------------------------------------------------------- typed helpers
@@ -986,9 +1129,8 @@ int job_stage2(rbicg_s *h, CycleJob &J) {
   if (m > 0) {
     TRY(tsgemm<V>(h, J.XU, J.Wc, m, h->Ua, 4));
     TRY(tsgemm<V>(h, J.XUt, J.Wtc, m, h->Uta, 5));
-    Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
-    launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
-    launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
+    op_spmm<V, M>(h, false, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
+    op_spmm<V, M>(h, true, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
     HIPCHECK(hipGetLastError());
     std::vector<const void *> X;
     for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Ca, j, h));
@@ -1090,14 +1232,14 @@ int job_stage4(rbicg_s *h, CycleJob &J) {
 // system's recycle space (rbicg_set_recycle, rbicg_update_recycle).
 template <class V, class M>
 int biorth_sync(rbicg_s *h, int m) {
+  TRY(ilu_check(h));
   CycleJob J;
   J.m = m;
   HIPCHECK(hipEventCreateWithFlags(&J.ev, hipEventDisableTiming));
   int rc = 0;
   if (m > 0) {
-    Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
-    launch_spmm<V, M>(h->st, A, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
-    launch_spmm<V, M>(h->st, AH, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
+    op_spmm<V, M>(h, false, (const V *)h->Ua, (V *)h->Ca, h->ld, m);
+    op_spmm<V, M>(h, true, (const V *)h->Uta, (V *)h->Cta, h->ld, m);
     std::vector<const void *> X;
     for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Ca, j, h));
     for (int j = 0; j < m; ++j) X.push_back(col_ptr(h->Cta, j, h));
@@ -1134,6 +1276,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
                bool inner = false) {
   rbicg_stats st{};
   const int n = h->n, ld = h->ld, s = h->opt.s, nb = h->nb;
+  TRY(ilu_check(h));
+  if (h->ilu && h->batch) return rbicg_fail(RBICG_EINVAL, "a preconditioned handle cannot be batched");
   Sell<M> A = view_A<M>(h), AH = view_AH<M>(h);
   hipEvent_t ev0, ev1;
   HIPCHECK(hipEventCreate(&ev0));
@@ -1173,8 +1317,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     // initial scalars: one host round trip.
     if (first)
       launch_dots<V>(h->st, nb, n, b, b, bt, bt, nullptr, nullptr, h->partial, h->S->red + 16);
-    launch_residual<V, M>(h->st, A, b, x, r);
-    launch_residual<V, M>(h->st, AH, bt, xt, rt);
+    op_residual<V, M>(h, false, b, x, r);
+    op_residual<V, M>(h, true, bt, xt, rt);
     if (first)
       launch_dots<V>(h->st, nb, n, r, r, rt, rt, nullptr, nullptr, h->partial, h->S->red + 24);
     if (ks > 0) {
@@ -1190,7 +1334,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
     // Algorithm 2 step 3: re-seed x~ if (r_0, r~_0) vanishes
     while (std::abs(rho) <= 1e-14 * rn * rtn && rn > 0 && reseeds < 3) {
       launch_reseed<V>(h->st, xt, (size_t)n, (unsigned long long)(h->opt.seed + reseeds));
-      launch_residual<V, M>(h->st, AH, bt, xt, rt);
+      op_residual<V, M>(h, true, bt, xt, rt);
       if (first)  // the unprojected dual residual of the re-seeded guess (scale when b~ = 0)
         launch_dots<V>(h->st, nb, n, rt, rt, nullptr, nullptr, nullptr, nullptr, h->partial,
                        h->S->red + 24 + nd);
@@ -1446,7 +1590,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
         chunk = std::min(chunk, h->opt.maxit - launched);
         const int chunk_start = launched;
         // profiling: time every opts.profile-th chunk (events between launches)
-        const bool prof = !h->batch && h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
+        const bool prof = !h->batch && !h->ilu && h->opt.profile > 0 && (int)h->pev.size() >= 8 * chunk &&
                           (h->prof_chunks++ % h->opt.profile) == 0;
         const int eb = (slot_next % 2) * 3 * chunk;
         // attached to a batch: the chunk's kernel arguments are handed to it
@@ -1478,9 +1622,18 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             continue;
           }
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c], h->st));
-          launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
-                           ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
-                           h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
+          if (h->ilu) {
+            // k_it1's work split around the preconditioned operator
+            launch_op_dir<V>(h->st, nb, n, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn, ptn,
+                             capR, capRt, h->P3, h->S, h->log, it, it == run_start + 1 ? 1 : 0);
+            ilu_apply<V, M>(h, pn, (V *)h->z, ptn, (V *)h->zt, h->S);
+            launch_op_restr<V>(h->st, nb, n, (const V *)h->z, (const V *)h->zt, ptn, C, Ct, ks, ld, capZ,
+                               capZt, h->P1, h->S);
+          } else {
+            launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
+                             ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
+                             h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
+          }
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 1], h->st));
           launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C,
                         Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp, zl, h->zstride);
@@ -1565,8 +1718,8 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       if (ks > 0)
         launch_expand2<V>(h->st, n, x, U, -1.0, nullptr, C, 0.0, xt, Ut, -1.0, nullptr, Ct, 0.0, ks, ld, h->S->zc);
       if (!inner) {
-        launch_residual<V, M>(h->st, A, b, x, (V *)h->t1);
-        launch_residual<V, M>(h->st, AH, bt, xt, (V *)h->t2);
+        op_residual<V, M>(h, false, b, x, (V *)h->t1);
+        op_residual<V, M>(h, true, bt, xt, (V *)h->t2);
         launch_dots<V>(h->st, nb, n, (V *)h->t1, (V *)h->t1, (V *)h->t2, (V *)h->t2, nullptr, nullptr,
                        h->partial, h->S->red);
         HIPCHECK(hipGetLastError());
@@ -1625,6 +1778,11 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
   h->last_log = fulllog;
   h->last_count = (int)(fulllog.size() / LOG_STRIDE);
   h->last_dev_status = status;
+  if (h->ilu) {  // a triangular solve's dependency wait gave up: results invalid
+    int e = 0;
+    HIPCHECK(hipMemcpy(&e, h->ilu->err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) return rbicg_fail(RBICG_EHIP, "triangular solve: dependency wait exceeded its bound");
+  }
   st.status = (status == ST_CONVERGED || status == ST_STAGNATED)
                   ? RBICG_OK
                   : (status == ST_BREAKDOWN ? RBICG_BREAKDOWN : RBICG_NOT_CONVERGED);
@@ -2741,6 +2899,184 @@ extern "C" int rbicg_rbilu_destroy(rbicg_rbilu P) {
   return RBICG_OK;
 }
 
+// ------------------------------------------------------ split ILUT
+namespace {
+int ilu_alloc(rbicg_ilu_s *P, void **dst, size_t bytes) {
+  void *p = nullptr;
+  HIPCHECK(hipMalloc(&p, std::max<size_t>(bytes, 1)));
+  P->allocs.push_back(p);
+  *dst = p;
+  return 0;
+}
+
+int ilu_put(rbicg_ilu_s *P, void **dst, const void *src, size_t bytes) {
+  TRY(ilu_alloc(P, dst, bytes));
+  if (bytes) HIPCHECK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+int ilu_put_vals(rbicg_ilu_s *P, void **dst, const std::vector<ilut::cplx> &v) {
+  std::vector<double> o(P->complex_vals ? 2 * v.size() : v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (P->complex_vals) {
+      o[2 * i] = v[i].real();
+      o[2 * i + 1] = v[i].imag();
+    } else {
+      o[i] = v[i].real();
+    }
+  }
+  return ilu_put(P, dst, o.data(), o.size() * sizeof(double));
+}
+
+// One factor on the device: its strictly triangular entries, the diagonal
+// (with_diag) and the level order padded to whole waves.
+int ilu_factor_upload(rbicg_ilu_s *P, const ilut::Csr &T, bool lower, bool with_diag,
+                      rbicg_ilu_s::Tri &out) {
+  const int n = T.n;
+  ilut::Csr S;
+  S.n = n;
+  S.rp.assign(1, 0);
+  std::vector<ilut::cplx> d(n, ilut::cplx(1.0, 0.0));
+  for (int i = 0; i < n; ++i) {
+    for (int e = T.rp[i]; e < T.rp[i + 1]; ++e) {
+      const int j = T.ci[e];
+      if (j == i) {
+        d[i] = T.v[e];
+      } else {
+        S.ci.push_back(j);
+        S.v.push_back(T.v[e]);
+      }
+    }
+    S.rp.push_back((int)S.ci.size());
+  }
+  std::vector<int> order;
+  out.levels = ilut::levels(S, lower, 64, order);
+  out.len = (int)order.size();
+  out.nnz = (int64_t)S.ci.size();
+  TRY(ilu_put(P, (void **)&out.order, order.data(), order.size() * sizeof(int)));
+  TRY(ilu_put(P, (void **)&out.rp, S.rp.data(), S.rp.size() * sizeof(int)));
+  TRY(ilu_put(P, (void **)&out.ci, S.ci.data(), S.ci.size() * sizeof(int)));
+  TRY(ilu_put_vals(P, &out.v, S.v));
+  if (with_diag) TRY(ilu_put_vals(P, &out.diag, d));
+  return 0;
+}
+}  // namespace
+
+extern "C" int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, rbicg_ilu *out) {
+  if (!A || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (!(droptol >= 0.0)) return rbicg_fail(RBICG_EINVAL, "droptol must be >= 0");
+  HostCsr hA;
+  TRY(read_csr(A, hA));
+  ilut::Csr a, L, U;
+  a.n = hA.n;
+  a.rp = hA.rowptr;
+  a.ci = hA.col;
+  a.v = hA.val;
+  std::string msg;
+  if (ilut::factor(a, droptol, fill, L, U, msg) < 0) return rbicg_fail(RBICG_EINVAL, "%s", msg.c_str());
+  std::unique_ptr<rbicg_ilu_s> P(new rbicg_ilu_s());
+  P->n = hA.n;
+  P->complex_vals = hA.complex_vals;
+  // L: unit lower; U: upper with its diagonal; L^H unit upper; U^H lower
+  // with the conjugated diagonal
+  TRY(ilu_factor_upload(P.get(), L, true, false, P->L));
+  TRY(ilu_factor_upload(P.get(), U, false, true, P->U));
+  TRY(ilu_factor_upload(P.get(), ilut::conj_transpose(L), false, false, P->LH));
+  TRY(ilu_factor_upload(P.get(), ilut::conj_transpose(U), true, true, P->UH));
+  const size_t n = (size_t)P->n;
+  for (auto &w : P->ws) {
+    for (void *&q : w.q) TRY(ilu_alloc(P.get(), &q, n * sizeof(cd)));
+    TRY(ilu_alloc(P.get(), (void **)&w.counter, sizeof(int)));
+  }
+  TRY(ilu_alloc(P.get(), (void **)&P->err, sizeof(int)));
+  HIPCHECK(hipMemset(P->err, 0, sizeof(int)));
+  HIPCHECK(hipDeviceSynchronize());
+  *out = P.release();
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_ilu_attach(rbicg_handle h, rbicg_ilu P) {
+  if (!h) return rbicg_fail(RBICG_EINVAL, "null handle");
+  if (P) {
+    if (P->n != h->n || P->complex_vals != h->mat->complex_vals)
+      return rbicg_fail(RBICG_EINVAL, "the preconditioner does not match the handle's matrix");
+    if (h->vkind == 2) return rbicg_fail(RBICG_EINVAL, "split preconditioning needs an FP64 or complex handle");
+    if (h->batch) return rbicg_fail(RBICG_EINVAL, "a batched handle cannot be preconditioned");
+  }
+  h->ilu = P;
+  return RBICG_OK;
+}
+
+namespace {
+// x = T1^{-1} b, x2 = T2^{-1} b2 on the rhs/solution workspace
+template <class V>
+int ilu_two_solves(rbicg_ilu P, int f1, const void *b, void *x, int f2, const void *b2, void *x2,
+                   hipStream_t st) {
+  rbicg_ilu_s::Ws &w = P->ws[2];
+  bool done = false;
+  if constexpr (std::is_same<V, cd>::value) {  // complex factors need complex vectors
+    if (P->complex_vals) {
+      ilu_trsv<V, cd>(st, P, w, f1, (const V *)b, (V *)x, f2, (const V *)b2, (V *)x2, nullptr);
+      done = true;
+    }
+  }
+  if (!done)
+    ilu_trsv<V, double>(st, P, w, f1, (const V *)b, (V *)x, f2, (const V *)b2, (V *)x2, nullptr);
+  HIPCHECK(hipGetLastError());
+  return RBICG_OK;
+}
+
+int ilu_transform(rbicg_ilu P, int f1, const void *b, void *x, int f2, const void *b2, void *x2,
+                  int32_t complex_vectors, void *stream) {
+  if (!P || !b || !b2 || !x || !x2) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (b == x || b2 == x2) return rbicg_fail(RBICG_EINVAL, "input and output must not alias");
+  if (P->complex_vals && !complex_vectors)
+    return rbicg_fail(RBICG_EINVAL, "a complex preconditioner needs complex vectors");
+  hipStream_t st = (hipStream_t)stream;
+  return complex_vectors ? ilu_two_solves<cd>(P, f1, b, x, f2, b2, x2, st)
+                         : ilu_two_solves<double>(P, f1, b, x, f2, b2, x2, st);
+}
+}  // namespace
+
+extern "C" int rbicg_ilu_rhs(rbicg_ilu P, const void *b, const void *bt, void *bh, void *ch,
+                             int32_t complex_vectors, void *stream) {
+  return ilu_transform(P, 0, b, bh, 3, bt, ch, complex_vectors, stream);  // L^{-1} b, U^{-H} b~
+}
+
+extern "C" int rbicg_ilu_solution(rbicg_ilu P, const void *y, const void *yt, void *x, void *xt,
+                                  int32_t complex_vectors, void *stream) {
+  return ilu_transform(P, 1, y, x, 2, yt, xt, complex_vectors, stream);  // U^{-1} y, L^{-H} y~
+}
+
+extern "C" int rbicg_ilu_set_waves(rbicg_ilu P, int32_t waves) {
+  if (!P) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (waves < 4 || waves > 65536) return rbicg_fail(RBICG_EINVAL, "waves=%d out of range [4, 65536]", waves);
+  P->waves = waves;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_ilu_info(rbicg_ilu P, int64_t *info) {
+  if (!P || !info) return rbicg_fail(RBICG_EINVAL, "null argument");
+  int e = 0;
+  HIPCHECK(hipDeviceSynchronize());
+  HIPCHECK(hipMemcpy(&e, P->err, sizeof(int), hipMemcpyDeviceToHost));
+  info[0] = P->n;
+  info[1] = P->L.nnz;
+  info[2] = P->U.nnz + P->n;
+  info[3] = P->L.levels;
+  info[4] = P->U.levels;
+  info[5] = e ? 1 : 0;
+  info[6] = P->complex_vals ? 1 : 0;
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_ilu_destroy(rbicg_ilu P) {
+  if (!P) return RBICG_OK;
+  (void)hipDeviceSynchronize();
+  delete P;
+  return RBICG_OK;
+}
+
 extern "C" int rbicg_matrix_destroy(rbicg_matrix m) {
   if (!m) return RBICG_OK;
   (void)hipDeviceSynchronize();
@@ -2950,6 +3286,7 @@ extern "C" int rbicg_get_log(rbicg_handle h, double *out, int32_t cap, int32_t *
 extern "C" int rbicg_bilinear(rbicg_handle h, const void *u, const void *w, double tol, void *value,
                               double *err_est, rbicg_stats *st) {
   if (!h || !u || !w || !value) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->ilu) return rbicg_fail(RBICG_EINVAL, "not with a split preconditioner attached");
   if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
   void *x = nullptr, *xt = nullptr;
   if (h->vkind == 2) {
@@ -3016,6 +3353,7 @@ extern "C" int rbicg_solve_shifted(rbicg_handle h, int32_t S, const double *sigm
                                    const void *c, void *X, void *Xt, double tol, int32_t update_from,
                                    rbicg_stats *st) {
   if (!h || !sigma || !b || !c || !X || !Xt || !st) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->ilu) return rbicg_fail(RBICG_EINVAL, "not with a split preconditioner attached");
   if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "shifted solves need a RBICG_C128 handle");
   if (S < 1 || S > SHMAX) return rbicg_fail(RBICG_EINVAL, "S=%d out of range [1, %d]", S, SHMAX);
   if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
@@ -3067,6 +3405,7 @@ int bilinear_batch_impl(rbicg_s *h, int S, const cd *U, const cd *W, double tol,
 
 extern "C" int rbicg_batch_attach(rbicg_handle h, rbicg_batch b) {
   if (!h) return rbicg_fail(RBICG_EINVAL, "null handle");
+  if (b && h->ilu) return rbicg_fail(RBICG_EINVAL, "a preconditioned handle cannot be batched");
   h->batch = b;
   return RBICG_OK;
 }
@@ -3074,6 +3413,7 @@ extern "C" int rbicg_batch_attach(rbicg_handle h, rbicg_batch b) {
 extern "C" int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, const void *W, double tol,
                                     double *values, double *err_est, rbicg_stats *st) {
   if (!h || !U || !W || !values || !st) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->ilu) return rbicg_fail(RBICG_EINVAL, "not with a split preconditioner attached");
   if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "batched bilinear forms need a RBICG_C128 handle");
   if (S < 1 || S > SHMAX) return rbicg_fail(RBICG_EINVAL, "S=%d out of range [1, %d]", S, SHMAX);
   if (!(tol > 0)) return rbicg_fail(RBICG_EINVAL, "tol must be positive");
@@ -3099,6 +3439,7 @@ extern "C" int rbicg_bilinear_batch(rbicg_handle h, int32_t S, const void *U, co
 extern "C" int rbicg_project(rbicg_handle h, int32_t m, const void *X, const void *Xt, const void *b,
                              const void *c, double *Ar, double *Er, double *br, double *cr) {
   if (!h || !X || !Xt || !Ar || !Er) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (h->ilu) return rbicg_fail(RBICG_EINVAL, "not with a split preconditioner attached");
   if (h->vkind != 1) return rbicg_fail(RBICG_EINVAL, "projection needs a RBICG_C128 handle");
   if (m < 1 || m > 32) return rbicg_fail(RBICG_EINVAL, "m=%d out of range [1, 32]", m);
   if ((b == nullptr) != (c == nullptr) || (b && (!br || !cr)))

@@ -223,6 +223,107 @@ def solve_split_sequence(mats, bs, bts, *, k=20, s=40, tol=1e-8, maxit=10000, **
     return out
 
 
+class ILUT:
+    """Split ILUT(droptol, fill) preconditioner of one matrix (rbicg_ilut_*):
+    the factorization runs on the host once, the factors and their level
+    schedules live on the device.  ``Solver.attach_ilu`` makes a handle
+    iterate with L^{-1} A U^{-1}; ``rhs`` and ``solution`` map a dual pair's
+    right-hand sides to the preconditioned pair and its solutions back."""
+
+    def __init__(self, A, droptol=0.05, fill=-1):
+        self.lib = _lib.load()
+        keep = []
+        a = _csr_struct(A, keep)
+        h = ct.c_void_p()
+        rc = self.lib.rbicg_ilut_create(ct.byref(a), float(droptol), int(fill), ct.byref(h))
+        _lib.check(rc, "rbicg_ilut_create")
+        self.h, self.n = h, a.n
+        self.complex = bool(a.values_complex)
+
+    def set_waves(self, waves):
+        """Waves working through a triangular solve's chunks (speed only)."""
+        _lib.check(self.lib.rbicg_ilu_set_waves(self.h, int(waves)), "rbicg_ilu_set_waves")
+
+    def info(self) -> dict:
+        out = (ct.c_int64 * 7)()
+        _lib.check(self.lib.rbicg_ilu_info(self.h, out), "rbicg_ilu_info")
+        keys = ["n", "nnz_L", "nnz_U", "levels_L", "levels_U", "wait_error", "complex"]
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def _v(self, v, name):
+        ok = (isinstance(v, torch.Tensor) and v.is_cuda and v.is_contiguous() and v.numel() == self.n
+              and v.dtype in ((torch.complex128,) if self.complex else (torch.float64, torch.complex128)))
+        if not ok:
+            raise TypeError(f"{name} must be a contiguous CUDA float64/complex128 tensor of length "
+                            f"{self.n} (complex128 for a complex matrix)")
+        return ct.c_void_p(v.data_ptr())
+
+    def _two(self, fn, u, v, stream):
+        if u.dtype != v.dtype:
+            raise TypeError("both vectors must have one dtype")
+        a, b = torch.empty_like(u), torch.empty_like(v)
+        cplx = 1 if u.dtype == torch.complex128 else 0
+        rc = fn(self.h, self._v(u, "u"), self._v(v, "v"), self._v(a, "out"), self._v(b, "out"), cplx,
+                ct.c_void_p(_stream_ptr(stream)))
+        _lib.check(rc, fn.__name__)
+        return a, b
+
+    def rhs(self, b, bt, stream=None):
+        """(L^{-1} b, U^{-H} b~)."""
+        return self._two(self.lib.rbicg_ilu_rhs, b, bt, stream)
+
+    def solution(self, y, yt, stream=None):
+        """(U^{-1} y, L^{-H} y~)."""
+        return self._two(self.lib.rbicg_ilu_solution, y, yt, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbicg_ilu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_ilut_sequence(mats, bs, bts, *, droptol=0.05, fill=-1, k=20, s=40, tol=1e-8,
+                        maxit=10000, prec="f64", **opts):
+    """Split-ILUT-preconditioned RBiCG over a sequence of dual pairs (Sec. 6):
+    each matrix gets its own ILUT(droptol, fill), one handle solves the
+    preconditioned pairs in order with the recycle space carried between
+    them (biorthogonalized against each new preconditioned operator).  Zero
+    initial guesses.  bs, bts: CUDA tensors.  Returns a list of
+    (x, x~, stats) with stats of the preconditioned solves."""
+    out, S, P = [], None, None
+    try:
+        for j, A in enumerate(mats):
+            Pn = ILUT(A, droptol, fill)
+            if S is None:
+                S = Solver(A, k=k, s=s, maxit=maxit, prec=prec, **opts)
+                S.attach_ilu(Pn)
+            else:
+                S.stream.synchronize()     # the previous solve no longer uses P
+                S.attach_ilu(Pn)
+                S.update_recycle(A)        # C = A^ U against the new operator
+            if P is not None:
+                P.close()
+            P = Pn
+            S._order()                     # b, b~ are complete before rhs reads them
+            bh, ch = P.rhs(bs[j], bts[j], stream=S.stream)
+            y, yt, st = S.solve(bh, ch, tol=tol)
+            x, xt = P.solution(y, yt, stream=S.stream)
+            out.append((x, xt, st))
+    finally:
+        if S is not None:
+            S.stream.synchronize()
+            S.close()
+        if P is not None:
+            P.close()
+    return out
+
+
 class Batch:
     """Continuous batching of iteration launches across solver handles
     (rbicg_batch_*): handles created with ``batch=`` hand their chunks of
@@ -344,6 +445,13 @@ class Solver:
         ok = (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED) if allow_not_converged else (_lib.RBICG_OK,)
         _lib.check(rc, "rbicg_solve_dual", ok)
         return x, xt, st.as_dict()
+
+    def attach_ilu(self, P):
+        """Iterate with the split-preconditioned operator of P (an ILUT; None
+        detaches) from the next call on (rbicg_ilu_attach)."""
+        rc = self.lib.rbicg_ilu_attach(self.h, P.h if P is not None else None)
+        _lib.check(rc, "rbicg_ilu_attach")
+        self.ilu = P
 
     def update_recycle(self, A_next=None, AH_next=None):
         if isinstance(A_next, DeviceMatrix):

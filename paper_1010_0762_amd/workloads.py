@@ -100,6 +100,44 @@ def convdiff(N: int, dim: int, beta: Sequence[float]) -> CSR:
     return _stencil([N] * dim, diag, lower, upper)
 
 
+def jump_convdiff2d(N: int = 63, contrast: float = 1e3, tiles: int = 4,
+                    beta: Sequence[float] = (50.0, 25.0)) -> CSR:
+    """-(a u_x)_x - (a u_y)_y + beta . grad(u) on the unit square, N x N
+    interior points (default h = 1/64, n = 3969, the grid of the 2D experiment
+    of Sec. 6.1), central differences for the convection (as there), and a
+    piecewise-constant diffusion coefficient a = contrast on the tiles x tiles
+    checkerboard's even cells and 1 on the odd ones (the paper's coefficient is
+    given only in a figure; this is a synthetic stand-in with the same kind of
+    jumps).  Face coefficients are harmonic means of the two cell-centre
+    values; Dirichlet zero boundary eliminated; unknowns x-fastest."""
+    h = 1.0 / (N + 1)
+    n = N * N
+    x = (np.arange(N) + 1) * h
+
+    def a(px, py):
+        ix = np.minimum((px * tiles).astype(np.int64), tiles - 1)
+        iy = np.minimum((py * tiles).astype(np.int64), tiles - 1)
+        return np.where((ix + iy) % 2 == 0, contrast, 1.0)
+
+    X, Y = np.meshgrid(x, x, indexing="xy")     # X[j, i] = x_i, Y[j, i] = y_j
+    X, Y = X.ravel(), Y.ravel()
+    ac = a(X, Y)
+
+    def face(dx, dy):
+        an = a(X + dx, Y + dy)
+        return 2.0 * ac * an / (ac + an)
+
+    aw, ae, as_, an_ = face(-h, 0.0), face(h, 0.0), face(0.0, -h), face(0.0, h)
+    idx = np.arange(n, dtype=np.int64)
+    i, j = idx % N, idx // N
+    bx, by = float(beta[0]), float(beta[1])
+    rows, cols, vals = [idx], [idx], [(aw + ae + as_ + an_) / h**2]
+    for m, off, v in ((i > 0, -1, -aw / h**2 - bx / (2 * h)), (i < N - 1, 1, -ae / h**2 + bx / (2 * h)),
+                      (j > 0, -N, -as_ / h**2 - by / (2 * h)), (j < N - 1, N, -an_ / h**2 + by / (2 * h))):
+        rows.append(idx[m]); cols.append(idx[m] + off); vals.append(v[m])
+    return _assemble(n, rows, cols, vals)
+
+
 def aniso_diffusion(N: int, kappa: Sequence[float] = (1.0, 0.1, 0.01),
                     shift: float = 0.1) -> CSR:
     """A = -L_kappa - shift*I with L_kappa the 7-point SPD operator
@@ -151,6 +189,27 @@ def cfg2_sequence(nsys: int = 10, N: int = 64) -> DualSequence:
     mats = [convdiff(N, 3, [20.0 * (1 + 0.02 * j), 10.0 * (1 + 0.02 * j),
                             5.0 * (1 + 0.02 * j)]) for j in range(nsys)]
     return DualSequence(f"convdiff3d_{N}", mats, [b] * nsys, [bt] * nsys, 20, 40, 1e-8)
+
+
+def ilut2d_sequence(nsys: int = 4, N: int = 40, repeat: bool = False) -> DualSequence:
+    """Split-ILUT cases: 2D convection-diffusion 5-point upwind on N x N
+    (default n=1600); beta_j = (40(1+0.03j), 20(1-0.02j)), or beta = (40, 20)
+    for every system when repeat (the same pair solved nsys times, as in the
+    2D experiment of Sec. 6.1); a fresh N(0,1) pair b_j, b~_j per system (one
+    pair when repeat); k=5, s=10 (k=10, s=20 when repeat), tol 1e-8.  The drop
+    tolerance goes in extra["droptol"] (0.2: a weaker factorization than the
+    paper's 0.05, so that these small systems take several cycles)."""
+    rng = np.random.default_rng(BASE_SEED + 6)
+    n = N * N
+    if repeat:
+        b, bt = rng.standard_normal(n), rng.standard_normal(n)
+        A = convdiff(N, 2, [40.0, 20.0])
+        return DualSequence(f"ilut_convdiff2d_{N}_repeat", [A] * nsys, [b] * nsys, [bt] * nsys,
+                            10, 20, 1e-8, {"droptol": 0.2})
+    bs = [rng.standard_normal(n) for _ in range(nsys)]
+    bts = [rng.standard_normal(n) for _ in range(nsys)]
+    mats = [convdiff(N, 2, [40.0 * (1 + 0.03 * j), 20.0 * (1 - 0.02 * j)]) for j in range(nsys)]
+    return DualSequence(f"ilut_convdiff2d_{N}", mats, bs, bts, 5, 10, 1e-8, {"droptol": 0.2})
 
 
 def irka_problem(N: int = 48, r: int = 8, eps: float = 0.3):

@@ -156,12 +156,13 @@ def cfg4(N=128):
     print("cfg4 bicg", r.iters, r.relres, r.relres_dual, flush=True)
 
 
-def cfg3(N=48, nsweeps=2):
+def cfg3(N=48, nsweeps=6):
     """Shifted pairs (sigma I - A), A = -L_kappa - 0.1 I on 48^3, 8 shifts per
     sweep, k = 20 shared recycle space updated from the shift of smallest
     modulus, primal solutions warm-starting the next sweep: per sweep and
     shift the iteration count, true residuals, retained recycle dimension and
-    256 sampled entries of x and x~."""
+    256 sampled entries of x and x~; and the counts of NPERT_SEQ - 1 runs with
+    b, c perturbed by 1e-13 relative."""
     A, b, c, sweeps = wl.cfg3_shifts(nsweeps=nsweeps, N=N)
     Asp = as_csr(A)
     n = Asp.shape[0]
@@ -181,8 +182,54 @@ def cfg3(N=48, nsweeps=2):
             "x_sample": [[[float(v.real), float(v.imag)] for v in r.x[idx]] for r in res],
             "xt_sample": [[[float(v.real), float(v.imag)] for v in r.xt[idx]] for r in res]})
         print("cfg3 sweep", [r.iters for r in res], flush=True)
+    # the oracle's own spread: the same sweeps with b, c perturbed by 1e-13
+    # relative (recycled counts move with rounding through the shared space)
+    runs = [[sw["iters"] for sw in out["sweeps"]]]
+    for j in range(NPERT_SEQ - 1):
+        bp, cp = _perturbed(b, 400 + j), _perturbed(c, 500 + j)
+        U = Ut = None
+        xs = None
+        its = []
+        for sig in sweeps:
+            res, (U, Ut) = oracle.shifted_pairs(Asp, bp, cp, sig, U, Ut, k=20, s=40, tol=1e-8, x0s=xs)
+            xs = [r.x for r in res]
+            its.append([int(r.iters) for r in res])
+        runs.append(its)
+        print("cfg3 pert", j, its, flush=True)
+    out["iters_runs"] = runs
     out["oracle_seconds"] = time.time() - t0
     with open(os.path.join(HERE, f"cfg3_shifted_{N}.json"), "w") as f:
+        json.dump(out, f)
+
+
+NPERT_ILUT = 24
+
+
+def ilut2d():
+    """Split-ILUT sequences (oracle.precond.rbicg_ilut_sequence) on the 2D
+    convection-diffusion cases: per system the iteration count and the
+    recycle dimension the solve started with, unperturbed and over
+    NPERT_ILUT runs with b, b~ perturbed entrywise by 1e-13 relative (the
+    harmonic Ritz selection on these small spaces, and with it the carried
+    dimension and the counts, moves with rounding)."""
+    from oracle.precond import rbicg_ilut_sequence
+    t0 = time.time()
+    out = {}
+    for repeat in (False, True):
+        seq = wl.ilut2d_sequence(repeat=repeat)
+        tau = seq.extra["droptol"]
+        runs_it, runs_k = [], []
+        for j in range(NPERT_ILUT + 1):
+            bp = seq.b if j == 0 else [_perturbed(v, 600 + 10 * j + i) for i, v in enumerate(seq.b)]
+            btp = seq.bt if j == 0 else [_perturbed(v, 700 + 10 * j + i) for i, v in enumerate(seq.bt)]
+            _, res = rbicg_ilut_sequence(seq.mats, bp, btp, seq.k, seq.s, seq.tol, tau)
+            runs_it.append([int(r.iters) for r in res])
+            runs_k.append([int(r.k_used) for r in res])
+            print("ilut2d", seq.name, j, runs_it[-1], runs_k[-1], flush=True)
+        out[seq.name] = {"iters": runs_it[0], "k_used": runs_k[0], "iters_runs": runs_it,
+                         "k_runs": runs_k}
+    out["oracle_seconds"] = time.time() - t0
+    with open(os.path.join(HERE, "ilut_convdiff2d_40.json"), "w") as f:
         json.dump(out, f)
 
 
@@ -196,3 +243,5 @@ if __name__ == "__main__":
         cfg3()
     if which in ("cfg2seq", "all"):
         cfg2seq()
+    if which in ("ilut2d", "all"):
+        ilut2d()
