@@ -373,7 +373,24 @@ __device__ __forceinline__ T spmv_plain(const Sell<M> &A, int row, const V *x) {
   const int slice = row >> 6, lane = row & 63;
   const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
   T acc = zero<T>();
-  for (int e = beg + lane; e < end; e += RBICG_WAVE) acc += up(A.val[e]) * up(x[A.col[e]]);
+  // eight entries at a time: their indices and values, then their gathers,
+  // are all in flight before the products (summed in entry order)
+  for (int e0 = beg + lane; e0 < end; e0 += 8 * RBICG_WAVE) {
+    int c[8];
+    M v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + t * RBICG_WAVE;
+      c[t] = e < end ? A.col[e] : -1;
+      v[t] = e < end ? A.val[e] : M{};
+    }
+    V xv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xv[t] = c[t] >= 0 ? x[c[t]] : V{};
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (c[t] >= 0) acc += up(v[t]) * up(xv[t]);
+  }
   if (A.shifted) acc = shift_apply<M, T>(A, acc, up(x[row]));
   return acc;
 }
@@ -604,8 +621,10 @@ __device__ __forceinline__ void it1_body(
       if (capR) {
         capR[row] = rv;
         capRt[row] = rtv;
-        capZ[row] = down<V>(zz);
-        capZt[row] = down<V>(zzt);
+        if (capZ != z) {  // z kept apart from its ring slot
+          capZ[row] = down<V>(zz);
+          capZt[row] = down<V>(zzt);
+        }
       }
     }
     put<T>(lds, ls, 3 * k, s0);
@@ -708,8 +727,10 @@ __device__ __forceinline__ void it1_body(
       if (capR) {
         capR[row] = rv;
         capRt[row] = rtv;
-        capZ[row] = down<V>(zz);
-        capZt[row] = down<V>(zzt);
+        if (capZ != z) {  // z kept apart from its ring slot
+          capZ[row] = down<V>(zz);
+          capZt[row] = down<V>(zzt);
+        }
       }
     }
   }
@@ -1753,12 +1774,28 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_spmm8(Sell<M> A, const V *X, V 
   for (int j = 0; j < 8; ++j) acc[j] = zero<T>();
   const int slice = row >> 6, lane = row & 63;
   const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
-  for (int e = beg + lane; e < end; e += RBICG_WAVE) {
-    const int c = A.col[e];
-    const auto a = up(A.val[e]);
+  // eight entries at a time: indices and values first, then per column the
+  // eight gathers together, then the products (in entry order per column)
+  for (int e0 = beg + lane; e0 < end; e0 += 8 * RBICG_WAVE) {
+    int c[8];
+    M v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = e0 + t * RBICG_WAVE;
+      c[t] = e < end ? A.col[e] : -1;
+      v[t] = e < end ? A.val[e] : M{};
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (j < nc) acc[j] += a * up(X[(size_t)(c0 + j) * ld + c]);
+      if (j < nc) {
+        const V *Xc = X + (size_t)(c0 + j) * ld;
+        V xv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xv[t] = c[t] >= 0 ? Xc[c[t]] : V{};
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (c[t] >= 0) acc[j] += up(v[t]) * up(xv[t]);
+      }
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j)

@@ -487,9 +487,9 @@ double svd_tol_eff(const rbicg_s *h) {
 // Algorithmic bytes of one launch of each iteration kernel (matrix values of
 // the type the kernels read, int32 column indices, one slice pointer per
 // row-slice rounded to one per row): k_it1 reads r, r~, p, p~ and C, C~ rows
-// and writes p, p~, z, z~ (plus r_{i-1}, r~_{i-1}, z, z~ into the cycle rings
-// when updating); k_it2 reads x, x~, r, r~, p, p~, z, z~ and C, C~ rows and
-// writes x, x~, r, r~.
+// and writes p, p~, z, z~ (plus r_{i-1}, r~_{i-1} into the cycle rings when
+// updating; z, z~ then live in their ring slots); k_it2 reads x, x~, r, r~,
+// p, p~, z, z~ and C, C~ rows and writes x, x~, r, r~.
 void kernel_bytes(const rbicg_s *h, int k, double out[2]) {
   const double ba = h->vkind == 2 ? 4.0 : (double)h->mat->A.vbytes;
   const double nnz = (double)h->mat->A.nnz, n = h->n, vb = (double)h->vb;
@@ -497,7 +497,7 @@ void kernel_bytes(const rbicg_s *h, int k, double out[2]) {
   // the index arrays once when A^H shares A's pattern
   const double ix = h->mat->AH.borrowed ? 1.0 : 2.0;
   out[0] = 2.0 * nnz * ba + ix * (4.0 * nnz + 4.0 * (n + 1.0)) +
-           (8.0 + 2.0 * k + (cap ? 4.0 : 0.0)) * n * vb;
+           (8.0 + 2.0 * k + (cap ? 2.0 : 0.0)) * n * vb;
   out[1] = (12.0 + 2.0 * k) * n * vb;
 }
 
@@ -1607,13 +1607,15 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             capZt = (V *)ring_col(h->Zt, set, s + 1, pos + 1, h);
           }
           V *pn = (V *)h->p[1 - pc], *ptn = (V *)h->pt[1 - pc];
+          // when updating, z and z~ live in their cycle ring slots (written once)
+          V *zw = capZ ? capZ : (V *)h->z, *ztw = capZt ? capZt : (V *)h->zt;
           double *zl = rec_mode && ks > 0 ? h->zlog : nullptr;
           if (h->batch) {
             const It1Args<V, M> a1{A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn, ptn,
-                                   (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt,
+                                   zw, ztw, C, Ct, ks, ld, capR, capRt, capZ, capZt,
                                    h->P3, h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp,
                                    0, 0};
-            const It2Args<V> a2{n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C, Ct,
+            const It2Args<V> a2{n, x, xt, r, rt, pn, ptn, zw, ztw, C, Ct,
                                 ks, ld, h->P1, h->P3, h->S, h->log, it, rp, zl, h->zstride, 0, 0};
             bc.it1.insert(bc.it1.end(), (const char *)&a1, (const char *)&a1 + sizeof(a1));
             bc.it2.insert(bc.it2.end(), (const char *)&a2, (const char *)&a2 + sizeof(a2));
@@ -1626,16 +1628,15 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             // k_it1's work split around the preconditioned operator
             launch_op_dir<V>(h->st, nb, n, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn, ptn,
                              capR, capRt, h->P3, h->S, h->log, it, it == run_start + 1 ? 1 : 0);
-            ilu_apply<V, M>(h, pn, (V *)h->z, ptn, (V *)h->zt, h->S);
-            launch_op_restr<V>(h->st, nb, n, (const V *)h->z, (const V *)h->zt, ptn, C, Ct, ks, ld, capZ,
-                               capZt, h->P1, h->S);
+            ilu_apply<V, M>(h, pn, zw, ptn, ztw, h->S);
+            launch_op_restr<V>(h->st, nb, n, zw, ztw, ptn, C, Ct, ks, ld, nullptr, nullptr, h->P1, h->S);
           } else {
             launch_it1<V, M>(h->st, nb, A, AH, r, (const V *)h->p[pc], rt, (const V *)h->pt[pc], pn,
-                             ptn, (V *)h->z, (V *)h->zt, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
+                             ptn, zw, ztw, C, Ct, ks, ld, capR, capRt, capZ, capZt, h->P3,
                              h->P1, h->S, h->log, it, it == run_start + 1 ? 1 : 0, rp);
           }
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 1], h->st));
-          launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, (const V *)h->z, (const V *)h->zt, C,
+          launch_it2<V>(h->st, nb, n, x, xt, r, rt, pn, ptn, zw, ztw, C,
                         Ct, ks, ld, h->P1, h->P3, h->S, h->log, it, rp, zl, h->zstride);
           if (prof) HIPCHECK(hipEventRecord(h->pev[eb + 3 * c + 2], h->st));
           pc = 1 - pc;
