@@ -238,6 +238,130 @@ def ilut(A, tau, p=None):
     return to_csr(Lrows, True), to_csr(Urows, False)
 
 
+# ---------------------------------------------------------------- ILUTP
+# ILUT with column pivoting (Sec. 6.2 preconditions with ILUTP).  Reading
+# (the paper gives no details): the column-pivoting variant of ILUT.  Columns
+# are tracked in a position list perm (position -> original column, initially
+# the identity); row i works in original column indices.  Its lower part is
+# the columns already pivotal for rows 0..i-1, eliminated in that pivot order
+# with the drop rule of ILUT (|w_c| < tau ||A(:, c)||_2 before division by the
+# pivot: dropped, no update); after the elimination the remaining entries are
+# dropped when |w_c| < tau ||A(:, c)||_2, except the entry of column perm[i]
+# (the unpivoted diagonal).  Among the kept remaining entries the largest in
+# modulus (ties: the smallest position) becomes the pivot when its modulus
+# times permtol exceeds that of column perm[i]; then the positions of the two
+# columns are swapped.  At most p off-pivot entries are then kept in the L and
+# U parts (largest modulus, ties by position).  With Q the permutation matrix
+# of perm ((A Q)(:, j) = A(:, perm[j])), A Q = L U + E.  permtol = 0 never
+# pivots (ILUT); tau = 0, permtol = 1 is LU with complete row-wise column
+# partial pivoting.
+
+
+def ilutp(A, tau, p=None, permtol=1.0):
+    """ILUTP(tau, p, permtol): (L unit lower, U upper, perm) with
+    A[:, perm] ~ L U; L and U in pivot-position numbering (scipy CSR,
+    complex128).  Plain loops over a dictionary working row (small n)."""
+    import heapq
+    A = as_csr(A).astype(np.complex128)
+    A.sort_indices()
+    n = A.shape[0]
+    cn = np.sqrt(np.asarray(abs(A).power(2).sum(axis=0)).ravel())
+    perm = list(range(n))       # position -> original column
+    pos = list(range(n))        # original column -> position
+    Lrows, Urows = [], []       # L: {position k < i: value}; U: {original column: value}
+    for i in range(n):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        w = dict(zip(A.indices[lo:hi].tolist(), A.data[lo:hi].tolist()))
+        heap = [pos[c] for c in w if pos[c] < i]
+        heapq.heapify(heap)
+        seen = set(heap)
+        lpart = {}
+        while heap:
+            k = heapq.heappop(heap)
+            c = perm[k]
+            wk = w.pop(c)
+            if abs(wk) < tau * cn[c]:
+                continue                      # dropped multiplier
+            wk = wk / Urows[k][c]
+            lpart[k] = wk
+            for c2, ukc in Urows[k].items():
+                if c2 == c:
+                    continue
+                w[c2] = w.get(c2, 0.0) - wk * ukc
+                k2 = pos[c2]
+                if k2 < i and k2 not in seen:
+                    seen.add(k2)
+                    heapq.heappush(heap, k2)
+        dcol = perm[i]
+        upart = {c: v for c, v in w.items() if pos[c] >= i and (c == dcol or abs(v) >= tau * cn[c])}
+        # pivot: the largest kept entry, ties by position
+        best = dcol
+        bmod = abs(upart.get(dcol, 0.0))
+        for c, v in upart.items():
+            if abs(v) > bmod or (abs(v) == bmod and pos[c] < pos[best]):
+                best, bmod = c, abs(v)
+        if best != dcol and bmod * permtol > abs(upart.get(dcol, 0.0)):
+            j = pos[best]
+            perm[i], perm[j] = best, dcol
+            pos[best], pos[dcol] = i, j
+            dcol = best
+        d = upart.pop(dcol, 0.0)
+        if d == 0:
+            raise ZeroDivisionError(f"ILUTP: zero pivot in row {i}")
+        lkeep, ukeep = lpart, upart
+        if p is not None:
+            lkeep = dict(sorted(lkeep.items(), key=lambda t: (-abs(t[1]), t[0]))[:p])
+            ukeep = dict(sorted(ukeep.items(), key=lambda t: (-abs(t[1]), pos[t[0]]))[:p])
+        ukeep[dcol] = d
+        Lrows.append(lkeep)
+        Urows.append(ukeep)
+    r, c, v = [], [], []
+    for i, row in enumerate(Lrows):
+        for k, val in row.items():
+            r.append(i); c.append(k); v.append(val)
+        r.append(i); c.append(i); v.append(1.0)
+    L = sp.csr_matrix((np.asarray(v, np.complex128), (r, c)), shape=(n, n))
+    r, c, v = [], [], []
+    for i, row in enumerate(Urows):
+        for col, val in row.items():
+            r.append(i); c.append(pos[col]); v.append(val)
+    U = sp.csr_matrix((np.asarray(v, np.complex128), (r, c)), shape=(n, n))
+    L.sort_indices()
+    U.sort_indices()
+    return L, U, np.asarray(perm, dtype=np.int64)
+
+
+class IlutpSystem:
+    """Split preconditioning by ILUTP factors, A Q = L U + E:
+        A^ y = L^{-1} b,   A^^H y~ = U^{-H} Q^T b~,   A^ = L^{-1} A Q U^{-1},
+        x = Q U^{-1} y,    x~ = L^{-H} y~."""
+
+    def __init__(self, A, tau, p=None, permtol=1.0):
+        self.A = as_csr(A).astype(np.complex128)
+        self.n = self.A.shape[0]
+        self.L, self.U, self.perm = ilutp(self.A, tau, p, permtol)
+
+    def operator(self) -> sp.csr_matrix:
+        """A^ = L^{-1} (A Q) U^{-1}, formed explicitly (dense, small n)."""
+        AQ = self.A[:, self.perm].toarray()
+        X = spla.spsolve_triangular(self.L.tocsr(), AQ, lower=True)
+        Y = spla.spsolve_triangular(self.U.T.tocsr(), X.T, lower=True).T
+        return sp.csr_matrix(Y)
+
+    def rhs(self, b, bt):
+        bh = spla.spsolve_triangular(self.L.tocsr(), np.asarray(b, np.complex128), lower=True)
+        qt = np.asarray(bt, np.complex128)[self.perm]            # Q^T b~
+        ch = spla.spsolve_triangular(self.U.conj().T.tocsr(), qt, lower=True)
+        return bh, ch
+
+    def solution(self, y, yt):
+        t = spla.spsolve_triangular(self.U.tocsr(), np.asarray(y, np.complex128), lower=False)
+        x = np.empty_like(t)
+        x[self.perm] = t                                          # Q t
+        xt = spla.spsolve_triangular(self.L.conj().T.tocsr(), np.asarray(yt, np.complex128), lower=False)
+        return x, xt
+
+
 class IlutSystem:
     """Split preconditioning of one matrix by its ILUT factors (no
     reordering): the dual pair A x = b, A^H x~ = b~ becomes
@@ -269,15 +393,16 @@ class IlutSystem:
 
 
 def rbicg_ilut_sequence(mats, bs, bts, k, s, tol, tau, p=None, maxit=5000, update=True,
-                        svd_tol=1e-2, seed=0, max_restarts=2, real=True):
+                        svd_tol=1e-2, seed=0, max_restarts=2, real=True, permtol=None):
     """The dual pairs in order, each split-preconditioned by its own
-    ILUT(tau, p), RBiCG on the preconditioned operators with the recycle
-    space carried between them.  Zero initial guesses; stopping on the
-    preconditioned residuals.  Returns (solutions [(x, x~)], results)."""
+    ILUT(tau, p) (ILUTP(tau, p, permtol) when permtol is given), RBiCG on the
+    preconditioned operators with the recycle space carried between them.
+    Zero initial guesses; stopping on the preconditioned residuals.  Returns
+    (solutions [(x, x~)], results)."""
     U = Ut = None
     sols, out = [], []
     for j, A in enumerate(mats):
-        ss = IlutSystem(A, tau, p)
+        ss = IlutSystem(A, tau, p) if permtol is None else IlutpSystem(A, tau, p, permtol)
         M = ss.operator()
         if real:
             M = M.real.tocsr()

@@ -56,3 +56,26 @@ def test_served_solutions_match_oracle():
             xg, xtg = r.solutions[j]
             assert np.linalg.norm(xg - x) / np.linalg.norm(x) <= 1e-6
             assert np.linalg.norm(xtg - xt) / np.linalg.norm(xt) <= 1e-6
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_alone_vs_mix_config5_edges(batched):
+    """Requests on the configuration-5 grid edges 32, 64 and 96 (n up to
+    884736), two systems each, served three at a time and one at a time, with
+    and without launch batching (the 96^3 request runs unbatched: batching
+    takes requests of at most 64^3): per request the same iteration counts and
+    bitwise the same solutions, every system at the FP64 true residual 1e-8."""
+    reqs = [wl.Request(rid, 0.001 * rid, edge, beta, 2, k, wl.BASE_SEED + 7000 + rid)
+            for rid, (edge, beta, k) in enumerate([(64, (20.0, 10.0, 5.0), 20),
+                                                   (96, (30.0, 12.0, 4.0), 10),
+                                                   (32, (45.0, 3.0, 17.0), 20)])]
+    print("case config-5 edges batched", batched, flush=True)
+    mix = serving.Server(slots=3, keep_solutions=True, batched=batched).run(reqs)
+    alone = serving.Server(slots=1, keep_solutions=True, batched=batched).run(reqs)
+    for a, m in zip(alone, mix):
+        assert a.rid == m.rid and a.edge == m.edge
+        assert [s["iters"] for s in a.stats] == [s["iters"] for s in m.stats]
+        for (xa, xta), (xm, xtm) in zip(a.solutions, m.solutions):
+            assert np.array_equal(xa, xm) and np.array_equal(xta, xtm)
+        for st in m.stats:
+            assert st["status"] == 0 and st["relres"] <= 1e-8 and st["relres_dual"] <= 1e-8

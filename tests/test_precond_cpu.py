@@ -166,3 +166,80 @@ def test_ilut_split_system_solves_original_pair():
     assert np.linalg.norm(b - As @ x) / np.linalg.norm(b) <= 1e-8
     assert np.linalg.norm(bt - As.T @ xt) / np.linalg.norm(bt) <= 1e-8
     assert res[0].iters < 40
+
+
+# ------------------------------------------------------------ ILUTP
+def test_ilutp_without_pivot_tolerance_is_ilut():
+    """permtol = 0 never pivots: the factors are ILUT's and perm is the
+    identity."""
+    A = _rand_dd(50, 5)
+    for tau in (0.0, 0.05):
+        L, U = pc.ilut(A, tau)
+        Lp, Up, perm = pc.ilutp(A, tau, permtol=0.0)
+        assert np.array_equal(perm, np.arange(50))
+        assert abs(Lp - L).max() == 0 and abs(Up - U).max() == 0
+
+
+def test_ilutp_complete_pivoted_lu():
+    """tau = 0, permtol = 1: A Q = L U exactly (no dropping) and every row of
+    U has its largest entry on the diagonal (the pivot is the largest entry
+    of the row left after the elimination); on a matrix whose diagonal is
+    small the columns are really permuted."""
+    rng = np.random.default_rng(8)
+    n = 40
+    A = sp.random(n, n, density=0.15, random_state=3, data_rvs=rng.standard_normal) + sp.eye(n) * 0.01
+    A = sp.csr_matrix(A + sp.diags(rng.standard_normal(n - 1) * 3, 1))
+    L, U, perm = pc.ilutp(A, 0.0, permtol=1.0)
+    assert sorted(perm.tolist()) == list(range(n)) and not np.array_equal(perm, np.arange(n))
+    AQ = A.toarray()[:, perm]
+    assert np.abs((L @ U).toarray() - AQ).max() <= 1e-10 * np.abs(AQ).max()
+    Ud = U.toarray()
+    for i in range(n):
+        assert abs(Ud[i, i]) >= np.abs(Ud[i, i + 1:]).max(initial=0.0) - 1e-14
+    assert sp.triu(L, 1).nnz == 0 and sp.tril(U, -1).nnz == 0
+
+
+def test_ilutp_hand_example():
+    """A = [[1, 4, 0], [2, 1, 3], [0, 5, 1]], tau = 0, permtol = 1, worked by
+    hand: row 0 pivots on column 1 (4 > 1); row 1 eliminates with l = 1/4,
+    leaving 1.75 in column 0 and 3 in column 2, and pivots on column 2; row 2
+    eliminates with 5/4 and 1/3, leaving -1.25 - 1.75/3 = -11/6 in column 0.
+    perm = [1, 2, 0]."""
+    A = sp.csr_matrix(np.array([[1.0, 4.0, 0.0], [2.0, 1.0, 3.0], [0.0, 5.0, 1.0]]))
+    L, U, perm = pc.ilutp(A, 0.0, permtol=1.0)
+    assert perm.tolist() == [1, 2, 0]
+    assert np.allclose(L.toarray().real, [[1, 0, 0], [0.25, 1, 0], [1.25, 1 / 3, 1]])
+    assert np.allclose(U.toarray().real, [[4, 0, 1], [0, 3, 1.75], [0, 0, -11 / 6]])
+
+
+def test_ilutp_zero_diagonal_where_ilut_fails():
+    """[[0, 1], [1, 0]]: ILUT meets a zero pivot; ILUTP swaps the columns
+    (perm = [1, 0], L = U = I)."""
+    A = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 0.0]]))
+    with pytest.raises(ZeroDivisionError):
+        pc.ilut(A, 0.0)
+    L, U, perm = pc.ilutp(A, 0.0, permtol=1.0)
+    assert perm.tolist() == [1, 0]
+    assert np.allclose(L.toarray(), np.eye(2)) and np.allclose(U.toarray(), np.eye(2))
+
+
+def test_ilutp_split_system_solves_original_pair():
+    """A row-permuted convection-diffusion matrix (most diagonal entries
+    zero): ILUTP(0.05) split preconditioning, RBiCG on the preconditioned pair,
+    and the transforms recover x, x~ with small original residuals; with
+    tau = 0 the preconditioned operator is the identity."""
+    A0 = wl.convdiff(10, 2, (10.0, 5.0))
+    As = sp.csr_matrix((A0.vals, A0.colind, A0.rowptr), shape=(A0.n, A0.n))
+    rng = np.random.default_rng(6)
+    rows = rng.permutation(A0.n)
+    Ap = sp.csr_matrix(As[rows])
+    assert (Ap.diagonal() == 0).sum() > A0.n // 2
+    ss = pc.IlutpSystem(Ap, 0.0, permtol=1.0)
+    assert np.abs(ss.operator().toarray() - np.eye(A0.n)).max() <= 1e-9
+    b, bt = rng.standard_normal(A0.n), rng.standard_normal(A0.n)
+    sols, res = pc.rbicg_ilut_sequence([Ap], [b], [bt], 0, 40, 1e-10, tau=0.05, permtol=1.0,
+                                       update=False)
+    x, xt = sols[0]
+    assert res[0].status == "ok"
+    assert np.linalg.norm(b - Ap @ x) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(bt - Ap.T @ xt) / np.linalg.norm(bt) <= 1e-8
