@@ -264,7 +264,9 @@ def ilut_leg(args, seq, mats, b, bt):
     h = 1/64 grid (n = 3969; a checkerboard diffusion coefficient with jumps
     of 1e3 stands in for the paper's, which only a figure gives), ILUT(0.05),
     the same dual pair solved four times, k = 10, s = 40, tol 1e-8 -- with
-    recycling and with k = 0 (plain BiCG); (b) the
+    recycling and with k = 0 (plain BiCG); (a') the same with the rows of
+    the operator permuted (most diagonal entries zero) and ILUTP(0.05,
+    permtol 1), the pivoting variant Sec. 6.2 uses; (b) the
     benchmark's 10-system 64^3 sequence, ILUT(0.05) per system, k = 20 and
     k = 0.  The host factorizations run before the timed passes (timed
     apart); a timed pass covers, per system, the right-hand-side transform,
@@ -276,13 +278,13 @@ def ilut_leg(args, seq, mats, b, bt):
     from paper_1010_0762_amd import workloads as wl
     from paper_1010_0762_amd.solver import ILUT, DeviceMatrix, Solver
 
-    def run(hmats, dmats, bs, bts, k, s, tol, tau):
+    def run(hmats, dmats, bs, bts, k, s, tol, tau, permtol=0.0):
         # one factorization per distinct matrix (host), timed apart
         t0 = time.perf_counter()
         cache = {}
         for A in hmats:
             if id(A) not in cache:
-                cache[id(A)] = ILUT(A, tau)
+                cache[id(A)] = ILUT(A, tau, permtol=permtol)
         Ps = [cache[id(A)] for A in hmats]
         setup_ms = (time.perf_counter() - t0) * 1e3
         S = Solver(dmats[0], k=k, s=s, chunk=args.chunk)
@@ -313,7 +315,8 @@ def ilut_leg(args, seq, mats, b, bt):
         dt = time.perf_counter() - t0
         rel = []
         for A, (x, xt), bb, bbt in zip(hmats, sols, bs, bts):
-            As = sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+            As = (sp.csr_matrix((A.vals, A.colind, A.rowptr), shape=(A.n, A.n))
+                  if hasattr(A, "rowptr") else A)
             bh_, bth_ = bb.cpu().numpy(), bbt.cpu().numpy()
             rel.append(max(np.linalg.norm(bh_ - As @ x.cpu().numpy()) / np.linalg.norm(bh_),
                            np.linalg.norm(bth_ - As.T @ xt.cpu().numpy()) / np.linalg.norm(bth_)))
@@ -321,13 +324,14 @@ def ilut_leg(args, seq, mats, b, bt):
         S.close()
         for P in cache.values():
             P.close()
-        print(f"ilut leg: k={k} n={hmats[0].n} systems={len(hmats)} iters={its} "
+        print(f"ilut leg: k={k} n={hmats[0].shape[0] if hasattr(hmats[0], 'shape') else hmats[0].n} "
+              f"systems={len(hmats)} iters={its} "
               f"{dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
         return {"solves_per_s": round(len(hmats) / dt, 3), "ms_per_sequence": round(dt * 1e3, 2),
                 "host_factorization_ms": round(setup_ms, 1), "iters_per_system": its,
                 "us_per_iter": round(dt / max(1, sum(its)) * 1e6, 2),
                 "max_true_relres": float(max(rel)),
-                "factor": {kk: info[kk] for kk in ("nnz_L", "nnz_U", "levels_L", "levels_U")}}
+                "factor": {kk: info[kk] for kk in ("nnz_L", "nnz_U", "levels_L", "levels_U", "moved")}}
 
     out = {}
     # (a) Sec. 6.1 shape: one pair solved four times on the h = 1/64 grid,
@@ -341,6 +345,18 @@ def ilut_leg(args, seq, mats, b, bt):
         out[f"jump_convdiff2d_63^2_same_pair_x4_ilut0.05_k{k}_s40"] = run(
             [A2] * 4, [D2] * 4, [b2] * 4, [bt2] * 4, k, 40, 1e-8, 0.05)
     D2.close()
+    # (a') ILUTP (Sec. 6.2 preconditions with it): the same pair on the
+    # row-permuted operator, whose diagonal is mostly zero, so that ILUT
+    # without pivoting breaks down
+    As2 = sp.csr_matrix((A2.vals, A2.colind, A2.rowptr), shape=(A2.n, A2.n))
+    rows = np.random.default_rng(wl.BASE_SEED + 62).permutation(A2.n)
+    A2p = sp.csr_matrix(As2[rows])
+    b2p, bt2p = b2[torch.as_tensor(rows, device="cuda")].contiguous(), bt2
+    D2p = DeviceMatrix(A2p)
+    for k in (10, 0):
+        out[f"jump_convdiff2d_63^2_rowperm_same_pair_x4_ilutp0.05_permtol1_k{k}_s40"] = run(
+            [A2p] * 4, [D2p] * 4, [b2p] * 4, [bt2p] * 4, k, 40, 1e-8, 0.05, permtol=1.0)
+    D2p.close()
     # (b) the benchmark's sequence
     for k in (seq.k, 0):
         out[f"convdiff3d_{args.N}^3_seq{len(mats)}_ilut0.05_k{k}_s{seq.s}"] = run(

@@ -239,8 +239,11 @@ int rbicg_rbilu_destroy(rbicg_rbilu P);
  * primal and dual directions' solves share launches).
  *   rbicg_ilut_create: host factorization of A (host or device CSR, real or
  *     complex) by ILUT(droptol, fill) -- the drop rules of rbicg_host_ilut
- *     (fill < 0: no per-row count limit) -- level schedules of L, U, L^H,
- *     U^H, and their upload.  RBICG_EINVAL on a zero pivot.
+ *     (fill < 0: no per-row count limit) -- or, with permtol > 0, by ILUTP
+ *     (column pivoting, Sec. 6.2; A Q = L U + E), level schedules of L, U,
+ *     L^H, U^H, and their upload.  With pivoting the operator is
+ *     A^ = L^{-1} A Q U^{-1}, c^ = U^{-H} Q^T b~ and x = Q U^{-1} y.
+ *     RBICG_EINVAL on a zero pivot.
  *   rbicg_ilu_attach: h iterates with A^ of P from its next call on (NULL
  *     detaches).  P must have h's order and value type (real / complex);
  *     attach it before the rbicg_update_recycle* call that moves h to A, so
@@ -255,7 +258,8 @@ int rbicg_rbilu_destroy(rbicg_rbilu P);
  *     interleaved complex; on `stream`; calls on one P must not overlap.
  *   rbicg_ilu_info: info[0..6] = n, nnz(L) (strict), nnz(U) (with the
  *     diagonal), levels of L, levels of U, 1 if a triangular solve's bounded
- *     wait ever gave up (results since are invalid), 1 if complex.
+ *     wait ever gave up (results since are invalid), 1 if complex; info[7]
+ *     = columns the pivoting moved (info: 8 int64).
  *   rbicg_ilu_set_waves: how many 64-lane waves work through the chunks of
  *     a triangular solve (default 512; [4, 65536]); fewer waves poll less,
  *     more cover wider levels.  Affects speed only, never results.
@@ -263,7 +267,8 @@ int rbicg_rbilu_destroy(rbicg_rbilu P);
  * correct schedule) sets an error flag; the solve that used it returns
  * RBICG_EHIP. */
 typedef struct rbicg_ilu_s *rbicg_ilu;
-int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, rbicg_ilu *out);
+int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, double permtol,
+                      rbicg_ilu *out);
 int rbicg_ilu_attach(rbicg_handle h, rbicg_ilu P);
 int rbicg_ilu_rhs(rbicg_ilu P, const void *b, const void *bt, void *bh, void *ch,
                   int32_t complex_vectors, void *stream);

@@ -72,14 +72,22 @@ int rbicg_host_biorth(int32_t k, const double *Gcc, const double *Gtt, const dou
  * elimination an entry w_j, j > i, is dropped if |w_j| < tau ||A(:,j)||_2; the
  * diagonal is kept; p >= 0 keeps at most p off-diagonal entries per row in
  * each factor (largest modulus first, ties by column), p < 0 no limit.
+ * permtol > 0 selects ILUTP, the column-pivoting variant (Sec. 6.2): after
+ * row i's elimination and dropping (the entry of the column at position i is
+ * never dropped), the largest remaining entry (ties: the smallest position)
+ * becomes the pivot when its modulus times permtol exceeds that of the
+ * position-i column, and the two columns swap positions; the factors then
+ * satisfy A Q = L U + E with (A Q)(:, j) = A(:, perm[j]) and are given in
+ * positions.  permtol = 0: ILUT, perm the identity.
  * Outputs: nnz[0] = entries of L (strictly lower, unit diagonal implied),
  * nnz[1] = entries of U (with the diagonal); with Lrp/Lci/Lv (n+1, nnz[0],
  * 2*nnz[0]) and Urp/Uci/Uv non-NULL the factors in CSR, columns ascending
- * (call once with them NULL for the sizes).  -1 on bad arguments or a zero
- * pivot. */
+ * (call once with them NULL for the sizes); perm (n entries) when non-NULL.
+ * -1 on bad arguments or a zero pivot. */
 int rbicg_host_ilut(int32_t n, const int32_t *rowptr, const int32_t *colind,
-                    const double *values, double tau, int32_t p, int64_t *nnz, int32_t *Lrp,
-                    int32_t *Lci, double *Lv, int32_t *Urp, int32_t *Uci, double *Uv);
+                    const double *values, double tau, int32_t p, double permtol, int64_t *nnz,
+                    int32_t *Lrp, int32_t *Lci, double *Lv, int32_t *Urp, int32_t *Uci,
+                    double *Uv, int32_t *perm);
 
 /* Level schedule of a triangular solve with the CSR matrix T (lower = 1: row
  * i depends on its columns j < i, else on j > i; other entries are ignored):

@@ -90,15 +90,15 @@ SIGNATURES = {
     "rbicg_batch_destroy": (ct.c_int, [_P]),
     "rbicg_solve_dual_noalloc": (ct.c_int, [_P, ct.POINTER(rbicg_opts), _P, _P, _P, _P, _D,
                                             ct.POINTER(rbicg_stats)]),
-    "rbicg_ilut_create": (ct.c_int, [ct.POINTER(rbicg_csr), _D, _I, ct.POINTER(_P)]),
+    "rbicg_ilut_create": (ct.c_int, [ct.POINTER(rbicg_csr), _D, _I, _D, ct.POINTER(_P)]),
     "rbicg_ilu_attach": (ct.c_int, [_P, _P]),
     "rbicg_ilu_rhs": (ct.c_int, [_P, _P, _P, _P, _P, _I, _P]),
     "rbicg_ilu_solution": (ct.c_int, [_P, _P, _P, _P, _P, _I, _P]),
     "rbicg_ilu_info": (ct.c_int, [_P, ct.POINTER(ct.c_int64)]),
     "rbicg_ilu_set_waves": (ct.c_int, [_P, _I]),
     "rbicg_ilu_destroy": (ct.c_int, [_P]),
-    "rbicg_host_ilut": (ct.c_int, [_I, _P, _P, _DP, _D, _I, ct.POINTER(ct.c_int64), _P, _P, _DP,
-                                   _P, _P, _DP]),
+    "rbicg_host_ilut": (ct.c_int, [_I, _P, _P, _DP, _D, _I, _D, ct.POINTER(ct.c_int64), _P, _P,
+                                   _DP, _P, _P, _DP, _P]),
     "rbicg_host_levels": (ct.c_int, [_I, _P, _P, _I, _I, _P, ct.POINTER(ct.c_int64)]),
     "rbicg_host_eig": (ct.c_int, [_I, _DP, _DP, _DP, _DP, _DP]),
     "rbicg_host_select": (ct.c_int, [_I, _DP, _DP, _DP, _I, _I, _DP, _DP]),

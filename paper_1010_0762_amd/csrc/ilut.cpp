@@ -102,6 +102,129 @@ int factor(const Csr &A, double tau, int p, Csr &L, Csr &U, std::string &msg) {
   return 0;
 }
 
+int factor_pivoted(const Csr &A, double tau, int p, double permtol, Csr &L, Csr &U,
+                   std::vector<int> &perm, std::string &msg) {
+  const int n = A.n;
+  std::vector<double> cn(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) cn[A.ci[e]] += std::norm(A.v[e]);
+  for (auto &c : cn) c = std::sqrt(c);
+  perm.resize(n);
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; ++i) perm[i] = pos[i] = i;
+  // U rows in columns of A: off-pivot entries and the pivot apart
+  std::vector<std::vector<std::pair<int, cplx>>> urows(n);
+  std::vector<cplx> piv(n);
+  L = Csr();
+  L.n = n;
+  L.rp.assign(1, 0);
+  std::vector<cplx> w(n, 0.0);
+  std::vector<int> mark(n, -1);
+  std::vector<int> upper;
+  std::priority_queue<int, std::vector<int>, std::greater<int>> heap;  // positions < i
+  std::vector<std::pair<int, cplx>> lrow, urow;
+  for (int i = 0; i < n; ++i) {
+    upper.clear();
+    lrow.clear();
+    urow.clear();
+    auto touch = [&](int c) {
+      if (mark[c] != i) {
+        mark[c] = i;
+        w[c] = 0.0;
+        if (pos[c] < i) heap.push(pos[c]);
+        else upper.push_back(c);
+      }
+    };
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      touch(A.ci[e]);
+      w[A.ci[e]] += A.v[e];
+    }
+    while (!heap.empty()) {
+      const int k = heap.top();
+      heap.pop();
+      const int c = perm[k];
+      cplx wk = w[c];
+      w[c] = 0.0;
+      if (std::abs(wk) < tau * cn[c]) continue;  // dropped: no update
+      wk /= piv[k];
+      lrow.emplace_back(k, wk);
+      for (const auto &t : urows[k]) {
+        touch(t.first);
+        w[t.first] -= wk * t.second;
+      }
+    }
+    int dcol = perm[i];
+    const cplx wd = mark[dcol] == i ? w[dcol] : cplx(0.0);
+    // kept remaining entries (the unpivoted diagonal always)
+    std::vector<int> kept;
+    for (int c : upper)
+      if (c == dcol || std::abs(w[c]) >= tau * cn[c]) kept.push_back(c);
+    int best = dcol;
+    double bmod = std::abs(wd);
+    for (int c : kept) {
+      const double m = std::abs(w[c]);
+      if (m > bmod || (m == bmod && pos[c] < pos[best])) {
+        best = c;
+        bmod = m;
+      }
+    }
+    if (best != dcol && bmod * permtol > std::abs(wd)) {
+      const int j = pos[best];
+      perm[i] = best;
+      perm[j] = dcol;
+      pos[best] = i;
+      pos[dcol] = j;
+      dcol = best;
+    }
+    const cplx d = mark[dcol] == i ? w[dcol] : cplx(0.0);
+    if (d == cplx(0.0)) {
+      msg = "ILUTP: zero pivot in row " + std::to_string(i);
+      return -1;
+    }
+    for (int c : kept)
+      if (c != dcol) urow.emplace_back(c, w[c]);
+    if (p >= 0 && (int)lrow.size() > p) {
+      std::sort(lrow.begin(), lrow.end(), [](const auto &a, const auto &b) {
+        const double ma = std::abs(a.second), mb = std::abs(b.second);
+        return ma != mb ? ma > mb : a.first < b.first;
+      });
+      lrow.resize(p);
+    }
+    std::sort(lrow.begin(), lrow.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    if (p >= 0 && (int)urow.size() > p) {
+      std::sort(urow.begin(), urow.end(), [&](const auto &a, const auto &b) {
+        const double ma = std::abs(a.second), mb = std::abs(b.second);
+        return ma != mb ? ma > mb : pos[a.first] < pos[b.first];
+      });
+      urow.resize(p);
+    }
+    for (auto &t : lrow) {
+      L.ci.push_back(t.first);
+      L.v.push_back(t.second);
+    }
+    L.rp.push_back((int)L.ci.size());
+    urows[i] = urow;
+    piv[i] = d;
+  }
+  // U in positions, columns ascending, pivot first
+  U = Csr();
+  U.n = n;
+  U.rp.assign(1, 0);
+  std::vector<std::pair<int, cplx>> row;
+  for (int i = 0; i < n; ++i) {
+    row.clear();
+    row.emplace_back(i, piv[i]);
+    for (const auto &t : urows[i]) row.emplace_back(pos[t.first], t.second);
+    std::sort(row.begin(), row.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (auto &t : row) {
+      U.ci.push_back(t.first);
+      U.v.push_back(t.second);
+    }
+    U.rp.push_back((int)U.ci.size());
+  }
+  return 0;
+}
+
 Csr conj_transpose(const Csr &T) {
   Csr R;
   R.n = T.n;
@@ -178,18 +301,23 @@ void store(const ilut::Csr &T, int32_t *rp, int32_t *ci, double *v) {
 }  // namespace
 
 extern "C" int rbicg_host_ilut(int32_t n, const int32_t *rowptr, const int32_t *colind,
-                               const double *values, double tau, int32_t p, int64_t *nnz,
-                               int32_t *Lrp, int32_t *Lci, double *Lv, int32_t *Urp,
-                               int32_t *Uci, double *Uv) {
+                               const double *values, double tau, int32_t p, double permtol,
+                               int64_t *nnz, int32_t *Lrp, int32_t *Lci, double *Lv, int32_t *Urp,
+                               int32_t *Uci, double *Uv, int32_t *perm) {
   ilut::Csr A, L, U;
-  if (!nnz || load_host(n, rowptr, colind, values, A) < 0 || !(tau >= 0.0))
+  if (!nnz || load_host(n, rowptr, colind, values, A) < 0 || !(tau >= 0.0) || !(permtol >= 0.0))
     return rbicg_fail(-1, "host_ilut: bad arguments");
   std::string msg;
-  if (ilut::factor(A, tau, p, L, U, msg) < 0) return rbicg_fail(-1, "%s", msg.c_str());
+  std::vector<int> pv;
+  const int rc = permtol > 0.0 ? ilut::factor_pivoted(A, tau, p, permtol, L, U, pv, msg)
+                               : ilut::factor(A, tau, p, L, U, msg);
+  if (rc < 0) return rbicg_fail(-1, "%s", msg.c_str());
   nnz[0] = (int64_t)L.ci.size();
   nnz[1] = (int64_t)U.ci.size();
   if (Lrp && Lci && Lv) store(L, Lrp, Lci, Lv);
   if (Urp && Uci && Uv) store(U, Urp, Uci, Uv);
+  if (perm)
+    for (int i = 0; i < n; ++i) perm[i] = pv.empty() ? i : pv[i];
   return 0;
 }
 

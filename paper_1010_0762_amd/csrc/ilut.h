@@ -28,6 +28,19 @@ struct Csr {
 // Returns 0, or -1 with msg set on a zero pivot.
 int factor(const Csr &A, double tau, int p, Csr &L, Csr &U, std::string &msg);
 
+// ILUTP(tau, p, permtol): ILUT with column pivoting.  Positions are tracked
+// as perm (position -> column of A, initially the identity); row i's lower
+// part is the columns already pivotal for rows 0..i-1, eliminated in that
+// order with ILUT's rule; the remaining entries are dropped by ILUT's rule
+// except that of column perm[i]; the largest kept remaining entry (ties: the
+// smallest position) becomes the pivot when its modulus times permtol exceeds
+// that of column perm[i], and the two columns swap positions; then at most p
+// off-pivot entries per part (largest modulus, ties by position).  On return
+// A Q = L U + E with (A Q)(:, j) = A(:, perm[j]); L and U in positions.
+// permtol = 0 never pivots.  Returns 0, or -1 with msg set on a zero pivot.
+int factor_pivoted(const Csr &A, double tau, int p, double permtol, Csr &L, Csr &U,
+                   std::vector<int> &perm, std::string &msg);
+
 // Conjugate transpose.
 Csr conj_transpose(const Csr &T);
 

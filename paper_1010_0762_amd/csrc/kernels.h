@@ -60,6 +60,14 @@ void launch_sptrsv(hipStream_t st, const TriDev<M> &T0, const V *b0, V *x0, cons
                    const V *b1, V *x1, int *counter, int waves, const Scalars *S, int *err);
 template <class V>
 void launch_rsub(hipStream_t st, int n, const V *b, const V *t, V *out);
+// y = A x with optional row map (row j computes A's row orow[j]) and gather
+// map (x read at gmap[c]); see k_spmv_perm
+template <class V, class M>
+void launch_spmv_perm(hipStream_t st, const Sell<M> &A, const V *x, V *y, const int *gmap,
+                      const int *orow, const Scalars *S);
+// out[i] = in[map[i]]
+template <class V>
+void launch_gather(hipStream_t st, int n, const V *in, const int *map, V *out);
 
 // ---- batched launches: several independent systems ("slots") per launch ----
 #define RBICG_BATCH_SLOTS 16

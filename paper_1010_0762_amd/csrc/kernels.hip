@@ -1257,6 +1257,41 @@ __global__ __launch_bounds__(RBICG_BLOCK) void k_sptrsv(TriDev<M> T0, const V *_
   }
 }
 
+// y = A x with optional index maps: row j computes A's row orow[j] (NULL:
+// j) and reads x at gmap[c] for column c (NULL: c).  With ILUTP's column
+// permutation Q (A Q)(:, j) = A(:, perm[j]): y = A (Q t) is gmap = pos
+// (column -> position), y = Q^T (A^H v) is orow = perm.  Nothing after the
+// stopping test.
+template <class V, class M>
+__global__ __launch_bounds__(RBICG_BLOCK) void k_spmv_perm(Sell<M> A, const V *__restrict__ x,
+                                                           V *__restrict__ y,
+                                                           const int *__restrict__ gmap,
+                                                           const int *__restrict__ orow,
+                                                           const Scalars *S) {
+  using T = typename Ar<V>::T;
+  if (S && S->done) return;
+  const int j = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (j >= A.n) return;
+  const int row = orow ? orow[j] : j;
+  const int slice = row >> 6, lane = row & 63;
+  const int beg = A.sliceptr[slice], end = A.sliceptr[slice + 1];
+  T acc = zero<T>();
+  for (int e = beg + lane; e < end; e += RBICG_WAVE) {
+    const int c = A.col[e];
+    acc += up(A.val[e]) * up(x[gmap ? gmap[c] : c]);
+  }
+  if (A.shifted) acc = shift_apply<M, T>(A, acc, up(x[gmap ? gmap[row] : row]));
+  y[j] = down<V>(acc);
+}
+
+// out[i] = in[map[i]]
+template <class V>
+__global__ void k_gather(int n, const V *__restrict__ in, const int *__restrict__ map,
+                         V *__restrict__ out) {
+  const int i = blockIdx.x * RBICG_BLOCK + threadIdx.x;
+  if (i < n) out[i] = in[map[i]];
+}
+
 // out = b - t (out may be t)
 template <class V>
 __global__ void k_rsub(int n, const V *__restrict__ b, const V *t, V *out) {
@@ -2394,6 +2429,16 @@ void launch_sptrsv(hipStream_t st, const TriDev<M> &T0, const V *b0, V *x0, cons
   hipLaunchKernelGGL((k_sptrsv<V, M>), dim3(blocks), dim3(RBICG_BLOCK), 0, st, T0, b0, x0,
                      T1 ? *T1 : T0, b1, x1, ns, counter, S, err);
 }
+template <class V, class M>
+void launch_spmv_perm(hipStream_t st, const Sell<M> &A, const V *x, V *y, const int *gmap,
+                      const int *orow, const Scalars *S) {
+  hipLaunchKernelGGL((k_spmv_perm<V, M>), dim3(nblk(A.n)), dim3(RBICG_BLOCK), 0, st, A, x, y, gmap,
+                     orow, S);
+}
+template <class V>
+void launch_gather(hipStream_t st, int n, const V *in, const int *map, V *out) {
+  if (n > 0) hipLaunchKernelGGL((k_gather<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, in, map, out);
+}
 template <class V>
 void launch_rsub(hipStream_t st, int n, const V *b, const V *t, V *out) {
   hipLaunchKernelGGL((k_rsub<V>), dim3(nblk(n)), dim3(RBICG_BLOCK), 0, st, n, b, t, out);
@@ -2641,7 +2686,9 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
   template void launch_it1_multi<V, M>(hipStream_t, const It1Args<V, M> *, int, int, size_t, \
                                        bool);                                                 \
   template void launch_spmv<V, M>(hipStream_t, const Sell<M> &, const V *, V *,              \
-                                  const Scalars *);
+                                  const Scalars *);                                           \
+  template void launch_spmv_perm<V, M>(hipStream_t, const Sell<M> &, const V *, V *,         \
+                                       const int *, const int *, const Scalars *);
 
 #define INST_V(V)                                                                            \
   template size_t it1_lds_bytes<V>(int, int);                                                \
@@ -2652,6 +2699,7 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
                                    const V *, const V *, int, int, V *, V *, double *,       \
                                    const Scalars *);                                          \
   template void launch_rsub<V>(hipStream_t, int, const V *, const V *, V *);                 \
+  template void launch_gather<V>(hipStream_t, int, const V *, const int *, V *);             \
   template void launch_it2_multi<V>(hipStream_t, const It2Args<V> *, int, int);              \
   template void launch_itfin_multi<V>(hipStream_t, const ItfinArgs *, int);                  \
   template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \

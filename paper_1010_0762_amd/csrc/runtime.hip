@@ -326,6 +326,10 @@ struct rbicg_ilu_s {
   int n = 0;
   bool complex_vals = false;
   int waves = 512;  // waves that work through the chunks of a triangular solve
+  // ILUTP's column permutation (NULL without pivoting): perm[j] = the column
+  // of A at position j, pos = its inverse; moved = columns out of place
+  int *perm = nullptr, *pos = nullptr;
+  int64_t moved = 0;
   struct Tri {
     int len = 0, levels = 0;
     int64_t nnz = 0;
@@ -567,7 +571,8 @@ void ilu_trsv(hipStream_t st, rbicg_ilu_s *P, rbicg_ilu_s::Ws &w, int f0, const 
   }
 }
 
-// y0 = A^ x0 and y1 = A^^H x1 (either pair may be absent; y0, y1 must not be
+// y0 = A^ x0 and y1 = A^^H x1, A^ = L^{-1} A Q U^{-1} (Q = I without
+// pivoting; either pair may be absent; y0, y1 must not be
 // workspace vectors or alias the x's): the two directions' triangular solves
 // share launches.  S: the kernels do nothing once the stopping test has
 // fired (NULL: always run).  FP64 and complex vectors only (FP32 handles
@@ -578,18 +583,27 @@ void ilu_apply(rbicg_s *h, const V *x0, V *y0, const V *x1, V *y1, const Scalars
     rbicg_ilu_s *P = h->ilu;
     rbicg_ilu_s::Ws &w = ilu_ws(h);
     V *a1 = (V *)w.q[0], *a2 = (V *)w.q[1], *d1 = (V *)w.q[2], *d2 = (V *)w.q[3];
+    // A (Q a1) and Q^T (A^H d1); plain SpMVs without pivoting
+    auto spmv_primal = [&]() {
+      if (P->perm) launch_spmv_perm<V, M>(h->st, view_A<M>(h), a1, a2, P->pos, nullptr, S);
+      else launch_spmv<V, M>(h->st, view_A<M>(h), a1, a2, S);
+    };
+    auto spmv_dual = [&]() {
+      if (P->perm) launch_spmv_perm<V, M>(h->st, view_AH<M>(h), d1, d2, nullptr, P->perm, S);
+      else launch_spmv<V, M>(h->st, view_AH<M>(h), d1, d2, S);
+    };
     if (x0 && x1) {
       ilu_trsv<V, M>(h->st, P, w, 1, x0, a1, 2, x1, d1, S);  // U^{-1} x0, L^{-H} x1
-      launch_spmv<V, M>(h->st, view_A<M>(h), a1, a2, S);
-      launch_spmv<V, M>(h->st, view_AH<M>(h), d1, d2, S);
+      spmv_primal();
+      spmv_dual();
       ilu_trsv<V, M>(h->st, P, w, 0, a2, y0, 3, d2, y1, S);  // L^{-1} ., U^{-H} .
     } else if (x0) {
       ilu_trsv<V, M>(h->st, P, w, 1, x0, a1, -1, (const V *)nullptr, (V *)nullptr, S);
-      launch_spmv<V, M>(h->st, view_A<M>(h), a1, a2, S);
+      spmv_primal();
       ilu_trsv<V, M>(h->st, P, w, 0, a2, y0, -1, (const V *)nullptr, (V *)nullptr, S);
     } else if (x1) {
       ilu_trsv<V, M>(h->st, P, w, 2, x1, d1, -1, (const V *)nullptr, (V *)nullptr, S);
-      launch_spmv<V, M>(h->st, view_AH<M>(h), d1, d2, S);
+      spmv_dual();
       ilu_trsv<V, M>(h->st, P, w, 3, d2, y1, -1, (const V *)nullptr, (V *)nullptr, S);
     }
   }
@@ -753,6 +767,14 @@ struct CycleJob {
   sec44::Blocks X, Xnext;        // carried blocks used, and those for the next cycle
   double rn_last2 = 0.0;
   cplx at_last = 0.0;
+  // A job dropped on an error path may still have its host part running on a
+  // worker thread, writing into the members above: wait for it before they
+  // are destroyed (a deferred part that never ran is not started).
+  ~CycleJob() {
+    if (fut.valid() && fut.wait_for(std::chrono::seconds(0)) != std::future_status::deferred) fut.wait();
+    if (ev) (void)hipEventDestroy(ev);
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 struct LogEntry {
@@ -1250,7 +1272,6 @@ int biorth_sync(rbicg_s *h, int m) {
     if (rc >= 0) rc = apply_biorth<V>(h, m, J.p, J.TU, J.TUt, h->U, h->Ut, h->C, h->Ct);
     if (rc >= 0) rc = sync(h);
   }
-  (void)hipEventDestroy(J.ev);
   if (rc < 0) return rc;
   return J.p;
 }
@@ -1485,9 +1506,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
             h->prof_cyc[2] += J.host_ms[1];
             h->prof_cyc[3] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - J.t_begin).count();
             st.cycles++;
-            (void)hipEventDestroy(J.ev);
-            (void)hipEventDestroy(J.ready);
-            jobs.pop_front();
+            jobs.pop_front();  // (its destructor frees the events)
             progress = true;
           }
         }
@@ -1704,8 +1723,6 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       CycleJob &J = *jobs.back();
       if (J.stage == 2 || J.stage == 4) J.fut.wait();
       if (J.stage >= 1) (void)hipEventSynchronize(J.ev);
-      (void)hipEventDestroy(J.ev);
-      (void)hipEventDestroy(J.ready);
       jobs.pop_back();
     }
     total = completed;
@@ -2963,9 +2980,11 @@ int ilu_factor_upload(rbicg_ilu_s *P, const ilut::Csr &T, bool lower, bool with_
 }
 }  // namespace
 
-extern "C" int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, rbicg_ilu *out) {
+extern "C" int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fill, double permtol,
+                                 rbicg_ilu *out) {
   if (!A || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
   if (!(droptol >= 0.0)) return rbicg_fail(RBICG_EINVAL, "droptol must be >= 0");
+  if (!(permtol >= 0.0)) return rbicg_fail(RBICG_EINVAL, "permtol must be >= 0");
   HostCsr hA;
   TRY(read_csr(A, hA));
   ilut::Csr a, L, U;
@@ -2974,10 +2993,20 @@ extern "C" int rbicg_ilut_create(const rbicg_csr *A, double droptol, int32_t fil
   a.ci = hA.col;
   a.v = hA.val;
   std::string msg;
-  if (ilut::factor(a, droptol, fill, L, U, msg) < 0) return rbicg_fail(RBICG_EINVAL, "%s", msg.c_str());
+  std::vector<int> perm;
+  const int frc = permtol > 0.0 ? ilut::factor_pivoted(a, droptol, fill, permtol, L, U, perm, msg)
+                                : ilut::factor(a, droptol, fill, L, U, msg);
+  if (frc < 0) return rbicg_fail(RBICG_EINVAL, "%s", msg.c_str());
   std::unique_ptr<rbicg_ilu_s> P(new rbicg_ilu_s());
   P->n = hA.n;
   P->complex_vals = hA.complex_vals;
+  for (int j = 0; j < (int)perm.size(); ++j) P->moved += perm[j] != j ? 1 : 0;
+  if (P->moved > 0) {  // the permutation and its inverse, only when columns moved
+    std::vector<int> pos(perm.size());
+    for (int j = 0; j < (int)perm.size(); ++j) pos[perm[j]] = j;
+    TRY(ilu_put(P.get(), (void **)&P->perm, perm.data(), perm.size() * sizeof(int)));
+    TRY(ilu_put(P.get(), (void **)&P->pos, pos.data(), pos.size() * sizeof(int)));
+  }
   // L: unit lower; U: upper with its diagonal; L^H unit upper; U^H lower
   // with the conjugated diagonal
   TRY(ilu_factor_upload(P.get(), L, true, false, P->L));
@@ -3037,16 +3066,39 @@ int ilu_transform(rbicg_ilu P, int f1, const void *b, void *x, int f2, const voi
   return complex_vectors ? ilu_two_solves<cd>(P, f1, b, x, f2, b2, x2, st)
                          : ilu_two_solves<double>(P, f1, b, x, f2, b2, x2, st);
 }
+
+// out[i] = in[map[i]] (ILUTP's column permutation)
+int ilu_permute(rbicg_ilu P, const void *in, const int *map, void *out, int32_t complex_vectors,
+                hipStream_t st) {
+  if (P->complex_vals && !complex_vectors)
+    return rbicg_fail(RBICG_EINVAL, "a complex preconditioner needs complex vectors");
+  if (complex_vectors) launch_gather<cd>(st, P->n, (const cd *)in, map, (cd *)out);
+  else launch_gather<double>(st, P->n, (const double *)in, map, (double *)out);
+  HIPCHECK(hipGetLastError());
+  return RBICG_OK;
+}
 }  // namespace
 
 extern "C" int rbicg_ilu_rhs(rbicg_ilu P, const void *b, const void *bt, void *bh, void *ch,
                              int32_t complex_vectors, void *stream) {
-  return ilu_transform(P, 0, b, bh, 3, bt, ch, complex_vectors, stream);  // L^{-1} b, U^{-H} b~
+  if (!P || !bt) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (!P->perm)  // L^{-1} b, U^{-H} b~
+    return ilu_transform(P, 0, b, bh, 3, bt, ch, complex_vectors, stream);
+  // L^{-1} b, U^{-H} Q^T b~ with (Q^T b~)[j] = b~[perm[j]]
+  void *q = P->ws[2].q[0];
+  TRY(ilu_permute(P, bt, P->perm, q, complex_vectors, (hipStream_t)stream));
+  return ilu_transform(P, 0, b, bh, 3, q, ch, complex_vectors, stream);
 }
 
 extern "C" int rbicg_ilu_solution(rbicg_ilu P, const void *y, const void *yt, void *x, void *xt,
                                   int32_t complex_vectors, void *stream) {
-  return ilu_transform(P, 1, y, x, 2, yt, xt, complex_vectors, stream);  // U^{-1} y, L^{-H} y~
+  if (!P || !x) return rbicg_fail(RBICG_EINVAL, "null argument");
+  if (!P->perm)  // U^{-1} y, L^{-H} y~
+    return ilu_transform(P, 1, y, x, 2, yt, xt, complex_vectors, stream);
+  // Q U^{-1} y with (Q t)[c] = t[pos[c]], L^{-H} y~
+  void *q = P->ws[2].q[0];
+  TRY(ilu_transform(P, 1, y, q, 2, yt, xt, complex_vectors, stream));
+  return ilu_permute(P, q, P->pos, x, complex_vectors, (hipStream_t)stream);
 }
 
 extern "C" int rbicg_ilu_set_waves(rbicg_ilu P, int32_t waves) {
@@ -3068,6 +3120,7 @@ extern "C" int rbicg_ilu_info(rbicg_ilu P, int64_t *info) {
   info[4] = P->U.levels;
   info[5] = e ? 1 : 0;
   info[6] = P->complex_vals ? 1 : 0;
+  info[7] = P->moved;
   return RBICG_OK;
 }
 

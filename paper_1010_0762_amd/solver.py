@@ -230,12 +230,14 @@ class ILUT:
     iterate with L^{-1} A U^{-1}; ``rhs`` and ``solution`` map a dual pair's
     right-hand sides to the preconditioned pair and its solutions back."""
 
-    def __init__(self, A, droptol=0.05, fill=-1):
+    def __init__(self, A, droptol=0.05, fill=-1, permtol=0.0):
+        """permtol > 0: ILUTP (column pivoting, Sec. 6.2)."""
         self.lib = _lib.load()
         keep = []
         a = _csr_struct(A, keep)
         h = ct.c_void_p()
-        rc = self.lib.rbicg_ilut_create(ct.byref(a), float(droptol), int(fill), ct.byref(h))
+        rc = self.lib.rbicg_ilut_create(ct.byref(a), float(droptol), int(fill), float(permtol),
+                                        ct.byref(h))
         _lib.check(rc, "rbicg_ilut_create")
         self.h, self.n = h, a.n
         self.complex = bool(a.values_complex)
@@ -245,9 +247,9 @@ class ILUT:
         _lib.check(self.lib.rbicg_ilu_set_waves(self.h, int(waves)), "rbicg_ilu_set_waves")
 
     def info(self) -> dict:
-        out = (ct.c_int64 * 7)()
+        out = (ct.c_int64 * 8)()
         _lib.check(self.lib.rbicg_ilu_info(self.h, out), "rbicg_ilu_info")
-        keys = ["n", "nnz_L", "nnz_U", "levels_L", "levels_U", "wait_error", "complex"]
+        keys = ["n", "nnz_L", "nnz_U", "levels_L", "levels_U", "wait_error", "complex", "moved"]
         return dict(zip(keys, [int(v) for v in out]))
 
     def _v(self, v, name):
@@ -288,10 +290,11 @@ class ILUT:
             pass
 
 
-def solve_ilut_sequence(mats, bs, bts, *, droptol=0.05, fill=-1, k=20, s=40, tol=1e-8,
-                        maxit=10000, prec="f64", **opts):
+def solve_ilut_sequence(mats, bs, bts, *, droptol=0.05, fill=-1, permtol=0.0, k=20, s=40,
+                        tol=1e-8, maxit=10000, prec="f64", **opts):
     """Split-ILUT-preconditioned RBiCG over a sequence of dual pairs (Sec. 6):
-    each matrix gets its own ILUT(droptol, fill), one handle solves the
+    each matrix gets its own ILUT(droptol, fill) (ILUTP when permtol > 0),
+    one handle solves the
     preconditioned pairs in order with the recycle space carried between
     them (biorthogonalized against each new preconditioned operator).  Zero
     initial guesses.  bs, bts: CUDA tensors.  Returns a list of
@@ -299,7 +302,7 @@ def solve_ilut_sequence(mats, bs, bts, *, droptol=0.05, fill=-1, k=20, s=40, tol
     out, S, P = [], None, None
     try:
         for j, A in enumerate(mats):
-            Pn = ILUT(A, droptol, fill)
+            Pn = ILUT(A, droptol, fill, permtol)
             if S is None:
                 S = Solver(A, k=k, s=s, maxit=maxit, prec=prec, **opts)
                 S.attach_ilu(Pn)

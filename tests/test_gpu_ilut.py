@@ -186,3 +186,80 @@ def test_ilut_refusals():
     S.close()
     B.close()
     P.close()
+
+
+def _rowperm(A, seed):
+    As = _csr(A) if hasattr(A, "rowptr") else sp.csr_matrix(A)
+    rows = np.random.default_rng(seed).permutation(As.shape[0])
+    return sp.csr_matrix(As[rows])
+
+
+@pytest.mark.parametrize("kind", ["convdiff_rowperm", "random_complex_rowperm"])
+def test_ilutp_transforms_match_oracle(kind):
+    """ILUTP (column pivoting, permtol 1) on row-permuted operators whose
+    diagonal is mostly zero: L^{-1} b, U^{-H} Q^T b~, Q U^{-1} y, L^{-H} y~
+    element by element against the oracle's (n = 1600, 1500)."""
+    from paper_1010_0762_amd.solver import ILUT
+    if kind == "convdiff_rowperm":
+        A = _rowperm(_mats_2d(40, 1)[0], 1)
+    else:
+        A = _rowperm(wl.random_sparse(1500, 6, 21, diag_shift=10.0, complex_vals=True), 2)
+    n = A.shape[0]
+    cplx = np.iscomplexobj(A.data)
+    print("case ilutp", kind, n, flush=True)
+    ss = pc.IlutpSystem(A, 0.05, permtol=1.0)
+    P = ILUT(A, 0.05, permtol=1.0)
+    info = P.info()
+    assert info["moved"] == int((ss.perm != np.arange(n)).sum()) > n // 2
+    rng = np.random.default_rng(4)
+    b, bt, y, yt = (rng.standard_normal(n) + (1j * rng.standard_normal(n) if cplx else 0)
+                    for _ in range(4))
+    bh, ch = P.rhs(_t(b), _t(bt))
+    x, xt = P.solution(_t(y), _t(yt))
+    refs = ss.rhs(b, bt) + ss.solution(y, yt)
+    for got, ref in zip((bh, ch, x, xt), refs):
+        ref = ref if cplx else ref.real
+        assert np.abs(got.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert P.info()["wait_error"] == 0
+    P.close()
+
+
+def test_ilutp_sequence_matches_oracle():
+    """Two row-permuted 2D convection-diffusion systems (n = 1600; ILUT
+    without pivoting meets zero pivots on them) with ILUTP(0.2, permtol 1),
+    k = 5, s = 10: solutions within 1e-6 of the oracle's, counts and carried
+    dimensions inside the oracle's spread over its unperturbed run and three
+    runs with b, b~ perturbed by 1e-13."""
+    base = wl.ilut2d_sequence(nsys=2)
+    mats = [_rowperm(A, 10 + j) for j, A in enumerate(base.mats)]
+    with pytest.raises(ZeroDivisionError):
+        pc.ilut(mats[0], 0.2)
+    seq = wl.DualSequence("rowperm", mats, base.b, base.bt, 5, 10, 1e-8)
+    runs = []
+    for j in range(4):
+        bp = seq.b if j == 0 else [_perturbed(v, 900 + 10 * j + i) for i, v in enumerate(seq.b)]
+        _, res = pc.rbicg_ilut_sequence(mats, bp, seq.bt, 5, 10, 1e-8, 0.2, permtol=1.0)
+        runs.append(res)
+    ranges = [([r[i].iters for r in runs], [r[i].k_used for r in runs]) for i in range(2)]
+    print("case ilutp sequence", ranges, flush=True)
+    _run_sequence_p(seq, 0.2, 1.0, ranges)
+
+
+def _run_sequence_p(seq, tau, permtol, ranges):
+    from paper_1010_0762_amd.solver import solve_ilut_sequence
+    ref_sols, ref = pc.rbicg_ilut_sequence(seq.mats, seq.b, seq.bt, seq.k, seq.s, seq.tol, tau,
+                                           permtol=permtol)
+    out = solve_ilut_sequence(seq.mats, [_t(b) for b in seq.b], [_t(b) for b in seq.bt],
+                              droptol=tau, permtol=permtol, k=seq.k, s=seq.s, tol=seq.tol)
+    print("iters gpu", [o[2]["iters"] for o in out], "oracle", [r.iters for r in ref], flush=True)
+    for i, (A, (x, xt, st), (xr, xtr), b, bt) in enumerate(zip(seq.mats, out, ref_sols, seq.b, seq.bt)):
+        its, ks = ranges[i]
+        slack = max(2, int(np.ceil(0.05 * max(its))))
+        assert st["status"] == 0 and st["relres"] <= seq.tol and st["relres_dual"] <= seq.tol
+        assert min(its) - slack <= st["iters"] <= max(its) + slack, (i, st["iters"], its)
+        assert min(ks) <= st["k_used"] <= max(ks), (i, st["k_used"], ks)
+        xv, xtv = x.cpu().numpy(), xt.cpu().numpy()
+        assert np.linalg.norm(xv - xr.real) <= 1e-6 * np.linalg.norm(xr)
+        assert np.linalg.norm(xtv - xtr.real) <= 1e-6 * np.linalg.norm(xtr)
+        assert np.linalg.norm(b - A @ xv) <= 1e-5 * np.linalg.norm(b)
+        assert np.linalg.norm(bt - A.T @ xtv) <= 1e-5 * np.linalg.norm(bt)

@@ -17,7 +17,7 @@ def _p(a):
     return ct.c_void_p(a.ctypes.data)
 
 
-def _host_ilut(A, tau, p):
+def _host_ilut(A, tau, p, permtol=0.0, with_perm=False):
     lib = _lib.load()
     A = sp.csr_matrix(A).astype(np.complex128)
     A.sort_indices()
@@ -27,19 +27,21 @@ def _host_ilut(A, tau, p):
     v = np.ascontiguousarray(A.data).view(np.float64).copy()
     nnz = (ct.c_int64 * 2)()
     pp = -1 if p is None else p
-    rc = lib.rbicg_host_ilut(n, _p(rp), _p(ci), _lib.dptr(v), tau, pp, nnz, None, None, None,
-                             None, None, None)
+    rc = lib.rbicg_host_ilut(n, _p(rp), _p(ci), _lib.dptr(v), tau, pp, permtol, nnz, None, None,
+                             None, None, None, None, None)
     assert rc == 0, _lib.last_error()
     Lrp = np.zeros(n + 1, np.int32); Lci = np.zeros(max(nnz[0], 1), np.int32)
     Lv = np.zeros(2 * max(nnz[0], 1))
     Urp = np.zeros(n + 1, np.int32); Uci = np.zeros(max(nnz[1], 1), np.int32)
     Uv = np.zeros(2 * max(nnz[1], 1))
-    rc = lib.rbicg_host_ilut(n, _p(rp), _p(ci), _lib.dptr(v), tau, pp, nnz, _p(Lrp), _p(Lci),
-                             _lib.dptr(Lv), _p(Urp), _p(Uci), _lib.dptr(Uv))
+    perm = np.zeros(n, np.int32)
+    rc = lib.rbicg_host_ilut(n, _p(rp), _p(ci), _lib.dptr(v), tau, pp, permtol, nnz, _p(Lrp),
+                             _p(Lci), _lib.dptr(Lv), _p(Urp), _p(Uci), _lib.dptr(Uv), _p(perm))
     assert rc == 0
     L = sp.csr_matrix((Lv.view(np.complex128)[:nnz[0]], Lci[:nnz[0]], Lrp), shape=(n, n))
     U = sp.csr_matrix((Uv.view(np.complex128)[:nnz[1]], Uci[:nnz[1]], Urp), shape=(n, n))
-    return L + sp.identity(n, dtype=np.complex128, format="csr"), U
+    L = L + sp.identity(n, dtype=np.complex128, format="csr")
+    return (L, U, perm) if with_perm else (L, U)
 
 
 def _mats():
@@ -64,6 +66,29 @@ def test_host_ilut_matches_oracle(tau, p):
             assert np.array_equal(F.indptr, G.indptr), name
             assert np.array_equal(F.indices, G.indices), name
             assert np.abs(F.data - G.data).max() <= 1e-12 * np.abs(G.data).max(), name
+
+
+@pytest.mark.parametrize("tau,p,permtol", [(0.0, None, 1.0), (0.05, None, 1.0), (0.05, 3, 0.5),
+                                            (0.01, None, 0.1)])
+def test_host_ilutp_matches_oracle(tau, p, permtol):
+    """ILUTP: the same permutation, pattern and values (1e-12) as the
+    oracle's, on the drop/limit cases and on a row-permuted operator whose
+    diagonal is mostly zero (pivoting needed)."""
+    cd = wl.convdiff(12, 2, (10.0, 5.0))
+    As = sp.csr_matrix((cd.vals, cd.colind, cd.rowptr), shape=(cd.n, cd.n))
+    rows = np.random.default_rng(3).permutation(cd.n)
+    cases = list(_mats()) + [("rowperm", sp.csr_matrix(As[rows]))]
+    for name, A in cases:
+        Lo, Uo, po = pc.ilutp(A, tau, p, permtol)
+        Lh, Uh, ph = _host_ilut(A, tau, p, permtol, with_perm=True)
+        assert np.array_equal(po, ph), name
+        for F, G in ((Lh, Lo), (Uh, Uo)):
+            F, G = F.tocsr(), G.tocsr()
+            F.sort_indices(); G.sort_indices()
+            assert np.array_equal(F.indptr, G.indptr), name
+            assert np.array_equal(F.indices, G.indices), name
+            assert np.abs(F.data - G.data).max() <= 1e-12 * np.abs(G.data).max(), name
+    assert not np.array_equal(ph, np.arange(len(ph)))   # the row-permuted case pivots
 
 
 def test_host_ilut_rejects_zero_pivot():
