@@ -91,6 +91,8 @@ def parse():
                     help="skip the device-copy bandwidth reference")
     ap.add_argument("--no-shifted", action="store_true",
                     help="skip the batched shifted-pair leg (48^3, 8 shifts, 6 sweeps)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner leg")
     ap.add_argument("--no-k20", action="store_true",
                     help="skip the extra kernel timing with an injected 20-vector recycle space")
     ap.add_argument("--pencil-setup", type=int, default=0, choices=(0, 1),
@@ -362,6 +364,20 @@ def ilut_leg(args, seq, mats, b, bt):
         out[f"convdiff3d_{args.N}^3_seq{len(mats)}_ilut0.05_k{k}_s{seq.s}"] = run(
             seq.mats, mats, [b] * len(mats), [bt] * len(mats), k, seq.s, seq.tol, 0.05)
     return out
+
+
+def tuning_leg(args, seq, mats):
+    """The launch-shape autotuner (paper_1010_0762_amd/tune.py) on the
+    benchmark's handle shape: every candidate (blocks, chunk) timed on a
+    two-cycle recycled solve of system 0 (outside the timed region; a fresh
+    cache file, so nothing is reused from earlier runs)."""
+    import tempfile
+    from paper_1010_0762_amd import tune
+    with tempfile.TemporaryDirectory() as d:
+        e = tune.autotune(mats[0], k=seq.k, s=seq.s, prec="f64", cache=os.path.join(d, "t.json"),
+                          refresh=True)
+    e.pop("cached", None)
+    return e
 
 
 def kernel_at_k20(args, seq, mats, b, bt):
@@ -782,6 +798,7 @@ def main():
                  "latency_ms_avg": round(prof["cycle_latency_ms"] / nup, 3),
                  "iteration_wait_ms_total": round(prof["cycle_wait_ms"], 2)}
     k20 = None if args.no_k20 else kernel_at_k20(args, seq, mats, b, bt)
+    tuning = None if args.no_tune else tuning_leg(args, seq, mats)
     bicg = None if args.no_k20 else bicg_leg(args, seq, mats, b, bt)
     other = (None if args.no_other_setup
              else pencil_setup_leg(args, seq, mats, b, bt, 1 - args.pencil_setup))
@@ -832,6 +849,7 @@ def main():
         "roofline": roof,
         "copy_reference": copy_ref,
         "kernel_at_k20": k20,
+        "launch_tuning": tuning,
         "bicg_same_sequence": bicg,
         "other_pencil_setup": other,
         "shifted_pairs": shifted,

@@ -114,7 +114,14 @@ typedef struct {
  *                Psi~^H Psi and Psi~^H Phi from cycle to cycle so that only
  *                Upsilon~_j^H U_{j-1} ((s+2) x k) is formed over the n rows
  *                (FP64 and complex handles; FP32-inner solves and the first
- *                cycle of a restarted run use 0). */
+ *                cycle of a restarted run use 0).
+ *   blocks       blocks of the iteration kernels (1024 threads each, up to 8
+ *                rows per thread; 0: automatic, min(ceil(n/1024), 256) but
+ *                at least ceil(n/8192)); must lie in [ceil(n/8192), 4096].
+ *                The block partial sums are reduced in a fixed order, so a
+ *                given value gives reproducible results; different values
+ *                round the reductions differently.  Chosen by the autotuner
+ *                (paper_1010_0762_amd/tune.py) or left automatic. */
 typedef struct {
   int32_t k, s, maxit, max_restarts, update;
   double svd_tol;
@@ -127,6 +134,7 @@ typedef struct {
   int32_t profile;
   int32_t stall_window;
   int32_t pencil_setup;
+  int32_t blocks;
 } rbicg_opts;
 
 /* A matrix repacked and resident in device memory (A and its explicit A^H),
@@ -145,7 +153,7 @@ typedef struct {
 /* Fill *opts with defaults: k=20, s=40, maxit=10000, max_restarts=2,
  * update=1, svd_tol=1e-2, seed=0, prec=RBICG_F64, inner_tol=1e-5,
  * max_outer=30, stream=NULL, chunk=0, profile=0, stall_window=0,
- * pencil_setup=0. */
+ * pencil_setup=0, blocks=0. */
 void rbicg_default_opts(rbicg_opts *opts);
 
 /* Repack A (and A^H, built on the host by a counting sort when AH is NULL)

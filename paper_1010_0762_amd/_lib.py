@@ -34,7 +34,8 @@ class rbicg_opts(ct.Structure):
                 ("svd_tol", ct.c_double), ("seed", ct.c_uint64), ("prec", ct.c_int),
                 ("inner_tol", ct.c_double), ("max_outer", ct.c_int32),
                 ("stream", ct.c_void_p), ("chunk", ct.c_int32), ("profile", ct.c_int32),
-                ("stall_window", ct.c_int32), ("pencil_setup", ct.c_int32)]
+                ("stall_window", ct.c_int32), ("pencil_setup", ct.c_int32),
+                ("blocks", ct.c_int32)]
 
 
 class rbicg_stats(ct.Structure):

@@ -13,6 +13,8 @@ struct ColList {
 
 // Blocks of the iteration kernels for n rows (at most 8 rows per thread).
 int iter_grid(int n);
+// fewest blocks that cover n rows (RMAX rows per thread)
+int iter_grid_min(int n);
 // whether nb iteration blocks cover n rows with one row per thread
 bool iter_one_row(int n, int nb);
 

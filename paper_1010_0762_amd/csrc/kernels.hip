@@ -2373,6 +2373,7 @@ inline unsigned nblk(size_t n) { return (unsigned)((n + RBICG_BLOCK - 1) / RBICG
 
 bool iter_one_row(int n, int nb) { return (size_t)nb * IB >= (size_t)n; }
 
+int iter_grid_min(int n) { return std::max(1, (n + IB * RMAX - 1) / (IB * RMAX)); }
 int iter_grid(int n) {
   const int a = (n + IB - 1) / IB;
   const int b = (n + IB * RMAX - 1) / (IB * RMAX);

@@ -2409,6 +2409,12 @@ int alloc_workspace(rbicg_s *h) {
                            hipHostMallocDefault));
   }
   h->nb = iter_grid(h->n);
+  if (h->opt.blocks > 0) {
+    if (h->opt.blocks < iter_grid_min(h->n))
+      return rbicg_fail(RBICG_EINVAL, "blocks=%d too few for n=%d (at least %d)", h->opt.blocks, h->n,
+                        iter_grid_min(h->n));
+    h->nb = h->opt.blocks;
+  }
   TRY(dalloc(h, (void **)&h->partial, (size_t)h->nb * 4 * KMAXD * sizeof(double)));
   TRY(dalloc(h, (void **)&h->P1, (size_t)h->nb * (6 * KMAXD + 2) * sizeof(double)));
   TRY(dalloc(h, (void **)&h->P3, (size_t)h->nb * 8 * sizeof(double)));
@@ -2510,6 +2516,7 @@ extern "C" void rbicg_default_opts(rbicg_opts *o) {
   o->profile = 0;
   o->stall_window = 0;
   o->pencil_setup = 0;
+  o->blocks = 0;
 }
 
 extern "C" int rbicg_create(const rbicg_csr *A, const rbicg_csr *AH, const rbicg_opts *opt,
@@ -3175,6 +3182,7 @@ static int check_opts(const rbicg_opts *opt) {
   if (opt->stall_window < 0) return rbicg_fail(RBICG_EINVAL, "stall_window must be >= 0");
   if (opt->pencil_setup != 0 && opt->pencil_setup != 1)
     return rbicg_fail(RBICG_EINVAL, "pencil_setup must be 0 or 1");
+  if (opt->blocks < 0 || opt->blocks > 4096) return rbicg_fail(RBICG_EINVAL, "blocks must be in [0, 4096]");
   if (opt->prec != RBICG_F64 && opt->prec != RBICG_C128 && opt->prec != RBICG_F32_IN_F64_OUT)
     return rbicg_fail(RBICG_EINVAL, "unknown precision mode %d", (int)opt->prec);
   if (opt->prec == RBICG_F32_IN_F64_OUT && (!(opt->inner_tol > 0) || opt->inner_tol >= 1 || opt->max_outer < 1))

@@ -70,8 +70,12 @@ class Server:
                  tol: float = 1e-8, inner_tol: float = 1e-5, s: int = 40,
                  keep_solutions: bool = False,
                  execute: Optional[Callable] = None, batched: bool = False,
-                 window_us: float = 50.0, batch_max_rows: int = 262144):
+                 window_us: float = 50.0, batch_max_rows: int = 262144,
+                 tune_cache: Optional[str] = None):
         self.slots = slots
+        # launch shapes from the autotuner's JSON cache (paper_1010_0762_amd/
+        # tune.py) for request shapes it holds; the automatic grid otherwise
+        self.tune_cache = tune_cache
         # requests of at most batch_max_rows unknowns go through the batch;
         # larger ones fill the GPU on their own and keep their own launches
         # (in one batch stream their long chunks would hold up the small ones)
@@ -116,9 +120,15 @@ class Server:
             # FP64 RBiCG restarts a stalled recycled solve without recycling
             # (stall guard; plain Algorithm 2 diverges on some of the larger
             # strongly convective systems)
+            shape = {}
+            if self.tune_cache is not None:
+                from . import tune
+                hit = tune.lookup(M, k=req.k, s=self.s, prec=self.prec, cache=self.tune_cache)
+                if hit:
+                    shape = {"blocks": hit["blocks"], "chunk": hit["chunk"]}
             S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
                        max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0,
-                       batch=self.batch if A.n <= self.batch_max_rows else None)
+                       batch=self.batch if A.n <= self.batch_max_rows else None, **shape)
             stats, sols = [], []
             for j in range(req.nsys):
                 b, bt = wl.request_rhs(req, j)

@@ -367,7 +367,8 @@ class Solver:
 
     def __init__(self, A, AH=None, *, k=20, s=40, maxit=10000, max_restarts=2, update=True,
                  svd_tol=1e-2, seed=0, prec="f64", inner_tol=1e-5, max_outer=30, chunk=0,
-                 stream=None, profile=False, stall_window=0, pencil_setup=0, batch=None):
+                 stream=None, profile=False, stall_window=0, pencil_setup=0, batch=None,
+                 blocks=0):
         self.lib = _lib.load()
         o = _lib.rbicg_opts()
         self.lib.rbicg_default_opts(ct.byref(o))
@@ -381,6 +382,8 @@ class Solver:
         o.stall_window = int(stall_window)
         # cycle-end pencil: 0 device Grams, 1 the recurrences of Sec. 4.4
         o.pencil_setup = int(pencil_setup)
+        # iteration-kernel blocks (0: automatic; the autotuner's choice otherwise)
+        o.blocks = int(blocks)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         o.stream = _stream_ptr(self.stream)
         self.opts = o

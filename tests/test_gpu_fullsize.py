@@ -264,3 +264,25 @@ def test_cfg2_split_preconditioned_full_size():
         assert st["status"] == 0 and st["iters"] < 200
         assert np.linalg.norm(bh - Aj @ x.cpu().numpy()) <= 1e-7 * np.linalg.norm(bh)
         assert np.linalg.norm(bth - Aj.T @ xt.cpu().numpy()) <= 1e-7 * np.linalg.norm(bth)
+
+
+@pytest.mark.parametrize("blocks", [64, 128])
+def test_cfg2_bicg_other_launch_shapes(gold, setup, blocks):
+    """The autotuner's other launch shapes (64 or 128 blocks of 1024 threads,
+    four or two rows per thread at 64^3) solve the same systems: plain BiCG
+    counts within 5% of the oracle's on three systems and sampled x, x~ of
+    system 0 to 1e-6."""
+    seq, mats, b, bt = setup
+    idx = np.asarray(gold["sample_index"])
+    S = _solver(mats[0], k=0, s=40, update=False, blocks=blocks)
+    print("case blocks", blocks, flush=True)
+    for j in range(3):
+        S.update_recycle(mats[j])
+        x, xt, st = S.solve(b, bt, tol=seq.tol)
+        ref = gold["bicg_iters"][j]
+        assert st["status"] == 0 and st["relres"] <= seq.tol and st["relres_dual"] <= seq.tol
+        assert abs(st["iters"] - ref) <= max(1, int(np.ceil(0.05 * ref))), (j, st["iters"], ref)
+        if j == 0:
+            assert _sample_rel(x, idx, gold["bicg_system0"]["x_sample"]) <= 1e-6
+            assert _sample_rel(xt, idx, gold["bicg_system0"]["xt_sample"]) <= 1e-6
+    S.close()
