@@ -642,12 +642,13 @@ def serving_leg(args):
            "trace": {"requests": len(trace), "lambda_per_s": args.serving_lam,
                      "systems": sum(r.nsys for r in trace),
                      "edges": sorted({r.edge for r in trace})}}
-    for name, slots, prec, batched in (
-            ("batched_fp32_inner", args.serving_slots, "mixed", True),
-            ("concurrent_unbatched_fp32_inner", args.serving_slots, "mixed", False),
-            ("one_at_a_time_fp64", 1, "f64", False)):
+    for name, slots, prec, batched, graphs in (
+            ("batched_fp32_inner", args.serving_slots, "mixed", True, False),
+            ("batched_graphs_fp32_inner", args.serving_slots, "mixed", True, True),
+            ("concurrent_unbatched_fp32_inner", args.serving_slots, "mixed", False, False),
+            ("one_at_a_time_fp64", 1, "f64", False, False)):
         srv = serving.Server(slots=slots, prec=prec, tol=1e-8, batched=batched,
-                             window_us=args.serving_window)
+                             window_us=args.serving_window, graphs=graphs)
         srv.prepare(trace)
         torch.cuda.synchronize()
         res = srv.run(trace)

@@ -455,9 +455,16 @@ int rbicg_batch_create(int32_t max_slots, double window_us, rbicg_batch *out);
 /* Attach h to b (NULL detaches); not while h is solving.  The batch must
  * outlive the attachment. */
 int rbicg_batch_attach(rbicg_handle h, rbicg_batch b);
-/* out[0..3]: launches, chunks launched, handle-iterations launched, most chunks
- * in one launch. */
+/* out[0..5]: launches, chunks launched, handle-iterations launched, most chunks
+ * in one launch, graph replays, graph captures (out: 6 doubles). */
 int rbicg_batch_stats(rbicg_batch b, double *out);
+/* on != 0: every launch set (the iteration kernels of one batch launch, which
+ * read their arguments from device tables) is captured once as a HIP graph
+ * per table buffer and shape and replayed afterwards, so that a steady mix of
+ * requests is served by graph launches only (at most 64 graphs kept, least
+ * recently used dropped); the tables are copied before each replay.  Results
+ * are those of direct launches.  Default off. */
+int rbicg_batch_use_graphs(rbicg_batch b, int32_t on);
 int rbicg_batch_destroy(rbicg_batch b);
 
 /* For callers that cannot allocate device memory (tight serving loops,

@@ -89,6 +89,7 @@ SIGNATURES = {
     "rbicg_batch_attach": (ct.c_int, [_P, _P]),
     "rbicg_batch_stats": (ct.c_int, [_P, _DP]),
     "rbicg_batch_destroy": (ct.c_int, [_P]),
+    "rbicg_batch_use_graphs": (ct.c_int, [_P, _I]),
     "rbicg_solve_dual_noalloc": (ct.c_int, [_P, ct.POINTER(rbicg_opts), _P, _P, _P, _P, _D,
                                             ct.POINTER(rbicg_stats)]),
     "rbicg_ilut_create": (ct.c_int, [ct.POINTER(rbicg_csr), _D, _I, _D, ct.POINTER(_P)]),

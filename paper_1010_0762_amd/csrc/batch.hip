@@ -20,11 +20,19 @@
 #include <condition_variable>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
 #include "errors.h"
+
+#define TRY_B(call)      \
+  do {                   \
+    const int r_ = call; \
+    if (r_ < 0) return r_; \
+  } while (0)
 
 #define B_HIPCHECK(call)                                                                  \
   do {                                                                                    \
@@ -47,6 +55,15 @@ struct Pending {
 
 constexpr int NBUF = 8;  // table buffers in flight
 constexpr int NSTREAM = 4;  // batch streams (launches rotate over them)
+constexpr int NGRAPH = 64;  // captured launch sets kept (least recently used dropped)
+
+// A launch set as a graph: the kernels of one batch launch, replayed whenever
+// the same table buffer holds tables of the same shape (the kernels read
+// their arguments from the tables, so only the table contents change).
+struct Captured {
+  hipGraphExec_t exec = nullptr;
+  long last = 0;
+};
 
 }  // namespace
 
@@ -69,8 +86,13 @@ struct rbicg_batch_s {
   hipEvent_t used[NBUF] = {};
   int next = 0;
   hipEvent_t fin = nullptr;
-  // statistics: launches, chunks, slot-iterations, largest batch
-  double stat[4] = {0, 0, 0, 0};
+  // statistics: launches, chunks, slot-iterations, largest batch, graph
+  // replays, graph captures
+  double stat[6] = {0, 0, 0, 0, 0, 0};
+  // launch sets captured as HIP graphs, keyed by table buffer and shape
+  bool graphs = false;
+  std::map<std::vector<long>, Captured> cap_sets;
+  long uses = 0;
 };
 
 namespace {
@@ -97,9 +119,16 @@ template <> struct KindT<BK_C128> { using V = cd; using M = cd; };
 template <> struct KindT<BK_F32> { using V = float; using M = float; };
 
 // Tables and launches of one group (one kind, one rows-per-thread mode).
+// One launch of a launch set: directly on the batch stream, or as a node of
+// a graph chained after the previous one.
+struct Op {
+  std::function<void()> launch;
+  std::function<hipError_t(hipGraph_t, hipGraphNode_t &)> node;
+};
+
 template <int K>
 int launch_group(rbicg_batch b, const std::vector<Pending *> &g, bool one_row, char *hbase,
-                 char *dbase, size_t &off, std::vector<std::function<void()>> &launches) {
+                 char *dbase, size_t &off, std::vector<Op> &launches, std::vector<long> &shape) {
   using V = typename KindT<K>::V;
   using M = typename KindT<K>::M;
   using A1 = It1Args<V, M>;
@@ -144,10 +173,16 @@ int launch_group(rbicg_batch b, const std::vector<Pending *> &g, bool one_row, c
     }
     const A1 *d1 = (const A1 *)(dbase + o1);
     const A2 *d2 = (const A2 *)(dbase + o2);
-    launches.push_back([=]() {
-      launch_it1_multi<V, M>(st, d1, ns, nblk, lds, one_row);
-      launch_it2_multi<V>(st, d2, ns, nblk);
-    });
+    shape.insert(shape.end(), {K, one_row ? 1L : 0L, (long)o1, (long)o2, ns, nblk, (long)lds});
+    launches.push_back({[=]() {
+                          launch_it1_multi<V, M>(st, d1, ns, nblk, lds, one_row);
+                          launch_it2_multi<V>(st, d2, ns, nblk);
+                        },
+                        [=](hipGraph_t gr, hipGraphNode_t &last) {
+                          hipError_t e = graph_it1_multi<V, M>(gr, last, d1, ns, nblk, lds, one_row);
+                          if (e == hipSuccess) e = graph_it2_multi<V>(gr, last, d2, ns, nblk);
+                          return e;
+                        }});
   }
   off = al16(off);
   const size_t of = off;
@@ -157,7 +192,53 @@ int launch_group(rbicg_batch b, const std::vector<Pending *> &g, bool one_row, c
   }
   const ItfinArgs *df = (const ItfinArgs *)(dbase + of);
   const int n = (int)g.size();
-  launches.push_back([=]() { launch_itfin_multi<V>(st, df, n); });
+  shape.insert(shape.end(), {-K - 1, (long)of, n});
+  launches.push_back({[=]() { launch_itfin_multi<V>(st, df, n); },
+                      [=](hipGraph_t gr, hipGraphNode_t &last) { return graph_itfin_multi<V>(gr, last, df, n); }});
+  return 0;
+}
+
+// Run the launches: directly, or as a HIP graph captured once per table
+// buffer and shape and replayed afterwards (kernels only; no memory nodes).
+int run_launches(rbicg_batch b, std::vector<Op> &launches, std::vector<long> key) {
+  if (!b->graphs) {
+    for (auto &f : launches) f.launch();
+    B_HIPCHECK(hipGetLastError());
+    return 0;
+  }
+  ++b->uses;
+  auto it = b->cap_sets.find(key);
+  if (it == b->cap_sets.end()) {
+    if ((int)b->cap_sets.size() >= NGRAPH) {  // drop the least recently used
+      auto lru = b->cap_sets.begin();
+      for (auto jt = b->cap_sets.begin(); jt != b->cap_sets.end(); ++jt)
+        if (jt->second.last < lru->second.last) lru = jt;
+      (void)hipGraphExecDestroy(lru->second.exec);
+      b->cap_sets.erase(lru);
+    }
+    // built node by node (no stream capture: other threads keep using
+    // their streams, the null stream included, while a graph is built)
+    hipGraph_t g = nullptr;
+    B_HIPCHECK(hipGraphCreate(&g, 0));
+    hipGraphNode_t last = nullptr;
+    for (auto &f : launches) {
+      const hipError_t e = f.node(g, last);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return rbicg_fail(RBICG_EHIP, "batch graph node: %s", hipGetErrorString(e));
+      }
+    }
+    Captured c;
+    const hipError_t ie = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return rbicg_fail(RBICG_EHIP, "batch graph instantiation failed: %s", hipGetErrorString(ie));
+    it = b->cap_sets.emplace(std::move(key), c).first;
+    b->stat[5] += 1;
+  } else {
+    b->stat[4] += 1;
+  }
+  it->second.last = b->uses;
+  B_HIPCHECK(hipGraphLaunch(it->second.exec, b->st));
   return 0;
 }
 
@@ -209,7 +290,8 @@ int launch(rbicg_batch b, std::vector<Pending *> &take) {
     B_HIPCHECK(hipMalloc((void **)&b->dev[bi], c));
     b->cap[bi] = c;
   }
-  std::vector<std::function<void()>> launches;
+  std::vector<Op> launches;
+  std::vector<long> shape{bi};  // the table buffer, then the launches' shape
   size_t off = 0;
   for (int gi = 0; gi < 2 * BK_KINDS; ++gi) {
     const auto &g = groups[gi];
@@ -217,19 +299,20 @@ int launch(rbicg_batch b, std::vector<Pending *> &take) {
     const bool one_row = gi % 2 == 1;
     int rc = 0;
     switch (gi / 2) {
-      case BK_F64: rc = launch_group<BK_F64>(b, g, one_row, b->host[bi], b->dev[bi], off, launches); break;
+      case BK_F64: rc = launch_group<BK_F64>(b, g, one_row, b->host[bi], b->dev[bi], off, launches, shape); break;
       case BK_C128_REAL_A:
-        rc = launch_group<BK_C128_REAL_A>(b, g, one_row, b->host[bi], b->dev[bi], off, launches);
+        rc = launch_group<BK_C128_REAL_A>(b, g, one_row, b->host[bi], b->dev[bi], off, launches, shape);
         break;
-      case BK_C128: rc = launch_group<BK_C128>(b, g, one_row, b->host[bi], b->dev[bi], off, launches); break;
-      default: rc = launch_group<BK_F32>(b, g, one_row, b->host[bi], b->dev[bi], off, launches); break;
+      case BK_C128: rc = launch_group<BK_C128>(b, g, one_row, b->host[bi], b->dev[bi], off, launches, shape); break;
+      default: rc = launch_group<BK_F32>(b, g, one_row, b->host[bi], b->dev[bi], off, launches, shape); break;
     }
     if (rc < 0) return rc;
   }
   if (off > b->cap[bi]) return rbicg_fail(RBICG_EINVAL, "batch tables overflow their buffer");
   B_HIPCHECK(hipMemcpyAsync(b->dev[bi], b->host[bi], off, hipMemcpyHostToDevice, b->st));
-  for (auto &f : launches) f();
-  B_HIPCHECK(hipGetLastError());
+  // a reallocated buffer changes the tables' addresses: its graphs are stale
+  shape.push_back((long)(uintptr_t)b->dev[bi]);
+  TRY_B(run_launches(b, launches, std::move(shape)));
   if (!b->used[bi]) B_HIPCHECK(hipEventCreateWithFlags(&b->used[bi], hipEventDisableTiming));
   B_HIPCHECK(hipEventRecord(b->used[bi], b->st));
   // every slot's stream continues after the batch
@@ -317,7 +400,19 @@ extern "C" int rbicg_batch_create(int32_t max_slots, double window_us, rbicg_bat
 extern "C" int rbicg_batch_stats(rbicg_batch b, double *out) {
   if (!b || !out) return rbicg_fail(RBICG_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(b->mu);
-  for (int i = 0; i < 4; ++i) out[i] = b->stat[i];
+  for (int i = 0; i < 6; ++i) out[i] = b->stat[i];
+  return RBICG_OK;
+}
+
+extern "C" int rbicg_batch_use_graphs(rbicg_batch b, int32_t on) {
+  if (!b) return rbicg_fail(RBICG_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(b->mu);
+  while (b->launching) {  // not while a launch is being built
+    lk.unlock();
+    std::this_thread::yield();
+    lk.lock();
+  }
+  b->graphs = on != 0;
   return RBICG_OK;
 }
 
@@ -330,6 +425,7 @@ extern "C" int rbicg_batch_destroy(rbicg_batch b) {
     if (b->used[i]) (void)hipEventDestroy(b->used[i]);
   }
   for (auto e : b->events) (void)hipEventDestroy(e);
+  for (auto &kv : b->cap_sets) (void)hipGraphExecDestroy(kv.second.exec);
   for (int i = 0; i < NSTREAM; ++i) (void)hipStreamDestroy(b->sts[i]);
   delete b;
   return RBICG_OK;

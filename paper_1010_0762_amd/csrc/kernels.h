@@ -123,6 +123,15 @@ template <class V>
 void launch_it2_multi(hipStream_t st, const It2Args<V> *dtab, int nslot, int nblocks);
 template <class V>
 void launch_itfin_multi(hipStream_t st, const ItfinArgs *dtab, int nslot);
+// the same three launches as kernel nodes of a graph, chained after `last`
+template <class V, class M>
+hipError_t graph_it1_multi(hipGraph_t g, hipGraphNode_t &last, const It1Args<V, M> *dtab, int nslot,
+                           int nblocks, size_t lds_bytes, bool rpt1);
+template <class V>
+hipError_t graph_it2_multi(hipGraph_t g, hipGraphNode_t &last, const It2Args<V> *dtab, int nslot,
+                           int nblocks);
+template <class V>
+hipError_t graph_itfin_multi(hipGraph_t g, hipGraphNode_t &last, const ItfinArgs *dtab, int nslot);
 // dynamic LDS bytes of k_it1 for recycle dimension k (and re-projection rp)
 template <class V>
 size_t it1_lds_bytes(int k, int rp);

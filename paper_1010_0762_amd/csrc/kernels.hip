@@ -2467,6 +2467,44 @@ template <class V>
 void launch_itfin_multi(hipStream_t st, const ItfinArgs *dtab, int nslot) {
   hipLaunchKernelGGL((k_itfin_multi<V>), dim3(nslot), dim3(IB), 0, st, dtab);
 }
+
+// The same launches as kernel nodes of a HIP graph, each after `last`
+// (nullptr: a root), which then becomes the new node.
+namespace {
+hipError_t add_node(hipGraph_t g, hipGraphNode_t &last, void *fn, dim3 grid, size_t lds,
+                    void **args) {
+  hipKernelNodeParams p{};
+  p.func = fn;
+  p.gridDim = grid;
+  p.blockDim = dim3(IB);
+  p.sharedMemBytes = (unsigned)lds;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  const hipError_t e = hipGraphAddKernelNode(&node, g, last ? &last : nullptr, last ? 1 : 0, &p);
+  if (e == hipSuccess) last = node;
+  return e;
+}
+}  // namespace
+template <class V, class M>
+hipError_t graph_it1_multi(hipGraph_t g, hipGraphNode_t &last, const It1Args<V, M> *dtab, int nslot,
+                           int nblocks, size_t lds_bytes, bool rpt1) {
+  void *args[] = {(void *)&dtab, (void *)&nslot};
+  void *fn = rpt1 ? reinterpret_cast<void *>(&k_it1_multi<V, M, 1>)
+                  : reinterpret_cast<void *>(&k_it1_multi<V, M, RMAX>);
+  return add_node(g, last, fn, dim3(nblocks), lds_bytes, args);
+}
+template <class V>
+hipError_t graph_it2_multi(hipGraph_t g, hipGraphNode_t &last, const It2Args<V> *dtab, int nslot,
+                           int nblocks) {
+  void *args[] = {(void *)&dtab, (void *)&nslot};
+  return add_node(g, last, reinterpret_cast<void *>(&k_it2_multi<V>), dim3(nblocks), 0, args);
+}
+template <class V>
+hipError_t graph_itfin_multi(hipGraph_t g, hipGraphNode_t &last, const ItfinArgs *dtab, int nslot) {
+  void *args[] = {(void *)&dtab};
+  return add_node(g, last, reinterpret_cast<void *>(&k_itfin_multi<V>), dim3(nslot), 0, args);
+}
 template <class V>
 void launch_it2(hipStream_t st, int nb, int n, V *x, V *xt, V *r, V *rt, const V *pn,
                 const V *ptn, const V *z, const V *zt, const V *C, const V *Ct, int k, int ld,
@@ -2686,6 +2724,8 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
   template void launch_spmm<V, M>(hipStream_t, const Sell<M> &, const V *, V *, int, int);      \
   template void launch_it1_multi<V, M>(hipStream_t, const It1Args<V, M> *, int, int, size_t, \
                                        bool);                                                 \
+  template hipError_t graph_it1_multi<V, M>(hipGraph_t, hipGraphNode_t &, const It1Args<V, M> *, \
+                                            int, int, size_t, bool);                          \
   template void launch_spmv<V, M>(hipStream_t, const Sell<M> &, const V *, V *,              \
                                   const Scalars *);                                           \
   template void launch_spmv_perm<V, M>(hipStream_t, const Sell<M> &, const V *, V *,         \
@@ -2703,6 +2743,9 @@ template void launch_sh1<cd>(hipStream_t, const Sell<cd> &, const Sell<cd> &, in
   template void launch_gather<V>(hipStream_t, int, const V *, const int *, V *);             \
   template void launch_it2_multi<V>(hipStream_t, const It2Args<V> *, int, int);              \
   template void launch_itfin_multi<V>(hipStream_t, const ItfinArgs *, int);                  \
+  template hipError_t graph_it2_multi<V>(hipGraph_t, hipGraphNode_t &, const It2Args<V> *, int, \
+                                         int);                                                 \
+  template hipError_t graph_itfin_multi<V>(hipGraph_t, hipGraphNode_t &, const ItfinArgs *, int); \
   template void launch_it2<V>(hipStream_t, int, int, V *, V *, V *, V *, const V *,          \
                               const V *, const V *, const V *, const V *, const V *, int, int, \
                               const double *, double *, Scalars *, double *, int, int,       \

@@ -71,7 +71,7 @@ class Server:
                  keep_solutions: bool = False,
                  execute: Optional[Callable] = None, batched: bool = False,
                  window_us: float = 50.0, batch_max_rows: int = 262144,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, graphs: bool = False):
         self.slots = slots
         # launch shapes from the autotuner's JSON cache (paper_1010_0762_amd/
         # tune.py) for request shapes it holds; the automatic grid otherwise
@@ -85,7 +85,7 @@ class Server:
         self.batch = None
         if batched:
             from .solver import Batch
-            self.batch = Batch(max_slots=min(16, slots), window_us=window_us)
+            self.batch = Batch(max_slots=min(16, slots), window_us=window_us, graphs=graphs)
         self.prec = prec
         self.tol = tol
         self.inner_tol = inner_tol

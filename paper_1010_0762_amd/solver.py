@@ -333,19 +333,24 @@ class Batch:
     iterations to it, and it launches the chunks of all handles that are
     iterating together."""
 
-    def __init__(self, max_slots=16, window_us=50.0):
+    def __init__(self, max_slots=16, window_us=50.0, graphs=False):
+        """graphs: replay each launch set as a captured HIP graph
+        (rbicg_batch_use_graphs)."""
         self.lib = _lib.load()
         h = ct.c_void_p()
         _lib.check(self.lib.rbicg_batch_create(int(max_slots), float(window_us), ct.byref(h)),
                    "rbicg_batch_create")
         self.h = h
+        if graphs:
+            _lib.check(self.lib.rbicg_batch_use_graphs(self.h, 1), "rbicg_batch_use_graphs")
 
     def stats(self) -> dict:
-        out = np.zeros(4)
+        out = np.zeros(6)
         _lib.check(self.lib.rbicg_batch_stats(self.h, _lib.dptr(out)), "rbicg_batch_stats")
         return {"launches": int(out[0]), "chunks": int(out[1]), "handle_iterations": int(out[2]),
                 "max_chunks_per_launch": int(out[3]),
-                "chunks_per_launch": float(out[1] / max(out[0], 1))}
+                "chunks_per_launch": float(out[1] / max(out[0], 1)),
+                "graph_replays": int(out[4]), "graph_captures": int(out[5])}
 
     def close(self):
         if getattr(self, "h", None):

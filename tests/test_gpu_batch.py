@@ -46,11 +46,16 @@ def _run(case, batch=None, stream=None):
     return res
 
 
-def test_batched_solves_bitwise_equal_alone():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batched_solves_bitwise_equal_alone(graphs):
+    """With graphs, every launch set is captured once per table buffer and
+    shape and replayed: the replays (many per solve, with the solves' own
+    eager work and synchronizations in between) give the same bits as the
+    solves alone."""
     from paper_1010_0762_amd.solver import Batch
     cases = _cases()
     alone = [_run(c) for c in cases]
-    B = Batch(max_slots=16, window_us=200.0)
+    B = Batch(max_slots=16, window_us=200.0, graphs=graphs)
     streams = [torch.cuda.Stream() for _ in cases]
     torch.cuda.synchronize()
     out = [None] * len(cases)
@@ -77,4 +82,9 @@ def test_batched_solves_bitwise_equal_alone():
             assert sa["iters"] == sb["iters"], (i, j)
             assert torch.equal(xa, xb) and torch.equal(xta, xtb), (i, j)
     assert stats["launches"] > 0 and stats["max_chunks_per_launch"] >= 2
+    if graphs:
+        assert stats["graph_replays"] > 0 and stats["graph_captures"] > 0
+        assert stats["graph_replays"] + stats["graph_captures"] == stats["launches"]
+    else:
+        assert stats["graph_replays"] == 0 and stats["graph_captures"] == 0
     B.close()
