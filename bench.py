@@ -29,7 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
 # 512 MiB device copy), valid only for the kernel source and the matrix
 # layout code (runtime.hip) they were taken on
-TRAFFIC_K_IT1 = {"sources_sha256_16": "a1a120ef0d97fb26", "bytes_per_launch": 87.39e6}
+TRAFFIC_K_IT1 = {"sources_sha256_16": "ea792151b4745592", "bytes_per_launch": 83.13e6}
+# the same for the FP32 k_it1 of the 128^3 mixed-precision leg, and the mean
+# kernel-trace duration of the 64^3 k_it1 (rocprofv3 --kernel-trace, the
+# sequence's launches), each from the committed profiles of these sources
+TRAFFIC_K_IT1_MIXED = {"sources_sha256_16": "ea792151b4745592", "bytes_per_launch": 294.20e6}
+TRACE_K_IT1 = {"sources_sha256_16": "ea792151b4745592", "avg_us": 19.19}
 TRAFFIC_SOURCES = ("kernels.hip", "runtime.hip")
 
 
@@ -43,16 +48,19 @@ def sources_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_k_it1():
-    """Counter-measured HBM bytes per k_it1 launch, or None once the sources
-    differ from the ones the counters were taken on."""
+def _if_current(rec, field):
+    """rec[field] when rec was measured on the current sources, else None."""
     try:
         digest = sources_digest()
     except OSError:
         return None
-    if digest != TRAFFIC_K_IT1["sources_sha256_16"]:
-        return None
-    return TRAFFIC_K_IT1["bytes_per_launch"]
+    return rec[field] if digest == rec["sources_sha256_16"] else None
+
+
+def traffic_k_it1():
+    """Counter-measured HBM bytes per k_it1 launch, or None once the sources
+    differ from the ones the counters were taken on."""
+    return _if_current(TRAFFIC_K_IT1, "bytes_per_launch")
 
 
 def parse():
@@ -552,7 +560,8 @@ def mixed_leg(args):
     M = DeviceMatrix(seq.mats[0])
     bs = [torch.as_tensor(v, device="cuda") for v in seq.b]
     bts = [torch.as_tensor(v, device="cuda") for v in seq.bt]
-    S = Solver(M, k=seq.k, s=seq.s, prec="mixed", inner_tol=seq.extra["inner_tol"], max_outer=30)
+    S = Solver(M, k=seq.k, s=seq.s, prec="mixed", inner_tol=seq.extra["inner_tol"], max_outer=30,
+               profile=args.profile_timed)
 
     def one_pass():
         S.set_recycle(None, None)
@@ -566,10 +575,28 @@ def mixed_leg(args):
 
     one_pass()
     torch.cuda.synchronize()
+    S.profile(reset=True)
     t0 = time.perf_counter()
     sts = one_pass()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # FP32 iteration kernels of the timed pass, event-timed on the solver's
+    # stream (every profile_timed-th chunk); beyond the 256 MB last-level
+    # cache at this size (one matrix copy in FP32 is 2 x 50 MB, the vectors
+    # and the k = 30 bases 2 x 30 x 8 MB)
+    prof = S.profile(reset=True)
+    roof = None
+    if prof["spmv_n"] > 0:
+        ach = prof["spmv_bytes_total"] / (prof["spmv_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": _if_current(TRAFFIC_K_IT1_MIXED, "bytes_per_launch"),
+                "kernel": "k_it1<float> (FP32 inner iterations)",
+                "avg_us": round(prof["spmv_ms"] / prof["spmv_n"] * 1e3, 2),
+                "alg_bytes_per_launch": round(prof["spmv_bytes_total"] / prof["spmv_n"]),
+                "launches": prof["spmv_n"],
+                "k_it2_avg_us": round(prof["update_ms"] / max(prof["update_n"], 1) * 1e3, 2),
+                "k_it2_gbs": round(prof["update_bytes_total"] / max(prof["update_ms"], 1e-12) * 1e-6, 1)}
     # the same systems in FP64 to the same true residual: RBiCG (same k, s;
     # plain Algorithm 2 diverges on some of these systems, so the stall guard
     # restarts them without recycling) and plain BiCG; each pass timed after
@@ -611,6 +638,8 @@ def mixed_leg(args):
             "fp64_inner_fallbacks": [st["restarts"] for st in sts],
             "n": M.n, "solves_per_s": round(len(sts) / dt, 3), "ms_per_pass": round(dt * 1e3, 1),
             "inner_iters": [st["iters"] for st in sts], "outer_steps": [st["outer_steps"] for st in sts],
+            "k_retained_per_system": [st["k_used"] for st in sts],
+            "roofline": roof,
             "max_true_relres": max(max(st["relres"], st["relres_dual"]) for st in sts),
             "all_converged": all(st["status"] == 0 for st in sts),
             "precision": "FP32 storage and SpMV inside FP64 refinement"}
@@ -790,6 +819,12 @@ def main():
                 "avg_us": round(avg_ms * 1e3, 2),
                 "alg_bytes_per_launch": round(bytes_per_launch),
                 "launches": prof["spmv_n"]}
+        # the committed kernel trace's mean duration of the same kernel (no
+        # event bracket: execution only), when taken on these sources
+        tr = _if_current(TRACE_K_IT1, "avg_us")
+        roof["avg_us_trace"] = tr
+        roof["frac_trace"] = (round(bytes_per_launch / (tr * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                              if tr else None)
     kernel_gbs = {name: round(prof[f"{key}_bytes_total"] / max(prof[f"{key}_ms"], 1e-12) * 1e-6, 1)
                   for name, key in (("spmv_restrict", "spmv"), ("expand_update", "update"))}
     nup = max(prof["cycle_updates"], 1)
