@@ -767,15 +767,13 @@ def main():
     S = Solver(mats[0], k=seq.k, s=seq.s, prec="f64", chunk=args.chunk,
                profile=args.profile_timed, pencil_setup=args.pencil_setup)
 
+    bl, btl = [b] * args.nsys, [bt] * args.nsys
+
     def step():
+        # the whole sequence in one library call (rbicg_solve_sequence): per
+        # system the move to its matrix, zeroed guesses, the solve
         S.set_recycle(None, None)
-        stats = []
-        for j in range(args.nsys):
-            S.update_recycle(mats[j])
-            xs[j].zero_()
-            xts[j].zero_()
-            _, _, st = S.solve(b, bt, xs[j], xts[j], tol=seq.tol)
-            stats.append(st)
+        _, _, stats = S.solve_sequence(mats, bl, btl, xs, xts, tol=seq.tol)
         return stats
 
     if args.copy_mb > 0:

@@ -293,6 +293,22 @@ int rbicg_create_on(rbicg_matrix A, const rbicg_opts *opt, rbicg_handle *out);
  * the current one): no host-side repacking or upload. */
 int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next);
 
+/* A whole sequence of dual systems (eq. initialSys) in one call: for system j
+ * the handle moves to mats[j] as rbicg_update_recycle_on does (the carried
+ * space biorthogonalized against it; for j = 0 only when mats[0] is not the
+ * handle's matrix, for j > 0 always, also when mats[j] == mats[j-1], which
+ * installs the previous system's last cycle space), x[j], x~[j] are zeroed
+ * first when zero_init, then rbicg_solve_dual(h, b[j], bt[j], x[j], xt[j],
+ * tol, &st[j]).  The same arithmetic as those calls made one by one, without
+ * a return to the caller between systems.  mats, b, bt, x, xt: host arrays
+ * of nsys pointers (resident matrices; device vectors as for
+ * rbicg_solve_dual); st: nsys entries (may be NULL).  Stops at the first
+ * system that returns an error (< 0) and returns it; else the worst status
+ * (RBICG_NOT_CONVERGED or RBICG_BREAKDOWN if any system ended so). */
+int rbicg_solve_sequence(rbicg_handle h, int32_t nsys, const rbicg_matrix *mats,
+                         const void *const *b, const void *const *bt, void *const *x,
+                         void *const *xt, int32_t zero_init, double tol, rbicg_stats *st);
+
 /* Kernel timing of the iteration kernels accumulated while opts.profile is
  * set: out[0..3] = total ms and launch count of (1) the fused direction
  * update + paired SpMV + restriction kernel and (2) the fused expansion +

@@ -59,6 +59,9 @@ SIGNATURES = {
     "rbicg_create": (ct.c_int, [ct.POINTER(rbicg_csr), ct.POINTER(rbicg_csr),
                                 ct.POINTER(rbicg_opts), ct.POINTER(_P)]),
     "rbicg_solve_dual": (ct.c_int, [_P, _P, _P, _P, _P, _D, ct.POINTER(rbicg_stats)]),
+    "rbicg_solve_sequence": (ct.c_int, [_P, _I, ct.POINTER(_P), ct.POINTER(_P), ct.POINTER(_P),
+                                        ct.POINTER(_P), ct.POINTER(_P), _I, _D,
+                                        ct.POINTER(rbicg_stats)]),
     "rbicg_update_recycle": (ct.c_int, [_P, ct.POINTER(rbicg_csr), ct.POINTER(rbicg_csr)]),
     "rbicg_bilinear": (ct.c_int, [_P, _P, _P, _D, _P, _DP, ct.POINTER(rbicg_stats)]),
     "rbicg_destroy": (ct.c_int, [_P]),

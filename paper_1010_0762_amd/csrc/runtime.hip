@@ -3287,6 +3287,31 @@ extern "C" int rbicg_solve_dual(rbicg_handle h, const void *b, const void *bt, v
   });
 }
 
+extern "C" int rbicg_solve_sequence(rbicg_handle h, int32_t nsys, const rbicg_matrix *mats,
+                                    const void *const *b, const void *const *bt, void *const *x,
+                                    void *const *xt, int32_t zero_init, double tol, rbicg_stats *st) {
+  if (!h || nsys < 0 || (nsys > 0 && (!mats || !b || !bt || !x || !xt)))
+    return rbicg_fail(RBICG_EINVAL, "null argument");
+  int worst = RBICG_OK;
+  for (int j = 0; j < nsys; ++j) {
+    if (!mats[j]) return rbicg_fail(RBICG_EINVAL, "system %d: null matrix", j);
+    if (j > 0 || mats[j] != h->mat) TRY(rbicg_update_recycle_on(h, mats[j]));
+    if (zero_init) {  // a fill kernel (no memset node), doubles at the boundary
+      if (!x[j] || !xt[j]) return rbicg_fail(RBICG_EINVAL, "system %d: null vector", j);
+      const size_t words = (size_t)h->n * (h->vkind == 1 ? 2 : 1);
+      launch_fill_zero<double>(h->st, (double *)x[j], words);
+      launch_fill_zero<double>(h->st, (double *)xt[j], words);
+      HIPCHECK(hipGetLastError());
+    }
+    rbicg_stats one{};
+    const int rc = rbicg_solve_dual(h, b[j], bt[j], x[j], xt[j], tol, &one);
+    if (st) st[j] = one;
+    if (rc < 0) return rc;
+    if (rc != RBICG_OK && worst == RBICG_OK) worst = rc;
+  }
+  return worst;
+}
+
 extern "C" int rbicg_update_recycle(rbicg_handle h, const rbicg_csr *A_next, const rbicg_csr *AH_next) {
   if (!h) return rbicg_fail(RBICG_EINVAL, "null handle");
   if (A_next) TRY(set_matrix(h, A_next, AH_next));

@@ -464,6 +464,30 @@ class Solver:
         _lib.check(rc, "rbicg_ilu_attach")
         self.ilu = P
 
+    def solve_sequence(self, mats, bs, bts, xs=None, xts=None, tol=1e-8, zero_init=True,
+                       allow_not_converged=True):
+        """rbicg_solve_sequence: the systems (mats[j] DeviceMatrix, bs[j], bts[j])
+        in one library call, the recycle space carried and updated between
+        them.  xs, xts: solution tensors (allocated when None; zeroed in the
+        library when zero_init).  Returns (xs, xts, [stats per system])."""
+        m = len(mats)
+        xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+        xts = [torch.empty_like(b) for b in bts] if xts is None else xts
+        for A in mats:
+            if not isinstance(A, DeviceMatrix):
+                raise TypeError("solve_sequence takes DeviceMatrix objects")
+        P = ct.c_void_p * m
+        arr = lambda vs, name: P(*[self._vec(v, name) for v in vs])
+        st = (_lib.rbicg_stats * m)()
+        self._order()
+        rc = self.lib.rbicg_solve_sequence(self.h, m, P(*[A.h for A in mats]), arr(bs, "b"),
+                                           arr(bts, "bt"), arr(xs, "x"), arr(xts, "xt"),
+                                           1 if zero_init else 0, float(tol), st)
+        ok = (_lib.RBICG_OK, _lib.RBICG_NOT_CONVERGED) if allow_not_converged else (_lib.RBICG_OK,)
+        _lib.check(rc, "rbicg_solve_sequence", ok)
+        self.matrix = mats[-1] if m else self.matrix
+        return xs, xts, [s.as_dict() for s in st]
+
     def update_recycle(self, A_next=None, AH_next=None):
         if isinstance(A_next, DeviceMatrix):
             self.matrix = A_next

@@ -311,3 +311,35 @@ def test_stall_guard_matches_oracle_driver():
     except _lib.RBiCGError as e:   # a drifting iteration may also break down
         assert e.code == _lib.RBICG_BREAKDOWN
     P.close()
+
+
+def test_solve_sequence_equals_one_by_one():
+    """rbicg_solve_sequence (the whole sequence in one library call) gives
+    bitwise the iterates and counts of the same calls made one by one
+    (rbicg_update_recycle_on, zeroed guesses, rbicg_solve_dual), over two
+    passes of a recycled 2D sequence with an unchanged matrix in between."""
+    from paper_1010_0762_amd.solver import DeviceMatrix, Solver
+    seq = wl.cfg1_sequence(nsys=4)
+    mats = [DeviceMatrix(A) for A in seq.mats]
+    mats.insert(2, mats[1])            # the same matrix twice in a row
+    bs = [torch.as_tensor(seq.b[0], device="cuda")] * len(mats)
+    bts = [torch.as_tensor(seq.bt[0], device="cuda")] * len(mats)
+    S1 = Solver(mats[0], k=seq.k, s=seq.s)
+    S2 = Solver(mats[0], k=seq.k, s=seq.s)
+    for rep in range(2):
+        S1.set_recycle(None, None)
+        one = []
+        for j, M in enumerate(mats):
+            if j > 0 or M is not S1.matrix:
+                S1.update_recycle(M)
+            x, xt, st = S1.solve(bs[j], bts[j], tol=seq.tol)
+            one.append((x, xt, st))
+        S2.set_recycle(None, None)
+        xs, xts, sts = S2.solve_sequence(mats, bs, bts, tol=seq.tol)
+        print("rep", rep, [o[2]["iters"] for o in one], [s["iters"] for s in sts], flush=True)
+        for (x, xt, st), xs_, xts_, st2 in zip(one, xs, xts, sts):
+            assert st["iters"] == st2["iters"] and st["k_used"] == st2["k_used"]
+            assert st2["status"] == 0
+            assert torch.equal(x, xs_) and torch.equal(xt, xts_)
+    S1.close()
+    S2.close()
