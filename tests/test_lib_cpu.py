@@ -205,3 +205,53 @@ def test_matrix_info_rejects_null_arguments():
     assert lib.rbicg_matrix_info(None, info) == _lib.RBICG_EINVAL
     assert b"null" in lib.rbicg_last_error()
     assert lib.rbicg_matrix_info(None, None) == _lib.RBICG_EINVAL
+
+
+def test_entry_points_reject_bad_arguments_before_any_device_call():
+    """The sequence, split-preconditioning and batch entry points check their
+    arguments on the host: null handles, out-of-range settings and a matrix
+    whose ILUT meets a zero pivot are RBICG_EINVAL with a message, and
+    destroying a null object is a no-op."""
+    lib = _lib.load()
+    E = _lib.RBICG_EINVAL
+    P = ct.c_void_p
+    # a whole sequence needs a handle and (for nsys > 0) its arrays
+    assert lib.rbicg_solve_sequence(None, 1, None, None, None, None, None, 1, 1e-8, None) == E
+    assert b"null" in lib.rbicg_last_error()
+    # split preconditioning: null objects
+    info = (ct.c_int64 * 8)()
+    assert lib.rbicg_ilu_info(None, info) == E
+    assert lib.rbicg_ilu_set_waves(None, 512) == E
+    assert lib.rbicg_ilu_attach(None, None) == E
+    assert lib.rbicg_ilu_rhs(None, None, None, None, None, 0, None) == E
+    assert lib.rbicg_ilu_solution(None, None, None, None, None, 0, None) == E
+    assert lib.rbicg_ilu_destroy(None) == _lib.RBICG_OK
+    # ILUT: bad thresholds, an invalid descriptor, a zero pivot without pivoting
+    rowptr = np.array([0, 1, 2], dtype=np.int32)
+    colind = np.array([1, 0], dtype=np.int32)
+    vals = np.array([1.0, 1.0])
+    A = _lib.rbicg_csr()
+    A.n, A.nnz = 2, 2
+    A.rowptr, A.colind, A.values = rowptr.ctypes.data, colind.ctypes.data, vals.ctypes.data
+    A.values_complex, A.on_device = 0, 0
+    out = P()
+    assert lib.rbicg_ilut_create(ct.byref(A), -1.0, -1, 0.0, ct.byref(out)) == E
+    assert b"droptol" in lib.rbicg_last_error()
+    assert lib.rbicg_ilut_create(ct.byref(A), 0.0, -1, -0.5, ct.byref(out)) == E
+    assert b"permtol" in lib.rbicg_last_error()
+    assert lib.rbicg_ilut_create(ct.byref(A), 0.0, -1, 0.0, None) == E
+    bad = _lib.rbicg_csr()
+    bad.n, bad.nnz = 0, 0
+    assert lib.rbicg_ilut_create(ct.byref(bad), 0.0, -1, 0.0, ct.byref(out)) == E
+    assert b"CSR" in lib.rbicg_last_error()
+    assert lib.rbicg_ilut_create(ct.byref(A), 0.0, -1, 0.0, ct.byref(out)) == E
+    assert b"zero pivot in row 0" in lib.rbicg_last_error()
+    assert not out.value
+    # batches: slot count and window are range-checked before any stream exists
+    assert lib.rbicg_batch_create(0, 50.0, ct.byref(out)) == E
+    assert lib.rbicg_batch_create(17, 50.0, ct.byref(out)) == E
+    assert lib.rbicg_batch_create(4, -1.0, ct.byref(out)) == E
+    assert lib.rbicg_batch_create(4, 50.0, None) == E
+    assert lib.rbicg_batch_use_graphs(None, 1) == E
+    assert lib.rbicg_batch_stats(None, None) == E
+    assert lib.rbicg_batch_destroy(None) == _lib.RBICG_OK
