@@ -1507,6 +1507,7 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 
 #define GRAM_MAXT 9        // output tiles per wave (at most 36 tiles of 16 x 16)
+#define TS_PC(JT) (16 * (JT) + 2)  // LDS row stride (doubles) of W in k_tsgemm_mfma
 #define GRAM_BLOCK 256
 
 // Gram partials over a chunk of rows: G[i][j] = sum conj(X_i) Y_j for every
@@ -1717,13 +1718,18 @@ template <class V, int JT>
 __global__ __launch_bounds__(256) void k_tsgemm_mfma(int n, ColList X, int m, const cd *W, int p,
                                                      V *Y, int ld) {
   constexpr int ndv = sizeof(V) == 16 ? 2 : 1;
+  constexpr int PC = TS_PC(JT);  // LDS row stride of W (padded against bank conflicts)
   __shared__ const V *cols[RBICG_MAXCOLS];
+  // W rows of one batch (up to 64 input columns), Re then Im planes:
+  // wl[(part * 64 + kk) * PC + c] = W(c, k0 + kk), zero outside m x p
+  extern __shared__ double wl[];
   for (int t = threadIdx.x; t < m; t += 256) cols[t] = (const V *)X.p[t];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = (blockIdx.x * 4 + w) * 16;
-  if (row0 >= n) return;
+  // a wave past n loads nothing but still takes part in the block's barriers
+  const bool live = row0 < n;
   // rows past n (within the columns' padded length) feed only output rows
   // that are not stored
   const int row = row0 + li;
@@ -1732,49 +1738,67 @@ __global__ __launch_bounds__(256) void k_tsgemm_mfma(int n, ColList X, int m, co
   for (int t = 0; t < JT; ++t)
 #pragma unroll
     for (int c = 0; c < ndv; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
-  // 16 columns per step: the four X loads and 4 JT W loads of a lane are
-  // issued together (column pointers from LDS, clamped indices, factors
-  // zeroed after the load), so that a wave has them all in flight at once
+  // batches of up to four 16-column steps: the batch's X loads are issued
+  // together (column pointers from LDS, clamped indices), W's rows of the
+  // batch are staged in LDS meanwhile, then the MFMAs run in the order of
+  // one step after another
 #pragma unroll 1
-  for (int k0 = 0; k0 < m; k0 += 16) {
-    double xr[4], xi[4], wr[4][JT], wi[4][JT];
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int ks = min(4, (m - k0 + 15) / 16);
+    double xr[4][4], xi[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kcol = k0 + 4 * u + lk;
-      const int kc = min(kcol, m - 1);
-      const V v = gload(cols[kc], row);
-      if constexpr (ndv == 2) {
-        xr[u] = ((const cd &)v).x;
-        xi[u] = ((const cd &)v).y;
-      } else {
-        xr[u] = (double)v;
-        xi[u] = 0.0;
-      }
+    for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int t = 0; t < JT; ++t) {
-        const int c = t * 16 + li;
-        const cd wv = W[(size_t)min(c, p - 1) * m + kc];
-        const bool in = kcol < m && c < p;
-        wr[u][t] = in ? wv.x : 0.0;
-        wi[u][t] = in ? wv.y : 0.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int t = 0; t < JT; ++t) {
-        if constexpr (ndv == 1) {
-          acc[t][0] = mfma(wr[u][t], xr[u], acc[t][0]);  // real bases take Re W
-        } else {
-          // (W^T X^T): re = wr xr - wi xi, im = wr xi + wi xr
-          acc[t][0] = mfma(wr[u][t], xr[u], acc[t][0]);
-          acc[t][0] = mfma(-wi[u][t], xi[u], acc[t][0]);
-          acc[t][1] = mfma(wr[u][t], xi[u], acc[t][1]);
-          acc[t][1] = mfma(wi[u][t], xr[u], acc[t][1]);
+      for (int u = 0; u < 4; ++u) {
+        xr[sp][u] = 0.0;
+        xi[sp][u] = 0.0;
+        if (live && sp < ks) {
+          const int kc = min(k0 + 16 * sp + 4 * u + lk, m - 1);
+          const V v = gload(cols[kc], row);
+          if constexpr (ndv == 2) {
+            xr[sp][u] = ((const cd &)v).x;
+            xi[sp][u] = ((const cd &)v).y;
+          } else {
+            xr[sp][u] = (double)v;
+          }
         }
       }
+    if (k0 > 0) __syncthreads();  // the previous batch's reads of wl are done
+    for (int e = threadIdx.x; e < 64 * 16 * JT; e += 256) {
+      const int kk = e / (16 * JT), c = e % (16 * JT);
+      const int kcol = k0 + kk;
+      const bool in = kcol < m && c < p;
+      const cd wv = in ? W[(size_t)c * m + kcol] : cd{0.0, 0.0};
+      wl[kk * PC + c] = wv.x;
+      if constexpr (ndv == 2) wl[(64 + kk) * PC + c] = wv.y;
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        if (sp < ks) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < JT; ++t) {
+              const int e = (16 * sp + 4 * u + lk) * PC + t * 16 + li;
+              const double wr = wl[e];
+              if constexpr (ndv == 1) {
+                acc[t][0] = mfma(wr, xr[sp][u], acc[t][0]);  // real bases take Re W
+              } else {
+                // (W^T X^T): re = wr xr - wi xi, im = wr xi + wi xr
+                const double wi = wl[64 * PC + e];
+                acc[t][0] = mfma(wr, xr[sp][u], acc[t][0]);
+                acc[t][0] = mfma(-wi, xi[sp][u], acc[t][0]);
+                acc[t][1] = mfma(wr, xi[sp][u], acc[t][1]);
+                acc[t][1] = mfma(wi, xr[sp][u], acc[t][1]);
+              }
+            }
+        }
+      }
+    }
   }
-  if (row >= n) return;
+  if (!live || row >= n) return;
 #pragma unroll
   for (int t = 0; t < JT; ++t) {
 #pragma unroll
@@ -2603,12 +2627,18 @@ void launch_gram2(hipStream_t st, int n, const ColList &X, int mx, const ColList
   bool same = !two && mx == my;
   for (int c = 0; same && c < mx; ++c) same = X.p[c] == Y.p[c];
   const int ncol = same ? mxp : mxp + myp;
-  // Slabs of 32 rows while the columns fit 18 prefetch slots per thread and
-  // the two LDS buffers leave room for a second block on the CU, else 16.
-  const int sr_big = 32;
-  const bool big = (size_t)ncol * sr_big <= 18 * GRAM_BLOCK &&
-                   2 * (size_t)ncol * (sr_big + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES / 2;
-  const int sr = big ? sr_big : sr_big / 2;
+  // Slabs of 64 rows, else 32, else 16: the widest whose columns fit 18
+  // prefetch slots per thread and whose two LDS buffers leave room for a
+  // second block on the CU (a block waits out one slab load at a time, so
+  // wider slabs mean fewer round trips; the rows still enter every
+  // accumulator in the same order, so the sums do not change).
+  auto fits = [&](int r) {
+    return (size_t)ncol * r <= 18 * GRAM_BLOCK &&
+           2 * (size_t)ncol * (r + 2) * ndv * sizeof(double) <= GRAM_LDS_BYTES / 2;
+  };
+  const bool wide = fits(64);
+  const bool big = fits(32);
+  const int sr = wide ? 64 : big ? 32 : 16;
   const size_t lds = 2 * (size_t)ncol * (sr + 2) * ndv * sizeof(double);
   const dim3 grid(nchunks, two ? 2 : 1);
   // at most one 16 x 16 output tile per wave (skinny products): a variant
@@ -2619,6 +2649,9 @@ void launch_gram2(hipStream_t st, int n, const ColList &X, int mx, const ColList
     const size_t lds1 = 2 * (size_t)ncol * (16 + 2) * ndv * sizeof(double);
     hipLaunchKernelGGL((k_gram_mfma<V, 16, 8, 1>), grid, dim3(GRAM_BLOCK), lds1, st, n, X, mx, Y,
                        my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
+  } else if (wide) {
+    hipLaunchKernelGGL((k_gram_mfma<V, 64, 18, GRAM_MAXT>), grid, dim3(GRAM_BLOCK), lds, st, n, X,
+                       mx, Y, my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
   } else if (big) {
     hipLaunchKernelGGL((k_gram_mfma<V, 32, 18, GRAM_MAXT>), grid, dim3(GRAM_BLOCK), lds, st, n, X,
                        mx, Y, my, rpc, partial, same ? 1 : 0, x1, mx1, y1, my1);
@@ -2647,14 +2680,17 @@ void launch_tsgemm(hipStream_t st, int n, const ColList &X, int m, const cd *W, 
   if (p <= 0) return;
   const unsigned nb = (unsigned)((n + 63) / 64);
   const int jt = (p + 15) / 16;  // p <= KMAXD = 64
+  // W's rows of one batch of 64 input columns in LDS (Re, and Im for complex
+  // bases): at most 2 x 64 x 66 doubles
+  const size_t lds = (sizeof(V) == 16 ? 2 : 1) * 64 * (size_t)TS_PC(jt) * sizeof(double);
   if (jt == 1)
-    hipLaunchKernelGGL((k_tsgemm_mfma<V, 1>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 1>), dim3(nb), dim3(256), lds, st, n, X, m, W, p, Y, ld);
   else if (jt == 2)
-    hipLaunchKernelGGL((k_tsgemm_mfma<V, 2>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 2>), dim3(nb), dim3(256), lds, st, n, X, m, W, p, Y, ld);
   else if (jt == 3)
-    hipLaunchKernelGGL((k_tsgemm_mfma<V, 3>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 3>), dim3(nb), dim3(256), lds, st, n, X, m, W, p, Y, ld);
   else
-    hipLaunchKernelGGL((k_tsgemm_mfma<V, 4>), dim3(nb), dim3(256), 0, st, n, X, m, W, p, Y, ld);
+    hipLaunchKernelGGL((k_tsgemm_mfma<V, 4>), dim3(nb), dim3(256), lds, st, n, X, m, W, p, Y, ld);
 }
 
 void launch_pencil(hipStream_t st, size_t m, const void *a, int acplx, const void *e, int ecplx,
