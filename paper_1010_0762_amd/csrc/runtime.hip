@@ -1703,14 +1703,7 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       if (update) TRY(advance(false));
       if (flight.empty()) break;
       TRY(read_one());
-      if (done) {
-        // drain the chunk still in flight (its launches returned at once)
-        while (!flight.empty()) {
-          HIPCHECK(hipEventSynchronize(h->sev[flight.front().slot]));
-          flight.pop_front();
-        }
-        break;
-      }
+      if (done) break;  // a chunk may still be in flight: drained below
     }
     if (!done) {
       // maxit reached without the stopping test firing
@@ -1718,19 +1711,14 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
       dev_status = ST_MAXIT;
       known = completed;
     }
-    // cycles that ended after the last completed iteration never happened
-    while (!jobs.empty() && jobs.back()->e > completed) {
-      CycleJob &J = *jobs.back();
-      if (J.stage == 2 || J.stage == 4) J.fut.wait();
-      if (J.stage >= 1) (void)hipEventSynchronize(J.ev);
-      jobs.pop_back();
-    }
     total = completed;
     status = dev_status;
     const bool stalled = status == ST_DIVERGED && guard;
-    // Algorithm 2 step 7 and the true residuals need nothing from the cycle
-    // updates still in flight: they are enqueued before the drain below, and
-    // their reductions are read after it
+    // Algorithm 2 step 7 and the true residuals need nothing from the chunk
+    // still in flight (its launches do nothing once the stopping test has
+    // fired) or from the cycle updates: they are enqueued first, behind that
+    // chunk on the iteration stream, and their reductions are read after the
+    // drains below
     if (!stalled) {
       // x -= U zeta_c, x~ -= U~ zeta~_c
       if (ks > 0)
@@ -1742,6 +1730,18 @@ int solve_impl(rbicg_s *h, const V *b, const V *bt, V *x, V *xt, double tol, rbi
                        h->partial, h->S->red);
         HIPCHECK(hipGetLastError());
       }
+    }
+    // the chunk still in flight (its launches returned at once)
+    while (!flight.empty()) {
+      HIPCHECK(hipEventSynchronize(h->sev[flight.front().slot]));
+      flight.pop_front();
+    }
+    // cycles that ended after the last completed iteration never happened
+    while (!jobs.empty() && jobs.back()->e > completed) {
+      CycleJob &J = *jobs.back();
+      if (J.stage == 2 || J.stage == 4) J.fut.wait();
+      if (J.stage >= 1) (void)hipEventSynchronize(J.ev);
+      jobs.pop_back();
     }
     // finish the remaining updates of this run; later work on the iteration
     // stream (next run, next system's recycle space) is ordered after them
