@@ -343,3 +343,55 @@ def test_solve_sequence_equals_one_by_one():
             assert torch.equal(x, xs_) and torch.equal(xt, xts_)
     S1.close()
     S2.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_wide_recycle_spaces_match_oracle(cplx):
+    """k = 40: the cycle-end tall-skinny products write three 16-column output
+    tiles, and from a system's second cycle on Phi = [U, V] has up to 80
+    columns (W staged in LDS in two batches of rows).  Real: the 2D
+    convection-diffusion sequence (126, 65, 65 iterations in the oracle, with
+    30-37 vectors kept); complex: a random sparse pair and its matrix scaled
+    by 1 + 0.01i (two cycles per system).  Iterations within 5%, solutions to
+    1e-6, and the space carried out of the last system against the oracle's
+    (dimension within one, C~^H C = I, principal angles within ten times the
+    oracle's own spread: at k = 40 the largest angle between the oracle's
+    spaces for b and for b perturbed by 1e-13 relative reaches 1e-2 on the
+    real sequence, with the same iteration counts, so the spread is the
+    largest over four perturbed runs)."""
+    from scipy.linalg import subspace_angles
+    if cplx:
+        A = wl.random_sparse(1500, 6, 41, 4.5, complex_vals=True)
+        rng = np.random.default_rng(42)
+        b = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+        bt = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+        mats = [A, wl.CSR(A.n, A.rowptr, A.colind, A.vals * (1 + 0.01j))]
+        bs, bts, tol = [b, b], [bt, bt], 1e-9
+    else:
+        seq = wl.cfg1_sequence(3)
+        mats, bs, bts, tol = seq.mats, seq.b, seq.bt, seq.tol
+    k, s = 40, 40
+    ref, (Ur, Utr) = oracle.rbicg_sequence(mats, bs, bts, k, s, tol)
+    rng = np.random.default_rng(9)
+    spread = 0.0
+    for _ in range(4):
+        bp = [v * (1 + 1e-13 * rng.standard_normal(v.shape)) for v in bs]
+        _, (Ur2, Utr2) = oracle.rbicg_sequence(mats, bp, bts, k, s, tol)
+        spread = max(spread, subspace_angles(Ur, Ur2).max(), subspace_angles(Utr, Utr2).max())
+    S = _solver(mats[0], k=k, s=s, prec="c128" if cplx else "f64")
+    for j, M in enumerate(mats):
+        if j:
+            S.update_recycle(M)
+        x, xt, st = S.solve(_t(bs[j]), _t(bts[j]), tol=tol)
+        assert st["status"] == 0, (j, st)
+        assert st["relres"] <= tol and st["relres_dual"] <= tol, (j, st)
+        assert _iters_close(st["iters"], ref[j].iters), (j, st["iters"], ref[j].iters)
+        assert st["cycles"] == ref[j].cycles, (j, st["cycles"], ref[j].cycles)
+        assert _rel(_np(x), ref[j].x) <= 1e-6 and _rel(_np(xt), ref[j].xt) <= 1e-6
+    Ug, Utg, Cg, Ctg = (_np(v) for v in S.get_recycle(next=True, kcap=k))
+    assert Ug.shape[1] > 32 and abs(Ug.shape[1] - Ur.shape[1]) <= 1, (Ug.shape, Ur.shape)
+    ang = max(subspace_angles(Ug, Ur).max(), subspace_angles(Utg, Utr).max())
+    print(f"k=40 {'complex' if cplx else 'real'}: p gpu={Ug.shape[1]} oracle={Ur.shape[1]} "
+          f"angle {ang:.2e} oracle spread {spread:.2e}", flush=True)
+    assert np.linalg.norm(Ctg.conj().T @ Cg - np.eye(Ug.shape[1])) <= 1e-12
+    assert ang <= max(1e-6, 10.0 * spread), (ang, spread)
