@@ -115,38 +115,45 @@ class Server:
         stream = torch.cuda.Stream()
         cache = getattr(self, "_csr", None)
         A = cache.pop(req.rid) if cache and req.rid in cache else wl.convdiff(req.edge, 3, req.beta)
-        with torch.cuda.stream(stream):
-            M = DeviceMatrix(A)
-            # FP64 RBiCG restarts a stalled recycled solve without recycling
-            # (stall guard; plain Algorithm 2 diverges on some of the larger
-            # strongly convective systems)
-            shape = {}
-            if self.tune_cache is not None:
-                from . import tune
-                hit = tune.lookup(M, k=req.k, s=self.s, prec=self.prec, cache=self.tune_cache)
-                if hit:
-                    shape = {"blocks": hit["blocks"], "chunk": hit["chunk"]}
-            S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
-                       max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0,
-                       batch=self.batch if A.n <= self.batch_max_rows else None, **shape)
-            stats, sols = [], []
-            for j in range(req.nsys):
-                b, bt = wl.request_rhs(req, j)
-                bd = torch.as_tensor(b, device="cuda")
-                btd = torch.as_tensor(bt, device="cuda")
-                if j:
-                    S.update_recycle()
-                try:
-                    x, xt, st = S.solve(bd, btd, tol=self.tol)
-                except RBiCGError as e:  # a failed system is reported, not fatal
-                    x, xt, st = None, None, {"status": e.code, "iters": 0, "relres": float("nan"),
-                                             "relres_dual": float("nan")}
-                stats.append(st)
-                if self.keep:
-                    sols.append(None if x is None else (x.cpu().numpy(), xt.cpu().numpy()))
-            stream.synchronize()
-            S.close()
-            M.close()
+        M = S = None
+        try:
+            with torch.cuda.stream(stream):
+                M = DeviceMatrix(A)
+                # FP64 RBiCG restarts a stalled recycled solve without recycling
+                # (stall guard; plain Algorithm 2 diverges on some of the larger
+                # strongly convective systems)
+                shape = {}
+                if self.tune_cache is not None:
+                    from . import tune
+                    hit = tune.lookup(M, k=req.k, s=self.s, prec=self.prec, cache=self.tune_cache)
+                    if hit:
+                        shape = {"blocks": hit["blocks"], "chunk": hit["chunk"]}
+                S = Solver(M, k=req.k, s=self.s, prec=self.prec, inner_tol=self.inner_tol,
+                           max_outer=30, stream=stream, stall_window=4 if self.prec == "f64" else 0,
+                           batch=self.batch if A.n <= self.batch_max_rows else None, **shape)
+                stats, sols = [], []
+                for j in range(req.nsys):
+                    b, bt = wl.request_rhs(req, j)
+                    bd = torch.as_tensor(b, device="cuda")
+                    btd = torch.as_tensor(bt, device="cuda")
+                    if j:
+                        S.update_recycle()
+                    try:
+                        x, xt, st = S.solve(bd, btd, tol=self.tol)
+                    except RBiCGError as e:  # a failed system is reported, not fatal
+                        x, xt, st = None, None, {"status": e.code, "iters": 0,
+                                                 "relres": float("nan"),
+                                                 "relres_dual": float("nan")}
+                    stats.append(st)
+                    if self.keep:
+                        sols.append(None if x is None else (x.cpu().numpy(), xt.cpu().numpy()))
+                stream.synchronize()
+        finally:
+            # the handle before the matrix it was created on
+            if S is not None:
+                S.close()
+            if M is not None:
+                M.close()
         return stats, (sols if self.keep else None)
 
     # ------------------------------------------------------------ scheduling
