@@ -324,7 +324,11 @@ template <class V, class M>
 __device__ __forceinline__ void row8_index(const Sell<M> &A, int row, Row8<V, M> &L) {
   const int slice = row >> 6, lane = row & 63;
   const int b0 = A.sliceptr[slice];
-  L.w = (A.sliceptr[slice + 1] - b0) >> 6;
+  // the 64 lanes of a wave own the 64 rows of one slice (rows are 64-aligned
+  // chunks of 1024 plus multiples of the grid's row stride): the width is the
+  // same on every active lane, and as a scalar the per-entry tests below
+  // become scalar branches instead of per-lane masks
+  L.w = __builtin_amdgcn_readfirstlane((A.sliceptr[slice + 1] - b0) >> 6);
 #pragma unroll
   for (int j = 0; j < 8; ++j)
     if (j < L.w) {
