@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE counter runs (each scaled by what the counter reads for a
 # 512 MiB device copy), valid only for the kernel source and the matrix
 # layout code (runtime.hip) they were taken on
-TRAFFIC_K_IT1 = {"sources_sha256_16": "72f630c926244942", "bytes_per_launch": 83.37e6}
+TRAFFIC_K_IT1 = {"sources_sha256_16": "3ab73373b82b6602", "bytes_per_launch": 81.50e6}
 # the same for the FP32 k_it1 of the 128^3 mixed-precision leg, and the mean
 # kernel-trace duration of the 64^3 k_it1 (rocprofv3 --kernel-trace, the
 # sequence's launches), each from the committed profiles of these sources
-TRAFFIC_K_IT1_MIXED = {"sources_sha256_16": "72f630c926244942", "bytes_per_launch": 294.6e6}
-TRACE_K_IT1 = {"sources_sha256_16": "72f630c926244942", "avg_us": 18.93}
+TRAFFIC_K_IT1_MIXED = {"sources_sha256_16": "3ab73373b82b6602", "bytes_per_launch": 295.9e6}
+TRACE_K_IT1 = {"sources_sha256_16": "3ab73373b82b6602", "avg_us": 19.17}
 TRAFFIC_SOURCES = ("kernels.hip", "runtime.hip")
 
 
