@@ -255,3 +255,44 @@ def test_entry_points_reject_bad_arguments_before_any_device_call():
     assert lib.rbicg_batch_use_graphs(None, 1) == E
     assert lib.rbicg_batch_stats(None, None) == E
     assert lib.rbicg_batch_destroy(None) == _lib.RBICG_OK
+
+
+def test_empty_and_mismatched_inputs_are_rejected_on_the_host():
+    """Degenerate inputs end in RBICG_EINVAL before any device call: an empty
+    (n = 0) matrix, an A^H of another size, and options out of range (k above
+    the maximum, a cycle shorter than two iterations)."""
+    lib = _lib.load()
+    E = _lib.RBICG_EINVAL
+    out = ct.c_void_p()
+    empty = _lib.rbicg_csr()
+    empty.n, empty.nnz = 0, 0
+    assert lib.rbicg_matrix_create(ct.byref(empty), None, ct.byref(out)) == E
+    assert b"CSR" in lib.rbicg_last_error()
+    opts = _lib.rbicg_opts()
+    lib.rbicg_default_opts(ct.byref(opts))
+    assert lib.rbicg_create(ct.byref(empty), None, ct.byref(opts), ct.byref(out)) == E
+    assert b"positive" in lib.rbicg_last_error()
+
+    def csr(n):
+        rowptr = np.arange(n + 1, dtype=np.int32)
+        colind = np.arange(n, dtype=np.int32)
+        vals = np.ones(n)
+        s = _lib.rbicg_csr()
+        s.n, s.nnz = n, n
+        s.rowptr, s.colind, s.values = rowptr.ctypes.data, colind.ctypes.data, vals.ctypes.data
+        s.values_complex, s.on_device = 0, 0
+        return s, (rowptr, colind, vals)
+
+    A2, keep2 = csr(2)
+    A3, keep3 = csr(3)
+    assert lib.rbicg_matrix_create(ct.byref(A2), ct.byref(A3), ct.byref(out)) == E
+    assert b"size mismatch" in lib.rbicg_last_error()
+    bad = _lib.rbicg_opts()
+    lib.rbicg_default_opts(ct.byref(bad))
+    bad.k = 65
+    assert lib.rbicg_create(ct.byref(A2), None, ct.byref(bad), ct.byref(out)) == E
+    assert b"k must be" in lib.rbicg_last_error()
+    lib.rbicg_default_opts(ct.byref(bad))
+    bad.s = 1
+    assert lib.rbicg_create(ct.byref(A2), None, ct.byref(bad), ct.byref(out)) == E
+    assert not out.value
