@@ -395,3 +395,45 @@ def test_wide_recycle_spaces_match_oracle(cplx):
           f"angle {ang:.2e} oracle spread {spread:.2e}", flush=True)
     assert np.linalg.norm(Ctg.conj().T @ Cg - np.eye(Ug.shape[1])) <= 1e-12
     assert ang <= max(1e-6, 10.0 * spread), (ang, spread)
+
+
+@pytest.mark.parametrize("k,s", [(64, 40), (20, 107)])
+def test_largest_recycle_space_and_cycle_match_oracle(k, s):
+    """The documented limits: k = 64 (the largest recycle dimension; the
+    cycle-end products write four 16-column tiles from up to 80 input
+    columns, the pencil Gram has 105 x 209 entries) and s + k + 1 = 128 (the
+    longest cycle: a 107-vector first cycle, a 128-column Gram, a 127 x 127
+    pencil on the host).  The 2D convection-diffusion sequence against the
+    oracle: iterations within 5%, cycles, solutions to 1e-6, the carried
+    space's dimension (within two), C~^H C = I, and its principal angles
+    within ten times the oracle's own spread over four 1e-13-perturbed runs
+    where that spread is small (at k = 64 it reaches 0.15 rad, so the angles
+    carry no information there)."""
+    from scipy.linalg import subspace_angles
+    seq = wl.cfg1_sequence(3)
+    mats, bs, bts, tol = seq.mats, seq.b, seq.bt, seq.tol
+    ref, (Ur, Utr) = oracle.rbicg_sequence(mats, bs, bts, k, s, tol)
+    rng = np.random.default_rng(9)
+    spread = 0.0
+    for _ in range(4):
+        bp = [v * (1 + 1e-13 * rng.standard_normal(v.shape)) for v in bs]
+        _, (Ur2, Utr2) = oracle.rbicg_sequence(mats, bp, bts, k, s, tol)
+        spread = max(spread, subspace_angles(Ur, Ur2).max(), subspace_angles(Utr, Utr2).max())
+    S = _solver(mats[0], k=k, s=s)
+    for j, M in enumerate(mats):
+        if j:
+            S.update_recycle(M)
+        x, xt, st = S.solve(_t(bs[j]), _t(bts[j]), tol=tol)
+        assert st["status"] == 0, (j, st)
+        assert st["relres"] <= tol and st["relres_dual"] <= tol, (j, st)
+        assert _iters_close(st["iters"], ref[j].iters), (j, st["iters"], ref[j].iters)
+        assert st["cycles"] == ref[j].cycles, (j, st["cycles"], ref[j].cycles)
+        assert _rel(_np(x), ref[j].x) <= 1e-6 and _rel(_np(xt), ref[j].xt) <= 1e-6
+    Ug, Utg, Cg, Ctg = (_np(v) for v in S.get_recycle(next=True, kcap=k))
+    assert Ug.shape[1] > 0 and abs(Ug.shape[1] - Ur.shape[1]) <= 2, (Ug.shape, Ur.shape)
+    ang = max(subspace_angles(Ug, Ur).max(), subspace_angles(Utg, Utr).max())
+    print(f"k={k} s={s}: p gpu={Ug.shape[1]} oracle={Ur.shape[1]} angle {ang:.2e} "
+          f"oracle spread {spread:.2e}", flush=True)
+    assert np.linalg.norm(Ctg.conj().T @ Cg - np.eye(Ug.shape[1])) <= 1e-11
+    if spread < 1e-3:
+        assert ang <= max(1e-6, 10.0 * spread), (ang, spread)
