@@ -397,21 +397,30 @@ def test_wide_recycle_spaces_match_oracle(cplx):
     assert ang <= max(1e-6, 10.0 * spread), (ang, spread)
 
 
-@pytest.mark.parametrize("k,s", [(64, 40), (20, 107)])
-def test_largest_recycle_space_and_cycle_match_oracle(k, s):
+@pytest.mark.parametrize("k,s,cplx", [(64, 40, False), (20, 107, False), (64, 40, True)])
+def test_largest_recycle_space_and_cycle_match_oracle(k, s, cplx):
     """The documented limits: k = 64 (the largest recycle dimension; the
     cycle-end products write four 16-column tiles from up to 80 input
     columns, the pencil Gram has 105 x 209 entries) and s + k + 1 = 128 (the
     longest cycle: a 107-vector first cycle, a 128-column Gram, a 127 x 127
-    pencil on the host).  The 2D convection-diffusion sequence against the
-    oracle: iterations within 5%, cycles, solutions to 1e-6, the carried
+    pencil on the host).  The 2D convection-diffusion sequence, and at k = 64
+    also the complex random sparse pair of the k = 40 test (the products'
+    largest LDS use: complex W rows of four tiles), against the oracle: iterations within 5%, cycles, solutions to 1e-6, the carried
     space's dimension (within two), C~^H C = I, and its principal angles
     within ten times the oracle's own spread over four 1e-13-perturbed runs
     where that spread is small (at k = 64 it reaches 0.15 rad, so the angles
     carry no information there)."""
     from scipy.linalg import subspace_angles
-    seq = wl.cfg1_sequence(3)
-    mats, bs, bts, tol = seq.mats, seq.b, seq.bt, seq.tol
+    if cplx:
+        A = wl.random_sparse(1500, 6, 41, 4.5, complex_vals=True)
+        rng = np.random.default_rng(42)
+        b = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+        bt = rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n)
+        mats = [A, wl.CSR(A.n, A.rowptr, A.colind, A.vals * (1 + 0.01j))]
+        bs, bts, tol = [b, b], [bt, bt], 1e-9
+    else:
+        seq = wl.cfg1_sequence(3)
+        mats, bs, bts, tol = seq.mats, seq.b, seq.bt, seq.tol
     ref, (Ur, Utr) = oracle.rbicg_sequence(mats, bs, bts, k, s, tol)
     rng = np.random.default_rng(9)
     spread = 0.0
@@ -419,7 +428,7 @@ def test_largest_recycle_space_and_cycle_match_oracle(k, s):
         bp = [v * (1 + 1e-13 * rng.standard_normal(v.shape)) for v in bs]
         _, (Ur2, Utr2) = oracle.rbicg_sequence(mats, bp, bts, k, s, tol)
         spread = max(spread, subspace_angles(Ur, Ur2).max(), subspace_angles(Utr, Utr2).max())
-    S = _solver(mats[0], k=k, s=s)
+    S = _solver(mats[0], k=k, s=s, prec="c128" if cplx else "f64")
     for j, M in enumerate(mats):
         if j:
             S.update_recycle(M)
@@ -432,7 +441,7 @@ def test_largest_recycle_space_and_cycle_match_oracle(k, s):
     Ug, Utg, Cg, Ctg = (_np(v) for v in S.get_recycle(next=True, kcap=k))
     assert Ug.shape[1] > 0 and abs(Ug.shape[1] - Ur.shape[1]) <= 2, (Ug.shape, Ur.shape)
     ang = max(subspace_angles(Ug, Ur).max(), subspace_angles(Utg, Utr).max())
-    print(f"k={k} s={s}: p gpu={Ug.shape[1]} oracle={Ur.shape[1]} angle {ang:.2e} "
+    print(f"k={k} s={s} {'complex' if cplx else 'real'}: p gpu={Ug.shape[1]} oracle={Ur.shape[1]} angle {ang:.2e} "
           f"oracle spread {spread:.2e}", flush=True)
     assert np.linalg.norm(Ctg.conj().T @ Cg - np.eye(Ug.shape[1])) <= 1e-11
     if spread < 1e-3:
