@@ -88,3 +88,59 @@ def test_batched_solves_bitwise_equal_alone(graphs):
     else:
         assert stats["graph_replays"] == 0 and stats["graph_captures"] == 0
     B.close()
+
+
+def test_more_solves_than_slots():
+    """Twenty small solves released together on their own threads and
+    streams share a batch of sixteen slots (a window long enough that chunks
+    accumulate): launch sets fill up to the sixteen slots and no further,
+    chunks beyond that go to the next set, and every solve gives the bits it
+    gives alone."""
+    from paper_1010_0762_amd.solver import Batch, Solver
+    rng = np.random.default_rng(17)
+    cases = []
+    for i in range(20):
+        A = wl.convdiff(14 + (i % 5), 3, (10.0 + i, 5.0, 2.0))
+        cases.append((A, "f64", 10, [(rng.standard_normal(A.n), rng.standard_normal(A.n))]))
+    alone = [_run(c) for c in cases]
+    B = Batch(max_slots=16, window_us=50000.0)
+    streams = [torch.cuda.Stream() for _ in cases]
+    solvers, rhs = [], []
+    for (A, prec, k, r), st in zip(cases, streams):
+        with torch.cuda.stream(st):
+            solvers.append(Solver(A, k=k, s=40, prec=prec, stream=st, batch=B))
+            b, bt = r[0]
+            rhs.append((torch.as_tensor(b, device="cuda"), torch.as_tensor(bt, device="cuda")))
+    torch.cuda.synchronize()
+    gate = threading.Barrier(len(cases))
+    out = [None] * len(cases)
+    errs = []
+
+    def work(i):
+        try:
+            gate.wait()
+            with torch.cuda.stream(streams[i]):
+                x, xt, st = solvers[i].solve(rhs[i][0], rhs[i][1], tol=1e-8)
+                out[i] = (x.cpu(), xt.cpu(), st)
+        except Exception as e:  # surfaced below
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(cases))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    stats = B.stats()
+    print("batch", stats, flush=True)
+    # sixteen in the runs so far; at least twelve leaves room for a slow
+    # thread start without losing what the test shows
+    assert 12 <= stats["max_chunks_per_launch"] <= 16
+    for i, (a, b) in enumerate(zip(alone, out)):
+        (xa, xta, sa), (xb, xtb, sb) = a[0], b
+        assert sa["status"] == 0 and sb["status"] == 0
+        assert sa["iters"] == sb["iters"], i
+        assert torch.equal(xa, xb) and torch.equal(xta, xtb), i
+    for S in solvers:
+        S.close()
+    B.close()
