@@ -23,7 +23,9 @@ def test_bilinear_batch_matches_direct_and_oracle(cplx):
     from paper_1010_0762_amd.solver import Solver
     seq = wl.cfg1_sequence(3)
     rng = np.random.default_rng(71)
-    S, n = 8, seq.mats[0].n
+    # complex: sixteen pairs, the largest batch (two sets of the update
+    # kernel's eight shifts per iteration)
+    S, n = (16 if cplx else 8), seq.mats[0].n
     H = Solver(seq.mats[0], k=10, s=40, prec="c128")
     mean_iters = []
     for j, A in enumerate(seq.mats):
