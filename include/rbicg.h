@@ -303,8 +303,9 @@ int rbicg_update_recycle_on(rbicg_handle h, rbicg_matrix A_next);
  * a return to the caller between systems.  mats, b, bt, x, xt: host arrays
  * of nsys pointers (resident matrices; device vectors as for
  * rbicg_solve_dual); st: nsys entries (may be NULL).  Stops at the first
- * system that returns an error (< 0) and returns it; else the worst status
- * (RBICG_NOT_CONVERGED or RBICG_BREAKDOWN if any system ended so). */
+ * system whose call returns a negative code (an error, or RBICG_BREAKDOWN)
+ * and returns that code, st filled up to that system; otherwise returns
+ * RBICG_NOT_CONVERGED if any system did not converge, else RBICG_OK. */
 int rbicg_solve_sequence(rbicg_handle h, int32_t nsys, const rbicg_matrix *mats,
                          const void *const *b, const void *const *bt, void *const *x,
                          void *const *xt, int32_t zero_init, double tol, rbicg_stats *st);
