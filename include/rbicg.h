@@ -476,8 +476,9 @@ int rbicg_batch_attach(rbicg_handle h, rbicg_batch b);
  * in one launch, graph replays, graph captures (out: 6 doubles). */
 int rbicg_batch_stats(rbicg_batch b, double *out);
 /* on != 0: every launch set (the iteration kernels of one batch launch, which
- * read their arguments from device tables) is captured once as a HIP graph
- * per table buffer and shape and replayed afterwards, so that a steady mix of
+ * read their arguments from device tables) is built once as a HIP graph of
+ * kernel nodes (no stream capture) per table buffer and shape and replayed
+ * afterwards, so that a steady mix of
  * requests is served by graph launches only (at most 64 graphs kept, least
  * recently used dropped); the tables are copied before each replay.  Results
  * are those of direct launches.  Default off. */
